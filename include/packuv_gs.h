@@ -1,0 +1,234 @@
+/*
+ * packuv_gs.h -- C ABI of the PackUV-GS differentiable splatting library
+ * (MI355X / gfx950).
+ *
+ * The library renders Gaussians stored in UV-atlas texels (one atlas per
+ * frame) into pinhole views and returns the gradient of a loss back to the
+ * texels: the "Fitting UV Maps Directly" step of PackUV (arXiv 2602.23040,
+ * Sec. 4.2) with the 3DGS tile rasteriser the paper names (Sec. 3,
+ * Preliminaries), the EWA projection of Sec. 4.2 / Algorithm 1 and the
+ * compositing formula of the supplementary viewer section.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ *  - Pointers marked "device" are HIP device pointers owned by the caller;
+ *    the library never allocates, frees or retains caller memory.  Pointers
+ *    marked "host" are read during the call only.
+ *  - `stream` is a hipStream_t (passed as void*).  Every compute call only
+ *    enqueues work on it and returns; none synchronises, allocates or issues
+ *    memset/memcpy nodes, so a sequence of calls can be captured in a HIP
+ *    graph.  The only calls that allocate are pg_views_create (device copy of
+ *    the camera table) and pg_views_destroy (frees it).
+ *  - Host-detectable problems (null pointers, bad sizes, unsupported tile
+ *    shapes, a device that is not gfx950) return an error code before
+ *    anything is enqueued; pg_last_error() gives a message (thread-local).
+ *  - Device-detected instance-capacity overflow sets *overflow_dev = 1 and
+ *    leaves the sorted outputs undefined; *n_inst_dev holds the capacity
+ *    that would have sufficed.  NaN inputs propagate; there are no checks on
+ *    the hot path.
+ *  - Forward outputs are bitwise deterministic.  Gradients are summed with
+ *    float atomics, so their last bits may vary run to run.
+ *
+ * Data layouts
+ * ------------
+ *  atlas      float [F][C][H][W], C = 11 + 3 (L+1)^2 channels per texel:
+ *             x y z | log-scale x y z | quaternion w x y z | logit-opacity |
+ *             SH k[j][ch] at channel 11 + 3 j + ch (j = l^2 + l + m).
+ *  occupancy  uint8 [H][W]; shared by all F frames.  Occupied texels in
+ *             row-major order are the Gaussians of each frame; Gaussian i of
+ *             frame f has global id g = f N + i.
+ *  params     float [F][C][N]: the occupied texels' raw channels.
+ *  views      V cameras; camera v renders frame cams[v].frame.  Per-view
+ *             records (pg_splat, pg_bin, 2D gradients) are indexed
+ *             gv = v N + i.  Tiles of view v are numbered
+ *             tile_base[v] + ty TX_v + tx; pixels pixel_base[v] + y W_v + x.
+ *  image      float, view v at offset 3 pixel_base[v], planar [3][H_v][W_v].
+ */
+#ifndef PACKUV_GS_H
+#define PACKUV_GS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    PG_OK = 0,
+    PG_ERR_INVALID_ARG = -1,
+    PG_ERR_UNSUPPORTED_DEVICE = -2,
+    PG_ERR_CAPACITY = -3,
+    PG_ERR_HIP = -4,
+    PG_ERR_WORKSPACE = -5
+} pg_status;
+
+/* Pinhole camera, OpenCV axes (x right, y down, z forward): x_c = R x + t.
+ * Pixel (i, j) has centre (i + 0.5, j + 0.5).  Viewer projection of the
+ * supplementary viewer section; Jacobian of Algorithm 1. */
+typedef struct pg_camera {
+    double R[9];            /* world -> camera rotation, row-major */
+    double t[3];
+    double fx, fy, cx, cy;  /* pixels */
+    int32_t width, height;  /* pixels, >= 1 */
+    int32_t frame;          /* atlas frame this view renders, 0 <= frame < F */
+    int32_t reserved;       /* must be 0 */
+} pg_camera;
+
+/* Screen tiling.  tile_w x tile_h must be 256 pixels: 16x16, 8x32 or 32x8
+ * (width x height).  lds_batch: Gaussians staged in LDS per step of the
+ * compositing loop, one of 64, 128, 256. */
+typedef struct pg_tiling {
+    int32_t tile_w, tile_h;
+    int32_t lds_batch;
+    int32_t reserved;       /* must be 0 */
+} pg_tiling;
+
+/* Projected Gaussian in one view: what the compositing kernels read. */
+typedef struct pg_splat {
+    double mean[2];         /* pixel-space mean m (FP64 so tile-local offsets stay exact) */
+    float conic[3];         /* (a, b, c) = inverse of Sigma2D: q = a dx^2 + 2 b dx dy + c dy^2 */
+    float opacity;          /* sigmoid(logit-opacity) */
+    float color[3];         /* max(0, 0.5 + sum_j Y_j(d) k_j), d = unit (mu - camera centre) */
+    float depth;            /* fp32(z_c) */
+} pg_splat;                 /* 48 bytes */
+
+/* Binning record of a projected Gaussian. */
+typedef struct pg_bin {
+    int16_t rect[4];        /* x_lo, y_lo, x_hi, y_hi: inclusive tile range */
+    uint32_t depth_key;     /* bit pattern of fp32(z_c) (z_c > 0, so it orders like z_c) */
+    int32_t n_tiles;        /* tiles in rect; 0 when culled */
+} pg_bin;                   /* 16 bytes */
+
+typedef struct pg_views pg_views;   /* opaque: camera table + tiling, resident on the device */
+
+typedef struct pg_views_info {
+    int32_t n_views, frames;
+    int64_t n_gauss;        /* Gaussians per frame (N) */
+    int32_t sh_degree, channels;
+    int64_t n_gv;           /* n_views * N */
+    int64_t n_tiles;        /* sum over views of TX_v * TY_v */
+    int64_t n_pixels;       /* sum over views of W_v * H_v */
+    int32_t key_bits;       /* significant bits of the (tile << 32 | depth) sort key */
+    int32_t sort_passes;    /* 8-bit radix passes */
+    int32_t tile_w, tile_h, lds_batch, reserved;
+} pg_views_info;
+
+/* Selects `device` for the calling thread and checks it is gfx950.
+ * Returns PG_ERR_UNSUPPORTED_DEVICE otherwise. */
+pg_status pg_init(int32_t device);
+
+/* Message for the last error of the calling thread ("" if none). */
+const char* pg_last_error(void);
+
+/* Builds the device-resident view table for V cameras over `frames` atlases
+ * of `n_gauss` Gaussians each (SH degree 0..3).  cams: host [V].  Fails with
+ * PG_ERR_INVALID_ARG on bad cameras (fx, fy <= 0, size < 1, frame out of
+ * range), unsupported tiling, or when V * n_gauss or the tile count exceed
+ * 2^31 - 1.  Allocates device memory (the only allocating call). */
+pg_status pg_views_create(const pg_camera* cams, int32_t n_views, int32_t frames, int64_t n_gauss,
+                          int32_t sh_degree, pg_tiling tiling, pg_views** out);
+pg_status pg_views_destroy(pg_views* views);
+pg_status pg_views_get_info(const pg_views* views, pg_views_info* info);
+/* Host arrays of n_views + 1 entries: tile_base[v], pixel_base[v] (last = totals). */
+pg_status pg_views_offsets(const pg_views* views, int64_t* tile_base, int64_t* pixel_base);
+
+/* Workspace bytes for pg_atlas_fetch on an H x W atlas. */
+pg_status pg_fetch_workspace_size(int32_t H, int32_t W, size_t* bytes);
+/* Workspace bytes for pg_bin_sort with room for inst_capacity instances. */
+pg_status pg_sort_workspace_size(const pg_views* views, int64_t inst_capacity, size_t* bytes);
+
+/* a1 -- Atlas fetch (Sec. 4.2 "Fitting UV Maps Directly"; atlas layout
+ * Sec. 4.1).  Compacts occupied texels (row-major rank = Gaussian id) and
+ * gathers their raw channels.
+ *   atlas       device float [F][C][H][W]
+ *   occupancy   device uint8 [H][W]
+ *   gauss_texel device int32 [n_cap] out: texel index y W + x of Gaussian i
+ *   texel_gauss device int32 [H W]  out: Gaussian id of a texel, -1 if empty
+ *   params      device float [F][C][n_cap] out (row stride n_cap)
+ *   n_gauss_dev device int64 [1] out: N (ids >= n_cap are not written)
+ *   ws          device workspace of pg_fetch_workspace_size bytes */
+pg_status pg_atlas_fetch(const float* atlas, const uint8_t* occupancy, int32_t frames, int32_t channels,
+                         int32_t H, int32_t W, int64_t n_cap, int32_t* gauss_texel, int32_t* texel_gauss,
+                         float* params, int64_t* n_gauss_dev, void* ws, size_t ws_bytes, void* stream);
+
+/* a2 -- EWA projection (Sec. 4.2 masking equations; Algorithm 1 steps 1-4;
+ * viewer projection).  For every view and every Gaussian of its frame:
+ * activations s = exp(l_s), unit quaternion, o = sigmoid(l_o); mu_c = R mu + t,
+ * cull z_c <= 0.2; Sigma2D = J R Sigma R^T J^T + 0.3 I; cull det <= 1e-7;
+ * radius ceil(3 sqrt(lambda_max)); tile rectangle; conic; SH colour.
+ * Decision quantities are evaluated in FP64 in a fixed order without
+ * contraction, from the FP32 texel values.
+ *   params   device float [F][C][n_gauss] (row stride n_gauss)
+ *   splats   device pg_splat [n_gv] out
+ *   bins     device pg_bin [n_gv] out
+ *   visible  device uint8 [F n_gauss]: set to 1 for Gaussians with n_tiles > 0
+ *            in at least one view of this call; never cleared (OR semantics). */
+pg_status pg_project(const pg_views* views, const float* params, pg_splat* splats, pg_bin* bins,
+                     uint8_t* visible, void* stream);
+
+/* a3 -- Tile binning and depth sort (tile rasteriser, Sec. 3; per-camera
+ * depth sort, viewer section).  Emits one instance per (Gaussian, covered
+ * tile) with key (global tile << 32 | depth_key) and value gv, sorts them by
+ * key with a stable LSD radix sort (equal keys keep ascending gv), and
+ * writes each tile's [start, end) instance range.
+ *   keys, values   device [inst_capacity] out (sorted)
+ *   tile_ranges    device int32 [n_tiles][2] out
+ *   n_inst_dev     device int64 [1] out: number of instances
+ *   overflow_dev   device int32 [1] out: 1 if n_inst > inst_capacity, else 0
+ *   ws             device workspace of pg_sort_workspace_size bytes */
+pg_status pg_bin_sort(const pg_views* views, const pg_bin* bins, int64_t inst_capacity, uint64_t* keys,
+                      int32_t* values, int32_t* tile_ranges, int64_t* n_inst_dev, int32_t* overflow_dev,
+                      void* ws, size_t ws_bytes, void* stream);
+
+/* a4 -- Front-to-back compositing (supplementary viewer section:
+ * C = sum_i T_i alpha_i c_i, T_i = prod_{j<i} (1 - alpha_j); footprint
+ * d^2 <= 9 of Sec. 4.2).  Per pixel: skip q > 9; alpha = min(0.99, o e^{-q/2});
+ * skip alpha < 1/255; stop before T (1 - alpha) < 1e-4.  Writes C + T bg.
+ *   bg         host float[3]
+ *   image      device float [3 n_pixels] out (per view planar [3][H][W])
+ *   final_T    device float [n_pixels] out
+ *   n_contrib  device int32 [n_pixels] out: 1-based list position of the last
+ *              composited Gaussian, 0 if none
+ *   counters   device uint64 [2] or NULL: += {pairs evaluated, pairs composited} */
+pg_status pg_render_fwd(const pg_views* views, const pg_splat* splats, const int32_t* values,
+                        const int32_t* tile_ranges, const float* bg, float* image, float* final_T,
+                        int32_t* n_contrib, uint64_t* counters, void* stream);
+
+/* a5 -- Adjoint of a2-a4 back to the texels, with gradient freezing
+ * grad <- D_i grad (Sec. 4.2 "Gradient Freezing").  Recomputes per-pixel
+ * transmittance from final_T instead of storing it.
+ *   dL_dimage    device float [3 n_pixels]
+ *   gauss_texel  device int32 [n_gauss] (from pg_atlas_fetch)
+ *   dynamic_mask device uint8 [H][W] or NULL (NULL: every Gaussian dynamic)
+ *   grad2d       device float [9][n_gv] out: per (view, Gaussian) dL/d(m_x,
+ *                m_y, a, b, c, opacity, r, g, b)
+ *   dL_datlas    device float [F][C][H][W] out; written (accumulate = 0: every
+ *                texel, unoccupied = 0) or added to (accumulate = 1: occupied
+ *                texels only). */
+pg_status pg_render_bwd(const pg_views* views, const float* params, const pg_splat* splats,
+                        const int32_t* values, const int32_t* tile_ranges, const float* bg, const float* final_T,
+                        const int32_t* n_contrib, const float* dL_dimage, const int32_t* gauss_texel,
+                        const uint8_t* dynamic_mask, int32_t H, int32_t W, float* grad2d, float* dL_datlas,
+                        int32_t accumulate, void* stream);
+
+/* a4' -- L1 photometric term of Sec. 4.2 "Objective" (lambda_ssim = 0):
+ * L = mean |image - target|, dL/dimage = sign(image - target) / n (sign 0 = 0).
+ *   partial   device double [1024] workspace
+ *   loss_dev  device float [1] out */
+pg_status pg_loss_l1(const float* image, const float* target, int64_t n, float* dL_dimage, double* partial,
+                     float* loss_dev, void* stream);
+
+/* a6 -- Sparse Adam on the FP32 atlas (Sec. 4.3, LPO paragraph: FP32 master
+ * weights, Sparse Adam).  Textbook Adam with bias correction at `step` >= 1,
+ * applied to channels of texels whose Gaussian is visible (visible[f N + i]);
+ * other texels and their moments are left untouched.
+ *   atlas, m, v  device float [F][C][H][W] in/out;  grad same layout */
+pg_status pg_adam_step(float* atlas, const float* grad, float* m, float* v, const uint8_t* visible,
+                       const int32_t* texel_gauss, int64_t n_gauss, int32_t frames, int32_t channels, int32_t H,
+                       int32_t W, float lr, float beta1, float beta2, float eps, int32_t step, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PACKUV_GS_H */

@@ -1,0 +1,318 @@
+// C ABI of the library: argument validation, the device-resident view
+// table, and the entry points that enqueue the kernels of the other
+// translation units.  Every check that can be made on the host is made
+// before anything is enqueued.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "pg_internal.h"
+
+namespace pg {
+
+namespace {
+thread_local std::string g_error;
+
+pg_status invalid(const std::string& msg) {
+    g_error = msg;
+    return PG_ERR_INVALID_ARG;
+}
+
+bool tiling_ok(const pg_tiling& t) {
+    const bool shape = (t.tile_w == 16 && t.tile_h == 16) || (t.tile_w == 8 && t.tile_h == 32) ||
+                       (t.tile_w == 32 && t.tile_h == 8);
+    const bool batch = t.lds_batch == 64 || t.lds_batch == 128 || t.lds_batch == 256;
+    return shape && batch && t.reserved == 0;
+}
+
+#define PG_CHECK_HIP(expr, what)                          \
+    do {                                                  \
+        hipError_t e_ = (expr);                           \
+        if (e_ != hipSuccess) return hip_fail(e_, what);  \
+    } while (0)
+
+}  // namespace
+
+void set_error(const std::string& msg) { g_error = msg; }
+
+pg_status hip_fail(hipError_t e, const char* what) {
+    g_error = std::string(what) + ": " + hipGetErrorString(e);
+    return PG_ERR_HIP;
+}
+
+}  // namespace pg
+
+using namespace pg;
+
+extern "C" {
+
+const char* pg_last_error(void) { return g_error.c_str(); }
+
+pg_status pg_init(int32_t device) {
+    g_error.clear();
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || n == 0) {
+        set_error("no HIP device available");
+        return PG_ERR_UNSUPPORTED_DEVICE;
+    }
+    if (device < 0 || device >= n) return invalid("device index out of range");
+    PG_CHECK_HIP(hipSetDevice(device), "hipSetDevice");
+    hipDeviceProp_t prop;
+    PG_CHECK_HIP(hipGetDeviceProperties(&prop, device), "hipGetDeviceProperties");
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) {
+        set_error(std::string("unsupported device architecture ") + prop.gcnArchName + " (needs gfx950)");
+        return PG_ERR_UNSUPPORTED_DEVICE;
+    }
+    return PG_OK;
+}
+
+pg_status pg_views_create(const pg_camera* cams, int32_t n_views, int32_t frames, int64_t n_gauss,
+                          int32_t sh_degree, pg_tiling tiling, pg_views** out) {
+    g_error.clear();
+    if (!out) return invalid("out is null");
+    *out = nullptr;
+    if (!cams) return invalid("cams is null");
+    if (n_views < 1 || n_views > kMaxViews) return invalid("n_views must be in [1, 65536]");
+    if (frames < 1) return invalid("frames must be >= 1");
+    if (n_gauss < 0) return invalid("n_gauss must be >= 0");
+    if (sh_degree < 0 || sh_degree > 3) return invalid("sh_degree must be in [0, 3]");
+    if (!tiling_ok(tiling))
+        return invalid("tiling must be 16x16, 8x32 or 32x8 with lds_batch 64, 128 or 256 (reserved = 0)");
+    if ((int64_t)n_views * n_gauss > INT32_MAX) return invalid("n_views * n_gauss exceeds 2^31 - 1");
+    std::vector<ViewDev> hv(n_views);
+    std::vector<int64_t> tb(n_views + 1), pb(n_views + 1);
+    int64_t tiles = 0, pixels = 0;
+    for (int32_t v = 0; v < n_views; v++) {
+        const pg_camera& c = cams[v];
+        if (!(c.fx > 0.0) || !(c.fy > 0.0) || !std::isfinite(c.fx) || !std::isfinite(c.fy))
+            return invalid("camera " + std::to_string(v) + ": fx and fy must be finite and > 0");
+        if (c.width < 1 || c.height < 1 || c.width > 32767 * 8 || c.height > 32767 * 8)
+            return invalid("camera " + std::to_string(v) + ": width and height must be in [1, 262136]");
+        if (c.frame < 0 || c.frame >= frames)
+            return invalid("camera " + std::to_string(v) + ": frame out of range");
+        if (c.reserved != 0) return invalid("camera " + std::to_string(v) + ": reserved must be 0");
+        for (int k = 0; k < 9; k++)
+            if (!std::isfinite(c.R[k])) return invalid("camera " + std::to_string(v) + ": R not finite");
+        for (int k = 0; k < 3; k++)
+            if (!std::isfinite(c.t[k])) return invalid("camera " + std::to_string(v) + ": t not finite");
+        ViewDev& d = hv[v];
+        std::memset(&d, 0, sizeof d);
+        std::memcpy(d.R, c.R, sizeof d.R);
+        std::memcpy(d.t, c.t, sizeof d.t);
+        d.fx = c.fx;
+        d.fy = c.fy;
+        d.cx = c.cx;
+        d.cy = c.cy;
+        for (int k = 0; k < 3; k++) d.cw[k] = -((c.R[k] * c.t[0] + c.R[3 + k] * c.t[1]) + c.R[6 + k] * c.t[2]);
+        d.W = c.width;
+        d.H = c.height;
+        d.TX = (c.width + tiling.tile_w - 1) / tiling.tile_w;
+        d.TY = (c.height + tiling.tile_h - 1) / tiling.tile_h;
+        d.frame = c.frame;
+        d.tile_base = tiles;
+        d.pix_base = pixels;
+        tb[v] = tiles;
+        pb[v] = pixels;
+        tiles += (int64_t)d.TX * d.TY;
+        pixels += (int64_t)c.width * c.height;
+    }
+    tb[n_views] = tiles;
+    pb[n_views] = pixels;
+    if (tiles > INT32_MAX) return invalid("total tile count exceeds 2^31 - 1");
+    std::vector<int32_t> fv(frames + 1, 0), order;
+    for (int32_t f = 0; f < frames; f++) {
+        fv[f] = (int32_t)order.size();
+        for (int32_t v = 0; v < n_views; v++)
+            if (cams[v].frame == f) order.push_back(v);
+    }
+    fv[frames] = (int32_t)order.size();
+    int tile_bits = 1;
+    while ((int64_t(1) << tile_bits) < tiles) tile_bits++;
+
+    pg_views* p = new pg_views();
+    p->n_views = n_views;
+    p->frames = frames;
+    p->sh_degree = sh_degree;
+    p->channels = 11 + 3 * (sh_degree + 1) * (sh_degree + 1);
+    p->n_gauss = n_gauss;
+    p->tiling = tiling;
+    p->n_gv = (int64_t)n_views * n_gauss;
+    p->n_tiles = tiles;
+    p->n_pixels = pixels;
+    p->key_bits = 32 + tile_bits;
+    p->sort_passes = (p->key_bits + kRadixBits - 1) / kRadixBits;
+    p->h_tile_base = new int64_t[n_views + 1];
+    p->h_pix_base = new int64_t[n_views + 1];
+    std::memcpy(p->h_tile_base, tb.data(), sizeof(int64_t) * (n_views + 1));
+    std::memcpy(p->h_pix_base, pb.data(), sizeof(int64_t) * (n_views + 1));
+    hipGetDevice(&p->device);
+    hipError_t e = hipMalloc(&p->d_views, sizeof(ViewDev) * n_views);
+    if (e == hipSuccess) e = hipMalloc(&p->d_frame_views, sizeof(int32_t) * (frames + 1));
+    if (e == hipSuccess) e = hipMalloc(&p->d_view_order, sizeof(int32_t) * n_views);
+    if (e == hipSuccess) e = hipMemcpy(p->d_views, hv.data(), sizeof(ViewDev) * n_views, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(p->d_frame_views, fv.data(), sizeof(int32_t) * (frames + 1), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(p->d_view_order, order.data(), sizeof(int32_t) * n_views, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        pg_views_destroy(p);
+        return hip_fail(e, "pg_views_create");
+    }
+    *out = p;
+    return PG_OK;
+}
+
+pg_status pg_views_destroy(pg_views* v) {
+    if (!v) return PG_OK;
+    if (v->d_views) hipFree(v->d_views);
+    if (v->d_frame_views) hipFree(v->d_frame_views);
+    if (v->d_view_order) hipFree(v->d_view_order);
+    delete[] v->h_tile_base;
+    delete[] v->h_pix_base;
+    delete v;
+    return PG_OK;
+}
+
+pg_status pg_views_get_info(const pg_views* v, pg_views_info* info) {
+    if (!v || !info) return invalid("null argument");
+    std::memset(info, 0, sizeof *info);
+    info->n_views = v->n_views;
+    info->frames = v->frames;
+    info->n_gauss = v->n_gauss;
+    info->sh_degree = v->sh_degree;
+    info->channels = v->channels;
+    info->n_gv = v->n_gv;
+    info->n_tiles = v->n_tiles;
+    info->n_pixels = v->n_pixels;
+    info->key_bits = v->key_bits;
+    info->sort_passes = v->sort_passes;
+    info->tile_w = v->tiling.tile_w;
+    info->tile_h = v->tiling.tile_h;
+    info->lds_batch = v->tiling.lds_batch;
+    return PG_OK;
+}
+
+pg_status pg_views_offsets(const pg_views* v, int64_t* tile_base, int64_t* pixel_base) {
+    if (!v || !tile_base || !pixel_base) return invalid("null argument");
+    std::memcpy(tile_base, v->h_tile_base, sizeof(int64_t) * (v->n_views + 1));
+    std::memcpy(pixel_base, v->h_pix_base, sizeof(int64_t) * (v->n_views + 1));
+    return PG_OK;
+}
+
+pg_status pg_fetch_workspace_size(int32_t H, int32_t W, size_t* bytes) {
+    if (!bytes) return invalid("bytes is null");
+    if (H < 1 || W < 1) return invalid("H and W must be >= 1");
+    *bytes = fetch_ws_bytes(H, W);
+    return PG_OK;
+}
+
+pg_status pg_sort_workspace_size(const pg_views* v, int64_t cap, size_t* bytes) {
+    if (!v || !bytes) return invalid("null argument");
+    if (cap < 0 || cap > INT32_MAX) return invalid("inst_capacity must be in [0, 2^31 - 1]");
+    *bytes = sort_ws_bytes(v, cap);
+    return PG_OK;
+}
+
+pg_status pg_atlas_fetch(const float* atlas, const uint8_t* occupancy, int32_t frames, int32_t channels, int32_t H,
+                         int32_t W, int64_t n_cap, int32_t* gauss_texel, int32_t* texel_gauss, float* params,
+                         int64_t* n_gauss_dev, void* ws, size_t ws_bytes, void* stream) {
+    g_error.clear();
+    if (!atlas || !occupancy || !texel_gauss || !n_gauss_dev || !ws) return invalid("null pointer argument");
+    if (n_cap > 0 && (!gauss_texel || !params)) return invalid("gauss_texel / params null with n_cap > 0");
+    if (frames < 1 || channels < 1 || H < 1 || W < 1 || n_cap < 0) return invalid("bad sizes");
+    if ((int64_t)H * W > INT32_MAX) return invalid("H * W exceeds 2^31 - 1");
+    if (ws_bytes < fetch_ws_bytes(H, W)) {
+        set_error("fetch workspace too small");
+        return PG_ERR_WORKSPACE;
+    }
+    PG_CHECK_HIP(launch_fetch(atlas, occupancy, frames, channels, H, W, n_cap, gauss_texel, texel_gauss, params,
+                              n_gauss_dev, ws, (hipStream_t)stream),
+                 "pg_atlas_fetch");
+    return PG_OK;
+}
+
+pg_status pg_project(const pg_views* v, const float* params, pg_splat* splats, pg_bin* bins, uint8_t* visible,
+                     void* stream) {
+    g_error.clear();
+    if (!v) return invalid("views is null");
+    if (v->n_gv > 0 && (!params || !splats || !bins || !visible)) return invalid("null pointer argument");
+    PG_CHECK_HIP(launch_project(v, params, splats, bins, visible, (hipStream_t)stream), "pg_project");
+    return PG_OK;
+}
+
+pg_status pg_bin_sort(const pg_views* v, const pg_bin* bins, int64_t cap, uint64_t* keys, int32_t* values,
+                      int32_t* tile_ranges, int64_t* n_inst_dev, int32_t* overflow_dev, void* ws, size_t ws_bytes,
+                      void* stream) {
+    g_error.clear();
+    if (!v) return invalid("views is null");
+    if (!tile_ranges || !n_inst_dev || !overflow_dev || !ws) return invalid("null pointer argument");
+    if (v->n_gv > 0 && !bins) return invalid("bins is null");
+    if (cap < 0 || cap > INT32_MAX) return invalid("inst_capacity must be in [0, 2^31 - 1]");
+    if (cap > 0 && (!keys || !values)) return invalid("keys / values null with inst_capacity > 0");
+    if (ws_bytes < sort_ws_bytes(v, cap)) {
+        set_error("sort workspace too small");
+        return PG_ERR_WORKSPACE;
+    }
+    PG_CHECK_HIP(launch_bin_sort(v, bins, cap, keys, values, tile_ranges, n_inst_dev, overflow_dev, ws,
+                                 (hipStream_t)stream),
+                 "pg_bin_sort");
+    return PG_OK;
+}
+
+pg_status pg_render_fwd(const pg_views* v, const pg_splat* splats, const int32_t* values, const int32_t* tile_ranges,
+                        const float* bg, float* image, float* final_T, int32_t* n_contrib, uint64_t* counters,
+                        void* stream) {
+    g_error.clear();
+    if (!v || !bg) return invalid("null argument");
+    if (!image || !final_T || !n_contrib || !tile_ranges) return invalid("null pointer argument");
+    if (v->n_gv > 0 && (!splats || !values)) return invalid("null pointer argument");
+    PG_CHECK_HIP(launch_render_fwd(v, splats, values, tile_ranges, bg, image, final_T, n_contrib, counters,
+                                   (hipStream_t)stream),
+                 "pg_render_fwd");
+    return PG_OK;
+}
+
+pg_status pg_render_bwd(const pg_views* v, const float* params, const pg_splat* splats, const int32_t* values,
+                        const int32_t* tile_ranges, const float* bg, const float* final_T, const int32_t* n_contrib,
+                        const float* dL_dimage, const int32_t* gauss_texel, const uint8_t* dynamic_mask, int32_t H,
+                        int32_t W, float* grad2d, float* dL_datlas, int32_t accumulate, void* stream) {
+    g_error.clear();
+    if (!v || !bg) return invalid("null argument");
+    if (!tile_ranges || !final_T || !n_contrib || !dL_dimage || !dL_datlas) return invalid("null pointer argument");
+    if (v->n_gv > 0 && (!params || !splats || !values || !gauss_texel || !grad2d))
+        return invalid("null pointer argument");
+    if (H < 1 || W < 1 || (int64_t)H * W < v->n_gauss) return invalid("H * W must hold n_gauss texels");
+    if (accumulate != 0 && accumulate != 1) return invalid("accumulate must be 0 or 1");
+    hipStream_t s = (hipStream_t)stream;
+    PG_CHECK_HIP(launch_render_bwd(v, splats, values, tile_ranges, bg, final_T, n_contrib, dL_dimage, grad2d, s),
+                 "pg_render_bwd (raster)");
+    PG_CHECK_HIP(launch_project_bwd(v, params, grad2d, gauss_texel, dynamic_mask, H, W, dL_datlas, accumulate, s),
+                 "pg_render_bwd (projection)");
+    return PG_OK;
+}
+
+pg_status pg_loss_l1(const float* image, const float* target, int64_t n, float* dL_dimage, double* partial,
+                     float* loss_dev, void* stream) {
+    g_error.clear();
+    if (!image || !target || !dL_dimage || !partial || !loss_dev) return invalid("null pointer argument");
+    if (n < 1) return invalid("n must be >= 1");
+    PG_CHECK_HIP(launch_loss_l1(image, target, n, dL_dimage, partial, loss_dev, (hipStream_t)stream), "pg_loss_l1");
+    return PG_OK;
+}
+
+pg_status pg_adam_step(float* atlas, const float* grad, float* m, float* v, const uint8_t* visible,
+                       const int32_t* texel_gauss, int64_t n_gauss, int32_t frames, int32_t channels, int32_t H,
+                       int32_t W, float lr, float beta1, float beta2, float eps, int32_t step, void* stream) {
+    g_error.clear();
+    if (!atlas || !grad || !m || !v || !visible || !texel_gauss) return invalid("null pointer argument");
+    if (frames < 1 || channels < 1 || H < 1 || W < 1 || n_gauss < 0) return invalid("bad sizes");
+    if (step < 1) return invalid("step must be >= 1");
+    if (!(beta1 >= 0.0f && beta1 < 1.0f) || !(beta2 >= 0.0f && beta2 < 1.0f) || !(eps > 0.0f))
+        return invalid("need 0 <= beta < 1 and eps > 0");
+    PG_CHECK_HIP(launch_adam(atlas, grad, m, v, visible, texel_gauss, n_gauss, frames, channels, H, W, lr, beta1,
+                             beta2, eps, step, (hipStream_t)stream),
+                 "pg_adam_step");
+    return PG_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,92 @@
+// a4' (L1 photometric term) and a6 (sparse Adam on the atlas).
+//
+// L1: L = mean |image - target| and dL/dimage = sign(image - target) / n
+// (Sec. 4.2 "Objective", lambda_ssim = 0).  The sum is reduced in a fixed
+// order (fixed grid, per-group partials in FP64, one final group), so the
+// loss value is deterministic.  HBM-bound: 12 bytes per element.
+//
+// Adam: textbook update with bias correction on the FP32 master atlas,
+// restricted to texels whose Gaussian was drawn in at least one view this
+// step ("Sparse Adam", Sec. 4.3 LPO paragraph).  HBM-bound: 28 bytes per
+// updated element (atlas, m, v read and written, gradient read).
+#include "pg_internal.h"
+
+namespace pg {
+
+namespace {
+
+constexpr int kLossBlocks = 1024;
+
+__global__ __launch_bounds__(256) void k_l1(const float* __restrict__ img, const float* __restrict__ tgt, int64_t n,
+                                            float* __restrict__ g, double* __restrict__ partial) {
+    __shared__ double s[4];
+    const float inv = (float)(1.0 / (double)n);
+    double acc = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const float d = img[i] - tgt[i];
+        acc += (double)fabsf(d);
+        g[i] = d > 0.0f ? inv : (d < 0.0f ? -inv : 0.0f);
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+    if ((threadIdx.x & 63) == 0) s[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) partial[blockIdx.x] = (s[0] + s[1]) + (s[2] + s[3]);
+}
+
+__global__ __launch_bounds__(kLossBlocks) void k_l1_final(const double* __restrict__ partial, int64_t n,
+                                                          float* __restrict__ loss) {
+    __shared__ double s[kLossBlocks];
+    s[threadIdx.x] = partial[threadIdx.x];
+    __syncthreads();
+    for (int o = kLossBlocks / 2; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) s[threadIdx.x] += s[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *loss = (float)(s[0] / (double)n);
+}
+
+__global__ __launch_bounds__(256) void k_adam(float* __restrict__ p, const float* __restrict__ g,
+                                              float* __restrict__ m, float* __restrict__ v,
+                                              const uint8_t* __restrict__ visible,
+                                              const int32_t* __restrict__ texel_gauss, int64_t N, int32_t C,
+                                              int64_t HW, int64_t total, float lr, float b1, float b2, float eps,
+                                              float inv_c1, float inv_c2) {
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t texel = e % HW;
+        const int64_t f = e / (HW * C);
+        const int32_t id = texel_gauss[texel];
+        if (id < 0 || !visible[f * N + id]) continue;
+        const float gr = g[e];
+        const float mm = b1 * m[e] + (1.0f - b1) * gr;
+        const float vv = b2 * v[e] + (1.0f - b2) * gr * gr;
+        m[e] = mm;
+        v[e] = vv;
+        p[e] = p[e] - lr * (mm * inv_c1) / (sqrtf(vv * inv_c2) + eps);
+    }
+}
+
+}  // namespace
+
+hipError_t launch_loss_l1(const float* img, const float* tgt, int64_t n, float* g, double* partial, float* loss,
+                          hipStream_t s) {
+    k_l1<<<kLossBlocks, 256, 0, s>>>(img, tgt, n, g, partial);
+    k_l1_final<<<1, kLossBlocks, 0, s>>>(partial, n, loss);
+    return hipGetLastError();
+}
+
+hipError_t launch_adam(float* atlas, const float* grad, float* m, float* v, const uint8_t* visible,
+                       const int32_t* texel_gauss, int64_t n_gauss, int32_t F, int32_t C, int32_t H, int32_t W,
+                       float lr, float b1, float b2, float eps, int32_t step, hipStream_t s) {
+    const int64_t HW = (int64_t)H * W;
+    const int64_t total = (int64_t)F * C * HW;
+    if (total == 0) return hipSuccess;
+    const double c1 = 1.0 - pow((double)b1, (double)step), c2 = 1.0 - pow((double)b2, (double)step);
+    const unsigned grid = (unsigned)imin(ceil_div(total, 256), 8192);
+    k_adam<<<grid, 256, 0, s>>>(atlas, grad, m, v, visible, texel_gauss, n_gauss, C, HW, total, lr, b1, b2, eps,
+                                (float)(1.0 / c1), (float)(1.0 / c2));
+    return hipGetLastError();
+}
+
+}  // namespace pg

@@ -1,0 +1,116 @@
+// Internal declarations shared by the HIP translation units of the library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+
+#include "packuv_gs.h"
+
+namespace pg {
+
+constexpr int kMaxViews = 1 << 16;
+constexpr int kScanBlocks = 1024;    // fixed grid of the device-length scans
+constexpr int kSortThreads = 256;    // radix sort work-group
+constexpr int kSortItems = 16;       // keys per thread
+constexpr int kSortTile = kSortThreads * kSortItems;
+constexpr int kRadixBits = 8;
+constexpr int kRadix = 1 << kRadixBits;
+
+// Per-view table resident on the device.
+struct ViewDev {
+    double R[9];
+    double t[3];
+    double fx, fy, cx, cy;
+    double cw[3];          // camera centre in world coordinates, -R^T t
+    int32_t W, H, TX, TY;
+    int32_t frame, pad;
+    int64_t tile_base, pix_base;
+};
+
+}  // namespace pg
+
+struct pg_views {
+    int32_t n_views, frames, sh_degree, channels;
+    int64_t n_gauss;
+    pg_tiling tiling;
+    int64_t n_gv, n_tiles, n_pixels;
+    int32_t key_bits, sort_passes;
+    int32_t device;
+    pg::ViewDev* d_views;      // [n_views]
+    int32_t* d_frame_views;    // [frames + 1] offsets into d_view_order
+    int32_t* d_view_order;     // [n_views] view indices grouped by frame
+    int64_t* h_tile_base;      // [n_views + 1]
+    int64_t* h_pix_base;       // [n_views + 1]
+};
+
+namespace pg {
+
+// thread-local error message
+void set_error(const std::string& msg);
+pg_status hip_fail(hipError_t e, const char* what);
+
+__host__ __device__ inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+__host__ __device__ inline int64_t imin(int64_t a, int64_t b) { return a < b ? a : b; }
+__host__ __device__ inline int64_t imax(int64_t a, int64_t b) { return a > b ? a : b; }
+inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// ---- launchers implemented in the kernel translation units (all enqueue only)
+
+// scan.hip
+hipError_t fill_u32(void* p, uint32_t value, int64_t n_words, hipStream_t s);
+// exclusive scan of n (device-read: *n_dev * n_mul, or n_host when n_dev == null) int64 values
+hipError_t scan_i64(const int64_t* in, int64_t* out, const int64_t* n_dev, int64_t n_mul, int64_t n_host,
+                    int64_t* total_out, int64_t* block_tmp, hipStream_t s);
+hipError_t scan_i32_as_i64(const int32_t* in, int64_t* out, const int64_t* n_dev, int64_t n_mul, int64_t n_host,
+                           int64_t* total_out, int64_t* block_tmp, hipStream_t s);
+hipError_t scan_i32(const int32_t* in, int32_t* out, const int64_t* n_dev, int64_t n_mul, int64_t n_host,
+                    int64_t* total_out, int64_t* block_tmp, hipStream_t s);
+constexpr int64_t kScanTmpWords = kScanBlocks + 1;   // int64 scratch words a scan needs
+
+// fetch.hip
+size_t fetch_ws_bytes(int32_t H, int32_t W);
+hipError_t launch_fetch(const float* atlas, const uint8_t* occ, int32_t F, int32_t C, int32_t H, int32_t W,
+                        int64_t n_cap, int32_t* gauss_texel, int32_t* texel_gauss, float* params,
+                        int64_t* n_gauss_dev, void* ws, hipStream_t s);
+
+// project.hip
+hipError_t launch_project(const pg_views* v, const float* params, pg_splat* splats, pg_bin* bins,
+                          uint8_t* visible, hipStream_t s);
+hipError_t launch_project_bwd(const pg_views* v, const float* params, const float* grad2d,
+                              const int32_t* gauss_texel, const uint8_t* dyn, int32_t H, int32_t W,
+                              float* dL_datlas, int32_t accumulate, hipStream_t s);
+
+// binsort.hip
+size_t sort_ws_bytes(const pg_views* v, int64_t cap);
+hipError_t launch_bin_sort(const pg_views* v, const pg_bin* bins, int64_t cap, uint64_t* keys, int32_t* values,
+                           int32_t* ranges, int64_t* n_inst_dev, int32_t* overflow_dev, void* ws, hipStream_t s);
+
+// render.hip
+hipError_t launch_render_fwd(const pg_views* v, const pg_splat* splats, const int32_t* values,
+                             const int32_t* ranges, const float bg[3], float* image, float* final_T,
+                             int32_t* n_contrib, uint64_t* counters, hipStream_t s);
+hipError_t launch_render_bwd(const pg_views* v, const pg_splat* splats, const int32_t* values,
+                             const int32_t* ranges, const float bg[3], const float* final_T,
+                             const int32_t* n_contrib, const float* dL_dimage, float* grad2d, hipStream_t s);
+
+// optim.hip
+hipError_t launch_loss_l1(const float* img, const float* tgt, int64_t n, float* g, double* partial, float* loss,
+                          hipStream_t s);
+hipError_t launch_adam(float* atlas, const float* grad, float* m, float* v, const uint8_t* visible,
+                       const int32_t* texel_gauss, int64_t n_gauss, int32_t F, int32_t C, int32_t H, int32_t W,
+                       float lr, float b1, float b2, float eps, int32_t step, hipStream_t s);
+
+// ---- device helpers
+
+__device__ __forceinline__ int find_view_by_tile(const ViewDev* views, int nv, int64_t tile) {
+    int lo = 0, hi = nv - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (views[mid].tile_base <= tile) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+}  // namespace pg

@@ -1,0 +1,481 @@
+// a2 -- EWA projection of every Gaussian into every view of its frame, and
+// (a5, second half) its adjoint back to the texel channels.
+//
+// Formulas: Sigma = R(q) diag(s)^2 R(q)^T; Sigma_c = W Sigma W^T; J the
+// perspective Jacobian at the camera-space mean; Sigma2D = J Sigma_c J^T
+// with +0.3 added to the diagonal; det / z validity test; lambda_max and the
+// radius ceil(3 sqrt(lambda_max)) ("Covariance-Aware Gaussian Masking",
+// Sec. 4.2, and Algorithm 1 steps 1-4); X_c = R X + t and the pixel mean
+// (supplementary, viewer section); SH colour of the 3DGS record (Sec. 3).
+//
+// Every quantity that decides an integer (culls, radius, tile rectangle,
+// depth key) is computed in FP64 from the FP32 texels in one fixed order:
+// sums of products left to right in ascending index, no contraction (this
+// file is compiled with -ffp-contract=off), IEEE division and square root.
+// The outputs the compositing kernels read are rounded to FP32 once.
+//
+// Launch shape: one thread per Gaussian of a frame; the thread reads the
+// texel record once and loops over the views of that frame, so a batched
+// call reads the parameters once instead of once per view.  Work per
+// (Gaussian, view) is ~300 FP64 flops against 64 bytes written, so at the
+// chip's FP64 rate the kernel stays close to its HBM bound.
+#include "pg_internal.h"
+
+#pragma clang fp contract(off)
+
+namespace pg {
+
+namespace {
+
+constexpr double kNearZ = 0.2;
+constexpr double kLowPass = 0.3;
+constexpr double kDetMin = 1e-7;
+
+// Real SH normalisations (Condon-Shortley phase kept).
+constexpr double kY0 = 0.28209479177387814;   // 1 / (2 sqrt(pi))
+constexpr double kY1 = 0.4886025119029199;    // sqrt(3 / (4 pi))
+constexpr double kY2a = 1.0925484305920792;   // sqrt(15 / pi) / 2
+constexpr double kY2b = 0.31539156525252005;  // sqrt(5 / pi) / 4
+constexpr double kY2c = 0.5462742152960396;   // sqrt(15 / pi) / 4
+constexpr double kY3a = 0.5900435899266435;   // sqrt(35 / (2 pi)) / 4
+constexpr double kY3b = 2.890611442640554;    // sqrt(105 / pi) / 2
+constexpr double kY3c = 0.4570457994644658;   // sqrt(21 / (2 pi)) / 4
+constexpr double kY3d = 0.3731763325901154;   // sqrt(7 / pi) / 4
+constexpr double kY3e = 1.445305721320277;    // sqrt(105 / pi) / 4
+
+template <int L>
+__device__ __forceinline__ void sh_basis(double x, double y, double z, double* Y) {
+    Y[0] = kY0;
+    if (L >= 1) {
+        Y[1] = -kY1 * y;
+        Y[2] = kY1 * z;
+        Y[3] = -kY1 * x;
+    }
+    if (L >= 2) {
+        Y[4] = kY2a * x * y;
+        Y[5] = -kY2a * y * z;
+        Y[6] = kY2b * (3.0 * z * z - 1.0);
+        Y[7] = -kY2a * x * z;
+        Y[8] = kY2c * (x * x - y * y);
+    }
+    if (L >= 3) {
+        Y[9] = -kY3a * y * (3.0 * x * x - y * y);
+        Y[10] = kY3b * x * y * z;
+        Y[11] = -kY3c * y * (5.0 * z * z - 1.0);
+        Y[12] = kY3d * z * (5.0 * z * z - 3.0);
+        Y[13] = -kY3c * x * (5.0 * z * z - 1.0);
+        Y[14] = kY3e * z * (x * x - y * y);
+        Y[15] = -kY3a * x * (x * x - 3.0 * y * y);
+    }
+}
+
+// d Y_j / d(x, y, z) of the polynomials above.
+template <int L>
+__device__ __forceinline__ void sh_basis_grad(double x, double y, double z, double (*G)[3]) {
+    constexpr int nb = (L + 1) * (L + 1);
+#pragma unroll
+    for (int j = 0; j < nb; j++) G[j][0] = G[j][1] = G[j][2] = 0.0;
+    if (L >= 1) {
+        G[1][1] = -kY1;
+        G[2][2] = kY1;
+        G[3][0] = -kY1;
+    }
+    if (L >= 2) {
+        G[4][0] = kY2a * y; G[4][1] = kY2a * x;
+        G[5][1] = -kY2a * z; G[5][2] = -kY2a * y;
+        G[6][2] = 6.0 * kY2b * z;
+        G[7][0] = -kY2a * z; G[7][2] = -kY2a * x;
+        G[8][0] = 2.0 * kY2c * x; G[8][1] = -2.0 * kY2c * y;
+    }
+    if (L >= 3) {
+        G[9][0] = -6.0 * kY3a * x * y; G[9][1] = -kY3a * (3.0 * x * x - 3.0 * y * y);
+        G[10][0] = kY3b * y * z; G[10][1] = kY3b * x * z; G[10][2] = kY3b * x * y;
+        G[11][1] = -kY3c * (5.0 * z * z - 1.0); G[11][2] = -10.0 * kY3c * y * z;
+        G[12][2] = kY3d * (15.0 * z * z - 3.0);
+        G[13][0] = -kY3c * (5.0 * z * z - 1.0); G[13][2] = -10.0 * kY3c * x * z;
+        G[14][0] = 2.0 * kY3e * x * z; G[14][1] = -2.0 * kY3e * y * z; G[14][2] = kY3e * (x * x - y * y);
+        G[15][0] = -kY3a * (3.0 * x * x - 3.0 * y * y); G[15][1] = 6.0 * kY3a * x * y;
+    }
+}
+
+// World-space part of the chain, shared by every view of a Gaussian.
+struct World {
+    double mu[3], s[3], qn, qh[4], o;
+    double Rq[9], M[9], S[9];
+};
+
+__device__ __forceinline__ void world_chain(const float* rec, World& w) {
+    w.mu[0] = rec[0]; w.mu[1] = rec[1]; w.mu[2] = rec[2];
+    w.s[0] = exp((double)rec[3]); w.s[1] = exp((double)rec[4]); w.s[2] = exp((double)rec[5]);
+    const double qw = rec[6], qx = rec[7], qy = rec[8], qz = rec[9];
+    w.qn = sqrt(((qw * qw + qx * qx) + qy * qy) + qz * qz);
+    w.qh[0] = qw / w.qn; w.qh[1] = qx / w.qn; w.qh[2] = qy / w.qn; w.qh[3] = qz / w.qn;
+    w.o = 1.0 / (1.0 + exp(-(double)rec[10]));
+    const double a = w.qh[0], x = w.qh[1], y = w.qh[2], z = w.qh[3];
+    w.Rq[0] = 1.0 - 2.0 * (y * y + z * z);
+    w.Rq[1] = 2.0 * (x * y - a * z);
+    w.Rq[2] = 2.0 * (x * z + a * y);
+    w.Rq[3] = 2.0 * (x * y + a * z);
+    w.Rq[4] = 1.0 - 2.0 * (x * x + z * z);
+    w.Rq[5] = 2.0 * (y * z - a * x);
+    w.Rq[6] = 2.0 * (x * z - a * y);
+    w.Rq[7] = 2.0 * (y * z + a * x);
+    w.Rq[8] = 1.0 - 2.0 * (x * x + y * y);
+#pragma unroll
+    for (int r = 0; r < 3; r++)
+#pragma unroll
+        for (int k = 0; k < 3; k++) w.M[3 * r + k] = w.Rq[3 * r + k] * w.s[k];
+#pragma unroll
+    for (int r = 0; r < 3; r++)
+#pragma unroll
+        for (int k = 0; k < 3; k++)
+            w.S[3 * r + k] = (w.M[3 * r] * w.M[3 * k] + w.M[3 * r + 1] * w.M[3 * k + 1]) + w.M[3 * r + 2] * w.M[3 * k + 2];
+}
+
+// Camera part of the chain.
+struct Cam {
+    double xc, yc, zc;
+    double Sc[9], J[6];
+    double ap, bp, cp, det;
+};
+
+__device__ __forceinline__ bool camera_chain(const ViewDev& V, const World& w, Cam& c) {
+    const double* R = V.R;
+    c.xc = ((R[0] * w.mu[0] + R[1] * w.mu[1]) + R[2] * w.mu[2]) + V.t[0];
+    c.yc = ((R[3] * w.mu[0] + R[4] * w.mu[1]) + R[5] * w.mu[2]) + V.t[1];
+    c.zc = ((R[6] * w.mu[0] + R[7] * w.mu[1]) + R[8] * w.mu[2]) + V.t[2];
+    if (!(c.zc > kNearZ)) return false;
+    double A[9];
+#pragma unroll
+    for (int r = 0; r < 3; r++)
+#pragma unroll
+        for (int k = 0; k < 3; k++) A[3 * r + k] = (R[3 * r] * w.S[k] + R[3 * r + 1] * w.S[3 + k]) + R[3 * r + 2] * w.S[6 + k];
+#pragma unroll
+    for (int r = 0; r < 3; r++)
+#pragma unroll
+        for (int k = 0; k < 3; k++) c.Sc[3 * r + k] = (A[3 * r] * R[3 * k] + A[3 * r + 1] * R[3 * k + 1]) + A[3 * r + 2] * R[3 * k + 2];
+    const double z2 = c.zc * c.zc;
+    c.J[0] = V.fx / c.zc;
+    c.J[1] = 0.0;
+    c.J[2] = -(V.fx * c.xc) / z2;
+    c.J[3] = 0.0;
+    c.J[4] = V.fy / c.zc;
+    c.J[5] = -(V.fy * c.yc) / z2;
+    double T[6];
+#pragma unroll
+    for (int r = 0; r < 2; r++)
+#pragma unroll
+        for (int k = 0; k < 3; k++) T[3 * r + k] = (c.J[3 * r] * c.Sc[k] + c.J[3 * r + 1] * c.Sc[3 + k]) + c.J[3 * r + 2] * c.Sc[6 + k];
+    const double s00 = (T[0] * c.J[0] + T[1] * c.J[1]) + T[2] * c.J[2];
+    const double s01 = (T[0] * c.J[3] + T[1] * c.J[4]) + T[2] * c.J[5];
+    const double s11 = (T[3] * c.J[3] + T[4] * c.J[4]) + T[5] * c.J[5];
+    c.ap = s00 + kLowPass;
+    c.bp = s01;
+    c.cp = s11 + kLowPass;
+    c.det = c.ap * c.cp - c.bp * c.bp;
+    return true;
+}
+
+template <int L>
+__device__ __forceinline__ void view_dir(const ViewDev& V, const World& w, double d[3], double* dn) {
+    d[0] = w.mu[0] - V.cw[0];
+    d[1] = w.mu[1] - V.cw[1];
+    d[2] = w.mu[2] - V.cw[2];
+    *dn = sqrt((d[0] * d[0] + d[1] * d[1]) + d[2] * d[2]);
+    d[0] /= *dn; d[1] /= *dn; d[2] /= *dn;
+}
+
+template <int L>
+__global__ __launch_bounds__(128) void k_project(const ViewDev* __restrict__ views,
+                                                 const int32_t* __restrict__ frame_views,
+                                                 const int32_t* __restrict__ view_order, int32_t F, int32_t C,
+                                                 int64_t N, int32_t tw, int32_t th,
+                                                 const float* __restrict__ params, pg_splat* __restrict__ splats,
+                                                 pg_bin* __restrict__ bins, uint8_t* __restrict__ visible) {
+    constexpr int NB = (L + 1) * (L + 1);
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= (int64_t)F * N) return;
+    const int32_t f = (int32_t)(g / N);
+    const int64_t i = g - (int64_t)f * N;
+    const int32_t v0 = frame_views[f], v1 = frame_views[f + 1];
+    if (v0 == v1) return;
+    const float* P = params + (int64_t)f * C * N + i;
+    float rec[11];
+#pragma unroll
+    for (int k = 0; k < 11; k++) rec[k] = P[(int64_t)k * N];
+    float sh[3 * NB];
+#pragma unroll
+    for (int k = 0; k < 3 * NB; k++) sh[k] = P[(int64_t)(11 + k) * N];
+    World w;
+    world_chain(rec, w);
+    bool any = false;
+    for (int32_t vi = v0; vi < v1; vi++) {
+        const int32_t v = view_order[vi];
+        const ViewDev& V = views[v];
+        Cam c;
+        float4 o0 = make_float4(0.f, 0.f, 0.f, 0.f), o1 = o0, o2 = o0;
+        uint4 bo = make_uint4(0u, 0u, 0u, 0u);
+        bool ok = camera_chain(V, w, c) && (c.det > kDetMin);
+        if (ok) {
+            const double tr = c.ap + c.cp;
+            const double lam = 0.5 * (tr + sqrt(fmax(0.0, tr * tr - 4.0 * c.det)));
+            const double rr = ceil(3.0 * sqrt(lam));
+            const double mx = (V.fx * c.xc) / c.zc + V.cx;
+            const double my = (V.fy * c.yc) / c.zc + V.cy;
+            const double xlo = fmax(0.0, floor((mx - rr) / (double)tw));
+            const double xhi = fmin((double)(V.TX - 1), floor((mx + rr) / (double)tw));
+            const double ylo = fmax(0.0, floor((my - rr) / (double)th));
+            const double yhi = fmin((double)(V.TY - 1), floor((my + rr) / (double)th));
+            const float zf = (float)c.zc;
+            double d[3], dn;
+            view_dir<L>(V, w, d, &dn);
+            double Y[16];
+            sh_basis<L>(d[0], d[1], d[2], Y);
+            float col[3];
+#pragma unroll
+            for (int ch = 0; ch < 3; ch++) {
+                double acc = 0.0;
+#pragma unroll
+                for (int j = 0; j < NB; j++) acc += Y[j] * (double)sh[3 * j + ch];
+                const double raw = 0.5 + acc;
+                col[ch] = (float)(raw > 0.0 ? raw : 0.0);
+            }
+            const double2 m2 = make_double2(mx, my);
+            o0 = *reinterpret_cast<const float4*>(&m2);
+            o1 = make_float4((float)(c.cp / c.det), (float)(-c.bp / c.det), (float)(c.ap / c.det), (float)w.o);
+            o2 = make_float4(col[0], col[1], col[2], zf);
+            if (xlo <= xhi && ylo <= yhi) {
+                const int32_t ixl = (int32_t)xlo, iyl = (int32_t)ylo, ixh = (int32_t)xhi, iyh = (int32_t)yhi;
+                bo.x = (uint32_t)(ixl & 0xffff) | ((uint32_t)(iyl & 0xffff) << 16);
+                bo.y = (uint32_t)(ixh & 0xffff) | ((uint32_t)(iyh & 0xffff) << 16);
+                bo.z = __float_as_uint(zf);
+                bo.w = (uint32_t)((ixh - ixl + 1) * (iyh - iyl + 1));
+                any = true;
+            }
+        }
+        const int64_t gv = (int64_t)v * N + i;
+        float4* sp = reinterpret_cast<float4*>(splats + gv);
+        sp[0] = o0;
+        sp[1] = o1;
+        sp[2] = o2;
+        reinterpret_cast<uint4*>(bins)[gv] = bo;
+    }
+    if (any) visible[g] = 1;
+}
+
+// ---------------------------------------------------------------- adjoint
+//
+// With Q the conic matrix and Gh = [[da, db/2], [db/2, dc]] (q = a dx^2 +
+// 2 b dx dy + c dy^2): dL/dSigma2D = -Q Gh Q; dL/dSigma_c = J^T (.) J;
+// dL/dJ = 2 (dL/dSigma2D) J Sigma_c; dL/dSigma = W^T (dL/dSigma_c) W;
+// dL/dM = 2 (dL/dSigma) M with M = R(q) diag(s); the mean through J and
+// through dJ/dmu_c; SH through the basis and the view direction.  Texel
+// chain: l_s via s, the raw quaternion via the normalisation, l_o via o (1 - o).
+template <int L>
+__global__ __launch_bounds__(128) void k_project_bwd(const ViewDev* __restrict__ views,
+                                                     const int32_t* __restrict__ frame_views,
+                                                     const int32_t* __restrict__ view_order, int32_t F, int32_t C,
+                                                     int64_t N, int64_t n_gv, const float* __restrict__ params,
+                                                     const float* __restrict__ grad2d,
+                                                     const int32_t* __restrict__ gauss_texel,
+                                                     const uint8_t* __restrict__ dyn, int64_t HW,
+                                                     float* __restrict__ gatlas, int32_t accumulate) {
+    constexpr int NB = (L + 1) * (L + 1);
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= (int64_t)F * N) return;
+    const int32_t f = (int32_t)(g / N);
+    const int64_t i = g - (int64_t)f * N;
+    const int32_t v0 = frame_views[f], v1 = frame_views[f + 1];
+    const float* P = params + (int64_t)f * C * N + i;
+    float rec[11];
+#pragma unroll
+    for (int k = 0; k < 11; k++) rec[k] = P[(int64_t)k * N];
+    float sh[3 * NB];
+#pragma unroll
+    for (int k = 0; k < 3 * NB; k++) sh[k] = P[(int64_t)(11 + k) * N];
+    float acc[11 + 3 * NB];
+#pragma unroll
+    for (int k = 0; k < 11 + 3 * NB; k++) acc[k] = 0.f;
+    World w;
+    bool have_world = false;
+    for (int32_t vi = v0; vi < v1; vi++) {
+        const int32_t v = view_order[vi];
+        const int64_t gv = (int64_t)v * N + i;
+        double g9[9];
+        bool nz = false;
+#pragma unroll
+        for (int k = 0; k < 9; k++) {
+            g9[k] = grad2d[(int64_t)k * n_gv + gv];
+            nz |= (g9[k] != 0.0);
+        }
+        if (!nz) continue;
+        if (!have_world) {
+            world_chain(rec, w);
+            have_world = true;
+        }
+        const ViewDev& V = views[v];
+        Cam c;
+        if (!camera_chain(V, w, c)) continue;
+        const double det = c.det;
+        const double Q00 = c.cp / det, Q01 = -c.bp / det, Q11 = c.ap / det;
+        const double G00 = g9[2], G01 = 0.5 * g9[3], G11 = g9[4];
+        // QG = Q Gh ; GS = -(QG Q)
+        const double QG00 = Q00 * G00 + Q01 * G01, QG01 = Q00 * G01 + Q01 * G11;
+        const double QG10 = Q01 * G00 + Q11 * G01, QG11 = Q01 * G01 + Q11 * G11;
+        const double GS00 = -(QG00 * Q00 + QG01 * Q01);
+        const double GS01 = -(QG00 * Q01 + QG01 * Q11);
+        const double GS11 = -(QG10 * Q01 + QG11 * Q11);
+        // GJ = GS J (2x3)
+        double GJ[6];
+#pragma unroll
+        for (int k = 0; k < 3; k++) {
+            GJ[k] = GS00 * c.J[k] + GS01 * c.J[3 + k];
+            GJ[3 + k] = GS01 * c.J[k] + GS11 * c.J[3 + k];
+        }
+        // dL/dSigma_c = J^T GJ
+        double GSc[9];
+#pragma unroll
+        for (int r = 0; r < 3; r++)
+#pragma unroll
+            for (int k = 0; k < 3; k++) GSc[3 * r + k] = c.J[r] * GJ[k] + c.J[3 + r] * GJ[3 + k];
+        // dL/dJ = 2 GJ Sigma_c
+        double GJm[6];
+#pragma unroll
+        for (int r = 0; r < 2; r++)
+#pragma unroll
+            for (int k = 0; k < 3; k++)
+                GJm[3 * r + k] = 2.0 * (GJ[3 * r] * c.Sc[k] + GJ[3 * r + 1] * c.Sc[3 + k] + GJ[3 * r + 2] * c.Sc[6 + k]);
+        // dL/dSigma = R^T GSc R
+        const double* R = V.R;
+        double tmp[9], GSw[9];
+#pragma unroll
+        for (int r = 0; r < 3; r++)
+#pragma unroll
+            for (int k = 0; k < 3; k++) tmp[3 * r + k] = GSc[3 * r] * R[k] + GSc[3 * r + 1] * R[3 + k] + GSc[3 * r + 2] * R[6 + k];
+#pragma unroll
+        for (int r = 0; r < 3; r++)
+#pragma unroll
+            for (int k = 0; k < 3; k++) GSw[3 * r + k] = R[r] * tmp[k] + R[3 + r] * tmp[3 + k] + R[6 + r] * tmp[6 + k];
+        // dL/dM = 2 GSw M ; dL/ds ; dL/dRq
+        double gs[3] = {0.0, 0.0, 0.0}, GR[9];
+#pragma unroll
+        for (int r = 0; r < 3; r++)
+#pragma unroll
+            for (int k = 0; k < 3; k++) {
+                const double gm = 2.0 * (GSw[3 * r] * w.M[k] + GSw[3 * r + 1] * w.M[3 + k] + GSw[3 * r + 2] * w.M[6 + k]);
+                gs[k] += gm * w.Rq[3 * r + k];
+                GR[3 * r + k] = gm * w.s[k];
+            }
+        const double qa = w.qh[0], qx = w.qh[1], qy = w.qh[2], qz = w.qh[3];
+        double gq[4];
+        gq[0] = 2.0 * (-qz * GR[1] + qy * GR[2] + qz * GR[3] - qx * GR[5] - qy * GR[6] + qx * GR[7]);
+        gq[1] = 2.0 * (qy * GR[1] + qz * GR[2] + qy * GR[3] - 2.0 * qx * GR[4] - qa * GR[5] + qz * GR[6] + qa * GR[7]
+                       - 2.0 * qx * GR[8]);
+        gq[2] = 2.0 * (-2.0 * qy * GR[0] + qx * GR[1] + qa * GR[2] + qx * GR[3] + qz * GR[5] - qa * GR[6] + qz * GR[7]
+                       - 2.0 * qy * GR[8]);
+        gq[3] = 2.0 * (-2.0 * qz * GR[0] - qa * GR[1] + qx * GR[2] + qa * GR[3] - 2.0 * qz * GR[4] + qy * GR[5]
+                       + qx * GR[6] + qy * GR[7]);
+        const double qd = gq[0] * qa + gq[1] * qx + gq[2] * qy + gq[3] * qz;
+        // mean: dm/dmu_c = J, plus the dependence of J on mu_c
+        const double z2 = c.zc * c.zc, z3 = z2 * c.zc;
+        double gmc0 = c.J[0] * g9[0] + c.J[3] * g9[1];
+        double gmc1 = c.J[1] * g9[0] + c.J[4] * g9[1];
+        double gmc2 = c.J[2] * g9[0] + c.J[5] * g9[1];
+        gmc0 += GJm[2] * (-V.fx / z2);
+        gmc1 += GJm[5] * (-V.fy / z2);
+        gmc2 += GJm[0] * (-V.fx / z2) + GJm[2] * (2.0 * V.fx * c.xc / z3) + GJm[4] * (-V.fy / z2)
+                + GJm[5] * (2.0 * V.fy * c.yc / z3);
+        double gmu[3];
+#pragma unroll
+        for (int k = 0; k < 3; k++) gmu[k] = R[k] * gmc0 + R[3 + k] * gmc1 + R[6 + k] * gmc2;
+        // colour
+        double d[3], dn;
+        view_dir<L>(V, w, d, &dn);
+        double Y[16], dY[16][3];
+        sh_basis<L>(d[0], d[1], d[2], Y);
+        sh_basis_grad<L>(d[0], d[1], d[2], dY);
+        double gd0 = 0.0, gd1 = 0.0, gd2 = 0.0;
+#pragma unroll
+        for (int ch = 0; ch < 3; ch++) {
+            double raw = 0.0;
+#pragma unroll
+            for (int j = 0; j < NB; j++) raw += Y[j] * (double)sh[3 * j + ch];
+            raw += 0.5;
+            const double gc = raw < 0.0 ? 0.0 : g9[6 + ch];
+#pragma unroll
+            for (int j = 0; j < NB; j++) {
+                acc[11 + 3 * j + ch] += (float)(Y[j] * gc);
+                const double kk = (double)sh[3 * j + ch] * gc;
+                gd0 += kk * dY[j][0];
+                gd1 += kk * dY[j][1];
+                gd2 += kk * dY[j][2];
+            }
+        }
+        const double dd = gd0 * d[0] + gd1 * d[1] + gd2 * d[2];
+        gmu[0] += (gd0 - d[0] * dd) / dn;
+        gmu[1] += (gd1 - d[1] * dd) / dn;
+        gmu[2] += (gd2 - d[2] * dd) / dn;
+#pragma unroll
+        for (int k = 0; k < 3; k++) {
+            acc[k] += (float)gmu[k];
+            acc[3 + k] += (float)(w.s[k] * gs[k]);
+        }
+#pragma unroll
+        for (int k = 0; k < 4; k++) acc[6 + k] += (float)((gq[k] - w.qh[k] * qd) / w.qn);
+        acc[10] += (float)(g9[5] * w.o * (1.0 - w.o));
+    }
+    const int64_t texel = gauss_texel[i];
+    const float m = dyn ? (dyn[texel] ? 1.f : 0.f) : 1.f;
+    float* out = gatlas + (int64_t)f * C * HW + texel;
+#pragma unroll
+    for (int k = 0; k < 11 + 3 * NB; k++) {
+        if (accumulate) out[(int64_t)k * HW] += m * acc[k];
+        else out[(int64_t)k * HW] = m * acc[k];
+    }
+}
+
+}  // namespace
+
+hipError_t launch_project(const pg_views* v, const float* params, pg_splat* splats, pg_bin* bins,
+                          uint8_t* visible, hipStream_t s) {
+    const int64_t n = (int64_t)v->frames * v->n_gauss;
+    if (n == 0) return hipSuccess;
+    const unsigned grid = (unsigned)ceil_div(n, 128);
+    auto args = [&](auto kern) {
+        kern<<<grid, 128, 0, s>>>(v->d_views, v->d_frame_views, v->d_view_order, v->frames, v->channels, v->n_gauss,
+                                  v->tiling.tile_w, v->tiling.tile_h, params, splats, bins, visible);
+    };
+    switch (v->sh_degree) {
+        case 0: args(k_project<0>); break;
+        case 1: args(k_project<1>); break;
+        case 2: args(k_project<2>); break;
+        default: args(k_project<3>); break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_project_bwd(const pg_views* v, const float* params, const float* grad2d,
+                              const int32_t* gauss_texel, const uint8_t* dyn, int32_t H, int32_t W,
+                              float* dL_datlas, int32_t accumulate, hipStream_t s) {
+    const int64_t HW = (int64_t)H * W;
+    if (!accumulate) {
+        hipError_t e = fill_u32(dL_datlas, 0u, (int64_t)v->frames * v->channels * HW, s);
+        if (e != hipSuccess) return e;
+    }
+    const int64_t n = (int64_t)v->frames * v->n_gauss;
+    if (n == 0) return hipGetLastError();
+    const unsigned grid = (unsigned)ceil_div(n, 128);
+    auto args = [&](auto kern) {
+        kern<<<grid, 128, 0, s>>>(v->d_views, v->d_frame_views, v->d_view_order, v->frames, v->channels, v->n_gauss,
+                                  v->n_gv, params, grad2d, gauss_texel, dyn, HW, dL_datlas, accumulate);
+    };
+    switch (v->sh_degree) {
+        case 0: args(k_project_bwd<0>); break;
+        case 1: args(k_project_bwd<1>); break;
+        case 2: args(k_project_bwd<2>); break;
+        default: args(k_project_bwd<3>); break;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace pg

@@ -1,0 +1,263 @@
+"""Buffers and call chains for one fitting step of PackUV-GS splatting.
+
+``Renderer`` owns every device buffer the C ABI needs (torch is used only to
+allocate device memory and to supply the current stream) and runs the chain
+
+    pg_atlas_fetch -> pg_project -> pg_bin_sort -> pg_render_fwd   (forward)
+    pg_loss_l1                                                      (L1 term)
+    pg_render_bwd                                                   (adjoint)
+    pg_adam_step                                                    (optional)
+
+in one of two modes over the same kernels:
+
+* batched: one view table holding every view (and frame); one call chain,
+  no host synchronisation, so the whole step can be captured in a HIP graph
+  and replayed;
+* plain: one view table per view; each view runs its own
+  project / bin-sort / render chain and the host reads that view's instance
+  count (one synchronisation per view) before compositing it.
+
+``PackUVRender`` wraps the forward and adjoint as a ``torch.autograd.Function``.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+import torch
+
+from . import _abi as abi
+
+
+def _u8(x, device):
+    return torch.as_tensor(np.ascontiguousarray(x, np.uint8)).to(device)
+
+
+class _ViewSet:
+    """One pg_views table plus the per-(view, Gaussian) and per-instance buffers."""
+
+    def __init__(self, cams, frames, n_gauss, sh_degree, tiling, device, inst_capacity):
+        self.cams = list(cams)
+        self.handle = abi.pg_views_create(self.cams, frames, n_gauss, sh_degree, tiling)
+        self.info = abi.pg_views_get_info(self.handle)
+        self.tile_base, self.pix_base = abi.pg_views_offsets(self.handle, len(self.cams))
+        n_gv = self.info.n_gv
+        self.splats = torch.empty(max(n_gv, 1) * abi.SPLAT_BYTES // 4, dtype=torch.float32, device=device)
+        self.bins = torch.empty(max(n_gv, 1) * abi.BIN_BYTES // 4, dtype=torch.int32, device=device)
+        self.grad2d = torch.empty(max(9 * n_gv, 1), dtype=torch.float32, device=device)
+        self.ranges = torch.empty(2 * max(self.info.n_tiles, 1), dtype=torch.int32, device=device)
+        self.n_inst = torch.zeros(1, dtype=torch.int64, device=device)
+        self.overflow = torch.zeros(1, dtype=torch.int32, device=device)
+        self.device = device
+        self.set_capacity(inst_capacity)
+
+    def set_capacity(self, cap):
+        cap = int(max(cap, 1))
+        self.cap = cap
+        self.keys = torch.empty(cap, dtype=torch.int64, device=self.device)
+        self.values = torch.empty(cap, dtype=torch.int32, device=self.device)
+        self.ws_bytes = abi.pg_sort_workspace_size(self.handle, cap)
+        self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.device)
+
+    def close(self):
+        if self.handle:
+            abi.pg_views_destroy(self.handle)
+            self.handle = None
+
+
+class Renderer:
+    """Device state for fitting one atlas window rendered into a set of views.
+
+    occupancy: (H, W) uint8 (host array), shared by all frames.
+    cams: camera objects with R (3x3), t, fx, fy, cx, cy, width, height, frame.
+    """
+
+    def __init__(self, occupancy, frames, sh_degree, cams, tiling=(16, 16, 256), batched=True, bg=(0.0, 0.0, 0.0),
+                 dynamic=None, inst_capacity=None, device="cuda", init=True):
+        self.device = torch.device(device)
+        if init:
+            abi.pg_init(self.device.index or 0)
+        occ = np.ascontiguousarray(occupancy, np.uint8)
+        self.H, self.W = occ.shape
+        self.frames = int(frames)
+        self.sh_degree = int(sh_degree)
+        self.C = 11 + 3 * (self.sh_degree + 1) ** 2
+        self.N = int(np.count_nonzero(occ))
+        self.cams = list(cams)
+        self.V = len(self.cams)
+        self.bg = tuple(float(b) for b in bg)
+        self.batched = bool(batched)
+        self.tiling = abi.make_tiling(*tiling)
+        dev = self.device
+        self.occ = _u8(occ, dev)
+        self.dynamic = None if dynamic is None else _u8(dynamic, dev)
+        self.gauss_texel = torch.empty(max(self.N, 1), dtype=torch.int32, device=dev)
+        self.texel_gauss = torch.empty(self.H * self.W, dtype=torch.int32, device=dev)
+        self.params = torch.empty(max(self.frames * self.C * self.N, 1), dtype=torch.float32, device=dev)
+        self.n_gauss_dev = torch.zeros(1, dtype=torch.int64, device=dev)
+        self.fetch_ws_bytes = abi.pg_fetch_workspace_size(self.H, self.W)
+        self.fetch_ws = torch.empty(self.fetch_ws_bytes, dtype=torch.uint8, device=dev)
+        self.visible = torch.zeros(max(self.frames * self.N, 1), dtype=torch.uint8, device=dev)
+        self.dL_datlas = torch.empty(self.frames * self.C * self.H * self.W, dtype=torch.float32, device=dev)
+        self.loss_partial = torch.empty(1024, dtype=torch.float64, device=dev)
+        self.loss = torch.zeros(1, dtype=torch.float32, device=dev)
+        if inst_capacity is None:
+            inst_capacity = 64 * max(self.N, 1) * (self.V if batched else 1)
+        if batched:
+            self.sets = [_ViewSet(self.cams, self.frames, self.N, self.sh_degree, self.tiling, dev, inst_capacity)]
+            self.pix_base = self.sets[0].pix_base
+        else:
+            self.sets = [_ViewSet([c], self.frames, self.N, self.sh_degree, self.tiling, dev, inst_capacity)
+                         for c in self.cams]
+            pb = [0]
+            for c in self.cams:
+                pb.append(pb[-1] + c.width * c.height)
+            self.pix_base = pb
+        self.n_pixels = self.pix_base[-1]
+        self.image = torch.empty(3 * self.n_pixels, dtype=torch.float32, device=dev)
+        self.final_T = torch.empty(self.n_pixels, dtype=torch.float32, device=dev)
+        self.n_contrib = torch.empty(self.n_pixels, dtype=torch.int32, device=dev)
+        self.dL_dimage = torch.empty(3 * self.n_pixels, dtype=torch.float32, device=dev)
+        self.counters = torch.zeros(2, dtype=torch.int64, device=dev)
+        self.adam_m = None
+        self.adam_v = None
+        self.adam_t = 0
+
+    # ------------------------------------------------------------------ helpers
+    def close(self):
+        for s in self.sets:
+            s.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def view_image(self, v):
+        c = self.cams[v]
+        o = 3 * self.pix_base[v]
+        return self.image[o:o + 3 * c.width * c.height].view(3, c.height, c.width)
+
+    def view_slice(self, buf, v, per_pixel=1):
+        c = self.cams[v]
+        o = per_pixel * self.pix_base[v]
+        return buf[o:o + per_pixel * c.width * c.height]
+
+    def _off(self, t, elems):
+        return t.data_ptr() + elems * t.element_size()
+
+    def grow_capacity(self, factor=1.25):
+        """Re-size instance buffers from the last counts (after an overflow)."""
+        for s in self.sets:
+            need = int(s.n_inst.item())
+            if need > s.cap:
+                s.set_capacity(int(math.ceil(need * factor)))
+
+    def overflowed(self) -> bool:
+        return any(int(s.overflow.item()) for s in self.sets)
+
+    # ------------------------------------------------------------------ stages
+    def fetch(self, atlas: torch.Tensor):
+        assert atlas.is_contiguous() and atlas.dtype == torch.float32
+        assert atlas.numel() == self.frames * self.C * self.H * self.W
+        abi.pg_atlas_fetch(atlas, self.occ, self.frames, self.C, self.H, self.W, self.N, self.gauss_texel,
+                           self.texel_gauss, self.params, self.n_gauss_dev, self.fetch_ws, self.fetch_ws_bytes)
+
+    def _project_sort_render(self, s: _ViewSet, pix_off: int, counters):
+        abi.pg_project(s.handle, self.params, s.splats, s.bins, self.visible)
+        abi.pg_bin_sort(s.handle, s.bins, s.cap, s.keys, s.values, s.ranges, s.n_inst, s.overflow, s.ws, s.ws_bytes)
+        if not self.batched:
+            # plain path: one instance-count synchronisation per view
+            if int(s.overflow.item()):
+                s.set_capacity(int(math.ceil(int(s.n_inst.item()) * 1.25)))
+                abi.pg_bin_sort(s.handle, s.bins, s.cap, s.keys, s.values, s.ranges, s.n_inst, s.overflow, s.ws,
+                                s.ws_bytes)
+        abi.pg_render_fwd(s.handle, s.splats, s.values, s.ranges, self.bg, self._off(self.image, 3 * pix_off),
+                          self._off(self.final_T, pix_off), self._off(self.n_contrib, pix_off), counters)
+
+    def forward(self, atlas: torch.Tensor, counters: bool = False) -> torch.Tensor:
+        """Render every view; returns the flat image buffer (valid until the next call)."""
+        self.fetch(atlas)
+        self.visible.zero_()
+        cnt = self.counters if counters else None
+        if counters:
+            self.counters.zero_()
+        for k, s in enumerate(self.sets):
+            self._project_sort_render(s, self.pix_base[k] if not self.batched else 0, cnt)
+        return self.image
+
+    def loss_l1(self, target: torch.Tensor) -> torch.Tensor:
+        n = 3 * self.n_pixels
+        abi.pg_loss_l1(self.image, target, n, self.dL_dimage, self.loss_partial, self.loss)
+        return self.loss
+
+    def backward(self, dL_dimage: torch.Tensor | None = None) -> torch.Tensor:
+        """Texel gradients for the cotangent of the flat image (default: the L1 gradient)."""
+        g = self.dL_dimage if dL_dimage is None else dL_dimage
+        assert g.is_contiguous() and g.numel() == 3 * self.n_pixels
+        if self.batched:
+            s = self.sets[0]
+            abi.pg_render_bwd(s.handle, self.params, s.splats, s.values, s.ranges, self.bg, self.final_T,
+                              self.n_contrib, g, self.gauss_texel, self.dynamic, self.H, self.W, s.grad2d,
+                              self.dL_datlas, 0)
+        else:
+            self.dL_datlas.zero_()
+            for k, s in enumerate(self.sets):
+                po = self.pix_base[k]
+                abi.pg_render_bwd(s.handle, self.params, s.splats, s.values, s.ranges, self.bg,
+                                  self._off(self.final_T, po), self._off(self.n_contrib, po), self._off(g, 3 * po),
+                                  self.gauss_texel, self.dynamic, self.H, self.W, s.grad2d, self.dL_datlas, 1)
+        return self.dL_datlas
+
+    def adam_step(self, atlas: torch.Tensor, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
+        if self.adam_m is None:
+            self.adam_m = torch.zeros_like(atlas)
+            self.adam_v = torch.zeros_like(atlas)
+        self.adam_t += 1
+        abi.pg_adam_step(atlas, self.dL_datlas, self.adam_m, self.adam_v, self.visible, self.texel_gauss, self.N,
+                         self.frames, self.C, self.H, self.W, lr, b1, b2, eps, self.adam_t)
+
+    def step(self, atlas, target, adam=False):
+        """One fitting step: forward, L1 loss, adjoint (and Adam)."""
+        self.forward(atlas)
+        self.loss_l1(target)
+        self.backward()
+        if adam:
+            self.adam_step(atlas)
+        return self.loss
+
+    # ------------------------------------------------------------------ readback helpers (tests)
+    def splat_records(self, k=0):
+        """numpy structured view of a view set's pg_splat records."""
+        dt = np.dtype([("mean", "<f8", (2,)), ("conic", "<f4", (3,)), ("opacity", "<f4"), ("color", "<f4", (3,)),
+                       ("depth", "<f4")])
+        s = self.sets[k]
+        return s.splats.cpu().numpy().view(np.uint8)[:s.info.n_gv * 48].view(dt)
+
+    def bin_records(self, k=0):
+        dt = np.dtype([("rect", "<i2", (4,)), ("key", "<u4"), ("n_tiles", "<i4")])
+        s = self.sets[k]
+        return s.bins.cpu().numpy().view(np.uint8)[:s.info.n_gv * 16].view(dt)
+
+    def sorted_instances(self, k=0):
+        s = self.sets[k]
+        n = int(s.n_inst.item())
+        return s.keys[:n].cpu().numpy().view(np.uint64), s.values[:n].cpu().numpy()
+
+
+class PackUVRender(torch.autograd.Function):
+    """images = PackUVRender.apply(atlas, renderer): flat image buffer of every view.
+
+    The backward returns dL/datlas (with the renderer's gradient-freeze mask
+    applied) and nothing for the renderer."""
+
+    @staticmethod
+    def forward(ctx, atlas, renderer):
+        ctx.renderer = renderer
+        return renderer.forward(atlas.contiguous()).clone()
+
+    @staticmethod
+    def backward(ctx, grad):
+        return ctx.renderer.backward(grad.contiguous()).view(ctx.renderer.frames, ctx.renderer.C, ctx.renderer.H,
+                                                             ctx.renderer.W).clone(), None

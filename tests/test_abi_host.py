@@ -1,0 +1,76 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports
+every function the header declares, and rejects bad arguments before
+touching the device."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+from paper_2602_23040_amd import _abi as abi
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    src = open(os.path.join(ROOT, "include", "packuv_gs.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(pg_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_header_declares_the_five_hot_path_calls():
+    fns = header_functions()
+    for name in ("pg_atlas_fetch", "pg_project", "pg_bin_sort", "pg_render_fwd", "pg_render_bwd"):
+        assert name in fns
+
+
+def test_library_exports_every_declared_symbol():
+    lib = abi.lib()
+    for name in header_functions():
+        assert hasattr(lib, name), name
+    assert set(header_functions()) == set(abi.SIGNATURES), "binding and header disagree"
+
+
+def _cam(**kw):
+    import numpy as np
+    import synth
+    c = synth.pinhole(np.eye(3), np.zeros(3), 64, 48)
+    for k, v in kw.items():
+        setattr(c, k, v)
+    return c
+
+
+@pytest.mark.parametrize("kw,needle", [
+    (dict(fx=0.0), "fx and fy"),
+    (dict(width=0), "width and height"),
+    (dict(frame=3), "frame out of range"),
+])
+def test_views_create_rejects_bad_cameras(kw, needle):
+    with pytest.raises(abi.PGError) as e:
+        abi.pg_views_create([_cam(**kw)], 1, 10, 0, abi.make_tiling())
+    assert e.value.status == -1 and needle in str(e.value)
+
+
+@pytest.mark.parametrize("tiling", [(16, 8, 256), (8, 32, 100), (32, 32, 64)])
+def test_views_create_rejects_bad_tiling(tiling):
+    with pytest.raises(abi.PGError) as e:
+        abi.pg_views_create([_cam()], 1, 10, 0, abi.make_tiling(*tiling))
+    assert e.value.status == -1
+
+
+def test_views_create_rejects_bad_sh_degree_and_overflow():
+    with pytest.raises(abi.PGError):
+        abi.pg_views_create([_cam()], 1, 10, 4, abi.make_tiling())
+    with pytest.raises(abi.PGError) as e:
+        abi.pg_views_create([_cam()] * 3, 1, 2 ** 30, 0, abi.make_tiling())
+    assert "2^31" in str(e.value)
+
+
+def test_entry_points_reject_null_pointers():
+    lib = abi.lib()
+    assert lib.pg_loss_l1(None, None, 10, None, None, None, None) == -1
+    assert "null" in abi.pg_last_error()
+    assert lib.pg_adam_step(None, None, None, None, None, None, 1, 1, 1, 1, 1, 0.1, 0.9, 0.99, 1e-8, 1, None) == -1
+    n = C.c_size_t()
+    assert lib.pg_fetch_workspace_size(0, 5, C.byref(n)) == -1
+    assert lib.pg_fetch_workspace_size(64, 64, C.byref(n)) == 0 and n.value > 0

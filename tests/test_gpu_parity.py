@@ -1,0 +1,264 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle on the
+same seeded scenes (tiny ragged scenes, a multi-frame window, and the two
+workloads small enough for the oracle to finish in seconds: the 64x64-atlas
+single view and the 256x256-atlas ring of eight 512x512 views)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from parity import (IMG_TOL, atlas_tensor, explain, gpu_images, grad_compare, renderer, run_forward, say)
+
+pytestmark = pytest.mark.gpu
+
+SCENES = {
+    "tiny": lambda: synth.random_scene(side=12, sh_degree=1, views=3, width=72, height=56, seed=0,
+                                       lscale=(-2.8, 0.5)),
+    "ragged": lambda: synth.random_scene(side=20, sh_degree=3, views=2, width=100, height=37, seed=1,
+                                         occupancy=0.7, lscale=(-3.0, 0.6)),
+    "multiframe": lambda: synth.random_scene(side=10, sh_degree=2, views=2, width=64, height=50, seed=2, frames=3,
+                                             lscale=(-2.7, 0.5), dynamic_frac=0.5),
+    "config1": lambda: synth.make_scene(1),
+    "config2": lambda: synth.make_scene(2),
+}
+
+_cache = {}
+
+
+def case(name):
+    if name not in _cache:
+        say(f"[case] {name}: building scene and oracle forward")
+        sc = SCENES[name]()
+        fw = oracle.Forward(sc)
+        _cache[name] = (sc, fw)
+    return _cache[name]
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    yield
+
+
+@pytest.mark.parametrize("name", list(SCENES))
+def test_fetch_project_sort_bit_exact(name):
+    sc, fw = case(name)
+    say(f"[gpu] fetch/project/sort {name}")
+    r = renderer(sc)
+    run_forward(r, atlas_tensor(sc))
+    N = r.N
+    assert int(r.n_gauss_dev.item()) == N == fw.n_gauss
+    assert np.array_equal(r.gauss_texel[:N].cpu().numpy(), fw.ids)
+    tg = r.texel_gauss.cpu().numpy()
+    exp_tg = np.full(sc.H * sc.W, -1, np.int32)
+    exp_tg[fw.ids] = np.arange(N, dtype=np.int32)
+    assert np.array_equal(tg, exp_tg)
+    P = r.params[:sc.frames * sc.C * N].cpu().numpy().reshape(sc.frames, sc.C, N)
+    assert np.array_equal(P.astype(np.float64), fw.params)
+    spl, bins = r.splat_records(), r.bin_records()
+    keys, vals = r.sorted_instances()
+    tb = r.sets[0].tile_base
+    exp_keys, exp_vals = [], []
+    for v in range(len(sc.cams)):
+        pr = fw.proj[v]
+        sl = slice(v * N, (v + 1) * N)
+        b, s = bins[sl], spl[sl]
+        valid = pr["valid"] == 1
+        assert np.array_equal(b["n_tiles"] > 0, valid), f"view {v}: cull decisions differ"
+        assert np.array_equal(b["rect"][valid], pr["rect"][valid].astype(np.int16))
+        assert np.array_equal(b["key"][valid], pr["key"][valid])
+        assert np.array_equal(s["mean"][valid], pr["mean"][valid]), f"view {v}: FP64 means differ"
+        np.testing.assert_allclose(s["conic"][valid], pr["conic"][valid], rtol=1e-6, atol=1e-9)
+        np.testing.assert_allclose(s["opacity"][valid], pr["opacity"][valid], rtol=1e-6)
+        np.testing.assert_allclose(s["color"][valid], pr["color"][valid], rtol=1e-6, atol=1e-7)
+        assert np.array_equal(s["depth"][valid].view(np.uint32), pr["key"][valid])
+        inst = fw.inst[v]
+        exp_keys.append(((inst["tile"].astype(np.uint64) + np.uint64(tb[v])) << np.uint64(32))
+                        | inst["key"].astype(np.uint64))
+        exp_vals.append(inst["id"].astype(np.int64) + v * N)
+        rg = r.sets[0].ranges.cpu().numpy().reshape(-1, 2)[tb[v]:tb[v + 1]]
+        ref_rg = fw.ranges[v]
+        nz = ref_rg[:, 1] > ref_rg[:, 0]
+        off = sum(len(fw.inst[u]) for u in range(v))
+        assert np.array_equal(rg[nz].astype(np.int64), ref_rg[nz] + off)
+        assert np.all(rg[~nz, 0] == rg[~nz, 1])
+    exp_keys = np.concatenate(exp_keys)
+    exp_vals = np.concatenate(exp_vals)
+    assert keys.size == exp_keys.size
+    assert np.array_equal(keys, exp_keys), "sorted keys differ"
+    assert np.array_equal(vals.astype(np.int64), exp_vals), "sorted values differ"
+    vis = r.visible[:sc.frames * N].cpu().numpy().reshape(sc.frames, N)
+    assert np.array_equal(vis, fw.visible())
+    r.close()
+
+
+@pytest.mark.parametrize("name", list(SCENES))
+def test_render_forward_parity(name):
+    sc, fw = case(name)
+    say(f"[gpu] render_fwd {name}")
+    r = renderer(sc)
+    run_forward(r, atlas_tensor(sc))
+    imgs = gpu_images(r)
+    total_bad = total_unexp = 0
+    for v in range(len(sc.cams)):
+        gi, gT, gn = imgs[v]
+        flips, unexp, nbad = explain(fw, v, gi)
+        total_bad += nbad
+        total_unexp += len(unexp)
+        ok = np.ones(gn.shape, bool)
+        for p in flips:
+            ok.reshape(-1)[p] = False
+        err = np.abs(gi - fw.image[v]).max(0)
+        assert err[ok].max() <= IMG_TOL if ok.any() else True
+        assert np.abs(gT - fw.T[v])[ok].max() <= IMG_TOL
+        agree = (gn == fw.n[v])[ok].mean() if ok.any() else 1.0
+        assert agree >= 0.999, f"view {v}: n_contrib agrees on {agree:.5f} of pixels"
+    say(f"[gpu] {name}: pixels beyond 1e-4: {total_bad}, unexplained: {total_unexp}")
+    assert total_unexp == 0
+    r.close()
+
+
+@pytest.mark.parametrize("name", list(SCENES))
+def test_backward_parity(name):
+    sc, fw = case(name)
+    say(f"[gpu] render_bwd {name}")
+    rng = np.random.default_rng(123)
+    targets = {v: rng.uniform(0, 1, fw.image[v].shape) for v in fw.views}
+    L, G = fw.loss(targets)
+    r = renderer(sc)
+    atlas = atlas_tensor(sc)
+    run_forward(r, atlas)
+    imgs = gpu_images(r)
+    flips = {}
+    for v in range(len(sc.cams)):
+        fl, unexp, _ = explain(fw, v, imgs[v][0])
+        assert not unexp
+        if fl:
+            flips[v] = fl
+    g_flat = np.concatenate([G[v].reshape(-1) for v in fw.views]).astype(np.float32)
+    gt = torch.from_numpy(g_flat).to("cuda:0")
+    r.backward(gt)
+    torch.cuda.synchronize()
+    ref_atlas, ref_g2 = fw.backward(G, flips=flips)
+    got = r.dL_datlas.cpu().numpy().reshape(sc.frames, sc.C, sc.H, sc.W)
+    occ = sc.occupancy.astype(bool)
+    assert np.all(got[:, :, ~occ] == 0.0)
+    # per (view, Gaussian) 2D gradients
+    g2 = r.sets[0].grad2d[:9 * r.sets[0].info.n_gv].cpu().numpy().reshape(9, len(sc.cams), r.N)
+    for v in range(len(sc.cams)):
+        st = grad_compare(g2[:, v, :][None], ref_g2[v].T[None])
+        say(f"[gpu] {name} view {v} grad2d: {st}")
+        assert st["n_bad"] == 0 and st["worst_l2"] <= 1e-3, st
+    st = grad_compare(got.reshape(sc.frames, sc.C, -1)[:, :, occ.reshape(-1)],
+                      ref_atlas.reshape(sc.frames, sc.C, -1)[:, :, occ.reshape(-1)])
+    say(f"[gpu] {name} dL/datlas: {st}")
+    assert st["n_bad"] == 0 and st["worst_l2"] <= 1e-3, st
+    r.close()
+
+
+def test_loss_l1_parity():
+    sc, fw = case("tiny")
+    r = renderer(sc)
+    run_forward(r, atlas_tensor(sc))
+    rng = np.random.default_rng(5)
+    tgt = rng.uniform(0, 1, 3 * r.n_pixels).astype(np.float32)
+    loss = float(r.loss_l1(torch.from_numpy(tgt).to("cuda:0")).item())
+    img = r.image.cpu().numpy().astype(np.float64)
+    L, G = oracle.loss_l1(img, tgt.astype(np.float64))
+    assert abs(loss - L) <= 1e-6 * max(1.0, L)
+    np.testing.assert_array_equal(r.dL_dimage.cpu().numpy(), G.astype(np.float32))
+    r.close()
+
+
+def test_adam_parity():
+    sc, fw = case("multiframe")
+    r = renderer(sc)
+    atlas = atlas_tensor(sc)
+    run_forward(r, atlas)
+    rng = np.random.default_rng(6)
+    g = rng.standard_normal(atlas.numel()).astype(np.float32)
+    r.dL_datlas.copy_(torch.from_numpy(g))
+    p = sc.atlas.reshape(-1).astype(np.float64).copy()
+    m = np.zeros_like(p)
+    vv = np.zeros_like(p)
+    vis_g = fw.visible()                                     # (F, N)
+    vis_t = np.zeros((sc.frames, sc.H * sc.W), np.uint8)
+    vis_t[:, fw.ids] = vis_g
+    vis_e = np.broadcast_to(vis_t[:, None, :], (sc.frames, sc.C, sc.H * sc.W)).reshape(-1)
+    for step in (1, 2, 3):
+        r.adam_step(atlas, lr=1e-2)
+        oracle.adam(p, g.astype(np.float64), m, vv, np.ascontiguousarray(vis_e), 1e-2, 0.9, 0.999, 1e-8, step)
+    got = atlas.cpu().numpy().astype(np.float64)
+    np.testing.assert_allclose(got, p, rtol=1e-5, atol=1e-6)
+    r.close()
+
+
+def test_tile_shape_and_batch_invariance():
+    sc, fw = case("ragged")
+    ref = None
+    for tiling in [(16, 16, 256), (16, 16, 64), (8, 32, 128), (32, 8, 256), (32, 8, 64)]:
+        say(f"[gpu] tiling {tiling}")
+        r = renderer(sc, tiling=tiling)
+        run_forward(r, atlas_tensor(sc))
+        img = r.image.cpu().numpy()
+        if ref is None:
+            ref = img
+        else:
+            assert np.array_equal(img, ref), f"image differs for tiling {tiling}"
+        r.close()
+
+
+def test_batched_equals_plain():
+    sc, fw = case("tiny")
+    atlas = atlas_tensor(sc)
+    out = []
+    for batched in (True, False):
+        say(f"[gpu] batched={batched}")
+        r = renderer(sc, batched=batched)
+        run_forward(r, atlas)
+        rng = np.random.default_rng(7)
+        tgt = torch.from_numpy(rng.uniform(0, 1, 3 * r.n_pixels).astype(np.float32)).to("cuda:0")
+        r.loss_l1(tgt)
+        r.backward()
+        torch.cuda.synchronize()
+        out.append((r.image.cpu().numpy(), r.dL_datlas.cpu().numpy()))
+        r.close()
+    assert np.array_equal(out[0][0], out[1][0])
+    st = grad_compare(out[1][1].reshape(sc.frames, sc.C, -1), out[0][1].reshape(sc.frames, sc.C, -1), rel=1e-4)
+    assert st["n_bad"] == 0, st
+
+
+def test_empty_atlas_renders_background():
+    sc = synth.random_scene(side=4, sh_degree=0, views=2, width=40, height=24, seed=0)
+    sc.occupancy[:] = 0
+    sc.atlas[:] = 0
+    sc.bg = (0.1, 0.2, 0.3)
+    r = renderer(sc)
+    run_forward(r, atlas_tensor(sc))
+    img = r.image.cpu().numpy().reshape(-1)
+    for v, c in enumerate(sc.cams):
+        im = img[3 * r.pix_base[v]:3 * r.pix_base[v + 1]].reshape(3, c.height, c.width)
+        for ch in range(3):
+            assert np.all(im[ch] == np.float32(sc.bg[ch]))
+    r.backward(torch.ones(3 * r.n_pixels, device="cuda:0"))
+    assert float(r.dL_datlas.abs().max().item()) == 0.0
+    r.close()
+
+
+def test_capacity_overflow_is_reported_and_recovered():
+    sc, fw = case("tiny")
+    r = renderer(sc, cap=16)
+    r.forward(atlas_tensor(sc))
+    torch.cuda.synchronize()
+    s = r.sets[0]
+    assert int(s.overflow.item()) == 1
+    need = int(s.n_inst.item())
+    assert need == sum(len(fw.inst[v]) for v in fw.views)
+    r.grow_capacity()
+    run_forward(r, atlas_tensor(sc))
+    img = gpu_images(r)
+    for v in fw.views:
+        assert np.abs(img[v][0] - fw.image[v]).max() < 1e-3
+    r.close()
