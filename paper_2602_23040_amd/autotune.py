@@ -1,0 +1,90 @@
+"""Autotuner for the compositing launch shape.
+
+Sweeps tile shape (16x16, 8x32, 32x8; width x height) and Gaussians staged
+in LDS per batch (64, 128, 256) on the caller's workload, timing the batched
+fwd+bwd chain with HIP events, and keeps the fastest.  Results are cached in
+a JSON file keyed by device name and workload (atlas size, Gaussian count,
+views and their resolutions), so later runs reuse the choice.
+"""
+from __future__ import annotations
+
+import hashlib
+import json
+import os
+
+CANDIDATES = [(16, 16, 64), (16, 16, 128), (16, 16, 256), (8, 32, 64), (8, 32, 128), (8, 32, 256),
+              (32, 8, 64), (32, 8, 128), (32, 8, 256)]
+
+
+def cache_path() -> str:
+    return os.environ.get("PACKUV_TUNE_CACHE",
+                          os.path.join(os.path.expanduser("~"), ".cache", "packuv_gs", "tune.json"))
+
+
+def workload_key(scene, device_name: str) -> str:
+    h = hashlib.sha256()
+    h.update(f"{scene.W}x{scene.H}x{scene.frames}|{scene.n_gauss}|{scene.sh_degree}".encode())
+    for c in scene.cams:
+        h.update(f"{c.width}x{c.height}f{c.frame}".encode())
+        h.update(bytes(memoryview(c.R.tobytes())))
+    return f"{device_name}|{h.hexdigest()[:16]}"
+
+
+def _load(path):
+    try:
+        with open(path) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return {}
+
+
+def choose(scene, atlas, device="cuda:0", reps=3, candidates=CANDIDATES, use_cache=True):
+    """Returns ((tile_w, tile_h, lds_batch), info)."""
+    import torch
+
+    from .pipeline import Renderer
+
+    dev = torch.device(device)
+    name = torch.cuda.get_device_name(dev)
+    key = workload_key(scene, name)
+    path = cache_path()
+    cache = _load(path) if use_cache else {}
+    if key in cache:
+        t = tuple(cache[key]["tiling"])
+        return t, {"source": "cache", "key": key, "tiling": list(t), "ms": cache[key]["ms"]}
+    target = None
+    timings = {}
+    cap = None
+    for cand in candidates:
+        r = Renderer(scene.occupancy, scene.frames, scene.sh_degree, scene.cams, tiling=cand, batched=True,
+                     bg=scene.bg, inst_capacity=cap, device=dev)
+        r.forward(atlas)
+        torch.cuda.synchronize()
+        if r.overflowed():
+            r.grow_capacity(1.1)
+        cap = r.sets[0].cap
+        if target is None:
+            target = torch.rand(3 * r.n_pixels, device=dev, generator=torch.Generator(dev).manual_seed(0))
+        r.step(atlas, target)
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(reps):
+            r.step(atlas, target)
+        b.record()
+        torch.cuda.synchronize()
+        timings["x".join(map(str, cand))] = a.elapsed_time(b) / reps
+        r.close()
+        del r
+    best = min(timings, key=timings.get)
+    t = tuple(int(x) for x in best.split("x"))
+    if use_cache:
+        cache[key] = {"tiling": list(t), "ms": timings[best], "all_ms": timings}
+        try:
+            os.makedirs(os.path.dirname(path), exist_ok=True)
+            with open(path, "w") as f:
+                json.dump(cache, f, indent=1)
+        except OSError:
+            pass
+    return t, {"source": "sweep", "key": key, "tiling": list(t), "ms": round(timings[best], 3),
+               "all_ms": {k: round(v, 3) for k, v in timings.items()}}

@@ -17,8 +17,10 @@
 // XCD (the dispatcher deals groups round-robin over the 8 XCDs), which keeps
 // the records that neighbouring tiles share in one L2.
 //
-// Pixel offsets inside a tile are formed in tile-local FP32 coordinates from
-// the FP64 pixel-space mean, so q keeps full FP32 precision at 1080p.
+// Pixel offsets are formed in FP32 coordinates local to the 32x32 pixel block
+// holding the tile (every supported tile shape nests in such a block), from
+// the FP64 pixel-space mean: q keeps full FP32 precision at 1080p, and a
+// pixel sees bit-identical inputs whatever the tile shape.
 //
 // The adjoint walks each pixel's composited Gaussians back to front,
 // recovering the transmittance in front of Gaussian k as T_k = T_{k+1} /
@@ -86,8 +88,8 @@ __device__ __forceinline__ TileCtx tile_ctx(const ViewDev* views, int nv, int64_
     c.H = V.H;
     c.px = tx * TW + lx;
     c.py = ty * TH + ly;
-    c.ox = (double)(tx * TW);
-    c.oy = (double)(ty * TH);
+    c.ox = (double)((tx * TW) & ~31);
+    c.oy = (double)((ty * TH) & ~31);
     c.inside = c.px < c.W && c.py < c.H;
     c.pix = V.pix_base + (int64_t)c.py * c.W + c.px;
     return c;
@@ -118,7 +120,7 @@ __global__ __launch_bounds__(256) void k_render_fwd(const ViewDev* __restrict__ 
     __shared__ float s_blu[BATCH];
     const TileCtx c = tile_ctx<TW, TH>(views, nv, n_tiles);
     const int2 rg = ranges[c.tile];
-    const float fx = (float)(threadIdx.x % TW) + 0.5f, fy = (float)(threadIdx.x / TW) + 0.5f;
+    const float fx = (float)(c.px - (int32_t)c.ox) + 0.5f, fy = (float)(c.py - (int32_t)c.oy) + 0.5f;
     float T = 1.0f, C0 = 0.0f, C1 = 0.0f, C2 = 0.0f;
     int32_t n = 0;
     bool done = !c.inside;
@@ -128,30 +130,29 @@ __global__ __launch_bounds__(256) void k_render_fwd(const ViewDev* __restrict__ 
         const int32_t j = b0 + (int32_t)threadIdx.x;
         if (threadIdx.x < BATCH && j < rg.y) stage(splats, values[j], c.ox, c.oy, s_geo, s_col, s_blu, threadIdx.x);
         __syncthreads();
-        if (!done) {
-            const int32_t cnt = min(BATCH, rg.y - b0);
-            for (int32_t k = 0; k < cnt; k++) {
-                const float4 g = s_geo[k];
-                const float4 cc = s_col[k];
-                const float dx = fx - g.x, dy = fy - g.y;
-                const float q = quad(dx, dy, g.z, g.w, cc.x);
-                if (STATS) n_eval++;
-                if (q > kQMax) continue;
-                const Eval ev = evaluate(q, cc.y);
-                if (ev.alpha < kAlphaMin) continue;
-                const float Tn = T * (1.0f - ev.alpha);
-                if (Tn < kTMin) {
-                    done = true;
-                    break;
-                }
-                const float w = T * ev.alpha;
-                C0 = fmaf(w, cc.z, C0);
-                C1 = fmaf(w, cc.w, C1);
-                C2 = fmaf(w, s_blu[k], C2);
-                T = Tn;
-                n = b0 - rg.x + k + 1;
-                if (STATS) n_comp++;
-            }
+        const int32_t cnt = min(BATCH, rg.y - b0);
+        for (int32_t k = 0; k < cnt; k++) {
+            const float4 g = s_geo[k];
+            const float dx = fx - g.x, dy = fy - g.y;
+            const float4 cc = s_col[k];
+            const float q = quad(dx, dy, g.z, g.w, cc.x);
+            if (STATS) n_eval += done ? 0u : 1u;
+            bool in = !done && q <= kQMax;
+            if (!__any(in)) continue;                 // wave-uniform: nobody inside the ellipse
+            const Eval ev = evaluate(q, cc.y);
+            in = in && ev.alpha >= kAlphaMin;
+            const float Tn = T * (1.0f - ev.alpha);
+            const bool stop = in && Tn < kTMin;
+            const bool take = in && !stop;
+            done = done || stop;
+            const float w = take ? T * ev.alpha : 0.0f;
+            C0 = fmaf(w, cc.z, C0);
+            C1 = fmaf(w, cc.w, C1);
+            C2 = fmaf(w, s_blu[k], C2);
+            T = take ? Tn : T;
+            n = take ? b0 - rg.x + k + 1 : n;
+            if (STATS) n_comp += take ? 1u : 0u;
+            if (!__any(!done)) break;                 // every pixel of the wave has terminated
         }
     }
     if (c.inside) {
@@ -178,10 +179,23 @@ __global__ __launch_bounds__(256) void k_render_fwd(const ViewDev* __restrict__ 
     }
 }
 
+// Cross-lane data-parallel-primitive move: lanes of disabled rows read 0.
+template <int CTRL, int ROW_MASK = 0xf>
+__device__ __forceinline__ float dpp(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROW_MASK, 0xf, false));
+}
+
+// Sum over the 64 lanes of a wave with DPP moves only (no LDS traffic):
+// butterflies inside quads, half-row and row mirrors give every lane its
+// 16-lane row sum; two row broadcasts fold the rows into lane 63.
 __device__ __forceinline__ float wave_sum(float x) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
-    return x;
+    x += dpp<0xB1>(x);          // quad_perm [1,0,3,2]
+    x += dpp<0x4E>(x);          // quad_perm [2,3,0,1]
+    x += dpp<0x141>(x);         // row_half_mirror
+    x += dpp<0x140>(x);         // row_mirror
+    x += dpp<0x142, 0xA>(x);    // row_bcast:15 into rows 1 and 3
+    x += dpp<0x143, 0xC>(x);    // row_bcast:31 into rows 2 and 3
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 63));
 }
 
 template <int TW, int TH, int BATCH>
@@ -201,7 +215,7 @@ __global__ __launch_bounds__(256) void k_render_bwd(const ViewDev* __restrict__ 
     __shared__ int32_t s_maxn;
     const TileCtx c = tile_ctx<TW, TH>(views, nv, n_tiles);
     const int2 rg = ranges[c.tile];
-    const float fx = (float)(threadIdx.x % TW) + 0.5f, fy = (float)(threadIdx.x / TW) + 0.5f;
+    const float fx = (float)(c.px - (int32_t)c.ox) + 0.5f, fy = (float)(c.py - (int32_t)c.oy) + 0.5f;
     float T = 1.0f, G0 = 0.0f, G1 = 0.0f, G2 = 0.0f;
     int32_t n = 0;
     if (c.inside) {
@@ -233,50 +247,42 @@ __global__ __launch_bounds__(256) void k_render_bwd(const ViewDev* __restrict__ 
         for (int32_t idx = threadIdx.x; idx < 9 * BATCH; idx += 256) (&s_acc[0][0])[idx] = 0.0f;
         __syncthreads();
         for (int32_t k = cnt - 1; k >= 0; k--) {
+            const float4 g = s_geo[k];
+            const float dx = fx - g.x, dy = fy - g.y;
+            const float4 cc = s_col[k];
+            const float q = quad(dx, dy, g.z, g.w, cc.x);
+            bool in = (bstart + k < n) && q <= kQMax;
+            if (!__any(in)) continue;                 // wave-uniform skip
+            const Eval ev = evaluate(q, cc.y);
+            in = in && ev.alpha >= kAlphaMin;
+            if (!__any(in)) continue;
+            const float al = ev.alpha;
+            const float Tk = T * __builtin_amdgcn_rcpf(1.0f - al);   // transmittance in front of k
+            T = in ? Tk : T;
+            const float cb = s_blu[k];
+            const float w = in ? Tk * al : 0.0f;
             float v[9];
+            v[6] = w * G0;
+            v[7] = w * G1;
+            v[8] = w * G2;
+            const float dal = in ? Tk * ((G0 * (cc.z - B0) + G1 * (cc.w - B1)) + G2 * (cb - B2)) : 0.0f;
+            B0 = in ? al * cc.z + (1.0f - al) * B0 : B0;
+            B1 = in ? al * cc.w + (1.0f - al) * B1 : B1;
+            B2 = in ? al * cb + (1.0f - al) * B2 : B2;
+            const float dau = ev.raw < kAlphaMax ? dal : 0.0f;     // alpha clamped: no opacity / shape terms
+            v[5] = dau * ev.e;
+            const float dq = -0.5f * al * dau;
+            const float bb = 0.5f * g.w;
+            v[2] = dq * dx * dx;
+            v[3] = dq * 2.0f * dx * dy;
+            v[4] = dq * dy * dy;
+            v[0] = -2.0f * dq * (g.z * dx + bb * dy);
+            v[1] = -2.0f * dq * (bb * dx + cc.x * dy);
 #pragma unroll
-            for (int i = 0; i < 9; i++) v[i] = 0.0f;
-            bool contrib = false;
-            if (bstart + k < n) {
-                const float4 g = s_geo[k];
-                const float4 cc = s_col[k];
-                const float dx = fx - g.x, dy = fy - g.y;
-                const float q = quad(dx, dy, g.z, g.w, cc.x);
-                if (q <= kQMax) {
-                    const Eval ev = evaluate(q, cc.y);
-                    if (ev.alpha >= kAlphaMin) {
-                        contrib = true;
-                        const float al = ev.alpha;
-                        T = T / (1.0f - al);
-                        const float w = T * al;
-                        const float cb = s_blu[k];
-                        v[6] = w * G0;
-                        v[7] = w * G1;
-                        v[8] = w * G2;
-                        const float dal = T * ((G0 * (cc.z - B0) + G1 * (cc.w - B1)) + G2 * (cb - B2));
-                        B0 = al * cc.z + (1.0f - al) * B0;
-                        B1 = al * cc.w + (1.0f - al) * B1;
-                        B2 = al * cb + (1.0f - al) * B2;
-                        if (ev.raw < kAlphaMax) {
-                            v[5] = dal * ev.e;
-                            const float dq = -0.5f * al * dal;
-                            const float bb = 0.5f * g.w;
-                            v[2] = dq * dx * dx;
-                            v[3] = dq * 2.0f * dx * dy;
-                            v[4] = dq * dy * dy;
-                            v[0] = -2.0f * dq * (g.z * dx + bb * dy);
-                            v[1] = -2.0f * dq * (bb * dx + cc.x * dy);
-                        }
-                    }
-                }
-            }
-            if (__any(contrib)) {
+            for (int i = 0; i < 9; i++) v[i] = wave_sum(v[i]);
+            if (lane == 63) {
 #pragma unroll
-                for (int i = 0; i < 9; i++) v[i] = wave_sum(v[i]);
-                if (lane == 0) {
-#pragma unroll
-                    for (int i = 0; i < 9; i++) atomicAdd(&s_acc[i][k], v[i]);
-                }
+                for (int i = 0; i < 9; i++) atomicAdd(&s_acc[i][k], v[i]);
             }
         }
         __syncthreads();

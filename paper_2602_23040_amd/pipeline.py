@@ -102,7 +102,8 @@ class Renderer:
         self.loss_partial = torch.empty(1024, dtype=torch.float64, device=dev)
         self.loss = torch.zeros(1, dtype=torch.float32, device=dev)
         if inst_capacity is None:
-            inst_capacity = 64 * max(self.N, 1) * (self.V if batched else 1)
+            # first guess; an overflow reports the count that suffices (grow_capacity)
+            inst_capacity = 8 * max(self.N, 1) * (self.V if batched else 1)
         if batched:
             self.sets = [_ViewSet(self.cams, self.frames, self.N, self.sh_degree, self.tiling, dev, inst_capacity)]
             self.pix_base = self.sets[0].pix_base
