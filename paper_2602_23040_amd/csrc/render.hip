@@ -67,35 +67,50 @@ __device__ __forceinline__ int64_t xcd_remap(int64_t i, int64_t n) {
     return x * per + imin(x, rem) + j;
 }
 
-struct TileCtx {
-    int64_t tile;
-    int32_t v, W, H, px, py;
+// One wave (64 lanes) composites one tile; lane l owns the four pixels
+// l, l + 64, l + 128, l + 192 of the tile in row-major order, so each group
+// of 64 pixels ("slot") is a 64-lane sub-block of the tile.  Every staged
+// Gaussian is read from LDS once per lane and applied to four pixels, and the
+// adjoint needs one cross-lane reduction per Gaussian and tile instead of one
+// per 64 pixels.  A slot whose 64 pixels all miss the ellipse is skipped with
+// a wave-uniform branch.
+constexpr int kLanes = 64;
+constexpr int kPPT = 4;
+
+struct TileGeo {
+    int64_t tile, vbase;
+    int32_t W, H;
     double ox, oy;
-    int64_t pix;
-    bool inside;
+    int32_t px[kPPT], py[kPPT];
+    float fx[kPPT], fy[kPPT];
+    bool inside[kPPT];
 };
 
 template <int TW, int TH>
-__device__ __forceinline__ TileCtx tile_ctx(const ViewDev* views, int nv, int64_t n_tiles) {
-    TileCtx c;
-    c.tile = xcd_remap(blockIdx.x, n_tiles);
-    c.v = find_view_by_tile(views, nv, c.tile);
-    const ViewDev& V = views[c.v];
-    const int64_t lt = c.tile - V.tile_base;
+__device__ __forceinline__ void tile_geo(const ViewDev* views, int nv, int64_t n_tiles, TileGeo& t) {
+    t.tile = xcd_remap(blockIdx.x, n_tiles);
+    const int v = find_view_by_tile(views, nv, t.tile);
+    const ViewDev& V = views[v];
+    const int64_t lt = t.tile - V.tile_base;
     const int32_t tx = (int32_t)(lt % V.TX), ty = (int32_t)(lt / V.TX);
-    const int32_t lx = threadIdx.x % TW, ly = threadIdx.x / TW;
-    c.W = V.W;
-    c.H = V.H;
-    c.px = tx * TW + lx;
-    c.py = ty * TH + ly;
-    c.ox = (double)((tx * TW) & ~31);
-    c.oy = (double)((ty * TH) & ~31);
-    c.inside = c.px < c.W && c.py < c.H;
-    c.pix = V.pix_base + (int64_t)c.py * c.W + c.px;
-    return c;
+    t.W = V.W;
+    t.H = V.H;
+    t.vbase = V.pix_base;
+    const int32_t ox = (tx * TW) & ~31, oy = (ty * TH) & ~31;
+    t.ox = (double)ox;
+    t.oy = (double)oy;
+#pragma unroll
+    for (int j = 0; j < kPPT; j++) {
+        const int32_t lp = (int32_t)threadIdx.x + kLanes * j;
+        t.px[j] = tx * TW + lp % TW;
+        t.py[j] = ty * TH + lp / TW;
+        t.fx[j] = (float)(t.px[j] - ox) + 0.5f;
+        t.fy[j] = (float)(t.py[j] - oy) + 0.5f;
+        t.inside[j] = t.px[j] < t.W && t.py[j] < t.H;
+    }
 }
 
-// Stage Gaussian `gv` into LDS slot `k` in tile-local coordinates.
+// Stage Gaussian `gv` into LDS slot `k` in coordinates local to (ox, oy).
 __device__ __forceinline__ void stage(const pg_splat* __restrict__ splats, int32_t gv, double ox, double oy,
                                       float4* s_geo, float4* s_col, float* s_blu, int k) {
     const float4* sp = reinterpret_cast<const float4*>(splats + gv);
@@ -108,73 +123,94 @@ __device__ __forceinline__ void stage(const pg_splat* __restrict__ splats, int32
 }
 
 template <int TW, int TH, int BATCH, bool STATS>
-__global__ __launch_bounds__(256) void k_render_fwd(const ViewDev* __restrict__ views, int nv, int64_t n_tiles,
-                                                    const pg_splat* __restrict__ splats,
-                                                    const int32_t* __restrict__ values,
-                                                    const int2* __restrict__ ranges, float bg0, float bg1,
-                                                    float bg2, float* __restrict__ image,
-                                                    float* __restrict__ final_T, int32_t* __restrict__ n_contrib,
-                                                    unsigned long long* __restrict__ counters) {
+__global__ __launch_bounds__(kLanes) void k_render_fwd(const ViewDev* __restrict__ views, int nv, int64_t n_tiles,
+                                                       const pg_splat* __restrict__ splats,
+                                                       const int32_t* __restrict__ values,
+                                                       const int2* __restrict__ ranges, float bg0, float bg1,
+                                                       float bg2, float* __restrict__ image,
+                                                       float* __restrict__ final_T, int32_t* __restrict__ n_contrib,
+                                                       unsigned long long* __restrict__ counters) {
     __shared__ float4 s_geo[BATCH];
     __shared__ float4 s_col[BATCH];
     __shared__ float s_blu[BATCH];
-    const TileCtx c = tile_ctx<TW, TH>(views, nv, n_tiles);
-    const int2 rg = ranges[c.tile];
-    const float fx = (float)(c.px - (int32_t)c.ox) + 0.5f, fy = (float)(c.py - (int32_t)c.oy) + 0.5f;
-    float T = 1.0f, C0 = 0.0f, C1 = 0.0f, C2 = 0.0f;
-    int32_t n = 0;
-    bool done = !c.inside;
+    TileGeo t;
+    tile_geo<TW, TH>(views, nv, n_tiles, t);
+    const int2 rg = ranges[t.tile];
+    float T[kPPT], C0[kPPT], C1[kPPT], C2[kPPT];
+    int32_t n[kPPT];
+    bool done[kPPT];
+#pragma unroll
+    for (int j = 0; j < kPPT; j++) {
+        T[j] = 1.0f;
+        C0[j] = C1[j] = C2[j] = 0.0f;
+        n[j] = 0;
+        done[j] = !t.inside[j];
+    }
     uint32_t n_eval = 0, n_comp = 0;
     for (int32_t b0 = rg.x; b0 < rg.y; b0 += BATCH) {
-        if (__syncthreads_count(!done) == 0) break;
-        const int32_t j = b0 + (int32_t)threadIdx.x;
-        if (threadIdx.x < BATCH && j < rg.y) stage(splats, values[j], c.ox, c.oy, s_geo, s_col, s_blu, threadIdx.x);
+        bool alive = false;
+#pragma unroll
+        for (int j = 0; j < kPPT; j++) alive = alive || !done[j];
+        if (!__any(alive)) break;
+        __syncthreads();
+        for (int32_t i = threadIdx.x; i < BATCH && b0 + i < rg.y; i += kLanes)
+            stage(splats, values[b0 + i], t.ox, t.oy, s_geo, s_col, s_blu, i);
         __syncthreads();
         const int32_t cnt = min(BATCH, rg.y - b0);
         for (int32_t k = 0; k < cnt; k++) {
             const float4 g = s_geo[k];
-            const float dx = fx - g.x, dy = fy - g.y;
             const float4 cc = s_col[k];
-            const float q = quad(dx, dy, g.z, g.w, cc.x);
-            if (STATS) n_eval += done ? 0u : 1u;
-            bool in = !done && q <= kQMax;
-            if (!__any(in)) continue;                 // wave-uniform: nobody inside the ellipse
-            const Eval ev = evaluate(q, cc.y);
-            in = in && ev.alpha >= kAlphaMin;
-            const float Tn = T * (1.0f - ev.alpha);
-            const bool stop = in && Tn < kTMin;
-            const bool take = in && !stop;
-            done = done || stop;
-            const float w = take ? T * ev.alpha : 0.0f;
-            C0 = fmaf(w, cc.z, C0);
-            C1 = fmaf(w, cc.w, C1);
-            C2 = fmaf(w, s_blu[k], C2);
-            T = take ? Tn : T;
-            n = take ? b0 - rg.x + k + 1 : n;
-            if (STATS) n_comp += take ? 1u : 0u;
-            if (!__any(!done)) break;                 // every pixel of the wave has terminated
+            const float cb = s_blu[k];
+            const int32_t pos1 = b0 - rg.x + k + 1;
+#pragma unroll
+            for (int j = 0; j < kPPT; j++) {
+                const float dx = t.fx[j] - g.x, dy = t.fy[j] - g.y;
+                const float q = quad(dx, dy, g.z, g.w, cc.x);
+                if (STATS) n_eval += done[j] ? 0u : 1u;
+                bool in = !done[j] && q <= kQMax;
+                if (!__any(in)) continue;             // wave-uniform: no pixel of this slot inside
+                const Eval ev = evaluate(q, cc.y);
+                in = in && ev.alpha >= kAlphaMin;
+                const float Tn = T[j] * (1.0f - ev.alpha);
+                const bool stop = in && Tn < kTMin;
+                const bool take = in && !stop;
+                done[j] = done[j] || stop;
+                const float w = take ? T[j] * ev.alpha : 0.0f;
+                C0[j] = fmaf(w, cc.z, C0[j]);
+                C1[j] = fmaf(w, cc.w, C1[j]);
+                C2[j] = fmaf(w, cb, C2[j]);
+                T[j] = take ? Tn : T[j];
+                n[j] = take ? pos1 : n[j];
+                if (STATS) n_comp += take ? 1u : 0u;
+            }
+            bool alive2 = false;
+#pragma unroll
+            for (int j = 0; j < kPPT; j++) alive2 = alive2 || !done[j];
+            if (!__any(alive2)) break;                // every pixel of the tile has terminated
         }
     }
-    if (c.inside) {
-        const int64_t HW = (int64_t)c.W * c.H;
-        const int64_t vb = c.pix - ((int64_t)c.py * c.W + c.px);   // pixel base of the view
-        float* img = image + 3 * vb + (int64_t)c.py * c.W + c.px;
-        img[0] = fmaf(T, bg0, C0);
-        img[HW] = fmaf(T, bg1, C1);
-        img[2 * HW] = fmaf(T, bg2, C2);
-        final_T[c.pix] = T;
-        n_contrib[c.pix] = n;
+    const int64_t HW = (int64_t)t.W * t.H;
+#pragma unroll
+    for (int j = 0; j < kPPT; j++) {
+        if (!t.inside[j]) continue;
+        const int64_t p = (int64_t)t.py[j] * t.W + t.px[j];
+        float* img = image + 3 * t.vbase + p;
+        img[0] = fmaf(T[j], bg0, C0[j]);
+        img[HW] = fmaf(T[j], bg1, C1[j]);
+        img[2 * HW] = fmaf(T[j], bg2, C2[j]);
+        final_T[t.vbase + p] = T[j];
+        n_contrib[t.vbase + p] = n[j];
     }
     if (STATS) {
-        unsigned long long e = n_eval, p = n_comp;
+        unsigned long long e = n_eval, c = n_comp;
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) {
             e += __shfl_xor(e, o, 64);
-            p += __shfl_xor(p, o, 64);
+            c += __shfl_xor(c, o, 64);
         }
-        if ((threadIdx.x & 63) == 0) {
+        if (threadIdx.x == 0) {
             atomicAdd(&counters[0], e);
-            atomicAdd(&counters[1], p);
+            atomicAdd(&counters[1], c);
         }
     }
 }
@@ -185,111 +221,127 @@ __device__ __forceinline__ float dpp(float v) {
     return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROW_MASK, 0xf, false));
 }
 
-// Sum over the 64 lanes of a wave with DPP moves only (no LDS traffic):
-// butterflies inside quads, half-row and row mirrors give every lane its
-// 16-lane row sum; two row broadcasts fold the rows into lane 63.
-__device__ __forceinline__ float wave_sum(float x) {
-    x += dpp<0xB1>(x);          // quad_perm [1,0,3,2]
-    x += dpp<0x4E>(x);          // quad_perm [2,3,0,1]
-    x += dpp<0x141>(x);         // row_half_mirror
-    x += dpp<0x140>(x);         // row_mirror
-    x += dpp<0x142, 0xA>(x);    // row_bcast:15 into rows 1 and 3
-    x += dpp<0x143, 0xC>(x);    // row_bcast:31 into rows 2 and 3
-    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 63));
+// Sums of N values over the 64 lanes of the wave with DPP moves only (no LDS
+// traffic), the N reductions interleaved step by step: butterflies inside
+// quads, half-row and row mirrors give every lane its 16-lane row sum, two row
+// broadcasts fold the rows into lane 63, which is read into a scalar.
+template <int N>
+__device__ __forceinline__ void wave_sums(float* x) {
+#pragma unroll
+    for (int i = 0; i < N; i++) x[i] += dpp<0xB1>(x[i]);          // quad_perm [1,0,3,2]
+#pragma unroll
+    for (int i = 0; i < N; i++) x[i] += dpp<0x4E>(x[i]);          // quad_perm [2,3,0,1]
+#pragma unroll
+    for (int i = 0; i < N; i++) x[i] += dpp<0x141>(x[i]);         // row_half_mirror
+#pragma unroll
+    for (int i = 0; i < N; i++) x[i] += dpp<0x140>(x[i]);         // row_mirror
+#pragma unroll
+    for (int i = 0; i < N; i++) x[i] += dpp<0x142, 0xA>(x[i]);    // row_bcast:15 into rows 1, 3
+#pragma unroll
+    for (int i = 0; i < N; i++) x[i] += dpp<0x143, 0xC>(x[i]);    // row_bcast:31 into rows 2, 3
+#pragma unroll
+    for (int i = 0; i < N; i++) x[i] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x[i]), 63));
 }
 
 template <int TW, int TH, int BATCH>
-__global__ __launch_bounds__(256) void k_render_bwd(const ViewDev* __restrict__ views, int nv, int64_t n_tiles,
-                                                    const pg_splat* __restrict__ splats,
-                                                    const int32_t* __restrict__ values,
-                                                    const int2* __restrict__ ranges, float bg0, float bg1,
-                                                    float bg2, const float* __restrict__ final_T,
-                                                    const int32_t* __restrict__ n_contrib,
-                                                    const float* __restrict__ dL_dimage, int64_t n_gv,
-                                                    float* __restrict__ grad2d) {
+__global__ __launch_bounds__(kLanes) void k_render_bwd(const ViewDev* __restrict__ views, int nv, int64_t n_tiles,
+                                                       const pg_splat* __restrict__ splats,
+                                                       const int32_t* __restrict__ values,
+                                                       const int2* __restrict__ ranges, float bg0, float bg1,
+                                                       float bg2, const float* __restrict__ final_T,
+                                                       const int32_t* __restrict__ n_contrib,
+                                                       const float* __restrict__ dL_dimage, int64_t n_gv,
+                                                       float* __restrict__ grad2d) {
     __shared__ float4 s_geo[BATCH];
     __shared__ float4 s_col[BATCH];
     __shared__ float s_blu[BATCH];
     __shared__ int32_t s_gv[BATCH];
-    __shared__ float s_acc[9][BATCH];
-    __shared__ int32_t s_maxn;
-    const TileCtx c = tile_ctx<TW, TH>(views, nv, n_tiles);
-    const int2 rg = ranges[c.tile];
-    const float fx = (float)(c.px - (int32_t)c.ox) + 0.5f, fy = (float)(c.py - (int32_t)c.oy) + 0.5f;
-    float T = 1.0f, G0 = 0.0f, G1 = 0.0f, G2 = 0.0f;
-    int32_t n = 0;
-    if (c.inside) {
-        const int64_t HW = (int64_t)c.W * c.H;
-        const int64_t vb = c.pix - ((int64_t)c.py * c.W + c.px);
-        const float* gi = dL_dimage + 3 * vb + (int64_t)c.py * c.W + c.px;
-        G0 = gi[0];
-        G1 = gi[HW];
-        G2 = gi[2 * HW];
-        T = final_T[c.pix];
-        n = n_contrib[c.pix];
+    TileGeo t;
+    tile_geo<TW, TH>(views, nv, n_tiles, t);
+    const int2 rg = ranges[t.tile];
+    const int64_t HW = (int64_t)t.W * t.H;
+    float T[kPPT], G0[kPPT], G1[kPPT], G2[kPPT], B0[kPPT], B1[kPPT], B2[kPPT];
+    int32_t n[kPPT];
+    int32_t maxn = 0;
+#pragma unroll
+    for (int j = 0; j < kPPT; j++) {
+        T[j] = 1.0f;
+        G0[j] = G1[j] = G2[j] = 0.0f;
+        B0[j] = bg0;
+        B1[j] = bg1;
+        B2[j] = bg2;
+        n[j] = 0;
+        if (t.inside[j]) {
+            const int64_t p = (int64_t)t.py[j] * t.W + t.px[j];
+            const float* gi = dL_dimage + 3 * t.vbase + p;
+            G0[j] = gi[0];
+            G1[j] = gi[HW];
+            G2[j] = gi[2 * HW];
+            T[j] = final_T[t.vbase + p];
+            n[j] = n_contrib[t.vbase + p];
+        }
+        maxn = max(maxn, n[j]);
     }
-    if (threadIdx.x == 0) s_maxn = 0;
-    __syncthreads();
-    if (n > 0) atomicMax(&s_maxn, n);
-    __syncthreads();
-    const int32_t len = s_maxn;
-    float B0 = bg0, B1 = bg1, B2 = bg2;
-    const int lane = threadIdx.x & 63;
-    for (int32_t bend = len; bend > 0; bend -= BATCH) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) maxn = max(maxn, __shfl_xor(maxn, o, 64));
+    const int lane = threadIdx.x;
+    for (int32_t bend = maxn; bend > 0; bend -= BATCH) {
         const int32_t bstart = max(0, bend - BATCH);
         const int32_t cnt = bend - bstart;
         __syncthreads();
-        if ((int32_t)threadIdx.x < cnt) {
-            const int32_t gv = values[rg.x + bstart + threadIdx.x];
-            s_gv[threadIdx.x] = gv;
-            stage(splats, gv, c.ox, c.oy, s_geo, s_col, s_blu, threadIdx.x);
+        for (int32_t i = lane; i < cnt; i += kLanes) {
+            const int32_t gv = values[rg.x + bstart + i];
+            s_gv[i] = gv;
+            stage(splats, gv, t.ox, t.oy, s_geo, s_col, s_blu, i);
         }
-        for (int32_t idx = threadIdx.x; idx < 9 * BATCH; idx += 256) (&s_acc[0][0])[idx] = 0.0f;
         __syncthreads();
         for (int32_t k = cnt - 1; k >= 0; k--) {
             const float4 g = s_geo[k];
-            const float dx = fx - g.x, dy = fy - g.y;
             const float4 cc = s_col[k];
-            const float q = quad(dx, dy, g.z, g.w, cc.x);
-            bool in = (bstart + k < n) && q <= kQMax;
-            if (!__any(in)) continue;                 // wave-uniform skip
-            const Eval ev = evaluate(q, cc.y);
-            in = in && ev.alpha >= kAlphaMin;
-            if (!__any(in)) continue;
-            const float al = ev.alpha;
-            const float Tk = T * __builtin_amdgcn_rcpf(1.0f - al);   // transmittance in front of k
-            T = in ? Tk : T;
             const float cb = s_blu[k];
-            const float w = in ? Tk * al : 0.0f;
-            float v[9];
-            v[6] = w * G0;
-            v[7] = w * G1;
-            v[8] = w * G2;
-            const float dal = in ? Tk * ((G0 * (cc.z - B0) + G1 * (cc.w - B1)) + G2 * (cb - B2)) : 0.0f;
-            B0 = in ? al * cc.z + (1.0f - al) * B0 : B0;
-            B1 = in ? al * cc.w + (1.0f - al) * B1 : B1;
-            B2 = in ? al * cb + (1.0f - al) * B2 : B2;
-            const float dau = ev.raw < kAlphaMax ? dal : 0.0f;     // alpha clamped: no opacity / shape terms
-            v[5] = dau * ev.e;
-            const float dq = -0.5f * al * dau;
             const float bb = 0.5f * g.w;
-            v[2] = dq * dx * dx;
-            v[3] = dq * 2.0f * dx * dy;
-            v[4] = dq * dy * dy;
-            v[0] = -2.0f * dq * (g.z * dx + bb * dy);
-            v[1] = -2.0f * dq * (bb * dx + cc.x * dy);
+            const int32_t pos = bstart + k;
+            float acc[9];
 #pragma unroll
-            for (int i = 0; i < 9; i++) v[i] = wave_sum(v[i]);
-            if (lane == 63) {
+            for (int i = 0; i < 9; i++) acc[i] = 0.0f;
+            bool any_c = false;
 #pragma unroll
-                for (int i = 0; i < 9; i++) atomicAdd(&s_acc[i][k], v[i]);
+            for (int j = 0; j < kPPT; j++) {
+                const float dx = t.fx[j] - g.x, dy = t.fy[j] - g.y;
+                const float q = quad(dx, dy, g.z, g.w, cc.x);
+                bool in = pos < n[j] && q <= kQMax;
+                if (!__any(in)) continue;             // wave-uniform skip
+                const Eval ev = evaluate(q, cc.y);
+                in = in && ev.alpha >= kAlphaMin;
+                if (!__any(in)) continue;
+                any_c = true;
+                const float al = ev.alpha;
+                const float Tk = T[j] * __builtin_amdgcn_rcpf(1.0f - al);   // transmittance in front of k
+                T[j] = in ? Tk : T[j];
+                const float w = in ? Tk * al : 0.0f;
+                acc[6] += w * G0[j];
+                acc[7] += w * G1[j];
+                acc[8] += w * G2[j];
+                const float dal =
+                    in ? Tk * ((G0[j] * (cc.z - B0[j]) + G1[j] * (cc.w - B1[j])) + G2[j] * (cb - B2[j])) : 0.0f;
+                B0[j] = in ? al * cc.z + (1.0f - al) * B0[j] : B0[j];
+                B1[j] = in ? al * cc.w + (1.0f - al) * B1[j] : B1[j];
+                B2[j] = in ? al * cb + (1.0f - al) * B2[j] : B2[j];
+                const float dau = ev.raw < kAlphaMax ? dal : 0.0f;   // clamped alpha: no opacity / shape terms
+                acc[5] += dau * ev.e;
+                const float dq = -0.5f * al * dau;
+                acc[2] += dq * dx * dx;
+                acc[3] += dq * 2.0f * dx * dy;
+                acc[4] += dq * dy * dy;
+                acc[0] += -2.0f * dq * (g.z * dx + bb * dy);
+                acc[1] += -2.0f * dq * (bb * dx + cc.x * dy);
             }
-        }
-        __syncthreads();
-        for (int32_t idx = threadIdx.x; idx < 9 * cnt; idx += 256) {
-            const int32_t i = idx / cnt, k = idx - i * cnt;
-            const float val = s_acc[i][k];
-            if (val != 0.0f) unsafeAtomicAdd(&grad2d[(int64_t)i * n_gv + s_gv[k]], val);
+            if (!any_c) continue;
+            wave_sums<9>(acc);
+            float mine = 0.0f;
+#pragma unroll
+            for (int i = 0; i < 9; i++) mine = (lane == i) ? acc[i] : mine;
+            if (lane < 9) unsafeAtomicAdd(&grad2d[(int64_t)lane * n_gv + s_gv[k]], mine);
         }
     }
 }
@@ -300,11 +352,11 @@ void fwd_launch(const pg_views* v, const pg_splat* splats, const int32_t* values
                 hipStream_t s) {
     const unsigned grid = (unsigned)v->n_tiles;
     if (counters)
-        k_render_fwd<TW, TH, BATCH, true><<<grid, 256, 0, s>>>(
+        k_render_fwd<TW, TH, BATCH, true><<<grid, kLanes, 0, s>>>(
             v->d_views, v->n_views, v->n_tiles, splats, values, reinterpret_cast<const int2*>(ranges), bg[0], bg[1],
             bg[2], image, final_T, n_contrib, reinterpret_cast<unsigned long long*>(counters));
     else
-        k_render_fwd<TW, TH, BATCH, false><<<grid, 256, 0, s>>>(
+        k_render_fwd<TW, TH, BATCH, false><<<grid, kLanes, 0, s>>>(
             v->d_views, v->n_views, v->n_tiles, splats, values, reinterpret_cast<const int2*>(ranges), bg[0], bg[1],
             bg[2], image, final_T, n_contrib, nullptr);
 }
@@ -313,7 +365,7 @@ template <int TW, int TH, int BATCH>
 void bwd_launch(const pg_views* v, const pg_splat* splats, const int32_t* values, const int32_t* ranges,
                 const float bg[3], const float* final_T, const int32_t* n_contrib, const float* dL_dimage,
                 float* grad2d, hipStream_t s) {
-    k_render_bwd<TW, TH, BATCH><<<(unsigned)v->n_tiles, 256, 0, s>>>(
+    k_render_bwd<TW, TH, BATCH><<<(unsigned)v->n_tiles, kLanes, 0, s>>>(
         v->d_views, v->n_views, v->n_tiles, splats, values, reinterpret_cast<const int2*>(ranges), bg[0], bg[1],
         bg[2], final_T, n_contrib, dL_dimage, v->n_gv, grad2d);
 }
