@@ -109,8 +109,8 @@ typedef struct pg_views_info {
     int64_t n_gv;           /* n_views * N */
     int64_t n_tiles;        /* sum over views of TX_v * TY_v */
     int64_t n_pixels;       /* sum over views of W_v * H_v */
-    int32_t key_bits;       /* significant bits of the (tile << 32 | depth) sort key */
-    int32_t sort_passes;    /* 8-bit radix passes */
+    int32_t key_bits;       /* bits of a global tile id (the instance sort key) */
+    int32_t sort_passes;    /* radix passes per pg_bin_sort (record sort + instance sort) */
     int32_t tile_w, tile_h, lds_batch, reserved;
 } pg_views_info;
 
@@ -168,16 +168,19 @@ pg_status pg_project(const pg_views* views, const float* params, pg_splat* splat
                      uint8_t* visible, void* stream);
 
 /* a3 -- Tile binning and depth sort (tile rasteriser, Sec. 3; per-camera
- * depth sort, viewer section).  Emits one instance per (Gaussian, covered
- * tile) with key (global tile << 32 | depth_key) and value gv, sorts them by
- * key with a stable LSD radix sort (equal keys keep ascending gv), and
- * writes each tile's [start, end) instance range.
- *   keys, values   device [inst_capacity] out (sorted)
- *   tile_ranges    device int32 [n_tiles][2] out
+ * depth sort, viewer section).  Lists every surviving (view, Gaussian) once
+ * per tile of its rectangle and orders each tile's list front to back by
+ * fp32(z_c), equal depths by ascending Gaussian id.  Implementation: the
+ * surviving records are stably radix-sorted by (view, depth); instances are
+ * emitted in that order and stably radix-sorted by global tile id.
+ *   keys           device uint32 [inst_capacity] out: global tile of each
+ *                  sorted instance (ascending)
+ *   values         device int32 [inst_capacity] out: gv of each sorted instance
+ *   tile_ranges    device int32 [n_tiles][2] out: [start, end) per tile
  *   n_inst_dev     device int64 [1] out: number of instances
  *   overflow_dev   device int32 [1] out: 1 if n_inst > inst_capacity, else 0
  *   ws             device workspace of pg_sort_workspace_size bytes */
-pg_status pg_bin_sort(const pg_views* views, const pg_bin* bins, int64_t inst_capacity, uint64_t* keys,
+pg_status pg_bin_sort(const pg_views* views, const pg_bin* bins, int64_t inst_capacity, uint32_t* keys,
                       int32_t* values, int32_t* tile_ranges, int64_t* n_inst_dev, int32_t* overflow_dev,
                       void* ws, size_t ws_bytes, void* stream);
 

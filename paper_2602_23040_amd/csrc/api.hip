@@ -130,6 +130,8 @@ pg_status pg_views_create(const pg_camera* cams, int32_t n_views, int32_t frames
     fv[frames] = (int32_t)order.size();
     int tile_bits = 1;
     while ((int64_t(1) << tile_bits) < tiles) tile_bits++;
+    int view_bits = 0;
+    while ((1 << view_bits) < n_views) view_bits++;
 
     pg_views* p = new pg_views();
     p->n_views = n_views;
@@ -141,8 +143,8 @@ pg_status pg_views_create(const pg_camera* cams, int32_t n_views, int32_t frames
     p->n_gv = (int64_t)n_views * n_gauss;
     p->n_tiles = tiles;
     p->n_pixels = pixels;
-    p->key_bits = 32 + tile_bits;
-    p->sort_passes = (p->key_bits + kRadixBits - 1) / kRadixBits;
+    p->key_bits = tile_bits;
+    p->sort_passes = (32 + view_bits + 7) / 8 + (tile_bits + 9) / 10;   // record passes + instance passes
     p->h_tile_base = new int64_t[n_views + 1];
     p->h_pix_base = new int64_t[n_views + 1];
     std::memcpy(p->h_tile_base, tb.data(), sizeof(int64_t) * (n_views + 1));
@@ -240,7 +242,7 @@ pg_status pg_project(const pg_views* v, const float* params, pg_splat* splats, p
     return PG_OK;
 }
 
-pg_status pg_bin_sort(const pg_views* v, const pg_bin* bins, int64_t cap, uint64_t* keys, int32_t* values,
+pg_status pg_bin_sort(const pg_views* v, const pg_bin* bins, int64_t cap, uint32_t* keys, int32_t* values,
                       int32_t* tile_ranges, int64_t* n_inst_dev, int32_t* overflow_dev, void* ws, size_t ws_bytes,
                       void* stream) {
     g_error.clear();

@@ -1,51 +1,89 @@
 // a3 -- tile binning and depth sort.
 //
 // Every projected Gaussian is listed once per screen tile its rectangle
-// covers (the 3DGS tile rasteriser the paper names, Sec. 3), keyed by
-// (global tile << 32 | fp32 depth bits), and the instances are sorted by that
-// key so each tile's list is front to back (depth sort per camera,
-// supplementary viewer section).  Because the instances are emitted in
-// ascending gv order and the sort is a stable LSD radix sort, equal depths
-// stay in ascending Gaussian id order.
+// covers (the 3DGS tile rasteriser the paper names, Sec. 3), and each tile's
+// list is ordered front to back by camera-space depth (depth sort per camera,
+// supplementary viewer section), equal depths by ascending Gaussian id.
+//
+// The order is built in two stable radix sorts instead of one sort of
+// (tile, depth) keys over all instances:
+//   1. the surviving (view, Gaussian) records -- far fewer than instances --
+//      are compacted and sorted by (view, fp32 depth bits);
+//   2. instances are emitted in that order (each record lists the tiles of
+//      its rectangle) and stably sorted by global tile id alone.
+// Because the second sort is stable and a tile belongs to one view, each
+// tile's list comes out ordered by (depth, id): the same order as sorting
+// (tile, depth, id) keys, with the wide sort running over records and only
+// the ~20 tile bits sorted over instances.
 //
 // Kernels (all HBM-bound):
-//   k_bin_count     per 1024 (view, Gaussian) records: sum of tiles touched
-//   scan            exclusive scan of the block sums -> instance offsets
-//   k_emit          work-group-cooperative emission: the group's output range
-//                   is written contiguously (coalesced), each lane locating its
-//                   (record, tile) by binary search over the group's prefix sums
-//   radix passes    per 8-bit digit: upsweep histogram, scan, downsweep
-//                   (wave-level multisplit ranking with ballots, LDS staging so
-//                   the scatter writes digit runs contiguously)
-//   k_ranges        [start, end) of every tile from the sorted keys
-// Counts that only the device knows (instances) are read from device memory,
-// so the chain needs no host synchronisation.
+//   k_valid_count / k_compact   records with n_tiles > 0 -> (view << 32 | depth, gv)
+//   radix passes (64-bit keys)  LSD, digit width <= 10 bits
+//   k_sorted_count / k_emit     tiles per sorted record -> instance offsets ->
+//                               work-group-cooperative emission (coalesced writes)
+//   radix passes (32-bit keys)  tile ids
+//   k_ranges                    [start, end) of every tile
+// Radix passes: per-tile digit histograms (upsweep), a scan of the histograms,
+// then a downsweep that ranks keys with a wave-level multisplit (one ballot per
+// digit bit) and scatters through LDS so each digit's run is written
+// contiguously.  Counts that only the device knows are read from device
+// memory, so the chain needs no host synchronisation.
 #include "pg_internal.h"
 
 namespace pg {
 
 namespace {
 
-constexpr int kEmitThreads = 1024;
+constexpr int kBlk = 1024;           // records per compaction / emission work-group
 constexpr int kSortGrid = 2048;      // persistent grid of the radix kernels (grid-stride over tiles)
+constexpr int kMaxDigitBits64 = 8;   // record sort (64-bit keys): LDS stays under 64 KiB per group
+constexpr int kMaxDigitBits32 = 10;  // instance sort (32-bit tile ids)
+
+struct SortPlan {
+    int d_bits, d_passes;            // depth sort: key bits, digit width, passes
+    int d_digit;
+    int t_bits, t_passes, t_digit;   // tile sort
+};
+
+SortPlan plan_for(const pg_views* v) {
+    SortPlan p{};
+    int view_bits = 0;
+    while ((1 << view_bits) < v->n_views) view_bits++;
+    p.d_bits = 32 + view_bits;
+    p.d_passes = (p.d_bits + kMaxDigitBits64 - 1) / kMaxDigitBits64;
+    p.d_digit = (p.d_bits + p.d_passes - 1) / p.d_passes;
+    p.t_bits = v->key_bits;          // ceil(log2(n_tiles)), >= 1
+    p.t_passes = (p.t_bits + kMaxDigitBits32 - 1) / kMaxDigitBits32;
+    p.t_digit = (p.t_bits + p.t_passes - 1) / p.t_passes;
+    return p;
+}
 
 struct SortWs {
-    int64_t* block_sums;
-    int64_t* block_offs;
+    int64_t* blk_a;          // per-block sums (compaction / emission)
+    int64_t* blk_a_off;
     int64_t* scan_tmp;
-    int64_t* misc;          // [0] instances to sort (0 on overflow), [1] 256 * sort tiles
-    uint64_t* keys_alt;
-    int32_t* vals_alt;
+    int64_t* misc;           // [0] valid records, [1] instances to sort (0 on overflow),
+                             // [2] depth-sort counts length, [3] tile-sort counts length
+    uint64_t* rk0;           // record sort ping-pong
+    int32_t* rv0;
+    uint64_t* rk1;
+    int32_t* rv1;
+    uint32_t* tk_alt;        // tile sort ping-pong partner of the caller's arrays
+    int32_t* tv_alt;
     int32_t* counts;
     int32_t* count_offs;
 };
 
-int64_t n_emit_blocks(const pg_views* v) { return ceil_div(v->n_gv, kEmitThreads); }
+int64_t n_blocks(const pg_views* v) { return imax(ceil_div(v->n_gv, kBlk), 1); }
 
 SortWs carve(const pg_views* v, int64_t cap, void* ws, size_t* total) {
+    const SortPlan pl = plan_for(v);
     SortWs w{};
-    const int64_t nb = imax(n_emit_blocks(v), 1);
-    const int64_t ntile = imax(ceil_div(cap, kSortTile), 1);
+    const int64_t nb = n_blocks(v);
+    const int64_t ngv = imax(v->n_gv, 1);
+    const int64_t cnt_d = ((int64_t)1 << pl.d_digit) * imax(ceil_div(ngv, kSortTile), 1);
+    const int64_t cnt_t = ((int64_t)1 << pl.t_digit) * imax(ceil_div(imax(cap, 1), kSortTile), 1);
+    const int64_t cnt = imax(cnt_d, cnt_t);
     char* p = (char*)ws;
     size_t off = 0;
     auto take = [&](size_t bytes) {
@@ -53,104 +91,145 @@ SortWs carve(const pg_views* v, int64_t cap, void* ws, size_t* total) {
         off += align256(bytes);
         return q;
     };
-    w.block_sums = (int64_t*)take(nb * 8);
-    w.block_offs = (int64_t*)take(nb * 8);
+    w.blk_a = (int64_t*)take(nb * 8);
+    w.blk_a_off = (int64_t*)take(nb * 8);
     w.scan_tmp = (int64_t*)take(kScanTmpWords * 8);
-    w.misc = (int64_t*)take(4 * 8);
-    w.keys_alt = (uint64_t*)take(imax(cap, 1) * 8);
-    w.vals_alt = (int32_t*)take(imax(cap, 1) * 4);
-    w.counts = (int32_t*)take(ntile * kRadix * 4);
-    w.count_offs = (int32_t*)take(ntile * kRadix * 4);
+    w.misc = (int64_t*)take(8 * 8);
+    w.rk0 = (uint64_t*)take(ngv * 8);
+    w.rv0 = (int32_t*)take(ngv * 4);
+    w.rk1 = (uint64_t*)take(ngv * 8);
+    w.rv1 = (int32_t*)take(ngv * 4);
+    w.tk_alt = (uint32_t*)take(imax(cap, 1) * 4);
+    w.tv_alt = (int32_t*)take(imax(cap, 1) * 4);
+    w.counts = (int32_t*)take(cnt * 4);
+    w.count_offs = (int32_t*)take(cnt * 4);
     if (total) *total = off;
     return w;
 }
 
-__global__ __launch_bounds__(kEmitThreads) void k_bin_count(const pg_bin* __restrict__ bins, int64_t n_gv,
-                                                            int64_t* __restrict__ block_sums) {
-    __shared__ int64_t s[kEmitThreads / 64];
-    const int64_t gv = (int64_t)blockIdx.x * kEmitThreads + threadIdx.x;
-    int64_t c = gv < n_gv ? (int64_t)bins[gv].n_tiles : 0;
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o, 64);
-    if ((threadIdx.x & 63) == 0) s[threadIdx.x >> 6] = c;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        int64_t t = 0;
-        for (int k = 0; k < kEmitThreads / 64; k++) t += s[k];
-        block_sums[blockIdx.x] = t;
-    }
-}
-
-__global__ void k_post_count(const int64_t* n_inst, int64_t cap, int32_t* overflow, int64_t* misc) {
-    const int64_t I = *n_inst;
-    const bool of = I > cap;
-    *overflow = of ? 1 : 0;
-    const int64_t eff = of ? 0 : I;
-    misc[0] = eff;
-    misc[1] = ceil_div(eff, kSortTile) * kRadix;
-}
-
-__global__ __launch_bounds__(kEmitThreads) void k_emit(const pg_bin* __restrict__ bins, int64_t n_gv, int64_t N,
-                                                       const ViewDev* __restrict__ views,
-                                                       const int64_t* __restrict__ block_offs,
-                                                       const int64_t* __restrict__ misc, uint64_t* __restrict__ keys,
-                                                       int32_t* __restrict__ vals) {
-    __shared__ int32_t s_incl[kEmitThreads];
-    __shared__ uint2 s_rect[kEmitThreads];
-    __shared__ uint32_t s_key[kEmitThreads];
-    __shared__ int32_t s_warp[kEmitThreads / 64];
-    if (misc[0] == 0) return;   // overflow (or nothing to emit): uniform exit
-    const int t = threadIdx.x;
-    const int64_t gv0 = (int64_t)blockIdx.x * kEmitThreads;
-    const int64_t gv = gv0 + t;
-    int32_t nt = 0;
-    if (gv < n_gv) {
-        const uint4 b = reinterpret_cast<const uint4*>(bins)[gv];
-        nt = (int32_t)b.w;
-        s_rect[t] = make_uint2(b.x, b.y);
-        s_key[t] = b.z;
-    }
-    const int lane = t & 63, wid = t >> 6;
-    int32_t v = nt;
+// Inclusive scan of one int per thread over a kBlk work-group.
+__device__ __forceinline__ int32_t block_incl_1024(int32_t v, int32_t* s_warp) {
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
 #pragma unroll
     for (int o = 1; o < 64; o <<= 1) {
-        int32_t u = __shfl_up(v, o, 64);
+        const int32_t u = __shfl_up(v, o, 64);
         if (lane >= o) v += u;
     }
     if (lane == 63) s_warp[wid] = v;
     __syncthreads();
     int32_t before = 0;
     for (int k = 0; k < wid; k++) before += s_warp[k];
-    s_incl[t] = v + before;
+    return v + before;
+}
+
+__device__ __forceinline__ int64_t block_sum_1024(int64_t c, int64_t* s) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o, 64);
+    if ((threadIdx.x & 63) == 0) s[threadIdx.x >> 6] = c;
     __syncthreads();
-    const int32_t total = s_incl[kEmitThreads - 1];
-    const int64_t base = block_offs[blockIdx.x];
-    for (int32_t p = t; p < total; p += kEmitThreads) {
-        int lo = 0, hi = kEmitThreads - 1;     // first j with s_incl[j] > p
+    int64_t t = 0;
+    for (int k = 0; k < kBlk / 64; k++) t += s[k];
+    return t;
+}
+
+__global__ __launch_bounds__(kBlk) void k_valid_count(const pg_bin* __restrict__ bins, int64_t n_gv,
+                                                      int64_t* __restrict__ blk) {
+    __shared__ int64_t s[kBlk / 64];
+    const int64_t gv = (int64_t)blockIdx.x * kBlk + threadIdx.x;
+    const int64_t c = (gv < n_gv && bins[gv].n_tiles > 0) ? 1 : 0;
+    const int64_t t = block_sum_1024(c, s);
+    if (threadIdx.x == 0) blk[blockIdx.x] = t;
+}
+
+__global__ __launch_bounds__(kBlk) void k_compact(const pg_bin* __restrict__ bins, int64_t n_gv, int64_t N,
+                                                  const int64_t* __restrict__ blk_off, uint64_t* __restrict__ rk,
+                                                  int32_t* __restrict__ rv) {
+    __shared__ int32_t s_warp[kBlk / 64];
+    const int64_t gv = (int64_t)blockIdx.x * kBlk + threadIdx.x;
+    uint4 b = make_uint4(0u, 0u, 0u, 0u);
+    if (gv < n_gv) b = reinterpret_cast<const uint4*>(bins)[gv];
+    const int32_t valid = (gv < n_gv && b.w > 0) ? 1 : 0;
+    const int32_t incl = block_incl_1024(valid, s_warp);
+    if (valid) {
+        const int64_t pos = blk_off[blockIdx.x] + incl - 1;
+        rk[pos] = ((uint64_t)(gv / N) << 32) | (uint64_t)b.z;
+        rv[pos] = (int32_t)gv;
+    }
+}
+
+__global__ __launch_bounds__(kBlk) void k_sorted_count(const pg_bin* __restrict__ bins,
+                                                       const int32_t* __restrict__ rv,
+                                                       const int64_t* __restrict__ misc, int64_t* __restrict__ blk) {
+    __shared__ int64_t s[kBlk / 64];
+    const int64_t p = (int64_t)blockIdx.x * kBlk + threadIdx.x;
+    const int64_t c = p < misc[0] ? (int64_t)bins[rv[p]].n_tiles : 0;
+    const int64_t t = block_sum_1024(c, s);
+    if (threadIdx.x == 0) blk[blockIdx.x] = t;
+}
+
+__global__ void k_post_count(const int64_t* n_inst, int64_t cap, int32_t* overflow, int64_t* misc, int t_digit) {
+    const int64_t I = *n_inst;
+    const bool of = I > cap;
+    *overflow = of ? 1 : 0;
+    const int64_t eff = of ? 0 : I;
+    misc[1] = eff;
+    misc[3] = ceil_div(eff, kSortTile) << t_digit;
+}
+
+__global__ void k_depth_counts_len(int64_t* misc, int d_digit) { misc[2] = ceil_div(misc[0], kSortTile) << d_digit; }
+
+// Emission in sorted-record order: the group's output range is written
+// contiguously; each lane finds its (record, tile) by binary search over the
+// group's prefix sums.
+__global__ __launch_bounds__(kBlk) void k_emit(const pg_bin* __restrict__ bins, const int32_t* __restrict__ rv,
+                                               int64_t N, const ViewDev* __restrict__ views,
+                                               const int64_t* __restrict__ blk_off, const int64_t* __restrict__ misc,
+                                               uint32_t* __restrict__ tkeys, int32_t* __restrict__ tvals) {
+    __shared__ int32_t s_incl[kBlk];
+    __shared__ uint2 s_rect[kBlk];
+    __shared__ int32_t s_gv[kBlk];
+    __shared__ int32_t s_warp[kBlk / 64];
+    if (misc[1] == 0) return;   // overflow (or nothing to emit): uniform exit
+    const int t = threadIdx.x;
+    const int64_t p = (int64_t)blockIdx.x * kBlk + t;
+    int32_t nt = 0;
+    if (p < misc[0]) {
+        const int32_t gv = rv[p];
+        const uint4 b = reinterpret_cast<const uint4*>(bins)[gv];
+        nt = (int32_t)b.w;
+        s_rect[t] = make_uint2(b.x, b.y);
+        s_gv[t] = gv;
+    }
+    s_incl[t] = block_incl_1024(nt, s_warp);
+    __syncthreads();
+    const int32_t total = s_incl[kBlk - 1];
+    const int64_t base = blk_off[blockIdx.x];
+    for (int32_t q = t; q < total; q += kBlk) {
+        int lo = 0, hi = kBlk - 1;     // first j with s_incl[j] > q
         while (lo < hi) {
             const int mid = (lo + hi) >> 1;
-            if (s_incl[mid] > p) hi = mid; else lo = mid + 1;
+            if (s_incl[mid] > q) hi = mid; else lo = mid + 1;
         }
-        const int32_t k = p - (lo ? s_incl[lo - 1] : 0);
+        const int32_t k = q - (lo ? s_incl[lo - 1] : 0);
         const uint2 r = s_rect[lo];
         const int32_t xlo = (int32_t)(r.x & 0xffff), ylo = (int32_t)(r.x >> 16);
         const int32_t xhi = (int32_t)(r.y & 0xffff);
         const int32_t w = xhi - xlo + 1;
         const int32_t tx = xlo + k % w, ty = ylo + k / w;
-        const int64_t g = gv0 + lo;
-        const int64_t view = g / N;
-        const ViewDev& V = views[view];
-        const uint64_t tile = (uint64_t)(V.tile_base + (int64_t)ty * V.TX + tx);
-        keys[base + p] = (tile << 32) | (uint64_t)s_key[lo];
-        vals[base + p] = (int32_t)g;
+        const int32_t gv = s_gv[lo];
+        const ViewDev& V = views[gv / N];
+        tkeys[base + q] = (uint32_t)(V.tile_base + (int64_t)ty * V.TX + tx);
+        tvals[base + q] = gv;
     }
 }
 
-// Peers of this lane: active lanes holding the same 8-bit digit.
+// ------------------------------------------------------------------ LSD radix pass
+// Peers of this lane: active lanes holding the same BITS-bit digit.
+template <int BITS>
 __device__ __forceinline__ uint64_t match_digit(uint32_t d, bool active) {
     uint64_t peers = __ballot(active);
 #pragma unroll
-    for (int b = 0; b < kRadixBits; b++) {
+    for (int b = 0; b < BITS; b++) {
         const bool bit = (d >> b) & 1u;
         const uint64_t m = __ballot(bit);
         peers &= bit ? m : ~m;
@@ -158,95 +237,123 @@ __device__ __forceinline__ uint64_t match_digit(uint32_t d, bool active) {
     return peers;
 }
 
-__global__ __launch_bounds__(kSortThreads) void k_radix_upsweep(const uint64_t* __restrict__ keys,
-                                                                const int64_t* __restrict__ misc, int shift,
+template <typename K, int BITS>
+__global__ __launch_bounds__(kSortThreads) void k_radix_upsweep(const K* __restrict__ keys,
+                                                                const int64_t* __restrict__ n_ptr, int shift,
                                                                 int32_t* __restrict__ counts) {
-    __shared__ uint32_t s_cnt[kRadix];
-    const int64_t I = misc[0];
-    const int64_t ntile = ceil_div(I, kSortTile);
+    constexpr int NB = 1 << BITS;
+    __shared__ uint32_t s_cnt[NB];
+    const int64_t n = *n_ptr;
+    const int64_t ntile = ceil_div(n, kSortTile);
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     for (int64_t b = blockIdx.x; b < ntile; b += gridDim.x) {
-        s_cnt[threadIdx.x] = 0;
+        for (int d = threadIdx.x; d < NB; d += kSortThreads) s_cnt[d] = 0;
         __syncthreads();
         const int64_t start = b * kSortTile + (int64_t)wid * (kSortTile / 4);
 #pragma unroll 4
         for (int r = 0; r < kSortItems; r++) {
             const int64_t idx = start + r * 64 + lane;
-            const bool active = idx < I;
-            const uint32_t d = active ? (uint32_t)((keys[idx] >> shift) & (kRadix - 1)) : 0u;
-            const uint64_t peers = match_digit(d, active);
+            const bool active = idx < n;
+            const uint32_t d = active ? (uint32_t)((keys[idx] >> shift) & (NB - 1)) : 0u;
+            const uint64_t peers = match_digit<BITS>(d, active);
             const uint64_t below = peers & ((1ull << lane) - 1ull);
             if (active && below == 0) atomicAdd(&s_cnt[d], (uint32_t)__popcll(peers));
         }
         __syncthreads();
-        counts[(int64_t)threadIdx.x * ntile + b] = (int32_t)s_cnt[threadIdx.x];
+        for (int d = threadIdx.x; d < NB; d += kSortThreads) counts[(int64_t)d * ntile + b] = (int32_t)s_cnt[d];
         __syncthreads();
     }
 }
 
-__global__ __launch_bounds__(kSortThreads) void k_radix_downsweep(const uint64_t* __restrict__ keys_in,
+template <typename K, int BITS>
+__global__ __launch_bounds__(kSortThreads) void k_radix_downsweep(const K* __restrict__ keys_in,
                                                                   const int32_t* __restrict__ vals_in,
-                                                                  uint64_t* __restrict__ keys_out,
+                                                                  K* __restrict__ keys_out,
                                                                   int32_t* __restrict__ vals_out,
-                                                                  const int64_t* __restrict__ misc, int shift,
+                                                                  const int64_t* __restrict__ n_ptr, int shift,
                                                                   const int32_t* __restrict__ count_offs) {
-    __shared__ uint32_t s_hist[4][kRadix];
-    __shared__ uint32_t s_boff[kRadix];
-    __shared__ int32_t s_glob[kRadix];
-    __shared__ uint32_t s_wsum[4];
-    __shared__ uint64_t s_keys[kSortTile];
+    constexpr int NB = 1 << BITS;
+    constexpr int PER = NB >= kSortThreads ? NB / kSortThreads : 1;   // digits per thread in the digit scan
+    constexpr int ACT = NB / PER;                                     // threads taking part in it
+    __shared__ uint32_t s_hist[4][NB];
+    __shared__ uint32_t s_boff[NB];
+    __shared__ int32_t s_glob[NB];
+    __shared__ uint32_t s_part[kSortThreads];
+    __shared__ K s_keys[kSortTile];
     __shared__ int32_t s_vals[kSortTile];
-    const int64_t I = misc[0];
-    const int64_t ntile = ceil_div(I, kSortTile);
+    const int64_t n = *n_ptr;
+    const int64_t ntile = ceil_div(n, kSortTile);
     const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
     for (int64_t b = blockIdx.x; b < ntile; b += gridDim.x) {
-        for (int w = 0; w < 4; w++) s_hist[w][t] = 0;
+        for (int d = t; d < NB; d += kSortThreads) {
+#pragma unroll
+            for (int w = 0; w < 4; w++) s_hist[w][d] = 0;
+        }
         __syncthreads();
         const int64_t start = b * kSortTile + (int64_t)wid * (kSortTile / 4);
-        uint64_t key[kSortItems];
+        K key[kSortItems];
         int32_t val[kSortItems];
         uint32_t rank[kSortItems];
 #pragma unroll
         for (int r = 0; r < kSortItems; r++) {
             const int64_t idx = start + r * 64 + lane;
-            const bool active = idx < I;
-            key[r] = active ? keys_in[idx] : 0ull;
+            const bool active = idx < n;
+            key[r] = active ? keys_in[idx] : (K)0;
             val[r] = active ? vals_in[idx] : 0;
-            const uint32_t d = (uint32_t)((key[r] >> shift) & (kRadix - 1));
-            const uint64_t peers = match_digit(d, active);
+            const uint32_t d = (uint32_t)((key[r] >> shift) & (NB - 1));
+            const uint64_t peers = match_digit<BITS>(d, active);
             const uint64_t below = peers & ((1ull << lane) - 1ull);
             const uint32_t base = s_hist[wid][d];
             rank[r] = base + (uint32_t)__popcll(below);
             if (active && below == 0) s_hist[wid][d] = base + (uint32_t)__popcll(peers);
         }
         __syncthreads();
-        // per digit: exclusive over waves, then exclusive over digits of the block totals
-        uint32_t run = 0;
+        // per digit: exclusive over waves; then exclusive over digits of the block totals
+        uint32_t tot[PER];
+        uint32_t mine = 0;
+        if (t < ACT) {
 #pragma unroll
-        for (int w = 0; w < 4; w++) {
-            const uint32_t c = s_hist[w][t];
-            s_hist[w][t] = run;
-            run += c;
+            for (int e = 0; e < PER; e++) {
+                const int d = t * PER + e;
+                uint32_t run = 0;
+#pragma unroll
+                for (int w = 0; w < 4; w++) {
+                    const uint32_t c = s_hist[w][d];
+                    s_hist[w][d] = run;
+                    run += c;
+                }
+                tot[e] = run;
+                mine += run;
+                s_glob[d] = count_offs[(int64_t)d * ntile + b];
+            }
         }
-        s_glob[t] = count_offs[(int64_t)t * ntile + b];
-        uint32_t incl = run;
+        // exclusive scan of s_part over the first ACT threads (serial per wave, then waves)
+        uint32_t incl = mine;
 #pragma unroll
         for (int o = 1; o < 64; o <<= 1) {
             const uint32_t u = __shfl_up(incl, o, 64);
             if (lane >= o) incl += u;
         }
-        if (lane == 63) s_wsum[wid] = incl;
+        __syncthreads();
+        if (lane == 63) s_part[wid] = incl;
         __syncthreads();
         uint32_t pre = 0;
-        for (int w = 0; w < wid; w++) pre += s_wsum[w];
-        s_boff[t] = pre + incl - run;
+        for (int w = 0; w < wid; w++) pre += s_part[w];
+        if (t < ACT) {
+            uint32_t x = pre + incl - mine;
+#pragma unroll
+            for (int e = 0; e < PER; e++) {
+                s_boff[t * PER + e] = x;
+                x += tot[e];
+            }
+        }
         __syncthreads();
-        const int64_t tile_n = imin(kSortTile, I - b * kSortTile);
+        const int64_t tile_n = imin(kSortTile, n - b * kSortTile);
 #pragma unroll
         for (int r = 0; r < kSortItems; r++) {
             const int64_t idx = start + r * 64 + lane;
-            if (idx < I) {
-                const uint32_t d = (uint32_t)((key[r] >> shift) & (kRadix - 1));
+            if (idx < n) {
+                const uint32_t d = (uint32_t)((key[r] >> shift) & (NB - 1));
                 const uint32_t pos = s_boff[d] + s_hist[wid][d] + rank[r];
                 s_keys[pos] = key[r];
                 s_vals[pos] = val[r];
@@ -254,8 +361,8 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_downsweep(const uint64_t
         }
         __syncthreads();
         for (int64_t i = t; i < tile_n; i += kSortThreads) {
-            const uint64_t k = s_keys[i];
-            const uint32_t d = (uint32_t)((k >> shift) & (kRadix - 1));
+            const K k = s_keys[i];
+            const uint32_t d = (uint32_t)((k >> shift) & (NB - 1));
             const int64_t o = (int64_t)s_glob[d] + (i - (int64_t)s_boff[d]);
             keys_out[o] = k;
             vals_out[o] = s_vals[i];
@@ -264,13 +371,41 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_downsweep(const uint64_t
     }
 }
 
-__global__ void k_ranges(const uint64_t* __restrict__ keys, const int64_t* __restrict__ misc,
+template <typename K>
+hipError_t radix_pass(int bits, const K* ki, const int32_t* vi, K* ko, int32_t* vo, const int64_t* n_ptr,
+                      int64_t* counts_len, int shift, SortWs& w, unsigned grid, hipStream_t s) {
+    switch (bits) {
+#define PG_PASS(B)                                                                                       \
+    case B:                                                                                              \
+        k_radix_upsweep<K, B><<<grid, kSortThreads, 0, s>>>(ki, n_ptr, shift, w.counts);                 \
+        break;
+        PG_PASS(1) PG_PASS(2) PG_PASS(3) PG_PASS(4) PG_PASS(5) PG_PASS(6) PG_PASS(7) PG_PASS(8) PG_PASS(9)
+        PG_PASS(10)
+#undef PG_PASS
+        default: return hipErrorInvalidValue;
+    }
+    hipError_t e = scan_i32(w.counts, w.count_offs, counts_len, 1, 0, nullptr, w.scan_tmp, s);
+    if (e != hipSuccess) return e;
+    switch (bits) {
+#define PG_PASS(B)                                                                                              \
+    case B:                                                                                                     \
+        k_radix_downsweep<K, B><<<grid, kSortThreads, 0, s>>>(ki, vi, ko, vo, n_ptr, shift, w.count_offs);       \
+        break;
+        PG_PASS(1) PG_PASS(2) PG_PASS(3) PG_PASS(4) PG_PASS(5) PG_PASS(6) PG_PASS(7) PG_PASS(8) PG_PASS(9)
+        PG_PASS(10)
+#undef PG_PASS
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+__global__ void k_ranges(const uint32_t* __restrict__ keys, const int64_t* __restrict__ misc,
                          int32_t* __restrict__ ranges) {
-    const int64_t I = misc[0];
+    const int64_t I = misc[1];
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < I; i += (int64_t)gridDim.x * blockDim.x) {
-        const uint32_t tile = (uint32_t)(keys[i] >> 32);
-        if (i == 0 || (uint32_t)(keys[i - 1] >> 32) != tile) ranges[2 * (int64_t)tile] = (int32_t)i;
-        if (i == I - 1 || (uint32_t)(keys[i + 1] >> 32) != tile) ranges[2 * (int64_t)tile + 1] = (int32_t)(i + 1);
+        const uint32_t tile = keys[i];
+        if (i == 0 || keys[i - 1] != tile) ranges[2 * (int64_t)tile] = (int32_t)i;
+        if (i == I - 1 || keys[i + 1] != tile) ranges[2 * (int64_t)tile + 1] = (int32_t)(i + 1);
     }
 }
 
@@ -282,39 +417,55 @@ size_t sort_ws_bytes(const pg_views* v, int64_t cap) {
     return total;
 }
 
-hipError_t launch_bin_sort(const pg_views* v, const pg_bin* bins, int64_t cap, uint64_t* keys, int32_t* values,
+hipError_t launch_bin_sort(const pg_views* v, const pg_bin* bins, int64_t cap, uint32_t* keys, int32_t* values,
                            int32_t* ranges, int64_t* n_inst_dev, int32_t* overflow_dev, void* ws, hipStream_t s) {
+    const SortPlan pl = plan_for(v);
     SortWs w = carve(v, cap, ws, nullptr);
-    const int64_t nb = n_emit_blocks(v);
+    const int64_t nb = n_blocks(v);
     hipError_t e = fill_u32(ranges, 0u, 2 * v->n_tiles, s);
     if (e != hipSuccess) return e;
-    if (nb > 0) {
-        k_bin_count<<<(unsigned)nb, kEmitThreads, 0, s>>>(bins, v->n_gv, w.block_sums);
-        e = scan_i64(w.block_sums, w.block_offs, nullptr, 0, nb, n_inst_dev, w.scan_tmp, s);
+    if (v->n_gv == 0) {
+        e = fill_u32(w.misc, 0u, 16, s);
         if (e != hipSuccess) return e;
-    } else {
         e = fill_u32(n_inst_dev, 0u, 2, s);
         if (e != hipSuccess) return e;
+        k_post_count<<<1, 1, 0, s>>>(n_inst_dev, cap, overflow_dev, w.misc, pl.t_digit);
+        return hipGetLastError();
     }
-    k_post_count<<<1, 1, 0, s>>>(n_inst_dev, cap, overflow_dev, w.misc);
-    const int passes = v->sort_passes;
-    // emit into the buffer that makes the last pass land in the caller's arrays
-    uint64_t* kA = (passes % 2 == 0) ? keys : w.keys_alt;
-    int32_t* vA = (passes % 2 == 0) ? values : w.vals_alt;
-    uint64_t* kB = (passes % 2 == 0) ? w.keys_alt : keys;
-    int32_t* vB = (passes % 2 == 0) ? w.vals_alt : values;
-    if (nb > 0)
-        k_emit<<<(unsigned)nb, kEmitThreads, 0, s>>>(bins, v->n_gv, v->n_gauss, v->d_views, w.block_offs, w.misc, kA,
-                                                     vA);
-    const unsigned grid = (unsigned)imax(1, imin(kSortGrid, ceil_div(cap, kSortTile)));
-    for (int p = 0; p < passes; p++) {
-        const int shift = p * kRadixBits;
-        k_radix_upsweep<<<grid, kSortThreads, 0, s>>>(kA, w.misc, shift, w.counts);
-        e = scan_i32(w.counts, w.count_offs, w.misc + 1, 1, 0, nullptr, w.scan_tmp, s);
+    // 1. compact surviving records, keyed (view << 32 | depth)
+    k_valid_count<<<(unsigned)nb, kBlk, 0, s>>>(bins, v->n_gv, w.blk_a);
+    e = scan_i64(w.blk_a, w.blk_a_off, nullptr, 0, nb, w.misc + 0, w.scan_tmp, s);
+    if (e != hipSuccess) return e;
+    k_compact<<<(unsigned)nb, kBlk, 0, s>>>(bins, v->n_gv, v->n_gauss, w.blk_a_off, w.rk0, w.rv0);
+    k_depth_counts_len<<<1, 1, 0, s>>>(w.misc, pl.d_digit);
+    // 2. stable LSD sort of the records by (view, depth)
+    const unsigned grid_r = (unsigned)imax(1, imin(kSortGrid, ceil_div(v->n_gv, kSortTile)));
+    uint64_t *rka = w.rk0, *rkb = w.rk1;
+    int32_t *rva = w.rv0, *rvb = w.rv1;
+    for (int p = 0; p < pl.d_passes; p++) {
+        e = radix_pass<uint64_t>(pl.d_digit, rka, rva, rkb, rvb, w.misc + 0, w.misc + 2, p * pl.d_digit, w, grid_r, s);
         if (e != hipSuccess) return e;
-        k_radix_downsweep<<<grid, kSortThreads, 0, s>>>(kA, vA, kB, vB, w.misc, shift, w.count_offs);
-        uint64_t* tk = kA; kA = kB; kB = tk;
-        int32_t* tv = vA; vA = vB; vB = tv;
+        uint64_t* tk = rka; rka = rkb; rkb = tk;
+        int32_t* tv = rva; rva = rvb; rvb = tv;
+    }
+    // 3. instance offsets in sorted-record order; overflow check
+    k_sorted_count<<<(unsigned)nb, kBlk, 0, s>>>(bins, rva, w.misc, w.blk_a);
+    e = scan_i64(w.blk_a, w.blk_a_off, nullptr, 0, nb, n_inst_dev, w.scan_tmp, s);
+    if (e != hipSuccess) return e;
+    k_post_count<<<1, 1, 0, s>>>(n_inst_dev, cap, overflow_dev, w.misc, pl.t_digit);
+    // 4. emit (tile, gv) in record order into the buffer that makes the last tile pass land in the caller's arrays
+    uint32_t* ta = (pl.t_passes % 2 == 0) ? keys : w.tk_alt;
+    int32_t* tva = (pl.t_passes % 2 == 0) ? values : w.tv_alt;
+    uint32_t* tb = (pl.t_passes % 2 == 0) ? w.tk_alt : keys;
+    int32_t* tvb = (pl.t_passes % 2 == 0) ? w.tv_alt : values;
+    k_emit<<<(unsigned)nb, kBlk, 0, s>>>(bins, rva, v->n_gauss, v->d_views, w.blk_a_off, w.misc, ta, tva);
+    // 5. stable LSD sort of the instances by tile id
+    const unsigned grid_i = (unsigned)imax(1, imin(kSortGrid, ceil_div(cap, kSortTile)));
+    for (int p = 0; p < pl.t_passes; p++) {
+        e = radix_pass<uint32_t>(pl.t_digit, ta, tva, tb, tvb, w.misc + 1, w.misc + 3, p * pl.t_digit, w, grid_i, s);
+        if (e != hipSuccess) return e;
+        uint32_t* tk = ta; ta = tb; tb = tk;
+        int32_t* tv = tva; tva = tvb; tvb = tv;
     }
     k_ranges<<<1024, 256, 0, s>>>(keys, w.misc, ranges);
     return hipGetLastError();

@@ -15,8 +15,6 @@ constexpr int kScanBlocks = 1024;    // fixed grid of the device-length scans
 constexpr int kSortThreads = 256;    // radix sort work-group
 constexpr int kSortItems = 16;       // keys per thread
 constexpr int kSortTile = kSortThreads * kSortItems;
-constexpr int kRadixBits = 8;
-constexpr int kRadix = 1 << kRadixBits;
 
 // Per-view table resident on the device.
 struct ViewDev {
@@ -84,7 +82,7 @@ hipError_t launch_project_bwd(const pg_views* v, const float* params, const floa
 
 // binsort.hip
 size_t sort_ws_bytes(const pg_views* v, int64_t cap);
-hipError_t launch_bin_sort(const pg_views* v, const pg_bin* bins, int64_t cap, uint64_t* keys, int32_t* values,
+hipError_t launch_bin_sort(const pg_views* v, const pg_bin* bins, int64_t cap, uint32_t* keys, int32_t* values,
                            int32_t* ranges, int64_t* n_inst_dev, int32_t* overflow_dev, void* ws, hipStream_t s);
 
 // render.hip

@@ -81,6 +81,7 @@ struct TileGeo {
     int64_t tile, vbase;
     int32_t W, H;
     double ox, oy;
+    float row0;                  // local y of the tile's first pixel row
     int32_t px[kPPT], py[kPPT];
     float fx[kPPT], fy[kPPT];
     bool inside[kPPT];
@@ -99,6 +100,7 @@ __device__ __forceinline__ void tile_geo(const ViewDev* views, int nv, int64_t n
     const int32_t ox = (tx * TW) & ~31, oy = (ty * TH) & ~31;
     t.ox = (double)ox;
     t.oy = (double)oy;
+    t.row0 = (float)(ty * TH - oy);
 #pragma unroll
     for (int j = 0; j < kPPT; j++) {
         const int32_t lp = (int32_t)threadIdx.x + kLanes * j;
@@ -110,16 +112,39 @@ __device__ __forceinline__ void tile_geo(const ViewDev* views, int nv, int64_t n
     }
 }
 
-// Stage Gaussian `gv` into LDS slot `k` in coordinates local to (ox, oy).
+// Stage Gaussian `gv` into LDS slot `k` in coordinates local to (ox, oy), with
+// the mask of pixel slots its ellipse q <= 9 can reach.  Slot j covers tile
+// rows [j R, (j + 1) R) (R = 64 / TW); the ellipse's vertical half-extent is
+// 3 sqrt(Sigma_yy), Sigma_yy = a / (a c - b^2) from the conic.  The bound is
+// widened (0.1% + 0.01 px) to cover FP32 rounding of q and falls back to "all
+// slots" for ill-conditioned conics, so a skipped slot never holds a pixel
+// with q <= 9 and results are unchanged.
+template <int TW, int TH>
 __device__ __forceinline__ void stage(const pg_splat* __restrict__ splats, int32_t gv, double ox, double oy,
-                                      float4* s_geo, float4* s_col, float* s_blu, int k) {
+                                      float row0, float4* s_geo, float4* s_col, float* s_blu, uint32_t* s_mask,
+                                      int k) {
     const float4* sp = reinterpret_cast<const float4*>(splats + gv);
     const float4 a = sp[0], b = sp[1], c = sp[2];
     double2 m;
     *reinterpret_cast<float4*>(&m) = a;
-    s_geo[k] = make_float4((float)(m.x - ox), (float)(m.y - oy), b.x, 2.0f * b.y);
+    const float my = (float)(m.y - oy);
+    s_geo[k] = make_float4((float)(m.x - ox), my, b.x, 2.0f * b.y);
     s_col[k] = make_float4(b.z, b.w, c.x, c.y);   // conic c, opacity, red, green
     s_blu[k] = c.z;
+    constexpr int R = kLanes / TW;                // pixel rows per slot
+    const float ac = b.x * b.z;
+    const float det = ac - b.y * b.y;
+    uint32_t mask = (1u << kPPT) - 1u;
+    if (det > 1e-2f * ac && b.x > 0.0f) {
+        const float ext = 3.0f * sqrtf(b.x / det) * 1.001f + 0.01f;
+        mask = 0u;
+#pragma unroll
+        for (int j = 0; j < kPPT; j++) {
+            const float lo = row0 + (float)(j * R) + 0.5f, hi = row0 + (float)(j * R + R - 1) + 0.5f;
+            if (my + ext >= lo && my - ext <= hi) mask |= 1u << j;
+        }
+    }
+    s_mask[k] = mask;
 }
 
 template <int TW, int TH, int BATCH, bool STATS>
@@ -133,60 +158,58 @@ __global__ __launch_bounds__(kLanes) void k_render_fwd(const ViewDev* __restrict
     __shared__ float4 s_geo[BATCH];
     __shared__ float4 s_col[BATCH];
     __shared__ float s_blu[BATCH];
+    __shared__ uint32_t s_mask[BATCH];
     TileGeo t;
     tile_geo<TW, TH>(views, nv, n_tiles, t);
     const int2 rg = ranges[t.tile];
     float T[kPPT], C0[kPPT], C1[kPPT], C2[kPPT];
     int32_t n[kPPT];
-    bool done[kPPT];
+    uint64_t live[kPPT];     // lanes of slot j still compositing (wave-uniform lane mask)
 #pragma unroll
     for (int j = 0; j < kPPT; j++) {
         T[j] = 1.0f;
         C0[j] = C1[j] = C2[j] = 0.0f;
         n[j] = 0;
-        done[j] = !t.inside[j];
+        live[j] = __ballot(t.inside[j]);
     }
-    uint32_t n_eval = 0, n_comp = 0;
+    uint64_t n_eval = 0, n_comp = 0;        // wave totals (STATS only)
     for (int32_t b0 = rg.x; b0 < rg.y; b0 += BATCH) {
-        bool alive = false;
-#pragma unroll
-        for (int j = 0; j < kPPT; j++) alive = alive || !done[j];
-        if (!__any(alive)) break;
+        if ((live[0] | live[1] | live[2] | live[3]) == 0) break;
         __syncthreads();
         for (int32_t i = threadIdx.x; i < BATCH && b0 + i < rg.y; i += kLanes)
-            stage(splats, values[b0 + i], t.ox, t.oy, s_geo, s_col, s_blu, i);
+            stage<TW, TH>(splats, values[b0 + i], t.ox, t.oy, t.row0, s_geo, s_col, s_blu, s_mask, i);
         __syncthreads();
         const int32_t cnt = min(BATCH, rg.y - b0);
         for (int32_t k = 0; k < cnt; k++) {
             const float4 g = s_geo[k];
             const float4 cc = s_col[k];
             const float cb = s_blu[k];
+            const uint32_t mask = s_mask[k];
             const int32_t pos1 = b0 - rg.x + k + 1;
 #pragma unroll
             for (int j = 0; j < kPPT; j++) {
+                if (STATS) n_eval += __popcll(live[j]);
+                if (!((mask >> j) & 1u) || live[j] == 0) continue;   // ellipse misses the slot / slot done
                 const float dx = t.fx[j] - g.x, dy = t.fy[j] - g.y;
                 const float q = quad(dx, dy, g.z, g.w, cc.x);
-                if (STATS) n_eval += done[j] ? 0u : 1u;
-                bool in = !done[j] && q <= kQMax;
-                if (!__any(in)) continue;             // wave-uniform: no pixel of this slot inside
+                const uint64_t inm = __ballot(q <= kQMax) & live[j];
+                if (inm == 0) continue;
                 const Eval ev = evaluate(q, cc.y);
-                in = in && ev.alpha >= kAlphaMin;
+                const uint64_t passm = __ballot(ev.alpha >= kAlphaMin) & inm;
                 const float Tn = T[j] * (1.0f - ev.alpha);
-                const bool stop = in && Tn < kTMin;
-                const bool take = in && !stop;
-                done[j] = done[j] || stop;
+                const uint64_t stopm = __ballot(Tn < kTMin) & passm;
+                const uint64_t takem = passm & ~stopm;
+                live[j] &= ~stopm;
+                if (STATS) n_comp += __popcll(takem);
+                const bool take = __builtin_amdgcn_inverse_ballot_w64(takem);
                 const float w = take ? T[j] * ev.alpha : 0.0f;
                 C0[j] = fmaf(w, cc.z, C0[j]);
                 C1[j] = fmaf(w, cc.w, C1[j]);
                 C2[j] = fmaf(w, cb, C2[j]);
                 T[j] = take ? Tn : T[j];
                 n[j] = take ? pos1 : n[j];
-                if (STATS) n_comp += take ? 1u : 0u;
             }
-            bool alive2 = false;
-#pragma unroll
-            for (int j = 0; j < kPPT; j++) alive2 = alive2 || !done[j];
-            if (!__any(alive2)) break;                // every pixel of the tile has terminated
+            if ((live[0] | live[1] | live[2] | live[3]) == 0) break;   // every pixel has terminated
         }
     }
     const int64_t HW = (int64_t)t.W * t.H;
@@ -201,17 +224,9 @@ __global__ __launch_bounds__(kLanes) void k_render_fwd(const ViewDev* __restrict
         final_T[t.vbase + p] = T[j];
         n_contrib[t.vbase + p] = n[j];
     }
-    if (STATS) {
-        unsigned long long e = n_eval, c = n_comp;
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1) {
-            e += __shfl_xor(e, o, 64);
-            c += __shfl_xor(c, o, 64);
-        }
-        if (threadIdx.x == 0) {
-            atomicAdd(&counters[0], e);
-            atomicAdd(&counters[1], c);
-        }
+    if (STATS && threadIdx.x == 0) {
+        atomicAdd(&counters[0], (unsigned long long)n_eval);
+        atomicAdd(&counters[1], (unsigned long long)n_comp);
     }
 }
 
@@ -221,26 +236,52 @@ __device__ __forceinline__ float dpp(float v) {
     return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROW_MASK, 0xf, false));
 }
 
-// Sums of N values over the 64 lanes of the wave with DPP moves only (no LDS
-// traffic), the N reductions interleaved step by step: butterflies inside
-// quads, half-row and row mirrors give every lane its 16-lane row sum, two row
-// broadcasts fold the rows into lane 63, which is read into a scalar.
-template <int N>
-__device__ __forceinline__ void wave_sums(float* x) {
+// Row/half-wave swaps of gfx950: lane i of every row (or half) meets lane i of
+// the partner row (half).  Adding both results leaves every lane holding the
+// sum over the pair of rows (halves).
+__device__ __forceinline__ float cross_rows(float x) {
+    auto a = __builtin_amdgcn_permlane16_swap(__float_as_uint(x), __float_as_uint(x), false, false);
+    x = __uint_as_float(a[0]) + __uint_as_float(a[1]);
+    auto b = __builtin_amdgcn_permlane32_swap(__float_as_uint(x), __float_as_uint(x), false, false);
+    return __uint_as_float(b[0]) + __uint_as_float(b[1]);
+}
+
+// Totals of nine per-lane values over the 64 lanes of the wave, delivered as
+// value i in lane i (i < 9).  Transpose butterfly: each exchange step sends
+// one half of a register pair to the partner lane and keeps the other, so
+// 8 values shrink to 2 registers after the two quad exchanges (xor 1, xor 2);
+// rotations by 4 and 8 inside a row then sum the lanes sharing the same two
+// low bits, and the row/half swaps add the four rows.  The ninth value is
+// reduced on its own.  DPP and permlane moves only; no LDS traffic.
+__device__ __forceinline__ float wave_totals9(const float* v, int lane) {
+    const bool o1 = lane & 1, o2 = lane & 2;
+    float r[4];
 #pragma unroll
-    for (int i = 0; i < N; i++) x[i] += dpp<0xB1>(x[i]);          // quad_perm [1,0,3,2]
+    for (int p = 0; p < 4; p++) {
+        const float keep = o1 ? v[2 * p + 1] : v[2 * p];
+        const float send = o1 ? v[2 * p] : v[2 * p + 1];
+        r[p] = keep + dpp<0xB1>(send);                  // quad_perm [1,0,3,2]
+    }
+    float t[2];
 #pragma unroll
-    for (int i = 0; i < N; i++) x[i] += dpp<0x4E>(x[i]);          // quad_perm [2,3,0,1]
+    for (int p = 0; p < 2; p++) {
+        const float keep = o2 ? r[2 * p + 1] : r[2 * p];
+        const float send = o2 ? r[2 * p] : r[2 * p + 1];
+        t[p] = keep + dpp<0x4E>(send);                  // quad_perm [2,3,0,1]
+    }
+    float x8 = v[8];
+    x8 += dpp<0xB1>(x8);
+    x8 += dpp<0x4E>(x8);
 #pragma unroll
-    for (int i = 0; i < N; i++) x[i] += dpp<0x141>(x[i]);         // row_half_mirror
-#pragma unroll
-    for (int i = 0; i < N; i++) x[i] += dpp<0x140>(x[i]);         // row_mirror
-#pragma unroll
-    for (int i = 0; i < N; i++) x[i] += dpp<0x142, 0xA>(x[i]);    // row_bcast:15 into rows 1, 3
-#pragma unroll
-    for (int i = 0; i < N; i++) x[i] += dpp<0x143, 0xC>(x[i]);    // row_bcast:31 into rows 2, 3
-#pragma unroll
-    for (int i = 0; i < N; i++) x[i] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x[i]), 63));
+    for (int p = 0; p < 2; p++) {
+        t[p] += dpp<0x124>(t[p]);                       // row_ror:4
+        t[p] += dpp<0x128>(t[p]);                       // row_ror:8
+        t[p] = cross_rows(t[p]);
+    }
+    x8 += dpp<0x124>(x8);
+    x8 += dpp<0x128>(x8);
+    x8 = cross_rows(x8);
+    return lane < 4 ? t[0] : (lane < 8 ? t[1] : x8);
 }
 
 template <int TW, int TH, int BATCH>
@@ -256,6 +297,7 @@ __global__ __launch_bounds__(kLanes) void k_render_bwd(const ViewDev* __restrict
     __shared__ float4 s_col[BATCH];
     __shared__ float s_blu[BATCH];
     __shared__ int32_t s_gv[BATCH];
+    __shared__ uint32_t s_mask[BATCH];
     TileGeo t;
     tile_geo<TW, TH>(views, nv, n_tiles, t);
     const int2 rg = ranges[t.tile];
@@ -292,21 +334,26 @@ __global__ __launch_bounds__(kLanes) void k_render_bwd(const ViewDev* __restrict
         for (int32_t i = lane; i < cnt; i += kLanes) {
             const int32_t gv = values[rg.x + bstart + i];
             s_gv[i] = gv;
-            stage(splats, gv, t.ox, t.oy, s_geo, s_col, s_blu, i);
+            stage<TW, TH>(splats, gv, t.ox, t.oy, t.row0, s_geo, s_col, s_blu, s_mask, i);
         }
         __syncthreads();
         for (int32_t k = cnt - 1; k >= 0; k--) {
             const float4 g = s_geo[k];
             const float4 cc = s_col[k];
             const float cb = s_blu[k];
-            const float bb = 0.5f * g.w;
+            const uint32_t mask = s_mask[k];
             const int32_t pos = bstart + k;
-            float acc[9];
+            // Per-lane sums over the lane's pixels, later reduced over the wave:
+            //   m[0..1] = sum dq' (dx, dy), m[2..4] = sum dq' (dx^2, dx dy, dy^2)
+            //   with dq' = alpha dL/dalpha (so dL/dq = -dq'/2), m[5] = sum e dL/dalpha,
+            //   m[6..8] = sum T alpha G (colour).
+            float m[9];
 #pragma unroll
-            for (int i = 0; i < 9; i++) acc[i] = 0.0f;
+            for (int i = 0; i < 9; i++) m[i] = 0.0f;
             bool any_c = false;
 #pragma unroll
             for (int j = 0; j < kPPT; j++) {
+                if (!((mask >> j) & 1u)) continue;    // ellipse cannot reach this slot
                 const float dx = t.fx[j] - g.x, dy = t.fy[j] - g.y;
                 const float q = quad(dx, dy, g.z, g.w, cc.x);
                 bool in = pos < n[j] && q <= kQMax;
@@ -318,29 +365,42 @@ __global__ __launch_bounds__(kLanes) void k_render_bwd(const ViewDev* __restrict
                 const float al = ev.alpha;
                 const float Tk = T[j] * __builtin_amdgcn_rcpf(1.0f - al);   // transmittance in front of k
                 T[j] = in ? Tk : T[j];
-                const float w = in ? Tk * al : 0.0f;
-                acc[6] += w * G0[j];
-                acc[7] += w * G1[j];
-                acc[8] += w * G2[j];
-                const float dal =
-                    in ? Tk * ((G0[j] * (cc.z - B0[j]) + G1[j] * (cc.w - B1[j])) + G2[j] * (cb - B2[j])) : 0.0f;
-                B0[j] = in ? al * cc.z + (1.0f - al) * B0[j] : B0[j];
-                B1[j] = in ? al * cc.w + (1.0f - al) * B1[j] : B1[j];
-                B2[j] = in ? al * cb + (1.0f - al) * B2[j] : B2[j];
+                const float Te = in ? Tk : 0.0f;
+                const float ae = in ? al : 0.0f;
+                const float w = Te * al;
+                m[6] = fmaf(w, G0[j], m[6]);
+                m[7] = fmaf(w, G1[j], m[7]);
+                m[8] = fmaf(w, G2[j], m[8]);
+                const float d0 = cc.z - B0[j], d1 = cc.w - B1[j], d2 = cb - B2[j];
+                const float dal = Te * fmaf(G2[j], d2, fmaf(G1[j], d1, G0[j] * d0));
+                B0[j] = fmaf(ae, d0, B0[j]);          // B <- alpha c + (1 - alpha) B
+                B1[j] = fmaf(ae, d1, B1[j]);
+                B2[j] = fmaf(ae, d2, B2[j]);
                 const float dau = ev.raw < kAlphaMax ? dal : 0.0f;   // clamped alpha: no opacity / shape terms
-                acc[5] += dau * ev.e;
-                const float dq = -0.5f * al * dau;
-                acc[2] += dq * dx * dx;
-                acc[3] += dq * 2.0f * dx * dy;
-                acc[4] += dq * dy * dy;
-                acc[0] += -2.0f * dq * (g.z * dx + bb * dy);
-                acc[1] += -2.0f * dq * (bb * dx + cc.x * dy);
+                m[5] = fmaf(dau, ev.e, m[5]);
+                const float dqp = al * dau;
+                const float px = dqp * dx, py = dqp * dy;
+                m[0] += px;
+                m[1] += py;
+                m[2] = fmaf(px, dx, m[2]);
+                m[3] = fmaf(px, dy, m[3]);
+                m[4] = fmaf(py, dy, m[4]);
             }
             if (!any_c) continue;
-            wave_sums<9>(acc);
-            float mine = 0.0f;
-#pragma unroll
-            for (int i = 0; i < 9; i++) mine = (lane == i) ? acc[i] : mine;
+            // per-lane partials of the 2D gradients: dm = [[a, b], [b, c]] (Sx, Sy);
+            // d(a, b, c) = -(Sxx / 2, Sxy, Syy / 2) (linear, so applied before the lane sum)
+            const float bb = 0.5f * g.w;
+            float v[9];
+            v[0] = fmaf(g.z, m[0], bb * m[1]);
+            v[1] = fmaf(bb, m[0], cc.x * m[1]);
+            v[2] = -0.5f * m[2];
+            v[3] = -m[3];
+            v[4] = -0.5f * m[4];
+            v[5] = m[5];
+            v[6] = m[6];
+            v[7] = m[7];
+            v[8] = m[8];
+            const float mine = wave_totals9(v, lane);
             if (lane < 9) unsafeAtomicAdd(&grad2d[(int64_t)lane * n_gv + s_gv[k]], mine);
         }
     }

@@ -54,7 +54,7 @@ class _ViewSet:
     def set_capacity(self, cap):
         cap = int(max(cap, 1))
         self.cap = cap
-        self.keys = torch.empty(cap, dtype=torch.int64, device=self.device)
+        self.keys = torch.empty(cap, dtype=torch.int32, device=self.device)
         self.values = torch.empty(cap, dtype=torch.int32, device=self.device)
         self.ws_bytes = abi.pg_sort_workspace_size(self.handle, cap)
         self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.device)
@@ -244,7 +244,7 @@ class Renderer:
     def sorted_instances(self, k=0):
         s = self.sets[k]
         n = int(s.n_inst.item())
-        return s.keys[:n].cpu().numpy().view(np.uint64), s.values[:n].cpu().numpy()
+        return s.keys[:n].cpu().numpy().view(np.uint32), s.values[:n].cpu().numpy()
 
 
 class PackUVRender(torch.autograd.Function):

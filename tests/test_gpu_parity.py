@@ -75,8 +75,7 @@ def test_fetch_project_sort_bit_exact(name):
         np.testing.assert_allclose(s["color"][valid], pr["color"][valid], rtol=1e-6, atol=1e-7)
         assert np.array_equal(s["depth"][valid].view(np.uint32), pr["key"][valid])
         inst = fw.inst[v]
-        exp_keys.append(((inst["tile"].astype(np.uint64) + np.uint64(tb[v])) << np.uint64(32))
-                        | inst["key"].astype(np.uint64))
+        exp_keys.append((inst["tile"] + tb[v]).astype(np.uint32))
         exp_vals.append(inst["id"].astype(np.int64) + v * N)
         rg = r.sets[0].ranges.cpu().numpy().reshape(-1, 2)[tb[v]:tb[v + 1]]
         ref_rg = fw.ranges[v]
