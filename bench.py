@@ -227,10 +227,11 @@ def stage_times(r, atlas, target, reps=5):
     calls = {
         "fetch": lambda: r.fetch(atlas),
         "project": lambda: abi.pg_project(s.handle, r.params, s.splats, s.bins, r.visible, stream),
-        "bin_sort": lambda: abi.pg_bin_sort(s.handle, s.bins, s.cap, s.keys, s.values, s.ranges, s.n_inst, s.overflow,
-                                            s.ws, s.ws_bytes, stream),
+        "bin_sort": lambda: abi.pg_bin_sort(s.handle, s.bins, s.cap, s.keys, s.values, s.ranges, s.inst_first,
+                                            s.n_inst, s.overflow, s.ws, s.ws_bytes, stream),
         "render_fwd": lambda: abi.pg_render_fwd(s.handle, s.splats, s.values, s.ranges, r.bg, r.image, r.final_T,
-                                                r.n_contrib, None, stream),
+                                                r.n_contrib, s.tile_entries, s.entry_pos, s.entry_mask, None,
+                                                stream),
         "loss_l1": lambda: r.loss_l1(target),
         "render_bwd": lambda: r.backward(),
     }

@@ -26,8 +26,8 @@
  *    leaves the sorted outputs undefined; *n_inst_dev holds the capacity
  *    that would have sufficed.  NaN inputs propagate; there are no checks on
  *    the hot path.
- *  - Forward outputs are bitwise deterministic.  Gradients are summed with
- *    float atomics, so their last bits may vary run to run.
+ *  - Forward and adjoint outputs are bitwise deterministic (fixed reduction
+ *    orders, no floating-point atomics).
  *
  * Data layouts
  * ------------
@@ -177,43 +177,70 @@ pg_status pg_project(const pg_views* views, const float* params, pg_splat* splat
  *                  sorted instance (ascending)
  *   values         device int32 [inst_capacity] out: gv of each sorted instance
  *   tile_ranges    device int32 [n_tiles][2] out: [start, end) per tile
+ *   inst_first     device int32 [n_gv] out: for each (view, Gaussian) with
+ *                  n_tiles > 0, the index of its first instance in emission
+ *                  order (the records sorted by depth, each followed by the
+ *                  tiles of its rectangle in row-major order); the adjoint
+ *                  keeps one gradient slot per instance in that order
  *   n_inst_dev     device int64 [1] out: number of instances
  *   overflow_dev   device int32 [1] out: 1 if n_inst > inst_capacity, else 0
  *   ws             device workspace of pg_sort_workspace_size bytes */
 pg_status pg_bin_sort(const pg_views* views, const pg_bin* bins, int64_t inst_capacity, uint32_t* keys,
-                      int32_t* values, int32_t* tile_ranges, int64_t* n_inst_dev, int32_t* overflow_dev,
-                      void* ws, size_t ws_bytes, void* stream);
+                      int32_t* values, int32_t* tile_ranges, int32_t* inst_first, int64_t* n_inst_dev,
+                      int32_t* overflow_dev, void* ws, size_t ws_bytes, void* stream);
 
 /* a4 -- Front-to-back compositing (supplementary viewer section:
  * C = sum_i T_i alpha_i c_i, T_i = prod_{j<i} (1 - alpha_j); footprint
  * d^2 <= 9 of Sec. 4.2).  Per pixel: skip q > 9; alpha = min(0.99, o e^{-q/2});
  * skip alpha < 1/255; stop before T (1 - alpha) < 1e-4.  Writes C + T bg.
- *   bg         host float[3]
- *   image      device float [3 n_pixels] out (per view planar [3][H][W])
- *   final_T    device float [n_pixels] out
- *   n_contrib  device int32 [n_pixels] out: 1-based list position of the last
- *              composited Gaussian, 0 if none
- *   counters   device uint64 [2] or NULL: += {pairs evaluated, pairs composited} */
+ * Also records, for the adjoint, which pixels composited which Gaussian.
+ *   bg           host float[3]
+ *   image        device float [3 n_pixels] out (per view planar [3][H][W])
+ *   final_T      device float [n_pixels] out
+ *   n_contrib    device int32 [n_pixels] out: 1-based list position of the
+ *                last composited Gaussian, 0 if none
+ *   tile_entries device int32 [n_tiles] out: number of entries of each tile
+ *   entry_pos    device int32 [inst_capacity] out: for tile t, entries
+ *                [start_t, start_t + tile_entries[t]) hold the 0-based list
+ *                positions (ascending) of the Gaussians that composited at
+ *                least one pixel of the tile
+ *   entry_mask   device uint64 [inst_capacity][4] out: per entry, the pixels
+ *                of each 8x8 block of the tile that composited it (bit l =
+ *                pixel (l % 8, l / 8) of the block; blocks in row-major order)
+ *   counters     device uint64 [2] or NULL: += {pairs evaluated, pairs composited} */
 pg_status pg_render_fwd(const pg_views* views, const pg_splat* splats, const int32_t* values,
                         const int32_t* tile_ranges, const float* bg, float* image, float* final_T,
-                        int32_t* n_contrib, uint64_t* counters, void* stream);
+                        int32_t* n_contrib, int32_t* tile_entries, int32_t* entry_pos, uint64_t* entry_mask,
+                        uint64_t* counters, void* stream);
 
 /* a5 -- Adjoint of a2-a4 back to the texels, with gradient freezing
- * grad <- D_i grad (Sec. 4.2 "Gradient Freezing").  Recomputes per-pixel
- * transmittance from final_T instead of storing it.
+ * grad <- D_i grad (Sec. 4.2 "Gradient Freezing").  Walks each tile's
+ * entries back to front with the forward's decisions, recomputing
+ * per-pixel transmittance from final_T instead of storing it.  Each
+ * (Gaussian, tile) sum lands in its own instance slot (no atomics); the
+ * projection adjoint adds a record's slots in a fixed order, so the result
+ * is bitwise deterministic.
+ *   bins, inst_first, n_inst_dev          from pg_project / pg_bin_sort; after an
+ *                overflowed sort (n_inst > inst_capacity) no slot is touched and
+ *                the texel gradient is zero
+ *   tile_entries, entry_pos, entry_mask   from pg_render_fwd
  *   dL_dimage    device float [3 n_pixels]
  *   gauss_texel  device int32 [n_gauss] (from pg_atlas_fetch)
  *   dynamic_mask device uint8 [H][W] or NULL (NULL: every Gaussian dynamic)
+ *   inst_capacity the capacity given to pg_bin_sort
+ *   inst_grad    device float [inst_capacity][9] workspace
  *   grad2d       device float [9][n_gv] out: per (view, Gaussian) dL/d(m_x,
  *                m_y, a, b, c, opacity, r, g, b)
  *   dL_datlas    device float [F][C][H][W] out; written (accumulate = 0: every
  *                texel, unoccupied = 0) or added to (accumulate = 1: occupied
  *                texels only). */
-pg_status pg_render_bwd(const pg_views* views, const float* params, const pg_splat* splats,
-                        const int32_t* values, const int32_t* tile_ranges, const float* bg, const float* final_T,
-                        const int32_t* n_contrib, const float* dL_dimage, const int32_t* gauss_texel,
-                        const uint8_t* dynamic_mask, int32_t H, int32_t W, float* grad2d, float* dL_datlas,
-                        int32_t accumulate, void* stream);
+pg_status pg_render_bwd(const pg_views* views, const float* params, const pg_splat* splats, const pg_bin* bins,
+                        const int32_t* values, const int32_t* tile_ranges, const int32_t* inst_first,
+                        const int64_t* n_inst_dev, int64_t inst_capacity, const int32_t* tile_entries,
+                        const int32_t* entry_pos,
+                        const uint64_t* entry_mask, const float* bg, const float* final_T, const float* dL_dimage,
+                        const int32_t* gauss_texel, const uint8_t* dynamic_mask, int32_t H, int32_t W,
+                        float* inst_grad, float* grad2d, float* dL_datlas, int32_t accumulate, void* stream);
 
 /* a4' -- L1 photometric term of Sec. 4.2 "Objective" (lambda_ssim = 0):
  * L = mean |image - target|, dL/dimage = sign(image - target) / n (sign 0 = 0).

@@ -60,9 +60,10 @@ SIGNATURES = {
     "pg_sort_workspace_size": (_i32, [_p, _i64, C.POINTER(_sz)]),
     "pg_atlas_fetch": (_i32, [_p, _p, _i32, _i32, _i32, _i32, _i64, _p, _p, _p, _p, _p, _sz, _p]),
     "pg_project": (_i32, [_p, _p, _p, _p, _p, _p]),
-    "pg_bin_sort": (_i32, [_p, _p, _i64, _p, _p, _p, _p, _p, _p, _sz, _p]),
-    "pg_render_fwd": (_i32, [_p, _p, _p, _p, _p, _p, _p, _p, _p, _p]),
-    "pg_render_bwd": (_i32, [_p, _p, _p, _p, _p, _p, _p, _p, _p, _p, _p, _i32, _i32, _p, _p, _i32, _p]),
+    "pg_bin_sort": (_i32, [_p, _p, _i64, _p, _p, _p, _p, _p, _p, _p, _sz, _p]),
+    "pg_render_fwd": (_i32, [_p, _p, _p, _p, _p, _p, _p, _p, _p, _p, _p, _p, _p]),
+    "pg_render_bwd": (_i32, [_p, _p, _p, _p, _p, _p, _p, _p, _i64, _p, _p, _p, _p, _p, _p, _p, _p, _i32, _i32, _p,
+                             _p, _p, _i32, _p]),
     "pg_loss_l1": (_i32, [_p, _p, _i64, _p, _p, _p, _p]),
     "pg_adam_step": (_i32, [_p, _p, _p, _p, _p, _p, _i64, _i32, _i32, _i32, _i32, _f32, _f32, _f32, _f32, _i32, _p]),
 }
@@ -189,26 +190,31 @@ def pg_project(views, params, splats, bins, visible, stream=None):
            "pg_project")
 
 
-def pg_bin_sort(views, bins, inst_capacity, keys, values, tile_ranges, n_inst_dev, overflow_dev, ws, ws_bytes,
-                stream=None):
+def pg_bin_sort(views, bins, inst_capacity, keys, values, tile_ranges, inst_first, n_inst_dev, overflow_dev, ws,
+                ws_bytes, stream=None):
     _check(lib().pg_bin_sort(views, _ptr(bins), int(inst_capacity), _ptr(keys), _ptr(values), _ptr(tile_ranges),
-                             _ptr(n_inst_dev), _ptr(overflow_dev), _ptr(ws), int(ws_bytes), _stream(stream)),
-           "pg_bin_sort")
+                             _ptr(inst_first), _ptr(n_inst_dev), _ptr(overflow_dev), _ptr(ws), int(ws_bytes),
+                             _stream(stream)), "pg_bin_sort")
 
 
-def pg_render_fwd(views, splats, values, tile_ranges, bg, image, final_T, n_contrib, counters=None, stream=None):
+def pg_render_fwd(views, splats, values, tile_ranges, bg, image, final_T, n_contrib, tile_entries, entry_pos,
+                  entry_mask, counters=None, stream=None):
     bgv = (C.c_float * 3)(*[float(b) for b in bg])
     _check(lib().pg_render_fwd(views, _ptr(splats), _ptr(values), _ptr(tile_ranges), C.addressof(bgv), _ptr(image),
-                               _ptr(final_T), _ptr(n_contrib), _ptr(counters), _stream(stream)), "pg_render_fwd")
+                               _ptr(final_T), _ptr(n_contrib), _ptr(tile_entries), _ptr(entry_pos),
+                               _ptr(entry_mask), _ptr(counters), _stream(stream)), "pg_render_fwd")
 
 
-def pg_render_bwd(views, params, splats, values, tile_ranges, bg, final_T, n_contrib, dL_dimage, gauss_texel,
-                  dynamic_mask, H, W, grad2d, dL_datlas, accumulate, stream=None):
+def pg_render_bwd(views, params, splats, bins, values, tile_ranges, inst_first, n_inst_dev, inst_capacity,
+                  tile_entries, entry_pos, entry_mask, bg, final_T, dL_dimage, gauss_texel, dynamic_mask, H, W,
+                  inst_grad, grad2d, dL_datlas, accumulate, stream=None):
     bgv = (C.c_float * 3)(*[float(b) for b in bg])
-    _check(lib().pg_render_bwd(views, _ptr(params), _ptr(splats), _ptr(values), _ptr(tile_ranges), C.addressof(bgv),
-                               _ptr(final_T), _ptr(n_contrib), _ptr(dL_dimage), _ptr(gauss_texel),
-                               _ptr(dynamic_mask), int(H), int(W), _ptr(grad2d), _ptr(dL_datlas), int(accumulate),
-                               _stream(stream)), "pg_render_bwd")
+    _check(lib().pg_render_bwd(views, _ptr(params), _ptr(splats), _ptr(bins), _ptr(values), _ptr(tile_ranges),
+                               _ptr(inst_first), _ptr(n_inst_dev), int(inst_capacity), _ptr(tile_entries),
+                               _ptr(entry_pos),
+                               _ptr(entry_mask), C.addressof(bgv), _ptr(final_T), _ptr(dL_dimage), _ptr(gauss_texel),
+                               _ptr(dynamic_mask), int(H), int(W), _ptr(inst_grad), _ptr(grad2d), _ptr(dL_datlas),
+                               int(accumulate), _stream(stream)), "pg_render_bwd")
 
 
 def pg_loss_l1(image, target, n, dL_dimage, partial, loss_dev, stream=None):

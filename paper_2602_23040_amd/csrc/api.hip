@@ -243,52 +243,60 @@ pg_status pg_project(const pg_views* v, const float* params, pg_splat* splats, p
 }
 
 pg_status pg_bin_sort(const pg_views* v, const pg_bin* bins, int64_t cap, uint32_t* keys, int32_t* values,
-                      int32_t* tile_ranges, int64_t* n_inst_dev, int32_t* overflow_dev, void* ws, size_t ws_bytes,
-                      void* stream) {
+                      int32_t* tile_ranges, int32_t* inst_first, int64_t* n_inst_dev, int32_t* overflow_dev, void* ws,
+                      size_t ws_bytes, void* stream) {
     g_error.clear();
     if (!v) return invalid("views is null");
     if (!tile_ranges || !n_inst_dev || !overflow_dev || !ws) return invalid("null pointer argument");
-    if (v->n_gv > 0 && !bins) return invalid("bins is null");
+    if (v->n_gv > 0 && (!bins || !inst_first)) return invalid("bins / inst_first is null");
     if (cap < 0 || cap > INT32_MAX) return invalid("inst_capacity must be in [0, 2^31 - 1]");
     if (cap > 0 && (!keys || !values)) return invalid("keys / values null with inst_capacity > 0");
     if (ws_bytes < sort_ws_bytes(v, cap)) {
         set_error("sort workspace too small");
         return PG_ERR_WORKSPACE;
     }
-    PG_CHECK_HIP(launch_bin_sort(v, bins, cap, keys, values, tile_ranges, n_inst_dev, overflow_dev, ws,
+    PG_CHECK_HIP(launch_bin_sort(v, bins, cap, keys, values, tile_ranges, inst_first, n_inst_dev, overflow_dev, ws,
                                  (hipStream_t)stream),
                  "pg_bin_sort");
     return PG_OK;
 }
 
 pg_status pg_render_fwd(const pg_views* v, const pg_splat* splats, const int32_t* values, const int32_t* tile_ranges,
-                        const float* bg, float* image, float* final_T, int32_t* n_contrib, uint64_t* counters,
-                        void* stream) {
+                        const float* bg, float* image, float* final_T, int32_t* n_contrib, int32_t* tile_entries,
+                        int32_t* entry_pos, uint64_t* entry_mask, uint64_t* counters, void* stream) {
     g_error.clear();
     if (!v || !bg) return invalid("null argument");
-    if (!image || !final_T || !n_contrib || !tile_ranges) return invalid("null pointer argument");
-    if (v->n_gv > 0 && (!splats || !values)) return invalid("null pointer argument");
-    PG_CHECK_HIP(launch_render_fwd(v, splats, values, tile_ranges, bg, image, final_T, n_contrib, counters,
-                                   (hipStream_t)stream),
+    if (!image || !final_T || !n_contrib || !tile_ranges || !tile_entries) return invalid("null pointer argument");
+    if (v->n_gv > 0 && (!splats || !values || !entry_pos || !entry_mask)) return invalid("null pointer argument");
+    PG_CHECK_HIP(launch_render_fwd(v, splats, values, tile_ranges, bg, image, final_T, n_contrib, tile_entries,
+                                   entry_pos, entry_mask, counters, (hipStream_t)stream),
                  "pg_render_fwd");
     return PG_OK;
 }
 
-pg_status pg_render_bwd(const pg_views* v, const float* params, const pg_splat* splats, const int32_t* values,
-                        const int32_t* tile_ranges, const float* bg, const float* final_T, const int32_t* n_contrib,
+pg_status pg_render_bwd(const pg_views* v, const float* params, const pg_splat* splats, const pg_bin* bins,
+                        const int32_t* values, const int32_t* tile_ranges, const int32_t* inst_first,
+                        const int64_t* n_inst_dev, int64_t inst_capacity, const int32_t* tile_entries,
+                        const int32_t* entry_pos, const uint64_t* entry_mask, const float* bg, const float* final_T,
                         const float* dL_dimage, const int32_t* gauss_texel, const uint8_t* dynamic_mask, int32_t H,
-                        int32_t W, float* grad2d, float* dL_datlas, int32_t accumulate, void* stream) {
+                        int32_t W, float* inst_grad, float* grad2d, float* dL_datlas, int32_t accumulate,
+                        void* stream) {
     g_error.clear();
     if (!v || !bg) return invalid("null argument");
-    if (!tile_ranges || !final_T || !n_contrib || !dL_dimage || !dL_datlas) return invalid("null pointer argument");
-    if (v->n_gv > 0 && (!params || !splats || !values || !gauss_texel || !grad2d))
+    if (!tile_ranges || !tile_entries || !final_T || !dL_dimage || !dL_datlas || !n_inst_dev)
+        return invalid("null pointer argument");
+    if (v->n_gv > 0 && (!params || !splats || !bins || !values || !inst_first || !entry_pos || !entry_mask ||
+                        !gauss_texel || !grad2d || !inst_grad))
         return invalid("null pointer argument");
     if (H < 1 || W < 1 || (int64_t)H * W < v->n_gauss) return invalid("H * W must hold n_gauss texels");
     if (accumulate != 0 && accumulate != 1) return invalid("accumulate must be 0 or 1");
+    if (inst_capacity < 0 || inst_capacity > INT32_MAX) return invalid("inst_capacity must be in [0, 2^31 - 1]");
     hipStream_t s = (hipStream_t)stream;
-    PG_CHECK_HIP(launch_render_bwd(v, splats, values, tile_ranges, bg, final_T, n_contrib, dL_dimage, grad2d, s),
+    PG_CHECK_HIP(launch_render_bwd(v, splats, bins, values, tile_ranges, inst_first, tile_entries, entry_pos,
+                                   entry_mask, bg, final_T, dL_dimage, n_inst_dev, inst_capacity, inst_grad, s),
                  "pg_render_bwd (raster)");
-    PG_CHECK_HIP(launch_project_bwd(v, params, grad2d, gauss_texel, dynamic_mask, H, W, dL_datlas, accumulate, s),
+    PG_CHECK_HIP(launch_project_bwd(v, params, bins, inst_first, n_inst_dev, inst_capacity, inst_grad, grad2d,
+                                    gauss_texel, dynamic_mask, H, W, dL_datlas, accumulate, s),
                  "pg_render_bwd (projection)");
     return PG_OK;
 }

@@ -20,7 +20,9 @@
 //   k_valid_count / k_compact   records with n_tiles > 0 -> (view << 32 | depth, gv)
 //   radix passes (64-bit keys)  LSD, digit width <= 10 bits
 //   k_sorted_count / k_emit     tiles per sorted record -> instance offsets ->
-//                               work-group-cooperative emission (coalesced writes)
+//                               work-group-cooperative emission (coalesced writes);
+//                               inst_first[gv] = emission index of the record's
+//                               first tile (its tiles follow in rectangle order)
 //   radix passes (32-bit keys)  tile ids
 //   k_ranges                    [start, end) of every tile
 // Radix passes: per-tile digit histograms (upsweep), a scan of the histograms,
@@ -184,7 +186,8 @@ __global__ void k_depth_counts_len(int64_t* misc, int d_digit) { misc[2] = ceil_
 __global__ __launch_bounds__(kBlk) void k_emit(const pg_bin* __restrict__ bins, const int32_t* __restrict__ rv,
                                                int64_t N, const ViewDev* __restrict__ views,
                                                const int64_t* __restrict__ blk_off, const int64_t* __restrict__ misc,
-                                               uint32_t* __restrict__ tkeys, int32_t* __restrict__ tvals) {
+                                               uint32_t* __restrict__ tkeys, int32_t* __restrict__ tvals,
+                                               int32_t* __restrict__ inst_first) {
     __shared__ int32_t s_incl[kBlk];
     __shared__ uint2 s_rect[kBlk];
     __shared__ int32_t s_gv[kBlk];
@@ -204,6 +207,7 @@ __global__ __launch_bounds__(kBlk) void k_emit(const pg_bin* __restrict__ bins, 
     __syncthreads();
     const int32_t total = s_incl[kBlk - 1];
     const int64_t base = blk_off[blockIdx.x];
+    if (nt > 0) inst_first[s_gv[t]] = (int32_t)(base + s_incl[t] - nt);   // emission index of the record's first tile
     for (int32_t q = t; q < total; q += kBlk) {
         int lo = 0, hi = kBlk - 1;     // first j with s_incl[j] > q
         while (lo < hi) {
@@ -418,7 +422,8 @@ size_t sort_ws_bytes(const pg_views* v, int64_t cap) {
 }
 
 hipError_t launch_bin_sort(const pg_views* v, const pg_bin* bins, int64_t cap, uint32_t* keys, int32_t* values,
-                           int32_t* ranges, int64_t* n_inst_dev, int32_t* overflow_dev, void* ws, hipStream_t s) {
+                           int32_t* ranges, int32_t* inst_first, int64_t* n_inst_dev, int32_t* overflow_dev,
+                           void* ws, hipStream_t s) {
     const SortPlan pl = plan_for(v);
     SortWs w = carve(v, cap, ws, nullptr);
     const int64_t nb = n_blocks(v);
@@ -458,7 +463,8 @@ hipError_t launch_bin_sort(const pg_views* v, const pg_bin* bins, int64_t cap, u
     int32_t* tva = (pl.t_passes % 2 == 0) ? values : w.tv_alt;
     uint32_t* tb = (pl.t_passes % 2 == 0) ? w.tk_alt : keys;
     int32_t* tvb = (pl.t_passes % 2 == 0) ? w.tv_alt : values;
-    k_emit<<<(unsigned)nb, kBlk, 0, s>>>(bins, rva, v->n_gauss, v->d_views, w.blk_a_off, w.misc, ta, tva);
+    k_emit<<<(unsigned)nb, kBlk, 0, s>>>(bins, rva, v->n_gauss, v->d_views, w.blk_a_off, w.misc, ta, tva,
+                                         inst_first);
     // 5. stable LSD sort of the instances by tile id
     const unsigned grid_i = (unsigned)imax(1, imin(kSortGrid, ceil_div(cap, kSortTile)));
     for (int p = 0; p < pl.t_passes; p++) {

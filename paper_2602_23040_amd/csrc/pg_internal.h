@@ -76,22 +76,29 @@ hipError_t launch_fetch(const float* atlas, const uint8_t* occ, int32_t F, int32
 // project.hip
 hipError_t launch_project(const pg_views* v, const float* params, pg_splat* splats, pg_bin* bins,
                           uint8_t* visible, hipStream_t s);
-hipError_t launch_project_bwd(const pg_views* v, const float* params, const float* grad2d,
+hipError_t launch_project_bwd(const pg_views* v, const float* params, const pg_bin* bins,
+                              const int32_t* inst_first, const int64_t* n_inst_dev, int64_t cap,
+                              const float* inst_grad, float* grad2d,
                               const int32_t* gauss_texel, const uint8_t* dyn, int32_t H, int32_t W,
                               float* dL_datlas, int32_t accumulate, hipStream_t s);
 
 // binsort.hip
 size_t sort_ws_bytes(const pg_views* v, int64_t cap);
 hipError_t launch_bin_sort(const pg_views* v, const pg_bin* bins, int64_t cap, uint32_t* keys, int32_t* values,
-                           int32_t* ranges, int64_t* n_inst_dev, int32_t* overflow_dev, void* ws, hipStream_t s);
+                           int32_t* ranges, int32_t* inst_first, int64_t* n_inst_dev, int32_t* overflow_dev,
+                           void* ws, hipStream_t s);
 
 // render.hip
 hipError_t launch_render_fwd(const pg_views* v, const pg_splat* splats, const int32_t* values,
                              const int32_t* ranges, const float bg[3], float* image, float* final_T,
-                             int32_t* n_contrib, uint64_t* counters, hipStream_t s);
-hipError_t launch_render_bwd(const pg_views* v, const pg_splat* splats, const int32_t* values,
-                             const int32_t* ranges, const float bg[3], const float* final_T,
-                             const int32_t* n_contrib, const float* dL_dimage, float* grad2d, hipStream_t s);
+                             int32_t* n_contrib, int32_t* tile_entries, int32_t* entry_pos, uint64_t* entry_mask,
+                             uint64_t* counters, hipStream_t s);
+hipError_t launch_render_bwd(const pg_views* v, const pg_splat* splats, const pg_bin* bins, const int32_t* values,
+                             const int32_t* ranges, const int32_t* inst_first, const int32_t* tile_entries,
+                             const int32_t* entry_pos, const uint64_t* entry_mask, const float bg[3],
+                             const float* final_T, const float* dL_dimage, const int64_t* n_inst_dev, int64_t cap,
+                             float* inst_grad, hipStream_t s);
+hipError_t fill_u32_dev(void* p, uint32_t value, const int64_t* n_dev, int64_t n_max, int64_t mul, hipStream_t s);
 
 // optim.hip
 hipError_t launch_loss_l1(const float* img, const float* tgt, int64_t n, float* g, double* partial, float* loss,

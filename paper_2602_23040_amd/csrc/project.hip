@@ -276,7 +276,11 @@ __global__ __launch_bounds__(128) void k_project_bwd(const ViewDev* __restrict__
                                                      const int32_t* __restrict__ frame_views,
                                                      const int32_t* __restrict__ view_order, int32_t F, int32_t C,
                                                      int64_t N, int64_t n_gv, const float* __restrict__ params,
-                                                     const float* __restrict__ grad2d,
+                                                     const pg_bin* __restrict__ bins,
+                                                     const int32_t* __restrict__ inst_first,
+                                                     const int64_t* __restrict__ n_inst_dev, int64_t cap,
+                                                     const float* __restrict__ inst_grad,
+                                                     float* __restrict__ grad2d,
                                                      const int32_t* __restrict__ gauss_texel,
                                                      const uint8_t* __restrict__ dyn, int64_t HW,
                                                      float* __restrict__ gatlas, int32_t accumulate) {
@@ -298,15 +302,31 @@ __global__ __launch_bounds__(128) void k_project_bwd(const ViewDev* __restrict__
     for (int k = 0; k < 11 + 3 * NB; k++) acc[k] = 0.f;
     World w;
     bool have_world = false;
+    const int64_t n_inst = *n_inst_dev;
+    const bool sorted_ok = n_inst <= cap;     // an overflowed sort leaves no usable slots
     for (int32_t vi = v0; vi < v1; vi++) {
         const int32_t v = view_order[vi];
         const int64_t gv = (int64_t)v * N + i;
+        // 2D gradient of the record: its per-tile sums, added in rectangle order
+        const int32_t nt = bins[gv].n_tiles;
+        float s9[9];
+#pragma unroll
+        for (int k = 0; k < 9; k++) s9[k] = 0.0f;
+        const int64_t first = nt > 0 ? (int64_t)inst_first[gv] : 0;
+        if (nt > 0 && sorted_ok && first >= 0 && first + nt <= n_inst) {
+            const float* ig = inst_grad + first * 9;
+            for (int32_t u = 0; u < nt; u++) {
+#pragma unroll
+                for (int k = 0; k < 9; k++) s9[k] += ig[(int64_t)u * 9 + k];
+            }
+        }
         double g9[9];
         bool nz = false;
 #pragma unroll
         for (int k = 0; k < 9; k++) {
-            g9[k] = grad2d[(int64_t)k * n_gv + gv];
-            nz |= (g9[k] != 0.0);
+            grad2d[(int64_t)k * n_gv + gv] = s9[k];
+            g9[k] = (double)s9[k];
+            nz |= (s9[k] != 0.0f);
         }
         if (!nz) continue;
         if (!have_world) {
@@ -454,7 +474,9 @@ hipError_t launch_project(const pg_views* v, const float* params, pg_splat* spla
     return hipGetLastError();
 }
 
-hipError_t launch_project_bwd(const pg_views* v, const float* params, const float* grad2d,
+hipError_t launch_project_bwd(const pg_views* v, const float* params, const pg_bin* bins,
+                              const int32_t* inst_first, const int64_t* n_inst_dev, int64_t cap,
+                              const float* inst_grad, float* grad2d,
                               const int32_t* gauss_texel, const uint8_t* dyn, int32_t H, int32_t W,
                               float* dL_datlas, int32_t accumulate, hipStream_t s) {
     const int64_t HW = (int64_t)H * W;
@@ -467,7 +489,8 @@ hipError_t launch_project_bwd(const pg_views* v, const float* params, const floa
     const unsigned grid = (unsigned)ceil_div(n, 128);
     auto args = [&](auto kern) {
         kern<<<grid, 128, 0, s>>>(v->d_views, v->d_frame_views, v->d_view_order, v->frames, v->channels, v->n_gauss,
-                                  v->n_gv, params, grad2d, gauss_texel, dyn, HW, dL_datlas, accumulate);
+                                  v->n_gv, params, bins, inst_first, n_inst_dev, cap, inst_grad, grad2d,
+                                  gauss_texel, dyn, HW, dL_datlas, accumulate);
     };
     switch (v->sh_degree) {
         case 0: args(k_project_bwd<0>); break;

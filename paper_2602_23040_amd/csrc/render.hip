@@ -22,13 +22,16 @@
 // the FP64 pixel-space mean: q keeps full FP32 precision at 1080p, and a
 // pixel sees bit-identical inputs whatever the tile shape.
 //
-// The adjoint walks each pixel's composited Gaussians back to front,
-// recovering the transmittance in front of Gaussian k as T_k = T_{k+1} /
-// (1 - alpha_k) from the stored final T (no per-step storage).  Per-Gaussian
-// sums over the tile's pixels are reduced across the wave (skipped when no
-// lane contributes), then across the four waves with LDS float atomics, then
-// added to the (view, Gaussian) gradient with one global float atomic per
-// value and tile.
+// The forward records, per tile, the list positions of the Gaussians that
+// composited at least one pixel and, per 8x8 block, which lanes did.  The
+// adjoint walks only those entries, back to front, with the forward's
+// decisions, recovering the transmittance in front of Gaussian k as
+// T_k = T_{k+1} / (1 - alpha_k) from the stored final T (no per-step
+// storage).  Per-Gaussian sums over the tile's pixels are reduced across the
+// wave with DPP / permlane moves and written, without atomics, to the
+// (Gaussian, tile) instance's own slot; the projection adjoint then adds the
+// slots of each (view, Gaussian) in a fixed order, so gradients are bitwise
+// deterministic.
 #include "pg_internal.h"
 
 namespace pg {
@@ -67,21 +70,21 @@ __device__ __forceinline__ int64_t xcd_remap(int64_t i, int64_t n) {
     return x * per + imin(x, rem) + j;
 }
 
-// One wave (64 lanes) composites one tile; lane l owns the four pixels
-// l, l + 64, l + 128, l + 192 of the tile in row-major order, so each group
-// of 64 pixels ("slot") is a 64-lane sub-block of the tile.  Every staged
-// Gaussian is read from LDS once per lane and applied to four pixels, and the
-// adjoint needs one cross-lane reduction per Gaussian and tile instead of one
-// per 64 pixels.  A slot whose 64 pixels all miss the ellipse is skipped with
-// a wave-uniform branch.
+// One wave (64 lanes) composites one tile of 256 pixels, seen as four 8x8
+// pixel blocks ("slots": 2x2 blocks for 16x16 tiles, 1x4 for 8x32, 4x1 for
+// 32x8).  Lane l owns pixel (l % 8, l / 8) of every block.  Every staged
+// Gaussian is read from LDS once per lane and applied to four pixels; the
+// adjoint needs one cross-lane reduction per Gaussian and tile; a block the
+// ellipse cannot reach is skipped with a scalar branch.
 constexpr int kLanes = 64;
 constexpr int kPPT = 4;
 
 struct TileGeo {
     int64_t tile, vbase;
+    int32_t tx, ty;
     int32_t W, H;
     double ox, oy;
-    float row0;                  // local y of the tile's first pixel row
+    float col0, row0;            // local x, y of the tile's first pixel
     int32_t px[kPPT], py[kPPT];
     float fx[kPPT], fy[kPPT];
     bool inside[kPPT];
@@ -94,18 +97,21 @@ __device__ __forceinline__ void tile_geo(const ViewDev* views, int nv, int64_t n
     const ViewDev& V = views[v];
     const int64_t lt = t.tile - V.tile_base;
     const int32_t tx = (int32_t)(lt % V.TX), ty = (int32_t)(lt / V.TX);
+    t.tx = tx;
+    t.ty = ty;
     t.W = V.W;
     t.H = V.H;
     t.vbase = V.pix_base;
     const int32_t ox = (tx * TW) & ~31, oy = (ty * TH) & ~31;
     t.ox = (double)ox;
     t.oy = (double)oy;
+    t.col0 = (float)(tx * TW - ox);
     t.row0 = (float)(ty * TH - oy);
 #pragma unroll
     for (int j = 0; j < kPPT; j++) {
-        const int32_t lp = (int32_t)threadIdx.x + kLanes * j;
-        t.px[j] = tx * TW + lp % TW;
-        t.py[j] = ty * TH + lp / TW;
+        constexpr int BPR = TW / 8;              // 8x8 blocks per tile row
+        t.px[j] = tx * TW + (j % BPR) * 8 + (int32_t)threadIdx.x % 8;
+        t.py[j] = ty * TH + (j / BPR) * 8 + (int32_t)threadIdx.x / 8;
         t.fx[j] = (float)(t.px[j] - ox) + 0.5f;
         t.fy[j] = (float)(t.py[j] - oy) + 0.5f;
         t.inside[j] = t.px[j] < t.W && t.py[j] < t.H;
@@ -113,35 +119,36 @@ __device__ __forceinline__ void tile_geo(const ViewDev* views, int nv, int64_t n
 }
 
 // Stage Gaussian `gv` into LDS slot `k` in coordinates local to (ox, oy), with
-// the mask of pixel slots its ellipse q <= 9 can reach.  Slot j covers tile
-// rows [j R, (j + 1) R) (R = 64 / TW); the ellipse's vertical half-extent is
-// 3 sqrt(Sigma_yy), Sigma_yy = a / (a c - b^2) from the conic.  The bound is
-// widened (0.1% + 0.01 px) to cover FP32 rounding of q and falls back to "all
-// slots" for ill-conditioned conics, so a skipped slot never holds a pixel
+// the mask of 8x8 pixel blocks its ellipse q <= 9 can reach.  The ellipse's
+// half-extents are 3 sqrt(Sigma_xx) and 3 sqrt(Sigma_yy), with
+// (Sigma_xx, Sigma_yy) = (c, a) / (a c - b^2) from the conic.  The bounds are
+// widened (0.1% + 0.01 px) to cover FP32 rounding of q and fall back to "all
+// blocks" for ill-conditioned conics, so a skipped block never holds a pixel
 // with q <= 9 and results are unchanged.
 template <int TW, int TH>
 __device__ __forceinline__ void stage(const pg_splat* __restrict__ splats, int32_t gv, double ox, double oy,
-                                      float row0, float4* s_geo, float4* s_col, float* s_blu, uint32_t* s_mask,
-                                      int k) {
+                                      float col0, float row0, float4* s_geo, float4* s_col, float* s_blu,
+                                      uint32_t* s_mask, int k) {
     const float4* sp = reinterpret_cast<const float4*>(splats + gv);
     const float4 a = sp[0], b = sp[1], c = sp[2];
     double2 m;
     *reinterpret_cast<float4*>(&m) = a;
-    const float my = (float)(m.y - oy);
-    s_geo[k] = make_float4((float)(m.x - ox), my, b.x, 2.0f * b.y);
+    const float mx = (float)(m.x - ox), my = (float)(m.y - oy);
+    s_geo[k] = make_float4(mx, my, b.x, 2.0f * b.y);
     s_col[k] = make_float4(b.z, b.w, c.x, c.y);   // conic c, opacity, red, green
     s_blu[k] = c.z;
-    constexpr int R = kLanes / TW;                // pixel rows per slot
+    constexpr int BPR = TW / 8;
     const float ac = b.x * b.z;
     const float det = ac - b.y * b.y;
     uint32_t mask = (1u << kPPT) - 1u;
-    if (det > 1e-2f * ac && b.x > 0.0f) {
-        const float ext = 3.0f * sqrtf(b.x / det) * 1.001f + 0.01f;
+    if (det > 1e-2f * ac && b.x > 0.0f && b.z > 0.0f) {
+        const float ex = 3.0f * sqrtf(b.z / det) * 1.001f + 0.01f;
+        const float ey = 3.0f * sqrtf(b.x / det) * 1.001f + 0.01f;
         mask = 0u;
 #pragma unroll
         for (int j = 0; j < kPPT; j++) {
-            const float lo = row0 + (float)(j * R) + 0.5f, hi = row0 + (float)(j * R + R - 1) + 0.5f;
-            if (my + ext >= lo && my - ext <= hi) mask |= 1u << j;
+            const float x0 = col0 + (float)((j % BPR) * 8) + 0.5f, y0 = row0 + (float)((j / BPR) * 8) + 0.5f;
+            if (mx + ex >= x0 && mx - ex <= x0 + 7.0f && my + ey >= y0 && my - ey <= y0 + 7.0f) mask |= 1u << j;
         }
     }
     s_mask[k] = mask;
@@ -154,6 +161,9 @@ __global__ __launch_bounds__(kLanes) void k_render_fwd(const ViewDev* __restrict
                                                        const int2* __restrict__ ranges, float bg0, float bg1,
                                                        float bg2, float* __restrict__ image,
                                                        float* __restrict__ final_T, int32_t* __restrict__ n_contrib,
+                                                       int32_t* __restrict__ tile_entries,
+                                                       int32_t* __restrict__ entry_pos,
+                                                       uint64_t* __restrict__ entry_mask,
                                                        unsigned long long* __restrict__ counters) {
     __shared__ float4 s_geo[BATCH];
     __shared__ float4 s_col[BATCH];
@@ -173,11 +183,13 @@ __global__ __launch_bounds__(kLanes) void k_render_fwd(const ViewDev* __restrict
         live[j] = __ballot(t.inside[j]);
     }
     uint64_t n_eval = 0, n_comp = 0;        // wave totals (STATS only)
+    int32_t n_entries = 0;                  // Gaussians of the tile list that composited somewhere
+    const int lane = threadIdx.x;
     for (int32_t b0 = rg.x; b0 < rg.y; b0 += BATCH) {
         if ((live[0] | live[1] | live[2] | live[3]) == 0) break;
         __syncthreads();
         for (int32_t i = threadIdx.x; i < BATCH && b0 + i < rg.y; i += kLanes)
-            stage<TW, TH>(splats, values[b0 + i], t.ox, t.oy, t.row0, s_geo, s_col, s_blu, s_mask, i);
+            stage<TW, TH>(splats, values[b0 + i], t.ox, t.oy, t.col0, t.row0, s_geo, s_col, s_blu, s_mask, i);
         __syncthreads();
         const int32_t cnt = min(BATCH, rg.y - b0);
         for (int32_t k = 0; k < cnt; k++) {
@@ -186,8 +198,10 @@ __global__ __launch_bounds__(kLanes) void k_render_fwd(const ViewDev* __restrict
             const float cb = s_blu[k];
             const uint32_t mask = s_mask[k];
             const int32_t pos1 = b0 - rg.x + k + 1;
+            uint64_t took[kPPT];
 #pragma unroll
             for (int j = 0; j < kPPT; j++) {
+                took[j] = 0;
                 if (STATS) n_eval += __popcll(live[j]);
                 if (!((mask >> j) & 1u) || live[j] == 0) continue;   // ellipse misses the slot / slot done
                 const float dx = t.fx[j] - g.x, dy = t.fy[j] - g.y;
@@ -200,6 +214,7 @@ __global__ __launch_bounds__(kLanes) void k_render_fwd(const ViewDev* __restrict
                 const uint64_t stopm = __ballot(Tn < kTMin) & passm;
                 const uint64_t takem = passm & ~stopm;
                 live[j] &= ~stopm;
+                took[j] = takem;
                 if (STATS) n_comp += __popcll(takem);
                 const bool take = __builtin_amdgcn_inverse_ballot_w64(takem);
                 const float w = take ? T[j] * ev.alpha : 0.0f;
@@ -208,6 +223,14 @@ __global__ __launch_bounds__(kLanes) void k_render_fwd(const ViewDev* __restrict
                 C2[j] = fmaf(w, cb, C2[j]);
                 T[j] = take ? Tn : T[j];
                 n[j] = take ? pos1 : n[j];
+            }
+            if ((took[0] | took[1] | took[2] | took[3]) != 0) {
+                // entry for the adjoint: list position and the lanes of each block that composited it
+                const int32_t e = rg.x + n_entries;
+                const uint64_t mine = lane == 0 ? took[0] : (lane == 1 ? took[1] : (lane == 2 ? took[2] : took[3]));
+                if (lane < kPPT) entry_mask[(int64_t)e * kPPT + lane] = mine;
+                if (lane == 0) entry_pos[e] = pos1 - 1;
+                n_entries++;
             }
             if ((live[0] | live[1] | live[2] | live[3]) == 0) break;   // every pixel has terminated
         }
@@ -224,6 +247,7 @@ __global__ __launch_bounds__(kLanes) void k_render_fwd(const ViewDev* __restrict
         final_T[t.vbase + p] = T[j];
         n_contrib[t.vbase + p] = n[j];
     }
+    if (lane == 0) tile_entries[t.tile] = n_entries;
     if (STATS && threadIdx.x == 0) {
         atomicAdd(&counters[0], (unsigned long long)n_eval);
         atomicAdd(&counters[1], (unsigned long long)n_comp);
@@ -247,14 +271,15 @@ __device__ __forceinline__ float cross_rows(float x) {
 }
 
 // Totals of nine per-lane values over the 64 lanes of the wave, delivered as
-// value i in lane i (i < 9).  Transpose butterfly: each exchange step sends
-// one half of a register pair to the partner lane and keeps the other, so
-// 8 values shrink to 2 registers after the two quad exchanges (xor 1, xor 2);
-// rotations by 4 and 8 inside a row then sum the lanes sharing the same two
-// low bits, and the row/half swaps add the four rows.  The ninth value is
-// reduced on its own.  DPP and permlane moves only; no LDS traffic.
+// value i in lane i (i < 9).  Transpose butterfly on the first eight: each
+// exchange step sends one register of a pair to the partner lane and keeps
+// the other, so after the quad exchanges (xor 1, xor 2) and a rotation by 4
+// inside the row, one register holds value (lane & 7) summed over 8 lanes; a
+// rotation by 8 completes the row, and the row / half-wave swaps add the four
+// rows.  The ninth value is reduced on its own.  DPP and permlane moves only;
+// no LDS traffic.
 __device__ __forceinline__ float wave_totals9(const float* v, int lane) {
-    const bool o1 = lane & 1, o2 = lane & 2;
+    const bool o1 = lane & 1, o2 = lane & 2, o4 = lane & 4;
     float r[4];
 #pragma unroll
     for (int p = 0; p < 4; p++) {
@@ -269,42 +294,50 @@ __device__ __forceinline__ float wave_totals9(const float* v, int lane) {
         const float send = o2 ? r[2 * p] : r[2 * p + 1];
         t[p] = keep + dpp<0x4E>(send);                  // quad_perm [2,3,0,1]
     }
+    float u;
+    {
+        const float keep = o4 ? t[1] : t[0];
+        const float send = o4 ? t[0] : t[1];
+        u = keep + dpp<0x124>(send);                    // row_ror:4 (lane i reads lane i+4 of its row)
+    }
+    u += dpp<0x128>(u);                                 // row_ror:8
+    u = cross_rows(u);
     float x8 = v[8];
     x8 += dpp<0xB1>(x8);
     x8 += dpp<0x4E>(x8);
-#pragma unroll
-    for (int p = 0; p < 2; p++) {
-        t[p] += dpp<0x124>(t[p]);                       // row_ror:4
-        t[p] += dpp<0x128>(t[p]);                       // row_ror:8
-        t[p] = cross_rows(t[p]);
-    }
     x8 += dpp<0x124>(x8);
     x8 += dpp<0x128>(x8);
     x8 = cross_rows(x8);
-    return lane < 4 ? t[0] : (lane < 8 ? t[1] : x8);
+    return lane < 8 ? u : x8;
 }
 
 template <int TW, int TH, int BATCH>
 __global__ __launch_bounds__(kLanes) void k_render_bwd(const ViewDev* __restrict__ views, int nv, int64_t n_tiles,
                                                        const pg_splat* __restrict__ splats,
+                                                       const pg_bin* __restrict__ bins,
                                                        const int32_t* __restrict__ values,
-                                                       const int2* __restrict__ ranges, float bg0, float bg1,
-                                                       float bg2, const float* __restrict__ final_T,
-                                                       const int32_t* __restrict__ n_contrib,
-                                                       const float* __restrict__ dL_dimage, int64_t n_gv,
-                                                       float* __restrict__ grad2d) {
+                                                       const int2* __restrict__ ranges,
+                                                       const int32_t* __restrict__ inst_first,
+                                                       const int32_t* __restrict__ tile_entries,
+                                                       const int32_t* __restrict__ entry_pos,
+                                                       const uint64_t* __restrict__ entry_mask, float bg0,
+                                                       float bg1, float bg2, const float* __restrict__ final_T,
+                                                       const float* __restrict__ dL_dimage,
+                                                       const int64_t* __restrict__ n_inst_dev, int64_t cap,
+                                                       float* __restrict__ inst_grad) {
     __shared__ float4 s_geo[BATCH];
     __shared__ float4 s_col[BATCH];
     __shared__ float s_blu[BATCH];
-    __shared__ int32_t s_gv[BATCH];
-    __shared__ uint32_t s_mask[BATCH];
+    __shared__ int32_t s_slot[BATCH];      // emission index of the (Gaussian, this tile) instance
+    __shared__ uint32_t s_unused[BATCH];
     TileGeo t;
     tile_geo<TW, TH>(views, nv, n_tiles, t);
     const int2 rg = ranges[t.tile];
+    const int32_t count = tile_entries[t.tile];
+    const int64_t n_inst = *n_inst_dev;
+    if (count == 0 || n_inst > cap) return;       // nothing composited here, or the sort overflowed
     const int64_t HW = (int64_t)t.W * t.H;
     float T[kPPT], G0[kPPT], G1[kPPT], G2[kPPT], B0[kPPT], B1[kPPT], B2[kPPT];
-    int32_t n[kPPT];
-    int32_t maxn = 0;
 #pragma unroll
     for (int j = 0; j < kPPT; j++) {
         T[j] = 1.0f;
@@ -312,7 +345,6 @@ __global__ __launch_bounds__(kLanes) void k_render_bwd(const ViewDev* __restrict
         B0[j] = bg0;
         B1[j] = bg1;
         B2[j] = bg2;
-        n[j] = 0;
         if (t.inside[j]) {
             const int64_t p = (int64_t)t.py[j] * t.W + t.px[j];
             const float* gi = dL_dimage + 3 * t.vbase + p;
@@ -320,29 +352,30 @@ __global__ __launch_bounds__(kLanes) void k_render_bwd(const ViewDev* __restrict
             G1[j] = gi[HW];
             G2[j] = gi[2 * HW];
             T[j] = final_T[t.vbase + p];
-            n[j] = n_contrib[t.vbase + p];
         }
-        maxn = max(maxn, n[j]);
     }
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) maxn = max(maxn, __shfl_xor(maxn, o, 64));
     const int lane = threadIdx.x;
-    for (int32_t bend = maxn; bend > 0; bend -= BATCH) {
+    // entries (composited Gaussians of this tile) back to front
+    for (int32_t bend = count; bend > 0; bend -= BATCH) {
         const int32_t bstart = max(0, bend - BATCH);
         const int32_t cnt = bend - bstart;
         __syncthreads();
         for (int32_t i = lane; i < cnt; i += kLanes) {
-            const int32_t gv = values[rg.x + bstart + i];
-            s_gv[i] = gv;
-            stage<TW, TH>(splats, gv, t.ox, t.oy, t.row0, s_geo, s_col, s_blu, s_mask, i);
+            const int32_t gv = values[rg.x + entry_pos[rg.x + bstart + i]];
+            const uint2 r = *reinterpret_cast<const uint2*>(bins + gv);     // tile rectangle of the record
+            const int32_t xlo = (int32_t)(r.x & 0xffff), ylo = (int32_t)(r.x >> 16);
+            const int32_t xhi = (int32_t)(r.y & 0xffff);
+            s_slot[i] = inst_first[gv] + (t.ty - ylo) * (xhi - xlo + 1) + (t.tx - xlo);
+            stage<TW, TH>(splats, gv, t.ox, t.oy, t.col0, t.row0, s_geo, s_col, s_blu, s_unused, i);
         }
         __syncthreads();
         for (int32_t k = cnt - 1; k >= 0; k--) {
             const float4 g = s_geo[k];
             const float4 cc = s_col[k];
             const float cb = s_blu[k];
-            const uint32_t mask = s_mask[k];
-            const int32_t pos = bstart + k;
+            // lanes of each block that composited this Gaussian (one scalar load of 32 bytes)
+            const ulonglong4 em4 = *reinterpret_cast<const ulonglong4*>(entry_mask + (int64_t)(rg.x + bstart + k) * kPPT);
+            const uint64_t em[kPPT] = {em4.x, em4.y, em4.z, em4.w};
             // Per-lane sums over the lane's pixels, later reduced over the wave:
             //   m[0..1] = sum dq' (dx, dy), m[2..4] = sum dq' (dx^2, dx dy, dy^2)
             //   with dq' = alpha dL/dalpha (so dL/dq = -dq'/2), m[5] = sum e dL/dalpha,
@@ -350,18 +383,14 @@ __global__ __launch_bounds__(kLanes) void k_render_bwd(const ViewDev* __restrict
             float m[9];
 #pragma unroll
             for (int i = 0; i < 9; i++) m[i] = 0.0f;
-            bool any_c = false;
 #pragma unroll
             for (int j = 0; j < kPPT; j++) {
-                if (!((mask >> j) & 1u)) continue;    // ellipse cannot reach this slot
+                const uint64_t cm = em[j];
+                if (cm == 0) continue;
+                const bool in = __builtin_amdgcn_inverse_ballot_w64(cm);
                 const float dx = t.fx[j] - g.x, dy = t.fy[j] - g.y;
                 const float q = quad(dx, dy, g.z, g.w, cc.x);
-                bool in = pos < n[j] && q <= kQMax;
-                if (!__any(in)) continue;             // wave-uniform skip
-                const Eval ev = evaluate(q, cc.y);
-                in = in && ev.alpha >= kAlphaMin;
-                if (!__any(in)) continue;
-                any_c = true;
+                const Eval ev = evaluate(q, cc.y);    // bit-identical to the forward's alpha
                 const float al = ev.alpha;
                 const float Tk = T[j] * __builtin_amdgcn_rcpf(1.0f - al);   // transmittance in front of k
                 T[j] = in ? Tk : T[j];
@@ -386,7 +415,6 @@ __global__ __launch_bounds__(kLanes) void k_render_bwd(const ViewDev* __restrict
                 m[3] = fmaf(px, dy, m[3]);
                 m[4] = fmaf(py, dy, m[4]);
             }
-            if (!any_c) continue;
             // per-lane partials of the 2D gradients: dm = [[a, b], [b, c]] (Sx, Sy);
             // d(a, b, c) = -(Sxx / 2, Sxy, Syy / 2) (linear, so applied before the lane sum)
             const float bb = 0.5f * g.w;
@@ -401,33 +429,38 @@ __global__ __launch_bounds__(kLanes) void k_render_bwd(const ViewDev* __restrict
             v[7] = m[7];
             v[8] = m[8];
             const float mine = wave_totals9(v, lane);
-            if (lane < 9) unsafeAtomicAdd(&grad2d[(int64_t)lane * n_gv + s_gv[k]], mine);
+            // the (Gaussian, tile) sums go to the instance's own slot: no atomics, and the
+            // projection adjoint adds a record's slots in a fixed order
+            const int64_t slot = s_slot[k];
+            if (lane < 9 && slot >= 0 && slot < n_inst) inst_grad[slot * 9 + lane] = mine;
         }
     }
 }
 
 template <int TW, int TH, int BATCH>
 void fwd_launch(const pg_views* v, const pg_splat* splats, const int32_t* values, const int32_t* ranges,
-                const float bg[3], float* image, float* final_T, int32_t* n_contrib, uint64_t* counters,
-                hipStream_t s) {
+                const float bg[3], float* image, float* final_T, int32_t* n_contrib, int32_t* tile_entries,
+                int32_t* entry_pos, uint64_t* entry_mask, uint64_t* counters, hipStream_t s) {
     const unsigned grid = (unsigned)v->n_tiles;
     if (counters)
         k_render_fwd<TW, TH, BATCH, true><<<grid, kLanes, 0, s>>>(
             v->d_views, v->n_views, v->n_tiles, splats, values, reinterpret_cast<const int2*>(ranges), bg[0], bg[1],
-            bg[2], image, final_T, n_contrib, reinterpret_cast<unsigned long long*>(counters));
+            bg[2], image, final_T, n_contrib, tile_entries, entry_pos, entry_mask,
+            reinterpret_cast<unsigned long long*>(counters));
     else
         k_render_fwd<TW, TH, BATCH, false><<<grid, kLanes, 0, s>>>(
             v->d_views, v->n_views, v->n_tiles, splats, values, reinterpret_cast<const int2*>(ranges), bg[0], bg[1],
-            bg[2], image, final_T, n_contrib, nullptr);
+            bg[2], image, final_T, n_contrib, tile_entries, entry_pos, entry_mask, nullptr);
 }
 
 template <int TW, int TH, int BATCH>
-void bwd_launch(const pg_views* v, const pg_splat* splats, const int32_t* values, const int32_t* ranges,
-                const float bg[3], const float* final_T, const int32_t* n_contrib, const float* dL_dimage,
-                float* grad2d, hipStream_t s) {
+void bwd_launch(const pg_views* v, const pg_splat* splats, const pg_bin* bins, const int32_t* values,
+                const int32_t* ranges, const int32_t* inst_first, const int32_t* tile_entries,
+                const int32_t* entry_pos, const uint64_t* entry_mask, const float bg[3], const float* final_T,
+                const float* dL_dimage, const int64_t* n_inst_dev, int64_t cap, float* inst_grad, hipStream_t s) {
     k_render_bwd<TW, TH, BATCH><<<(unsigned)v->n_tiles, kLanes, 0, s>>>(
-        v->d_views, v->n_views, v->n_tiles, splats, values, reinterpret_cast<const int2*>(ranges), bg[0], bg[1],
-        bg[2], final_T, n_contrib, dL_dimage, v->n_gv, grad2d);
+        v->d_views, v->n_views, v->n_tiles, splats, bins, values, reinterpret_cast<const int2*>(ranges), inst_first,
+        tile_entries, entry_pos, entry_mask, bg[0], bg[1], bg[2], final_T, dL_dimage, n_inst_dev, cap, inst_grad);
 }
 
 template <template <int, int, int> class F, typename... A>
@@ -457,18 +490,24 @@ struct BwdRun {
 
 hipError_t launch_render_fwd(const pg_views* v, const pg_splat* splats, const int32_t* values,
                              const int32_t* ranges, const float bg[3], float* image, float* final_T,
-                             int32_t* n_contrib, uint64_t* counters, hipStream_t s) {
+                             int32_t* n_contrib, int32_t* tile_entries, int32_t* entry_pos, uint64_t* entry_mask,
+                             uint64_t* counters, hipStream_t s) {
     if (v->n_tiles == 0) return hipSuccess;
-    dispatch<FwdRun>(v->tiling, v, splats, values, ranges, bg, image, final_T, n_contrib, counters, s);
+    dispatch<FwdRun>(v->tiling, v, splats, values, ranges, bg, image, final_T, n_contrib, tile_entries, entry_pos,
+                     entry_mask, counters, s);
     return hipGetLastError();
 }
 
-hipError_t launch_render_bwd(const pg_views* v, const pg_splat* splats, const int32_t* values,
-                             const int32_t* ranges, const float bg[3], const float* final_T,
-                             const int32_t* n_contrib, const float* dL_dimage, float* grad2d, hipStream_t s) {
-    hipError_t e = fill_u32(grad2d, 0u, 9 * v->n_gv, s);
+hipError_t launch_render_bwd(const pg_views* v, const pg_splat* splats, const pg_bin* bins, const int32_t* values,
+                             const int32_t* ranges, const int32_t* inst_first, const int32_t* tile_entries,
+                             const int32_t* entry_pos, const uint64_t* entry_mask, const float bg[3],
+                             const float* final_T, const float* dL_dimage, const int64_t* n_inst_dev, int64_t cap,
+                             float* inst_grad, hipStream_t s) {
+    // instances nobody composited keep zero sums
+    hipError_t e = fill_u32_dev(inst_grad, 0u, n_inst_dev, cap, 9, s);
     if (e != hipSuccess || v->n_tiles == 0) return e;
-    dispatch<BwdRun>(v->tiling, v, splats, values, ranges, bg, final_T, n_contrib, dL_dimage, grad2d, s);
+    dispatch<BwdRun>(v->tiling, v, splats, bins, values, ranges, inst_first, tile_entries, entry_pos, entry_mask, bg,
+                     final_T, dL_dimage, n_inst_dev, cap, inst_grad, s);
     return hipGetLastError();
 }
 

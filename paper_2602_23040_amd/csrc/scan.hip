@@ -20,6 +20,13 @@ __global__ void k_fill_u32(uint32_t* p, uint32_t value, int64_t n) {
     for (; i < n; i += stride) p[i] = value;
 }
 
+__global__ void k_fill_u32_dev(uint32_t* p, uint32_t value, const int64_t* n_dev, int64_t n_max, int64_t mul) {
+    const int64_t n = imin(*n_dev, n_max) * mul;
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (; i < n; i += stride) p[i] = value;
+}
+
 __device__ __forceinline__ int64_t scan_length(const int64_t* n_dev, int64_t n_mul, int64_t n_host) {
     return n_dev ? (*n_dev) * n_mul : n_host;
 }
@@ -125,6 +132,12 @@ hipError_t fill_u32(void* p, uint32_t value, int64_t n_words, hipStream_t s) {
     if (n_words <= 0) return hipSuccess;
     int64_t blocks = imin(ceil_div(n_words, 256), 4096);
     k_fill_u32<<<(unsigned)blocks, 256, 0, s>>>((uint32_t*)p, value, n_words);
+    return hipGetLastError();
+}
+
+// Fill of min(*n_dev, n_max) * mul words, the count read on the device.
+hipError_t fill_u32_dev(void* p, uint32_t value, const int64_t* n_dev, int64_t n_max, int64_t mul, hipStream_t s) {
+    k_fill_u32_dev<<<4096, 256, 0, s>>>((uint32_t*)p, value, n_dev, n_max, mul);
     return hipGetLastError();
 }
 

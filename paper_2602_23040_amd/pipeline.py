@@ -46,6 +46,8 @@ class _ViewSet:
         self.bins = torch.empty(max(n_gv, 1) * abi.BIN_BYTES // 4, dtype=torch.int32, device=device)
         self.grad2d = torch.empty(max(9 * n_gv, 1), dtype=torch.float32, device=device)
         self.ranges = torch.empty(2 * max(self.info.n_tiles, 1), dtype=torch.int32, device=device)
+        self.tile_entries = torch.empty(max(self.info.n_tiles, 1), dtype=torch.int32, device=device)
+        self.inst_first = torch.empty(max(n_gv, 1), dtype=torch.int32, device=device)
         self.n_inst = torch.zeros(1, dtype=torch.int64, device=device)
         self.overflow = torch.zeros(1, dtype=torch.int32, device=device)
         self.device = device
@@ -56,6 +58,9 @@ class _ViewSet:
         self.cap = cap
         self.keys = torch.empty(cap, dtype=torch.int32, device=self.device)
         self.values = torch.empty(cap, dtype=torch.int32, device=self.device)
+        self.entry_pos = torch.empty(cap, dtype=torch.int32, device=self.device)
+        self.entry_mask = torch.empty(4 * cap, dtype=torch.int64, device=self.device)
+        self.inst_grad = torch.empty(9 * cap, dtype=torch.float32, device=self.device)
         self.ws_bytes = abi.pg_sort_workspace_size(self.handle, cap)
         self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.device)
 
@@ -167,15 +172,17 @@ class Renderer:
 
     def _project_sort_render(self, s: _ViewSet, pix_off: int, counters):
         abi.pg_project(s.handle, self.params, s.splats, s.bins, self.visible)
-        abi.pg_bin_sort(s.handle, s.bins, s.cap, s.keys, s.values, s.ranges, s.n_inst, s.overflow, s.ws, s.ws_bytes)
+        abi.pg_bin_sort(s.handle, s.bins, s.cap, s.keys, s.values, s.ranges, s.inst_first, s.n_inst, s.overflow, s.ws,
+                        s.ws_bytes)
         if not self.batched:
             # plain path: one instance-count synchronisation per view
             if int(s.overflow.item()):
                 s.set_capacity(int(math.ceil(int(s.n_inst.item()) * 1.25)))
-                abi.pg_bin_sort(s.handle, s.bins, s.cap, s.keys, s.values, s.ranges, s.n_inst, s.overflow, s.ws,
-                                s.ws_bytes)
+                abi.pg_bin_sort(s.handle, s.bins, s.cap, s.keys, s.values, s.ranges, s.inst_first, s.n_inst,
+                                s.overflow, s.ws, s.ws_bytes)
         abi.pg_render_fwd(s.handle, s.splats, s.values, s.ranges, self.bg, self._off(self.image, 3 * pix_off),
-                          self._off(self.final_T, pix_off), self._off(self.n_contrib, pix_off), counters)
+                          self._off(self.final_T, pix_off), self._off(self.n_contrib, pix_off), s.tile_entries,
+                          s.entry_pos, s.entry_mask, counters)
 
     def forward(self, atlas: torch.Tensor, counters: bool = False) -> torch.Tensor:
         """Render every view; returns the flat image buffer (valid until the next call)."""
@@ -199,16 +206,17 @@ class Renderer:
         assert g.is_contiguous() and g.numel() == 3 * self.n_pixels
         if self.batched:
             s = self.sets[0]
-            abi.pg_render_bwd(s.handle, self.params, s.splats, s.values, s.ranges, self.bg, self.final_T,
-                              self.n_contrib, g, self.gauss_texel, self.dynamic, self.H, self.W, s.grad2d,
-                              self.dL_datlas, 0)
+            abi.pg_render_bwd(s.handle, self.params, s.splats, s.bins, s.values, s.ranges, s.inst_first, s.n_inst,
+                              s.cap, s.tile_entries, s.entry_pos, s.entry_mask, self.bg, self.final_T, g, self.gauss_texel,
+                              self.dynamic, self.H, self.W, s.inst_grad, s.grad2d, self.dL_datlas, 0)
         else:
             self.dL_datlas.zero_()
             for k, s in enumerate(self.sets):
                 po = self.pix_base[k]
-                abi.pg_render_bwd(s.handle, self.params, s.splats, s.values, s.ranges, self.bg,
-                                  self._off(self.final_T, po), self._off(self.n_contrib, po), self._off(g, 3 * po),
-                                  self.gauss_texel, self.dynamic, self.H, self.W, s.grad2d, self.dL_datlas, 1)
+                abi.pg_render_bwd(s.handle, self.params, s.splats, s.bins, s.values, s.ranges, s.inst_first,
+                                  s.n_inst, s.cap, s.tile_entries, s.entry_pos, s.entry_mask, self.bg,
+                                  self._off(self.final_T, po), self._off(g, 3 * po), self.gauss_texel, self.dynamic,
+                                  self.H, self.W, s.inst_grad, s.grad2d, self.dL_datlas, 1)
         return self.dL_datlas
 
     def adam_step(self, atlas: torch.Tensor, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):

@@ -261,3 +261,20 @@ def test_capacity_overflow_is_reported_and_recovered():
     for v in fw.views:
         assert np.abs(img[v][0] - fw.image[v]).max() < 1e-3
     r.close()
+
+
+def test_gradients_bitwise_deterministic():
+    """No floating-point atomics: two adjoint runs give identical bits."""
+    sc, fw = case("ragged")
+    r = renderer(sc)
+    atlas = atlas_tensor(sc)
+    run_forward(r, atlas)
+    g = torch.from_numpy(np.random.default_rng(3).standard_normal(3 * r.n_pixels).astype(np.float32)).to("cuda:0")
+    outs = []
+    for _ in range(3):
+        r.backward(g)
+        torch.cuda.synchronize()
+        outs.append((r.dL_datlas.clone(), r.sets[0].grad2d.clone()))
+    for a, b in outs[1:]:
+        assert torch.equal(a, outs[0][0]) and torch.equal(b, outs[0][1])
+    r.close()
