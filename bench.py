@@ -40,6 +40,12 @@ PEAK_FP32_TFLOPS = 157.3
 # three colour FMAs (6) = 12.
 FLOP_EVAL = 9
 FLOP_COMP = 12
+# FP32 operations per composited pair in the compositing adjoint: dx, dy (2),
+# q (9), alpha (-q/2, exp, o e, clamp: 4), 1 - alpha, its reciprocal, T_k (3),
+# T alpha (1), colour moments (3 FMA: 6), c - B (3), dL/dalpha (5 + 1),
+# B update (3 FMA: 6), opacity moment (FMA: 2), alpha dL/dalpha (1),
+# dq' (dx, dy) (2), first moments (2), second moments (3 FMA: 6) = 53.
+FLOP_BWD = 53
 # Bytes per radix pass and instance: upsweep reads the key (8), downsweep reads
 # key + value (12) and writes them (12).
 SORT_BYTES_PER_PASS = 32
@@ -168,6 +174,7 @@ def main():
     sort_passes = rb.sets[0].info.sort_passes
     work = {
         "render_fwd": ("alu", (FLOP_EVAL * n_eval + FLOP_COMP * n_comp) / 1e12, "TFLOP/s", PEAK_FP32_TFLOPS),
+        "render_bwd": ("alu", FLOP_BWD * n_comp / 1e12, "TFLOP/s", PEAK_FP32_TFLOPS),
         "bin_sort": ("hbm", (SORT_BYTES_PER_PASS * sort_passes * n_inst + 28 * n_inst) / 1e9, "GB/s", PEAK_HBM_GBS),
         "project": ("hbm", (4 * sc.C * N + 64 * N * V) / 1e9, "GB/s", PEAK_HBM_GBS),
     }
@@ -230,10 +237,14 @@ def stage_times(r, atlas, target, reps=5):
         "bin_sort": lambda: abi.pg_bin_sort(s.handle, s.bins, s.cap, s.keys, s.values, s.ranges, s.inst_first,
                                             s.n_inst, s.overflow, s.ws, s.ws_bytes, stream),
         "render_fwd": lambda: abi.pg_render_fwd(s.handle, s.splats, s.values, s.ranges, r.bg, r.image, r.final_T,
-                                                r.n_contrib, s.tile_entries, s.entry_pos, s.entry_mask, None,
-                                                stream),
+                                                r.n_contrib, s.tile_entries, s.entries, None, stream),
         "loss_l1": lambda: r.loss_l1(target),
-        "render_bwd": lambda: r.backward(),
+        "render_bwd": lambda: abi.pg_render_bwd(s.handle, s.splats, s.bins, s.values, s.ranges, s.inst_first,
+                                                s.n_inst, s.cap, s.tile_entries, s.entries, r.n_contrib, r.bg,
+                                                r.final_T, r.dL_dimage, s.inst_grad, stream),
+        "project_bwd": lambda: abi.pg_project_bwd(s.handle, r.params, s.bins, s.inst_first, s.n_inst,
+                                                  s.cap, s.inst_grad, r.gauss_texel, r.dynamic, r.H, r.W, s.grad2d,
+                                                  r.dL_datlas, 0, stream),
     }
     out = {}
     for name, fn in calls.items():

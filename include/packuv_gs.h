@@ -124,8 +124,9 @@ const char* pg_last_error(void);
 /* Builds the device-resident view table for V cameras over `frames` atlases
  * of `n_gauss` Gaussians each (SH degree 0..3).  cams: host [V].  Fails with
  * PG_ERR_INVALID_ARG on bad cameras (fx, fy <= 0, size < 1, frame out of
- * range), unsupported tiling, or when V * n_gauss or the tile count exceed
- * 2^31 - 1.  Allocates device memory (the only allocating call). */
+ * range), unsupported tiling, when n_gauss exceeds 2^28, or when V * n_gauss
+ * or the tile count exceed 2^31 - 1.  Allocates device memory (the only
+ * allocating call). */
 pg_status pg_views_create(const pg_camera* cams, int32_t n_views, int32_t frames, int64_t n_gauss,
                           int32_t sh_degree, pg_tiling tiling, pg_views** out);
 pg_status pg_views_destroy(pg_views* views);
@@ -171,17 +172,18 @@ pg_status pg_project(const pg_views* views, const float* params, pg_splat* splat
  * depth sort, viewer section).  Lists every surviving (view, Gaussian) once
  * per tile of its rectangle and orders each tile's list front to back by
  * fp32(z_c), equal depths by ascending Gaussian id.  Implementation: the
- * surviving records are stably radix-sorted by (view, depth); instances are
- * emitted in that order and stably radix-sorted by global tile id.
+ * surviving records, taken in (view, id) order, are stably radix-sorted by
+ * depth; instances are emitted in that order and stably radix-sorted by
+ * global tile id (a tile belongs to one view, so its list ends up ordered by
+ * (depth, id)).
  *   keys           device uint32 [inst_capacity] out: global tile of each
  *                  sorted instance (ascending)
  *   values         device int32 [inst_capacity] out: gv of each sorted instance
  *   tile_ranges    device int32 [n_tiles][2] out: [start, end) per tile
- *   inst_first     device int32 [n_gv] out: for each (view, Gaussian) with
- *                  n_tiles > 0, the index of its first instance in emission
- *                  order (the records sorted by depth, each followed by the
- *                  tiles of its rectangle in row-major order); the adjoint
- *                  keeps one gradient slot per instance in that order
+ *   inst_first     device int32 [n_gv] out: the number of instances of all
+ *                  records before gv in (view, id) order.  The adjoint keeps
+ *                  one gradient slot per instance, record by record in that
+ *                  order, the record's tiles in rectangle row-major order.
  *   n_inst_dev     device int64 [1] out: number of instances
  *   overflow_dev   device int32 [1] out: 1 if n_inst > inst_capacity, else 0
  *   ws             device workspace of pg_sort_workspace_size bytes */
@@ -200,47 +202,57 @@ pg_status pg_bin_sort(const pg_views* views, const pg_bin* bins, int64_t inst_ca
  *   n_contrib    device int32 [n_pixels] out: 1-based list position of the
  *                last composited Gaussian, 0 if none
  *   tile_entries device int32 [n_tiles] out: number of entries of each tile
- *   entry_pos    device int32 [inst_capacity] out: for tile t, entries
- *                [start_t, start_t + tile_entries[t]) hold the 0-based list
- *                positions (ascending) of the Gaussians that composited at
- *                least one pixel of the tile
- *   entry_mask   device uint64 [inst_capacity][4] out: per entry, the pixels
- *                of each 8x8 block of the tile that composited it (bit l =
- *                pixel (l % 8, l / 8) of the block; blocks in row-major order)
+ *   entries      device uint32 [inst_capacity] out: for tile t, words
+ *                [start_t, start_t + tile_entries[t]) describe, in ascending
+ *                list order, the Gaussians that composited at least one
+ *                pixel of the tile: (0-based list position << 4) | bit b set
+ *                when a pixel of the tile's 8x8 block b (row-major) took it.
+ *                A tile's list never exceeds n_gauss <= 2^28, so the
+ *                position fits.
  *   counters     device uint64 [2] or NULL: += {pairs evaluated, pairs composited} */
 pg_status pg_render_fwd(const pg_views* views, const pg_splat* splats, const int32_t* values,
                         const int32_t* tile_ranges, const float* bg, float* image, float* final_T,
-                        int32_t* n_contrib, int32_t* tile_entries, int32_t* entry_pos, uint64_t* entry_mask,
-                        uint64_t* counters, void* stream);
+                        int32_t* n_contrib, int32_t* tile_entries, uint32_t* entries, uint64_t* counters,
+                        void* stream);
 
-/* a5 -- Adjoint of a2-a4 back to the texels, with gradient freezing
- * grad <- D_i grad (Sec. 4.2 "Gradient Freezing").  Walks each tile's
- * entries back to front with the forward's decisions, recomputing
- * per-pixel transmittance from final_T instead of storing it.  Each
- * (Gaussian, tile) sum lands in its own instance slot (no atomics); the
- * projection adjoint adds a record's slots in a fixed order, so the result
- * is bitwise deterministic.
- *   bins, inst_first, n_inst_dev          from pg_project / pg_bin_sort; after an
- *                overflowed sort (n_inst > inst_capacity) no slot is touched and
- *                the texel gradient is zero
- *   tile_entries, entry_pos, entry_mask   from pg_render_fwd
+/* a5, first half -- Adjoint of the compositing (a4) per screen tile.  Walks
+ * each tile's entries back to front with the forward's decisions,
+ * recomputing per-pixel transmittance from final_T instead of storing it,
+ * and writes each (Gaussian, tile) instance's summed 2D gradient
+ * dL/d(m_x, m_y, a, b, c, opacity, r, g, b) to that instance's own slot (no
+ * atomics).  Slots of instances that composited nothing are zero.
+ *   bins, inst_first, n_inst_dev   from pg_project / pg_bin_sort; after an
+ *                overflowed sort (n_inst > inst_capacity) no slot is written
+ *   tile_entries, entries, n_contrib, final_T   from pg_render_fwd
  *   dL_dimage    device float [3 n_pixels]
+ *   inst_capacity the capacity given to pg_bin_sort
+ *   inst_grad    device float [inst_capacity][9] out, slot inst_first[gv] + k
+ *                for tile k (row-major) of record gv's rectangle */
+pg_status pg_render_bwd(const pg_views* views, const pg_splat* splats, const pg_bin* bins, const int32_t* values,
+                        const int32_t* tile_ranges, const int32_t* inst_first, const int64_t* n_inst_dev,
+                        int64_t inst_capacity, const int32_t* tile_entries, const uint32_t* entries,
+                        const int32_t* n_contrib, const float* bg, const float* final_T, const float* dL_dimage,
+                        float* inst_grad, void* stream);
+
+/* a5, second half -- Adjoint of the projection (a2) and the fetch (a1)
+ * back to the texels, with gradient freezing grad <- D_i grad (Sec. 4.2
+ * "Gradient Freezing").  Adds each record's instance slots in rectangle
+ * order (a fixed order, so the result is bitwise deterministic), then
+ * applies the chain rule through the EWA projection, the activations and
+ * the SH colour of every view of the Gaussian's frame.
+ *   bins, inst_first, n_inst_dev   from pg_project / pg_bin_sort;
+ *                after an overflowed sort the texel gradient is zero
+ *   inst_grad    device float [inst_capacity][9] from pg_render_bwd
  *   gauss_texel  device int32 [n_gauss] (from pg_atlas_fetch)
  *   dynamic_mask device uint8 [H][W] or NULL (NULL: every Gaussian dynamic)
- *   inst_capacity the capacity given to pg_bin_sort
- *   inst_grad    device float [inst_capacity][9] workspace
  *   grad2d       device float [9][n_gv] out: per (view, Gaussian) dL/d(m_x,
- *                m_y, a, b, c, opacity, r, g, b)
+ *                m_y, a, b, c, opacity, r, g, b); 0 for culled records
  *   dL_datlas    device float [F][C][H][W] out; written (accumulate = 0: every
  *                texel, unoccupied = 0) or added to (accumulate = 1: occupied
  *                texels only). */
-pg_status pg_render_bwd(const pg_views* views, const float* params, const pg_splat* splats, const pg_bin* bins,
-                        const int32_t* values, const int32_t* tile_ranges, const int32_t* inst_first,
-                        const int64_t* n_inst_dev, int64_t inst_capacity, const int32_t* tile_entries,
-                        const int32_t* entry_pos,
-                        const uint64_t* entry_mask, const float* bg, const float* final_T, const float* dL_dimage,
-                        const int32_t* gauss_texel, const uint8_t* dynamic_mask, int32_t H, int32_t W,
-                        float* inst_grad, float* grad2d, float* dL_datlas, int32_t accumulate, void* stream);
+pg_status pg_project_bwd(const pg_views* views, const float* params, const pg_bin* bins, const int32_t* inst_first,
+                         const int64_t* n_inst_dev, int64_t inst_capacity, const float* inst_grad, const int32_t* gauss_texel, const uint8_t* dynamic_mask, int32_t H,
+                         int32_t W, float* grad2d, float* dL_datlas, int32_t accumulate, void* stream);
 
 /* a4' -- L1 photometric term of Sec. 4.2 "Objective" (lambda_ssim = 0):
  * L = mean |image - target|, dL/dimage = sign(image - target) / n (sign 0 = 0).

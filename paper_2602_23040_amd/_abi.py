@@ -61,9 +61,9 @@ SIGNATURES = {
     "pg_atlas_fetch": (_i32, [_p, _p, _i32, _i32, _i32, _i32, _i64, _p, _p, _p, _p, _p, _sz, _p]),
     "pg_project": (_i32, [_p, _p, _p, _p, _p, _p]),
     "pg_bin_sort": (_i32, [_p, _p, _i64, _p, _p, _p, _p, _p, _p, _p, _sz, _p]),
-    "pg_render_fwd": (_i32, [_p, _p, _p, _p, _p, _p, _p, _p, _p, _p, _p, _p, _p]),
-    "pg_render_bwd": (_i32, [_p, _p, _p, _p, _p, _p, _p, _p, _i64, _p, _p, _p, _p, _p, _p, _p, _p, _i32, _i32, _p,
-                             _p, _p, _i32, _p]),
+    "pg_render_fwd": (_i32, [_p, _p, _p, _p, _p, _p, _p, _p, _p, _p, _p, _p]),
+    "pg_render_bwd": (_i32, [_p, _p, _p, _p, _p, _p, _p, _i64, _p, _p, _p, _p, _p, _p, _p, _p]),
+    "pg_project_bwd": (_i32, [_p, _p, _p, _p, _p, _i64, _p, _p, _p, _i32, _i32, _p, _p, _i32, _p]),
     "pg_loss_l1": (_i32, [_p, _p, _i64, _p, _p, _p, _p]),
     "pg_adam_step": (_i32, [_p, _p, _p, _p, _p, _p, _i64, _i32, _i32, _i32, _i32, _f32, _f32, _f32, _f32, _i32, _p]),
 }
@@ -197,24 +197,29 @@ def pg_bin_sort(views, bins, inst_capacity, keys, values, tile_ranges, inst_firs
                              _stream(stream)), "pg_bin_sort")
 
 
-def pg_render_fwd(views, splats, values, tile_ranges, bg, image, final_T, n_contrib, tile_entries, entry_pos,
-                  entry_mask, counters=None, stream=None):
+def pg_render_fwd(views, splats, values, tile_ranges, bg, image, final_T, n_contrib, tile_entries, entries,
+                  counters=None, stream=None):
     bgv = (C.c_float * 3)(*[float(b) for b in bg])
     _check(lib().pg_render_fwd(views, _ptr(splats), _ptr(values), _ptr(tile_ranges), C.addressof(bgv), _ptr(image),
-                               _ptr(final_T), _ptr(n_contrib), _ptr(tile_entries), _ptr(entry_pos),
-                               _ptr(entry_mask), _ptr(counters), _stream(stream)), "pg_render_fwd")
+                               _ptr(final_T), _ptr(n_contrib), _ptr(tile_entries), _ptr(entries), _ptr(counters),
+                               _stream(stream)), "pg_render_fwd")
 
 
-def pg_render_bwd(views, params, splats, bins, values, tile_ranges, inst_first, n_inst_dev, inst_capacity,
-                  tile_entries, entry_pos, entry_mask, bg, final_T, dL_dimage, gauss_texel, dynamic_mask, H, W,
-                  inst_grad, grad2d, dL_datlas, accumulate, stream=None):
+def pg_render_bwd(views, splats, bins, values, tile_ranges, inst_first, n_inst_dev, inst_capacity, tile_entries,
+                  entries, n_contrib, bg, final_T, dL_dimage, inst_grad, stream=None):
     bgv = (C.c_float * 3)(*[float(b) for b in bg])
-    _check(lib().pg_render_bwd(views, _ptr(params), _ptr(splats), _ptr(bins), _ptr(values), _ptr(tile_ranges),
-                               _ptr(inst_first), _ptr(n_inst_dev), int(inst_capacity), _ptr(tile_entries),
-                               _ptr(entry_pos),
-                               _ptr(entry_mask), C.addressof(bgv), _ptr(final_T), _ptr(dL_dimage), _ptr(gauss_texel),
-                               _ptr(dynamic_mask), int(H), int(W), _ptr(inst_grad), _ptr(grad2d), _ptr(dL_datlas),
-                               int(accumulate), _stream(stream)), "pg_render_bwd")
+    _check(lib().pg_render_bwd(views, _ptr(splats), _ptr(bins), _ptr(values), _ptr(tile_ranges), _ptr(inst_first),
+                               _ptr(n_inst_dev), int(inst_capacity), _ptr(tile_entries), _ptr(entries),
+                               _ptr(n_contrib), C.addressof(bgv), _ptr(final_T), _ptr(dL_dimage), _ptr(inst_grad),
+                               _stream(stream)), "pg_render_bwd")
+
+
+def pg_project_bwd(views, params, bins, inst_first, n_inst_dev, inst_capacity, inst_grad, gauss_texel, dynamic_mask,
+                   H, W, grad2d, dL_datlas, accumulate, stream=None):
+    _check(lib().pg_project_bwd(views, _ptr(params), _ptr(bins), _ptr(inst_first), _ptr(n_inst_dev),
+                                int(inst_capacity), _ptr(inst_grad), _ptr(gauss_texel),
+                                _ptr(dynamic_mask), int(H), int(W), _ptr(grad2d), _ptr(dL_datlas), int(accumulate),
+                                _stream(stream)), "pg_project_bwd")
 
 
 def pg_loss_l1(image, target, n, dL_dimage, partial, loss_dev, stream=None):

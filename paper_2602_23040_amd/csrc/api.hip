@@ -2,6 +2,7 @@
 // table, and the entry points that enqueue the kernels of the other
 // translation units.  Every check that can be made on the host is made
 // before anything is enqueued.
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -81,6 +82,7 @@ pg_status pg_views_create(const pg_camera* cams, int32_t n_views, int32_t frames
     if (!tiling_ok(tiling))
         return invalid("tiling must be 16x16, 8x32 or 32x8 with lds_batch 64, 128 or 256 (reserved = 0)");
     if ((int64_t)n_views * n_gauss > INT32_MAX) return invalid("n_views * n_gauss exceeds 2^31 - 1");
+    if (n_gauss > ((int64_t)1 << 28)) return invalid("n_gauss exceeds 2^28");
     std::vector<ViewDev> hv(n_views);
     std::vector<int64_t> tb(n_views + 1), pb(n_views + 1);
     int64_t tiles = 0, pixels = 0;
@@ -106,6 +108,13 @@ pg_status pg_views_create(const pg_camera* cams, int32_t n_views, int32_t frames
         d.cx = c.cx;
         d.cy = c.cy;
         for (int k = 0; k < 3; k++) d.cw[k] = -((c.R[k] * c.t[0] + c.R[3 + k] * c.t[1]) + c.R[6 + k] * c.t[2]);
+        for (int k = 0; k < 9; k++) d.Rf[k] = (float)d.R[k];
+        for (int k = 0; k < 3; k++) {
+            d.tf[k] = (float)d.t[k];
+            d.cwf[k] = (float)d.cw[k];
+        }
+        d.fxf = (float)d.fx;
+        d.fyf = (float)d.fy;
         d.W = c.width;
         d.H = c.height;
         d.TX = (c.width + tiling.tile_w - 1) / tiling.tile_w;
@@ -130,8 +139,6 @@ pg_status pg_views_create(const pg_camera* cams, int32_t n_views, int32_t frames
     fv[frames] = (int32_t)order.size();
     int tile_bits = 1;
     while ((int64_t(1) << tile_bits) < tiles) tile_bits++;
-    int view_bits = 0;
-    while ((1 << view_bits) < n_views) view_bits++;
 
     pg_views* p = new pg_views();
     p->n_views = n_views;
@@ -144,7 +151,7 @@ pg_status pg_views_create(const pg_camera* cams, int32_t n_views, int32_t frames
     p->n_tiles = tiles;
     p->n_pixels = pixels;
     p->key_bits = tile_bits;
-    p->sort_passes = (32 + view_bits + 7) / 8 + (tile_bits + 9) / 10;   // record passes + instance passes
+    p->sort_passes = (32 + 9) / 10 + (tile_bits + 9) / 10;   // record (depth) passes + instance (tile) passes
     p->h_tile_base = new int64_t[n_views + 1];
     p->h_pix_base = new int64_t[n_views + 1];
     std::memcpy(p->h_tile_base, tb.data(), sizeof(int64_t) * (n_views + 1));
@@ -243,8 +250,8 @@ pg_status pg_project(const pg_views* v, const float* params, pg_splat* splats, p
 }
 
 pg_status pg_bin_sort(const pg_views* v, const pg_bin* bins, int64_t cap, uint32_t* keys, int32_t* values,
-                      int32_t* tile_ranges, int32_t* inst_first, int64_t* n_inst_dev, int32_t* overflow_dev, void* ws,
-                      size_t ws_bytes, void* stream) {
+                      int32_t* tile_ranges, int32_t* inst_first, int64_t* n_inst_dev, int32_t* overflow_dev,
+                      void* ws, size_t ws_bytes, void* stream) {
     g_error.clear();
     if (!v) return invalid("views is null");
     if (!tile_ranges || !n_inst_dev || !overflow_dev || !ws) return invalid("null pointer argument");
@@ -263,41 +270,52 @@ pg_status pg_bin_sort(const pg_views* v, const pg_bin* bins, int64_t cap, uint32
 
 pg_status pg_render_fwd(const pg_views* v, const pg_splat* splats, const int32_t* values, const int32_t* tile_ranges,
                         const float* bg, float* image, float* final_T, int32_t* n_contrib, int32_t* tile_entries,
-                        int32_t* entry_pos, uint64_t* entry_mask, uint64_t* counters, void* stream) {
+                        uint32_t* entries, uint64_t* counters, void* stream) {
     g_error.clear();
     if (!v || !bg) return invalid("null argument");
     if (!image || !final_T || !n_contrib || !tile_ranges || !tile_entries) return invalid("null pointer argument");
-    if (v->n_gv > 0 && (!splats || !values || !entry_pos || !entry_mask)) return invalid("null pointer argument");
+    if (v->n_gv > 0 && (!splats || !values || !entries)) return invalid("null pointer argument");
     PG_CHECK_HIP(launch_render_fwd(v, splats, values, tile_ranges, bg, image, final_T, n_contrib, tile_entries,
-                                   entry_pos, entry_mask, counters, (hipStream_t)stream),
+                                   entries, counters, (hipStream_t)stream),
                  "pg_render_fwd");
     return PG_OK;
 }
 
-pg_status pg_render_bwd(const pg_views* v, const float* params, const pg_splat* splats, const pg_bin* bins,
-                        const int32_t* values, const int32_t* tile_ranges, const int32_t* inst_first,
-                        const int64_t* n_inst_dev, int64_t inst_capacity, const int32_t* tile_entries,
-                        const int32_t* entry_pos, const uint64_t* entry_mask, const float* bg, const float* final_T,
-                        const float* dL_dimage, const int32_t* gauss_texel, const uint8_t* dynamic_mask, int32_t H,
-                        int32_t W, float* inst_grad, float* grad2d, float* dL_datlas, int32_t accumulate,
-                        void* stream) {
+pg_status pg_render_bwd(const pg_views* v, const pg_splat* splats, const pg_bin* bins, const int32_t* values,
+                        const int32_t* tile_ranges, const int32_t* inst_first, const int64_t* n_inst_dev,
+                        int64_t inst_capacity, const int32_t* tile_entries, const uint32_t* entries,
+                        const int32_t* n_contrib, const float* bg, const float* final_T, const float* dL_dimage,
+                        float* inst_grad, void* stream) {
     g_error.clear();
     if (!v || !bg) return invalid("null argument");
-    if (!tile_ranges || !tile_entries || !final_T || !dL_dimage || !dL_datlas || !n_inst_dev)
+    if (!tile_ranges || !tile_entries || !n_contrib || !final_T || !dL_dimage || !n_inst_dev)
         return invalid("null pointer argument");
-    if (v->n_gv > 0 && (!params || !splats || !bins || !values || !inst_first || !entry_pos || !entry_mask ||
-                        !gauss_texel || !grad2d || !inst_grad))
+    if (v->n_gv > 0 && (!splats || !bins || !values || !inst_first || !entries || !inst_grad))
+        return invalid("null pointer argument");
+    if (inst_capacity < 0 || inst_capacity > INT32_MAX) return invalid("inst_capacity must be in [0, 2^31 - 1]");
+    PG_CHECK_HIP(launch_render_bwd(v, splats, bins, values, tile_ranges, inst_first, tile_entries, entries,
+                                   n_contrib, bg, final_T, dL_dimage, n_inst_dev, inst_capacity, inst_grad,
+                                   (hipStream_t)stream),
+                 "pg_render_bwd");
+    return PG_OK;
+}
+
+pg_status pg_project_bwd(const pg_views* v, const float* params, const pg_bin* bins, const int32_t* inst_first,
+                         const int64_t* n_inst_dev, int64_t inst_capacity, const float* inst_grad, const int32_t* gauss_texel, const uint8_t* dynamic_mask, int32_t H,
+                         int32_t W, float* grad2d, float* dL_datlas, int32_t accumulate, void* stream) {
+    g_error.clear();
+    if (!v) return invalid("null argument");
+    if (!dL_datlas || !n_inst_dev) return invalid("null pointer argument");
+    if (v->n_gv > 0 && (!params || !bins || !inst_first || !inst_grad || !gauss_texel || !grad2d))
         return invalid("null pointer argument");
     if (H < 1 || W < 1 || (int64_t)H * W < v->n_gauss) return invalid("H * W must hold n_gauss texels");
     if (accumulate != 0 && accumulate != 1) return invalid("accumulate must be 0 or 1");
     if (inst_capacity < 0 || inst_capacity > INT32_MAX) return invalid("inst_capacity must be in [0, 2^31 - 1]");
     hipStream_t s = (hipStream_t)stream;
-    PG_CHECK_HIP(launch_render_bwd(v, splats, bins, values, tile_ranges, inst_first, tile_entries, entry_pos,
-                                   entry_mask, bg, final_T, dL_dimage, n_inst_dev, inst_capacity, inst_grad, s),
-                 "pg_render_bwd (raster)");
-    PG_CHECK_HIP(launch_project_bwd(v, params, bins, inst_first, n_inst_dev, inst_capacity, inst_grad, grad2d,
-                                    gauss_texel, dynamic_mask, H, W, dL_datlas, accumulate, s),
-                 "pg_render_bwd (projection)");
+    PG_CHECK_HIP(launch_slot_sum(v, bins, inst_first, n_inst_dev, inst_capacity, inst_grad, grad2d, s),
+                 "pg_project_bwd (slot sums)");
+    PG_CHECK_HIP(launch_project_bwd(v, params, grad2d, gauss_texel, dynamic_mask, H, W, dL_datlas, accumulate, s),
+                 "pg_project_bwd");
     return PG_OK;
 }
 

@@ -8,21 +8,23 @@
 // The order is built in two stable radix sorts instead of one sort of
 // (tile, depth) keys over all instances:
 //   1. the surviving (view, Gaussian) records -- far fewer than instances --
-//      are compacted and sorted by (view, fp32 depth bits);
+//      are compacted in (view, id) order and stably sorted by their fp32
+//      depth bits alone (all views mixed);
 //   2. instances are emitted in that order (each record lists the tiles of
 //      its rectangle) and stably sorted by global tile id alone.
-// Because the second sort is stable and a tile belongs to one view, each
-// tile's list comes out ordered by (depth, id): the same order as sorting
-// (tile, depth, id) keys, with the wide sort running over records and only
-// the ~20 tile bits sorted over instances.
+// Because the second sort is stable and every tile belongs to one view, each
+// tile's list comes out ordered by (depth, id): equal depths keep the
+// compaction order, which inside one view is ascending id.  That is the order
+// of sorting (tile, depth, id) keys, with 32-bit keys in both sorts.
 //
 // Kernels (all HBM-bound):
-//   k_valid_count / k_compact   records with n_tiles > 0 -> (view << 32 | depth, gv)
-//   radix passes (64-bit keys)  LSD, digit width <= 10 bits
+//   k_valid_count / k_compact   records with n_tiles > 0 -> (depth bits, gv);
+//                               inst_first[gv] = instances of all records before
+//                               gv in (view, id) order: the record's gradient
+//                               slots, one per tile in rectangle order
+//   radix passes (32-bit keys)  LSD, digit width <= 10 bits
 //   k_sorted_count / k_emit     tiles per sorted record -> instance offsets ->
-//                               work-group-cooperative emission (coalesced writes);
-//                               inst_first[gv] = emission index of the record's
-//                               first tile (its tiles follow in rectangle order)
+//                               work-group-cooperative emission (coalesced writes)
 //   radix passes (32-bit keys)  tile ids
 //   k_ranges                    [start, end) of every tile
 // Radix passes: per-tile digit histograms (upsweep), a scan of the histograms,
@@ -38,8 +40,7 @@ namespace {
 
 constexpr int kBlk = 1024;           // records per compaction / emission work-group
 constexpr int kSortGrid = 2048;      // persistent grid of the radix kernels (grid-stride over tiles)
-constexpr int kMaxDigitBits64 = 8;   // record sort (64-bit keys): LDS stays under 64 KiB per group
-constexpr int kMaxDigitBits32 = 10;  // instance sort (32-bit tile ids)
+constexpr int kMaxDigitBits = 10;    // digit width cap of both sorts (32-bit keys)
 
 struct SortPlan {
     int d_bits, d_passes;            // depth sort: key bits, digit width, passes
@@ -49,13 +50,11 @@ struct SortPlan {
 
 SortPlan plan_for(const pg_views* v) {
     SortPlan p{};
-    int view_bits = 0;
-    while ((1 << view_bits) < v->n_views) view_bits++;
-    p.d_bits = 32 + view_bits;
-    p.d_passes = (p.d_bits + kMaxDigitBits64 - 1) / kMaxDigitBits64;
+    p.d_bits = 32;
+    p.d_passes = (p.d_bits + kMaxDigitBits - 1) / kMaxDigitBits;
     p.d_digit = (p.d_bits + p.d_passes - 1) / p.d_passes;
     p.t_bits = v->key_bits;          // ceil(log2(n_tiles)), >= 1
-    p.t_passes = (p.t_bits + kMaxDigitBits32 - 1) / kMaxDigitBits32;
+    p.t_passes = (p.t_bits + kMaxDigitBits - 1) / kMaxDigitBits;
     p.t_digit = (p.t_bits + p.t_passes - 1) / p.t_passes;
     return p;
 }
@@ -63,12 +62,14 @@ SortPlan plan_for(const pg_views* v) {
 struct SortWs {
     int64_t* blk_a;          // per-block sums (compaction / emission)
     int64_t* blk_a_off;
+    int64_t* blk_b;          // per-block tile sums in (view, id) order (slot offsets)
+    int64_t* blk_b_off;
     int64_t* scan_tmp;
     int64_t* misc;           // [0] valid records, [1] instances to sort (0 on overflow),
                              // [2] depth-sort counts length, [3] tile-sort counts length
-    uint64_t* rk0;           // record sort ping-pong
+    uint32_t* rk0;           // record sort ping-pong
+    uint32_t* rk1;
     int32_t* rv0;
-    uint64_t* rk1;
     int32_t* rv1;
     uint32_t* tk_alt;        // tile sort ping-pong partner of the caller's arrays
     int32_t* tv_alt;
@@ -95,11 +96,13 @@ SortWs carve(const pg_views* v, int64_t cap, void* ws, size_t* total) {
     };
     w.blk_a = (int64_t*)take(nb * 8);
     w.blk_a_off = (int64_t*)take(nb * 8);
+    w.blk_b = (int64_t*)take(nb * 8);
+    w.blk_b_off = (int64_t*)take(nb * 8);
     w.scan_tmp = (int64_t*)take(kScanTmpWords * 8);
     w.misc = (int64_t*)take(8 * 8);
-    w.rk0 = (uint64_t*)take(ngv * 8);
+    w.rk0 = (uint32_t*)take(ngv * 4);
+    w.rk1 = (uint32_t*)take(ngv * 4);
     w.rv0 = (int32_t*)take(ngv * 4);
-    w.rk1 = (uint64_t*)take(ngv * 8);
     w.rv1 = (int32_t*)take(ngv * 4);
     w.tk_alt = (uint32_t*)take(imax(cap, 1) * 4);
     w.tv_alt = (int32_t*)take(imax(cap, 1) * 4);
@@ -124,6 +127,20 @@ __device__ __forceinline__ int32_t block_incl_1024(int32_t v, int32_t* s_warp) {
     return v + before;
 }
 
+__device__ __forceinline__ int64_t block_incl_1024_i64(int64_t v, int64_t* s_warp) {
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int64_t u = __shfl_up(v, o, 64);
+        if (lane >= o) v += u;
+    }
+    if (lane == 63) s_warp[wid] = v;
+    __syncthreads();
+    int64_t before = 0;
+    for (int k = 0; k < wid; k++) before += s_warp[k];
+    return v + before;
+}
+
 __device__ __forceinline__ int64_t block_sum_1024(int64_t c, int64_t* s) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o, 64);
@@ -135,26 +152,39 @@ __device__ __forceinline__ int64_t block_sum_1024(int64_t c, int64_t* s) {
 }
 
 __global__ __launch_bounds__(kBlk) void k_valid_count(const pg_bin* __restrict__ bins, int64_t n_gv,
-                                                      int64_t* __restrict__ blk) {
+                                                      int64_t* __restrict__ blk_cnt, int64_t* __restrict__ blk_nt) {
     __shared__ int64_t s[kBlk / 64];
     const int64_t gv = (int64_t)blockIdx.x * kBlk + threadIdx.x;
-    const int64_t c = (gv < n_gv && bins[gv].n_tiles > 0) ? 1 : 0;
-    const int64_t t = block_sum_1024(c, s);
-    if (threadIdx.x == 0) blk[blockIdx.x] = t;
+    const int64_t nt = gv < n_gv ? (int64_t)bins[gv].n_tiles : 0;
+    const int64_t c = block_sum_1024(nt > 0 ? 1 : 0, s);
+    __syncthreads();
+    const int64_t t = block_sum_1024(nt, s);
+    if (threadIdx.x == 0) {
+        blk_cnt[blockIdx.x] = c;
+        blk_nt[blockIdx.x] = t;
+    }
 }
 
-__global__ __launch_bounds__(kBlk) void k_compact(const pg_bin* __restrict__ bins, int64_t n_gv, int64_t N,
-                                                  const int64_t* __restrict__ blk_off, uint64_t* __restrict__ rk,
-                                                  int32_t* __restrict__ rv) {
+// Compaction of the surviving records (key: depth bits, value: gv) and the
+// instance-slot offsets in (view, id) order: inst_first[gv] = number of
+// instances of all records before gv.
+__global__ __launch_bounds__(kBlk) void k_compact(const pg_bin* __restrict__ bins, int64_t n_gv,
+                                                  const int64_t* __restrict__ blk_off,
+                                                  const int64_t* __restrict__ blk_nt_off, uint32_t* __restrict__ rk,
+                                                  int32_t* __restrict__ rv, int32_t* __restrict__ inst_first) {
     __shared__ int32_t s_warp[kBlk / 64];
+    __shared__ int64_t s_warp64[kBlk / 64];
     const int64_t gv = (int64_t)blockIdx.x * kBlk + threadIdx.x;
     uint4 b = make_uint4(0u, 0u, 0u, 0u);
     if (gv < n_gv) b = reinterpret_cast<const uint4*>(bins)[gv];
     const int32_t valid = (gv < n_gv && b.w > 0) ? 1 : 0;
     const int32_t incl = block_incl_1024(valid, s_warp);
+    const int64_t nt = valid ? (int64_t)b.w : 0;
+    const int64_t nt_incl = block_incl_1024_i64(nt, s_warp64);
+    if (gv < n_gv) inst_first[gv] = (int32_t)(blk_nt_off[blockIdx.x] + nt_incl - nt);
     if (valid) {
         const int64_t pos = blk_off[blockIdx.x] + incl - 1;
-        rk[pos] = ((uint64_t)(gv / N) << 32) | (uint64_t)b.z;
+        rk[pos] = b.z;
         rv[pos] = (int32_t)gv;
     }
 }
@@ -182,14 +212,18 @@ __global__ void k_depth_counts_len(int64_t* misc, int d_digit) { misc[2] = ceil_
 
 // Emission in sorted-record order: the group's output range is written
 // contiguously; each lane finds its (record, tile) by binary search over the
-// group's prefix sums.
+// group's prefix sums.  Per record the group keeps, in LDS, the global tile
+// id of the rectangle's first tile, the rectangle width and the row stride of
+// the view's tile grid, so an instance costs one small division.
 __global__ __launch_bounds__(kBlk) void k_emit(const pg_bin* __restrict__ bins, const int32_t* __restrict__ rv,
                                                int64_t N, const ViewDev* __restrict__ views,
                                                const int64_t* __restrict__ blk_off, const int64_t* __restrict__ misc,
-                                               uint32_t* __restrict__ tkeys, int32_t* __restrict__ tvals,
-                                               int32_t* __restrict__ inst_first) {
+                                               uint32_t* __restrict__ tkeys, int32_t* __restrict__ tvals) {
     __shared__ int32_t s_incl[kBlk];
-    __shared__ uint2 s_rect[kBlk];
+    __shared__ uint32_t s_tile0[kBlk];     // global tile id of the rectangle's first (top-left) tile
+    __shared__ int32_t s_w[kBlk];          // rectangle width in tiles
+    __shared__ int32_t s_tx[kBlk];         // tiles per row of the view
+    __shared__ float s_rw[kBlk];           // 1 / width
     __shared__ int32_t s_gv[kBlk];
     __shared__ int32_t s_warp[kBlk / 64];
     if (misc[1] == 0) return;   // overflow (or nothing to emit): uniform exit
@@ -200,14 +234,20 @@ __global__ __launch_bounds__(kBlk) void k_emit(const pg_bin* __restrict__ bins, 
         const int32_t gv = rv[p];
         const uint4 b = reinterpret_cast<const uint4*>(bins)[gv];
         nt = (int32_t)b.w;
-        s_rect[t] = make_uint2(b.x, b.y);
+        const int32_t xlo = (int32_t)(b.x & 0xffff), ylo = (int32_t)(b.x >> 16);
+        const int32_t xhi = (int32_t)(b.y & 0xffff);
+        const ViewDev& V = views[gv / N];
+        const int32_t w = xhi - xlo + 1;
+        s_tile0[t] = (uint32_t)(V.tile_base + (int64_t)ylo * V.TX + xlo);
+        s_w[t] = w;
+        s_tx[t] = V.TX;
+        s_rw[t] = 1.0f / (float)w;
         s_gv[t] = gv;
     }
     s_incl[t] = block_incl_1024(nt, s_warp);
     __syncthreads();
     const int32_t total = s_incl[kBlk - 1];
     const int64_t base = blk_off[blockIdx.x];
-    if (nt > 0) inst_first[s_gv[t]] = (int32_t)(base + s_incl[t] - nt);   // emission index of the record's first tile
     for (int32_t q = t; q < total; q += kBlk) {
         int lo = 0, hi = kBlk - 1;     // first j with s_incl[j] > q
         while (lo < hi) {
@@ -215,15 +255,14 @@ __global__ __launch_bounds__(kBlk) void k_emit(const pg_bin* __restrict__ bins, 
             if (s_incl[mid] > q) hi = mid; else lo = mid + 1;
         }
         const int32_t k = q - (lo ? s_incl[lo - 1] : 0);
-        const uint2 r = s_rect[lo];
-        const int32_t xlo = (int32_t)(r.x & 0xffff), ylo = (int32_t)(r.x >> 16);
-        const int32_t xhi = (int32_t)(r.y & 0xffff);
-        const int32_t w = xhi - xlo + 1;
-        const int32_t tx = xlo + k % w, ty = ylo + k / w;
-        const int32_t gv = s_gv[lo];
-        const ViewDev& V = views[gv / N];
-        tkeys[base + q] = (uint32_t)(V.tile_base + (int64_t)ty * V.TX + tx);
-        tvals[base + q] = gv;
+        const int32_t w = s_w[lo];
+        // row = k / w from a float estimate (k < 2^24), corrected to the exact quotient
+        int32_t row = (int32_t)((float)k * s_rw[lo]);
+        int32_t col = k - row * w;
+        if (col < 0) { row--; col += w; }
+        else if (col >= w) { row++; col -= w; }
+        tkeys[base + q] = s_tile0[lo] + (uint32_t)(row * s_tx[lo] + col);
+        tvals[base + q] = s_gv[lo];
     }
 }
 
@@ -437,20 +476,22 @@ hipError_t launch_bin_sort(const pg_views* v, const pg_bin* bins, int64_t cap, u
         k_post_count<<<1, 1, 0, s>>>(n_inst_dev, cap, overflow_dev, w.misc, pl.t_digit);
         return hipGetLastError();
     }
-    // 1. compact surviving records, keyed (view << 32 | depth)
-    k_valid_count<<<(unsigned)nb, kBlk, 0, s>>>(bins, v->n_gv, w.blk_a);
+    // 1. compact surviving records in (view, id) order, keyed by depth; slot offsets in the same order
+    int32_t *rva = w.rv0, *rvb = w.rv1;
+    k_valid_count<<<(unsigned)nb, kBlk, 0, s>>>(bins, v->n_gv, w.blk_a, w.blk_b);
     e = scan_i64(w.blk_a, w.blk_a_off, nullptr, 0, nb, w.misc + 0, w.scan_tmp, s);
     if (e != hipSuccess) return e;
-    k_compact<<<(unsigned)nb, kBlk, 0, s>>>(bins, v->n_gv, v->n_gauss, w.blk_a_off, w.rk0, w.rv0);
+    e = scan_i64(w.blk_b, w.blk_b_off, nullptr, 0, nb, w.misc + 4, w.scan_tmp, s);
+    if (e != hipSuccess) return e;
+    k_compact<<<(unsigned)nb, kBlk, 0, s>>>(bins, v->n_gv, w.blk_a_off, w.blk_b_off, w.rk0, rva, inst_first);
     k_depth_counts_len<<<1, 1, 0, s>>>(w.misc, pl.d_digit);
-    // 2. stable LSD sort of the records by (view, depth)
+    // 2. stable LSD sort of the records by depth
     const unsigned grid_r = (unsigned)imax(1, imin(kSortGrid, ceil_div(v->n_gv, kSortTile)));
-    uint64_t *rka = w.rk0, *rkb = w.rk1;
-    int32_t *rva = w.rv0, *rvb = w.rv1;
+    uint32_t *rka = w.rk0, *rkb = w.rk1;
     for (int p = 0; p < pl.d_passes; p++) {
-        e = radix_pass<uint64_t>(pl.d_digit, rka, rva, rkb, rvb, w.misc + 0, w.misc + 2, p * pl.d_digit, w, grid_r, s);
+        e = radix_pass<uint32_t>(pl.d_digit, rka, rva, rkb, rvb, w.misc + 0, w.misc + 2, p * pl.d_digit, w, grid_r, s);
         if (e != hipSuccess) return e;
-        uint64_t* tk = rka; rka = rkb; rkb = tk;
+        uint32_t* tk = rka; rka = rkb; rkb = tk;
         int32_t* tv = rva; rva = rvb; rvb = tv;
     }
     // 3. instance offsets in sorted-record order; overflow check
@@ -463,8 +504,7 @@ hipError_t launch_bin_sort(const pg_views* v, const pg_bin* bins, int64_t cap, u
     int32_t* tva = (pl.t_passes % 2 == 0) ? values : w.tv_alt;
     uint32_t* tb = (pl.t_passes % 2 == 0) ? w.tk_alt : keys;
     int32_t* tvb = (pl.t_passes % 2 == 0) ? w.tv_alt : values;
-    k_emit<<<(unsigned)nb, kBlk, 0, s>>>(bins, rva, v->n_gauss, v->d_views, w.blk_a_off, w.misc, ta, tva,
-                                         inst_first);
+    k_emit<<<(unsigned)nb, kBlk, 0, s>>>(bins, rva, v->n_gauss, v->d_views, w.blk_a_off, w.misc, ta, tva);
     // 5. stable LSD sort of the instances by tile id
     const unsigned grid_i = (unsigned)imax(1, imin(kSortGrid, ceil_div(cap, kSortTile)));
     for (int p = 0; p < pl.t_passes; p++) {

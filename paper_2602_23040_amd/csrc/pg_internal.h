@@ -22,6 +22,7 @@ struct ViewDev {
     double t[3];
     double fx, fy, cx, cy;
     double cw[3];          // camera centre in world coordinates, -R^T t
+    float Rf[9], tf[3], fxf, fyf, cwf[3];   // FP32 copies for the adjoint
     int32_t W, H, TX, TY;
     int32_t frame, pad;
     int64_t tile_base, pix_base;
@@ -76,9 +77,11 @@ hipError_t launch_fetch(const float* atlas, const uint8_t* occ, int32_t F, int32
 // project.hip
 hipError_t launch_project(const pg_views* v, const float* params, pg_splat* splats, pg_bin* bins,
                           uint8_t* visible, hipStream_t s);
-hipError_t launch_project_bwd(const pg_views* v, const float* params, const pg_bin* bins,
-                              const int32_t* inst_first, const int64_t* n_inst_dev, int64_t cap,
-                              const float* inst_grad, float* grad2d,
+// per-record sums of the instance slots -> grad2d
+hipError_t launch_slot_sum(const pg_views* v, const pg_bin* bins, const int32_t* inst_first,
+                           const int64_t* n_inst_dev, int64_t cap, const float* inst_grad, float* grad2d,
+                           hipStream_t s);
+hipError_t launch_project_bwd(const pg_views* v, const float* params, const float* grad2d,
                               const int32_t* gauss_texel, const uint8_t* dyn, int32_t H, int32_t W,
                               float* dL_datlas, int32_t accumulate, hipStream_t s);
 
@@ -91,11 +94,11 @@ hipError_t launch_bin_sort(const pg_views* v, const pg_bin* bins, int64_t cap, u
 // render.hip
 hipError_t launch_render_fwd(const pg_views* v, const pg_splat* splats, const int32_t* values,
                              const int32_t* ranges, const float bg[3], float* image, float* final_T,
-                             int32_t* n_contrib, int32_t* tile_entries, int32_t* entry_pos, uint64_t* entry_mask,
-                             uint64_t* counters, hipStream_t s);
+                             int32_t* n_contrib, int32_t* tile_entries, uint32_t* entries, uint64_t* counters,
+                             hipStream_t s);
 hipError_t launch_render_bwd(const pg_views* v, const pg_splat* splats, const pg_bin* bins, const int32_t* values,
                              const int32_t* ranges, const int32_t* inst_first, const int32_t* tile_entries,
-                             const int32_t* entry_pos, const uint64_t* entry_mask, const float bg[3],
+                             const uint32_t* entries, const int32_t* n_contrib, const float bg[3],
                              const float* final_T, const float* dL_dimage, const int64_t* n_inst_dev, int64_t cap,
                              float* inst_grad, hipStream_t s);
 hipError_t fill_u32_dev(void* p, uint32_t value, const int64_t* n_dev, int64_t n_max, int64_t mul, hipStream_t s);
@@ -108,6 +111,14 @@ hipError_t launch_adam(float* atlas, const float* grad, float* m, float* v, cons
                        float lr, float b1, float b2, float eps, int32_t step, hipStream_t s);
 
 // ---- device helpers
+
+// Cross-lane data-parallel-primitive move of a float: lanes of rows disabled
+// by ROW_MASK read 0 (control codes: quad_perm 0x00-0xFF, row_ror:n 0x120+n,
+// row_mirror 0x140, row_half_mirror 0x141, row_bcast:15 0x142, row_bcast:31 0x143).
+template <int CTRL, int ROW_MASK = 0xf>
+__device__ __forceinline__ float dpp_f32(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROW_MASK, 0xf, false));
+}
 
 __device__ __forceinline__ int find_view_by_tile(const ViewDev* views, int nv, int64_t tile) {
     int lo = 0, hi = nv - 1;

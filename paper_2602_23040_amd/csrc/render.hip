@@ -7,31 +7,39 @@
 // with alpha < 1/255 are skipped, and a pixel stops before the Gaussian that
 // would bring T below 1e-4.
 //
-// Launch shape: one 256-lane work-group (four wave64s) per (view, tile), one
-// pixel per lane.  The tile's list is staged through LDS in batches of
-// BATCH Gaussians; every lane of the group reads each staged Gaussian as an
-// LDS broadcast, so the per-instance HBM record (48 bytes) is reused by up to
-// 256 pixels and the loop is bound by FP32 VALU work, not HBM.  A group stops
-// loading batches once every lane has terminated (__syncthreads_count).
-// Work-groups are assigned to tiles so that consecutive tiles run on the same
-// XCD (the dispatcher deals groups round-robin over the 8 XCDs), which keeps
-// the records that neighbouring tiles share in one L2.
+// Launch shape: one wave64 work-group per (view, tile) of 256 pixels, four
+// pixels per lane.  The tile is four 8x8 blocks (2x2 for 16x16 tiles, 1x4 for
+// 8x32, 4x1 for 32x8); lane l holds pixel (l % 8, l / 8) of every block.  The
+// tile's list is staged through LDS in batches of BATCH Gaussians (one
+// gathered 48-byte record each) and every lane reads each staged Gaussian as
+// an LDS broadcast, so the loop is bound by FP32 VALU work, not HBM.  Blocks
+// that a Gaussian's conservative x/y extent misses, or whose pixels have all
+// terminated, are skipped wave-uniformly (ballots), and the tile stops once
+// every pixel has terminated.  Work-groups are assigned so that consecutive
+// tiles run on the same XCD (the dispatcher deals groups round-robin over the
+// 8 XCDs), which keeps the records neighbouring tiles share in one L2.
 //
 // Pixel offsets are formed in FP32 coordinates local to the 32x32 pixel block
 // holding the tile (every supported tile shape nests in such a block), from
 // the FP64 pixel-space mean: q keeps full FP32 precision at 1080p, and a
 // pixel sees bit-identical inputs whatever the tile shape.
 //
-// The forward records, per tile, the list positions of the Gaussians that
-// composited at least one pixel and, per 8x8 block, which lanes did.  The
-// adjoint walks only those entries, back to front, with the forward's
-// decisions, recovering the transmittance in front of Gaussian k as
-// T_k = T_{k+1} / (1 - alpha_k) from the stored final T (no per-step
-// storage).  Per-Gaussian sums over the tile's pixels are reduced across the
-// wave with DPP / permlane moves and written, without atomics, to the
-// (Gaussian, tile) instance's own slot; the projection adjoint then adds the
-// slots of each (view, Gaussian) in a fixed order, so gradients are bitwise
-// deterministic.
+// The forward records, per tile, one 32-bit word per Gaussian that composited
+// at least one pixel: its list position and the blocks where it did.  While
+// 64 Gaussians are composited, one scalar bit mask per block collects which
+// of them were taken; lane i then forms the word of Gaussian i and the words
+// are stored compacted and coalesced.  The adjoint walks only those entries,
+// back to front.  A pixel took
+// entry k exactly when its list position is below the pixel's n_contrib and
+// q <= 9 and alpha >= 1/255 (a pixel stops only after its last contribution),
+// and q and alpha are recomputed by the same code as the forward, so the
+// adjoint's decisions are the forward's.  The transmittance in front of
+// Gaussian k is recovered as T_k = T_{k+1} / (1 - alpha_k) from the stored
+// final T (no per-step storage).  Per-Gaussian sums over the tile's pixels
+// are reduced across the wave with DPP / permlane moves and written, without
+// atomics, to the (Gaussian, tile) instance's own slot; the projection
+// adjoint then adds the slots of each (view, Gaussian) in a fixed order, so
+// gradients are bitwise deterministic.
 #include "pg_internal.h"
 
 namespace pg {
@@ -162,8 +170,7 @@ __global__ __launch_bounds__(kLanes) void k_render_fwd(const ViewDev* __restrict
                                                        float bg2, float* __restrict__ image,
                                                        float* __restrict__ final_T, int32_t* __restrict__ n_contrib,
                                                        int32_t* __restrict__ tile_entries,
-                                                       int32_t* __restrict__ entry_pos,
-                                                       uint64_t* __restrict__ entry_mask,
+                                                       uint32_t* __restrict__ entries,
                                                        unsigned long long* __restrict__ counters) {
     __shared__ float4 s_geo[BATCH];
     __shared__ float4 s_col[BATCH];
@@ -192,47 +199,51 @@ __global__ __launch_bounds__(kLanes) void k_render_fwd(const ViewDev* __restrict
             stage<TW, TH>(splats, values[b0 + i], t.ox, t.oy, t.col0, t.row0, s_geo, s_col, s_blu, s_mask, i);
         __syncthreads();
         const int32_t cnt = min(BATCH, rg.y - b0);
-        for (int32_t k = 0; k < cnt; k++) {
-            const float4 g = s_geo[k];
-            const float4 cc = s_col[k];
-            const float cb = s_blu[k];
-            const uint32_t mask = s_mask[k];
-            const int32_t pos1 = b0 - rg.x + k + 1;
-            uint64_t took[kPPT];
+        // sub-batches of 64 Gaussians: bit (k - k0) of took[j] records that a pixel of block j took Gaussian k
+        for (int32_t k0 = 0; k0 < cnt && (live[0] | live[1] | live[2] | live[3]) != 0; k0 += kLanes) {
+            const int32_t k1 = min(cnt, k0 + kLanes);
+            uint64_t took[kPPT] = {0, 0, 0, 0};
+            for (int32_t k = k0; k < k1; k++) {
+                const float4 g = s_geo[k];
+                const float4 cc = s_col[k];
+                const float cb = s_blu[k];
+                const uint32_t mask = s_mask[k];
+                const int32_t pos1 = b0 - rg.x + k + 1;
+                const uint64_t kbit = 1ull << (k - k0);
 #pragma unroll
-            for (int j = 0; j < kPPT; j++) {
-                took[j] = 0;
-                if (STATS) n_eval += __popcll(live[j]);
-                if (!((mask >> j) & 1u) || live[j] == 0) continue;   // ellipse misses the slot / slot done
-                const float dx = t.fx[j] - g.x, dy = t.fy[j] - g.y;
-                const float q = quad(dx, dy, g.z, g.w, cc.x);
-                const uint64_t inm = __ballot(q <= kQMax) & live[j];
-                if (inm == 0) continue;
-                const Eval ev = evaluate(q, cc.y);
-                const uint64_t passm = __ballot(ev.alpha >= kAlphaMin) & inm;
-                const float Tn = T[j] * (1.0f - ev.alpha);
-                const uint64_t stopm = __ballot(Tn < kTMin) & passm;
-                const uint64_t takem = passm & ~stopm;
-                live[j] &= ~stopm;
-                took[j] = takem;
-                if (STATS) n_comp += __popcll(takem);
-                const bool take = __builtin_amdgcn_inverse_ballot_w64(takem);
-                const float w = take ? T[j] * ev.alpha : 0.0f;
-                C0[j] = fmaf(w, cc.z, C0[j]);
-                C1[j] = fmaf(w, cc.w, C1[j]);
-                C2[j] = fmaf(w, cb, C2[j]);
-                T[j] = take ? Tn : T[j];
-                n[j] = take ? pos1 : n[j];
+                for (int j = 0; j < kPPT; j++) {
+                    if (STATS) n_eval += __popcll(live[j]);
+                    if (!((mask >> j) & 1u) || live[j] == 0) continue;   // ellipse misses the block / block done
+                    const float dx = t.fx[j] - g.x, dy = t.fy[j] - g.y;
+                    const float q = quad(dx, dy, g.z, g.w, cc.x);
+                    const uint64_t inm = __ballot(q <= kQMax) & live[j];
+                    if (inm == 0) continue;
+                    const Eval ev = evaluate(q, cc.y);
+                    const uint64_t passm = __ballot(ev.alpha >= kAlphaMin) & inm;
+                    const float Tn = T[j] * (1.0f - ev.alpha);
+                    const uint64_t stopm = __ballot(Tn < kTMin) & passm;
+                    const uint64_t takem = passm & ~stopm;
+                    live[j] &= ~stopm;
+                    took[j] |= takem ? kbit : 0ull;
+                    if (STATS) n_comp += __popcll(takem);
+                    const bool take = __builtin_amdgcn_inverse_ballot_w64(takem);
+                    const float w = take ? T[j] * ev.alpha : 0.0f;
+                    C0[j] = fmaf(w, cc.z, C0[j]);
+                    C1[j] = fmaf(w, cc.w, C1[j]);
+                    C2[j] = fmaf(w, cb, C2[j]);
+                    T[j] = take ? Tn : T[j];
+                    n[j] = take ? pos1 : n[j];
+                }
+                if ((live[0] | live[1] | live[2] | live[3]) == 0) break;   // every pixel has terminated
             }
-            if ((took[0] | took[1] | took[2] | took[3]) != 0) {
-                // entry for the adjoint: list position and the lanes of each block that composited it
-                const int32_t e = rg.x + n_entries;
-                const uint64_t mine = lane == 0 ? took[0] : (lane == 1 ? took[1] : (lane == 2 ? took[2] : took[3]));
-                if (lane < kPPT) entry_mask[(int64_t)e * kPPT + lane] = mine;
-                if (lane == 0) entry_pos[e] = pos1 - 1;
-                n_entries++;
-            }
-            if ((live[0] | live[1] | live[2] | live[3]) == 0) break;   // every pixel has terminated
+            // entries of the sub-batch for the adjoint (lane i: Gaussian k0 + i), stored in list order
+            uint32_t bits = 0;
+#pragma unroll
+            for (int j = 0; j < kPPT; j++) bits |= (uint32_t)((took[j] >> lane) & 1ull) << j;
+            const uint64_t em = __ballot(bits != 0);
+            const uint32_t before = __builtin_amdgcn_mbcnt_hi((uint32_t)(em >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)em, 0u));
+            if (bits != 0) entries[rg.x + n_entries + (int32_t)before] = ((uint32_t)(b0 - rg.x + k0 + lane) << 4) | bits;
+            n_entries += __popcll(em);
         }
     }
     const int64_t HW = (int64_t)t.W * t.H;
@@ -254,10 +265,9 @@ __global__ __launch_bounds__(kLanes) void k_render_fwd(const ViewDev* __restrict
     }
 }
 
-// Cross-lane data-parallel-primitive move: lanes of disabled rows read 0.
 template <int CTRL, int ROW_MASK = 0xf>
 __device__ __forceinline__ float dpp(float v) {
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROW_MASK, 0xf, false));
+    return dpp_f32<CTRL, ROW_MASK>(v);
 }
 
 // Row/half-wave swaps of gfx950: lane i of every row (or half) meets lane i of
@@ -319,8 +329,8 @@ __global__ __launch_bounds__(kLanes) void k_render_bwd(const ViewDev* __restrict
                                                        const int2* __restrict__ ranges,
                                                        const int32_t* __restrict__ inst_first,
                                                        const int32_t* __restrict__ tile_entries,
-                                                       const int32_t* __restrict__ entry_pos,
-                                                       const uint64_t* __restrict__ entry_mask, float bg0,
+                                                       const uint32_t* __restrict__ entries,
+                                                       const int32_t* __restrict__ n_contrib, float bg0,
                                                        float bg1, float bg2, const float* __restrict__ final_T,
                                                        const float* __restrict__ dL_dimage,
                                                        const int64_t* __restrict__ n_inst_dev, int64_t cap,
@@ -329,6 +339,7 @@ __global__ __launch_bounds__(kLanes) void k_render_bwd(const ViewDev* __restrict
     __shared__ float4 s_col[BATCH];
     __shared__ float s_blu[BATCH];
     __shared__ int32_t s_slot[BATCH];      // emission index of the (Gaussian, this tile) instance
+    __shared__ uint32_t s_word[BATCH];     // entry word: list position << 4 | blocks that composited it
     __shared__ uint32_t s_unused[BATCH];
     TileGeo t;
     tile_geo<TW, TH>(views, nv, n_tiles, t);
@@ -338,9 +349,11 @@ __global__ __launch_bounds__(kLanes) void k_render_bwd(const ViewDev* __restrict
     if (count == 0 || n_inst > cap) return;       // nothing composited here, or the sort overflowed
     const int64_t HW = (int64_t)t.W * t.H;
     float T[kPPT], G0[kPPT], G1[kPPT], G2[kPPT], B0[kPPT], B1[kPPT], B2[kPPT];
+    int32_t nc[kPPT];      // list positions below nc[j] were reached by pixel j (0 outside the image)
 #pragma unroll
     for (int j = 0; j < kPPT; j++) {
         T[j] = 1.0f;
+        nc[j] = 0;
         G0[j] = G1[j] = G2[j] = 0.0f;
         B0[j] = bg0;
         B1[j] = bg1;
@@ -352,6 +365,7 @@ __global__ __launch_bounds__(kLanes) void k_render_bwd(const ViewDev* __restrict
             G1[j] = gi[HW];
             G2[j] = gi[2 * HW];
             T[j] = final_T[t.vbase + p];
+            nc[j] = n_contrib[t.vbase + p];
         }
     }
     const int lane = threadIdx.x;
@@ -361,7 +375,9 @@ __global__ __launch_bounds__(kLanes) void k_render_bwd(const ViewDev* __restrict
         const int32_t cnt = bend - bstart;
         __syncthreads();
         for (int32_t i = lane; i < cnt; i += kLanes) {
-            const int32_t gv = values[rg.x + entry_pos[rg.x + bstart + i]];
+            const uint32_t word = entries[rg.x + bstart + i];
+            s_word[i] = word;
+            const int32_t gv = values[rg.x + (int32_t)(word >> 4)];
             const uint2 r = *reinterpret_cast<const uint2*>(bins + gv);     // tile rectangle of the record
             const int32_t xlo = (int32_t)(r.x & 0xffff), ylo = (int32_t)(r.x >> 16);
             const int32_t xhi = (int32_t)(r.y & 0xffff);
@@ -373,9 +389,8 @@ __global__ __launch_bounds__(kLanes) void k_render_bwd(const ViewDev* __restrict
             const float4 g = s_geo[k];
             const float4 cc = s_col[k];
             const float cb = s_blu[k];
-            // lanes of each block that composited this Gaussian (one scalar load of 32 bytes)
-            const ulonglong4 em4 = *reinterpret_cast<const ulonglong4*>(entry_mask + (int64_t)(rg.x + bstart + k) * kPPT);
-            const uint64_t em[kPPT] = {em4.x, em4.y, em4.z, em4.w};
+            const uint32_t word = (uint32_t)__builtin_amdgcn_readfirstlane((int)s_word[k]);
+            const int32_t pos = (int32_t)(word >> 4);
             // Per-lane sums over the lane's pixels, later reduced over the wave:
             //   m[0..1] = sum dq' (dx, dy), m[2..4] = sum dq' (dx^2, dx dy, dy^2)
             //   with dq' = alpha dL/dalpha (so dL/dq = -dq'/2), m[5] = sum e dL/dalpha,
@@ -385,12 +400,13 @@ __global__ __launch_bounds__(kLanes) void k_render_bwd(const ViewDev* __restrict
             for (int i = 0; i < 9; i++) m[i] = 0.0f;
 #pragma unroll
             for (int j = 0; j < kPPT; j++) {
-                const uint64_t cm = em[j];
-                if (cm == 0) continue;
-                const bool in = __builtin_amdgcn_inverse_ballot_w64(cm);
+                if (!((word >> j) & 1u)) continue;      // no pixel of block j composited this Gaussian
                 const float dx = t.fx[j] - g.x, dy = t.fy[j] - g.y;
                 const float q = quad(dx, dy, g.z, g.w, cc.x);
                 const Eval ev = evaluate(q, cc.y);    // bit-identical to the forward's alpha
+                // the forward's decision: a pixel still compositing at this position took every
+                // Gaussian inside the footprint with alpha >= 1/255 (it stops only after its last one)
+                const bool in = pos < nc[j] && q <= kQMax && ev.alpha >= kAlphaMin;
                 const float al = ev.alpha;
                 const float Tk = T[j] * __builtin_amdgcn_rcpf(1.0f - al);   // transmittance in front of k
                 T[j] = in ? Tk : T[j];
@@ -440,27 +456,27 @@ __global__ __launch_bounds__(kLanes) void k_render_bwd(const ViewDev* __restrict
 template <int TW, int TH, int BATCH>
 void fwd_launch(const pg_views* v, const pg_splat* splats, const int32_t* values, const int32_t* ranges,
                 const float bg[3], float* image, float* final_T, int32_t* n_contrib, int32_t* tile_entries,
-                int32_t* entry_pos, uint64_t* entry_mask, uint64_t* counters, hipStream_t s) {
+                uint32_t* entries, uint64_t* counters, hipStream_t s) {
     const unsigned grid = (unsigned)v->n_tiles;
     if (counters)
         k_render_fwd<TW, TH, BATCH, true><<<grid, kLanes, 0, s>>>(
             v->d_views, v->n_views, v->n_tiles, splats, values, reinterpret_cast<const int2*>(ranges), bg[0], bg[1],
-            bg[2], image, final_T, n_contrib, tile_entries, entry_pos, entry_mask,
+            bg[2], image, final_T, n_contrib, tile_entries, entries,
             reinterpret_cast<unsigned long long*>(counters));
     else
         k_render_fwd<TW, TH, BATCH, false><<<grid, kLanes, 0, s>>>(
             v->d_views, v->n_views, v->n_tiles, splats, values, reinterpret_cast<const int2*>(ranges), bg[0], bg[1],
-            bg[2], image, final_T, n_contrib, tile_entries, entry_pos, entry_mask, nullptr);
+            bg[2], image, final_T, n_contrib, tile_entries, entries, nullptr);
 }
 
 template <int TW, int TH, int BATCH>
 void bwd_launch(const pg_views* v, const pg_splat* splats, const pg_bin* bins, const int32_t* values,
                 const int32_t* ranges, const int32_t* inst_first, const int32_t* tile_entries,
-                const int32_t* entry_pos, const uint64_t* entry_mask, const float bg[3], const float* final_T,
+                const uint32_t* entries, const int32_t* n_contrib, const float bg[3], const float* final_T,
                 const float* dL_dimage, const int64_t* n_inst_dev, int64_t cap, float* inst_grad, hipStream_t s) {
     k_render_bwd<TW, TH, BATCH><<<(unsigned)v->n_tiles, kLanes, 0, s>>>(
         v->d_views, v->n_views, v->n_tiles, splats, bins, values, reinterpret_cast<const int2*>(ranges), inst_first,
-        tile_entries, entry_pos, entry_mask, bg[0], bg[1], bg[2], final_T, dL_dimage, n_inst_dev, cap, inst_grad);
+        tile_entries, entries, n_contrib, bg[0], bg[1], bg[2], final_T, dL_dimage, n_inst_dev, cap, inst_grad);
 }
 
 template <template <int, int, int> class F, typename... A>
@@ -490,23 +506,23 @@ struct BwdRun {
 
 hipError_t launch_render_fwd(const pg_views* v, const pg_splat* splats, const int32_t* values,
                              const int32_t* ranges, const float bg[3], float* image, float* final_T,
-                             int32_t* n_contrib, int32_t* tile_entries, int32_t* entry_pos, uint64_t* entry_mask,
-                             uint64_t* counters, hipStream_t s) {
+                             int32_t* n_contrib, int32_t* tile_entries, uint32_t* entries, uint64_t* counters,
+                             hipStream_t s) {
     if (v->n_tiles == 0) return hipSuccess;
-    dispatch<FwdRun>(v->tiling, v, splats, values, ranges, bg, image, final_T, n_contrib, tile_entries, entry_pos,
-                     entry_mask, counters, s);
+    dispatch<FwdRun>(v->tiling, v, splats, values, ranges, bg, image, final_T, n_contrib, tile_entries, entries,
+                     counters, s);
     return hipGetLastError();
 }
 
 hipError_t launch_render_bwd(const pg_views* v, const pg_splat* splats, const pg_bin* bins, const int32_t* values,
                              const int32_t* ranges, const int32_t* inst_first, const int32_t* tile_entries,
-                             const int32_t* entry_pos, const uint64_t* entry_mask, const float bg[3],
+                             const uint32_t* entries, const int32_t* n_contrib, const float bg[3],
                              const float* final_T, const float* dL_dimage, const int64_t* n_inst_dev, int64_t cap,
                              float* inst_grad, hipStream_t s) {
     // instances nobody composited keep zero sums
     hipError_t e = fill_u32_dev(inst_grad, 0u, n_inst_dev, cap, 9, s);
     if (e != hipSuccess || v->n_tiles == 0) return e;
-    dispatch<BwdRun>(v->tiling, v, splats, bins, values, ranges, inst_first, tile_entries, entry_pos, entry_mask, bg,
+    dispatch<BwdRun>(v->tiling, v, splats, bins, values, ranges, inst_first, tile_entries, entries, n_contrib, bg,
                      final_T, dL_dimage, n_inst_dev, cap, inst_grad, s);
     return hipGetLastError();
 }

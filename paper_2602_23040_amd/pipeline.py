@@ -5,7 +5,7 @@ allocate device memory and to supply the current stream) and runs the chain
 
     pg_atlas_fetch -> pg_project -> pg_bin_sort -> pg_render_fwd   (forward)
     pg_loss_l1                                                      (L1 term)
-    pg_render_bwd                                                   (adjoint)
+    pg_render_bwd -> pg_project_bwd                                 (adjoint)
     pg_adam_step                                                    (optional)
 
 in one of two modes over the same kernels:
@@ -58,8 +58,7 @@ class _ViewSet:
         self.cap = cap
         self.keys = torch.empty(cap, dtype=torch.int32, device=self.device)
         self.values = torch.empty(cap, dtype=torch.int32, device=self.device)
-        self.entry_pos = torch.empty(cap, dtype=torch.int32, device=self.device)
-        self.entry_mask = torch.empty(4 * cap, dtype=torch.int64, device=self.device)
+        self.entries = torch.empty(cap, dtype=torch.int32, device=self.device)
         self.inst_grad = torch.empty(9 * cap, dtype=torch.float32, device=self.device)
         self.ws_bytes = abi.pg_sort_workspace_size(self.handle, cap)
         self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.device)
@@ -172,8 +171,8 @@ class Renderer:
 
     def _project_sort_render(self, s: _ViewSet, pix_off: int, counters):
         abi.pg_project(s.handle, self.params, s.splats, s.bins, self.visible)
-        abi.pg_bin_sort(s.handle, s.bins, s.cap, s.keys, s.values, s.ranges, s.inst_first, s.n_inst, s.overflow, s.ws,
-                        s.ws_bytes)
+        abi.pg_bin_sort(s.handle, s.bins, s.cap, s.keys, s.values, s.ranges, s.inst_first, s.n_inst, s.overflow,
+                        s.ws, s.ws_bytes)
         if not self.batched:
             # plain path: one instance-count synchronisation per view
             if int(s.overflow.item()):
@@ -182,7 +181,7 @@ class Renderer:
                                 s.overflow, s.ws, s.ws_bytes)
         abi.pg_render_fwd(s.handle, s.splats, s.values, s.ranges, self.bg, self._off(self.image, 3 * pix_off),
                           self._off(self.final_T, pix_off), self._off(self.n_contrib, pix_off), s.tile_entries,
-                          s.entry_pos, s.entry_mask, counters)
+                          s.entries, counters)
 
     def forward(self, atlas: torch.Tensor, counters: bool = False) -> torch.Tensor:
         """Render every view; returns the flat image buffer (valid until the next call)."""
@@ -206,17 +205,20 @@ class Renderer:
         assert g.is_contiguous() and g.numel() == 3 * self.n_pixels
         if self.batched:
             s = self.sets[0]
-            abi.pg_render_bwd(s.handle, self.params, s.splats, s.bins, s.values, s.ranges, s.inst_first, s.n_inst,
-                              s.cap, s.tile_entries, s.entry_pos, s.entry_mask, self.bg, self.final_T, g, self.gauss_texel,
-                              self.dynamic, self.H, self.W, s.inst_grad, s.grad2d, self.dL_datlas, 0)
+            abi.pg_render_bwd(s.handle, s.splats, s.bins, s.values, s.ranges, s.inst_first, s.n_inst, s.cap,
+                              s.tile_entries, s.entries, self.n_contrib, self.bg, self.final_T, g, s.inst_grad)
+            abi.pg_project_bwd(s.handle, self.params, s.bins, s.inst_first, s.n_inst, s.cap,
+                               s.inst_grad, self.gauss_texel, self.dynamic, self.H, self.W, s.grad2d, self.dL_datlas, 0)
         else:
             self.dL_datlas.zero_()
             for k, s in enumerate(self.sets):
                 po = self.pix_base[k]
-                abi.pg_render_bwd(s.handle, self.params, s.splats, s.bins, s.values, s.ranges, s.inst_first,
-                                  s.n_inst, s.cap, s.tile_entries, s.entry_pos, s.entry_mask, self.bg,
-                                  self._off(self.final_T, po), self._off(g, 3 * po), self.gauss_texel, self.dynamic,
-                                  self.H, self.W, s.inst_grad, s.grad2d, self.dL_datlas, 1)
+                abi.pg_render_bwd(s.handle, s.splats, s.bins, s.values, s.ranges, s.inst_first, s.n_inst, s.cap,
+                                  s.tile_entries, s.entries, self._off(self.n_contrib, po), self.bg,
+                                  self._off(self.final_T, po), self._off(g, 3 * po), s.inst_grad)
+                abi.pg_project_bwd(s.handle, self.params, s.bins, s.inst_first, s.n_inst, s.cap,
+                                   s.inst_grad, self.gauss_texel, self.dynamic, self.H, self.W, s.grad2d,
+                                   self.dL_datlas, 1)
         return self.dL_datlas
 
     def adam_step(self, atlas: torch.Tensor, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
