@@ -50,6 +50,7 @@ constexpr float kQMax = 9.0f;
 constexpr float kAlphaMax = 0.99f;
 constexpr float kAlphaMin = 1.0f / 255.0f;
 constexpr float kTMin = 1e-4f;
+constexpr float kNegHalfLog2e = -0.72134752044448170f;   // -log2(e) / 2
 
 // The one definition of q and alpha used by both the forward and the adjoint,
 // with explicit fused multiply-adds so both kernels take bit-identical
@@ -66,7 +67,7 @@ __device__ __forceinline__ float quad(float dx, float dy, float a, float b2, flo
 __device__ __forceinline__ Eval evaluate(float q, float o) {
     Eval r;
     r.q = q;
-    r.e = __expf(-0.5f * q);
+    r.e = __builtin_amdgcn_exp2f(q * kNegHalfLog2e);   // e^{-q/2} as 2^{-q log2(e) / 2}
     r.raw = o * r.e;
     r.alpha = r.raw < kAlphaMax ? r.raw : kAlphaMax;
     return r;
@@ -126,14 +127,16 @@ __device__ __forceinline__ void tile_geo(const ViewDev* views, int nv, int64_t n
     }
 }
 
-// Stage Gaussian `gv` into LDS slot `k` in coordinates local to (ox, oy), with
-// the mask of 8x8 pixel blocks its ellipse q <= 9 can reach.  The ellipse's
-// half-extents are 3 sqrt(Sigma_xx) and 3 sqrt(Sigma_yy), with
-// (Sigma_xx, Sigma_yy) = (c, a) / (a c - b^2) from the conic.  The bounds are
-// widened (0.1% + 0.01 px) to cover FP32 rounding of q and fall back to "all
-// blocks" for ill-conditioned conics, so a skipped block never holds a pixel
-// with q <= 9 and results are unchanged.
-template <int TW, int TH>
+// Stage Gaussian `gv` into LDS slot `k` in coordinates local to (ox, oy) and,
+// when MASK is set, the mask of 8x8 pixel blocks its ellipse q <= 9 can reach:
+// blocks whose pixel-centre rectangle meets the ellipse's bounding box, with
+// half-extents 3 sqrt(Sigma_xx) and 3 sqrt(Sigma_yy), (Sigma_xx, Sigma_yy) =
+// (c, a) / (a c - b^2) from the conic.  The bounds are widened (0.1% +
+// 0.01 px) to cover FP32 rounding of q and fall back to "all blocks" for
+// ill-conditioned conics, so a skipped block never holds a pixel with q <= 9
+// and results are unchanged.  (Testing the minimum of q over each block
+// rectangle instead cost more at staging than it saved.)
+template <int TW, int TH, bool MASK>
 __device__ __forceinline__ void stage(const pg_splat* __restrict__ splats, int32_t gv, double ox, double oy,
                                       float col0, float row0, float4* s_geo, float4* s_col, float* s_blu,
                                       uint32_t* s_mask, int k) {
@@ -145,6 +148,7 @@ __device__ __forceinline__ void stage(const pg_splat* __restrict__ splats, int32
     s_geo[k] = make_float4(mx, my, b.x, 2.0f * b.y);
     s_col[k] = make_float4(b.z, b.w, c.x, c.y);   // conic c, opacity, red, green
     s_blu[k] = c.z;
+    if (!MASK) return;
     constexpr int BPR = TW / 8;
     const float ac = b.x * b.z;
     const float det = ac - b.y * b.y;
@@ -196,7 +200,7 @@ __global__ __launch_bounds__(kLanes) void k_render_fwd(const ViewDev* __restrict
         if ((live[0] | live[1] | live[2] | live[3]) == 0) break;
         __syncthreads();
         for (int32_t i = threadIdx.x; i < BATCH && b0 + i < rg.y; i += kLanes)
-            stage<TW, TH>(splats, values[b0 + i], t.ox, t.oy, t.col0, t.row0, s_geo, s_col, s_blu, s_mask, i);
+            stage<TW, TH, true>(splats, values[b0 + i], t.ox, t.oy, t.col0, t.row0, s_geo, s_col, s_blu, s_mask, i);
         __syncthreads();
         const int32_t cnt = min(BATCH, rg.y - b0);
         // sub-batches of 64 Gaussians: bit (k - k0) of took[j] records that a pixel of block j took Gaussian k
@@ -340,7 +344,6 @@ __global__ __launch_bounds__(kLanes) void k_render_bwd(const ViewDev* __restrict
     __shared__ float s_blu[BATCH];
     __shared__ int32_t s_slot[BATCH];      // emission index of the (Gaussian, this tile) instance
     __shared__ uint32_t s_word[BATCH];     // entry word: list position << 4 | blocks that composited it
-    __shared__ uint32_t s_unused[BATCH];
     TileGeo t;
     tile_geo<TW, TH>(views, nv, n_tiles, t);
     const int2 rg = ranges[t.tile];
@@ -348,16 +351,16 @@ __global__ __launch_bounds__(kLanes) void k_render_bwd(const ViewDev* __restrict
     const int64_t n_inst = *n_inst_dev;
     if (count == 0 || n_inst > cap) return;       // nothing composited here, or the sort overflowed
     const int64_t HW = (int64_t)t.W * t.H;
-    float T[kPPT], G0[kPPT], G1[kPPT], G2[kPPT], B0[kPPT], B1[kPPT], B2[kPPT];
+    // Per pixel: T, the colour cotangent G, and S = G . B, where B is the colour
+    // composited behind the current Gaussian (background first); with
+    // B <- alpha c + (1 - alpha) B, S follows S <- S + alpha (G . c - S).
+    float T[kPPT], G0[kPPT], G1[kPPT], G2[kPPT], S[kPPT];
     int32_t nc[kPPT];      // list positions below nc[j] were reached by pixel j (0 outside the image)
 #pragma unroll
     for (int j = 0; j < kPPT; j++) {
         T[j] = 1.0f;
         nc[j] = 0;
         G0[j] = G1[j] = G2[j] = 0.0f;
-        B0[j] = bg0;
-        B1[j] = bg1;
-        B2[j] = bg2;
         if (t.inside[j]) {
             const int64_t p = (int64_t)t.py[j] * t.W + t.px[j];
             const float* gi = dL_dimage + 3 * t.vbase + p;
@@ -367,6 +370,7 @@ __global__ __launch_bounds__(kLanes) void k_render_bwd(const ViewDev* __restrict
             T[j] = final_T[t.vbase + p];
             nc[j] = n_contrib[t.vbase + p];
         }
+        S[j] = fmaf(G2[j], bg2, fmaf(G1[j], bg1, G0[j] * bg0));
     }
     const int lane = threadIdx.x;
     // entries (composited Gaussians of this tile) back to front
@@ -382,7 +386,7 @@ __global__ __launch_bounds__(kLanes) void k_render_bwd(const ViewDev* __restrict
             const int32_t xlo = (int32_t)(r.x & 0xffff), ylo = (int32_t)(r.x >> 16);
             const int32_t xhi = (int32_t)(r.y & 0xffff);
             s_slot[i] = inst_first[gv] + (t.ty - ylo) * (xhi - xlo + 1) + (t.tx - xlo);
-            stage<TW, TH>(splats, gv, t.ox, t.oy, t.col0, t.row0, s_geo, s_col, s_blu, s_unused, i);
+            stage<TW, TH, false>(splats, gv, t.ox, t.oy, t.col0, t.row0, s_geo, s_col, s_blu, nullptr, i);
         }
         __syncthreads();
         for (int32_t k = cnt - 1; k >= 0; k--) {
@@ -408,20 +412,18 @@ __global__ __launch_bounds__(kLanes) void k_render_bwd(const ViewDev* __restrict
                 // Gaussian inside the footprint with alpha >= 1/255 (it stops only after its last one)
                 const bool in = pos < nc[j] && q <= kQMax && ev.alpha >= kAlphaMin;
                 const float al = ev.alpha;
-                const float Tk = T[j] * __builtin_amdgcn_rcpf(1.0f - al);   // transmittance in front of k
-                T[j] = in ? Tk : T[j];
-                const float Te = in ? Tk : 0.0f;
-                const float ae = in ? al : 0.0f;
-                const float w = Te * al;
+                const float ae = in ? al : 0.0f;      // 0 for pixels that did not take it: T, S unchanged
+                const float Tk = T[j] * __builtin_amdgcn_rcpf(1.0f - ae);   // transmittance in front of k
+                T[j] = Tk;
+                const float w = Tk * ae;
                 m[6] = fmaf(w, G0[j], m[6]);
                 m[7] = fmaf(w, G1[j], m[7]);
                 m[8] = fmaf(w, G2[j], m[8]);
-                const float d0 = cc.z - B0[j], d1 = cc.w - B1[j], d2 = cb - B2[j];
-                const float dal = Te * fmaf(G2[j], d2, fmaf(G1[j], d1, G0[j] * d0));
-                B0[j] = fmaf(ae, d0, B0[j]);          // B <- alpha c + (1 - alpha) B
-                B1[j] = fmaf(ae, d1, B1[j]);
-                B2[j] = fmaf(ae, d2, B2[j]);
-                const float dau = ev.raw < kAlphaMax ? dal : 0.0f;   // clamped alpha: no opacity / shape terms
+                const float gc = fmaf(G2[j], cb, fmaf(G1[j], cc.w, G0[j] * cc.z));
+                const float diff = gc - S[j];         // G . (c - B)
+                S[j] = fmaf(ae, diff, S[j]);
+                // dL/dalpha, kept only where the pixel took the Gaussian and alpha was not clamped
+                const float dau = (in && ev.raw < kAlphaMax) ? Tk * diff : 0.0f;
                 m[5] = fmaf(dau, ev.e, m[5]);
                 const float dqp = al * dau;
                 const float px = dqp * dx, py = dqp * dy;
