@@ -68,6 +68,23 @@ def parse():
     return ap.parse_args()
 
 
+def recorded_traffic(kernel, workload, tiling):
+    """HBM bytes per launch of `kernel` from the committed counter record
+    (profiles/traffic.json: FETCH_SIZE and WRITE_SIZE of the same launch,
+    scaled by what the counters read for a copy of known size), or None when
+    there is no record for this workload and tiling or the kernel's source
+    has changed since the counters were taken."""
+    import hashlib
+    try:
+        with open(os.path.join(ROOT, "profiles", "traffic.json")) as f:
+            rec = json.load(f)[f"{kernel}|{workload}|{tiling}"]
+        with open(os.path.join(ROOT, rec["source"]), "rb") as f:
+            digest = hashlib.sha256(f.read()).hexdigest()
+    except (OSError, KeyError, ValueError):
+        return None
+    return rec["bytes_per_launch"] if digest == rec["source_sha256"] else None
+
+
 def calibrate_copy(mib):
     import torch
     n = mib * (1 << 20) // 4
@@ -201,7 +218,9 @@ def main():
         bound, amount, unit, peak = work[dom]
         achieved = amount / (stages[dom] / 1e3)
         roof = {"kernel": dom, "bound": bound, "achieved": round(achieved, 3), "peak": peak, "unit": unit,
-                "frac": round(achieved / peak, 4), "traffic": None, "ms": round(stages[dom], 4)}
+                "frac": round(achieved / peak, 4),
+                "traffic": recorded_traffic(dom, sc.name, "x".join(str(x) for x in tiling)),
+                "ms": round(stages[dom], 4)}
     else:
         roof = {"kernel": dom, "bound": "alu", "achieved": None, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                 "frac": None, "traffic": None, "ms": round(stages[dom], 4)}
@@ -252,7 +271,7 @@ def stage_times(r, atlas, target, reps=5):
         "fetch": lambda: r.fetch(atlas),
         "project": lambda: abi.pg_project(s.handle, r.params, s.splats, s.bins, r.visible, stream),
         "bin_sort": lambda: abi.pg_bin_sort(s.handle, s.bins, s.cap, s.keys, s.values, s.ranges, s.inst_first,
-                                            s.n_inst, s.overflow, s.ws, s.ws_bytes, stream),
+                                            s.n_inst, s.overflow, s.inst_grad, s.ws, s.ws_bytes, stream),
         "render_fwd": lambda: abi.pg_render_fwd(s.handle, s.splats, s.values, s.ranges, r.bg, r.image, r.final_T,
                                                 r.n_contrib, s.tile_entries, s.entries, None, stream),
         "loss_l1": lambda: r.loss_l1(target),

@@ -186,10 +186,12 @@ pg_status pg_project(const pg_views* views, const float* params, pg_splat* splat
  *                  order, the record's tiles in rectangle row-major order.
  *   n_inst_dev     device int64 [1] out: number of instances
  *   overflow_dev   device int32 [1] out: 1 if n_inst > inst_capacity, else 0
+ *   inst_grad      device float [inst_capacity][9] or NULL: the adjoint's
+ *                  per-instance gradient slots; the first n_inst are zeroed
  *   ws             device workspace of pg_sort_workspace_size bytes */
 pg_status pg_bin_sort(const pg_views* views, const pg_bin* bins, int64_t inst_capacity, uint32_t* keys,
                       int32_t* values, int32_t* tile_ranges, int32_t* inst_first, int64_t* n_inst_dev,
-                      int32_t* overflow_dev, void* ws, size_t ws_bytes, void* stream);
+                      int32_t* overflow_dev, float* inst_grad, void* ws, size_t ws_bytes, void* stream);
 
 /* a4 -- Front-to-back compositing (supplementary viewer section:
  * C = sum_i T_i alpha_i c_i, T_i = prod_{j<i} (1 - alpha_j); footprint
@@ -220,13 +222,14 @@ pg_status pg_render_fwd(const pg_views* views, const pg_splat* splats, const int
  * recomputing per-pixel transmittance from final_T instead of storing it,
  * and writes each (Gaussian, tile) instance's summed 2D gradient
  * dL/d(m_x, m_y, a, b, c, opacity, r, g, b) to that instance's own slot (no
- * atomics).  Slots of instances that composited nothing are zero.
+ * atomics).  Slots of instances that composited nothing are not written:
+ * they keep the zero pg_bin_sort gave them.
  *   bins, inst_first, n_inst_dev   from pg_project / pg_bin_sort; after an
  *                overflowed sort (n_inst > inst_capacity) no slot is written
  *   tile_entries, entries, n_contrib, final_T   from pg_render_fwd
  *   dL_dimage    device float [3 n_pixels]
  *   inst_capacity the capacity given to pg_bin_sort
- *   inst_grad    device float [inst_capacity][9] out, slot inst_first[gv] + k
+ *   inst_grad    device float [inst_capacity][9] in/out (zeroed by pg_bin_sort), slot inst_first[gv] + k
  *                for tile k (row-major) of record gv's rectangle */
 pg_status pg_render_bwd(const pg_views* views, const pg_splat* splats, const pg_bin* bins, const int32_t* values,
                         const int32_t* tile_ranges, const int32_t* inst_first, const int64_t* n_inst_dev,

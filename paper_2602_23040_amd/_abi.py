@@ -60,7 +60,7 @@ SIGNATURES = {
     "pg_sort_workspace_size": (_i32, [_p, _i64, C.POINTER(_sz)]),
     "pg_atlas_fetch": (_i32, [_p, _p, _i32, _i32, _i32, _i32, _i64, _p, _p, _p, _p, _p, _sz, _p]),
     "pg_project": (_i32, [_p, _p, _p, _p, _p, _p]),
-    "pg_bin_sort": (_i32, [_p, _p, _i64, _p, _p, _p, _p, _p, _p, _p, _sz, _p]),
+    "pg_bin_sort": (_i32, [_p, _p, _i64, _p, _p, _p, _p, _p, _p, _p, _p, _sz, _p]),
     "pg_render_fwd": (_i32, [_p, _p, _p, _p, _p, _p, _p, _p, _p, _p, _p, _p]),
     "pg_render_bwd": (_i32, [_p, _p, _p, _p, _p, _p, _p, _i64, _p, _p, _p, _p, _p, _p, _p, _p]),
     "pg_project_bwd": (_i32, [_p, _p, _p, _p, _p, _i64, _p, _p, _p, _i32, _i32, _p, _p, _i32, _p]),
@@ -190,10 +190,11 @@ def pg_project(views, params, splats, bins, visible, stream=None):
            "pg_project")
 
 
-def pg_bin_sort(views, bins, inst_capacity, keys, values, tile_ranges, inst_first, n_inst_dev, overflow_dev, ws,
-                ws_bytes, stream=None):
+def pg_bin_sort(views, bins, inst_capacity, keys, values, tile_ranges, inst_first, n_inst_dev, overflow_dev,
+                inst_grad, ws, ws_bytes, stream=None):
     _check(lib().pg_bin_sort(views, _ptr(bins), int(inst_capacity), _ptr(keys), _ptr(values), _ptr(tile_ranges),
-                             _ptr(inst_first), _ptr(n_inst_dev), _ptr(overflow_dev), _ptr(ws), int(ws_bytes),
+                             _ptr(inst_first), _ptr(n_inst_dev), _ptr(overflow_dev), _ptr(inst_grad), _ptr(ws),
+                             int(ws_bytes),
                              _stream(stream)), "pg_bin_sort")
 
 

@@ -251,7 +251,7 @@ pg_status pg_project(const pg_views* v, const float* params, pg_splat* splats, p
 
 pg_status pg_bin_sort(const pg_views* v, const pg_bin* bins, int64_t cap, uint32_t* keys, int32_t* values,
                       int32_t* tile_ranges, int32_t* inst_first, int64_t* n_inst_dev, int32_t* overflow_dev,
-                      void* ws, size_t ws_bytes, void* stream) {
+                      float* inst_grad, void* ws, size_t ws_bytes, void* stream) {
     g_error.clear();
     if (!v) return invalid("views is null");
     if (!tile_ranges || !n_inst_dev || !overflow_dev || !ws) return invalid("null pointer argument");
@@ -262,8 +262,8 @@ pg_status pg_bin_sort(const pg_views* v, const pg_bin* bins, int64_t cap, uint32
         set_error("sort workspace too small");
         return PG_ERR_WORKSPACE;
     }
-    PG_CHECK_HIP(launch_bin_sort(v, bins, cap, keys, values, tile_ranges, inst_first, n_inst_dev, overflow_dev, ws,
-                                 (hipStream_t)stream),
+    PG_CHECK_HIP(launch_bin_sort(v, bins, cap, keys, values, tile_ranges, inst_first, n_inst_dev, overflow_dev,
+                                 inst_grad, ws, (hipStream_t)stream),
                  "pg_bin_sort");
     return PG_OK;
 }

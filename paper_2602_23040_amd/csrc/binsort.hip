@@ -462,7 +462,7 @@ size_t sort_ws_bytes(const pg_views* v, int64_t cap) {
 
 hipError_t launch_bin_sort(const pg_views* v, const pg_bin* bins, int64_t cap, uint32_t* keys, int32_t* values,
                            int32_t* ranges, int32_t* inst_first, int64_t* n_inst_dev, int32_t* overflow_dev,
-                           void* ws, hipStream_t s) {
+                           float* inst_grad, void* ws, hipStream_t s) {
     const SortPlan pl = plan_for(v);
     SortWs w = carve(v, cap, ws, nullptr);
     const int64_t nb = n_blocks(v);
@@ -514,6 +514,8 @@ hipError_t launch_bin_sort(const pg_views* v, const pg_bin* bins, int64_t cap, u
         int32_t* tv = tva; tva = tvb; tvb = tv;
     }
     k_ranges<<<1024, 256, 0, s>>>(keys, w.misc, ranges);
+    // 6. zero the adjoint's per-instance gradient slots (instances nobody composites keep 0)
+    if (inst_grad) return fill_u32_dev(inst_grad, 0u, n_inst_dev, cap, 9, s);
     return hipGetLastError();
 }
 

@@ -89,7 +89,7 @@ hipError_t launch_project_bwd(const pg_views* v, const float* params, const floa
 size_t sort_ws_bytes(const pg_views* v, int64_t cap);
 hipError_t launch_bin_sort(const pg_views* v, const pg_bin* bins, int64_t cap, uint32_t* keys, int32_t* values,
                            int32_t* ranges, int32_t* inst_first, int64_t* n_inst_dev, int32_t* overflow_dev,
-                           void* ws, hipStream_t s);
+                           float* inst_grad, void* ws, hipStream_t s);
 
 // render.hip
 hipError_t launch_render_fwd(const pg_views* v, const pg_splat* splats, const int32_t* values,

@@ -521,9 +521,7 @@ hipError_t launch_render_bwd(const pg_views* v, const pg_splat* splats, const pg
                              const uint32_t* entries, const int32_t* n_contrib, const float bg[3],
                              const float* final_T, const float* dL_dimage, const int64_t* n_inst_dev, int64_t cap,
                              float* inst_grad, hipStream_t s) {
-    // instances nobody composited keep zero sums
-    hipError_t e = fill_u32_dev(inst_grad, 0u, n_inst_dev, cap, 9, s);
-    if (e != hipSuccess || v->n_tiles == 0) return e;
+    if (v->n_tiles == 0) return hipSuccess;
     dispatch<BwdRun>(v->tiling, v, splats, bins, values, ranges, inst_first, tile_entries, entries, n_contrib, bg,
                      final_T, dL_dimage, n_inst_dev, cap, inst_grad, s);
     return hipGetLastError();

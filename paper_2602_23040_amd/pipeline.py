@@ -172,13 +172,13 @@ class Renderer:
     def _project_sort_render(self, s: _ViewSet, pix_off: int, counters):
         abi.pg_project(s.handle, self.params, s.splats, s.bins, self.visible)
         abi.pg_bin_sort(s.handle, s.bins, s.cap, s.keys, s.values, s.ranges, s.inst_first, s.n_inst, s.overflow,
-                        s.ws, s.ws_bytes)
+                        s.inst_grad, s.ws, s.ws_bytes)
         if not self.batched:
             # plain path: one instance-count synchronisation per view
             if int(s.overflow.item()):
                 s.set_capacity(int(math.ceil(int(s.n_inst.item()) * 1.25)))
                 abi.pg_bin_sort(s.handle, s.bins, s.cap, s.keys, s.values, s.ranges, s.inst_first, s.n_inst,
-                                s.overflow, s.ws, s.ws_bytes)
+                                s.overflow, s.inst_grad, s.ws, s.ws_bytes)
         abi.pg_render_fwd(s.handle, s.splats, s.values, s.ranges, self.bg, self._off(self.image, 3 * pix_off),
                           self._off(self.final_T, pix_off), self._off(self.n_contrib, pix_off), s.tile_entries,
                           s.entries, counters)
