@@ -20,9 +20,11 @@
 // (Gaussian, view) is ~300 FP64 flops against 64 bytes written, so at the
 // chip's FP64 rate the kernel stays close to its HBM bound.
 //
-// The adjoint takes no integer decision, so it runs the same chain in FP32
-// (half the registers of FP64: 216 instead of 256 plus spills at SH degree
-// 3), after a streaming pass has summed each record's instance slots.
+// The adjoint runs as three passes: a streaming sum of each record's
+// instance slots, the geometric chain in FP64 (position, scale, rotation,
+// opacity), and the SH colour chain in FP32 (its 48 coefficient gradients and
+// the view-direction term of the position gradient).  Splitting them keeps
+// both under 256 registers without spills.
 #include "pg_internal.h"
 
 #pragma clang fp contract(off)
@@ -71,35 +73,6 @@ __device__ __forceinline__ void sh_basis(double x, double y, double z, double* Y
         Y[14] = kY3e * z * (x * x - y * y);
         Y[15] = -kY3a * x * (x * x - 3.0 * y * y);
     }
-}
-
-// Sum over j of w_j * grad Y_j(x, y, z): the derivatives of the polynomials
-// above, contracted with the weights as they are formed.
-template <int L>
-__device__ __forceinline__ void sh_grad_dot(double x, double y, double z, const double* w, double g[3]) {
-    double g0 = 0.0, g1 = 0.0, g2 = 0.0;
-    if (L >= 1) {
-        g0 -= kY1 * w[3];
-        g1 -= kY1 * w[1];
-        g2 += kY1 * w[2];
-    }
-    if (L >= 2) {
-        g0 += kY2a * y * w[4] - kY2a * z * w[7] + 2.0 * kY2c * x * w[8];
-        g1 += kY2a * x * w[4] - kY2a * z * w[5] - 2.0 * kY2c * y * w[8];
-        g2 += -kY2a * y * w[5] + 6.0 * kY2b * z * w[6] - kY2a * x * w[7];
-    }
-    if (L >= 3) {
-        const double p3 = 3.0 * x * x - 3.0 * y * y, p5 = 5.0 * z * z - 1.0;
-        g0 += -6.0 * kY3a * x * y * w[9] + kY3b * y * z * w[10] - kY3c * p5 * w[13] + 2.0 * kY3e * x * z * w[14]
-              - kY3a * p3 * w[15];
-        g1 += -kY3a * p3 * w[9] + kY3b * x * z * w[10] - kY3c * p5 * w[11] - 2.0 * kY3e * y * z * w[14]
-              + 6.0 * kY3a * x * y * w[15];
-        g2 += kY3b * x * y * w[10] - 10.0 * kY3c * y * z * w[11] + kY3d * (15.0 * z * z - 3.0) * w[12]
-              - 10.0 * kY3c * x * z * w[13] + kY3e * (x * x - y * y) * w[14];
-    }
-    g[0] = g0;
-    g[1] = g1;
-    g[2] = g2;
 }
 
 // World-space part of the chain, shared by every view of a Gaussian.
@@ -189,8 +162,7 @@ __device__ __forceinline__ void view_dir(const ViewDev& V, const World& w, doubl
     d[0] /= *dn; d[1] /= *dn; d[2] /= *dn;
 }
 
-// ---- FP32 copies of the chain for the adjoint (gradients need no FP64:
-// their tolerance is relative, and no integer decision is taken here).
+// ---- FP32 SH basis and its contracted gradient for the colour adjoint
 
 template <int L>
 __device__ __forceinline__ void sh_basis_f(float x, float y, float z, float* Y) {
@@ -244,91 +216,6 @@ __device__ __forceinline__ void sh_grad_dot_f(float x, float y, float z, const f
     g[1] = g1;
     g[2] = g2;
 }
-
-struct WorldF {
-    float mu[3], s[3], qn, qh[4], o;
-    float Rq[9], M[9], S[9];
-};
-
-__device__ __forceinline__ void world_chain_f(const float* rec, WorldF& w) {
-    w.mu[0] = rec[0]; w.mu[1] = rec[1]; w.mu[2] = rec[2];
-    w.s[0] = expf((float)rec[3]); w.s[1] = expf((float)rec[4]); w.s[2] = expf((float)rec[5]);
-    const float qw = rec[6], qx = rec[7], qy = rec[8], qz = rec[9];
-    w.qn = sqrtf(((qw * qw + qx * qx) + qy * qy) + qz * qz);
-    w.qh[0] = qw / w.qn; w.qh[1] = qx / w.qn; w.qh[2] = qy / w.qn; w.qh[3] = qz / w.qn;
-    w.o = 1.0f / (1.0f + expf(-(float)rec[10]));
-    const float a = w.qh[0], x = w.qh[1], y = w.qh[2], z = w.qh[3];
-    w.Rq[0] = 1.0f - 2.0f * (y * y + z * z);
-    w.Rq[1] = 2.0f * (x * y - a * z);
-    w.Rq[2] = 2.0f * (x * z + a * y);
-    w.Rq[3] = 2.0f * (x * y + a * z);
-    w.Rq[4] = 1.0f - 2.0f * (x * x + z * z);
-    w.Rq[5] = 2.0f * (y * z - a * x);
-    w.Rq[6] = 2.0f * (x * z - a * y);
-    w.Rq[7] = 2.0f * (y * z + a * x);
-    w.Rq[8] = 1.0f - 2.0f * (x * x + y * y);
-#pragma unroll
-    for (int r = 0; r < 3; r++)
-#pragma unroll
-        for (int k = 0; k < 3; k++) w.M[3 * r + k] = w.Rq[3 * r + k] * w.s[k];
-#pragma unroll
-    for (int r = 0; r < 3; r++)
-#pragma unroll
-        for (int k = 0; k < 3; k++)
-            w.S[3 * r + k] = (w.M[3 * r] * w.M[3 * k] + w.M[3 * r + 1] * w.M[3 * k + 1]) + w.M[3 * r + 2] * w.M[3 * k + 2];
-}
-
-struct CamF {
-    float xc, yc, zc;
-    float Sc[9], J[6];
-    float ap, bp, cp, det;
-};
-
-// (no near-plane test: only records the forward kept reach the adjoint)
-__device__ __forceinline__ void camera_chain_f(const ViewDev& V, const WorldF& w, CamF& c) {
-    const float* R = V.Rf;
-    c.xc = ((R[0] * w.mu[0] + R[1] * w.mu[1]) + R[2] * w.mu[2]) + V.tf[0];
-    c.yc = ((R[3] * w.mu[0] + R[4] * w.mu[1]) + R[5] * w.mu[2]) + V.tf[1];
-    c.zc = ((R[6] * w.mu[0] + R[7] * w.mu[1]) + R[8] * w.mu[2]) + V.tf[2];
-    float A[9];
-#pragma unroll
-    for (int r = 0; r < 3; r++)
-#pragma unroll
-        for (int k = 0; k < 3; k++) A[3 * r + k] = (R[3 * r] * w.S[k] + R[3 * r + 1] * w.S[3 + k]) + R[3 * r + 2] * w.S[6 + k];
-#pragma unroll
-    for (int r = 0; r < 3; r++)
-#pragma unroll
-        for (int k = 0; k < 3; k++) c.Sc[3 * r + k] = (A[3 * r] * R[3 * k] + A[3 * r + 1] * R[3 * k + 1]) + A[3 * r + 2] * R[3 * k + 2];
-    const float z2 = c.zc * c.zc;
-    c.J[0] = V.fxf / c.zc;
-    c.J[1] = 0.0f;
-    c.J[2] = -(V.fxf * c.xc) / z2;
-    c.J[3] = 0.0f;
-    c.J[4] = V.fyf / c.zc;
-    c.J[5] = -(V.fyf * c.yc) / z2;
-    float T[6];
-#pragma unroll
-    for (int r = 0; r < 2; r++)
-#pragma unroll
-        for (int k = 0; k < 3; k++) T[3 * r + k] = (c.J[3 * r] * c.Sc[k] + c.J[3 * r + 1] * c.Sc[3 + k]) + c.J[3 * r + 2] * c.Sc[6 + k];
-    const float s00 = (T[0] * c.J[0] + T[1] * c.J[1]) + T[2] * c.J[2];
-    const float s01 = (T[0] * c.J[3] + T[1] * c.J[4]) + T[2] * c.J[5];
-    const float s11 = (T[3] * c.J[3] + T[4] * c.J[4]) + T[5] * c.J[5];
-    c.ap = s00 + (float)kLowPass;
-    c.bp = s01;
-    c.cp = s11 + (float)kLowPass;
-    c.det = c.ap * c.cp - c.bp * c.bp;
-}
-
-template <int L>
-__device__ __forceinline__ void view_dir_f(const ViewDev& V, const WorldF& w, float d[3], float* dn) {
-    d[0] = w.mu[0] - V.cwf[0];
-    d[1] = w.mu[1] - V.cwf[1];
-    d[2] = w.mu[2] - V.cwf[2];
-    *dn = sqrtf((d[0] * d[0] + d[1] * d[1]) + d[2] * d[2]);
-    d[0] /= *dn; d[1] /= *dn; d[2] /= *dn;
-}
-
 
 template <int L>
 __global__ __launch_bounds__(128) void k_project(const ViewDev* __restrict__ views,
@@ -416,16 +303,21 @@ __global__ __launch_bounds__(128) void k_project(const ViewDev* __restrict__ vie
 // dL/dM = 2 (dL/dSigma) M with M = R(q) diag(s); the mean through J and
 // through dJ/dmu_c; SH through the basis and the view direction.  Texel
 // chain: l_s via s, the raw quaternion via the normalisation, l_o via o (1 - o).
-template <int L>
-__global__ __launch_bounds__(128) void k_project_bwd(const ViewDev* __restrict__ views,
-                                                     const int32_t* __restrict__ frame_views,
-                                                     const int32_t* __restrict__ view_order, int32_t F, int32_t C,
-                                                     int64_t N, int64_t n_gv, const float* __restrict__ params,
-                                                     const float* __restrict__ grad2d,
-                                                     const int32_t* __restrict__ gauss_texel,
-                                                     const uint8_t* __restrict__ dyn, int64_t HW,
-                                                     float* __restrict__ gatlas, int32_t accumulate) {
-    constexpr int NB = (L + 1) * (L + 1);
+// Geometric part of the adjoint, FP64: position, log-scale, quaternion and
+// logit-opacity gradients through the EWA chain of every view of the
+// Gaussian's frame.  FP64 because the gradient of a rotation about an
+// elongated Gaussian's long axis (and the quaternion's tangent component in
+// general) is a small difference of large terms: in FP32 a few texels of the
+// 2048^2 workload missed 1e-3.  No SH coefficients are held here.
+__global__ __launch_bounds__(128) void k_project_bwd_geo(const ViewDev* __restrict__ views,
+                                                         const int32_t* __restrict__ frame_views,
+                                                         const int32_t* __restrict__ view_order, int32_t F,
+                                                         int32_t C, int64_t N, int64_t n_gv,
+                                                         const float* __restrict__ params,
+                                                         const float* __restrict__ grad2d,
+                                                         const int32_t* __restrict__ gauss_texel,
+                                                         const uint8_t* __restrict__ dyn, int64_t HW,
+                                                         float* __restrict__ gatlas, int32_t accumulate) {
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= (int64_t)F * N) return;
     const int32_t f = (int32_t)(g / N);
@@ -435,65 +327,63 @@ __global__ __launch_bounds__(128) void k_project_bwd(const ViewDev* __restrict__
     float rec[11];
 #pragma unroll
     for (int k = 0; k < 11; k++) rec[k] = P[(int64_t)k * N];
-    float sh[3 * NB];
+    double acc[11];
 #pragma unroll
-    for (int k = 0; k < 3 * NB; k++) sh[k] = P[(int64_t)(11 + k) * N];
-    float acc[11 + 3 * NB];
-#pragma unroll
-    for (int k = 0; k < 11 + 3 * NB; k++) acc[k] = 0.f;
-    WorldF w;
+    for (int k = 0; k < 11; k++) acc[k] = 0.0;
+    World w;
     bool have_world = false;
     for (int32_t vi = v0; vi < v1; vi++) {
         const int32_t v = view_order[vi];
         const int64_t gv = (int64_t)v * N + i;
-        // 2D gradient of the record (its slot sums; 0 for culled records)
-        float g9[9];
+        // 2D gradient of the record (its slot sums; 0 for culled records): mean, conic, opacity
+        double g6[6];
         bool nz = false;
 #pragma unroll
-        for (int k = 0; k < 9; k++) {
-            g9[k] = grad2d[(int64_t)k * n_gv + gv];
-            nz |= (g9[k] != 0.0f);
+        for (int k = 0; k < 6; k++) {
+            const float x = grad2d[(int64_t)k * n_gv + gv];
+            g6[k] = (double)x;
+            nz |= (x != 0.0f);
         }
         if (!nz) continue;
         if (!have_world) {
-            world_chain_f(rec, w);
+            world_chain(rec, w);
             have_world = true;
         }
         const ViewDev& V = views[v];
-        CamF c;
-        camera_chain_f(V, w, c);
-        const float det = c.det;
-        const float Q00 = c.cp / det, Q01 = -c.bp / det, Q11 = c.ap / det;
-        const float G00 = g9[2], G01 = 0.5f * g9[3], G11 = g9[4];
+        Cam c;
+        if (!camera_chain(V, w, c)) continue;   // never for a record with a gradient: the forward kept it
+        const double det = c.det;
+        const double Q00 = c.cp / det, Q01 = -c.bp / det, Q11 = c.ap / det;
+        const double G00 = g6[2], G01 = 0.5 * g6[3], G11 = g6[4];
         // QG = Q Gh ; GS = -(QG Q)
-        const float QG00 = Q00 * G00 + Q01 * G01, QG01 = Q00 * G01 + Q01 * G11;
-        const float QG10 = Q01 * G00 + Q11 * G01, QG11 = Q01 * G01 + Q11 * G11;
-        const float GS00 = -(QG00 * Q00 + QG01 * Q01);
-        const float GS01 = -(QG00 * Q01 + QG01 * Q11);
-        const float GS11 = -(QG10 * Q01 + QG11 * Q11);
+        const double QG00 = Q00 * G00 + Q01 * G01, QG01 = Q00 * G01 + Q01 * G11;
+        const double QG10 = Q01 * G00 + Q11 * G01, QG11 = Q01 * G01 + Q11 * G11;
+        const double GS00 = -(QG00 * Q00 + QG01 * Q01);
+        const double GS01 = -(QG00 * Q01 + QG01 * Q11);
+        const double GS11 = -(QG10 * Q01 + QG11 * Q11);
         // GJ = GS J (2x3)
-        float GJ[6];
+        double GJ[6];
 #pragma unroll
         for (int k = 0; k < 3; k++) {
             GJ[k] = GS00 * c.J[k] + GS01 * c.J[3 + k];
             GJ[3 + k] = GS01 * c.J[k] + GS11 * c.J[3 + k];
         }
         // dL/dSigma_c = J^T GJ
-        float GSc[9];
+        double GSc[9];
 #pragma unroll
         for (int r = 0; r < 3; r++)
 #pragma unroll
             for (int k = 0; k < 3; k++) GSc[3 * r + k] = c.J[r] * GJ[k] + c.J[3 + r] * GJ[3 + k];
         // dL/dJ = 2 GJ Sigma_c
-        float GJm[6];
+        double GJm[6];
 #pragma unroll
         for (int r = 0; r < 2; r++)
 #pragma unroll
             for (int k = 0; k < 3; k++)
-                GJm[3 * r + k] = 2.0f * (GJ[3 * r] * c.Sc[k] + GJ[3 * r + 1] * c.Sc[3 + k] + GJ[3 * r + 2] * c.Sc[6 + k]);
+                GJm[3 * r + k] = 2.0 * (GJ[3 * r] * c.Sc[k] + GJ[3 * r + 1] * c.Sc[3 + k] + GJ[3 * r + 2] * c.Sc[6 + k]);
         // dL/dSigma = R^T GSc R
-        const float* R = V.Rf;
-        float tmp[9], GSw[9];
+        const double* R = V.R;
+        double tmp[9], GSw[9];
 #pragma unroll
         for (int r = 0; r < 3; r++)
 #pragma unroll
@@ -503,82 +393,133 @@ __global__ __launch_bounds__(128) void k_project_bwd(const ViewDev* __restrict__
 #pragma unroll
             for (int k = 0; k < 3; k++) GSw[3 * r + k] = R[r] * tmp[k] + R[3 + r] * tmp[3 + k] + R[6 + r] * tmp[6 + k];
         // dL/dM = 2 GSw M ; dL/ds ; dL/dRq
-        float gs[3] = {0.0f, 0.0f, 0.0f}, GR[9];
+        double gs[3] = {0.0, 0.0, 0.0}, GR[9];
 #pragma unroll
         for (int r = 0; r < 3; r++)
 #pragma unroll
             for (int k = 0; k < 3; k++) {
-                const float gm = 2.0f * (GSw[3 * r] * w.M[k] + GSw[3 * r + 1] * w.M[3 + k] + GSw[3 * r + 2] * w.M[6 + k]);
+                const double gm = 2.0 * (GSw[3 * r] * w.M[k] + GSw[3 * r + 1] * w.M[3 + k] + GSw[3 * r + 2] * w.M[6 + k]);
                 gs[k] += gm * w.Rq[3 * r + k];
                 GR[3 * r + k] = gm * w.s[k];
             }
-        const float qa = w.qh[0], qx = w.qh[1], qy = w.qh[2], qz = w.qh[3];
-        float gq[4];
-        gq[0] = 2.0f * (-qz * GR[1] + qy * GR[2] + qz * GR[3] - qx * GR[5] - qy * GR[6] + qx * GR[7]);
-        gq[1] = 2.0f * (qy * GR[1] + qz * GR[2] + qy * GR[3] - 2.0f * qx * GR[4] - qa * GR[5] + qz * GR[6] + qa * GR[7]
-                       - 2.0f * qx * GR[8]);
-        gq[2] = 2.0f * (-2.0f * qy * GR[0] + qx * GR[1] + qa * GR[2] + qx * GR[3] + qz * GR[5] - qa * GR[6] + qz * GR[7]
-                       - 2.0f * qy * GR[8]);
-        gq[3] = 2.0f * (-2.0f * qz * GR[0] - qa * GR[1] + qx * GR[2] + qa * GR[3] - 2.0f * qz * GR[4] + qy * GR[5]
+        const double qa = w.qh[0], qx = w.qh[1], qy = w.qh[2], qz = w.qh[3];
+        double gq[4];
+        gq[0] = 2.0 * (-qz * GR[1] + qy * GR[2] + qz * GR[3] - qx * GR[5] - qy * GR[6] + qx * GR[7]);
+        gq[1] = 2.0 * (qy * GR[1] + qz * GR[2] + qy * GR[3] - 2.0 * qx * GR[4] - qa * GR[5] + qz * GR[6] + qa * GR[7]
+                       - 2.0 * qx * GR[8]);
+        gq[2] = 2.0 * (-2.0 * qy * GR[0] + qx * GR[1] + qa * GR[2] + qx * GR[3] + qz * GR[5] - qa * GR[6] + qz * GR[7]
+                       - 2.0 * qy * GR[8]);
+        gq[3] = 2.0 * (-2.0 * qz * GR[0] - qa * GR[1] + qx * GR[2] + qa * GR[3] - 2.0 * qz * GR[4] + qy * GR[5]
                        + qx * GR[6] + qy * GR[7]);
-        const float qd = gq[0] * qa + gq[1] * qx + gq[2] * qy + gq[3] * qz;
+        const double qd = gq[0] * qa + gq[1] * qx + gq[2] * qy + gq[3] * qz;
         // mean: dm/dmu_c = J, plus the dependence of J on mu_c
-        const float z2 = c.zc * c.zc, z3 = z2 * c.zc;
-        float gmc0 = c.J[0] * g9[0] + c.J[3] * g9[1];
-        float gmc1 = c.J[1] * g9[0] + c.J[4] * g9[1];
-        float gmc2 = c.J[2] * g9[0] + c.J[5] * g9[1];
-        gmc0 += GJm[2] * (-V.fxf / z2);
-        gmc1 += GJm[5] * (-V.fyf / z2);
-        gmc2 += GJm[0] * (-V.fxf / z2) + GJm[2] * (2.0f * V.fxf * c.xc / z3) + GJm[4] * (-V.fyf / z2)
-                + GJm[5] * (2.0f * V.fyf * c.yc / z3);
-        float gmu[3];
-#pragma unroll
-        for (int k = 0; k < 3; k++) gmu[k] = R[k] * gmc0 + R[3 + k] * gmc1 + R[6 + k] * gmc2;
-        // colour
-        float d[3], dn;
-        view_dir_f<L>(V, w, d, &dn);
-        float Y[NB];
-        sh_basis_f<L>(d[0], d[1], d[2], Y);
-        float gc[3];
-#pragma unroll
-        for (int ch = 0; ch < 3; ch++) {
-            float raw = 0.0f;
-#pragma unroll
-            for (int j = 0; j < NB; j++) raw += Y[j] * (float)sh[3 * j + ch];
-            raw += 0.5f;
-            gc[ch] = raw < 0.0f ? 0.0f : g9[6 + ch];   // clamped channel: no gradient
-        }
-        // SH coefficients: dL/dk[j][ch] = Y_j gc_ch; direction: sum_j (sum_ch k[j][ch] gc_ch) grad Y_j
-        float wj[NB];
-#pragma unroll
-        for (int j = 0; j < NB; j++) {
-#pragma unroll
-            for (int ch = 0; ch < 3; ch++) acc[11 + 3 * j + ch] += (float)(Y[j] * gc[ch]);
-            wj[j] = ((float)sh[3 * j] * gc[0] + (float)sh[3 * j + 1] * gc[1]) + (float)sh[3 * j + 2] * gc[2];
-        }
-        float gdv[3];
-        sh_grad_dot_f<L>(d[0], d[1], d[2], wj, gdv);
-        const float gd0 = gdv[0], gd1 = gdv[1], gd2 = gdv[2];
-        const float dd = gd0 * d[0] + gd1 * d[1] + gd2 * d[2];
-        gmu[0] += (gd0 - d[0] * dd) / dn;
-        gmu[1] += (gd1 - d[1] * dd) / dn;
-        gmu[2] += (gd2 - d[2] * dd) / dn;
+        const double z2 = c.zc * c.zc, z3 = z2 * c.zc;
+        double gmc0 = c.J[0] * g6[0] + c.J[3] * g6[1];
+        double gmc1 = c.J[1] * g6[0] + c.J[4] * g6[1];
+        double gmc2 = c.J[2] * g6[0] + c.J[5] * g6[1];
+        gmc0 += GJm[2] * (-V.fx / z2);
+        gmc1 += GJm[5] * (-V.fy / z2);
+        gmc2 += GJm[0] * (-V.fx / z2) + GJm[2] * (2.0 * V.fx * c.xc / z3) + GJm[4] * (-V.fy / z2)
+                + GJm[5] * (2.0 * V.fy * c.yc / z3);
 #pragma unroll
         for (int k = 0; k < 3; k++) {
-            acc[k] += (float)gmu[k];
-            acc[3 + k] += (float)(w.s[k] * gs[k]);
+            acc[k] += R[k] * gmc0 + R[3 + k] * gmc1 + R[6 + k] * gmc2;
+            acc[3 + k] += w.s[k] * gs[k];
         }
 #pragma unroll
-        for (int k = 0; k < 4; k++) acc[6 + k] += (float)((gq[k] - w.qh[k] * qd) / w.qn);
-        acc[10] += (float)(g9[5] * w.o * (1.0f - w.o));
+        for (int k = 0; k < 4; k++) acc[6 + k] += (gq[k] - w.qh[k] * qd) / w.qn;
+        acc[10] += g6[5] * w.o * (1.0 - w.o);
     }
     const int64_t texel = gauss_texel[i];
     const float m = dyn ? (dyn[texel] ? 1.f : 0.f) : 1.f;
     float* out = gatlas + (int64_t)f * C * HW + texel;
 #pragma unroll
-    for (int k = 0; k < 11 + 3 * NB; k++) {
-        if (accumulate) out[(int64_t)k * HW] += m * acc[k];
-        else out[(int64_t)k * HW] = m * acc[k];
+    for (int k = 0; k < 11; k++) {
+        if (accumulate) out[(int64_t)k * HW] += m * (float)acc[k];
+        else out[(int64_t)k * HW] = m * (float)acc[k];
+    }
+}
+
+// Colour part of the adjoint, FP32: SH coefficient gradients Y_j gc and the
+// view-direction term of the position gradient, added to what the geometric
+// kernel wrote.  The clamp decision (colour = max(0, 0.5 + sum Y k)) is taken
+// on the forward's own FP64 sum, so it is the forward's decision.
+template <int L>
+__global__ __launch_bounds__(128) void k_project_bwd_sh(const ViewDev* __restrict__ views,
+                                                        const int32_t* __restrict__ frame_views,
+                                                        const int32_t* __restrict__ view_order, int32_t F,
+                                                        int32_t C, int64_t N, int64_t n_gv,
+                                                        const float* __restrict__ params,
+                                                        const float* __restrict__ grad2d,
+                                                        const int32_t* __restrict__ gauss_texel,
+                                                        const uint8_t* __restrict__ dyn, int64_t HW,
+                                                        float* __restrict__ gatlas, int32_t accumulate) {
+    constexpr int NB = (L + 1) * (L + 1);
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= (int64_t)F * N) return;
+    const int32_t f = (int32_t)(g / N);
+    const int64_t i = g - (int64_t)f * N;
+    const int32_t v0 = frame_views[f], v1 = frame_views[f + 1];
+    const float* P = params + (int64_t)f * C * N + i;
+    World wpos;                      // only mu is used (view direction)
+    wpos.mu[0] = P[0];
+    wpos.mu[1] = P[N];
+    wpos.mu[2] = P[2 * N];
+    float sh[3 * NB];
+#pragma unroll
+    for (int k = 0; k < 3 * NB; k++) sh[k] = P[(int64_t)(11 + k) * N];
+    float acc[3 * NB], gmu[3] = {0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int k = 0; k < 3 * NB; k++) acc[k] = 0.0f;
+    for (int32_t vi = v0; vi < v1; vi++) {
+        const int32_t v = view_order[vi];
+        const int64_t gv = (int64_t)v * N + i;
+        float gcol[3];
+#pragma unroll
+        for (int ch = 0; ch < 3; ch++) gcol[ch] = grad2d[(int64_t)(6 + ch) * n_gv + gv];
+        if (gcol[0] == 0.0f && gcol[1] == 0.0f && gcol[2] == 0.0f) continue;
+        const ViewDev& V = views[v];
+        // the forward's colour sum, for the clamp decision
+        double dd64[3], dn64;
+        view_dir<L>(V, wpos, dd64, &dn64);
+        double Y64[NB];
+        sh_basis<L>(dd64[0], dd64[1], dd64[2], Y64);
+        float gc[3];
+#pragma unroll
+        for (int ch = 0; ch < 3; ch++) {
+            double raw = 0.0;
+#pragma unroll
+            for (int j = 0; j < NB; j++) raw += Y64[j] * (double)sh[3 * j + ch];
+            raw += 0.5;
+            gc[ch] = raw < 0.0 ? 0.0f : gcol[ch];   // clamped channel: no gradient
+        }
+        const float d[3] = {(float)dd64[0], (float)dd64[1], (float)dd64[2]};
+        const float dn = (float)dn64;
+        float Y[NB];
+        sh_basis_f<L>(d[0], d[1], d[2], Y);
+        // SH coefficients: dL/dk[j][ch] = Y_j gc_ch; direction: sum_j (sum_ch k[j][ch] gc_ch) grad Y_j
+        float wj[NB];
+#pragma unroll
+        for (int j = 0; j < NB; j++) {
+#pragma unroll
+            for (int ch = 0; ch < 3; ch++) acc[3 * j + ch] += Y[j] * gc[ch];
+            wj[j] = (sh[3 * j] * gc[0] + sh[3 * j + 1] * gc[1]) + sh[3 * j + 2] * gc[2];
+        }
+        float gd[3];
+        sh_grad_dot_f<L>(d[0], d[1], d[2], wj, gd);
+        const float dd = gd[0] * d[0] + gd[1] * d[1] + gd[2] * d[2];
+#pragma unroll
+        for (int k = 0; k < 3; k++) gmu[k] += (gd[k] - d[k] * dd) / dn;
+    }
+    const int64_t texel = gauss_texel[i];
+    const float m = dyn ? (dyn[texel] ? 1.f : 0.f) : 1.f;
+    float* out = gatlas + (int64_t)f * C * HW + texel;
+#pragma unroll
+    for (int k = 0; k < 3; k++) out[(int64_t)k * HW] += m * gmu[k];   // after the geometric kernel
+#pragma unroll
+    for (int k = 0; k < 3 * NB; k++) {
+        if (accumulate) out[(int64_t)(11 + k) * HW] += m * acc[k];
+        else out[(int64_t)(11 + k) * HW] = m * acc[k];
     }
 }
 
@@ -682,15 +623,18 @@ hipError_t launch_project_bwd(const pg_views* v, const float* params, const floa
     const int64_t n = (int64_t)v->frames * v->n_gauss;
     if (n == 0) return hipGetLastError();
     const unsigned grid = (unsigned)ceil_div(n, 128);
+    k_project_bwd_geo<<<grid, 128, 0, s>>>(v->d_views, v->d_frame_views, v->d_view_order, v->frames, v->channels,
+                                           v->n_gauss, v->n_gv, params, grad2d, gauss_texel, dyn, HW, dL_datlas,
+                                           accumulate);
     auto args = [&](auto kern) {
         kern<<<grid, 128, 0, s>>>(v->d_views, v->d_frame_views, v->d_view_order, v->frames, v->channels, v->n_gauss,
                                   v->n_gv, params, grad2d, gauss_texel, dyn, HW, dL_datlas, accumulate);
     };
     switch (v->sh_degree) {
-        case 0: args(k_project_bwd<0>); break;
-        case 1: args(k_project_bwd<1>); break;
-        case 2: args(k_project_bwd<2>); break;
-        default: args(k_project_bwd<3>); break;
+        case 0: args(k_project_bwd_sh<0>); break;
+        case 1: args(k_project_bwd_sh<1>); break;
+        case 2: args(k_project_bwd_sh<2>); break;
+        default: args(k_project_bwd_sh<3>); break;
     }
     return hipGetLastError();
 }

@@ -5,9 +5,10 @@ Comparison rules:
   * discrete outputs (Gaussian ids, culls, tile rectangles, depth keys, sorted
     instance lists, tile ranges) must be bit-identical;
   * projected floats within 1e-6 relative of the FP64 oracle;
-  * images within 1e-4 absolute per pixel, except pixels "explained" by
-    taking at most two of the oracle's near-threshold decisions (relative
-    margin below 1e-4 of q = 9, alpha = 1/255 or T = 1e-4) the other way;
+  * images and final transmittance within 1e-4 absolute per pixel, except
+    pixels "explained" by taking at most two of the oracle's near-threshold
+    decisions (relative margin below 1e-4 of q = 9, alpha = 1/255 or
+    T = 1e-4) the other way;
   * gradients within 1e-3 relative per element with a floor of 1% of the
     channel's largest magnitude, and 1e-3 relative L2 error per channel, both
     sides using the same cotangent.
@@ -65,10 +66,16 @@ def gpu_images(r):
     return out
 
 
-def explain(fw, v, gpu_img, tol=IMG_TOL, band=BAND, max_pixels=20000):
-    """Returns (flips {pixel: positions}, unexplained [(x, y, err)], n_bad)."""
+def explain(fw, v, gpu_img, gpu_T=None, tol=IMG_TOL, band=BAND, max_pixels=20000):
+    """Returns (flips {pixel: positions}, unexplained [(x, y, err)], n_bad).
+    A pixel is off when its colour (or, if gpu_T is given, its final
+    transmittance) differs from the oracle's by more than tol; it is
+    explained when taking at most two of the oracle's near-threshold
+    decisions the other way brings every compared value within tol."""
     cam = fw.scene.cams[v]
     err = np.abs(gpu_img - fw.image[v]).max(0)
+    if gpu_T is not None:
+        err = np.maximum(err, np.abs(gpu_T - fw.T[v]))
     ys, xs = np.nonzero(err > tol)
     flips, unexplained = {}, []
     for x, y in list(zip(xs, ys))[:max_pixels]:
@@ -77,9 +84,9 @@ def explain(fw, v, gpu_img, tol=IMG_TOL, band=BAND, max_pixels=20000):
         found = None
         cands = [[k] for k in near] + [list(p) for p in itertools.combinations(near, 2)]
         for fl in cands:
-            rgb, _, _, _ = oracle.pixel(fw.proj[v], cam, fw.tw, fw.th, fw.inst[v], fw.ranges[v], x, y, flips=fl,
+            rgb, T, _, _ = oracle.pixel(fw.proj[v], cam, fw.tw, fw.th, fw.inst[v], fw.ranges[v], x, y, flips=fl,
                                         band=band, bg=fw.bg)
-            if np.abs(rgb - gpu_img[:, y, x]).max() <= tol:
+            if np.abs(rgb - gpu_img[:, y, x]).max() <= tol and (gpu_T is None or abs(T - gpu_T[y, x]) <= tol):
                 found = fl
                 break
         if found is None:
@@ -95,6 +102,7 @@ def grad_compare(g, ref, mask=None, rel=1e-3, floor_frac=0.01):
     ref = np.asarray(ref, np.float64)
     C = g.shape[-2]
     worst_el, worst_l2, bad = 0.0, 0.0, 0
+    bad_channels = {}
     for c in range(C):
         a = g[..., c, :].reshape(-1)
         b = ref[..., c, :].reshape(-1)
@@ -107,7 +115,14 @@ def grad_compare(g, ref, mask=None, rel=1e-3, floor_frac=0.01):
         den = np.maximum(np.abs(b), floor_frac * mx)
         r = np.abs(a - b) / den
         worst_el = max(worst_el, float(r.max()))
-        bad += int((r > rel).sum())
+        nb = int((r > rel).sum())
+        bad += nb
+        if nb:
+            i = int(np.argmax(r))
+            bad_channels[c] = (nb, float(r[i]), float(a[i]), float(b[i]), float(mx))
         l2 = np.linalg.norm(a - b) / np.linalg.norm(b)
         worst_l2 = max(worst_l2, float(l2))
-    return {"worst_elem": worst_el, "worst_l2": worst_l2, "n_bad": bad}
+    out = {"worst_elem": worst_el, "worst_l2": worst_l2, "n_bad": bad}
+    if bad_channels:
+        out["bad_channels"] = bad_channels   # channel: (count, worst ratio, got, ref, channel max)
+    return out

@@ -103,7 +103,7 @@ def test_render_forward_parity(name):
     total_bad = total_unexp = 0
     for v in range(len(sc.cams)):
         gi, gT, gn = imgs[v]
-        flips, unexp, nbad = explain(fw, v, gi)
+        flips, unexp, nbad = explain(fw, v, gi, gT)
         total_bad += nbad
         total_unexp += len(unexp)
         ok = np.ones(gn.shape, bool)
@@ -132,7 +132,7 @@ def test_backward_parity(name):
     imgs = gpu_images(r)
     flips = {}
     for v in range(len(sc.cams)):
-        fl, unexp, _ = explain(fw, v, imgs[v][0])
+        fl, unexp, _ = explain(fw, v, imgs[v][0], imgs[v][1])
         assert not unexp
         if fl:
             flips[v] = fl
