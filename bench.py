@@ -62,6 +62,10 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--also-configs", type=str, default="",
+                    help="comma-separated workload numbers (2, 4, 5) whose batched and plain steps are also timed "
+                         "and reported under 'other_configs' (off by default: config 4 and 5 scenes take a minute "
+                         "to build)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB three times (a reference of known "
                          "size for the HBM traffic counters) and exit")
@@ -255,8 +259,95 @@ def main():
         "cpu_baseline": cpu,
         "autotune": tune_info,
     }
-    print(json.dumps(out), flush=True)
     rb.close()
+    if args.also_configs:
+        del rp, rb
+        torch.cuda.empty_cache()
+        out["other_configs"] = [other_config(int(c), tiling, max(2, args.steps // 4), 2)
+                                for c in args.also_configs.split(",") if c.strip()]
+    print(json.dumps(out), flush=True)
+
+
+def other_config(cfg, tiling, steps, warmup):
+    """Batched (graph) and plain step time of another workload: fetch,
+    projection, bin/sort, compositing, L1 against a second seeded Gaussian
+    set, adjoint, and for the 2048^2 workload the sparse Adam update."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2602_23040_amd.pipeline import Renderer
+
+    dev = torch.device("cuda:0")
+    sc = synth.make_scene(cfg)
+    tgt_sc = synth.make_scene(cfg, target=True)
+    adam = cfg == 5
+    atlas = torch.from_numpy(np.ascontiguousarray(sc.atlas).reshape(-1)).to(dev)
+    tgt_atlas = torch.from_numpy(np.ascontiguousarray(tgt_sc.atlas).reshape(-1)).to(dev)
+    del tgt_sc
+    V, N = len(sc.cams), sc.n_gauss
+
+    def make(batched, source, cap=None):
+        r = Renderer(sc.occupancy, sc.frames, sc.sh_degree, sc.cams, tiling=tiling, batched=batched, bg=sc.bg,
+                     dynamic=sc.dynamic, inst_capacity=cap, device=dev)
+        r.forward(source)
+        torch.cuda.synchronize()
+        if r.overflowed():
+            r.grow_capacity(1.3)     # headroom: Adam moves the Gaussians between steps
+        return r
+
+    rt = make(True, tgt_atlas, 2 * N * V)
+    rt.forward(tgt_atlas)
+    torch.cuda.synchronize()
+    target = rt.image.clone()
+    rt.close()
+    del rt, tgt_atlas
+    torch.cuda.empty_cache()
+    rb = make(True, atlas, 2 * N * V)
+    work = atlas.clone()
+    stream = torch.cuda.current_stream()
+    side = torch.cuda.Stream()
+    side.wait_stream(stream)
+    with torch.cuda.stream(side):
+        rb.step(work, target, adam=adam)
+    stream.wait_stream(side)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        rb.step(work, target, adam=adam)
+    torch.cuda.synchronize()
+    for _ in range(warmup):
+        graph.replay()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        graph.replay()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    assert not rb.overflowed(), f"config {cfg}: instance capacity overflowed inside the timed region"
+    n_inst = int(rb.sets[0].n_inst.item())
+    P = rb.n_pixels
+    rb.close()
+    del rb, graph
+    torch.cuda.empty_cache()
+    rp = make(False, atlas)
+    work = atlas.clone()
+    rp.step(work, target, adam=adam)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(2):
+        rp.step(work, target, adam=adam)
+    torch.cuda.synchronize()
+    ms_plain = (time.perf_counter() - t0) * 1e3 / 2
+    rp.close()
+    del rp
+    torch.cuda.empty_cache()
+    return {"config": cfg, "workload": sc.name, "views": V, "frames": sc.frames, "gaussians": N, "pixels": P,
+            "instances": n_inst, "adam": adam, "steps": steps, "ms_per_step": round(ms, 3),
+            "mpixels_per_s": round(P / ms / 1e3, 2), "gaussians_per_s": round(N * V / ms * 1e3, 1),
+            "plain_ms_per_step": round(ms_plain, 3), "speedup_vs_plain": round(ms_plain / ms, 3)}
 
 
 def stage_times(r, atlas, target, reps=5):

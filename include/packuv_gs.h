@@ -268,10 +268,15 @@ pg_status pg_loss_l1(const float* image, const float* target, int64_t n, float* 
  * weights, Sparse Adam).  Textbook Adam with bias correction at `step` >= 1,
  * applied to channels of texels whose Gaussian is visible (visible[f N + i]);
  * other texels and their moments are left untouched.
- *   atlas, m, v  device float [F][C][H][W] in/out;  grad same layout */
+ *   atlas, m, v  device float [F][C][H][W] in/out;  grad same layout
+ *   step         the step number (>= 1) for bias correction, or ignored when
+ *   step_dev     (device int32 [1], may be NULL) is given: the call then adds
+ *                1 to *step_dev on the device and uses the new value, so the
+ *                replays of a captured step count their steps */
 pg_status pg_adam_step(float* atlas, const float* grad, float* m, float* v, const uint8_t* visible,
                        const int32_t* texel_gauss, int64_t n_gauss, int32_t frames, int32_t channels, int32_t H,
-                       int32_t W, float lr, float beta1, float beta2, float eps, int32_t step, void* stream);
+                       int32_t W, float lr, float beta1, float beta2, float eps, int32_t step, int32_t* step_dev,
+                       void* stream);
 
 #ifdef __cplusplus
 }

@@ -65,7 +65,8 @@ SIGNATURES = {
     "pg_render_bwd": (_i32, [_p, _p, _p, _p, _p, _p, _p, _i64, _p, _p, _p, _p, _p, _p, _p, _p]),
     "pg_project_bwd": (_i32, [_p, _p, _p, _p, _p, _i64, _p, _p, _p, _i32, _i32, _p, _p, _i32, _p]),
     "pg_loss_l1": (_i32, [_p, _p, _i64, _p, _p, _p, _p]),
-    "pg_adam_step": (_i32, [_p, _p, _p, _p, _p, _p, _i64, _i32, _i32, _i32, _i32, _f32, _f32, _f32, _f32, _i32, _p]),
+    "pg_adam_step": (_i32, [_p, _p, _p, _p, _p, _p, _i64, _i32, _i32, _i32, _i32, _f32, _f32, _f32, _f32, _i32, _p,
+                            _p]),
 }
 
 
@@ -229,7 +230,7 @@ def pg_loss_l1(image, target, n, dL_dimage, partial, loss_dev, stream=None):
 
 
 def pg_adam_step(atlas, grad, m, v, visible, texel_gauss, n_gauss, frames, channels, H, W, lr, beta1, beta2, eps,
-                 step, stream=None):
+                 step, step_dev=None, stream=None):
     _check(lib().pg_adam_step(_ptr(atlas), _ptr(grad), _ptr(m), _ptr(v), _ptr(visible), _ptr(texel_gauss),
                               int(n_gauss), int(frames), int(channels), int(H), int(W), float(lr), float(beta1),
-                              float(beta2), float(eps), int(step), _stream(stream)), "pg_adam_step")
+                              float(beta2), float(eps), int(step), _ptr(step_dev), _stream(stream)), "pg_adam_step")

@@ -330,15 +330,16 @@ pg_status pg_loss_l1(const float* image, const float* target, int64_t n, float* 
 
 pg_status pg_adam_step(float* atlas, const float* grad, float* m, float* v, const uint8_t* visible,
                        const int32_t* texel_gauss, int64_t n_gauss, int32_t frames, int32_t channels, int32_t H,
-                       int32_t W, float lr, float beta1, float beta2, float eps, int32_t step, void* stream) {
+                       int32_t W, float lr, float beta1, float beta2, float eps, int32_t step, int32_t* step_dev,
+                       void* stream) {
     g_error.clear();
     if (!atlas || !grad || !m || !v || !visible || !texel_gauss) return invalid("null pointer argument");
     if (frames < 1 || channels < 1 || H < 1 || W < 1 || n_gauss < 0) return invalid("bad sizes");
-    if (step < 1) return invalid("step must be >= 1");
+    if (!step_dev && step < 1) return invalid("step must be >= 1");
     if (!(beta1 >= 0.0f && beta1 < 1.0f) || !(beta2 >= 0.0f && beta2 < 1.0f) || !(eps > 0.0f))
         return invalid("need 0 <= beta < 1 and eps > 0");
     PG_CHECK_HIP(launch_adam(atlas, grad, m, v, visible, texel_gauss, n_gauss, frames, channels, H, W, lr, beta1,
-                             beta2, eps, step, (hipStream_t)stream),
+                             beta2, eps, step, step_dev, (hipStream_t)stream),
                  "pg_adam_step");
     return PG_OK;
 }

@@ -71,6 +71,7 @@ struct SortWs {
     uint32_t* rk1;
     int32_t* rv0;
     int32_t* rv1;
+    uint4* sbins;            // the records' bins gathered in depth order (read by the emission)
     uint32_t* tk_alt;        // tile sort ping-pong partner of the caller's arrays
     int32_t* tv_alt;
     int32_t* counts;
@@ -104,6 +105,7 @@ SortWs carve(const pg_views* v, int64_t cap, void* ws, size_t* total) {
     w.rk1 = (uint32_t*)take(ngv * 4);
     w.rv0 = (int32_t*)take(ngv * 4);
     w.rv1 = (int32_t*)take(ngv * 4);
+    w.sbins = (uint4*)take(ngv * 16);
     w.tk_alt = (uint32_t*)take(imax(cap, 1) * 4);
     w.tv_alt = (int32_t*)take(imax(cap, 1) * 4);
     w.counts = (int32_t*)take(cnt * 4);
@@ -191,10 +193,16 @@ __global__ __launch_bounds__(kBlk) void k_compact(const pg_bin* __restrict__ bin
 
 __global__ __launch_bounds__(kBlk) void k_sorted_count(const pg_bin* __restrict__ bins,
                                                        const int32_t* __restrict__ rv,
-                                                       const int64_t* __restrict__ misc, int64_t* __restrict__ blk) {
+                                                       const int64_t* __restrict__ misc, int64_t* __restrict__ blk,
+                                                       uint4* __restrict__ sbins) {
     __shared__ int64_t s[kBlk / 64];
     const int64_t p = (int64_t)blockIdx.x * kBlk + threadIdx.x;
-    const int64_t c = p < misc[0] ? (int64_t)bins[rv[p]].n_tiles : 0;
+    int64_t c = 0;
+    if (p < misc[0]) {
+        const uint4 b = reinterpret_cast<const uint4*>(bins)[rv[p]];
+        sbins[p] = b;
+        c = (int64_t)b.w;
+    }
     const int64_t t = block_sum_1024(c, s);
     if (threadIdx.x == 0) blk[blockIdx.x] = t;
 }
@@ -215,7 +223,7 @@ __global__ void k_depth_counts_len(int64_t* misc, int d_digit) { misc[2] = ceil_
 // group's prefix sums.  Per record the group keeps, in LDS, the global tile
 // id of the rectangle's first tile, the rectangle width and the row stride of
 // the view's tile grid, so an instance costs one small division.
-__global__ __launch_bounds__(kBlk) void k_emit(const pg_bin* __restrict__ bins, const int32_t* __restrict__ rv,
+__global__ __launch_bounds__(kBlk) void k_emit(const uint4* __restrict__ sbins, const int32_t* __restrict__ rv,
                                                int64_t N, const ViewDev* __restrict__ views,
                                                const int64_t* __restrict__ blk_off, const int64_t* __restrict__ misc,
                                                uint32_t* __restrict__ tkeys, int32_t* __restrict__ tvals) {
@@ -232,7 +240,7 @@ __global__ __launch_bounds__(kBlk) void k_emit(const pg_bin* __restrict__ bins, 
     int32_t nt = 0;
     if (p < misc[0]) {
         const int32_t gv = rv[p];
-        const uint4 b = reinterpret_cast<const uint4*>(bins)[gv];
+        const uint4 b = sbins[p];
         nt = (int32_t)b.w;
         const int32_t xlo = (int32_t)(b.x & 0xffff), ylo = (int32_t)(b.x >> 16);
         const int32_t xhi = (int32_t)(b.y & 0xffff);
@@ -296,11 +304,7 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_upsweep(const K* __restr
 #pragma unroll 4
         for (int r = 0; r < kSortItems; r++) {
             const int64_t idx = start + r * 64 + lane;
-            const bool active = idx < n;
-            const uint32_t d = active ? (uint32_t)((keys[idx] >> shift) & (NB - 1)) : 0u;
-            const uint64_t peers = match_digit<BITS>(d, active);
-            const uint64_t below = peers & ((1ull << lane) - 1ull);
-            if (active && below == 0) atomicAdd(&s_cnt[d], (uint32_t)__popcll(peers));
+            if (idx < n) atomicAdd(&s_cnt[(uint32_t)((keys[idx] >> shift) & (NB - 1))], 1u);   // counts only: order-free
         }
         __syncthreads();
         for (int d = threadIdx.x; d < NB; d += kSortThreads) counts[(int64_t)d * ntile + b] = (int32_t)s_cnt[d];
@@ -495,7 +499,7 @@ hipError_t launch_bin_sort(const pg_views* v, const pg_bin* bins, int64_t cap, u
         int32_t* tv = rva; rva = rvb; rvb = tv;
     }
     // 3. instance offsets in sorted-record order; overflow check
-    k_sorted_count<<<(unsigned)nb, kBlk, 0, s>>>(bins, rva, w.misc, w.blk_a);
+    k_sorted_count<<<(unsigned)nb, kBlk, 0, s>>>(bins, rva, w.misc, w.blk_a, w.sbins);
     e = scan_i64(w.blk_a, w.blk_a_off, nullptr, 0, nb, n_inst_dev, w.scan_tmp, s);
     if (e != hipSuccess) return e;
     k_post_count<<<1, 1, 0, s>>>(n_inst_dev, cap, overflow_dev, w.misc, pl.t_digit);
@@ -504,7 +508,7 @@ hipError_t launch_bin_sort(const pg_views* v, const pg_bin* bins, int64_t cap, u
     int32_t* tva = (pl.t_passes % 2 == 0) ? values : w.tv_alt;
     uint32_t* tb = (pl.t_passes % 2 == 0) ? w.tk_alt : keys;
     int32_t* tvb = (pl.t_passes % 2 == 0) ? w.tv_alt : values;
-    k_emit<<<(unsigned)nb, kBlk, 0, s>>>(bins, rva, v->n_gauss, v->d_views, w.blk_a_off, w.misc, ta, tva);
+    k_emit<<<(unsigned)nb, kBlk, 0, s>>>(w.sbins, rva, v->n_gauss, v->d_views, w.blk_a_off, w.misc, ta, tva);
     // 5. stable LSD sort of the instances by tile id
     const unsigned grid_i = (unsigned)imax(1, imin(kSortGrid, ceil_div(cap, kSortTile)));
     for (int p = 0; p < pl.t_passes; p++) {

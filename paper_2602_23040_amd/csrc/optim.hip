@@ -51,7 +51,12 @@ __global__ __launch_bounds__(256) void k_adam(float* __restrict__ p, const float
                                               const uint8_t* __restrict__ visible,
                                               const int32_t* __restrict__ texel_gauss, int64_t N, int32_t C,
                                               int64_t HW, int64_t total, float lr, float b1, float b2, float eps,
-                                              float inv_c1, float inv_c2) {
+                                              float inv_c1, float inv_c2, const int32_t* __restrict__ step_dev) {
+    if (step_dev) {   // bias correction of the device-counted step
+        const double t = (double)*step_dev;
+        inv_c1 = (float)(1.0 / (1.0 - pow((double)b1, t)));
+        inv_c2 = (float)(1.0 / (1.0 - pow((double)b2, t)));
+    }
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
          e += (int64_t)gridDim.x * blockDim.x) {
         const int64_t texel = e % HW;
@@ -67,6 +72,8 @@ __global__ __launch_bounds__(256) void k_adam(float* __restrict__ p, const float
     }
 }
 
+__global__ void k_step_inc(int32_t* step) { *step += 1; }
+
 }  // namespace
 
 hipError_t launch_loss_l1(const float* img, const float* tgt, int64_t n, float* g, double* partial, float* loss,
@@ -78,14 +85,16 @@ hipError_t launch_loss_l1(const float* img, const float* tgt, int64_t n, float* 
 
 hipError_t launch_adam(float* atlas, const float* grad, float* m, float* v, const uint8_t* visible,
                        const int32_t* texel_gauss, int64_t n_gauss, int32_t F, int32_t C, int32_t H, int32_t W,
-                       float lr, float b1, float b2, float eps, int32_t step, hipStream_t s) {
+                       float lr, float b1, float b2, float eps, int32_t step, int32_t* step_dev, hipStream_t s) {
     const int64_t HW = (int64_t)H * W;
     const int64_t total = (int64_t)F * C * HW;
-    if (total == 0) return hipSuccess;
-    const double c1 = 1.0 - pow((double)b1, (double)step), c2 = 1.0 - pow((double)b2, (double)step);
+    if (step_dev) k_step_inc<<<1, 1, 0, s>>>(step_dev);
+    if (total == 0) return hipGetLastError();
+    const double c1 = step_dev ? 1.0 : 1.0 - pow((double)b1, (double)step);
+    const double c2 = step_dev ? 1.0 : 1.0 - pow((double)b2, (double)step);
     const unsigned grid = (unsigned)imin(ceil_div(total, 256), 8192);
     k_adam<<<grid, 256, 0, s>>>(atlas, grad, m, v, visible, texel_gauss, n_gauss, C, HW, total, lr, b1, b2, eps,
-                                (float)(1.0 / c1), (float)(1.0 / c2));
+                                (float)(1.0 / c1), (float)(1.0 / c2), step_dev);
     return hipGetLastError();
 }
 

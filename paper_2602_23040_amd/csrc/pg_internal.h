@@ -108,7 +108,7 @@ hipError_t launch_loss_l1(const float* img, const float* tgt, int64_t n, float* 
                           hipStream_t s);
 hipError_t launch_adam(float* atlas, const float* grad, float* m, float* v, const uint8_t* visible,
                        const int32_t* texel_gauss, int64_t n_gauss, int32_t F, int32_t C, int32_t H, int32_t W,
-                       float lr, float b1, float b2, float eps, int32_t step, hipStream_t s);
+                       float lr, float b1, float b2, float eps, int32_t step, int32_t* step_dev, hipStream_t s);
 
 // ---- device helpers
 

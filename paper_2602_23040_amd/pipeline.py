@@ -126,7 +126,7 @@ class Renderer:
         self.counters = torch.zeros(2, dtype=torch.int64, device=dev)
         self.adam_m = None
         self.adam_v = None
-        self.adam_t = 0
+        self.adam_t = None           # device step counter of the Adam update
 
     # ------------------------------------------------------------------ helpers
     def close(self):
@@ -222,12 +222,14 @@ class Renderer:
         return self.dL_datlas
 
     def adam_step(self, atlas: torch.Tensor, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
+        """Sparse Adam on `atlas` in place; the step count lives on the device, so
+        replays of a captured step keep counting."""
         if self.adam_m is None:
             self.adam_m = torch.zeros_like(atlas)
             self.adam_v = torch.zeros_like(atlas)
-        self.adam_t += 1
+            self.adam_t = torch.zeros(1, dtype=torch.int32, device=self.device)
         abi.pg_adam_step(atlas, self.dL_datlas, self.adam_m, self.adam_v, self.visible, self.texel_gauss, self.N,
-                         self.frames, self.C, self.H, self.W, lr, b1, b2, eps, self.adam_t)
+                         self.frames, self.C, self.H, self.W, lr, b1, b2, eps, 0, self.adam_t)
 
     def step(self, atlas, target, adam=False):
         """One fitting step: forward, L1 loss, adjoint (and Adam)."""

@@ -70,7 +70,7 @@ def test_entry_points_reject_null_pointers():
     lib = abi.lib()
     assert lib.pg_loss_l1(None, None, 10, None, None, None, None) == -1
     assert "null" in abi.pg_last_error()
-    assert lib.pg_adam_step(None, None, None, None, None, None, 1, 1, 1, 1, 1, 0.1, 0.9, 0.99, 1e-8, 1, None) == -1
+    assert lib.pg_adam_step(None, None, None, None, None, None, 1, 1, 1, 1, 1, 0.1, 0.9, 0.99, 1e-8, 1, None, None) == -1
     n = C.c_size_t()
     assert lib.pg_fetch_workspace_size(0, 5, C.byref(n)) == -1
     assert lib.pg_fetch_workspace_size(64, 64, C.byref(n)) == 0 and n.value > 0

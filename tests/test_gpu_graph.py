@@ -48,3 +48,47 @@ def test_graph_replays_match_eager():
         assert torch.equal(r.dL_datlas, ref_g), f"replay {rep}: gradient differs"
     assert not r.overflowed()
     r.close()
+
+
+def test_graph_replays_with_adam_count_steps():
+    """A captured step that ends with the Adam update: replays advance the
+    device step counter, so k replays equal k eager steps bitwise (atlas,
+    moments, counter)."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    sc = synth.random_scene(side=14, sh_degree=2, views=3, width=80, height=60, seed=9, lscale=(-2.9, 0.5))
+    tgt = torch.rand(3 * sum(c.width * c.height for c in sc.cams), device="cuda:0",
+                     generator=torch.Generator("cuda:0").manual_seed(2))
+    # eager reference: three steps
+    re = renderer(sc)
+    a_eager = atlas_tensor(sc)
+    run_forward(re, a_eager)
+    re.grow_capacity(2.0)
+    for _ in range(3):
+        re.step(a_eager, tgt, adam=True)
+    torch.cuda.synchronize()
+    assert not re.overflowed()
+    # captured: warm-up step on a side stream, capture, then two replays
+    rg = renderer(sc)
+    a_graph = atlas_tensor(sc)
+    run_forward(rg, a_graph)
+    rg.grow_capacity(2.0)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        rg.step(a_graph, tgt, adam=True)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):        # capture records the step without running it
+        rg.step(a_graph, tgt, adam=True)
+    for rep in range(2):
+        say(f"[gpu] adam graph replay {rep}")
+        g.replay()
+        torch.cuda.synchronize()
+    assert not rg.overflowed()
+    assert int(rg.adam_t.item()) == int(re.adam_t.item()) == 3
+    assert torch.equal(rg.adam_m, re.adam_m) and torch.equal(rg.adam_v, re.adam_v)
+    assert torch.equal(a_graph, a_eager)
+    re.close()
+    rg.close()
