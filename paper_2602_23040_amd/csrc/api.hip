@@ -151,7 +151,7 @@ pg_status pg_views_create(const pg_camera* cams, int32_t n_views, int32_t frames
     p->n_tiles = tiles;
     p->n_pixels = pixels;
     p->key_bits = tile_bits;
-    p->sort_passes = (32 + 9) / 10 + (tile_bits + 9) / 10;   // record (depth) passes + instance (tile) passes
+    p->sort_passes = (32 + 7) / 8 + (tile_bits + 7) / 8;   // record (depth) passes + instance (tile) passes
     p->h_tile_base = new int64_t[n_views + 1];
     p->h_pix_base = new int64_t[n_views + 1];
     std::memcpy(p->h_tile_base, tb.data(), sizeof(int64_t) * (n_views + 1));

@@ -27,11 +27,13 @@
 //                               work-group-cooperative emission (coalesced writes)
 //   radix passes (32-bit keys)  tile ids
 //   k_ranges                    [start, end) of every tile
-// Radix passes: per-tile digit histograms (upsweep), a scan of the histograms,
-// then a downsweep that ranks keys with a wave-level multisplit (one ballot per
-// digit bit) and scatters through LDS so each digit's run is written
-// contiguously.  Counts that only the device knows are read from device
-// memory, so the chain needs no host synchronisation.
+// Radix passes: per-tile digit histograms (upsweep, LDS atomics), a scan of
+// the histograms into per-tile digit offsets, then a downsweep that ranks keys
+// with a wave-level multisplit (one ballot per digit bit) and scatters through
+// LDS so each digit's run is written contiguously.  Histograms and offsets are
+// stored tile-major ([tile][digit], coalesced for both kernels) and scanned in
+// two levels over chunks of 64 tiles.  Counts that only the device knows are
+// read from device memory, so the chain needs no host synchronisation.
 #include "pg_internal.h"
 
 namespace pg {
@@ -40,7 +42,7 @@ namespace {
 
 constexpr int kBlk = 1024;           // records per compaction / emission work-group
 constexpr int kSortGrid = 2048;      // persistent grid of the radix kernels (grid-stride over tiles)
-constexpr int kMaxDigitBits = 10;    // digit width cap of both sorts (32-bit keys)
+constexpr int kMaxDigitBits = 8;     // digit width cap of both sorts: wider digits rank and scatter slower
 
 struct SortPlan {
     int d_bits, d_passes;            // depth sort: key bits, digit width, passes
@@ -65,8 +67,7 @@ struct SortWs {
     int64_t* blk_b;          // per-block tile sums in (view, id) order (slot offsets)
     int64_t* blk_b_off;
     int64_t* scan_tmp;
-    int64_t* misc;           // [0] valid records, [1] instances to sort (0 on overflow),
-                             // [2] depth-sort counts length, [3] tile-sort counts length
+    int64_t* misc;           // [0] valid records, [1] instances to sort (0 on overflow), [4] instances (slot scan)
     uint32_t* rk0;           // record sort ping-pong
     uint32_t* rk1;
     int32_t* rv0;
@@ -74,11 +75,21 @@ struct SortWs {
     uint4* sbins;            // the records' bins gathered in depth order (read by the emission)
     uint32_t* tk_alt;        // tile sort ping-pong partner of the caller's arrays
     int32_t* tv_alt;
-    int32_t* counts;
-    int32_t* count_offs;
+    int32_t* counts;         // per radix tile, its digit counts (tile-major: [tile][digit])
+    int32_t* count_offs;     // per radix tile, the output offset of each digit (same layout)
+    int32_t* chunk_dm;       // digit-major [digit][chunk] sums of kChunkTiles tiles, and their exclusive scan
+    int32_t* chunk_off;
 };
 
 int64_t n_blocks(const pg_views* v) { return imax(ceil_div(v->n_gv, kBlk), 1); }
+
+constexpr int kChunkTiles = 64;   // radix tiles per chunk of the two-level offset scan
+
+// Radix tiles (and chunks of them) either sort can have at most.
+int64_t tiles_max(const pg_views* v, int64_t cap) {
+    return imax(imax(ceil_div(imax(v->n_gv, 1), kSortTile), ceil_div(imax(cap, 1), kSortTile)), 1);
+}
+int64_t chunks_max(const pg_views* v, int64_t cap) { return ceil_div(tiles_max(v, cap), kChunkTiles); }
 
 SortWs carve(const pg_views* v, int64_t cap, void* ws, size_t* total) {
     const SortPlan pl = plan_for(v);
@@ -88,6 +99,8 @@ SortWs carve(const pg_views* v, int64_t cap, void* ws, size_t* total) {
     const int64_t cnt_d = ((int64_t)1 << pl.d_digit) * imax(ceil_div(ngv, kSortTile), 1);
     const int64_t cnt_t = ((int64_t)1 << pl.t_digit) * imax(ceil_div(imax(cap, 1), kSortTile), 1);
     const int64_t cnt = imax(cnt_d, cnt_t);
+    const int64_t nch = chunks_max(v, cap);
+    const int64_t ch = ((int64_t)1 << imax(pl.d_digit, pl.t_digit)) * nch;
     char* p = (char*)ws;
     size_t off = 0;
     auto take = [&](size_t bytes) {
@@ -110,6 +123,8 @@ SortWs carve(const pg_views* v, int64_t cap, void* ws, size_t* total) {
     w.tv_alt = (int32_t*)take(imax(cap, 1) * 4);
     w.counts = (int32_t*)take(cnt * 4);
     w.count_offs = (int32_t*)take(cnt * 4);
+    w.chunk_dm = (int32_t*)take(ch * 4);
+    w.chunk_off = (int32_t*)take(ch * 4);
     if (total) *total = off;
     return w;
 }
@@ -207,16 +222,14 @@ __global__ __launch_bounds__(kBlk) void k_sorted_count(const pg_bin* __restrict_
     if (threadIdx.x == 0) blk[blockIdx.x] = t;
 }
 
-__global__ void k_post_count(const int64_t* n_inst, int64_t cap, int32_t* overflow, int64_t* misc, int t_digit) {
+__global__ void k_post_count(const int64_t* n_inst, int64_t cap, int32_t* overflow, int64_t* misc) {
     const int64_t I = *n_inst;
     const bool of = I > cap;
     *overflow = of ? 1 : 0;
     const int64_t eff = of ? 0 : I;
     misc[1] = eff;
-    misc[3] = ceil_div(eff, kSortTile) << t_digit;
 }
 
-__global__ void k_depth_counts_len(int64_t* misc, int d_digit) { misc[2] = ceil_div(misc[0], kSortTile) << d_digit; }
 
 // Emission in sorted-record order: the group's output range is written
 // contiguously; each lane finds its (record, tile) by binary search over the
@@ -307,7 +320,7 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_upsweep(const K* __restr
             if (idx < n) atomicAdd(&s_cnt[(uint32_t)((keys[idx] >> shift) & (NB - 1))], 1u);   // counts only: order-free
         }
         __syncthreads();
-        for (int d = threadIdx.x; d < NB; d += kSortThreads) counts[(int64_t)d * ntile + b] = (int32_t)s_cnt[d];
+        for (int d = threadIdx.x; d < NB; d += kSortThreads) counts[b * NB + d] = (int32_t)s_cnt[d];
         __syncthreads();
     }
 }
@@ -371,7 +384,7 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_downsweep(const K* __res
                 }
                 tot[e] = run;
                 mine += run;
-                s_glob[d] = count_offs[(int64_t)d * ntile + b];
+                s_glob[d] = count_offs[b * NB + d];
             }
         }
         // exclusive scan of s_part over the first ACT threads (serial per wave, then waves)
@@ -418,9 +431,41 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_downsweep(const K* __res
     }
 }
 
+// Two-level scan of the tile-major digit counts into output offsets:
+// offset(tile b, digit d) = (keys with a digit below d) + (keys with digit d in
+// tiles before b).  Threads are (chunk, digit) pairs with the digit fastest,
+// so every pass over the counts reads consecutive words.
+__global__ void k_chunk_sums(const int32_t* __restrict__ counts, const int64_t* __restrict__ n_ptr, int nd,
+                             int64_t nch, int32_t* __restrict__ chunk_dm) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nch * nd) return;
+    const int64_t c = t / nd;
+    const int d = (int)(t - c * nd);
+    const int64_t ntile = ceil_div(*n_ptr, kSortTile);
+    const int64_t b1 = imin(ntile, (c + 1) * kChunkTiles);
+    int32_t sum = 0;
+    for (int64_t b = c * kChunkTiles; b < b1; b++) sum += counts[b * nd + d];
+    chunk_dm[(int64_t)d * nch + c] = sum;
+}
+
+__global__ void k_tile_offsets(const int32_t* __restrict__ counts, const int32_t* __restrict__ chunk_off,
+                               const int64_t* __restrict__ n_ptr, int nd, int64_t nch, int32_t* __restrict__ offs) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nch * nd) return;
+    const int64_t c = t / nd;
+    const int d = (int)(t - c * nd);
+    const int64_t ntile = ceil_div(*n_ptr, kSortTile);
+    const int64_t b1 = imin(ntile, (c + 1) * kChunkTiles);
+    int32_t run = chunk_off[(int64_t)d * nch + c];
+    for (int64_t b = c * kChunkTiles; b < b1; b++) {
+        offs[b * nd + d] = run;
+        run += counts[b * nd + d];
+    }
+}
+
 template <typename K>
 hipError_t radix_pass(int bits, const K* ki, const int32_t* vi, K* ko, int32_t* vo, const int64_t* n_ptr,
-                      int64_t* counts_len, int shift, SortWs& w, unsigned grid, hipStream_t s) {
+                      int64_t nch, int shift, SortWs& w, unsigned grid, hipStream_t s) {
     switch (bits) {
 #define PG_PASS(B)                                                                                       \
     case B:                                                                                              \
@@ -431,8 +476,13 @@ hipError_t radix_pass(int bits, const K* ki, const int32_t* vi, K* ko, int32_t* 
 #undef PG_PASS
         default: return hipErrorInvalidValue;
     }
-    hipError_t e = scan_i32(w.counts, w.count_offs, counts_len, 1, 0, nullptr, w.scan_tmp, s);
+    const int nd = 1 << bits;
+    const int64_t nth = nch * nd;
+    const unsigned g2 = (unsigned)ceil_div(nth, 256);
+    k_chunk_sums<<<g2, 256, 0, s>>>(w.counts, n_ptr, nd, nch, w.chunk_dm);
+    hipError_t e = scan_i32(w.chunk_dm, w.chunk_off, nullptr, 0, nth, nullptr, w.scan_tmp, s);
     if (e != hipSuccess) return e;
+    k_tile_offsets<<<g2, 256, 0, s>>>(w.counts, w.chunk_off, n_ptr, nd, nch, w.count_offs);
     switch (bits) {
 #define PG_PASS(B)                                                                                              \
     case B:                                                                                                     \
@@ -446,14 +496,26 @@ hipError_t radix_pass(int bits, const K* ki, const int32_t* vi, K* ko, int32_t* 
     return hipGetLastError();
 }
 
-__global__ void k_ranges(const uint32_t* __restrict__ keys, const int64_t* __restrict__ misc,
-                         int32_t* __restrict__ ranges) {
+// [start, end) of every tile from the sorted keys: a tile starts where the key
+// differs from its predecessor, which is also where the previous tile ends.
+// One thread per key; the predecessor comes from the neighbouring lane (only
+// the first lane of a wave loads it), so every key is read once.
+__global__ __launch_bounds__(256) void k_ranges(const uint32_t* __restrict__ keys, const int64_t* __restrict__ misc,
+                                                int32_t* __restrict__ ranges) {
     const int64_t I = misc[1];
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < I; i += (int64_t)gridDim.x * blockDim.x) {
-        const uint32_t tile = keys[i];
-        if (i == 0 || keys[i - 1] != tile) ranges[2 * (int64_t)tile] = (int32_t)i;
-        if (i == I - 1 || keys[i + 1] != tile) ranges[2 * (int64_t)tile + 1] = (int32_t)(i + 1);
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if ((int64_t)blockIdx.x * blockDim.x >= I) return;   // whole group past the end (uniform)
+    const uint32_t k = i < I ? keys[i] : 0u;
+    uint32_t prev = __shfl_up(k, 1, 64);
+    if ((threadIdx.x & 63) == 0 && i > 0 && i < I) prev = keys[i - 1];
+    if (i >= I) return;
+    if (i == 0) {
+        ranges[2 * (int64_t)k] = 0;
+    } else if (prev != k) {
+        ranges[2 * (int64_t)k] = (int32_t)i;
+        ranges[2 * (int64_t)prev + 1] = (int32_t)i;
     }
+    if (i == I - 1) ranges[2 * (int64_t)k + 1] = (int32_t)I;
 }
 
 }  // namespace
@@ -477,7 +539,7 @@ hipError_t launch_bin_sort(const pg_views* v, const pg_bin* bins, int64_t cap, u
         if (e != hipSuccess) return e;
         e = fill_u32(n_inst_dev, 0u, 2, s);
         if (e != hipSuccess) return e;
-        k_post_count<<<1, 1, 0, s>>>(n_inst_dev, cap, overflow_dev, w.misc, pl.t_digit);
+        k_post_count<<<1, 1, 0, s>>>(n_inst_dev, cap, overflow_dev, w.misc);
         return hipGetLastError();
     }
     // 1. compact surviving records in (view, id) order, keyed by depth; slot offsets in the same order
@@ -488,12 +550,12 @@ hipError_t launch_bin_sort(const pg_views* v, const pg_bin* bins, int64_t cap, u
     e = scan_i64(w.blk_b, w.blk_b_off, nullptr, 0, nb, w.misc + 4, w.scan_tmp, s);
     if (e != hipSuccess) return e;
     k_compact<<<(unsigned)nb, kBlk, 0, s>>>(bins, v->n_gv, w.blk_a_off, w.blk_b_off, w.rk0, rva, inst_first);
-    k_depth_counts_len<<<1, 1, 0, s>>>(w.misc, pl.d_digit);
     // 2. stable LSD sort of the records by depth
     const unsigned grid_r = (unsigned)imax(1, imin(kSortGrid, ceil_div(v->n_gv, kSortTile)));
+    const int64_t nch_r = ceil_div(imax(ceil_div(v->n_gv, kSortTile), 1), kChunkTiles);
     uint32_t *rka = w.rk0, *rkb = w.rk1;
     for (int p = 0; p < pl.d_passes; p++) {
-        e = radix_pass<uint32_t>(pl.d_digit, rka, rva, rkb, rvb, w.misc + 0, w.misc + 2, p * pl.d_digit, w, grid_r, s);
+        e = radix_pass<uint32_t>(pl.d_digit, rka, rva, rkb, rvb, w.misc + 0, nch_r, p * pl.d_digit, w, grid_r, s);
         if (e != hipSuccess) return e;
         uint32_t* tk = rka; rka = rkb; rkb = tk;
         int32_t* tv = rva; rva = rvb; rvb = tv;
@@ -502,7 +564,7 @@ hipError_t launch_bin_sort(const pg_views* v, const pg_bin* bins, int64_t cap, u
     k_sorted_count<<<(unsigned)nb, kBlk, 0, s>>>(bins, rva, w.misc, w.blk_a, w.sbins);
     e = scan_i64(w.blk_a, w.blk_a_off, nullptr, 0, nb, n_inst_dev, w.scan_tmp, s);
     if (e != hipSuccess) return e;
-    k_post_count<<<1, 1, 0, s>>>(n_inst_dev, cap, overflow_dev, w.misc, pl.t_digit);
+    k_post_count<<<1, 1, 0, s>>>(n_inst_dev, cap, overflow_dev, w.misc);
     // 4. emit (tile, gv) in record order into the buffer that makes the last tile pass land in the caller's arrays
     uint32_t* ta = (pl.t_passes % 2 == 0) ? keys : w.tk_alt;
     int32_t* tva = (pl.t_passes % 2 == 0) ? values : w.tv_alt;
@@ -511,13 +573,14 @@ hipError_t launch_bin_sort(const pg_views* v, const pg_bin* bins, int64_t cap, u
     k_emit<<<(unsigned)nb, kBlk, 0, s>>>(w.sbins, rva, v->n_gauss, v->d_views, w.blk_a_off, w.misc, ta, tva);
     // 5. stable LSD sort of the instances by tile id
     const unsigned grid_i = (unsigned)imax(1, imin(kSortGrid, ceil_div(cap, kSortTile)));
+    const int64_t nch_i = ceil_div(imax(ceil_div(cap, kSortTile), 1), kChunkTiles);
     for (int p = 0; p < pl.t_passes; p++) {
-        e = radix_pass<uint32_t>(pl.t_digit, ta, tva, tb, tvb, w.misc + 1, w.misc + 3, p * pl.t_digit, w, grid_i, s);
+        e = radix_pass<uint32_t>(pl.t_digit, ta, tva, tb, tvb, w.misc + 1, nch_i, p * pl.t_digit, w, grid_i, s);
         if (e != hipSuccess) return e;
         uint32_t* tk = ta; ta = tb; tb = tk;
         int32_t* tv = tva; tva = tvb; tvb = tv;
     }
-    k_ranges<<<1024, 256, 0, s>>>(keys, w.misc, ranges);
+    k_ranges<<<(unsigned)imax(1, ceil_div(cap, 256)), 256, 0, s>>>(keys, w.misc, ranges);
     // 6. zero the adjoint's per-instance gradient slots (instances nobody composites keep 0)
     if (inst_grad) return fill_u32_dev(inst_grad, 0u, n_inst_dev, cap, 9, s);
     return hipGetLastError();

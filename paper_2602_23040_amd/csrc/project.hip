@@ -479,24 +479,31 @@ __global__ __launch_bounds__(128) void k_project_bwd_sh(const ViewDev* __restric
         for (int ch = 0; ch < 3; ch++) gcol[ch] = grad2d[(int64_t)(6 + ch) * n_gv + gv];
         if (gcol[0] == 0.0f && gcol[1] == 0.0f && gcol[2] == 0.0f) continue;
         const ViewDev& V = views[v];
-        // the forward's colour sum, for the clamp decision
         double dd64[3], dn64;
         view_dir<L>(V, wpos, dd64, &dn64);
-        double Y64[NB];
-        sh_basis<L>(dd64[0], dd64[1], dd64[2], Y64);
-        float gc[3];
-#pragma unroll
-        for (int ch = 0; ch < 3; ch++) {
-            double raw = 0.0;
-#pragma unroll
-            for (int j = 0; j < NB; j++) raw += Y64[j] * (double)sh[3 * j + ch];
-            raw += 0.5;
-            gc[ch] = raw < 0.0 ? 0.0f : gcol[ch];   // clamped channel: no gradient
-        }
         const float d[3] = {(float)dd64[0], (float)dd64[1], (float)dd64[2]};
         const float dn = (float)dn64;
         float Y[NB];
         sh_basis_f<L>(d[0], d[1], d[2], Y);
+        // clamp decision: the FP32 colour sum settles it unless it lies within 1e-3 of the clamp;
+        // then the forward's own FP64 sum decides
+        float gc[3];
+#pragma unroll
+        for (int ch = 0; ch < 3; ch++) {
+            float raw = 0.5f;
+#pragma unroll
+            for (int j = 0; j < NB; j++) raw = fmaf(Y[j], sh[3 * j + ch], raw);
+            bool clamped = raw < 0.0f;
+            if (fabsf(raw) < 1e-3f) {
+                double Y64[NB];
+                sh_basis<L>(dd64[0], dd64[1], dd64[2], Y64);
+                double r64 = 0.0;
+#pragma unroll
+                for (int j = 0; j < NB; j++) r64 += Y64[j] * (double)sh[3 * j + ch];
+                clamped = r64 + 0.5 < 0.0;
+            }
+            gc[ch] = clamped ? 0.0f : gcol[ch];   // clamped channel: no gradient
+        }
         // SH coefficients: dL/dk[j][ch] = Y_j gc_ch; direction: sum_j (sum_ch k[j][ch] gc_ch) grad Y_j
         float wj[NB];
 #pragma unroll
