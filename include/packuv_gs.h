@@ -97,7 +97,7 @@ typedef struct pg_splat {
 typedef struct pg_bin {
     int16_t rect[4];        /* x_lo, y_lo, x_hi, y_hi: inclusive tile range */
     uint32_t depth_key;     /* bit pattern of fp32(z_c) (z_c > 0, so it orders like z_c) */
-    int32_t n_tiles;        /* tiles in rect; 0 when culled */
+    int32_t n_tiles;        /* kept tiles of rect (pg_project); 0 when culled */
 } pg_bin;                   /* 16 bytes */
 
 typedef struct pg_views pg_views;   /* opaque: camera table + tiling, resident on the device */
@@ -158,24 +158,34 @@ pg_status pg_atlas_fetch(const float* atlas, const uint8_t* occupancy, int32_t f
  * activations s = exp(l_s), unit quaternion, o = sigmoid(l_o); mu_c = R mu + t,
  * cull z_c <= 0.2; Sigma2D = J R Sigma R^T J^T + 0.3 I; cull det <= 1e-7;
  * radius ceil(3 sqrt(lambda_max)); tile rectangle; conic; SH colour.
+ * Tile culling by the ellipse: of a rectangle of at most 64 tiles, a tile is
+ * kept when the least q over the rectangle of its pixel centres is at most
+ * 9.001 (q = 0 when the mean is inside; else the least of the four edge
+ * minima, each taken at the edge parabola's clamped vertex); larger
+ * rectangles keep every tile.  A record with no kept tile is culled.  The
+ * kept tiles hold every pixel with q <= 9, so the image does not change.
  * Decision quantities are evaluated in FP64 in a fixed order without
  * contraction, from the FP32 texel values.
- *   params   device float [F][C][n_gauss] (row stride n_gauss)
- *   splats   device pg_splat [n_gv] out
- *   bins     device pg_bin [n_gv] out
- *   visible  device uint8 [F n_gauss]: set to 1 for Gaussians with n_tiles > 0
- *            in at least one view of this call; never cleared (OR semantics). */
+ *   params     device float [F][C][n_gauss] (row stride n_gauss)
+ *   splats     device pg_splat [n_gv] out
+ *   bins       device pg_bin [n_gv] out
+ *   tile_mask  device uint64 [n_gv] out: bit (ty - y_lo) w + (tx - x_lo) set
+ *              for each kept tile of a rectangle of w x h <= 64 tiles; 0 for
+ *              larger rectangles (every tile kept) and for culled records
+ *   visible    device uint8 [F n_gauss]: set to 1 for Gaussians with n_tiles > 0
+ *              in at least one view of this call; never cleared (OR semantics). */
 pg_status pg_project(const pg_views* views, const float* params, pg_splat* splats, pg_bin* bins,
-                     uint8_t* visible, void* stream);
+                     uint64_t* tile_mask, uint8_t* visible, void* stream);
 
 /* a3 -- Tile binning and depth sort (tile rasteriser, Sec. 3; per-camera
  * depth sort, viewer section).  Lists every surviving (view, Gaussian) once
- * per tile of its rectangle and orders each tile's list front to back by
+ * per kept tile of its rectangle and orders each tile's list front to back by
  * fp32(z_c), equal depths by ascending Gaussian id.  Implementation: the
  * surviving records, taken in (view, id) order, are stably radix-sorted by
  * depth; instances are emitted in that order and stably radix-sorted by
  * global tile id (a tile belongs to one view, so its list ends up ordered by
  * (depth, id)).
+ *   bins, tile_mask  from pg_project
  *   keys           device uint32 [inst_capacity] out: global tile of each
  *                  sorted instance (ascending)
  *   values         device int32 [inst_capacity] out: gv of each sorted instance
@@ -183,13 +193,14 @@ pg_status pg_project(const pg_views* views, const float* params, pg_splat* splat
  *   inst_first     device int32 [n_gv] out: the number of instances of all
  *                  records before gv in (view, id) order.  The adjoint keeps
  *                  one gradient slot per instance, record by record in that
- *                  order, the record's tiles in rectangle row-major order.
+ *                  order, the record's kept tiles in rectangle row-major order.
  *   n_inst_dev     device int64 [1] out: number of instances
  *   overflow_dev   device int32 [1] out: 1 if n_inst > inst_capacity, else 0
  *   inst_grad      device float [inst_capacity][9] or NULL: the adjoint's
  *                  per-instance gradient slots; the first n_inst are zeroed
  *   ws             device workspace of pg_sort_workspace_size bytes */
-pg_status pg_bin_sort(const pg_views* views, const pg_bin* bins, int64_t inst_capacity, uint32_t* keys,
+pg_status pg_bin_sort(const pg_views* views, const pg_bin* bins, const uint64_t* tile_mask, int64_t inst_capacity,
+                      uint32_t* keys,
                       int32_t* values, int32_t* tile_ranges, int32_t* inst_first, int64_t* n_inst_dev,
                       int32_t* overflow_dev, float* inst_grad, void* ws, size_t ws_bytes, void* stream);
 
@@ -224,14 +235,15 @@ pg_status pg_render_fwd(const pg_views* views, const pg_splat* splats, const int
  * dL/d(m_x, m_y, a, b, c, opacity, r, g, b) to that instance's own slot (no
  * atomics).  Slots of instances that composited nothing are not written:
  * they keep the zero pg_bin_sort gave them.
- *   bins, inst_first, n_inst_dev   from pg_project / pg_bin_sort; after an
+ *   bins, tile_mask, inst_first, n_inst_dev   from pg_project / pg_bin_sort; after an
  *                overflowed sort (n_inst > inst_capacity) no slot is written
  *   tile_entries, entries, n_contrib, final_T   from pg_render_fwd
  *   dL_dimage    device float [3 n_pixels]
  *   inst_capacity the capacity given to pg_bin_sort
  *   inst_grad    device float [inst_capacity][9] in/out (zeroed by pg_bin_sort), slot inst_first[gv] + k
- *                for tile k (row-major) of record gv's rectangle */
-pg_status pg_render_bwd(const pg_views* views, const pg_splat* splats, const pg_bin* bins, const int32_t* values,
+ *                for the k-th kept tile (row-major) of record gv's rectangle */
+pg_status pg_render_bwd(const pg_views* views, const pg_splat* splats, const pg_bin* bins, const uint64_t* tile_mask,
+                        const int32_t* values,
                         const int32_t* tile_ranges, const int32_t* inst_first, const int64_t* n_inst_dev,
                         int64_t inst_capacity, const int32_t* tile_entries, const uint32_t* entries,
                         const int32_t* n_contrib, const float* bg, const float* final_T, const float* dL_dimage,

@@ -33,13 +33,14 @@ PROJ_DTYPE = np.dtype([
     ("valid", "<i4"), ("radius", "<i4"), ("rect", "<i4", (4,)), ("key", "<u4"), ("pad", "<u4"),
     ("z", "<f8"), ("mean", "<f8", (2,)), ("cov2d", "<f8", (3,)), ("det", "<f8"),
     ("conic", "<f8", (3,)), ("opacity", "<f8"), ("color", "<f8", (3,)), ("color_raw", "<f8", (3,)),
+    ("tile_mask", "<u8"), ("n_tiles", "<i8"),
 ])
 INST_DTYPE = np.dtype([("tile", "<i8"), ("key", "<u4"), ("id", "<i4")])
 CAM_DTYPE = np.dtype([
     ("R", "<f8", (9,)), ("t", "<f8", (3,)), ("fx", "<f8"), ("fy", "<f8"), ("cx", "<f8"), ("cy", "<f8"),
     ("width", "<i4"), ("height", "<i4"), ("frame", "<i4"), ("reserved", "<i4"),
 ])
-assert PROJ_DTYPE.itemsize == 168 and CAM_DTYPE.itemsize == 144 and INST_DTYPE.itemsize == 16
+assert PROJ_DTYPE.itemsize == 184 and CAM_DTYPE.itemsize == 144 and INST_DTYPE.itemsize == 16
 
 _lib = None
 

@@ -1,7 +1,8 @@
 // a3 -- tile binning and depth sort.
 //
-// Every projected Gaussian is listed once per screen tile its rectangle
-// covers (the 3DGS tile rasteriser the paper names, Sec. 3), and each tile's
+// Every projected Gaussian is listed once per kept screen tile of its
+// rectangle (the 3DGS tile rasteriser the paper names, Sec. 3; the projection
+// drops tiles the ellipse q <= 9 cannot reach), and each tile's
 // list is ordered front to back by camera-space depth (depth sort per camera,
 // supplementary viewer section), equal depths by ascending Gaussian id.
 //
@@ -10,8 +11,8 @@
 //   1. the surviving (view, Gaussian) records -- far fewer than instances --
 //      are compacted in (view, id) order and stably sorted by their fp32
 //      depth bits alone (all views mixed);
-//   2. instances are emitted in that order (each record lists the tiles of
-//      its rectangle) and stably sorted by global tile id alone.
+//   2. instances are emitted in that order (each record lists the kept tiles
+//      of its rectangle) and stably sorted by global tile id alone.
 // Because the second sort is stable and every tile belongs to one view, each
 // tile's list comes out ordered by (depth, id): equal depths keep the
 // compaction order, which inside one view is ascending id.  That is the order
@@ -21,7 +22,7 @@
 //   k_valid_count / k_compact   records with n_tiles > 0 -> (depth bits, gv);
 //                               inst_first[gv] = instances of all records before
 //                               gv in (view, id) order: the record's gradient
-//                               slots, one per tile in rectangle order
+//                               slots, one per kept tile in rectangle order
 //   radix passes (32-bit keys)  LSD, digit width <= 10 bits
 //   k_sorted_count / k_emit     tiles per sorted record -> instance offsets ->
 //                               work-group-cooperative emission (coalesced writes)
@@ -73,6 +74,7 @@ struct SortWs {
     int32_t* rv0;
     int32_t* rv1;
     uint4* sbins;            // the records' bins gathered in depth order (read by the emission)
+    uint64_t* smask;         // their kept-tile masks, same order
     uint32_t* tk_alt;        // tile sort ping-pong partner of the caller's arrays
     int32_t* tv_alt;
     int32_t* counts;         // per radix tile, its digit counts (tile-major: [tile][digit])
@@ -119,6 +121,7 @@ SortWs carve(const pg_views* v, int64_t cap, void* ws, size_t* total) {
     w.rv0 = (int32_t*)take(ngv * 4);
     w.rv1 = (int32_t*)take(ngv * 4);
     w.sbins = (uint4*)take(ngv * 16);
+    w.smask = (uint64_t*)take(ngv * 8);
     w.tk_alt = (uint32_t*)take(imax(cap, 1) * 4);
     w.tv_alt = (int32_t*)take(imax(cap, 1) * 4);
     w.counts = (int32_t*)take(cnt * 4);
@@ -207,15 +210,18 @@ __global__ __launch_bounds__(kBlk) void k_compact(const pg_bin* __restrict__ bin
 }
 
 __global__ __launch_bounds__(kBlk) void k_sorted_count(const pg_bin* __restrict__ bins,
+                                                       const uint64_t* __restrict__ tile_mask,
                                                        const int32_t* __restrict__ rv,
                                                        const int64_t* __restrict__ misc, int64_t* __restrict__ blk,
-                                                       uint4* __restrict__ sbins) {
+                                                       uint4* __restrict__ sbins, uint64_t* __restrict__ smask) {
     __shared__ int64_t s[kBlk / 64];
     const int64_t p = (int64_t)blockIdx.x * kBlk + threadIdx.x;
     int64_t c = 0;
     if (p < misc[0]) {
-        const uint4 b = reinterpret_cast<const uint4*>(bins)[rv[p]];
+        const int32_t gv = rv[p];
+        const uint4 b = reinterpret_cast<const uint4*>(bins)[gv];
         sbins[p] = b;
+        smask[p] = tile_mask[gv];
         c = (int64_t)b.w;
     }
     const int64_t t = block_sum_1024(c, s);
@@ -232,11 +238,13 @@ __global__ void k_post_count(const int64_t* n_inst, int64_t cap, int32_t* overfl
 
 
 // Emission in sorted-record order: the group's output range is written
-// contiguously; each lane finds its (record, tile) by binary search over the
-// group's prefix sums.  Per record the group keeps, in LDS, the global tile
-// id of the rectangle's first tile, the rectangle width and the row stride of
-// the view's tile grid, so an instance costs one small division.
-__global__ __launch_bounds__(kBlk) void k_emit(const uint4* __restrict__ sbins, const int32_t* __restrict__ rv,
+// contiguously; each lane finds its (record, kept tile) by binary search over
+// the group's prefix sums, then the tile's rectangle bit from the kept-tile
+// mask.  Per record the group keeps, in LDS, the global tile id of the
+// rectangle's first tile, the rectangle width, the row stride of the view's
+// tile grid and the mask, so an instance costs one small division.
+__global__ __launch_bounds__(kBlk) void k_emit(const uint4* __restrict__ sbins, const uint64_t* __restrict__ smask,
+                                               const int32_t* __restrict__ rv,
                                                int64_t N, const ViewDev* __restrict__ views,
                                                const int64_t* __restrict__ blk_off, const int64_t* __restrict__ misc,
                                                uint32_t* __restrict__ tkeys, int32_t* __restrict__ tvals) {
@@ -246,6 +254,7 @@ __global__ __launch_bounds__(kBlk) void k_emit(const uint4* __restrict__ sbins, 
     __shared__ int32_t s_tx[kBlk];         // tiles per row of the view
     __shared__ float s_rw[kBlk];           // 1 / width
     __shared__ int32_t s_gv[kBlk];
+    __shared__ uint64_t s_mask[kBlk];
     __shared__ int32_t s_warp[kBlk / 64];
     if (misc[1] == 0) return;   // overflow (or nothing to emit): uniform exit
     const int t = threadIdx.x;
@@ -264,6 +273,7 @@ __global__ __launch_bounds__(kBlk) void k_emit(const uint4* __restrict__ sbins, 
         s_tx[t] = V.TX;
         s_rw[t] = 1.0f / (float)w;
         s_gv[t] = gv;
+        s_mask[t] = smask[p];
     }
     s_incl[t] = block_incl_1024(nt, s_warp);
     __syncthreads();
@@ -275,7 +285,7 @@ __global__ __launch_bounds__(kBlk) void k_emit(const uint4* __restrict__ sbins, 
             const int mid = (lo + hi) >> 1;
             if (s_incl[mid] > q) hi = mid; else lo = mid + 1;
         }
-        const int32_t k = q - (lo ? s_incl[lo - 1] : 0);
+        const int32_t k = kept_select(s_mask[lo], q - (lo ? s_incl[lo - 1] : 0));
         const int32_t w = s_w[lo];
         // row = k / w from a float estimate (k < 2^24), corrected to the exact quotient
         int32_t row = (int32_t)((float)k * s_rw[lo]);
@@ -526,7 +536,8 @@ size_t sort_ws_bytes(const pg_views* v, int64_t cap) {
     return total;
 }
 
-hipError_t launch_bin_sort(const pg_views* v, const pg_bin* bins, int64_t cap, uint32_t* keys, int32_t* values,
+hipError_t launch_bin_sort(const pg_views* v, const pg_bin* bins, const uint64_t* tile_mask, int64_t cap,
+                           uint32_t* keys, int32_t* values,
                            int32_t* ranges, int32_t* inst_first, int64_t* n_inst_dev, int32_t* overflow_dev,
                            float* inst_grad, void* ws, hipStream_t s) {
     const SortPlan pl = plan_for(v);
@@ -561,7 +572,7 @@ hipError_t launch_bin_sort(const pg_views* v, const pg_bin* bins, int64_t cap, u
         int32_t* tv = rva; rva = rvb; rvb = tv;
     }
     // 3. instance offsets in sorted-record order; overflow check
-    k_sorted_count<<<(unsigned)nb, kBlk, 0, s>>>(bins, rva, w.misc, w.blk_a, w.sbins);
+    k_sorted_count<<<(unsigned)nb, kBlk, 0, s>>>(bins, tile_mask, rva, w.misc, w.blk_a, w.sbins, w.smask);
     e = scan_i64(w.blk_a, w.blk_a_off, nullptr, 0, nb, n_inst_dev, w.scan_tmp, s);
     if (e != hipSuccess) return e;
     k_post_count<<<1, 1, 0, s>>>(n_inst_dev, cap, overflow_dev, w.misc);
@@ -570,7 +581,7 @@ hipError_t launch_bin_sort(const pg_views* v, const pg_bin* bins, int64_t cap, u
     int32_t* tva = (pl.t_passes % 2 == 0) ? values : w.tv_alt;
     uint32_t* tb = (pl.t_passes % 2 == 0) ? w.tk_alt : keys;
     int32_t* tvb = (pl.t_passes % 2 == 0) ? w.tv_alt : values;
-    k_emit<<<(unsigned)nb, kBlk, 0, s>>>(w.sbins, rva, v->n_gauss, v->d_views, w.blk_a_off, w.misc, ta, tva);
+    k_emit<<<(unsigned)nb, kBlk, 0, s>>>(w.sbins, w.smask, rva, v->n_gauss, v->d_views, w.blk_a_off, w.misc, ta, tva);
     // 5. stable LSD sort of the instances by tile id
     const unsigned grid_i = (unsigned)imax(1, imin(kSortGrid, ceil_div(cap, kSortTile)));
     const int64_t nch_i = ceil_div(imax(ceil_div(cap, kSortTile), 1), kChunkTiles);

@@ -76,7 +76,7 @@ hipError_t launch_fetch(const float* atlas, const uint8_t* occ, int32_t F, int32
 
 // project.hip
 hipError_t launch_project(const pg_views* v, const float* params, pg_splat* splats, pg_bin* bins,
-                          uint8_t* visible, hipStream_t s);
+                          uint64_t* tile_mask, uint8_t* visible, hipStream_t s);
 // per-record sums of the instance slots -> grad2d
 hipError_t launch_slot_sum(const pg_views* v, const pg_bin* bins, const int32_t* inst_first,
                            const int64_t* n_inst_dev, int64_t cap, const float* inst_grad, float* grad2d,
@@ -87,7 +87,8 @@ hipError_t launch_project_bwd(const pg_views* v, const float* params, const floa
 
 // binsort.hip
 size_t sort_ws_bytes(const pg_views* v, int64_t cap);
-hipError_t launch_bin_sort(const pg_views* v, const pg_bin* bins, int64_t cap, uint32_t* keys, int32_t* values,
+hipError_t launch_bin_sort(const pg_views* v, const pg_bin* bins, const uint64_t* tile_mask, int64_t cap,
+                           uint32_t* keys, int32_t* values,
                            int32_t* ranges, int32_t* inst_first, int64_t* n_inst_dev, int32_t* overflow_dev,
                            float* inst_grad, void* ws, hipStream_t s);
 
@@ -96,8 +97,9 @@ hipError_t launch_render_fwd(const pg_views* v, const pg_splat* splats, const in
                              const int32_t* ranges, const float bg[3], float* image, float* final_T,
                              int32_t* n_contrib, int32_t* tile_entries, uint32_t* entries, uint64_t* counters,
                              hipStream_t s);
-hipError_t launch_render_bwd(const pg_views* v, const pg_splat* splats, const pg_bin* bins, const int32_t* values,
-                             const int32_t* ranges, const int32_t* inst_first, const int32_t* tile_entries,
+hipError_t launch_render_bwd(const pg_views* v, const pg_splat* splats, const pg_bin* bins,
+                             const uint64_t* tile_mask, const int32_t* values, const int32_t* ranges,
+                             const int32_t* inst_first, const int32_t* tile_entries,
                              const uint32_t* entries, const int32_t* n_contrib, const float bg[3],
                              const float* final_T, const float* dL_dimage, const int64_t* n_inst_dev, int64_t cap,
                              float* inst_grad, hipStream_t s);
@@ -111,6 +113,34 @@ hipError_t launch_adam(float* atlas, const float* grad, float* m, float* v, cons
                        float lr, float b1, float b2, float eps, int32_t step, int32_t* step_dev, hipStream_t s);
 
 // ---- device helpers
+
+// Kept-tile masks (from the projection): bit (ty - y_lo) w + (tx - x_lo) of a
+// record's mask is set when that tile of its rectangle is kept; a zero mask on
+// a surviving record means every tile is kept.  The record's instances and
+// gradient slots follow its kept tiles in rectangle row-major order.
+
+// Index among the kept tiles of the tile at rectangle bit `bit`.
+__device__ __forceinline__ int32_t kept_rank(uint64_t mask, int32_t bit) {
+    return mask ? (int32_t)__popcll(mask & (((uint64_t)1 << bit) - 1)) : bit;
+}
+
+// Rectangle bit of the k-th kept tile (k < number kept): halving search on
+// bit counts.
+__device__ __forceinline__ int32_t kept_select(uint64_t mask, int32_t k) {
+    if (!mask) return k;
+    int32_t pos = 0;
+#pragma unroll
+    for (int wdt = 32; wdt >= 1; wdt >>= 1) {
+        const uint64_t low = mask & ((((uint64_t)1) << wdt) - 1);
+        const int32_t c = (int32_t)__popcll(low);
+        if (k >= c) {
+            k -= c;
+            mask >>= wdt;
+            pos += wdt;
+        }
+    }
+    return pos;
+}
 
 // Cross-lane data-parallel-primitive move of a float: lanes of rows disabled
 // by ROW_MASK read 0 (control codes: quad_perm 0x00-0xFF, row_ror:n 0x120+n,

@@ -217,43 +217,103 @@ __device__ __forceinline__ void sh_grad_dot_f(float x, float y, float z, const f
     g[2] = g2;
 }
 
+// Tile culling by the ellipse.  A tile of the rectangle is kept when the
+// smallest q over the rectangle spanned by its pixel centres is at most 9 +
+// 1e-3 (the margin covers the compositor's FP32 evaluation of q): zero when
+// the mean lies inside, else the least of the four edge minima, each the
+// parabola on that edge at its clamped vertex (on x = X the vertex is at
+// y = (-B / C) X, on y = Y at x = (-B / A) Y).  Rectangles of more than
+// kMaskTiles tiles keep every tile.  Same FP64 operations in the same order
+// as the independent reference, so the kept sets agree bit for bit.
+constexpr int kMaskTiles = 64;
+constexpr double kQCull = 9.001;
+constexpr int kProjBlk = 128;
+
+__device__ __forceinline__ double q_at(double A, double B, double C, double X, double Y) {
+    return (A * X * X + 2.0 * B * X * Y) + C * Y * Y;
+}
+
+// Least q over the pixel-centre rectangle [X0, X1] x [Y0, Y1] (offsets from the mean).
+__device__ __forceinline__ double rect_qmin(double A, double B, double C, double ky, double kx, double X0,
+                                            double X1, double Y0, double Y1) {
+    if (X0 <= 0.0 && X1 >= 0.0 && Y0 <= 0.0 && Y1 >= 0.0) return 0.0;
+    const double ya = fmin(fmax(ky * X0, Y0), Y1), yb = fmin(fmax(ky * X1, Y0), Y1);
+    const double xa = fmin(fmax(kx * Y0, X0), X1), xb = fmin(fmax(kx * Y1, X0), X1);
+    return fmin(fmin(q_at(A, B, C, X0, ya), q_at(A, B, C, X1, yb)),
+                fmin(q_at(A, B, C, xa, Y0), q_at(A, B, C, xb, Y1)));
+}
+
+// One thread per Gaussian, looping over the views of its frame.  The loop
+// runs the work-group's largest view count on every thread (threads past
+// their own count only take part in the tile tests), because each view's
+// tile tests are shared out over the work-group: rectangles range from one
+// tile to dozens, so a thread testing only its own would hold its wave for
+// the largest rectangle among 64.  Per view: every thread stages its record
+// (mean, conic, edge-vertex slopes, rectangle) in LDS; a work-group scan of
+// the rectangles' tile counts numbers the (record, tile) tests, and each
+// record writes its tests' (owner, tile) words at its place in that
+// numbering; thread t takes tests t, t + 128, ... and ORs kept tiles into
+// the owner's LDS mask.
 template <int L>
-__global__ __launch_bounds__(128) void k_project(const ViewDev* __restrict__ views,
-                                                 const int32_t* __restrict__ frame_views,
-                                                 const int32_t* __restrict__ view_order, int32_t F, int32_t C,
-                                                 int64_t N, int32_t tw, int32_t th,
-                                                 const float* __restrict__ params, pg_splat* __restrict__ splats,
-                                                 pg_bin* __restrict__ bins, uint8_t* __restrict__ visible) {
+__global__ __launch_bounds__(kProjBlk) void k_project(const ViewDev* __restrict__ views,
+                                                      const int32_t* __restrict__ frame_views,
+                                                      const int32_t* __restrict__ view_order, int32_t F, int32_t C,
+                                                      int64_t N, int32_t tw, int32_t th,
+                                                      const float* __restrict__ params,
+                                                      pg_splat* __restrict__ splats, pg_bin* __restrict__ bins,
+                                                      uint64_t* __restrict__ tile_mask,
+                                                      uint8_t* __restrict__ visible) {
     constexpr int NB = (L + 1) * (L + 1);
-    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= (int64_t)F * N) return;
-    const int32_t f = (int32_t)(g / N);
-    const int64_t i = g - (int64_t)f * N;
-    const int32_t v0 = frame_views[f], v1 = frame_views[f + 1];
-    if (v0 == v1) return;
+    __shared__ double s_geo[7][kProjBlk];       // mean x, y; conic A, B, C; slopes -B/C, -B/A
+    __shared__ int32_t s_rect[4][kProjBlk];     // x_lo, y_lo, width, 2^16 / width rounded up
+    __shared__ uint16_t s_item[kProjBlk * kMaskTiles];   // test q: owner thread << 6 | rectangle bit
+    __shared__ unsigned long long s_mask[kProjBlk];
+    __shared__ int32_t s_wsum[kProjBlk / 64];
+    __shared__ int32_t s_nv;
+    const int tid = threadIdx.x;
+    const int64_t g = (int64_t)blockIdx.x * kProjBlk + tid;
+    int32_t f = 0, v0 = 0, v1 = 0;
+    int64_t i = 0;
+    if (g < (int64_t)F * N) {
+        f = (int32_t)(g / N);
+        i = g - (int64_t)f * N;
+        v0 = frame_views[f];
+        v1 = frame_views[f + 1];
+    }
+    if (tid == 0) s_nv = 0;
+    __syncthreads();
+    if (v1 > v0) atomicMax(&s_nv, v1 - v0);
+    __syncthreads();
+    const int32_t nv = s_nv;
+    if (nv == 0) return;     // uniform over the work-group
     const float* P = params + (int64_t)f * C * N + i;
+    const bool has = v1 > v0;
     float rec[11];
 #pragma unroll
-    for (int k = 0; k < 11; k++) rec[k] = P[(int64_t)k * N];
+    for (int k = 0; k < 11; k++) rec[k] = has ? P[(int64_t)k * N] : 0.0f;
     float sh[3 * NB];
 #pragma unroll
-    for (int k = 0; k < 3 * NB; k++) sh[k] = P[(int64_t)(11 + k) * N];
+    for (int k = 0; k < 3 * NB; k++) sh[k] = has ? P[(int64_t)(11 + k) * N] : 0.0f;
     World w;
     world_chain(rec, w);
     bool any = false;
-    for (int32_t vi = v0; vi < v1; vi++) {
-        const int32_t v = view_order[vi];
+    for (int32_t k = 0; k < nv; k++) {
+        const bool act = v0 + k < v1;
+        const int32_t v = act ? view_order[v0 + k] : 0;
         const ViewDev& V = views[v];
         Cam c;
         float4 o0 = make_float4(0.f, 0.f, 0.f, 0.f), o1 = o0, o2 = o0;
         uint4 bo = make_uint4(0u, 0u, 0u, 0u);
-        bool ok = camera_chain(V, w, c) && (c.det > kDetMin);
+        int32_t nrect = 0;      // tiles of the rectangle (0: culled)
+        double mx = 0.0, my = 0.0, A = 1.0, B = 0.0, Cq = 1.0;
+        int32_t ixl = 0, iyl = 0, ixh = 0, iyh = 0;
+        bool ok = act && camera_chain(V, w, c) && (c.det > kDetMin);
         if (ok) {
             const double tr = c.ap + c.cp;
             const double lam = 0.5 * (tr + sqrt(fmax(0.0, tr * tr - 4.0 * c.det)));
             const double rr = ceil(3.0 * sqrt(lam));
-            const double mx = (V.fx * c.xc) / c.zc + V.cx;
-            const double my = (V.fy * c.yc) / c.zc + V.cy;
+            mx = (V.fx * c.xc) / c.zc + V.cx;
+            my = (V.fy * c.yc) / c.zc + V.cy;
             const double xlo = fmax(0.0, floor((mx - rr) / (double)tw));
             const double xhi = fmin((double)(V.TX - 1), floor((mx + rr) / (double)tw));
             const double ylo = fmax(0.0, floor((my - rr) / (double)th));
@@ -272,25 +332,81 @@ __global__ __launch_bounds__(128) void k_project(const ViewDev* __restrict__ vie
                 const double raw = 0.5 + acc;
                 col[ch] = (float)(raw > 0.0 ? raw : 0.0);
             }
+            A = c.cp / c.det;
+            B = -c.bp / c.det;
+            Cq = c.ap / c.det;
             const double2 m2 = make_double2(mx, my);
             o0 = *reinterpret_cast<const float4*>(&m2);
-            o1 = make_float4((float)(c.cp / c.det), (float)(-c.bp / c.det), (float)(c.ap / c.det), (float)w.o);
+            o1 = make_float4((float)A, (float)B, (float)Cq, (float)w.o);
             o2 = make_float4(col[0], col[1], col[2], zf);
             if (xlo <= xhi && ylo <= yhi) {
-                const int32_t ixl = (int32_t)xlo, iyl = (int32_t)ylo, ixh = (int32_t)xhi, iyh = (int32_t)yhi;
+                ixl = (int32_t)xlo;
+                iyl = (int32_t)ylo;
+                ixh = (int32_t)xhi;
+                iyh = (int32_t)yhi;
+                nrect = (ixh - ixl + 1) * (iyh - iyl + 1);
                 bo.x = (uint32_t)(ixl & 0xffff) | ((uint32_t)(iyl & 0xffff) << 16);
                 bo.y = (uint32_t)(ixh & 0xffff) | ((uint32_t)(iyh & 0xffff) << 16);
                 bo.z = __float_as_uint(zf);
-                bo.w = (uint32_t)((ixh - ixl + 1) * (iyh - iyl + 1));
-                any = true;
             }
         }
-        const int64_t gv = (int64_t)v * N + i;
-        float4* sp = reinterpret_cast<float4*>(splats + gv);
-        sp[0] = o0;
-        sp[1] = o1;
-        sp[2] = o2;
-        reinterpret_cast<uint4*>(bins)[gv] = bo;
+        // ---- tile tests, shared out over the work-group
+        const int32_t ntest = nrect <= kMaskTiles ? nrect : 0;
+        const int32_t wdt = ixh - ixl + 1;
+        s_geo[0][tid] = mx;
+        s_geo[1][tid] = my;
+        s_geo[2][tid] = A;
+        s_geo[3][tid] = B;
+        s_geo[4][tid] = Cq;
+        s_geo[5][tid] = -B / Cq;
+        s_geo[6][tid] = -B / A;
+        s_rect[0][tid] = ixl;
+        s_rect[1][tid] = iyl;
+        s_rect[2][tid] = wdt;
+        s_rect[3][tid] = (65536 + wdt - 1) / wdt;
+        s_mask[tid] = 0ull;
+        int32_t incl = ntest;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const int32_t u = __shfl_up(incl, o, 64);
+            if ((tid & 63) >= o) incl += u;
+        }
+        if ((tid & 63) == 63) s_wsum[tid >> 6] = incl;
+        __syncthreads();
+        if (tid >= 64) incl += s_wsum[0];
+        for (int32_t b = 0; b < ntest; b++) s_item[incl - ntest + b] = (uint16_t)((tid << 6) | b);
+        const int32_t total = s_wsum[0] + s_wsum[1];
+        __syncthreads();
+        for (int32_t q = tid; q < total; q += kProjBlk) {
+            const uint32_t it = s_item[q];
+            const int32_t lo = (int32_t)(it >> 6);                 // owner
+            const int32_t bit = (int32_t)(it & 63u);               // row-major index in the rectangle
+            const int32_t row = (bit * s_rect[3][lo]) >> 16;        // bit / width (bit < 64)
+            const int32_t tx = s_rect[0][lo] + (bit - row * s_rect[2][lo]), ty = s_rect[1][lo] + row;
+            const double X0 = ((double)tx * tw + 0.5) - s_geo[0][lo], X1 = X0 + (double)(tw - 1);
+            const double Y0 = ((double)ty * th + 0.5) - s_geo[1][lo], Y1 = Y0 + (double)(th - 1);
+            const double qmin = rect_qmin(s_geo[2][lo], s_geo[3][lo], s_geo[4][lo], s_geo[5][lo], s_geo[6][lo], X0,
+                                          X1, Y0, Y1);
+            if (qmin <= kQCull) atomicOr(&s_mask[lo], 1ull << bit);
+        }
+        __syncthreads();
+        const uint64_t tmask = ntest ? (uint64_t)s_mask[tid] : 0ull;
+        const int32_t nt = ntest ? (int32_t)__popcll(tmask) : nrect;
+        if (nt > 0) {
+            bo.w = (uint32_t)nt;
+            any = true;
+        } else {
+            bo = make_uint4(0u, 0u, 0u, 0u);
+        }
+        if (act) {
+            const int64_t gv = (int64_t)v * N + i;
+            float4* sp = reinterpret_cast<float4*>(splats + gv);
+            sp[0] = o0;
+            sp[1] = o1;
+            sp[2] = o2;
+            reinterpret_cast<uint4*>(bins)[gv] = bo;
+            tile_mask[gv] = tmask;
+        }
     }
     if (any) visible[g] = 1;
 }
@@ -593,13 +709,13 @@ __global__ __launch_bounds__(kSumRecs) void k_slot_sum(const pg_bin* __restrict_
 }  // namespace
 
 hipError_t launch_project(const pg_views* v, const float* params, pg_splat* splats, pg_bin* bins,
-                          uint8_t* visible, hipStream_t s) {
+                          uint64_t* tile_mask, uint8_t* visible, hipStream_t s) {
     const int64_t n = (int64_t)v->frames * v->n_gauss;
     if (n == 0) return hipSuccess;
     const unsigned grid = (unsigned)ceil_div(n, 128);
     auto args = [&](auto kern) {
         kern<<<grid, 128, 0, s>>>(v->d_views, v->d_frame_views, v->d_view_order, v->frames, v->channels, v->n_gauss,
-                                  v->tiling.tile_w, v->tiling.tile_h, params, splats, bins, visible);
+                                  v->tiling.tile_w, v->tiling.tile_h, params, splats, bins, tile_mask, visible);
     };
     switch (v->sh_degree) {
         case 0: args(k_project<0>); break;

@@ -329,6 +329,7 @@ template <int TW, int TH, int BATCH>
 __global__ __launch_bounds__(kLanes) void k_render_bwd(const ViewDev* __restrict__ views, int nv, int64_t n_tiles,
                                                        const pg_splat* __restrict__ splats,
                                                        const pg_bin* __restrict__ bins,
+                                                       const uint64_t* __restrict__ tile_mask,
                                                        const int32_t* __restrict__ values,
                                                        const int2* __restrict__ ranges,
                                                        const int32_t* __restrict__ inst_first,
@@ -385,7 +386,7 @@ __global__ __launch_bounds__(kLanes) void k_render_bwd(const ViewDev* __restrict
             const uint2 r = *reinterpret_cast<const uint2*>(bins + gv);     // tile rectangle of the record
             const int32_t xlo = (int32_t)(r.x & 0xffff), ylo = (int32_t)(r.x >> 16);
             const int32_t xhi = (int32_t)(r.y & 0xffff);
-            s_slot[i] = inst_first[gv] + (t.ty - ylo) * (xhi - xlo + 1) + (t.tx - xlo);
+            s_slot[i] = inst_first[gv] + kept_rank(tile_mask[gv], (t.ty - ylo) * (xhi - xlo + 1) + (t.tx - xlo));
             stage<TW, TH, false>(splats, gv, t.ox, t.oy, t.col0, t.row0, s_geo, s_col, s_blu, nullptr, i);
         }
         __syncthreads();
@@ -472,13 +473,14 @@ void fwd_launch(const pg_views* v, const pg_splat* splats, const int32_t* values
 }
 
 template <int TW, int TH, int BATCH>
-void bwd_launch(const pg_views* v, const pg_splat* splats, const pg_bin* bins, const int32_t* values,
+void bwd_launch(const pg_views* v, const pg_splat* splats, const pg_bin* bins, const uint64_t* tile_mask,
+                const int32_t* values,
                 const int32_t* ranges, const int32_t* inst_first, const int32_t* tile_entries,
                 const uint32_t* entries, const int32_t* n_contrib, const float bg[3], const float* final_T,
                 const float* dL_dimage, const int64_t* n_inst_dev, int64_t cap, float* inst_grad, hipStream_t s) {
     k_render_bwd<TW, TH, BATCH><<<(unsigned)v->n_tiles, kLanes, 0, s>>>(
-        v->d_views, v->n_views, v->n_tiles, splats, bins, values, reinterpret_cast<const int2*>(ranges), inst_first,
-        tile_entries, entries, n_contrib, bg[0], bg[1], bg[2], final_T, dL_dimage, n_inst_dev, cap, inst_grad);
+        v->d_views, v->n_views, v->n_tiles, splats, bins, tile_mask, values, reinterpret_cast<const int2*>(ranges),
+        inst_first, tile_entries, entries, n_contrib, bg[0], bg[1], bg[2], final_T, dL_dimage, n_inst_dev, cap, inst_grad);
 }
 
 template <template <int, int, int> class F, typename... A>
@@ -516,13 +518,14 @@ hipError_t launch_render_fwd(const pg_views* v, const pg_splat* splats, const in
     return hipGetLastError();
 }
 
-hipError_t launch_render_bwd(const pg_views* v, const pg_splat* splats, const pg_bin* bins, const int32_t* values,
-                             const int32_t* ranges, const int32_t* inst_first, const int32_t* tile_entries,
+hipError_t launch_render_bwd(const pg_views* v, const pg_splat* splats, const pg_bin* bins,
+                             const uint64_t* tile_mask, const int32_t* values, const int32_t* ranges,
+                             const int32_t* inst_first, const int32_t* tile_entries,
                              const uint32_t* entries, const int32_t* n_contrib, const float bg[3],
                              const float* final_T, const float* dL_dimage, const int64_t* n_inst_dev, int64_t cap,
                              float* inst_grad, hipStream_t s) {
     if (v->n_tiles == 0) return hipSuccess;
-    dispatch<BwdRun>(v->tiling, v, splats, bins, values, ranges, inst_first, tile_entries, entries, n_contrib, bg,
+    dispatch<BwdRun>(v->tiling, v, splats, bins, tile_mask, values, ranges, inst_first, tile_entries, entries, n_contrib, bg,
                      final_T, dL_dimage, n_inst_dev, cap, inst_grad, s);
     return hipGetLastError();
 }

@@ -70,6 +70,7 @@ def test_full_size_sampled_parity(cfg):
     fw = oracle.Forward(sc, views=views)
     assert fw.n_gauss == N
     spl, bins = r.splat_records(), r.bin_records()
+    masks = r.tile_masks()
     keys, vals = r.sorted_instances()
     tb = r.sets[0].tile_base
     ranges = r.sets[0].ranges.cpu().numpy().reshape(-1, 2).astype(np.int64)
@@ -84,6 +85,8 @@ def test_full_size_sampled_parity(cfg):
         assert np.array_equal(b["n_tiles"] > 0, valid), f"view {v}: cull decisions differ"
         assert np.array_equal(b["rect"][valid], pr["rect"][valid].astype(np.int16))
         assert np.array_equal(b["key"][valid], pr["key"][valid])
+        assert np.array_equal(b["n_tiles"][valid], pr["n_tiles"][valid]), f"view {v}: kept-tile counts differ"
+        assert np.array_equal(masks[sl][valid], pr["tile_mask"][valid]), f"view {v}: kept-tile masks differ"
         assert np.array_equal(s["mean"][valid], pr["mean"][valid]), f"view {v}: FP64 means differ"
         # this view's tile lists: a contiguous slice of the sorted instances
         rg = ranges[tb[v]:tb[v + 1]]

@@ -235,6 +235,54 @@ def test_rect_covers_every_pixel_inside_the_ellipse():
                 assert np.all((ty >= g["rect"][1]) & (ty <= g["rect"][3]))
 
 
+def kept(g, tx, ty):
+    """Membership of tile (tx, ty) in Gaussian g's lists, read from its mask."""
+    r = g["rect"]
+    w, h = r[2] - r[0] + 1, r[3] - r[1] + 1
+    if not (r[0] <= tx <= r[2] and r[1] <= ty <= r[3]):
+        return False
+    if w * h > 64:
+        return True
+    return bool((int(g["tile_mask"]) >> int((ty - r[1]) * w + (tx - r[0]))) & 1)
+
+
+def test_tile_culling_against_dense_sampling():
+    """A culled tile of the rectangle has q > 9.001 everywhere on the rectangle
+    of its pixel centres (checked on a 1/8-pixel grid, whose minimum can only
+    be larger than the true one); a kept tile comes within 0.05 of 9.001 on
+    that grid (the grid's spacing bounds the gap).  n_tiles is the popcount,
+    and a Gaussian with no kept tile is culled."""
+    sc = synth.random_scene(side=10, sh_degree=0, views=3, width=96, height=80, seed=15, lscale=(-2.4, 0.8))
+    ids, params = oracle.fetch(sc.atlas, sc.occupancy)
+    n_culled_tiles = 0
+    for tw, th in ((16, 16), (8, 32), (32, 8)):
+        for cam in sc.cams:
+            pr = oracle.project(params[0], 0, cam, tw, th)
+            u = (np.arange(8 * (tw - 1) + 1) / 8.0)
+            v = (np.arange(8 * (th - 1) + 1) / 8.0)
+            for g in pr[pr["valid"] == 1][:60]:
+                r = g["rect"]
+                w, h = r[2] - r[0] + 1, r[3] - r[1] + 1
+                a, b, c = g["conic"]
+                n = 0
+                for ty in range(r[1], r[3] + 1):
+                    for tx in range(r[0], r[2] + 1):
+                        X = tx * tw + 0.5 + u[None, :] - g["mean"][0]
+                        Y = ty * th + 0.5 + v[:, None] - g["mean"][1]
+                        qmin = float((a * X * X + 2 * b * X * Y + c * Y * Y).min())
+                        if kept(g, tx, ty):
+                            n += 1
+                            if w * h <= 64:
+                                assert qmin <= 9.001 + 0.05, (tx, ty, qmin)
+                        else:
+                            n_culled_tiles += 1
+                            assert qmin > 9.001, (tx, ty, qmin)
+                assert n == g["n_tiles"]
+                assert g["n_tiles"] == (w * h if w * h > 64 else bin(int(g["tile_mask"])).count("1"))
+            assert np.all(pr[pr["valid"] == 0]["n_tiles"] == 0)
+    assert n_culled_tiles > 0, "the scene must exercise culling"
+
+
 def test_bin_sort_matches_brute_force_enumeration():
     sc = synth.random_scene(side=12, sh_degree=0, views=2, width=100, height=70, seed=6)
     ids, params = oracle.fetch(sc.atlas, sc.occupancy)
@@ -247,13 +295,12 @@ def test_bin_sort_matches_brute_force_enumeration():
             for t in range(TX * TY):
                 tx, ty = t % TX, t // TX
                 for i in range(pr.shape[0]):
-                    r = pr[i]["rect"]
-                    if pr[i]["valid"] and r[0] <= tx <= r[2] and r[1] <= ty <= r[3]:
+                    if pr[i]["valid"] and kept(pr[i], tx, ty):
                         brute.append((t, int(pr[i]["key"]), i))
             brute.sort()
             got = [(int(a), int(b), int(c)) for a, b, c in zip(inst["tile"], inst["key"], inst["id"])]
             assert got == brute
-            assert len(inst) == int(sum((r[2] - r[0] + 1) * (r[3] - r[1] + 1) for r in pr[pr["valid"] == 1]["rect"]))
+            assert len(inst) == int(pr[pr["valid"] == 1]["n_tiles"].sum())
             # ranges partition [0, I)
             nonempty = ranges[ranges[:, 1] > ranges[:, 0]]
             assert nonempty[0, 0] == 0 and nonempty[-1, 1] == len(inst)
