@@ -114,6 +114,12 @@ hipError_t launch_adam(float* atlas, const float* grad, float* m, float* v, cons
 
 // ---- device helpers
 
+// Fourth word of a raw buffer resource on gfx9-family chips: 32-bit data
+// format, no swizzle, no index stride.  Raw (untyped) buffer accesses bound
+// every lane's offset by the resource's byte count; stores past it are
+// dropped and loads return 0.
+constexpr int kBufWord3 = 0x00020000;
+
 // Kept-tile masks (from the projection): bit (ty - y_lo) w + (tx - x_lo) of a
 // record's mask is set when that tile of its rectangle is kept; a zero mask on
 // a surviving record means every tile is kept.  The record's instances and

@@ -274,55 +274,47 @@ __device__ __forceinline__ float dpp(float v) {
     return dpp_f32<CTRL, ROW_MASK>(v);
 }
 
-// Row/half-wave swaps of gfx950: lane i of every row (or half) meets lane i of
-// the partner row (half).  Adding both results leaves every lane holding the
-// sum over the pair of rows (halves).
-__device__ __forceinline__ float cross_rows(float x) {
-    auto a = __builtin_amdgcn_permlane16_swap(__float_as_uint(x), __float_as_uint(x), false, false);
-    x = __uint_as_float(a[0]) + __uint_as_float(a[1]);
-    auto b = __builtin_amdgcn_permlane32_swap(__float_as_uint(x), __float_as_uint(x), false, false);
-    return __uint_as_float(b[0]) + __uint_as_float(b[1]);
+// Totals of nine per-lane values over the 64 lanes of the wave.  The first
+// eight go across the four 16-lane rows first, with the gfx950 register
+// swaps: a row swap of two registers a, b followed by an add leaves rows
+// (a0+a1, b0+b1, a2+a3, b2+b3), and a half-wave swap of two such registers
+// then leaves one register whose row r holds value r summed over the rows --
+// four values per register, no selects.  Inside each row, a transposed
+// exchange with the lane at xor 1 merges the two registers (even lanes values
+// 0-3, odd lanes 4-7), and three more exchanges finish the row sums.  The
+// ninth is summed inside each row and then across rows by two row
+// broadcasts.  Result: lane 16 r holds the total of v[r], lane 16 r + 1 that
+// of v[4 + r], lane 63 that of v[8] (see total_index).  No LDS traffic.
+__device__ __forceinline__ float swap16_sum(float a, float b) {
+    auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(a), __float_as_uint(b), false, false);
+    return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+__device__ __forceinline__ float swap32_sum(float a, float b) {
+    auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(a), __float_as_uint(b), false, false);
+    return __uint_as_float(r[0]) + __uint_as_float(r[1]);
 }
 
-// Totals of nine per-lane values over the 64 lanes of the wave, delivered as
-// value i in lane i (i < 9).  Transpose butterfly on the first eight: each
-// exchange step sends one register of a pair to the partner lane and keeps
-// the other, so after the quad exchanges (xor 1, xor 2) and a rotation by 4
-// inside the row, one register holds value (lane & 7) summed over 8 lanes; a
-// rotation by 8 completes the row, and the row / half-wave swaps add the four
-// rows.  The ninth value is reduced on its own.  DPP and permlane moves only;
-// no LDS traffic.
-__device__ __forceinline__ float wave_totals9(const float* v, int lane) {
-    const bool o1 = lane & 1, o2 = lane & 2, o4 = lane & 4;
-    float r[4];
-#pragma unroll
-    for (int p = 0; p < 4; p++) {
-        const float keep = o1 ? v[2 * p + 1] : v[2 * p];
-        const float send = o1 ? v[2 * p] : v[2 * p + 1];
-        r[p] = keep + dpp<0xB1>(send);                  // quad_perm [1,0,3,2]
-    }
-    float t[2];
-#pragma unroll
-    for (int p = 0; p < 2; p++) {
-        const float keep = o2 ? r[2 * p + 1] : r[2 * p];
-        const float send = o2 ? r[2 * p] : r[2 * p + 1];
-        t[p] = keep + dpp<0x4E>(send);                  // quad_perm [2,3,0,1]
-    }
-    float u;
-    {
-        const float keep = o4 ? t[1] : t[0];
-        const float send = o4 ? t[0] : t[1];
-        u = keep + dpp<0x124>(send);                    // row_ror:4 (lane i reads lane i+4 of its row)
-    }
-    u += dpp<0x128>(u);                                 // row_ror:8
-    u = cross_rows(u);
-    float x8 = v[8];
-    x8 += dpp<0xB1>(x8);
-    x8 += dpp<0x4E>(x8);
-    x8 += dpp<0x124>(x8);
-    x8 += dpp<0x128>(x8);
-    x8 = cross_rows(x8);
-    return lane < 8 ? u : x8;
+__device__ __forceinline__ float wave_totals9(const float* v, bool o1, bool last) {
+    const float t0 = swap32_sum(swap16_sum(v[0], v[1]), swap16_sum(v[2], v[3]));
+    const float t1 = swap32_sum(swap16_sum(v[4], v[5]), swap16_sum(v[6], v[7]));
+    float u = (o1 ? t1 : t0) + dpp<0xB1>(o1 ? t0 : t1);     // quad_perm [1,0,3,2]
+    u += dpp<0x4E>(u);                                      // quad_perm [2,3,0,1]
+    u += dpp<0x124>(u);                                     // row_ror:4
+    u += dpp<0x128>(u);                                     // row_ror:8
+    float x = v[8];
+    x += dpp<0xB1>(x);
+    x += dpp<0x4E>(x);
+    x += dpp<0x124>(x);
+    x += dpp<0x128>(x);
+    x += dpp_f32<0x142, 0xa>(x);                            // row_bcast:15 into rows 1, 3
+    x += dpp_f32<0x143, 0xc>(x);                            // row_bcast:31 into rows 2, 3
+    return last ? x : u;
+}
+
+// Which total wave_totals9 leaves in `lane` (-1: none).
+__device__ __forceinline__ int total_index(int lane) {
+    const int p = lane & 15, r = lane >> 4;
+    return p == 0 ? r : (p == 1 ? 4 + r : (lane == 63 ? 8 : -1));
 }
 
 template <int TW, int TH, int BATCH>
@@ -343,7 +335,7 @@ __global__ __launch_bounds__(kLanes) void k_render_bwd(const ViewDev* __restrict
     __shared__ float4 s_geo[BATCH];
     __shared__ float4 s_col[BATCH];
     __shared__ float s_blu[BATCH];
-    __shared__ int32_t s_slot[BATCH];      // emission index of the (Gaussian, this tile) instance
+    __shared__ int32_t s_slot[BATCH];      // gradient slot of the (Gaussian, this tile) instance (-1: none)
     __shared__ uint32_t s_word[BATCH];     // entry word: list position << 4 | blocks that composited it
     TileGeo t;
     tile_geo<TW, TH>(views, nv, n_tiles, t);
@@ -374,6 +366,9 @@ __global__ __launch_bounds__(kLanes) void k_render_bwd(const ViewDev* __restrict
         S[j] = fmaf(G2[j], bg2, fmaf(G1[j], bg1, G0[j] * bg0));
     }
     const int lane = threadIdx.x;
+    const bool o1 = lane & 1;
+    const int tidx = total_index(lane);
+    const int toff = tidx >= 0 ? 4 * tidx : 36;     // byte offset of this lane's total in a slot
     // entries (composited Gaussians of this tile) back to front
     for (int32_t bend = count; bend > 0; bend -= BATCH) {
         const int32_t bstart = max(0, bend - BATCH);
@@ -386,7 +381,9 @@ __global__ __launch_bounds__(kLanes) void k_render_bwd(const ViewDev* __restrict
             const uint2 r = *reinterpret_cast<const uint2*>(bins + gv);     // tile rectangle of the record
             const int32_t xlo = (int32_t)(r.x & 0xffff), ylo = (int32_t)(r.x >> 16);
             const int32_t xhi = (int32_t)(r.y & 0xffff);
-            s_slot[i] = inst_first[gv] + kept_rank(tile_mask[gv], (t.ty - ylo) * (xhi - xlo + 1) + (t.tx - xlo));
+            const int32_t slot =
+                inst_first[gv] + kept_rank(tile_mask[gv], (t.ty - ylo) * (xhi - xlo + 1) + (t.tx - xlo));
+            s_slot[i] = (slot >= 0 && slot < n_inst) ? slot : -1;
             stage<TW, TH, false>(splats, gv, t.ox, t.oy, t.col0, t.row0, s_geo, s_col, s_blu, nullptr, i);
         }
         __syncthreads();
@@ -447,11 +444,17 @@ __global__ __launch_bounds__(kLanes) void k_render_bwd(const ViewDev* __restrict
             v[6] = m[6];
             v[7] = m[7];
             v[8] = m[8];
-            const float mine = wave_totals9(v, lane);
+            const float tot = wave_totals9(v, o1, lane == 63);
             // the (Gaussian, tile) sums go to the instance's own slot: no atomics, and the
             // projection adjoint adds a record's slots in a fixed order
-            const int64_t slot = s_slot[k];
-            if (lane < 9 && slot >= 0 && slot < n_inst) inst_grad[slot * 9 + lane] = mine;
+            const int32_t slot = __builtin_amdgcn_readfirstlane(s_slot[k]);
+            if (slot >= 0) {
+                // 36-byte raw buffer over the slot: the address stays scalar, and lanes
+                // holding no total (offset 36) fall outside it and store nothing
+                const __amdgpu_buffer_rsrc_t dst = __builtin_amdgcn_make_buffer_rsrc(
+                    inst_grad + (int64_t)slot * 9, (short)0, 36, kBufWord3);
+                __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(tot), dst, toff, 0, 0);
+            }
         }
     }
 }
