@@ -231,9 +231,12 @@ pg_status pg_render_fwd(const pg_views* views, const pg_splat* splats, const int
 /* a5, first half -- Adjoint of the compositing (a4) per screen tile.  Walks
  * each tile's entries back to front with the forward's decisions,
  * recomputing per-pixel transmittance from final_T instead of storing it,
- * and writes each (Gaussian, tile) instance's summed 2D gradient
- * dL/d(m_x, m_y, a, b, c, opacity, r, g, b) to that instance's own slot (no
- * atomics).  Slots of instances that composited nothing are not written:
+ * and writes each (Gaussian, tile) instance's sums over the tile's pixels to
+ * that instance's own slot (no atomics): with dq' = alpha dL/dalpha (so
+ * dL/dq = -dq'/2) and (dx, dy) = pixel - mean, the nine floats are
+ * sum dq' dx, sum dq' dy, sum dq' dx^2, sum dq' dx dy, sum dq' dy^2, dL/dopacity
+ * and dL/d(r, g, b).  The mean and conic gradients are linear in the first
+ * five; pg_project_bwd forms them per record.  Slots of instances that composited nothing are not written:
  * they keep the zero pg_bin_sort gave them.
  *   bins, tile_mask, inst_first, n_inst_dev   from pg_project / pg_bin_sort; after an
  *                overflowed sort (n_inst > inst_capacity) no slot is written
@@ -261,7 +264,8 @@ pg_status pg_render_bwd(const pg_views* views, const pg_splat* splats, const pg_
  *   gauss_texel  device int32 [n_gauss] (from pg_atlas_fetch)
  *   dynamic_mask device uint8 [H][W] or NULL (NULL: every Gaussian dynamic)
  *   grad2d       device float [9][n_gv] out: per (view, Gaussian) dL/d(m_x,
- *                m_y, a, b, c, opacity, r, g, b); 0 for culled records
+ *                m_y, a, b, c, opacity, r, g, b) (mean and conic formed from
+ *                the summed moments with the FP64 conic); 0 for culled records
  *   dL_datlas    device float [F][C][H][W] out; written (accumulate = 0: every
  *                texel, unoccupied = 0) or added to (accumulate = 1: occupied
  *                texels only). */

@@ -430,7 +430,7 @@ __global__ __launch_bounds__(128) void k_project_bwd_geo(const ViewDev* __restri
                                                          const int32_t* __restrict__ view_order, int32_t F,
                                                          int32_t C, int64_t N, int64_t n_gv,
                                                          const float* __restrict__ params,
-                                                         const float* __restrict__ grad2d,
+                                                         float* __restrict__ grad2d,
                                                          const int32_t* __restrict__ gauss_texel,
                                                          const uint8_t* __restrict__ dyn, int64_t HW,
                                                          float* __restrict__ gatlas, int32_t accumulate) {
@@ -451,7 +451,8 @@ __global__ __launch_bounds__(128) void k_project_bwd_geo(const ViewDev* __restri
     for (int32_t vi = v0; vi < v1; vi++) {
         const int32_t v = view_order[vi];
         const int64_t gv = (int64_t)v * N + i;
-        // 2D gradient of the record (its slot sums; 0 for culled records): mean, conic, opacity
+        // the record's slot sums (0 for culled records): the compositing moments
+        // sum dq' (dx, dy, dx^2, dx dy, dy^2) with dq' = alpha dL/dalpha, and dL/do
         double g6[6];
         bool nz = false;
 #pragma unroll
@@ -470,6 +471,18 @@ __global__ __launch_bounds__(128) void k_project_bwd_geo(const ViewDev* __restri
         if (!camera_chain(V, w, c)) continue;   // never for a record with a gradient: the forward kept it
         const double det = c.det;
         const double Q00 = c.cp / det, Q01 = -c.bp / det, Q11 = c.ap / det;
+        // 2D gradients from the moments (dL/dq = -dq'/2): dL/dm = Q (m0, m1),
+        // dL/d(a, b, c) = -(m2 / 2, m3, m4 / 2); written back as the record's grad2d
+        {
+            const double m0 = g6[0], m1 = g6[1];
+            g6[0] = Q00 * m0 + Q01 * m1;
+            g6[1] = Q01 * m0 + Q11 * m1;
+            g6[2] = -0.5 * g6[2];
+            g6[3] = -g6[3];
+            g6[4] = -0.5 * g6[4];
+#pragma unroll
+            for (int k = 0; k < 5; k++) grad2d[(int64_t)k * n_gv + gv] = (float)g6[k];
+        }
         const double G00 = g6[2], G01 = 0.5 * g6[3], G11 = g6[4];
         // QG = Q Gh ; GS = -(QG Q)
         const double QG00 = Q00 * G00 + Q01 * G01, QG01 = Q00 * G01 + Q01 * G11;
@@ -735,7 +748,7 @@ hipError_t launch_slot_sum(const pg_views* v, const pg_bin* bins, const int32_t*
     return hipGetLastError();
 }
 
-hipError_t launch_project_bwd(const pg_views* v, const float* params, const float* grad2d,
+hipError_t launch_project_bwd(const pg_views* v, const float* params, float* grad2d,
                               const int32_t* gauss_texel, const uint8_t* dyn, int32_t H, int32_t W,
                               float* dL_datlas, int32_t accumulate, hipStream_t s) {
     const int64_t HW = (int64_t)H * W;

@@ -431,20 +431,10 @@ __global__ __launch_bounds__(kLanes) void k_render_bwd(const ViewDev* __restrict
                 m[3] = fmaf(px, dy, m[3]);
                 m[4] = fmaf(py, dy, m[4]);
             }
-            // per-lane partials of the 2D gradients: dm = [[a, b], [b, c]] (Sx, Sy);
-            // d(a, b, c) = -(Sxx / 2, Sxy, Syy / 2) (linear, so applied before the lane sum)
-            const float bb = 0.5f * g.w;
-            float v[9];
-            v[0] = fmaf(g.z, m[0], bb * m[1]);
-            v[1] = fmaf(bb, m[0], cc.x * m[1]);
-            v[2] = -0.5f * m[2];
-            v[3] = -m[3];
-            v[4] = -0.5f * m[4];
-            v[5] = m[5];
-            v[6] = m[6];
-            v[7] = m[7];
-            v[8] = m[8];
-            const float tot = wave_totals9(v, o1, lane == 63);
+            // the moments go to the slot as they are: the mean and conic gradients are
+            // linear in them (dm = Q (m0, m1), d(a, b, c) = -(m2 / 2, m3, m4 / 2)), so the
+            // projection adjoint forms them once per record from its summed slots
+            const float tot = wave_totals9(m, o1, lane == 63);
             // the (Gaussian, tile) sums go to the instance's own slot: no atomics, and the
             // projection adjoint adds a record's slots in a fixed order
             const int32_t slot = __builtin_amdgcn_readfirstlane(s_slot[k]);
