@@ -400,9 +400,8 @@ __global__ __launch_bounds__(kLanes) void k_render_bwd(const ViewDev* __restrict
             float m[9];
 #pragma unroll
             for (int i = 0; i < 9; i++) m[i] = 0.0f;
-#pragma unroll
-            for (int j = 0; j < kPPT; j++) {
-                if (!((word >> j) & 1u)) continue;      // no pixel of block j composited this Gaussian
+            // one block of the lane's four pixels (j is a constant after inlining)
+            auto block = [&](const int j) __attribute__((always_inline)) {
                 const float dx = t.fx[j] - g.x, dy = t.fy[j] - g.y;
                 const float q = quad(dx, dy, g.z, g.w, cc.x);
                 const Eval ev = evaluate(q, cc.y);    // bit-identical to the forward's alpha
@@ -430,6 +429,26 @@ __global__ __launch_bounds__(kLanes) void k_render_bwd(const ViewDev* __restrict
                 m[2] = fmaf(px, dx, m[2]);
                 m[3] = fmaf(px, dy, m[3]);
                 m[4] = fmaf(py, dy, m[4]);
+            };
+            // blocks whose bit is set, entered at the first one so that its code starts the
+            // sums from zero (a tile's entry always has at least one block)
+            static_assert(kPPT == 4, "four blocks per tile");
+            const uint32_t bits = word & ((1u << kPPT) - 1u);
+            const int j0 = __builtin_ctz(bits);
+            if (j0 == 0) {
+                block(0);
+                if (bits & 2u) block(1);
+                if (bits & 4u) block(2);
+                if (bits & 8u) block(3);
+            } else if (j0 == 1) {
+                block(1);
+                if (bits & 4u) block(2);
+                if (bits & 8u) block(3);
+            } else if (j0 == 2) {
+                block(2);
+                if (bits & 8u) block(3);
+            } else {
+                block(3);
             }
             // the moments go to the slot as they are: the mean and conic gradients are
             // linear in them (dm = Q (m0, m1), d(a, b, c) = -(m2 / 2, m3, m4 / 2)), so the
