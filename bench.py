@@ -362,13 +362,13 @@ def stage_times(r, atlas, target, reps=5):
     stream = torch.cuda.current_stream()
     calls = {
         "fetch": lambda: r.fetch(atlas),
-        "project": lambda: abi.pg_project(s.handle, r.params, s.splats, s.bins, s.tile_mask, r.visible, stream),
-        "bin_sort": lambda: abi.pg_bin_sort(s.handle, s.bins, s.tile_mask, s.cap, s.keys, s.values, s.ranges, s.inst_first,
+        "project": lambda: abi.pg_project(s.handle, r.params, s.splats, s.bins, s.tiles, r.visible, stream),
+        "bin_sort": lambda: abi.pg_bin_sort(s.handle, s.bins, s.tiles, s.cap, s.keys, s.values, s.ranges, s.inst_first,
                                             s.n_inst, s.overflow, s.inst_grad, s.ws, s.ws_bytes, stream),
         "render_fwd": lambda: abi.pg_render_fwd(s.handle, s.splats, s.values, s.ranges, r.bg, r.image, r.final_T,
                                                 r.n_contrib, s.tile_entries, s.entries, None, stream),
         "loss_l1": lambda: r.loss_l1(target),
-        "render_bwd": lambda: abi.pg_render_bwd(s.handle, s.splats, s.bins, s.tile_mask, s.values, s.ranges, s.inst_first,
+        "render_bwd": lambda: abi.pg_render_bwd(s.handle, s.splats, s.tiles, s.values, s.ranges, s.inst_first,
                                                 s.n_inst, s.cap, s.tile_entries, s.entries, r.n_contrib, r.bg,
                                                 r.final_T, r.dL_dimage, s.inst_grad, stream),
         "project_bwd": lambda: abi.pg_project_bwd(s.handle, r.params, s.bins, s.inst_first, s.n_inst,

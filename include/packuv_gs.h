@@ -100,6 +100,15 @@ typedef struct pg_bin {
     int32_t n_tiles;        /* kept tiles of rect (pg_project); 0 when culled */
 } pg_bin;                   /* 16 bytes */
 
+/* Kept tiles of a (view, Gaussian) record, as pg_project leaves them for the
+ * sort's emission and the adjoint's slot lookup (one 16-byte read). */
+typedef struct pg_tile_set {
+    uint64_t mask;          /* bit (ty - y_lo) w + (tx - x_lo) set for each kept tile of a
+                               rectangle of w x h <= 64 tiles; 0: every tile of the rectangle */
+    int16_t x_lo, y_lo;     /* rectangle origin, in tiles */
+    uint16_t width, height; /* rectangle size in tiles; all fields 0 for culled records */
+} pg_tile_set;              /* 16 bytes */
+
 typedef struct pg_views pg_views;   /* opaque: camera table + tiling, resident on the device */
 
 typedef struct pg_views_info {
@@ -169,13 +178,11 @@ pg_status pg_atlas_fetch(const float* atlas, const uint8_t* occupancy, int32_t f
  *   params     device float [F][C][n_gauss] (row stride n_gauss)
  *   splats     device pg_splat [n_gv] out
  *   bins       device pg_bin [n_gv] out
- *   tile_mask  device uint64 [n_gv] out: bit (ty - y_lo) w + (tx - x_lo) set
- *              for each kept tile of a rectangle of w x h <= 64 tiles; 0 for
- *              larger rectangles (every tile kept) and for culled records
+ *   tiles      device pg_tile_set [n_gv] out: each record's kept tiles
  *   visible    device uint8 [F n_gauss]: set to 1 for Gaussians with n_tiles > 0
  *              in at least one view of this call; never cleared (OR semantics). */
 pg_status pg_project(const pg_views* views, const float* params, pg_splat* splats, pg_bin* bins,
-                     uint64_t* tile_mask, uint8_t* visible, void* stream);
+                     pg_tile_set* tiles, uint8_t* visible, void* stream);
 
 /* a3 -- Tile binning and depth sort (tile rasteriser, Sec. 3; per-camera
  * depth sort, viewer section).  Lists every surviving (view, Gaussian) once
@@ -185,7 +192,7 @@ pg_status pg_project(const pg_views* views, const float* params, pg_splat* splat
  * depth; instances are emitted in that order and stably radix-sorted by
  * global tile id (a tile belongs to one view, so its list ends up ordered by
  * (depth, id)).
- *   bins, tile_mask  from pg_project
+ *   bins, tiles    from pg_project
  *   keys           device uint32 [inst_capacity] out: global tile of each
  *                  sorted instance (ascending)
  *   values         device int32 [inst_capacity] out: gv of each sorted instance
@@ -199,7 +206,7 @@ pg_status pg_project(const pg_views* views, const float* params, pg_splat* splat
  *   inst_grad      device float [inst_capacity][9] or NULL: the adjoint's
  *                  per-instance gradient slots; the first n_inst are zeroed
  *   ws             device workspace of pg_sort_workspace_size bytes */
-pg_status pg_bin_sort(const pg_views* views, const pg_bin* bins, const uint64_t* tile_mask, int64_t inst_capacity,
+pg_status pg_bin_sort(const pg_views* views, const pg_bin* bins, const pg_tile_set* tiles, int64_t inst_capacity,
                       uint32_t* keys,
                       int32_t* values, int32_t* tile_ranges, int32_t* inst_first, int64_t* n_inst_dev,
                       int32_t* overflow_dev, float* inst_grad, void* ws, size_t ws_bytes, void* stream);
@@ -238,16 +245,16 @@ pg_status pg_render_fwd(const pg_views* views, const pg_splat* splats, const int
  * and dL/d(r, g, b).  The mean and conic gradients are linear in the first
  * five; pg_project_bwd forms them per record.  Slots of instances that composited nothing are not written:
  * they keep the zero pg_bin_sort gave them.
- *   bins, tile_mask, inst_first, n_inst_dev   from pg_project / pg_bin_sort; after an
+ *   tiles, inst_first, n_inst_dev   from pg_project / pg_bin_sort; after an
  *                overflowed sort (n_inst > inst_capacity) no slot is written
  *   tile_entries, entries, n_contrib, final_T   from pg_render_fwd
  *   dL_dimage    device float [3 n_pixels]
  *   inst_capacity the capacity given to pg_bin_sort
  *   inst_grad    device float [inst_capacity][9] in/out (zeroed by pg_bin_sort), slot inst_first[gv] + k
  *                for the k-th kept tile (row-major) of record gv's rectangle */
-pg_status pg_render_bwd(const pg_views* views, const pg_splat* splats, const pg_bin* bins, const uint64_t* tile_mask,
-                        const int32_t* values,
-                        const int32_t* tile_ranges, const int32_t* inst_first, const int64_t* n_inst_dev,
+pg_status pg_render_bwd(const pg_views* views, const pg_splat* splats, const pg_tile_set* tiles,
+                        const int32_t* values, const int32_t* tile_ranges, const int32_t* inst_first,
+                        const int64_t* n_inst_dev,
                         int64_t inst_capacity, const int32_t* tile_entries, const uint32_t* entries,
                         const int32_t* n_contrib, const float* bg, const float* final_T, const float* dL_dimage,
                         float* inst_grad, void* stream);

@@ -240,30 +240,30 @@ pg_status pg_atlas_fetch(const float* atlas, const uint8_t* occupancy, int32_t f
     return PG_OK;
 }
 
-pg_status pg_project(const pg_views* v, const float* params, pg_splat* splats, pg_bin* bins, uint64_t* tile_mask,
+pg_status pg_project(const pg_views* v, const float* params, pg_splat* splats, pg_bin* bins, pg_tile_set* tiles,
                      uint8_t* visible, void* stream) {
     g_error.clear();
     if (!v) return invalid("views is null");
-    if (v->n_gv > 0 && (!params || !splats || !bins || !tile_mask || !visible)) return invalid("null pointer argument");
-    PG_CHECK_HIP(launch_project(v, params, splats, bins, tile_mask, visible, (hipStream_t)stream), "pg_project");
+    if (v->n_gv > 0 && (!params || !splats || !bins || !tiles || !visible)) return invalid("null pointer argument");
+    PG_CHECK_HIP(launch_project(v, params, splats, bins, tiles, visible, (hipStream_t)stream), "pg_project");
     return PG_OK;
 }
 
-pg_status pg_bin_sort(const pg_views* v, const pg_bin* bins, const uint64_t* tile_mask, int64_t cap, uint32_t* keys,
+pg_status pg_bin_sort(const pg_views* v, const pg_bin* bins, const pg_tile_set* tiles, int64_t cap, uint32_t* keys,
                       int32_t* values,
                       int32_t* tile_ranges, int32_t* inst_first, int64_t* n_inst_dev, int32_t* overflow_dev,
                       float* inst_grad, void* ws, size_t ws_bytes, void* stream) {
     g_error.clear();
     if (!v) return invalid("views is null");
     if (!tile_ranges || !n_inst_dev || !overflow_dev || !ws) return invalid("null pointer argument");
-    if (v->n_gv > 0 && (!bins || !tile_mask || !inst_first)) return invalid("bins / tile_mask / inst_first is null");
+    if (v->n_gv > 0 && (!bins || !tiles || !inst_first)) return invalid("bins / tiles / inst_first is null");
     if (cap < 0 || cap > INT32_MAX) return invalid("inst_capacity must be in [0, 2^31 - 1]");
     if (cap > 0 && (!keys || !values)) return invalid("keys / values null with inst_capacity > 0");
     if (ws_bytes < sort_ws_bytes(v, cap)) {
         set_error("sort workspace too small");
         return PG_ERR_WORKSPACE;
     }
-    PG_CHECK_HIP(launch_bin_sort(v, bins, tile_mask, cap, keys, values, tile_ranges, inst_first, n_inst_dev, overflow_dev,
+    PG_CHECK_HIP(launch_bin_sort(v, bins, tiles, cap, keys, values, tile_ranges, inst_first, n_inst_dev, overflow_dev,
                                  inst_grad, ws, (hipStream_t)stream),
                  "pg_bin_sort");
     return PG_OK;
@@ -282,7 +282,7 @@ pg_status pg_render_fwd(const pg_views* v, const pg_splat* splats, const int32_t
     return PG_OK;
 }
 
-pg_status pg_render_bwd(const pg_views* v, const pg_splat* splats, const pg_bin* bins, const uint64_t* tile_mask,
+pg_status pg_render_bwd(const pg_views* v, const pg_splat* splats, const pg_tile_set* tiles,
                         const int32_t* values, const int32_t* tile_ranges, const int32_t* inst_first, const int64_t* n_inst_dev,
                         int64_t inst_capacity, const int32_t* tile_entries, const uint32_t* entries,
                         const int32_t* n_contrib, const float* bg, const float* final_T, const float* dL_dimage,
@@ -291,10 +291,10 @@ pg_status pg_render_bwd(const pg_views* v, const pg_splat* splats, const pg_bin*
     if (!v || !bg) return invalid("null argument");
     if (!tile_ranges || !tile_entries || !n_contrib || !final_T || !dL_dimage || !n_inst_dev)
         return invalid("null pointer argument");
-    if (v->n_gv > 0 && (!splats || !bins || !tile_mask || !values || !inst_first || !entries || !inst_grad))
+    if (v->n_gv > 0 && (!splats || !tiles || !values || !inst_first || !entries || !inst_grad))
         return invalid("null pointer argument");
     if (inst_capacity < 0 || inst_capacity > INT32_MAX) return invalid("inst_capacity must be in [0, 2^31 - 1]");
-    PG_CHECK_HIP(launch_render_bwd(v, splats, bins, tile_mask, values, tile_ranges, inst_first, tile_entries, entries,
+    PG_CHECK_HIP(launch_render_bwd(v, splats, tiles, values, tile_ranges, inst_first, tile_entries, entries,
                                    n_contrib, bg, final_T, dL_dimage, n_inst_dev, inst_capacity, inst_grad,
                                    (hipStream_t)stream),
                  "pg_render_bwd");

@@ -73,8 +73,7 @@ struct SortWs {
     uint32_t* rk1;
     int32_t* rv0;
     int32_t* rv1;
-    uint4* sbins;            // the records' bins gathered in depth order (read by the emission)
-    uint64_t* smask;         // their kept-tile masks, same order
+    uint4* stiles;           // the records' tile sets gathered in depth order (read by the emission)
     uint32_t* tk_alt;        // tile sort ping-pong partner of the caller's arrays
     int32_t* tv_alt;
     int32_t* counts;         // per radix tile, its digit counts (tile-major: [tile][digit])
@@ -120,8 +119,7 @@ SortWs carve(const pg_views* v, int64_t cap, void* ws, size_t* total) {
     w.rk1 = (uint32_t*)take(ngv * 4);
     w.rv0 = (int32_t*)take(ngv * 4);
     w.rv1 = (int32_t*)take(ngv * 4);
-    w.sbins = (uint4*)take(ngv * 16);
-    w.smask = (uint64_t*)take(ngv * 8);
+    w.stiles = (uint4*)take(ngv * 16);
     w.tk_alt = (uint32_t*)take(imax(cap, 1) * 4);
     w.tv_alt = (int32_t*)take(imax(cap, 1) * 4);
     w.counts = (int32_t*)take(cnt * 4);
@@ -209,20 +207,19 @@ __global__ __launch_bounds__(kBlk) void k_compact(const pg_bin* __restrict__ bin
     }
 }
 
-__global__ __launch_bounds__(kBlk) void k_sorted_count(const pg_bin* __restrict__ bins,
-                                                       const uint64_t* __restrict__ tile_mask,
+// Tile sets gathered into depth order (one 16-byte read per record) and the
+// group sums of the kept-tile counts.
+__global__ __launch_bounds__(kBlk) void k_sorted_count(const pg_tile_set* __restrict__ tiles,
                                                        const int32_t* __restrict__ rv,
                                                        const int64_t* __restrict__ misc, int64_t* __restrict__ blk,
-                                                       uint4* __restrict__ sbins, uint64_t* __restrict__ smask) {
+                                                       uint4* __restrict__ stiles) {
     __shared__ int64_t s[kBlk / 64];
     const int64_t p = (int64_t)blockIdx.x * kBlk + threadIdx.x;
     int64_t c = 0;
     if (p < misc[0]) {
-        const int32_t gv = rv[p];
-        const uint4 b = reinterpret_cast<const uint4*>(bins)[gv];
-        sbins[p] = b;
-        smask[p] = tile_mask[gv];
-        c = (int64_t)b.w;
+        const uint4 ts = reinterpret_cast<const uint4*>(tiles)[rv[p]];
+        stiles[p] = ts;
+        c = (int64_t)kept_count(ts);
     }
     const int64_t t = block_sum_1024(c, s);
     if (threadIdx.x == 0) blk[blockIdx.x] = t;
@@ -243,8 +240,7 @@ __global__ void k_post_count(const int64_t* n_inst, int64_t cap, int32_t* overfl
 // mask.  Per record the group keeps, in LDS, the global tile id of the
 // rectangle's first tile, the rectangle width, the row stride of the view's
 // tile grid and the mask, so an instance costs one small division.
-__global__ __launch_bounds__(kBlk) void k_emit(const uint4* __restrict__ sbins, const uint64_t* __restrict__ smask,
-                                               const int32_t* __restrict__ rv,
+__global__ __launch_bounds__(kBlk) void k_emit(const uint4* __restrict__ stiles, const int32_t* __restrict__ rv,
                                                int64_t N, const ViewDev* __restrict__ views,
                                                const int64_t* __restrict__ blk_off, const int64_t* __restrict__ misc,
                                                uint32_t* __restrict__ tkeys, int32_t* __restrict__ tvals) {
@@ -262,18 +258,17 @@ __global__ __launch_bounds__(kBlk) void k_emit(const uint4* __restrict__ sbins, 
     int32_t nt = 0;
     if (p < misc[0]) {
         const int32_t gv = rv[p];
-        const uint4 b = sbins[p];
-        nt = (int32_t)b.w;
-        const int32_t xlo = (int32_t)(b.x & 0xffff), ylo = (int32_t)(b.x >> 16);
-        const int32_t xhi = (int32_t)(b.y & 0xffff);
+        const uint4 ts = stiles[p];
+        nt = kept_count(ts);
+        const int32_t xlo = (int32_t)(ts.z & 0xffff), ylo = (int32_t)(ts.z >> 16);
         const ViewDev& V = views[gv / N];
-        const int32_t w = xhi - xlo + 1;
+        const int32_t w = (int32_t)(ts.w & 0xffff);
         s_tile0[t] = (uint32_t)(V.tile_base + (int64_t)ylo * V.TX + xlo);
         s_w[t] = w;
         s_tx[t] = V.TX;
         s_rw[t] = 1.0f / (float)w;
         s_gv[t] = gv;
-        s_mask[t] = smask[p];
+        s_mask[t] = (uint64_t)ts.x | ((uint64_t)ts.y << 32);
     }
     s_incl[t] = block_incl_1024(nt, s_warp);
     __syncthreads();
@@ -536,7 +531,7 @@ size_t sort_ws_bytes(const pg_views* v, int64_t cap) {
     return total;
 }
 
-hipError_t launch_bin_sort(const pg_views* v, const pg_bin* bins, const uint64_t* tile_mask, int64_t cap,
+hipError_t launch_bin_sort(const pg_views* v, const pg_bin* bins, const pg_tile_set* tiles, int64_t cap,
                            uint32_t* keys, int32_t* values,
                            int32_t* ranges, int32_t* inst_first, int64_t* n_inst_dev, int32_t* overflow_dev,
                            float* inst_grad, void* ws, hipStream_t s) {
@@ -572,7 +567,7 @@ hipError_t launch_bin_sort(const pg_views* v, const pg_bin* bins, const uint64_t
         int32_t* tv = rva; rva = rvb; rvb = tv;
     }
     // 3. instance offsets in sorted-record order; overflow check
-    k_sorted_count<<<(unsigned)nb, kBlk, 0, s>>>(bins, tile_mask, rva, w.misc, w.blk_a, w.sbins, w.smask);
+    k_sorted_count<<<(unsigned)nb, kBlk, 0, s>>>(tiles, rva, w.misc, w.blk_a, w.stiles);
     e = scan_i64(w.blk_a, w.blk_a_off, nullptr, 0, nb, n_inst_dev, w.scan_tmp, s);
     if (e != hipSuccess) return e;
     k_post_count<<<1, 1, 0, s>>>(n_inst_dev, cap, overflow_dev, w.misc);
@@ -581,7 +576,7 @@ hipError_t launch_bin_sort(const pg_views* v, const pg_bin* bins, const uint64_t
     int32_t* tva = (pl.t_passes % 2 == 0) ? values : w.tv_alt;
     uint32_t* tb = (pl.t_passes % 2 == 0) ? w.tk_alt : keys;
     int32_t* tvb = (pl.t_passes % 2 == 0) ? w.tv_alt : values;
-    k_emit<<<(unsigned)nb, kBlk, 0, s>>>(w.sbins, w.smask, rva, v->n_gauss, v->d_views, w.blk_a_off, w.misc, ta, tva);
+    k_emit<<<(unsigned)nb, kBlk, 0, s>>>(w.stiles, rva, v->n_gauss, v->d_views, w.blk_a_off, w.misc, ta, tva);
     // 5. stable LSD sort of the instances by tile id
     const unsigned grid_i = (unsigned)imax(1, imin(kSortGrid, ceil_div(cap, kSortTile)));
     const int64_t nch_i = ceil_div(imax(ceil_div(cap, kSortTile), 1), kChunkTiles);

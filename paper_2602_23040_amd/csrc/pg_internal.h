@@ -76,7 +76,7 @@ hipError_t launch_fetch(const float* atlas, const uint8_t* occ, int32_t F, int32
 
 // project.hip
 hipError_t launch_project(const pg_views* v, const float* params, pg_splat* splats, pg_bin* bins,
-                          uint64_t* tile_mask, uint8_t* visible, hipStream_t s);
+                          pg_tile_set* tiles, uint8_t* visible, hipStream_t s);
 // per-record sums of the instance slots -> grad2d
 hipError_t launch_slot_sum(const pg_views* v, const pg_bin* bins, const int32_t* inst_first,
                            const int64_t* n_inst_dev, int64_t cap, const float* inst_grad, float* grad2d,
@@ -87,7 +87,7 @@ hipError_t launch_project_bwd(const pg_views* v, const float* params, float* gra
 
 // binsort.hip
 size_t sort_ws_bytes(const pg_views* v, int64_t cap);
-hipError_t launch_bin_sort(const pg_views* v, const pg_bin* bins, const uint64_t* tile_mask, int64_t cap,
+hipError_t launch_bin_sort(const pg_views* v, const pg_bin* bins, const pg_tile_set* tiles, int64_t cap,
                            uint32_t* keys, int32_t* values,
                            int32_t* ranges, int32_t* inst_first, int64_t* n_inst_dev, int32_t* overflow_dev,
                            float* inst_grad, void* ws, hipStream_t s);
@@ -97,8 +97,7 @@ hipError_t launch_render_fwd(const pg_views* v, const pg_splat* splats, const in
                              const int32_t* ranges, const float bg[3], float* image, float* final_T,
                              int32_t* n_contrib, int32_t* tile_entries, uint32_t* entries, uint64_t* counters,
                              hipStream_t s);
-hipError_t launch_render_bwd(const pg_views* v, const pg_splat* splats, const pg_bin* bins,
-                             const uint64_t* tile_mask, const int32_t* values, const int32_t* ranges,
+hipError_t launch_render_bwd(const pg_views* v, const pg_splat* splats, const pg_tile_set* tiles, const int32_t* values, const int32_t* ranges,
                              const int32_t* inst_first, const int32_t* tile_entries,
                              const uint32_t* entries, const int32_t* n_contrib, const float bg[3],
                              const float* final_T, const float* dL_dimage, const int64_t* n_inst_dev, int64_t cap,
@@ -120,10 +119,15 @@ hipError_t launch_adam(float* atlas, const float* grad, float* m, float* v, cons
 // dropped and loads return 0.
 constexpr int kBufWord3 = 0x00020000;
 
-// Kept-tile masks (from the projection): bit (ty - y_lo) w + (tx - x_lo) of a
-// record's mask is set when that tile of its rectangle is kept; a zero mask on
-// a surviving record means every tile is kept.  The record's instances and
+// Kept-tile sets (pg_tile_set, from the projection): bit (ty - y_lo) w +
+// (tx - x_lo) of a record's mask is set when that tile of its rectangle is
+// kept; a zero mask means every tile is kept.  The record's instances and
 // gradient slots follow its kept tiles in rectangle row-major order.
+
+__device__ __forceinline__ int32_t kept_count(const uint4& ts) {
+    const uint64_t mask = (uint64_t)ts.x | ((uint64_t)ts.y << 32);
+    return mask ? (int32_t)__popcll(mask) : (int32_t)(ts.w & 0xffffu) * (int32_t)(ts.w >> 16);
+}
 
 // Index among the kept tiles of the tile at rectangle bit `bit`.
 __device__ __forceinline__ int32_t kept_rank(uint64_t mask, int32_t bit) {

@@ -261,7 +261,7 @@ __global__ __launch_bounds__(kProjBlk) void k_project(const ViewDev* __restrict_
                                                       int64_t N, int32_t tw, int32_t th,
                                                       const float* __restrict__ params,
                                                       pg_splat* __restrict__ splats, pg_bin* __restrict__ bins,
-                                                      uint64_t* __restrict__ tile_mask,
+                                                      pg_tile_set* __restrict__ tiles,
                                                       uint8_t* __restrict__ visible) {
     constexpr int NB = (L + 1) * (L + 1);
     __shared__ double s_geo[7][kProjBlk];       // mean x, y; conic A, B, C; slopes -B/C, -B/A
@@ -392,8 +392,11 @@ __global__ __launch_bounds__(kProjBlk) void k_project(const ViewDev* __restrict_
         __syncthreads();
         const uint64_t tmask = ntest ? (uint64_t)s_mask[tid] : 0ull;
         const int32_t nt = ntest ? (int32_t)__popcll(tmask) : nrect;
+        uint4 ts = make_uint4(0u, 0u, 0u, 0u);
         if (nt > 0) {
             bo.w = (uint32_t)nt;
+            ts = make_uint4((uint32_t)tmask, (uint32_t)(tmask >> 32), bo.x,
+                            (uint32_t)(ixh - ixl + 1) | ((uint32_t)(iyh - iyl + 1) << 16));
             any = true;
         } else {
             bo = make_uint4(0u, 0u, 0u, 0u);
@@ -405,7 +408,7 @@ __global__ __launch_bounds__(kProjBlk) void k_project(const ViewDev* __restrict_
             sp[1] = o1;
             sp[2] = o2;
             reinterpret_cast<uint4*>(bins)[gv] = bo;
-            tile_mask[gv] = tmask;
+            reinterpret_cast<uint4*>(tiles)[gv] = ts;
         }
     }
     if (any) visible[g] = 1;
@@ -722,13 +725,13 @@ __global__ __launch_bounds__(kSumRecs) void k_slot_sum(const pg_bin* __restrict_
 }  // namespace
 
 hipError_t launch_project(const pg_views* v, const float* params, pg_splat* splats, pg_bin* bins,
-                          uint64_t* tile_mask, uint8_t* visible, hipStream_t s) {
+                          pg_tile_set* tiles, uint8_t* visible, hipStream_t s) {
     const int64_t n = (int64_t)v->frames * v->n_gauss;
     if (n == 0) return hipSuccess;
     const unsigned grid = (unsigned)ceil_div(n, 128);
     auto args = [&](auto kern) {
         kern<<<grid, 128, 0, s>>>(v->d_views, v->d_frame_views, v->d_view_order, v->frames, v->channels, v->n_gauss,
-                                  v->tiling.tile_w, v->tiling.tile_h, params, splats, bins, tile_mask, visible);
+                                  v->tiling.tile_w, v->tiling.tile_h, params, splats, bins, tiles, visible);
     };
     switch (v->sh_degree) {
         case 0: args(k_project<0>); break;

@@ -320,8 +320,7 @@ __device__ __forceinline__ int total_index(int lane) {
 template <int TW, int TH, int BATCH>
 __global__ __launch_bounds__(kLanes) void k_render_bwd(const ViewDev* __restrict__ views, int nv, int64_t n_tiles,
                                                        const pg_splat* __restrict__ splats,
-                                                       const pg_bin* __restrict__ bins,
-                                                       const uint64_t* __restrict__ tile_mask,
+                                                       const pg_tile_set* __restrict__ tiles,
                                                        const int32_t* __restrict__ values,
                                                        const int2* __restrict__ ranges,
                                                        const int32_t* __restrict__ inst_first,
@@ -378,11 +377,11 @@ __global__ __launch_bounds__(kLanes) void k_render_bwd(const ViewDev* __restrict
             const uint32_t word = entries[rg.x + bstart + i];
             s_word[i] = word;
             const int32_t gv = values[rg.x + (int32_t)(word >> 4)];
-            const uint2 r = *reinterpret_cast<const uint2*>(bins + gv);     // tile rectangle of the record
-            const int32_t xlo = (int32_t)(r.x & 0xffff), ylo = (int32_t)(r.x >> 16);
-            const int32_t xhi = (int32_t)(r.y & 0xffff);
-            const int32_t slot =
-                inst_first[gv] + kept_rank(tile_mask[gv], (t.ty - ylo) * (xhi - xlo + 1) + (t.tx - xlo));
+            const uint4 ts = reinterpret_cast<const uint4*>(tiles)[gv];     // the record's kept tiles
+            const int32_t xlo = (int32_t)(ts.z & 0xffff), ylo = (int32_t)(ts.z >> 16);
+            const int32_t w = (int32_t)(ts.w & 0xffff);
+            const uint64_t mask = (uint64_t)ts.x | ((uint64_t)ts.y << 32);
+            const int32_t slot = inst_first[gv] + kept_rank(mask, (t.ty - ylo) * w + (t.tx - xlo));
             s_slot[i] = (slot >= 0 && slot < n_inst) ? slot : -1;
             stage<TW, TH, false>(splats, gv, t.ox, t.oy, t.col0, t.row0, s_geo, s_col, s_blu, nullptr, i);
         }
@@ -485,13 +484,13 @@ void fwd_launch(const pg_views* v, const pg_splat* splats, const int32_t* values
 }
 
 template <int TW, int TH, int BATCH>
-void bwd_launch(const pg_views* v, const pg_splat* splats, const pg_bin* bins, const uint64_t* tile_mask,
+void bwd_launch(const pg_views* v, const pg_splat* splats, const pg_tile_set* tiles,
                 const int32_t* values,
                 const int32_t* ranges, const int32_t* inst_first, const int32_t* tile_entries,
                 const uint32_t* entries, const int32_t* n_contrib, const float bg[3], const float* final_T,
                 const float* dL_dimage, const int64_t* n_inst_dev, int64_t cap, float* inst_grad, hipStream_t s) {
     k_render_bwd<TW, TH, BATCH><<<(unsigned)v->n_tiles, kLanes, 0, s>>>(
-        v->d_views, v->n_views, v->n_tiles, splats, bins, tile_mask, values, reinterpret_cast<const int2*>(ranges),
+        v->d_views, v->n_views, v->n_tiles, splats, tiles, values, reinterpret_cast<const int2*>(ranges),
         inst_first, tile_entries, entries, n_contrib, bg[0], bg[1], bg[2], final_T, dL_dimage, n_inst_dev, cap, inst_grad);
 }
 
@@ -530,14 +529,13 @@ hipError_t launch_render_fwd(const pg_views* v, const pg_splat* splats, const in
     return hipGetLastError();
 }
 
-hipError_t launch_render_bwd(const pg_views* v, const pg_splat* splats, const pg_bin* bins,
-                             const uint64_t* tile_mask, const int32_t* values, const int32_t* ranges,
+hipError_t launch_render_bwd(const pg_views* v, const pg_splat* splats, const pg_tile_set* tiles, const int32_t* values, const int32_t* ranges,
                              const int32_t* inst_first, const int32_t* tile_entries,
                              const uint32_t* entries, const int32_t* n_contrib, const float bg[3],
                              const float* final_T, const float* dL_dimage, const int64_t* n_inst_dev, int64_t cap,
                              float* inst_grad, hipStream_t s) {
     if (v->n_tiles == 0) return hipSuccess;
-    dispatch<BwdRun>(v->tiling, v, splats, bins, tile_mask, values, ranges, inst_first, tile_entries, entries, n_contrib, bg,
+    dispatch<BwdRun>(v->tiling, v, splats, tiles, values, ranges, inst_first, tile_entries, entries, n_contrib, bg,
                      final_T, dL_dimage, n_inst_dev, cap, inst_grad, s);
     return hipGetLastError();
 }

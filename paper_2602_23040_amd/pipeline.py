@@ -44,7 +44,7 @@ class _ViewSet:
         n_gv = self.info.n_gv
         self.splats = torch.empty(max(n_gv, 1) * abi.SPLAT_BYTES // 4, dtype=torch.float32, device=device)
         self.bins = torch.empty(max(n_gv, 1) * abi.BIN_BYTES // 4, dtype=torch.int32, device=device)
-        self.tile_mask = torch.empty(max(n_gv, 1), dtype=torch.int64, device=device)
+        self.tiles = torch.empty(2 * max(n_gv, 1), dtype=torch.int64, device=device)   # pg_tile_set [n_gv]
         self.grad2d = torch.empty(max(9 * n_gv, 1), dtype=torch.float32, device=device)
         self.ranges = torch.empty(2 * max(self.info.n_tiles, 1), dtype=torch.int32, device=device)
         self.tile_entries = torch.empty(max(self.info.n_tiles, 1), dtype=torch.int32, device=device)
@@ -171,14 +171,14 @@ class Renderer:
                            self.texel_gauss, self.params, self.n_gauss_dev, self.fetch_ws, self.fetch_ws_bytes)
 
     def _project_sort_render(self, s: _ViewSet, pix_off: int, counters):
-        abi.pg_project(s.handle, self.params, s.splats, s.bins, s.tile_mask, self.visible)
-        abi.pg_bin_sort(s.handle, s.bins, s.tile_mask, s.cap, s.keys, s.values, s.ranges, s.inst_first, s.n_inst, s.overflow,
+        abi.pg_project(s.handle, self.params, s.splats, s.bins, s.tiles, self.visible)
+        abi.pg_bin_sort(s.handle, s.bins, s.tiles, s.cap, s.keys, s.values, s.ranges, s.inst_first, s.n_inst, s.overflow,
                         s.inst_grad, s.ws, s.ws_bytes)
         if not self.batched:
             # plain path: one instance-count synchronisation per view
             if int(s.overflow.item()):
                 s.set_capacity(int(math.ceil(int(s.n_inst.item()) * 1.25)))
-                abi.pg_bin_sort(s.handle, s.bins, s.tile_mask, s.cap, s.keys, s.values, s.ranges, s.inst_first, s.n_inst,
+                abi.pg_bin_sort(s.handle, s.bins, s.tiles, s.cap, s.keys, s.values, s.ranges, s.inst_first, s.n_inst,
                                 s.overflow, s.inst_grad, s.ws, s.ws_bytes)
         abi.pg_render_fwd(s.handle, s.splats, s.values, s.ranges, self.bg, self._off(self.image, 3 * pix_off),
                           self._off(self.final_T, pix_off), self._off(self.n_contrib, pix_off), s.tile_entries,
@@ -206,7 +206,7 @@ class Renderer:
         assert g.is_contiguous() and g.numel() == 3 * self.n_pixels
         if self.batched:
             s = self.sets[0]
-            abi.pg_render_bwd(s.handle, s.splats, s.bins, s.tile_mask, s.values, s.ranges, s.inst_first, s.n_inst, s.cap,
+            abi.pg_render_bwd(s.handle, s.splats, s.tiles, s.values, s.ranges, s.inst_first, s.n_inst, s.cap,
                               s.tile_entries, s.entries, self.n_contrib, self.bg, self.final_T, g, s.inst_grad)
             abi.pg_project_bwd(s.handle, self.params, s.bins, s.inst_first, s.n_inst, s.cap,
                                s.inst_grad, self.gauss_texel, self.dynamic, self.H, self.W, s.grad2d, self.dL_datlas, 0)
@@ -214,7 +214,7 @@ class Renderer:
             self.dL_datlas.zero_()
             for k, s in enumerate(self.sets):
                 po = self.pix_base[k]
-                abi.pg_render_bwd(s.handle, s.splats, s.bins, s.tile_mask, s.values, s.ranges, s.inst_first, s.n_inst, s.cap,
+                abi.pg_render_bwd(s.handle, s.splats, s.tiles, s.values, s.ranges, s.inst_first, s.n_inst, s.cap,
                                   s.tile_entries, s.entries, self._off(self.n_contrib, po), self.bg,
                                   self._off(self.final_T, po), self._off(g, 3 * po), s.inst_grad)
                 abi.pg_project_bwd(s.handle, self.params, s.bins, s.inst_first, s.n_inst, s.cap,
@@ -254,9 +254,11 @@ class Renderer:
         s = self.sets[k]
         return s.bins.cpu().numpy().view(np.uint8)[:s.info.n_gv * 16].view(dt)
 
-    def tile_masks(self, k=0):
+    def tile_sets(self, k=0):
+        """numpy structured view of a view set's pg_tile_set records."""
+        dt = np.dtype([("mask", "<u8"), ("x_lo", "<i2"), ("y_lo", "<i2"), ("width", "<u2"), ("height", "<u2")])
         s = self.sets[k]
-        return s.tile_mask[:s.info.n_gv].cpu().numpy().view(np.uint64)
+        return s.tiles.cpu().numpy().view(np.uint8)[:s.info.n_gv * 16].view(dt)
 
     def sorted_instances(self, k=0):
         s = self.sets[k]

@@ -70,7 +70,7 @@ def test_full_size_sampled_parity(cfg):
     fw = oracle.Forward(sc, views=views)
     assert fw.n_gauss == N
     spl, bins = r.splat_records(), r.bin_records()
-    masks = r.tile_masks()
+    tsets = r.tile_sets()
     keys, vals = r.sorted_instances()
     tb = r.sets[0].tile_base
     ranges = r.sets[0].ranges.cpu().numpy().reshape(-1, 2).astype(np.int64)
@@ -86,7 +86,12 @@ def test_full_size_sampled_parity(cfg):
         assert np.array_equal(b["rect"][valid], pr["rect"][valid].astype(np.int16))
         assert np.array_equal(b["key"][valid], pr["key"][valid])
         assert np.array_equal(b["n_tiles"][valid], pr["n_tiles"][valid]), f"view {v}: kept-tile counts differ"
-        assert np.array_equal(masks[sl][valid], pr["tile_mask"][valid]), f"view {v}: kept-tile masks differ"
+        ts = tsets[sl]
+        assert np.array_equal(ts["mask"][valid], pr["tile_mask"][valid]), f"view {v}: kept-tile masks differ"
+        assert np.array_equal(ts["x_lo"][valid], pr["rect"][valid, 0]) and np.array_equal(ts["y_lo"][valid], pr["rect"][valid, 1])
+        assert np.array_equal(ts["width"][valid], pr["rect"][valid, 2] - pr["rect"][valid, 0] + 1)
+        assert np.array_equal(ts["height"][valid], pr["rect"][valid, 3] - pr["rect"][valid, 1] + 1)
+        assert not ts.view(np.uint8).reshape(-1, 16)[~valid].any(), f"view {v}: culled tile sets not zero"
         assert np.array_equal(s["mean"][valid], pr["mean"][valid]), f"view {v}: FP64 means differ"
         # this view's tile lists: a contiguous slice of the sorted instances
         rg = ranges[tb[v]:tb[v + 1]]

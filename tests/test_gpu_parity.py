@@ -58,7 +58,7 @@ def test_fetch_project_sort_bit_exact(name):
     P = r.params[:sc.frames * sc.C * N].cpu().numpy().reshape(sc.frames, sc.C, N)
     assert np.array_equal(P.astype(np.float64), fw.params)
     spl, bins = r.splat_records(), r.bin_records()
-    masks = r.tile_masks()
+    tsets = r.tile_sets()
     keys, vals = r.sorted_instances()
     tb = r.sets[0].tile_base
     exp_keys, exp_vals = [], []
@@ -71,7 +71,12 @@ def test_fetch_project_sort_bit_exact(name):
         assert np.array_equal(b["rect"][valid], pr["rect"][valid].astype(np.int16))
         assert np.array_equal(b["key"][valid], pr["key"][valid])
         assert np.array_equal(b["n_tiles"][valid], pr["n_tiles"][valid]), f"view {v}: kept-tile counts differ"
-        assert np.array_equal(masks[sl][valid], pr["tile_mask"][valid]), f"view {v}: kept-tile masks differ"
+        ts = tsets[sl]
+        assert np.array_equal(ts["mask"][valid], pr["tile_mask"][valid]), f"view {v}: kept-tile masks differ"
+        assert np.array_equal(ts["x_lo"][valid], pr["rect"][valid, 0]) and np.array_equal(ts["y_lo"][valid], pr["rect"][valid, 1])
+        assert np.array_equal(ts["width"][valid], pr["rect"][valid, 2] - pr["rect"][valid, 0] + 1)
+        assert np.array_equal(ts["height"][valid], pr["rect"][valid, 3] - pr["rect"][valid, 1] + 1)
+        assert not ts.view(np.uint8).reshape(-1, 16)[~valid].any(), f"view {v}: culled tile sets not zero"
         assert np.array_equal(s["mean"][valid], pr["mean"][valid]), f"view {v}: FP64 means differ"
         np.testing.assert_allclose(s["conic"][valid], pr["conic"][valid], rtol=1e-6, atol=1e-9)
         np.testing.assert_allclose(s["opacity"][valid], pr["opacity"][valid], rtol=1e-6)
