@@ -503,24 +503,29 @@ hipError_t radix_pass(int bits, const K* ki, const int32_t* vi, K* ko, int32_t* 
 
 // [start, end) of every tile from the sorted keys: a tile starts where the key
 // differs from its predecessor, which is also where the previous tile ends.
-// One thread per key; the predecessor comes from the neighbouring lane (only
-// the first lane of a wave loads it), so every key is read once.
+// One thread per key, over a fixed grid that strides through the device-side
+// count (a grid sized for the capacity was mostly empty groups); the
+// predecessor comes from the neighbouring lane (only the first lane of a wave
+// loads it), so every key is read once.
+constexpr int kRangeGrid = 4096;
 __global__ __launch_bounds__(256) void k_ranges(const uint32_t* __restrict__ keys, const int64_t* __restrict__ misc,
                                                 int32_t* __restrict__ ranges) {
     const int64_t I = misc[1];
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if ((int64_t)blockIdx.x * blockDim.x >= I) return;   // whole group past the end (uniform)
-    const uint32_t k = i < I ? keys[i] : 0u;
-    uint32_t prev = __shfl_up(k, 1, 64);
-    if ((threadIdx.x & 63) == 0 && i > 0 && i < I) prev = keys[i - 1];
-    if (i >= I) return;
-    if (i == 0) {
-        ranges[2 * (int64_t)k] = 0;
-    } else if (prev != k) {
-        ranges[2 * (int64_t)k] = (int32_t)i;
-        ranges[2 * (int64_t)prev + 1] = (int32_t)i;
+    for (int64_t base = (int64_t)blockIdx.x * 256; base < I; base += (int64_t)gridDim.x * 256) {
+        const int64_t i = base + threadIdx.x;
+        const uint32_t k = i < I ? keys[i] : 0u;
+        uint32_t prev = __shfl_up(k, 1, 64);
+        if ((threadIdx.x & 63) == 0 && i > 0 && i < I) prev = keys[i - 1];
+        if (i < I) {
+            if (i == 0) {
+                ranges[2 * (int64_t)k] = 0;
+            } else if (prev != k) {
+                ranges[2 * (int64_t)k] = (int32_t)i;
+                ranges[2 * (int64_t)prev + 1] = (int32_t)i;
+            }
+            if (i == I - 1) ranges[2 * (int64_t)k + 1] = (int32_t)I;
+        }
     }
-    if (i == I - 1) ranges[2 * (int64_t)k + 1] = (int32_t)I;
 }
 
 }  // namespace
@@ -586,7 +591,7 @@ hipError_t launch_bin_sort(const pg_views* v, const pg_bin* bins, const pg_tile_
         uint32_t* tk = ta; ta = tb; tb = tk;
         int32_t* tv = tva; tva = tvb; tvb = tv;
     }
-    k_ranges<<<(unsigned)imax(1, ceil_div(cap, 256)), 256, 0, s>>>(keys, w.misc, ranges);
+    k_ranges<<<(unsigned)imax(1, imin(kRangeGrid, ceil_div(cap, 256))), 256, 0, s>>>(keys, w.misc, ranges);
     // 6. zero the adjoint's per-instance gradient slots (instances nobody composites keep 0)
     if (inst_grad) return fill_u32_dev(inst_grad, 0u, n_inst_dev, cap, 9, s);
     return hipGetLastError();
