@@ -18,6 +18,8 @@ Parity status of each function (what pins it; see ``tests/test_oracle_*.py``):
   backward          -- two-Gaussian closed-form derivatives; central finite
                        differences of the forward with frozen decisions.
   loss_l1, adam     -- textbook closed forms.
+  fake_quant        -- unit-step grid against numpy's rint, brute-force nearest level,
+                       endpoints, monotonicity, untouched texels and channels.
 """
 from __future__ import annotations
 
@@ -68,6 +70,7 @@ def lib():
             "or_scatter": (None, [p, p, p, i32, i32, i32, i32, i64, p]),
             "or_fd_frozen": (f64, [p, i64, i32, i32, p, i32, i32, p, p, p, p, p, i64, i32, f64]),
             "or_adam": (None, [p, p, p, p, p, i64, f64, f64, f64, f64, i32]),
+            "or_fake_quant": (None, [p, p, i32, i32, i32, i32, p, p, p, p]),
             "or_num_threads": (i32, []),
         }
         for name, (res, args) in sig.items():
@@ -118,6 +121,20 @@ def fetch(atlas: np.ndarray, occ: np.ndarray):
     got = lib().or_fetch(_p(atlas), _p(occ), F, Cc, H, W, _p(ids), _p(params))
     assert got == n
     return ids[:n], np.ascontiguousarray(params[:, :, :n])
+
+
+def fake_quant(atlas: np.ndarray, occ: np.ndarray, bits):
+    """LPO proxy of an atlas (F, C, H, W): returns (proxy atlas, range (C, 2), codes uint16)."""
+    atlas = np.ascontiguousarray(atlas, np.float32)
+    occ = np.ascontiguousarray(occ, np.uint8)
+    F, Cc, H, W = atlas.shape
+    b = np.ascontiguousarray(bits, np.int32)
+    assert b.shape == (Cc,)
+    out = np.empty_like(atlas)
+    rng = np.zeros((Cc, 2), np.float32)
+    codes = np.zeros(atlas.shape, np.uint16)
+    lib().or_fake_quant(_p(atlas), _p(occ), F, Cc, H, W, _p(b), _p(rng), _p(out), _p(codes))
+    return out, rng, codes
 
 
 def project(params_f: np.ndarray, sh_degree: int, cam, tw: int, th: int) -> np.ndarray:
@@ -248,12 +265,20 @@ def adam(p, g, m, v, visible, lr, b1, b2, eps, t):
 class Forward:
     """Oracle forward pass over every view of a scene."""
 
-    def __init__(self, scene, views=None, bg=None, counts=False):
+    def __init__(self, scene, views=None, bg=None, counts=False, quant_bits=None):
+        """quant_bits: per-channel bit widths of the LPO proxy (None: no
+        quantisation).  With a proxy the whole pass runs on it, and the
+        straight-through texel gradient is the gradient at the proxy."""
         self.scene = scene
         tl = scene.tiling
         self.tw, self.th = tl.tile_w, tl.tile_h
         self.bg = tuple(scene.bg if bg is None else bg)
-        self.ids, self.params = fetch(scene.atlas, scene.occupancy)
+        atlas = scene.atlas
+        self.quant = None
+        if quant_bits is not None:
+            atlas, rng, codes = fake_quant(scene.atlas, scene.occupancy, quant_bits)
+            self.quant = (rng, codes)
+        self.ids, self.params = fetch(atlas, scene.occupancy)
         self.views = list(range(len(scene.cams))) if views is None else list(views)
         self.proj, self.inst, self.ranges = {}, {}, {}
         self.image, self.T, self.n, self.counts = {}, {}, {}, {}

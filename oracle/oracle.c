@@ -23,6 +23,9 @@
  *   - Gradient freezing grad <- D_i grad: Sec. 4.2 "Gradient Freezing".
  *   - L1 photometric term: Sec. 4.2 "Objective" with lambda_ssim = 0.
  *   - Sparse Adam on FP32 master weights: Sec. 4.3 LPO paragraph.
+ *   - LPO fake quantiser (uniform K-bit proxy, straight-through gradient,
+ *     per-channel min/max scale): Sec. 4.3 LPO paragraph, supplementary
+ *     low-precision training and video-coding sections.
  * Where the paper is silent (alpha rule, termination, SH basis, camera axes,
  * activations, tie-breaks) the readings listed in the design notes are used;
  * each is restated next to the code that takes it.
@@ -919,6 +922,59 @@ void or_adam(double* p, const double* g, double* m, double* v, const uint8_t* vi
         v[e] = b2 * v[e] + (1.0 - b2) * g[e] * g[e];
         const double mh = m[e] / c1, vh = v[e] / c2;
         p[e] = p[e] - lr * mh / (sqrt(vh) + eps);
+    }
+}
+
+/* ------------------------------------------------------------------ LPO fake quantiser
+ * Low-precision optimisation (Sec. 4.3 LPO paragraph; supplementary,
+ * low-precision training): the renderer consumes a uniform K-bit proxy of
+ * the texel values, gradients pass straight through to the FP32 master
+ * values, and the scale comes from a per-channel min/max normalisation (the
+ * video-coding section normalises each channel by its min/max).  Reading:
+ * per channel c with K = bits[c] > 0, lo / hi = min / max over the occupied
+ * texels of every frame, levels = 2^K - 1, delta = (hi - lo) / levels,
+ * code = clamp(rint((v - lo) / delta), 0, levels), proxy = lo + code delta.
+ * The code is an integer decided by floating point, so it is computed in the
+ * precision of the texels, FP32, each operation rounded once (no
+ * contraction), ties to even; delta = 0 gives code 0 and proxy lo.
+ * Unoccupied texels and channels with bits[c] = 0 are copied unchanged.
+ *   range  float [C][2] out (lo, hi; 0, 0 for unquantised channels)
+ *   codes  uint16 [F][C][H][W] out or NULL (0 where nothing is quantised) */
+void or_fake_quant(const float* atlas, const uint8_t* occ, int32_t F, int32_t C, int32_t H, int32_t W,
+                   const int32_t* bits, float* range, float* out, uint16_t* codes) {
+    const int64_t HW = (int64_t)H * W;
+    memcpy(out, atlas, sizeof(float) * (size_t)((int64_t)F * C * HW));
+    if (codes) memset(codes, 0, sizeof(uint16_t) * (size_t)((int64_t)F * C * HW));
+    for (int32_t c = 0; c < C; c++) {
+        range[2 * c] = range[2 * c + 1] = 0.0f;
+        if (bits[c] <= 0) continue;
+        float lo = INFINITY, hi = -INFINITY;
+        for (int32_t f = 0; f < F; f++)
+            for (int64_t p = 0; p < HW; p++)
+                if (occ[p]) {
+                    const float v = atlas[((int64_t)f * C + c) * HW + p];
+                    lo = fminf(lo, v);
+                    hi = fmaxf(hi, v);
+                }
+        if (lo > hi) continue;   /* no occupied texel */
+        range[2 * c] = lo;
+        range[2 * c + 1] = hi;
+        const float levels = (float)((1 << bits[c]) - 1);
+        const float delta = (hi - lo) / levels;
+        for (int32_t f = 0; f < F; f++)
+            for (int64_t p = 0; p < HW; p++) {
+                if (!occ[p]) continue;
+                const int64_t e = ((int64_t)f * C + c) * HW + p;
+                float k = 0.0f;
+                if (delta > 0.0f) {
+                    const float d = atlas[e] - lo;
+                    k = rintf(d / delta);
+                    k = fminf(fmaxf(k, 0.0f), levels);
+                }
+                const float step = k * delta;
+                out[e] = lo + step;
+                if (codes) codes[e] = (uint16_t)k;
+            }
     }
 }
 
