@@ -64,6 +64,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--no-lpo", action="store_true",
+                    help="skip the step with the LPO fake quantiser (reported under 'lpo')")
     ap.add_argument("--also-configs", type=str, default="",
                     help="comma-separated workload numbers (2, 4, 5) whose batched and plain steps are also timed "
                          "and reported under 'other_configs' (off by default: config 4 and 5 scenes take a minute "
@@ -216,7 +218,7 @@ def main():
         "render_fwd": ("alu", (FLOP_EVAL * n_eval + FLOP_COMP * n_comp) / 1e12, "TFLOP/s", PEAK_FP32_TFLOPS),
         "render_bwd": ("alu", FLOP_BWD * n_comp / 1e12, "TFLOP/s", PEAK_FP32_TFLOPS),
         "bin_sort": ("hbm", (SORT_BYTES_PER_PASS * sort_passes * n_inst + 28 * n_inst) / 1e9, "GB/s", PEAK_HBM_GBS),
-        "project": ("hbm", (4 * sc.C * N + 64 * N * V) / 1e9, "GB/s", PEAK_HBM_GBS),
+        "project": ("hbm", (4 * sc.C * N + 80 * N * V) / 1e9, "GB/s", PEAK_HBM_GBS),
     }
     dom = max(stages, key=lambda k: stages[k])
     roof = None
@@ -232,6 +234,7 @@ def main():
                 "frac": None, "traffic": None, "ms": round(stages[dom], 4)}
 
     cpu = None if args.no_cpu_baseline else cpu_baseline(sc, rb, target, args.cpu_seconds)
+    lpo = None if args.no_lpo else lpo_leg(sc, atlas, target, tiling, args.steps, args.warmup, not args.no_graph)
 
     out = {
         "metric": "fwd+bwd Mpixels/s & Gaussians/s, batched vs plain, at oracle-matched tolerance",
@@ -259,6 +262,7 @@ def main():
         "stages_ms": {k: round(v, 4) for k, v in stages.items()},
         "roofline": roof,
         "cpu_baseline": cpu,
+        "lpo": lpo,
         "autotune": tune_info,
     }
     rb.close()
@@ -268,6 +272,72 @@ def main():
         out["other_configs"] = [other_config(int(c), tiling, max(2, args.steps // 4), 2)
                                 for c in args.also_configs.split(",") if c.strip()]
     print(json.dumps(out), flush=True)
+
+
+def lpo_leg(sc, atlas, target, tiling, steps, warmup, graph):
+    """The same step with the LPO fake quantiser after the fetch (16-bit
+    position, 8-bit other channels), and the quantiser alone: its three
+    kernels read each fetched value twice and write it once (12 bytes per
+    value, HBM-bound), timed with events on the stream they run on."""
+    import torch
+
+    from paper_2602_23040_amd import _abi as abi
+    from paper_2602_23040_amd.pipeline import Renderer
+
+    dev = torch.device("cuda:0")
+    bits = abi.lpo_bits(sc.C)
+    r = Renderer(sc.occupancy, sc.frames, sc.sh_degree, sc.cams, tiling=tiling, batched=True, bg=sc.bg,
+                 dynamic=sc.dynamic, device=dev, quant_bits=bits)
+    r.forward(atlas)
+    torch.cuda.synchronize()
+    if r.overflowed():
+        r.grow_capacity(1.1)
+    stream = torch.cuda.current_stream()
+    if graph:
+        side = torch.cuda.Stream()
+        side.wait_stream(stream)
+        with torch.cuda.stream(side):
+            r.step(atlas, target)
+        stream.wait_stream(side)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            r.step(atlas, target)
+        torch.cuda.synchronize()
+        run = g.replay
+    else:
+        def run():
+            r.step(atlas, target)
+    for _ in range(warmup):
+        run()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(steps):
+        run()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    assert not r.overflowed()
+    # the quantiser alone (re-quantising the proxy does the same work)
+    reps = 20
+    F, C, N = sc.frames, sc.C, r.N
+    q0, q1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    q0.record(stream)
+    for _ in range(reps):
+        abi.pg_atlas_fake_quant(r.params, r.n_gauss_dev, N, F, C, bits, r.quant_range, None, r.quant_partial,
+                                stream)
+    q1.record(stream)
+    torch.cuda.synchronize()
+    qms = q0.elapsed_time(q1) / reps
+    nbytes = 12 * F * C * N
+    P = r.n_pixels
+    r.close()
+    gbs = nbytes / (qms / 1e3) / 1e9
+    return {"bits": "16 (x, y, z), 8 (other channels)", "ms_per_step": round(ms, 4),
+            "mpixels_per_s": round(P / ms / 1e3, 2), "fake_quant_ms": round(qms, 4),
+            "fake_quant_roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                                    "frac": round(gbs / PEAK_HBM_GBS, 4), "bytes": nbytes}}
 
 
 def other_config(cfg, tiling, steps, warmup):

@@ -162,6 +162,34 @@ pg_status pg_atlas_fetch(const float* atlas, const uint8_t* occupancy, int32_t f
                          int32_t H, int32_t W, int64_t n_cap, int32_t* gauss_texel, int32_t* texel_gauss,
                          float* params, int64_t* n_gauss_dev, void* ws, size_t ws_bytes, void* stream);
 
+/* Low-precision optimisation (LPO) -- the uniform K-bit fake quantiser the
+ * renderer consumes instead of the FP32 master texel values (Sec. 4.3 LPO
+ * paragraph; supplementary low-precision training section), with the
+ * per-channel min/max normalisation of the supplementary video-coding
+ * section.  Replaces the fetched values in place by their proxy: for channel
+ * c with K = bits[c] in [1, 16], lo / hi = min / max over the fetched
+ * Gaussians of every frame, delta = (hi - lo) / (2^K - 1),
+ * code = clamp(rint((v - lo) / delta), 0, 2^K - 1), proxy = lo + code delta,
+ * each step one FP32 operation rounded to nearest (rint: ties to even);
+ * delta = 0 gives code 0.  The paper's widths are 16 bits for the position
+ * and 8 for scale, rotation, opacity and colour.  Nothing changes in the
+ * adjoint: the straight-through estimator passes the gradient at the proxy
+ * to the FP32 master texels as it is (pg_project_bwd's output).
+ *   params       device float [F][C][n_cap] in/out (from pg_atlas_fetch)
+ *   n_gauss_dev  device int64 [1] (from pg_atlas_fetch); min(N, n_cap) values
+ *                per row are used
+ *   bits         host int32 [C], C <= 64: 0 leaves a channel unchanged
+ *   range        device float [C][2] out: (lo, hi); (0, 0) for channels left
+ *                alone or without values
+ *   codes        device uint16 [F][C][n_cap] out or NULL: the integer code of
+ *                each value (0 in channels left alone); 16-bit codes are what
+ *                the storage splits into two 8-bit planes
+ *   partial      device float [2 PG_QUANT_BLOCKS C] workspace */
+#define PG_QUANT_BLOCKS 256
+pg_status pg_atlas_fake_quant(float* params, const int64_t* n_gauss_dev, int64_t n_cap, int32_t frames,
+                              int32_t channels, const int32_t* bits, float* range, uint16_t* codes, float* partial,
+                              void* stream);
+
 /* a2 -- EWA projection (Sec. 4.2 masking equations; Algorithm 1 steps 1-4;
  * viewer projection).  For every view and every Gaussian of its frame:
  * activations s = exp(l_s), unit quaternion, o = sigmoid(l_o); mu_c = R mu + t,

@@ -18,6 +18,7 @@ STATUS_NAMES = {0: "PG_OK", -1: "PG_ERR_INVALID_ARG", -2: "PG_ERR_UNSUPPORTED_DE
 
 SPLAT_BYTES = 48
 BIN_BYTES = 16
+QUANT_BLOCKS = 256          # PG_QUANT_BLOCKS: the fake quantiser's workspace is 2 * QUANT_BLOCKS * C floats
 
 
 class PGError(RuntimeError):
@@ -59,6 +60,7 @@ SIGNATURES = {
     "pg_fetch_workspace_size": (_i32, [_i32, _i32, C.POINTER(_sz)]),
     "pg_sort_workspace_size": (_i32, [_p, _i64, C.POINTER(_sz)]),
     "pg_atlas_fetch": (_i32, [_p, _p, _i32, _i32, _i32, _i32, _i64, _p, _p, _p, _p, _p, _sz, _p]),
+    "pg_atlas_fake_quant": (_i32, [_p, _p, _i64, _i32, _i32, _p, _p, _p, _p, _p]),
     "pg_project": (_i32, [_p, _p, _p, _p, _p, _p, _p]),
     "pg_bin_sort": (_i32, [_p, _p, _p, _i64, _p, _p, _p, _p, _p, _p, _p, _p, _sz, _p]),
     "pg_render_fwd": (_i32, [_p, _p, _p, _p, _p, _p, _p, _p, _p, _p, _p, _p]),
@@ -184,6 +186,20 @@ def pg_atlas_fetch(atlas, occupancy, frames, channels, H, W, n_cap, gauss_texel,
     _check(lib().pg_atlas_fetch(_ptr(atlas), _ptr(occupancy), int(frames), int(channels), int(H), int(W), int(n_cap),
                                 _ptr(gauss_texel), _ptr(texel_gauss), _ptr(params), _ptr(n_gauss_dev), _ptr(ws),
                                 int(ws_bytes), _stream(stream)), "pg_atlas_fetch")
+
+
+def pg_atlas_fake_quant(params, n_gauss_dev, n_cap, frames, channels, bits, range_out, codes, partial, stream=None):
+    """LPO proxy in place; `bits` is a host sequence of per-channel widths."""
+    b = (C.c_int32 * int(channels))(*[int(x) for x in bits])
+    _check(lib().pg_atlas_fake_quant(_ptr(params), _ptr(n_gauss_dev), int(n_cap), int(frames), int(channels),
+                                     C.cast(b, _p), _ptr(range_out), _ptr(codes), _ptr(partial), _stream(stream)),
+           "pg_atlas_fake_quant")
+
+
+def lpo_bits(channels):
+    """The paper's LPO widths: 16 bits for the position (x, y, z), 8 for every
+    other channel (log-scale, quaternion, logit-opacity, SH)."""
+    return [16, 16, 16] + [8] * (int(channels) - 3)
 
 
 def pg_project(views, params, splats, bins, tiles, visible, stream=None):

@@ -329,6 +329,23 @@ pg_status pg_loss_l1(const float* image, const float* target, int64_t n, float* 
     return PG_OK;
 }
 
+pg_status pg_atlas_fake_quant(float* params, const int64_t* n_gauss_dev, int64_t n_cap, int32_t frames,
+                              int32_t channels, const int32_t* bits, float* range, uint16_t* codes, float* partial,
+                              void* stream) {
+    g_error.clear();
+    if (!n_gauss_dev || !bits || !range || !partial) return invalid("null pointer argument");
+    if (n_cap < 0 || (n_cap > 0 && !params)) return invalid("params is null with n_cap > 0");
+    if (frames < 1 || channels < 1 || channels > kMaxQuantChannels) return invalid("need frames >= 1, 1 <= channels <= 64");
+    if ((int64_t)frames * channels > 65535) return invalid("frames * channels must be <= 65535");
+    if (n_cap > ((int64_t)1 << 31)) return invalid("n_cap must be <= 2^31");
+    for (int c = 0; c < channels; c++)
+        if (bits[c] < 0 || bits[c] > 16) return invalid("bits must be in [0, 16]");
+    PG_CHECK_HIP(launch_fake_quant(params, n_gauss_dev, n_cap, frames, channels, bits, range, codes, partial,
+                                   (hipStream_t)stream),
+                 "pg_atlas_fake_quant");
+    return PG_OK;
+}
+
 pg_status pg_adam_step(float* atlas, const float* grad, float* m, float* v, const uint8_t* visible,
                        const int32_t* texel_gauss, int64_t n_gauss, int32_t frames, int32_t channels, int32_t H,
                        int32_t W, float lr, float beta1, float beta2, float eps, int32_t step, int32_t* step_dev,

@@ -74,6 +74,12 @@ hipError_t launch_fetch(const float* atlas, const uint8_t* occ, int32_t F, int32
                         int64_t n_cap, int32_t* gauss_texel, int32_t* texel_gauss, float* params,
                         int64_t* n_gauss_dev, void* ws, hipStream_t s);
 
+// quant.hip
+constexpr int kMaxQuantChannels = 64;       // channels a fake-quantiser call may hold
+constexpr int kQuantBlocks = PG_QUANT_BLOCKS;
+hipError_t launch_fake_quant(float* params, const int64_t* n_dev, int64_t n_cap, int32_t F, int32_t C,
+                             const int32_t* bits, float* range, uint16_t* codes, float* partial, hipStream_t s);
+
 // project.hip
 hipError_t launch_project(const pg_views* v, const float* params, pg_splat* splats, pg_bin* bins,
                           pg_tile_set* tiles, uint8_t* visible, hipStream_t s);

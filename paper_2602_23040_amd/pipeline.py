@@ -78,7 +78,9 @@ class Renderer:
     """
 
     def __init__(self, occupancy, frames, sh_degree, cams, tiling=(16, 16, 256), batched=True, bg=(0.0, 0.0, 0.0),
-                 dynamic=None, inst_capacity=None, device="cuda", init=True):
+                 dynamic=None, inst_capacity=None, device="cuda", init=True, quant_bits=None):
+        """quant_bits: per-channel widths of the LPO fake quantiser (e.g.
+        ``_abi.lpo_bits(C)``); None renders the FP32 texel values as they are."""
         self.device = torch.device(device)
         if init:
             abi.pg_init(self.device.index or 0)
@@ -102,6 +104,11 @@ class Renderer:
         self.n_gauss_dev = torch.zeros(1, dtype=torch.int64, device=dev)
         self.fetch_ws_bytes = abi.pg_fetch_workspace_size(self.H, self.W)
         self.fetch_ws = torch.empty(self.fetch_ws_bytes, dtype=torch.uint8, device=dev)
+        self.quant_bits = None if quant_bits is None else [int(b) for b in quant_bits]
+        if self.quant_bits is not None:
+            assert len(self.quant_bits) == self.C
+            self.quant_range = torch.zeros(2 * self.C, dtype=torch.float32, device=dev)
+            self.quant_partial = torch.empty(2 * abi.QUANT_BLOCKS * self.C, dtype=torch.float32, device=dev)
         self.visible = torch.zeros(max(self.frames * self.N, 1), dtype=torch.uint8, device=dev)
         self.dL_datlas = torch.empty(self.frames * self.C * self.H * self.W, dtype=torch.float32, device=dev)
         self.loss_partial = torch.empty(1024, dtype=torch.float64, device=dev)
@@ -169,6 +176,11 @@ class Renderer:
         assert atlas.numel() == self.frames * self.C * self.H * self.W
         abi.pg_atlas_fetch(atlas, self.occ, self.frames, self.C, self.H, self.W, self.N, self.gauss_texel,
                            self.texel_gauss, self.params, self.n_gauss_dev, self.fetch_ws, self.fetch_ws_bytes)
+        if self.quant_bits is not None:
+            # LPO: the rest of the step runs on the proxy; its texel gradient passes
+            # straight through to the FP32 master atlas
+            abi.pg_atlas_fake_quant(self.params, self.n_gauss_dev, self.N, self.frames, self.C, self.quant_bits,
+                                    self.quant_range, None, self.quant_partial)
 
     def _project_sort_render(self, s: _ViewSet, pix_off: int, counters):
         abi.pg_project(s.handle, self.params, s.splats, s.bins, s.tiles, self.visible)

@@ -33,11 +33,11 @@ def say(*a):
     sys.stdout.flush()
 
 
-def renderer(scene, batched=True, tiling=None, cap=None, dynamic="scene"):
+def renderer(scene, batched=True, tiling=None, cap=None, dynamic="scene", quant_bits=None):
     t = tiling or (scene.tiling.tile_w, scene.tiling.tile_h, scene.tiling.lds_batch)
     dyn = scene.dynamic if dynamic == "scene" else dynamic
     return Renderer(scene.occupancy, scene.frames, scene.sh_degree, scene.cams, tiling=t, batched=batched,
-                    bg=scene.bg, dynamic=dyn, inst_capacity=cap, device="cuda:0")
+                    bg=scene.bg, dynamic=dyn, inst_capacity=cap, device="cuda:0", quant_bits=quant_bits)
 
 
 def atlas_tensor(scene):

@@ -74,3 +74,19 @@ def test_entry_points_reject_null_pointers():
     n = C.c_size_t()
     assert lib.pg_fetch_workspace_size(0, 5, C.byref(n)) == -1
     assert lib.pg_fetch_workspace_size(64, 64, C.byref(n)) == 0 and n.value > 0
+
+
+def test_fake_quant_rejects_bad_arguments_on_the_host():
+    """Widths outside [0, 16], too many channels and missing buffers are
+    refused before any device work (the pointers below are never touched)."""
+    lib = abi.lib()
+    dummy = C.c_void_p(0x1000)
+    bits = (C.c_int32 * 3)(8, 17, 8)
+    assert lib.pg_atlas_fake_quant(dummy, dummy, 4, 1, 3, C.cast(bits, C.c_void_p), dummy, None, dummy, None) == -1
+    assert "bits" in abi.pg_last_error()
+    ok = (C.c_int32 * 3)(8, 8, 8)
+    assert lib.pg_atlas_fake_quant(dummy, dummy, 4, 1, 3, C.cast(ok, C.c_void_p), None, None, dummy, None) == -1
+    assert "null" in abi.pg_last_error()
+    many = (C.c_int32 * 65)(*([8] * 65))
+    assert lib.pg_atlas_fake_quant(dummy, dummy, 4, 1, 65, C.cast(many, C.c_void_p), dummy, None, dummy, None) == -1
+    assert abi.lpo_bits(59) == [16, 16, 16] + [8] * 56
