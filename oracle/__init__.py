@@ -18,6 +18,9 @@ Parity status of each function (what pins it; see ``tests/test_oracle_*.py``):
   backward          -- two-Gaussian closed-form derivatives; central finite
                        differences of the forward with frozen decisions.
   loss_l1, adam     -- textbook closed forms.
+  flow_mask         -- on-axis isotropic disc closed form (pixels just inside / outside
+                       3 sigma), brute force over every pixel of the image, OR across
+                       cameras, empty and full masks.
   fake_quant        -- unit-step grid against numpy's rint, brute-force nearest level,
                        endpoints, monotonicity, untouched texels and channels.
 """
@@ -71,6 +74,7 @@ def lib():
             "or_fd_frozen": (f64, [p, i64, i32, i32, p, i32, i32, p, p, p, p, p, i64, i32, f64]),
             "or_adam": (None, [p, p, p, p, p, i64, f64, f64, f64, f64, i32]),
             "or_fake_quant": (None, [p, p, i32, i32, i32, i32, p, p, p, p]),
+            "or_flow_mask": (None, [p, i64, i32, p, p, p]),
             "or_num_threads": (i32, []),
         }
         for name, (res, args) in sig.items():
@@ -121,6 +125,19 @@ def fetch(atlas: np.ndarray, occ: np.ndarray):
     got = lib().or_fetch(_p(atlas), _p(occ), F, Cc, H, W, _p(ids), _p(params))
     assert got == n
     return ids[:n], np.ascontiguousarray(params[:, :, :n])
+
+
+def flow_mask(params_f: np.ndarray, sh_degree: int, cam, mask: np.ndarray, D: np.ndarray | None = None):
+    """Dynamic labels (N,) uint8 of one frame's Gaussians for one camera's flow
+    mask (H, W), OR-ed into D when given."""
+    P = np.ascontiguousarray(params_f, np.float64)
+    Cc, N = P.shape
+    m = np.ascontiguousarray(mask, np.uint8)
+    assert m.shape == (cam.height, cam.width)
+    out = np.zeros(N, np.uint8) if D is None else D
+    assert out.dtype == np.uint8 and out.flags.c_contiguous
+    lib().or_flow_mask(_p(P), N, sh_degree, _p(cam_record(cam)), _p(m), _p(out))
+    return out
 
 
 def fake_quant(atlas: np.ndarray, occ: np.ndarray, bits):

@@ -23,6 +23,8 @@
  *   - Gradient freezing grad <- D_i grad: Sec. 4.2 "Gradient Freezing".
  *   - L1 photometric term: Sec. 4.2 "Objective" with lambda_ssim = 0.
  *   - Sparse Adam on FP32 master weights: Sec. 4.3 LPO paragraph.
+ *   - Covariance-aware flow masking (dynamic label per Gaussian, OR across
+ *     cameras): Sec. 4.2 masking paragraph and Algorithm 1.
  *   - LPO fake quantiser (uniform K-bit proxy, straight-through gradient,
  *     per-channel min/max scale): Sec. 4.3 LPO paragraph, supplementary
  *     low-precision training and video-coding sections.
@@ -922,6 +924,43 @@ void or_adam(double* p, const double* g, double* m, double* v, const uint8_t* vi
         v[e] = b2 * v[e] + (1.0 - b2) * g[e] * g[e];
         const double mh = m[e] / c1, vh = v[e] / c2;
         p[e] = p[e] - lr * mh / (sqrt(vh) + eps);
+    }
+}
+
+/* ------------------------------------------------------------------ flow masking
+ * Covariance-aware flow masking (Sec. 4.2 "Covariance-Aware Gaussian
+ * Masking", Algorithm 1): project the Gaussian with the EWA chain above
+ * (same culls; a culled projection leaves it static for this camera), take
+ * the sampling radius r = ceil(3 sqrt(lambda_max)), and scan the pixels whose
+ * centre (x + 0.5, y + 0.5) lies within r of the mean on both axes, inside
+ * the image; the Gaussian is dynamic for the camera when one of them has
+ * d^2 = q <= 9 (FP64, the conic of the projection) and a non-zero flow mask.
+ * D is OR-ed in place, so calling this for each camera of a frame gives the
+ * paper's OR across cameras.
+ *   mask  uint8 [H][W] of this camera;  D  uint8 [N] in/out */
+void or_flow_mask(const double* P, int64_t N, int32_t L, const or_camera* cam, const uint8_t* mask,
+                  uint8_t* D) {
+    const int32_t W = cam->width, H = cam->height;
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t i = 0; i < N; i++) {
+        if (D[i]) continue;
+        or_proj o;
+        project_one(P, N, i, L, cam, 16, 16, &o);
+        if (o.radius <= 0) continue;   /* culled: z or det */
+        const double r = (double)o.radius;
+        const double x0 = fmax(0.0, ceil(o.mean[0] - r - 0.5)), x1 = fmin((double)(W - 1), floor(o.mean[0] + r - 0.5));
+        const double y0 = fmax(0.0, ceil(o.mean[1] - r - 0.5)), y1 = fmin((double)(H - 1), floor(o.mean[1] + r - 0.5));
+        int hit = 0;
+        for (double y = y0; y <= y1 && !hit; y += 1.0)
+            for (double x = x0; x <= x1; x += 1.0) {
+                if (!mask[(int64_t)y * W + (int64_t)x]) continue;
+                const double dx = (x + 0.5) - o.mean[0], dy = (y + 0.5) - o.mean[1];
+                if (q_at(o.conic[0], o.conic[1], o.conic[2], dx, dy) <= 9.0) {
+                    hit = 1;
+                    break;
+                }
+            }
+        if (hit) D[i] = 1;
     }
 }
 
