@@ -212,6 +212,27 @@ pg_status pg_atlas_fake_quant(float* params, const int64_t* n_gauss_dev, int64_t
 pg_status pg_project(const pg_views* views, const float* params, pg_splat* splats, pg_bin* bins,
                      pg_tile_set* tiles, uint8_t* visible, void* stream);
 
+/* Covariance-aware flow masking (Sec. 4.2 "Covariance-Aware Gaussian
+ * Masking"; Algorithm 1): the dynamic labels D that gradient freezing uses.
+ * For every view and every Gaussian of its frame: the projection of
+ * pg_project (same FP64 chain and culls; a culled projection leaves the
+ * Gaussian static for that view) and the radius r = ceil(3 sqrt(lambda_max));
+ * the Gaussian is dynamic for the view when a pixel whose centre is within r
+ * of the mean on both axes, inside the image, has q <= 9 (FP64, at the pixel
+ * centre) and a non-zero flow mask.  D is the OR over the views of the
+ * Gaussian's frame (the paper's OR across cameras).
+ *   params       device float [F][C][n_gauss] (from pg_atlas_fetch)
+ *   flow_masks   device uint8 [n_pixels]: view v's [H_v][W_v] mask at its
+ *                pixel base; non-zero = motion
+ *   dyn_gauss    device uint8 [F][n_gauss] out: D per frame and Gaussian
+ *   texel_gauss  device int32 [H W] (from pg_atlas_fetch); read only with
+ *   dyn_texel    device uint8 [H W] out or NULL: 1 where the texel's Gaussian
+ *                is dynamic in some frame (the mask pg_project_bwd takes)
+ *   counters     device uint64 [1] or NULL: += pixel centres tested */
+pg_status pg_flow_mask(const pg_views* views, const float* params, const uint8_t* flow_masks, uint8_t* dyn_gauss,
+                       const int32_t* texel_gauss, int32_t H, int32_t W, uint8_t* dyn_texel, uint64_t* counters,
+                       void* stream);
+
 /* a3 -- Tile binning and depth sort (tile rasteriser, Sec. 3; per-camera
  * depth sort, viewer section).  Lists every surviving (view, Gaussian) once
  * per kept tile of its rectangle and orders each tile's list front to back by

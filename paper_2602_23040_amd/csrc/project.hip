@@ -414,6 +414,92 @@ __global__ __launch_bounds__(kProjBlk) void k_project(const ViewDev* __restrict_
     if (any) visible[g] = 1;
 }
 
+// ---------------------------------------------------------------- flow masking
+// Covariance-aware flow masking (Sec. 4.2 masking paragraph, Algorithm 1):
+// a Gaussian is dynamic when, in some view of its frame, a pixel whose centre
+// is within r = ceil(3 sqrt(lambda_max)) of the mean on both axes and inside
+// the image has q <= 9 and a non-zero flow mask (the OR across cameras).
+// One thread per Gaussian, its frame's views in turn until one marks it; the
+// projection chain, culls and radius are those of k_project.  Each row of the
+// square is scanned only where q <= 9 can hold: between the roots of the
+// row's quadratic in x, widened by a pixel on each side and by 1e-9 of the
+// discriminant's terms, so the FP64 test on each candidate's centre (mask
+// first) decides exactly as a scan of the whole square would.
+__global__ __launch_bounds__(128) void k_flow_mask(const ViewDev* __restrict__ views,
+                                                   const int32_t* __restrict__ frame_views,
+                                                   const int32_t* __restrict__ view_order, int32_t F, int32_t C,
+                                                   int64_t N, const float* __restrict__ params,
+                                                   const uint8_t* __restrict__ masks, uint8_t* __restrict__ dyn_gauss,
+                                                   unsigned long long* __restrict__ counters) {
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    uint64_t tests = 0;
+    if (g < (int64_t)F * N) {
+        const int32_t f = (int32_t)(g / N);
+        const int64_t i = g - (int64_t)f * N;
+        const float* P = params + (int64_t)f * C * N + i;
+        float rec[11];
+#pragma unroll
+        for (int k = 0; k < 11; k++) rec[k] = P[(int64_t)k * N];
+        World w;
+        world_chain(rec, w);
+        bool dyn = false;
+        for (int32_t vi = frame_views[f]; vi < frame_views[f + 1] && !dyn; vi++) {
+            const ViewDev& V = views[view_order[vi]];
+            Cam c;
+            if (!camera_chain(V, w, c) || !(c.det > kDetMin)) continue;   // culled: static for this view
+            const double tr = c.ap + c.cp;
+            const double lam = 0.5 * (tr + sqrt(fmax(0.0, tr * tr - 4.0 * c.det)));
+            const double rr = ceil(3.0 * sqrt(lam));
+            const double mx = (V.fx * c.xc) / c.zc + V.cx;
+            const double my = (V.fy * c.yc) / c.zc + V.cy;
+            const double A = c.cp / c.det, B = -c.bp / c.det, Cq = c.ap / c.det;
+            const double x0 = fmax(0.0, ceil(mx - rr - 0.5)), x1 = fmin((double)(V.W - 1), floor(mx + rr - 0.5));
+            const double y0 = fmax(0.0, ceil(my - rr - 0.5)), y1 = fmin((double)(V.H - 1), floor(my + rr - 0.5));
+            const uint8_t* M = masks + V.pix_base;
+            for (double y = y0; y <= y1 && !dyn; y += 1.0) {
+                const double dy = (y + 0.5) - my;
+                // q <= 9 on this row: A X^2 + 2 (B dy) X + (C dy^2 - 9) <= 0, X = x + 0.5 - mx
+                const double bq = B * dy, cdy = Cq * dy * dy;
+                const double disc = bq * bq - A * (cdy - 9.0);
+                const double slack = 1e-9 * (bq * bq + A * cdy + 9.0 * A);
+                if (disc + slack < 0.0) continue;
+                const double sq = sqrt(disc + slack);
+                const double xa = fmax(x0, floor(mx + (-bq - sq) / A - 0.5) - 1.0);
+                const double xb = fmin(x1, ceil(mx + (-bq + sq) / A - 0.5) + 1.0);
+                const uint8_t* row = M + (int64_t)y * V.W;
+                for (double x = xa; x <= xb; x += 1.0) {
+                    if (!row[(int64_t)x]) continue;
+                    tests++;
+                    if (q_at(A, B, Cq, (x + 0.5) - mx, dy) <= 9.0) {
+                        dyn = true;
+                        break;
+                    }
+                }
+            }
+        }
+        dyn_gauss[g] = dyn ? 1 : 0;
+    }
+    if (counters) {
+        unsigned long long t = tests;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o, 64);
+        if ((threadIdx.x & 63) == 0 && t) atomicAdd(counters, t);
+    }
+}
+
+// Texel form of the labels: 1 where the texel's Gaussian is dynamic in some frame.
+__global__ __launch_bounds__(256) void k_dyn_texel(const uint8_t* __restrict__ dyn_gauss,
+                                                   const int32_t* __restrict__ texel_gauss, int64_t HW, int32_t F,
+                                                   int64_t N, uint8_t* __restrict__ dyn_texel) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= HW) return;
+    const int32_t gi = texel_gauss[t];
+    uint8_t d = 0;
+    if (gi >= 0 && gi < N)
+        for (int32_t f = 0; f < F; f++) d |= dyn_gauss[(int64_t)f * N + gi];
+    dyn_texel[t] = d;
+}
+
 // ---------------------------------------------------------------- adjoint
 //
 // With Q the conic matrix and Gh = [[da, db/2], [db/2, dc]] (q = a dx^2 +
@@ -723,6 +809,21 @@ __global__ __launch_bounds__(kSumRecs) void k_slot_sum(const pg_bin* __restrict_
 }
 
 }  // namespace
+
+hipError_t launch_flow_mask(const pg_views* v, const float* params, const uint8_t* masks, uint8_t* dyn_gauss,
+                            const int32_t* texel_gauss, int64_t HW, uint8_t* dyn_texel, uint64_t* counters,
+                            hipStream_t s) {
+    const int64_t n = (int64_t)v->frames * v->n_gauss;
+    if (n > 0)
+        k_flow_mask<<<(unsigned)ceil_div(n, 128), 128, 0, s>>>(v->d_views, v->d_frame_views, v->d_view_order,
+                                                               v->frames, v->channels, v->n_gauss, params, masks,
+                                                               dyn_gauss,
+                                                               reinterpret_cast<unsigned long long*>(counters));
+    if (dyn_texel && HW > 0)
+        k_dyn_texel<<<(unsigned)ceil_div(HW, 256), 256, 0, s>>>(dyn_gauss, texel_gauss, HW, v->frames, v->n_gauss,
+                                                               dyn_texel);
+    return hipGetLastError();
+}
 
 hipError_t launch_project(const pg_views* v, const float* params, pg_splat* splats, pg_bin* bins,
                           pg_tile_set* tiles, uint8_t* visible, hipStream_t s) {

@@ -207,6 +207,19 @@ class Renderer:
             self._project_sort_render(s, self.pix_base[k] if not self.batched else 0, cnt)
         return self.image
 
+    def flow_mask(self, atlas: torch.Tensor, masks: torch.Tensor, counters=None):
+        """Covariance-aware flow masking of the fetched Gaussians against per-view
+        motion masks (uint8, the views' [H][W] masks concatenated like final_T):
+        returns (dyn_gauss [F N], dyn_texel [H W]), both uint8; dyn_texel is the
+        gradient-freezing mask the adjoint takes (set it as ``self.dynamic``)."""
+        assert self.batched, "flow masking runs on the batched view table"
+        assert masks.dtype == torch.uint8 and masks.numel() == self.n_pixels
+        self.fetch(atlas)
+        dg = torch.empty(max(self.frames * self.N, 1), dtype=torch.uint8, device=self.device)
+        dt = torch.empty(self.H * self.W, dtype=torch.uint8, device=self.device)
+        abi.pg_flow_mask(self.sets[0].handle, self.params, masks, dg, self.texel_gauss, self.H, self.W, dt, counters)
+        return dg[:self.frames * self.N], dt
+
     def loss_l1(self, target: torch.Tensor) -> torch.Tensor:
         n = 3 * self.n_pixels
         abi.pg_loss_l1(self.image, target, n, self.dL_dimage, self.loss_partial, self.loss)

@@ -317,3 +317,29 @@ def random_scene(side=16, sh_degree=0, views=1, width=64, height=48, seed=0,
         dyn = ((mrng.random((side, side)) < dynamic_frac) & (occ > 0)).astype(np.uint8)
     return Scene(f"random-{side}-{seed}", atlas, occ, cams, sh_degree,
                  tiling or Tiling(16, 16, 64), dynamic=dyn, seed=seed)
+
+
+def flow_masks(scene: Scene, seed: int, coverage: float = 0.2, mean_radius: float = 0.06) -> np.ndarray:
+    """Seeded stand-ins for per-camera motion masks (the thresholded, dilated
+    optical flow the paper computes from video, which this workload does not
+    have): for every view, random discs until about `coverage` of its pixels
+    are set.  Returns uint8 [n_pixels], the views' [H][W] masks concatenated in
+    view order (the layout of the rendered per-pixel buffers)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for cam in scene.cams:
+        H, W = cam.height, cam.width
+        m = np.zeros((H, W), np.uint8)
+        set_px, target = 0, coverage * H * W
+        while set_px < target:
+            cx, cy = rng.uniform(0, W), rng.uniform(0, H)
+            r = rng.uniform(0.5, 1.5) * mean_radius * min(H, W)
+            x0, x1 = max(0, int(cx - r)), min(W, int(cx + r) + 1)
+            y0, y1 = max(0, int(cy - r)), min(H, int(cy + r) + 1)
+            yy, xx = np.ogrid[y0:y1, x0:x1]
+            sub = m[y0:y1, x0:x1]
+            disc = (xx + 0.0 - cx) ** 2 + (yy + 0.0 - cy) ** 2 <= r * r
+            set_px += int(np.count_nonzero(disc & (sub == 0)))
+            sub[disc] = 1
+        out.append(m.reshape(-1))
+    return np.concatenate(out) if out else np.zeros(0, np.uint8)
