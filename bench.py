@@ -65,7 +65,8 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--no-lpo", action="store_true",
-                    help="skip the step with the LPO fake quantiser (reported under 'lpo')")
+                    help="skip the step with the LPO fake quantiser and the flow-masking timing (reported under "
+                         "'lpo' and 'flow_mask')")
     ap.add_argument("--also-configs", type=str, default="",
                     help="comma-separated workload numbers (2, 4, 5) whose batched and plain steps are also timed "
                          "and reported under 'other_configs' (off by default: config 4 and 5 scenes take a minute "
@@ -235,6 +236,7 @@ def main():
 
     cpu = None if args.no_cpu_baseline else cpu_baseline(sc, rb, target, args.cpu_seconds)
     lpo = None if args.no_lpo else lpo_leg(sc, atlas, target, tiling, args.steps, args.warmup, not args.no_graph)
+    fmask = None if args.no_lpo else flow_mask_leg(sc, rb, atlas)
 
     out = {
         "metric": "fwd+bwd Mpixels/s & Gaussians/s, batched vs plain, at oracle-matched tolerance",
@@ -263,6 +265,7 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
         "lpo": lpo,
+        "flow_mask": fmask,
         "autotune": tune_info,
     }
     rb.close()
@@ -272,6 +275,46 @@ def main():
         out["other_configs"] = [other_config(int(c), tiling, max(2, args.steps // 4), 2)
                                 for c in args.also_configs.split(",") if c.strip()]
     print(json.dumps(out), flush=True)
+
+
+# FP64 operations of the flow-masking kernel: the projection chain per
+# (Gaussian, view) (world and camera transforms, Sigma, Sigma_c, J, Sigma2D,
+# det, lambda_max, mean, conic: about 300) and the quadratic form per tested
+# pixel centre (9).
+FLOP64_FMASK_RECORD = 300
+FLOP64_FMASK_TEST = 9
+PEAK_FP64_TFLOPS = 78.6
+
+
+def flow_mask_leg(sc, r, atlas, reps=5):
+    """Covariance-aware flow masking of the workload's Gaussians against seeded
+    motion masks (discs over about 2 % of each view), timed with events on the
+    stream it runs on; FP64-bound (the projection chain per Gaussian-view and
+    the quadratic form per tested pixel)."""
+    import torch
+
+    import synth
+    masks = torch.from_numpy(synth.flow_masks(sc, seed=44, coverage=0.02, mean_radius=0.02)).to("cuda:0")
+    cnt = torch.zeros(1, dtype=torch.int64, device="cuda:0")
+    dg, _ = r.flow_mask(atlas, masks, counters=cnt)
+    torch.cuda.synchronize()
+    tests = int(cnt.item())
+    dyn = int(dg.sum().item())
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        r.flow_mask(atlas, masks)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps    # includes the fetch the call starts with (0.07 ms)
+    n_gv = r.N * len(sc.cams)
+    flops = FLOP64_FMASK_RECORD * n_gv + FLOP64_FMASK_TEST * tests
+    ach = flops / (ms / 1e3) / 1e12
+    return {"ms": round(ms, 4), "gaussian_views_per_s": round(n_gv / ms * 1e3, 1), "dynamic": dyn,
+            "gaussians": r.N * sc.frames, "pixel_tests": tests,
+            "roofline": {"bound": "alu", "achieved": round(ach, 3), "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s (FP64)",
+                         "frac": round(ach / PEAK_FP64_TFLOPS, 4)}}
 
 
 def lpo_leg(sc, atlas, target, tiling, steps, warmup, graph):

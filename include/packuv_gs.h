@@ -224,14 +224,16 @@ pg_status pg_project(const pg_views* views, const float* params, pg_splat* splat
  *   params       device float [F][C][n_gauss] (from pg_atlas_fetch)
  *   flow_masks   device uint8 [n_pixels]: view v's [H_v][W_v] mask at its
  *                pixel base; non-zero = motion
+ *   tile_motion  device uint8 [n_tiles] workspace: which screen tiles of the
+ *                view table hold motion (filled by the call)
  *   dyn_gauss    device uint8 [F][n_gauss] out: D per frame and Gaussian
  *   texel_gauss  device int32 [H W] (from pg_atlas_fetch); read only with
  *   dyn_texel    device uint8 [H W] out or NULL: 1 where the texel's Gaussian
  *                is dynamic in some frame (the mask pg_project_bwd takes)
  *   counters     device uint64 [1] or NULL: += pixel centres tested */
-pg_status pg_flow_mask(const pg_views* views, const float* params, const uint8_t* flow_masks, uint8_t* dyn_gauss,
-                       const int32_t* texel_gauss, int32_t H, int32_t W, uint8_t* dyn_texel, uint64_t* counters,
-                       void* stream);
+pg_status pg_flow_mask(const pg_views* views, const float* params, const uint8_t* flow_masks, uint8_t* tile_motion,
+                       uint8_t* dyn_gauss, const int32_t* texel_gauss, int32_t H, int32_t W, uint8_t* dyn_texel,
+                       uint64_t* counters, void* stream);
 
 /* a3 -- Tile binning and depth sort (tile rasteriser, Sec. 3; per-camera
  * depth sort, viewer section).  Lists every surviving (view, Gaussian) once

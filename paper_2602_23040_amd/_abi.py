@@ -62,7 +62,7 @@ SIGNATURES = {
     "pg_atlas_fetch": (_i32, [_p, _p, _i32, _i32, _i32, _i32, _i64, _p, _p, _p, _p, _p, _sz, _p]),
     "pg_atlas_fake_quant": (_i32, [_p, _p, _i64, _i32, _i32, _p, _p, _p, _p, _p]),
     "pg_project": (_i32, [_p, _p, _p, _p, _p, _p, _p]),
-    "pg_flow_mask": (_i32, [_p, _p, _p, _p, _p, _i32, _i32, _p, _p, _p]),
+    "pg_flow_mask": (_i32, [_p, _p, _p, _p, _p, _p, _i32, _i32, _p, _p, _p]),
     "pg_bin_sort": (_i32, [_p, _p, _p, _i64, _p, _p, _p, _p, _p, _p, _p, _p, _sz, _p]),
     "pg_render_fwd": (_i32, [_p, _p, _p, _p, _p, _p, _p, _p, _p, _p, _p, _p]),
     "pg_render_bwd": (_i32, [_p, _p, _p, _p, _p, _p, _p, _i64, _p, _p, _p, _p, _p, _p, _p, _p]),
@@ -197,8 +197,10 @@ def pg_atlas_fake_quant(params, n_gauss_dev, n_cap, frames, channels, bits, rang
            "pg_atlas_fake_quant")
 
 
-def pg_flow_mask(views, params, flow_masks, dyn_gauss, texel_gauss, H, W, dyn_texel, counters, stream=None):
-    _check(lib().pg_flow_mask(views, _ptr(params), _ptr(flow_masks), _ptr(dyn_gauss), _ptr(texel_gauss), int(H),
+def pg_flow_mask(views, params, flow_masks, tile_motion, dyn_gauss, texel_gauss, H, W, dyn_texel, counters,
+                 stream=None):
+    _check(lib().pg_flow_mask(views, _ptr(params), _ptr(flow_masks), _ptr(tile_motion), _ptr(dyn_gauss),
+                              _ptr(texel_gauss), int(H),
                               int(W), _ptr(dyn_texel), _ptr(counters), _stream(stream)), "pg_flow_mask")
 
 

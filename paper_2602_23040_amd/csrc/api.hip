@@ -329,14 +329,14 @@ pg_status pg_loss_l1(const float* image, const float* target, int64_t n, float* 
     return PG_OK;
 }
 
-pg_status pg_flow_mask(const pg_views* v, const float* params, const uint8_t* flow_masks, uint8_t* dyn_gauss,
-                       const int32_t* texel_gauss, int32_t H, int32_t W, uint8_t* dyn_texel, uint64_t* counters,
-                       void* stream) {
+pg_status pg_flow_mask(const pg_views* v, const float* params, const uint8_t* flow_masks, uint8_t* tile_motion,
+                       uint8_t* dyn_gauss, const int32_t* texel_gauss, int32_t H, int32_t W, uint8_t* dyn_texel,
+                       uint64_t* counters, void* stream) {
     g_error.clear();
     if (!v) return invalid("views is null");
-    if (v->n_gv > 0 && (!params || !flow_masks || !dyn_gauss)) return invalid("null pointer argument");
+    if (v->n_gv > 0 && (!params || !flow_masks || !dyn_gauss || !tile_motion)) return invalid("null pointer argument");
     if (dyn_texel && (!texel_gauss || H < 1 || W < 1)) return invalid("dyn_texel needs texel_gauss and H, W >= 1");
-    PG_CHECK_HIP(launch_flow_mask(v, params, flow_masks, dyn_gauss, texel_gauss, dyn_texel ? (int64_t)H * W : 0,
+    PG_CHECK_HIP(launch_flow_mask(v, params, flow_masks, tile_motion, dyn_gauss, texel_gauss, dyn_texel ? (int64_t)H * W : 0,
                                   dyn_texel, counters, (hipStream_t)stream),
                  "pg_flow_mask");
     return PG_OK;

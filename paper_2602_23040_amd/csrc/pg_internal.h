@@ -83,9 +83,9 @@ hipError_t launch_fake_quant(float* params, const int64_t* n_dev, int64_t n_cap,
 // project.hip
 hipError_t launch_project(const pg_views* v, const float* params, pg_splat* splats, pg_bin* bins,
                           pg_tile_set* tiles, uint8_t* visible, hipStream_t s);
-hipError_t launch_flow_mask(const pg_views* v, const float* params, const uint8_t* masks, uint8_t* dyn_gauss,
-                            const int32_t* texel_gauss, int64_t HW, uint8_t* dyn_texel, uint64_t* counters,
-                            hipStream_t s);
+hipError_t launch_flow_mask(const pg_views* v, const float* params, const uint8_t* masks, uint8_t* tile_motion,
+                            uint8_t* dyn_gauss, const int32_t* texel_gauss, int64_t HW, uint8_t* dyn_texel,
+                            uint64_t* counters, hipStream_t s);
 // per-record sums of the instance slots -> grad2d
 hipError_t launch_slot_sum(const pg_views* v, const pg_bin* bins, const int32_t* inst_first,
                            const int64_t* n_inst_dev, int64_t cap, const float* inst_grad, float* grad2d,

@@ -419,65 +419,110 @@ __global__ __launch_bounds__(kProjBlk) void k_project(const ViewDev* __restrict_
 // a Gaussian is dynamic when, in some view of its frame, a pixel whose centre
 // is within r = ceil(3 sqrt(lambda_max)) of the mean on both axes and inside
 // the image has q <= 9 and a non-zero flow mask (the OR across cameras).
-// One thread per Gaussian, its frame's views in turn until one marks it; the
-// projection chain, culls and radius are those of k_project.  Each row of the
-// square is scanned only where q <= 9 can hold: between the roots of the
-// row's quadratic in x, widened by a pixel on each side and by 1e-9 of the
-// discriminant's terms, so the FP64 test on each candidate's centre (mask
-// first) decides exactly as a scan of the whole square would.
-__global__ __launch_bounds__(128) void k_flow_mask(const ViewDev* __restrict__ views,
-                                                   const int32_t* __restrict__ frame_views,
-                                                   const int32_t* __restrict__ view_order, int32_t F, int32_t C,
-                                                   int64_t N, const float* __restrict__ params,
-                                                   const uint8_t* __restrict__ masks, uint8_t* __restrict__ dyn_gauss,
+//
+// k_tile_motion marks the screen tiles holding any motion (one wave per
+// tile).  k_flow_mask then runs one thread per (view, Gaussian) record: the
+// projection chain, culls and radius of k_project; the record stops there
+// unless a tile under its square has motion.  Rows are scanned only where
+// q <= 9 can hold -- between the roots of the row's quadratic in x, widened
+// by a pixel on each side and by 1e-9 of the discriminant's terms -- and only
+// when a tile under that stretch has motion, so the FP64 test on each
+// candidate's centre (mask first) decides exactly as a scan of the whole
+// square would.  A hit writes 1 to the Gaussian's zeroed label: every writer
+// stores the same value, so the OR over views needs no atomics.
+__global__ __launch_bounds__(64) void k_tile_motion(const ViewDev* __restrict__ views, int nv, int64_t n_tiles,
+                                                    int32_t tw, int32_t th, const uint8_t* __restrict__ masks,
+                                                    uint8_t* __restrict__ tmot) {
+    const int64_t tile = blockIdx.x;
+    if (tile >= n_tiles) return;
+    const ViewDev& V = views[find_view_by_tile(views, nv, tile)];
+    const int64_t local = tile - V.tile_base;
+    const int32_t ty = (int32_t)(local / V.TX), tx = (int32_t)(local - (int64_t)ty * V.TX);
+    bool any = false;
+    for (int32_t k = threadIdx.x; k < tw * th; k += 64) {
+        const int32_t x = tx * tw + k % tw, y = ty * th + k / tw;
+        if (x < V.W && y < V.H) any |= masks[V.pix_base + (int64_t)y * V.W + x] != 0;
+    }
+    const uint64_t b = __ballot(any);
+    if (threadIdx.x == 0) tmot[tile] = b ? 1 : 0;
+}
+
+__global__ void k_fill_u8(uint8_t* __restrict__ p, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0;
+}
+
+__global__ __launch_bounds__(128) void k_flow_mask(const ViewDev* __restrict__ views, int32_t C, int64_t N,
+                                                   int64_t n_gv, int32_t tw, int32_t th,
+                                                   const float* __restrict__ params,
+                                                   const uint8_t* __restrict__ masks,
+                                                   const uint8_t* __restrict__ tmot, uint8_t* __restrict__ dyn_gauss,
                                                    unsigned long long* __restrict__ counters) {
-    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t gv = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     uint64_t tests = 0;
-    if (g < (int64_t)F * N) {
-        const int32_t f = (int32_t)(g / N);
-        const int64_t i = g - (int64_t)f * N;
-        const float* P = params + (int64_t)f * C * N + i;
+    if (gv < n_gv) {
+        const int32_t v = (int32_t)(gv / N);
+        const int64_t i = gv - (int64_t)v * N;
+        const ViewDev& V = views[v];
+        const float* P = params + (int64_t)V.frame * C * N + i;
         float rec[11];
 #pragma unroll
         for (int k = 0; k < 11; k++) rec[k] = P[(int64_t)k * N];
         World w;
         world_chain(rec, w);
-        bool dyn = false;
-        for (int32_t vi = frame_views[f]; vi < frame_views[f + 1] && !dyn; vi++) {
-            const ViewDev& V = views[view_order[vi]];
-            Cam c;
-            if (!camera_chain(V, w, c) || !(c.det > kDetMin)) continue;   // culled: static for this view
+        Cam c;
+        if (camera_chain(V, w, c) && c.det > kDetMin) {
             const double tr = c.ap + c.cp;
             const double lam = 0.5 * (tr + sqrt(fmax(0.0, tr * tr - 4.0 * c.det)));
             const double rr = ceil(3.0 * sqrt(lam));
             const double mx = (V.fx * c.xc) / c.zc + V.cx;
             const double my = (V.fy * c.yc) / c.zc + V.cy;
-            const double A = c.cp / c.det, B = -c.bp / c.det, Cq = c.ap / c.det;
             const double x0 = fmax(0.0, ceil(mx - rr - 0.5)), x1 = fmin((double)(V.W - 1), floor(mx + rr - 0.5));
             const double y0 = fmax(0.0, ceil(my - rr - 0.5)), y1 = fmin((double)(V.H - 1), floor(my + rr - 0.5));
-            const uint8_t* M = masks + V.pix_base;
-            for (double y = y0; y <= y1 && !dyn; y += 1.0) {
-                const double dy = (y + 0.5) - my;
-                // q <= 9 on this row: A X^2 + 2 (B dy) X + (C dy^2 - 9) <= 0, X = x + 0.5 - mx
-                const double bq = B * dy, cdy = Cq * dy * dy;
-                const double disc = bq * bq - A * (cdy - 9.0);
-                const double slack = 1e-9 * (bq * bq + A * cdy + 9.0 * A);
-                if (disc + slack < 0.0) continue;
-                const double sq = sqrt(disc + slack);
-                const double xa = fmax(x0, floor(mx + (-bq - sq) / A - 0.5) - 1.0);
-                const double xb = fmin(x1, ceil(mx + (-bq + sq) / A - 0.5) + 1.0);
-                const uint8_t* row = M + (int64_t)y * V.W;
-                for (double x = xa; x <= xb; x += 1.0) {
-                    if (!row[(int64_t)x]) continue;
-                    tests++;
-                    if (q_at(A, B, Cq, (x + 0.5) - mx, dy) <= 9.0) {
-                        dyn = true;
-                        break;
+            bool any = false;
+            if (x0 <= x1 && y0 <= y1) {
+                const int32_t txa = (int32_t)x0 / tw, txb = (int32_t)x1 / tw;
+                const int32_t tya = (int32_t)y0 / th, tyb = (int32_t)y1 / th;
+                for (int32_t ty = tya; ty <= tyb && !any; ty++)
+                    for (int32_t tx = txa; tx <= txb; tx++)
+                        if (tmot[V.tile_base + (int64_t)ty * V.TX + tx]) {
+                            any = true;
+                            break;
+                        }
+            }
+            if (any) {
+                const double A = c.cp / c.det, B = -c.bp / c.det, Cq = c.ap / c.det;
+                const double iA = 1.0 / A;
+                const uint8_t* M = masks + V.pix_base;
+                bool dyn = false;
+                for (double y = y0; y <= y1 && !dyn; y += 1.0) {
+                    const double dy = (y + 0.5) - my;
+                    // q <= 9 on this row: A X^2 + 2 (B dy) X + (C dy^2 - 9) <= 0, X = x + 0.5 - mx
+                    const double bq = B * dy, cdy = Cq * dy * dy;
+                    const double disc = bq * bq - A * (cdy - 9.0);
+                    const double slack = 1e-9 * (bq * bq + A * cdy + 9.0 * A);
+                    if (disc + slack < 0.0) continue;
+                    const double sq = sqrt(disc + slack);
+                    const double xa = fmax(x0, floor(mx + (-bq - sq) * iA - 0.5) - 1.0);
+                    const double xb = fmin(x1, ceil(mx + (-bq + sq) * iA - 0.5) + 1.0);
+                    if (xa > xb) continue;
+                    const int64_t trow = V.tile_base + (int64_t)((int32_t)y / th) * V.TX;
+                    bool row_motion = false;
+                    for (int32_t tx = (int32_t)xa / tw; tx <= (int32_t)xb / tw; tx++) row_motion |= tmot[trow + tx] != 0;
+                    if (!row_motion) continue;
+                    const uint8_t* row = M + (int64_t)y * V.W;
+                    for (double x = xa; x <= xb; x += 1.0) {
+                        if (!row[(int64_t)x]) continue;
+                        tests++;
+                        if (q_at(A, B, Cq, (x + 0.5) - mx, dy) <= 9.0) {
+                            dyn = true;
+                            break;
+                        }
                     }
                 }
+                if (dyn) dyn_gauss[(int64_t)V.frame * N + i] = 1;
             }
         }
-        dyn_gauss[g] = dyn ? 1 : 0;
     }
     if (counters) {
         unsigned long long t = tests;
@@ -810,15 +855,18 @@ __global__ __launch_bounds__(kSumRecs) void k_slot_sum(const pg_bin* __restrict_
 
 }  // namespace
 
-hipError_t launch_flow_mask(const pg_views* v, const float* params, const uint8_t* masks, uint8_t* dyn_gauss,
-                            const int32_t* texel_gauss, int64_t HW, uint8_t* dyn_texel, uint64_t* counters,
-                            hipStream_t s) {
-    const int64_t n = (int64_t)v->frames * v->n_gauss;
-    if (n > 0)
-        k_flow_mask<<<(unsigned)ceil_div(n, 128), 128, 0, s>>>(v->d_views, v->d_frame_views, v->d_view_order,
-                                                               v->frames, v->channels, v->n_gauss, params, masks,
-                                                               dyn_gauss,
-                                                               reinterpret_cast<unsigned long long*>(counters));
+hipError_t launch_flow_mask(const pg_views* v, const float* params, const uint8_t* masks, uint8_t* tile_motion,
+                            uint8_t* dyn_gauss, const int32_t* texel_gauss, int64_t HW, uint8_t* dyn_texel,
+                            uint64_t* counters, hipStream_t s) {
+    const int64_t nfn = (int64_t)v->frames * v->n_gauss;
+    if (nfn > 0) k_fill_u8<<<(unsigned)ceil_div(nfn, 256), 256, 0, s>>>(dyn_gauss, nfn);
+    if (v->n_tiles > 0)
+        k_tile_motion<<<(unsigned)v->n_tiles, 64, 0, s>>>(v->d_views, v->n_views, v->n_tiles, v->tiling.tile_w,
+                                                          v->tiling.tile_h, masks, tile_motion);
+    if (v->n_gv > 0)
+        k_flow_mask<<<(unsigned)ceil_div(v->n_gv, 128), 128, 0, s>>>(
+            v->d_views, v->channels, v->n_gauss, v->n_gv, v->tiling.tile_w, v->tiling.tile_h, params, masks,
+            tile_motion, dyn_gauss, reinterpret_cast<unsigned long long*>(counters));
     if (dyn_texel && HW > 0)
         k_dyn_texel<<<(unsigned)ceil_div(HW, 256), 256, 0, s>>>(dyn_gauss, texel_gauss, HW, v->frames, v->n_gauss,
                                                                dyn_texel);

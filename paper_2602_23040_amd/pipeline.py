@@ -217,7 +217,9 @@ class Renderer:
         self.fetch(atlas)
         dg = torch.empty(max(self.frames * self.N, 1), dtype=torch.uint8, device=self.device)
         dt = torch.empty(self.H * self.W, dtype=torch.uint8, device=self.device)
-        abi.pg_flow_mask(self.sets[0].handle, self.params, masks, dg, self.texel_gauss, self.H, self.W, dt, counters)
+        s = self.sets[0]
+        tm = torch.empty(max(s.info.n_tiles, 1), dtype=torch.uint8, device=self.device)
+        abi.pg_flow_mask(s.handle, self.params, masks, tm, dg, self.texel_gauss, self.H, self.W, dt, counters)
         return dg[:self.frames * self.N], dt
 
     def loss_l1(self, target: torch.Tensor) -> torch.Tensor:
