@@ -18,6 +18,10 @@ Parity status of each function (what pins it; see ``tests/test_oracle_*.py``):
   backward          -- two-Gaussian closed-form derivatives; central finite
                        differences of the forward with frozen decisions.
   loss_l1, adam     -- textbook closed forms.
+  ssim              -- SSIM(x, x) = 1 with zero gradient; constant planes against the closed
+                       form (2ab + C1)/(a^2 + b^2 + C1) in the interior; window statistics
+                       against scipy.ndimage.correlate; symmetry; FD of the gradient.
+  regularisers      -- hand-evaluated hinge and o (1 - o) on chosen values; FD of both.
   flow_mask         -- on-axis isotropic disc closed form (pixels just inside / outside
                        3 sigma), brute force over every pixel of the image, OR across
                        cameras, empty and full masks.
@@ -75,6 +79,8 @@ def lib():
             "or_adam": (None, [p, p, p, p, p, i64, f64, f64, f64, f64, i32]),
             "or_fake_quant": (None, [p, p, i32, i32, i32, i32, p, p, p, p]),
             "or_flow_mask": (None, [p, i64, i32, p, p, p]),
+            "or_ssim": (f64, [p, p, i32, i32, p, p]),
+            "or_regularisers": (i64, [p, i32, i32, i64, p, f64, f64, f64, p, p]),
             "or_num_threads": (i32, []),
         }
         for name, (res, args) in sig.items():
@@ -125,6 +131,52 @@ def fetch(atlas: np.ndarray, occ: np.ndarray):
     got = lib().or_fetch(_p(atlas), _p(occ), F, Cc, H, W, _p(ids), _p(params))
     assert got == n
     return ids[:n], np.ascontiguousarray(params[:, :, :n])
+
+
+def ssim(x: np.ndarray, y: np.ndarray, grad: bool = False, smap: bool = False):
+    """Sum over an (H, W) plane of the SSIM map of x against y, and (if grad)
+    its gradient with respect to x, (if smap) the map itself."""
+    xx = np.ascontiguousarray(x, np.float64)
+    yy = np.ascontiguousarray(y, np.float64)
+    H, W = xx.shape
+    g = np.zeros((H, W), np.float64) if grad else None
+    m = np.zeros((H, W), np.float64) if smap else None
+    tot = lib().or_ssim(_p(xx), _p(yy), H, W, _p(g) if grad else None, _p(m) if smap else None)
+    out = (tot,) + ((g,) if grad else ()) + ((m,) if smap else ())
+    return out if len(out) > 1 else tot
+
+
+def regularisers(params: np.ndarray, s_max: float, w_scale: float = 1.0, w_opacity: float = 1.0, dyn=None):
+    """(L_scale, L_opacity, gradient (F, C, N) of w_scale L_scale + w_opacity
+    L_opacity, number of Gaussians averaged) over params (F, C, N)."""
+    P = np.ascontiguousarray(params, np.float64)
+    F, Cc, N = P.shape
+    d = None if dyn is None else np.ascontiguousarray(dyn, np.uint8).reshape(F * N)
+    g = np.zeros_like(P)
+    out = np.zeros(2, np.float64)
+    n = lib().or_regularisers(_p(P), F, Cc, N, _p(d) if d is not None else None, float(s_max), float(w_scale),
+                              float(w_opacity), _p(g), _p(out))
+    return float(out[0]), float(out[1]), g, int(n)
+
+
+def photo_loss(images: dict, targets: dict, lam_ssim: float):
+    """(1 - lam) mean |I - T| + lam (1 - mean SSIM) over every view, pixel and
+    channel, and its cotangents dL/dI per view (3, H, W)."""
+    views = list(images)
+    n = sum(images[v].size for v in views)
+    l1 = sum(float(np.abs(np.asarray(images[v], np.float64) - targets[v]).sum()) for v in views)
+    s_sum, G = 0.0, {}
+    for v in views:
+        I = np.asarray(images[v], np.float64)
+        T = np.asarray(targets[v], np.float64)
+        g = np.zeros_like(I)
+        for ch in range(I.shape[0]):
+            s, gs = ssim(I[ch], T[ch], grad=True)
+            s_sum += s
+            g[ch] = -lam_ssim * gs / n
+        G[v] = g + (1.0 - lam_ssim) * np.sign(I - T) / n
+    L = (1.0 - lam_ssim) * l1 / n + lam_ssim * (1.0 - s_sum / n)
+    return L, G
 
 
 def flow_mask(params_f: np.ndarray, sh_degree: int, cam, mask: np.ndarray, D: np.ndarray | None = None):

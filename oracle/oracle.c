@@ -21,7 +21,8 @@
  *   - Compositing C = sum_i T_i alpha_i c_i, T_i = prod_{j<i} (1 - alpha_j):
  *     supplementary, viewer section (the formula is front to back).
  *   - Gradient freezing grad <- D_i grad: Sec. 4.2 "Gradient Freezing".
- *   - L1 photometric term: Sec. 4.2 "Objective" with lambda_ssim = 0.
+ *   - Photometric objective (1 - lambda_ssim) L1 + lambda_ssim (1 - SSIM),
+ *     scale and opacity regularisers: Sec. 4.2 "Objective".
  *   - Sparse Adam on FP32 master weights: Sec. 4.3 LPO paragraph.
  *   - Covariance-aware flow masking (dynamic label per Gaussian, OR across
  *     cameras): Sec. 4.2 masking paragraph and Algorithm 1.
@@ -925,6 +926,136 @@ void or_adam(double* p, const double* g, double* m, double* v, const uint8_t* vi
         const double mh = m[e] / c1, vh = v[e] / c2;
         p[e] = p[e] - lr * mh / (sqrt(vh) + eps);
     }
+}
+
+/* ------------------------------------------------------------------ SSIM
+ * Structural similarity of the photometric objective (Sec. 4.2
+ * "Objective"; the paper names SSIM without its parameters, read here as
+ * the usual definition): per channel plane, local statistics under an
+ * 11 x 11 Gaussian window (sigma 1.5, weights normalised to sum 1) with zero
+ * padding outside the image,
+ *   a = w * x, b = w * y, c = w * x^2, d = w * y^2, e = w * x y,
+ *   S = (2 a b + C1) (2 (e - a b) + C2) / ((a^2 + b^2 + C1) ((c - a^2) + (d - b^2) + C2)),
+ * C1 = 0.01^2, C2 = 0.03^2 (data range 1).  Returns the sum of S over the
+ * plane (smap, if given, receives S per pixel); grad (or NULL) receives
+ * d(sum S)/dx, by the chain rule through the
+ * five window sums:  dS/da = 2 b (N2 - N1) / (D1 D2) - S (2 a / D1 - 2 a / D2),
+ * dS/dc = -S / D2, dS/de = 2 N1 / (D1 D2), and each window sum's adjoint is
+ * the same window correlation (the window is symmetric). */
+#define OR_SSIM_R 5
+#define OR_SSIM_C1 (0.01 * 0.01)
+#define OR_SSIM_C2 (0.03 * 0.03)
+
+static void ssim_window(double w[2 * OR_SSIM_R + 1]) {
+    double sum = 0.0;
+    for (int k = 0; k <= 2 * OR_SSIM_R; k++) {
+        const double t = (double)(k - OR_SSIM_R);
+        w[k] = exp(-(t * t) / (2.0 * 1.5 * 1.5));
+        sum += w[k];
+    }
+    for (int k = 0; k <= 2 * OR_SSIM_R; k++) w[k] /= sum;
+}
+
+double or_ssim(const double* x, const double* y, int32_t H, int32_t W, double* grad, double* smap) {
+    const int R = OR_SSIM_R;
+    double w[2 * OR_SSIM_R + 1];
+    ssim_window(w);
+    const int64_t n = (int64_t)H * W;
+    double* pa = grad ? (double*)calloc((size_t)n, sizeof(double)) : NULL;
+    double* pc = grad ? (double*)calloc((size_t)n, sizeof(double)) : NULL;
+    double* pe = grad ? (double*)calloc((size_t)n, sizeof(double)) : NULL;
+    double total = 0.0;
+#pragma omp parallel for reduction(+ : total) schedule(static)
+    for (int32_t py = 0; py < H; py++)
+        for (int32_t px = 0; px < W; px++) {
+            double a = 0.0, b = 0.0, c = 0.0, d = 0.0, e = 0.0;
+            for (int dy = -R; dy <= R; dy++)
+                for (int dx = -R; dx <= R; dx++) {
+                    const int32_t qy = py + dy, qx = px + dx;
+                    if (qy < 0 || qy >= H || qx < 0 || qx >= W) continue;   /* zero padding */
+                    const double wt = w[dy + R] * w[dx + R];
+                    const double xv = x[(int64_t)qy * W + qx], yv = y[(int64_t)qy * W + qx];
+                    a += wt * xv;
+                    b += wt * yv;
+                    c += wt * xv * xv;
+                    d += wt * yv * yv;
+                    e += wt * xv * yv;
+                }
+            const double N1 = 2.0 * a * b + OR_SSIM_C1, N2 = 2.0 * (e - a * b) + OR_SSIM_C2;
+            const double D1 = a * a + b * b + OR_SSIM_C1, D2 = (c - a * a) + (d - b * b) + OR_SSIM_C2;
+            const double S = (N1 * N2) / (D1 * D2);
+            total += S;
+            if (smap) smap[(int64_t)py * W + px] = S;
+            if (grad) {
+                const int64_t p = (int64_t)py * W + px;
+                pa[p] = 2.0 * b * (N2 - N1) / (D1 * D2) - S * (2.0 * a / D1 - 2.0 * a / D2);
+                pc[p] = -S / D2;
+                pe[p] = 2.0 * N1 / (D1 * D2);
+            }
+        }
+    if (grad) {
+#pragma omp parallel for schedule(static)
+        for (int32_t qy = 0; qy < H; qy++)
+            for (int32_t qx = 0; qx < W; qx++) {
+                double A = 0.0, Cc = 0.0, E = 0.0;
+                for (int dy = -R; dy <= R; dy++)
+                    for (int dx = -R; dx <= R; dx++) {
+                        const int32_t py = qy + dy, px = qx + dx;
+                        if (py < 0 || py >= H || px < 0 || px >= W) continue;
+                        const double wt = w[dy + R] * w[dx + R];
+                        const int64_t p = (int64_t)py * W + px;
+                        A += wt * pa[p];
+                        Cc += wt * pc[p];
+                        E += wt * pe[p];
+                    }
+                const int64_t q = (int64_t)qy * W + qx;
+                grad[q] = A + 2.0 * x[q] * Cc + y[q] * E;
+            }
+        free(pa);
+        free(pc);
+        free(pe);
+    }
+    return total;
+}
+
+/* ------------------------------------------------------------------ regularisers
+ * Scale and opacity regularisers of the objective (Sec. 4.2 "Objective"),
+ * over the Gaussians of every frame, or only the dynamic ones (dyn[f N + i]
+ * != 0) when dyn is given:
+ *   L_scale   = mean_i max(0, max_k s_ik - s_max)^2,  s = exp(l_s),
+ *   L_opacity = mean_i o_i (1 - o_i),                 o = sigmoid(l_o).
+ * Their gradients with respect to the texel channels (l_s through exp, l_o
+ * through the sigmoid) are written to grad [F][C][N] (channels 3-5 and 10;
+ * zero elsewhere) as dL_scale and dL_opacity scaled by w_scale, w_opacity.
+ * Writes the two means to out[0], out[1]; returns the number averaged. */
+int64_t or_regularisers(const double* P, int32_t F, int32_t C, int64_t N, const uint8_t* dyn, double s_max,
+                        double w_scale, double w_opacity, double* grad, double* out) {
+    int64_t n = 0;
+    for (int64_t g = 0; g < (int64_t)F * N; g++)
+        if (!dyn || dyn[g]) n++;
+    memset(grad, 0, sizeof(double) * (size_t)((int64_t)F * C * N));
+    double ls = 0.0, lo = 0.0;
+    for (int32_t f = 0; f < F; f++)
+        for (int64_t i = 0; i < N; i++) {
+            if (dyn && !dyn[(int64_t)f * N + i]) continue;
+            const double* Pf = P + (int64_t)f * C * N;
+            double* Gf = grad + (int64_t)f * C * N;
+            int kmax = 0;
+            double smax = exp(Pf[3 * N + i]);
+            for (int k = 1; k < 3; k++) {
+                const double sk = exp(Pf[(3 + k) * N + i]);
+                if (sk > smax) { smax = sk; kmax = k; }
+            }
+            const double h = smax > s_max ? smax - s_max : 0.0;
+            ls += h * h;
+            Gf[(3 + kmax) * N + i] = w_scale * (2.0 * h * smax) / (double)n;   /* d/dl of exp(l) is exp(l) */
+            const double o = 1.0 / (1.0 + exp(-Pf[10 * N + i]));
+            lo += o * (1.0 - o);
+            Gf[10 * N + i] = w_opacity * ((1.0 - 2.0 * o) * o * (1.0 - o)) / (double)n;
+        }
+    out[0] = n ? ls / (double)n : 0.0;
+    out[1] = n ? lo / (double)n : 0.0;
+    return n;
 }
 
 /* ------------------------------------------------------------------ flow masking
