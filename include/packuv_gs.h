@@ -338,6 +338,22 @@ pg_status pg_project_bwd(const pg_views* views, const float* params, const pg_bi
 pg_status pg_loss_l1(const float* image, const float* target, int64_t n, float* dL_dimage, double* partial,
                      float* loss_dev, void* stream);
 
+/* Full photometric term of Sec. 4.2 "Objective":
+ * L = (1 - lambda_ssim) mean |image - target| + lambda_ssim (1 - mean SSIM),
+ * means over every view, pixel and channel, and dL/dimage.  SSIM per channel
+ * plane of each view: 11 x 11 Gaussian window (sigma 1.5, weights summing to
+ * 1), zero padding outside the view, C1 = 0.01^2, C2 = 0.03^2 (data range 1);
+ * its image gradient is the window correlation of its partials with respect
+ * to the window sums.  The paper does not give lambda_ssim (0 gives the L1
+ * term of pg_loss_l1; 3DGS uses 0.2).  FP32 arithmetic, FP64 sums.
+ *   image, target  device float [3 n_pixels] (per view planar [3][H][W])
+ *   dL_dimage      device float [3 n_pixels] out
+ *   loss_dev       device float [1] out
+ *   ws             device workspace of pg_photo_workspace_size bytes */
+pg_status pg_photo_workspace_size(const pg_views* views, size_t* bytes);
+pg_status pg_loss_photo(const pg_views* views, const float* image, const float* target, float lambda_ssim,
+                        float* dL_dimage, float* loss_dev, void* ws, size_t ws_bytes, void* stream);
+
 /* a6 -- Sparse Adam on the FP32 atlas (Sec. 4.3, LPO paragraph: FP32 master
  * weights, Sparse Adam).  Textbook Adam with bias correction at `step` >= 1,
  * applied to channels of texels whose Gaussian is visible (visible[f N + i]);

@@ -68,6 +68,8 @@ SIGNATURES = {
     "pg_render_bwd": (_i32, [_p, _p, _p, _p, _p, _p, _p, _i64, _p, _p, _p, _p, _p, _p, _p, _p]),
     "pg_project_bwd": (_i32, [_p, _p, _p, _p, _p, _i64, _p, _p, _p, _i32, _i32, _p, _p, _i32, _p]),
     "pg_loss_l1": (_i32, [_p, _p, _i64, _p, _p, _p, _p]),
+    "pg_photo_workspace_size": (_i32, [_p, C.POINTER(_sz)]),
+    "pg_loss_photo": (_i32, [_p, _p, _p, _f32, _p, _p, _p, _sz, _p]),
     "pg_adam_step": (_i32, [_p, _p, _p, _p, _p, _p, _i64, _i32, _i32, _i32, _i32, _f32, _f32, _f32, _f32, _i32, _p,
                             _p]),
 }
@@ -251,6 +253,17 @@ def pg_project_bwd(views, params, bins, inst_first, n_inst_dev, inst_capacity, i
 def pg_loss_l1(image, target, n, dL_dimage, partial, loss_dev, stream=None):
     _check(lib().pg_loss_l1(_ptr(image), _ptr(target), int(n), _ptr(dL_dimage), _ptr(partial), _ptr(loss_dev),
                             _stream(stream)), "pg_loss_l1")
+
+
+def pg_photo_workspace_size(views) -> int:
+    n = C.c_size_t()
+    _check(lib().pg_photo_workspace_size(views, C.byref(n)), "pg_photo_workspace_size")
+    return n.value
+
+
+def pg_loss_photo(views, image, target, lambda_ssim, dL_dimage, loss_dev, ws, ws_bytes, stream=None):
+    _check(lib().pg_loss_photo(views, _ptr(image), _ptr(target), float(lambda_ssim), _ptr(dL_dimage), _ptr(loss_dev),
+                               _ptr(ws), int(ws_bytes), _stream(stream)), "pg_loss_photo")
 
 
 def pg_adam_step(atlas, grad, m, v, visible, texel_gauss, n_gauss, frames, channels, H, W, lr, beta1, beta2, eps,

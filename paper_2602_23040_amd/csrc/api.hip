@@ -84,8 +84,8 @@ pg_status pg_views_create(const pg_camera* cams, int32_t n_views, int32_t frames
     if ((int64_t)n_views * n_gauss > INT32_MAX) return invalid("n_views * n_gauss exceeds 2^31 - 1");
     if (n_gauss > ((int64_t)1 << 28)) return invalid("n_gauss exceeds 2^28");
     std::vector<ViewDev> hv(n_views);
-    std::vector<int64_t> tb(n_views + 1), pb(n_views + 1);
-    int64_t tiles = 0, pixels = 0;
+    std::vector<int64_t> tb(n_views + 1), pb(n_views + 1), sb(n_views);
+    int64_t tiles = 0, pixels = 0, sblocks = 0;
     for (int32_t v = 0; v < n_views; v++) {
         const pg_camera& c = cams[v];
         if (!(c.fx > 0.0) || !(c.fy > 0.0) || !std::isfinite(c.fx) || !std::isfinite(c.fy))
@@ -124,6 +124,8 @@ pg_status pg_views_create(const pg_camera* cams, int32_t n_views, int32_t frames
         d.pix_base = pixels;
         tb[v] = tiles;
         pb[v] = pixels;
+        sb[v] = sblocks;
+        sblocks += (int64_t)((c.width + 31) / 32) * ((c.height + 31) / 32);
         tiles += (int64_t)d.TX * d.TY;
         pixels += (int64_t)c.width * c.height;
     }
@@ -152,6 +154,7 @@ pg_status pg_views_create(const pg_camera* cams, int32_t n_views, int32_t frames
     p->n_pixels = pixels;
     p->key_bits = tile_bits;
     p->sort_passes = (32 + 7) / 8 + (tile_bits + 7) / 8;   // record (depth) passes + instance (tile) passes
+    p->n_ssim_blocks = sblocks;
     p->h_tile_base = new int64_t[n_views + 1];
     p->h_pix_base = new int64_t[n_views + 1];
     std::memcpy(p->h_tile_base, tb.data(), sizeof(int64_t) * (n_views + 1));
@@ -160,6 +163,8 @@ pg_status pg_views_create(const pg_camera* cams, int32_t n_views, int32_t frames
     hipError_t e = hipMalloc(&p->d_views, sizeof(ViewDev) * n_views);
     if (e == hipSuccess) e = hipMalloc(&p->d_frame_views, sizeof(int32_t) * (frames + 1));
     if (e == hipSuccess) e = hipMalloc(&p->d_view_order, sizeof(int32_t) * n_views);
+    if (e == hipSuccess) e = hipMalloc(&p->d_ssim_base, sizeof(int64_t) * n_views);
+    if (e == hipSuccess) e = hipMemcpy(p->d_ssim_base, sb.data(), sizeof(int64_t) * n_views, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(p->d_views, hv.data(), sizeof(ViewDev) * n_views, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(p->d_frame_views, fv.data(), sizeof(int32_t) * (frames + 1), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(p->d_view_order, order.data(), sizeof(int32_t) * n_views, hipMemcpyHostToDevice);
@@ -176,6 +181,7 @@ pg_status pg_views_destroy(pg_views* v) {
     if (v->d_views) hipFree(v->d_views);
     if (v->d_frame_views) hipFree(v->d_frame_views);
     if (v->d_view_order) hipFree(v->d_view_order);
+    if (v->d_ssim_base) hipFree(v->d_ssim_base);
     delete[] v->h_tile_base;
     delete[] v->h_pix_base;
     delete v;
@@ -326,6 +332,29 @@ pg_status pg_loss_l1(const float* image, const float* target, int64_t n, float* 
     if (!image || !target || !dL_dimage || !partial || !loss_dev) return invalid("null pointer argument");
     if (n < 1) return invalid("n must be >= 1");
     PG_CHECK_HIP(launch_loss_l1(image, target, n, dL_dimage, partial, loss_dev, (hipStream_t)stream), "pg_loss_l1");
+    return PG_OK;
+}
+
+pg_status pg_photo_workspace_size(const pg_views* v, size_t* bytes) {
+    g_error.clear();
+    if (!v || !bytes) return invalid("null argument");
+    *bytes = (size_t)(2 * imax(photo_blocks(v), 1)) * sizeof(double);
+    return PG_OK;
+}
+
+pg_status pg_loss_photo(const pg_views* v, const float* image, const float* target, float lambda_ssim,
+                        float* dL_dimage, float* loss_dev, void* ws, size_t ws_bytes, void* stream) {
+    g_error.clear();
+    if (!v) return invalid("views is null");
+    if (!loss_dev || !ws) return invalid("null pointer argument");
+    if (v->n_pixels > 0 && (!image || !target || !dL_dimage)) return invalid("null pointer argument");
+    if (!(lambda_ssim >= 0.0f && lambda_ssim <= 1.0f)) return invalid("lambda_ssim must be in [0, 1]");
+    if (ws_bytes < (size_t)(2 * imax(photo_blocks(v), 1)) * sizeof(double)) {
+        set_error("photometric-loss workspace too small");
+        return PG_ERR_WORKSPACE;
+    }
+    PG_CHECK_HIP(launch_photo(v, image, target, lambda_ssim, dL_dimage, loss_dev, (double*)ws, (hipStream_t)stream),
+                 "pg_loss_photo");
     return PG_OK;
 }
 

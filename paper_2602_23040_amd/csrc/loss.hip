@@ -1,0 +1,242 @@
+// Photometric objective (Sec. 4.2 "Objective"):
+//   L = (1 - lambda) mean |I - T| + lambda (1 - mean SSIM(I, T))
+// over every view, pixel and channel, and its cotangent dL/dI, in one pass.
+//
+// SSIM per channel plane: local statistics under an 11 x 11 Gaussian window
+// (sigma 1.5, weights summing to 1) with zero padding outside the view,
+//   S = (2 a b + C1) (2 s_xy + C2) / ((a^2 + b^2 + C1) (s_x + s_y + C2)),
+// a, b the window means, s_x, s_y, s_xy the window (co)variances,
+// C1 = 0.01^2, C2 = 0.03^2.  Its gradient with respect to the image is the
+// window correlation (the window is symmetric, so its own adjoint) of the
+// partials P_a = dS/da, P_c = dS/dE[x^2], P_e = dS/dE[xy]:
+//   dS/dx_q = (w * P_a)_q + 2 x_q (w * P_c)_q + y_q (w * P_e)_q.
+//
+// One work-group of 1024 threads per 32 x 32 pixel block of a view and one
+// channel at a time.  Everything stays in LDS: the inputs with a 10-pixel
+// halo, their separable window sums over the 42 x 42 region the adjoint
+// needs, the three partial maps there (zero outside the view, where no S is
+// taken), and their separable blur back to the block.  The inputs are
+// shifted by the block's first pixel before squaring (E[x~^2] - a~^2 with
+// x~ = x - k equals the variance, padding included, since the window sums to
+// 1), which keeps FP32 cancellation in the variances small.  Per-block sums
+// of S and |I - T| (FP64) go to a small partial array that k_photo_final
+// reduces.
+#include "pg_internal.h"
+
+namespace pg {
+
+namespace {
+
+constexpr int kR = 5;                       // window half-width
+constexpr int kK = 2 * kR + 1;
+constexpr int kB = 32;                      // output block side
+constexpr int kIW = kB + 4 * kR;            // input patch side (42 + 10 = 52 with 2 halos)
+constexpr int kMW = kB + 2 * kR;            // partial-map region side (42)
+constexpr int kThreads = kB * kB;
+constexpr float kC1 = 0.01f * 0.01f, kC2 = 0.03f * 0.03f;
+
+struct Win {
+    float w[kK];
+};
+
+__device__ __forceinline__ double block_sum_d(double v, double* s_w) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) s_w[wid] = v;
+    __syncthreads();
+    double t = 0.0;
+    if (threadIdx.x == 0)
+        for (int k = 0; k < kThreads / 64; k++) t += s_w[k];
+    return t;
+}
+
+// blocks: one per 32 x 32 block of every view, numbered per view row-major
+// (ceil(W/32) x ceil(H/32)) from blk_base[v].
+__global__ __launch_bounds__(kThreads) void k_photo(const ViewDev* __restrict__ views, int nv,
+                                                    const int64_t* __restrict__ blk_base,
+                                                    const float* __restrict__ image, const float* __restrict__ target,
+                                                    Win win, float lambda, double inv_n, float* __restrict__ dimg,
+                                                    double* __restrict__ partial) {
+    __shared__ float sx[kIW * kIW], sy[kIW * kIW];
+    __shared__ float h5[5][kIW * kMW];
+    __shared__ float sm[3][kMW * kMW];
+    __shared__ float h3[3][kMW * kB];
+    __shared__ double s_w[kThreads / 64];
+    // view of this block (binary search over the per-view block bases)
+    const int64_t blk = blockIdx.x;
+    int lo = 0, hi = nv - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (blk_base[mid] <= blk) lo = mid; else hi = mid - 1;
+    }
+    const ViewDev& V = views[lo];
+    const int32_t BX = (V.W + kB - 1) / kB;
+    const int64_t local = blk - blk_base[lo];
+    const int32_t x0 = (int32_t)(local % BX) * kB, y0 = (int32_t)(local / BX) * kB;
+    const int64_t HW = (int64_t)V.W * V.H;
+    const int t = threadIdx.x;
+    const int tx = t % kB, ty = t / kB;
+    double s_sum = 0.0, l1_sum = 0.0;
+    for (int ch = 0; ch < 3; ch++) {
+        const float* X = image + 3 * V.pix_base + ch * HW;
+        const float* Y = target + 3 * V.pix_base + ch * HW;
+        const float kx = X[(int64_t)y0 * V.W + x0], ky = Y[(int64_t)y0 * V.W + x0];
+        __syncthreads();   // the previous channel is done with the LDS
+        for (int k = t; k < kIW * kIW; k += kThreads) {
+            const int gx = x0 - 2 * kR + k % kIW, gy = y0 - 2 * kR + k / kIW;
+            const bool in = gx >= 0 && gx < V.W && gy >= 0 && gy < V.H;
+            const int64_t p = (int64_t)gy * V.W + gx;
+            sx[k] = (in ? X[p] : 0.0f) - kx;
+            sy[k] = (in ? Y[p] : 0.0f) - ky;
+        }
+        __syncthreads();
+        // horizontal window sums: input rows x partial-map columns
+        for (int k = t; k < kIW * kMW; k += kThreads) {
+            const int r = k / kMW, c = k % kMW;
+            float a = 0.f, b = 0.f, cc = 0.f, d = 0.f, e = 0.f;
+#pragma unroll
+            for (int j = 0; j < kK; j++) {
+                const float xv = sx[r * kIW + c + j], yv = sy[r * kIW + c + j], w = win.w[j];
+                a = fmaf(w, xv, a);
+                b = fmaf(w, yv, b);
+                cc = fmaf(w, xv * xv, cc);
+                d = fmaf(w, yv * yv, d);
+                e = fmaf(w, xv * yv, e);
+            }
+            h5[0][k] = a;
+            h5[1][k] = b;
+            h5[2][k] = cc;
+            h5[3][k] = d;
+            h5[4][k] = e;
+        }
+        __syncthreads();
+        // vertical window sums on the partial-map region -> S and its partials
+        for (int k = t; k < kMW * kMW; k += kThreads) {
+            const int r = k / kMW, c = k % kMW;
+            float m[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int j = 0; j < kK; j++) {
+                const float w = win.w[j];
+#pragma unroll
+                for (int q = 0; q < 5; q++) m[q] = fmaf(w, h5[q][(r + j) * kMW + c], m[q]);
+            }
+            const int gx = x0 - kR + c, gy = y0 - kR + r;
+            float pa = 0.f, pc = 0.f, pe = 0.f;
+            if (gx >= 0 && gx < V.W && gy >= 0 && gy < V.H) {
+                const float a = m[0] + kx, b = m[1] + ky;
+                const float vx = m[2] - m[0] * m[0], vy = m[3] - m[1] * m[1], cxy = m[4] - m[0] * m[1];
+                const float N1 = 2.0f * a * b + kC1, N2 = 2.0f * cxy + kC2;
+                const float D1 = a * a + b * b + kC1, D2 = vx + vy + kC2;
+                const float iD = 1.0f / (D1 * D2);
+                const float S = N1 * N2 * iD;
+                pa = 2.0f * b * (N2 - N1) * iD - S * (2.0f * a / D1 - 2.0f * a / D2);
+                pc = -S / D2;
+                pe = 2.0f * N1 * iD;
+                if (r >= kR && r < kR + kB && c >= kR && c < kR + kB) s_sum += (double)S;
+            }
+            sm[0][k] = pa;
+            sm[1][k] = pc;
+            sm[2][k] = pe;
+        }
+        __syncthreads();
+        // adjoint: blur the partial maps back to the block (horizontal, then vertical)
+        for (int k = t; k < kMW * kB; k += kThreads) {
+            const int r = k / kB, c = k % kB;
+            float a = 0.f, cc = 0.f, e = 0.f;
+#pragma unroll
+            for (int j = 0; j < kK; j++) {
+                const float w = win.w[j];
+                a = fmaf(w, sm[0][r * kMW + c + j], a);
+                cc = fmaf(w, sm[1][r * kMW + c + j], cc);
+                e = fmaf(w, sm[2][r * kMW + c + j], e);
+            }
+            h3[0][k] = a;
+            h3[1][k] = cc;
+            h3[2][k] = e;
+        }
+        __syncthreads();
+        {
+            float ga = 0.f, gc = 0.f, ge = 0.f;
+#pragma unroll
+            for (int j = 0; j < kK; j++) {
+                const float w = win.w[j];
+                ga = fmaf(w, h3[0][(ty + j) * kB + tx], ga);
+                gc = fmaf(w, h3[1][(ty + j) * kB + tx], gc);
+                ge = fmaf(w, h3[2][(ty + j) * kB + tx], ge);
+            }
+            const int gx = x0 + tx, gy = y0 + ty;
+            if (gx < V.W && gy < V.H) {
+                const int64_t p = (int64_t)gy * V.W + gx;
+                const float xv = X[p], yv = Y[p];
+                const float gs = ga + 2.0f * xv * gc + yv * ge;
+                const float df = xv - yv;
+                const float sg = df > 0.f ? 1.f : (df < 0.f ? -1.f : 0.f);
+                dimg[3 * V.pix_base + ch * HW + p] =
+                    (float)(((double)(1.0f - lambda) * sg - (double)lambda * gs) * inv_n);
+                l1_sum += (double)fabsf(df);
+            }
+        }
+    }
+    const double ts = block_sum_d(s_sum, s_w);
+    const double tl = block_sum_d(l1_sum, s_w);
+    if (t == 0) {
+        partial[2 * blk] = ts;
+        partial[2 * blk + 1] = tl;
+    }
+}
+
+__global__ __launch_bounds__(1024) void k_photo_final(const double* __restrict__ partial, int64_t n_blk,
+                                                      float lambda, double inv_n, float* __restrict__ loss) {
+    __shared__ double s_s[16], s_l[16];
+    double ss = 0.0, sl = 0.0;
+    for (int64_t i = threadIdx.x; i < n_blk; i += 1024) {
+        ss += partial[2 * i];
+        sl += partial[2 * i + 1];
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        ss += __shfl_xor(ss, o, 64);
+        sl += __shfl_xor(sl, o, 64);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        s_s[threadIdx.x >> 6] = ss;
+        s_l[threadIdx.x >> 6] = sl;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        ss = 0.0;
+        sl = 0.0;
+        for (int k = 0; k < 16; k++) {
+            ss += s_s[k];
+            sl += s_l[k];
+        }
+        *loss = (float)((1.0 - (double)lambda) * sl * inv_n + (double)lambda * (1.0 - ss * inv_n));
+    }
+}
+
+}  // namespace
+
+int64_t photo_blocks(const pg_views* v) { return v->n_ssim_blocks; }
+
+hipError_t launch_photo(const pg_views* v, const float* image, const float* target, float lambda, float* dimg,
+                        float* loss, double* partial, hipStream_t s) {
+    const int64_t nb = v->n_ssim_blocks;
+    if (nb == 0 || v->n_pixels == 0) return hipSuccess;
+    Win win;
+    double g[kK], sum = 0.0;
+    for (int k = 0; k < kK; k++) {
+        const double d = (double)(k - kR);
+        g[k] = exp(-(d * d) / (2.0 * 1.5 * 1.5));
+        sum += g[k];
+    }
+    for (int k = 0; k < kK; k++) win.w[k] = (float)(g[k] / sum);
+    const double inv_n = 1.0 / (3.0 * (double)v->n_pixels);
+    k_photo<<<(unsigned)nb, kThreads, 0, s>>>(v->d_views, v->n_views, v->d_ssim_base, image, target, win, lambda,
+                                              inv_n, dimg, partial);
+    k_photo_final<<<1, 1024, 0, s>>>(partial, nb, lambda, inv_n, loss);
+    return hipGetLastError();
+}
+
+}  // namespace pg

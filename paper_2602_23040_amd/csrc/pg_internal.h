@@ -40,6 +40,8 @@ struct pg_views {
     pg::ViewDev* d_views;      // [n_views]
     int32_t* d_frame_views;    // [frames + 1] offsets into d_view_order
     int32_t* d_view_order;     // [n_views] view indices grouped by frame
+    int64_t n_ssim_blocks;     // 32 x 32 pixel blocks of all views (photometric loss)
+    int64_t* d_ssim_base;      // [n_views] first block of each view
     int64_t* h_tile_base;      // [n_views + 1]
     int64_t* h_pix_base;       // [n_views + 1]
 };
@@ -73,6 +75,11 @@ size_t fetch_ws_bytes(int32_t H, int32_t W);
 hipError_t launch_fetch(const float* atlas, const uint8_t* occ, int32_t F, int32_t C, int32_t H, int32_t W,
                         int64_t n_cap, int32_t* gauss_texel, int32_t* texel_gauss, float* params,
                         int64_t* n_gauss_dev, void* ws, hipStream_t s);
+
+// loss.hip (photometric objective)
+int64_t photo_blocks(const pg_views* v);
+hipError_t launch_photo(const pg_views* v, const float* image, const float* target, float lambda, float* dimg,
+                        float* loss, double* partial, hipStream_t s);
 
 // quant.hip
 constexpr int kMaxQuantChannels = 64;       // channels a fake-quantiser call may hold

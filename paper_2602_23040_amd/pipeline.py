@@ -135,11 +135,15 @@ class Renderer:
         self.adam_m = None
         self.adam_v = None
         self.adam_t = None           # device step counter of the Adam update
+        self._photo = None           # (view table, workspace, bytes, own table) of the photometric loss
 
     # ------------------------------------------------------------------ helpers
     def close(self):
         for s in self.sets:
             s.close()
+        if self._photo is not None and self._photo[3]:
+            abi.pg_views_destroy(self._photo[0])
+        self._photo = None
 
     def __del__(self):
         try:
@@ -222,6 +226,17 @@ class Renderer:
         abi.pg_flow_mask(s.handle, self.params, masks, tm, dg, self.texel_gauss, self.H, self.W, dt, counters)
         return dg[:self.frames * self.N], dt
 
+    def loss_photo(self, target: torch.Tensor, lambda_ssim: float) -> torch.Tensor:
+        """(1 - lambda) L1 + lambda (1 - SSIM) over every view; fills dL_dimage."""
+        if self._photo is None:
+            h = self.sets[0].handle if self.batched else abi.pg_views_create(self.cams, self.frames, self.N,
+                                                                            self.sh_degree, self.tiling)
+            nb = abi.pg_photo_workspace_size(h)
+            self._photo = (h, torch.empty(nb, dtype=torch.uint8, device=self.device), nb, not self.batched)
+        h, ws, nb, _ = self._photo
+        abi.pg_loss_photo(h, self.image, target, lambda_ssim, self.dL_dimage, self.loss, ws, nb)
+        return self.loss
+
     def loss_l1(self, target: torch.Tensor) -> torch.Tensor:
         n = 3 * self.n_pixels
         abi.pg_loss_l1(self.image, target, n, self.dL_dimage, self.loss_partial, self.loss)
@@ -259,10 +274,14 @@ class Renderer:
         abi.pg_adam_step(atlas, self.dL_datlas, self.adam_m, self.adam_v, self.visible, self.texel_gauss, self.N,
                          self.frames, self.C, self.H, self.W, lr, b1, b2, eps, 0, self.adam_t)
 
-    def step(self, atlas, target, adam=False):
-        """One fitting step: forward, L1 loss, adjoint (and Adam)."""
+    def step(self, atlas, target, adam=False, lambda_ssim=None):
+        """One fitting step: forward, loss (L1, or the L1/SSIM blend when
+        lambda_ssim is given), adjoint (and Adam)."""
         self.forward(atlas)
-        self.loss_l1(target)
+        if lambda_ssim is None:
+            self.loss_l1(target)
+        else:
+            self.loss_photo(target, lambda_ssim)
         self.backward()
         if adam:
             self.adam_step(atlas)
