@@ -354,6 +354,26 @@ pg_status pg_photo_workspace_size(const pg_views* views, size_t* bytes);
 pg_status pg_loss_photo(const pg_views* views, const float* image, const float* target, float lambda_ssim,
                         float* dL_dimage, float* loss_dev, void* ws, size_t ws_bytes, void* stream);
 
+/* Scale and opacity regularisers of Sec. 4.2 "Objective", over the fetched
+ * Gaussians of every frame (or only the dynamic ones):
+ *   L_scale = mean max(0, max_k s_k - s_max)^2,  L_opacity = mean o (1 - o),
+ * s = exp(l_s), o = sigmoid(l_o), FP64 from the FP32 texel values (the
+ * paper's weights are 1e-4 each; s_max is not given).  Adds
+ * w_scale dL_scale + w_opacity dL_opacity to the texel gradient (the
+ * largest scale's log-scale channel and the logit-opacity channel).
+ *   params       device float [F][C][n_cap] (from pg_atlas_fetch)
+ *   n_gauss_dev  device int64 [1]; min(N, n_cap) Gaussians per frame
+ *   gauss_texel  device int32 [n_cap] (from pg_atlas_fetch)
+ *   dyn_gauss    device uint8 [F][n_cap] or NULL (NULL: every Gaussian)
+ *   dL_datlas    device float [F][C][H][W], added to
+ *   reg_loss     device float [2] out: L_scale, L_opacity
+ *   partial      device double [3 PG_REG_BLOCKS + 1] workspace */
+#define PG_REG_BLOCKS 256
+pg_status pg_loss_regularisers(const float* params, const int64_t* n_gauss_dev, int64_t n_cap, int32_t frames,
+                               int32_t channels, const int32_t* gauss_texel, int32_t H, int32_t W,
+                               const uint8_t* dyn_gauss, float s_max, float w_scale, float w_opacity,
+                               float* dL_datlas, float* reg_loss, double* partial, void* stream);
+
 /* a6 -- Sparse Adam on the FP32 atlas (Sec. 4.3, LPO paragraph: FP32 master
  * weights, Sparse Adam).  Textbook Adam with bias correction at `step` >= 1,
  * applied to channels of texels whose Gaussian is visible (visible[f N + i]);

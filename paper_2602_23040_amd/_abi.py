@@ -19,6 +19,7 @@ STATUS_NAMES = {0: "PG_OK", -1: "PG_ERR_INVALID_ARG", -2: "PG_ERR_UNSUPPORTED_DE
 SPLAT_BYTES = 48
 BIN_BYTES = 16
 QUANT_BLOCKS = 256          # PG_QUANT_BLOCKS: the fake quantiser's workspace is 2 * QUANT_BLOCKS * C floats
+REG_BLOCKS = 256            # PG_REG_BLOCKS: the regularisers' workspace is 3 * REG_BLOCKS + 1 doubles
 
 
 class PGError(RuntimeError):
@@ -69,6 +70,7 @@ SIGNATURES = {
     "pg_project_bwd": (_i32, [_p, _p, _p, _p, _p, _i64, _p, _p, _p, _i32, _i32, _p, _p, _i32, _p]),
     "pg_loss_l1": (_i32, [_p, _p, _i64, _p, _p, _p, _p]),
     "pg_photo_workspace_size": (_i32, [_p, C.POINTER(_sz)]),
+    "pg_loss_regularisers": (_i32, [_p, _p, _i64, _i32, _i32, _p, _i32, _i32, _p, _f32, _f32, _f32, _p, _p, _p, _p]),
     "pg_loss_photo": (_i32, [_p, _p, _p, _f32, _p, _p, _p, _sz, _p]),
     "pg_adam_step": (_i32, [_p, _p, _p, _p, _p, _p, _i64, _i32, _i32, _i32, _i32, _f32, _f32, _f32, _f32, _i32, _p,
                             _p]),
@@ -264,6 +266,14 @@ def pg_photo_workspace_size(views) -> int:
 def pg_loss_photo(views, image, target, lambda_ssim, dL_dimage, loss_dev, ws, ws_bytes, stream=None):
     _check(lib().pg_loss_photo(views, _ptr(image), _ptr(target), float(lambda_ssim), _ptr(dL_dimage), _ptr(loss_dev),
                                _ptr(ws), int(ws_bytes), _stream(stream)), "pg_loss_photo")
+
+
+def pg_loss_regularisers(params, n_gauss_dev, n_cap, frames, channels, gauss_texel, H, W, dyn_gauss, s_max,
+                         w_scale, w_opacity, dL_datlas, reg_loss, partial, stream=None):
+    _check(lib().pg_loss_regularisers(_ptr(params), _ptr(n_gauss_dev), int(n_cap), int(frames), int(channels),
+                                      _ptr(gauss_texel), int(H), int(W), _ptr(dyn_gauss), float(s_max),
+                                      float(w_scale), float(w_opacity), _ptr(dL_datlas), _ptr(reg_loss),
+                                      _ptr(partial), _stream(stream)), "pg_loss_regularisers")
 
 
 def pg_adam_step(atlas, grad, m, v, visible, texel_gauss, n_gauss, frames, channels, H, W, lr, beta1, beta2, eps,

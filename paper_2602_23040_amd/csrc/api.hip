@@ -358,6 +358,22 @@ pg_status pg_loss_photo(const pg_views* v, const float* image, const float* targ
     return PG_OK;
 }
 
+pg_status pg_loss_regularisers(const float* params, const int64_t* n_gauss_dev, int64_t n_cap, int32_t frames,
+                               int32_t channels, const int32_t* gauss_texel, int32_t H, int32_t W,
+                               const uint8_t* dyn_gauss, float s_max, float w_scale, float w_opacity,
+                               float* dL_datlas, float* reg_loss, double* partial, void* stream) {
+    g_error.clear();
+    if (!n_gauss_dev || !reg_loss || !partial || !dL_datlas) return invalid("null pointer argument");
+    if (n_cap < 0 || (n_cap > 0 && (!params || !gauss_texel))) return invalid("params / gauss_texel null");
+    if (frames < 1 || channels < 11 || H < 1 || W < 1) return invalid("bad sizes (need frames >= 1, channels >= 11)");
+    if (!std::isfinite(s_max) || !std::isfinite(w_scale) || !std::isfinite(w_opacity)) return invalid("weights must be finite");
+    PG_CHECK_HIP(launch_regularisers(params, n_gauss_dev, n_cap, frames, channels, gauss_texel, (int64_t)H * W,
+                                     dyn_gauss, s_max, w_scale, w_opacity, dL_datlas, reg_loss, partial,
+                                     (hipStream_t)stream),
+                 "pg_loss_regularisers");
+    return PG_OK;
+}
+
 pg_status pg_flow_mask(const pg_views* v, const float* params, const uint8_t* flow_masks, uint8_t* tile_motion,
                        uint8_t* dyn_gauss, const int32_t* texel_gauss, int32_t H, int32_t W, uint8_t* dyn_texel,
                        uint64_t* counters, void* stream) {

@@ -1,4 +1,7 @@
-// Photometric objective (Sec. 4.2 "Objective"):
+// Objective terms of Sec. 4.2 "Objective": the photometric blend and the
+// scale / opacity regularisers.
+//
+// Photometric objective:
 //   L = (1 - lambda) mean |I - T| + lambda (1 - mean SSIM(I, T))
 // over every view, pixel and channel, and its cotangent dL/dI, in one pass.
 //
@@ -216,7 +219,120 @@ __global__ __launch_bounds__(1024) void k_photo_final(const double* __restrict__
     }
 }
 
+// ---------------------------------------------------------------- regularisers
+// Scale and opacity regularisers of the objective over the Gaussians of every
+// frame (or the dynamic ones):  L_scale = mean max(0, max_k s_k - s_max)^2,
+// L_opacity = mean o (1 - o), s = exp(l_s), o = sigmoid(l_o), in FP64 from
+// the FP32 texel values.  Three kernels: block sums of (count, hinge^2,
+// o (1 - o)); their total and the two means; the weighted gradients added to
+// the texel gradient (l_s through exp on the largest scale's channel, l_o
+// through the sigmoid), divided by the count.
+constexpr int kRegThreads = 256;
+
+struct RegTerms {
+    int kmax;
+    double smax, h, o;
+};
+
+__device__ __forceinline__ RegTerms reg_terms(const float* P, int64_t stride, double s_max) {
+    RegTerms r;
+    r.kmax = 0;
+    r.smax = exp((double)P[3 * stride]);
+    for (int k = 1; k < 3; k++) {
+        const double sk = exp((double)P[(3 + k) * stride]);
+        if (sk > r.smax) {
+            r.smax = sk;
+            r.kmax = k;
+        }
+    }
+    r.h = r.smax > s_max ? r.smax - s_max : 0.0;
+    r.o = 1.0 / (1.0 + exp(-(double)P[10 * stride]));
+    return r;
+}
+
+__global__ __launch_bounds__(kRegThreads) void k_reg_sum(const float* __restrict__ params,
+                                                         const int64_t* __restrict__ n_dev, int64_t n_cap,
+                                                         int32_t F, int32_t C, const uint8_t* __restrict__ dyn,
+                                                         double s_max, double* __restrict__ partial) {
+    __shared__ double s_w[3][kRegThreads / 64];
+    const int64_t n = imin(*n_dev, n_cap);
+    double cnt = 0.0, hs = 0.0, os = 0.0;
+    for (int64_t g = (int64_t)blockIdx.x * kRegThreads + threadIdx.x; g < (int64_t)F * n;
+         g += (int64_t)gridDim.x * kRegThreads) {
+        const int32_t f = (int32_t)(g / n);
+        const int64_t i = g - (int64_t)f * n;
+        if (dyn && !dyn[(int64_t)f * n_cap + i]) continue;
+        const RegTerms r = reg_terms(params + (int64_t)f * C * n_cap + i, n_cap, s_max);
+        cnt += 1.0;
+        hs += r.h * r.h;
+        os += r.o * (1.0 - r.o);
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        cnt += __shfl_xor(cnt, o, 64);
+        hs += __shfl_xor(hs, o, 64);
+        os += __shfl_xor(os, o, 64);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        s_w[0][threadIdx.x >> 6] = cnt;
+        s_w[1][threadIdx.x >> 6] = hs;
+        s_w[2][threadIdx.x >> 6] = os;
+    }
+    __syncthreads();
+    if (threadIdx.x < 3) {
+        double t = 0.0;
+        for (int w = 0; w < kRegThreads / 64; w++) t += s_w[threadIdx.x][w];
+        partial[3 * blockIdx.x + threadIdx.x] = t;
+    }
+}
+
+// partial[3 PG_REG_BLOCKS] <- the count; loss[0..1] <- the two means
+__global__ void k_reg_final(double* __restrict__ partial, float* __restrict__ loss) {
+    if (threadIdx.x != 0) return;
+    double cnt = 0.0, hs = 0.0, os = 0.0;
+    for (int b = 0; b < PG_REG_BLOCKS; b++) {
+        cnt += partial[3 * b];
+        hs += partial[3 * b + 1];
+        os += partial[3 * b + 2];
+    }
+    partial[3 * PG_REG_BLOCKS] = cnt;
+    loss[0] = cnt > 0.0 ? (float)(hs / cnt) : 0.0f;
+    loss[1] = cnt > 0.0 ? (float)(os / cnt) : 0.0f;
+}
+
+__global__ __launch_bounds__(kRegThreads) void k_reg_grad(const float* __restrict__ params,
+                                                          const int64_t* __restrict__ n_dev, int64_t n_cap,
+                                                          int32_t F, int32_t C, const uint8_t* __restrict__ dyn,
+                                                          const int32_t* __restrict__ gauss_texel, int64_t HW,
+                                                          double s_max, double w_scale, double w_opacity,
+                                                          const double* __restrict__ partial,
+                                                          float* __restrict__ gatlas) {
+    const int64_t n = imin(*n_dev, n_cap);
+    const double cnt = partial[3 * PG_REG_BLOCKS];
+    const int64_t g = (int64_t)blockIdx.x * kRegThreads + threadIdx.x;
+    if (g >= (int64_t)F * n || cnt <= 0.0) return;
+    const int32_t f = (int32_t)(g / n);
+    const int64_t i = g - (int64_t)f * n;
+    if (dyn && !dyn[(int64_t)f * n_cap + i]) return;
+    const RegTerms r = reg_terms(params + (int64_t)f * C * n_cap + i, n_cap, s_max);
+    float* out = gatlas + (int64_t)f * C * HW + gauss_texel[i];
+    if (r.h > 0.0) out[(int64_t)(3 + r.kmax) * HW] += (float)(w_scale * (2.0 * r.h * r.smax) / cnt);
+    out[10 * HW] += (float)(w_opacity * ((1.0 - 2.0 * r.o) * r.o * (1.0 - r.o)) / cnt);
+}
+
 }  // namespace
+
+hipError_t launch_regularisers(const float* params, const int64_t* n_dev, int64_t n_cap, int32_t F, int32_t C,
+                               const int32_t* gauss_texel, int64_t HW, const uint8_t* dyn, double s_max,
+                               double w_scale, double w_opacity, float* gatlas, float* loss, double* partial,
+                               hipStream_t s) {
+    k_reg_sum<<<PG_REG_BLOCKS, kRegThreads, 0, s>>>(params, n_dev, n_cap, F, C, dyn, s_max, partial);
+    k_reg_final<<<1, 64, 0, s>>>(partial, loss);
+    if (n_cap > 0)
+        k_reg_grad<<<(unsigned)ceil_div((int64_t)F * n_cap, kRegThreads), kRegThreads, 0, s>>>(
+            params, n_dev, n_cap, F, C, dyn, gauss_texel, HW, s_max, w_scale, w_opacity, partial, gatlas);
+    return hipGetLastError();
+}
 
 int64_t photo_blocks(const pg_views* v) { return v->n_ssim_blocks; }
 

@@ -80,6 +80,10 @@ hipError_t launch_fetch(const float* atlas, const uint8_t* occ, int32_t F, int32
 int64_t photo_blocks(const pg_views* v);
 hipError_t launch_photo(const pg_views* v, const float* image, const float* target, float lambda, float* dimg,
                         float* loss, double* partial, hipStream_t s);
+hipError_t launch_regularisers(const float* params, const int64_t* n_dev, int64_t n_cap, int32_t F, int32_t C,
+                               const int32_t* gauss_texel, int64_t HW, const uint8_t* dyn, double s_max,
+                               double w_scale, double w_opacity, float* gatlas, float* loss, double* partial,
+                               hipStream_t s);
 
 // quant.hip
 constexpr int kMaxQuantChannels = 64;       // channels a fake-quantiser call may hold

@@ -136,6 +136,7 @@ class Renderer:
         self.adam_v = None
         self.adam_t = None           # device step counter of the Adam update
         self._photo = None           # (view table, workspace, bytes, own table) of the photometric loss
+        self.reg_loss = None         # (L_scale, L_opacity) of the last regulariser call
 
     # ------------------------------------------------------------------ helpers
     def close(self):
@@ -237,6 +238,17 @@ class Renderer:
         abi.pg_loss_photo(h, self.image, target, lambda_ssim, self.dL_dimage, self.loss, ws, nb)
         return self.loss
 
+    def regularisers(self, s_max: float, w_scale: float = 1e-4, w_opacity: float = 1e-4, dyn_gauss=None):
+        """Adds w_scale dL_scale + w_opacity dL_opacity to dL_datlas (after the
+        adjoint); returns the device tensor (L_scale, L_opacity)."""
+        if self.reg_loss is None:
+            self.reg_loss = torch.zeros(2, dtype=torch.float32, device=self.device)
+            self.reg_partial = torch.empty(3 * abi.REG_BLOCKS + 1, dtype=torch.float64, device=self.device)
+        abi.pg_loss_regularisers(self.params, self.n_gauss_dev, self.N, self.frames, self.C, self.gauss_texel, self.H,
+                                 self.W, dyn_gauss, s_max, w_scale, w_opacity, self.dL_datlas, self.reg_loss,
+                                 self.reg_partial)
+        return self.reg_loss
+
     def loss_l1(self, target: torch.Tensor) -> torch.Tensor:
         n = 3 * self.n_pixels
         abi.pg_loss_l1(self.image, target, n, self.dL_dimage, self.loss_partial, self.loss)
@@ -274,15 +286,18 @@ class Renderer:
         abi.pg_adam_step(atlas, self.dL_datlas, self.adam_m, self.adam_v, self.visible, self.texel_gauss, self.N,
                          self.frames, self.C, self.H, self.W, lr, b1, b2, eps, 0, self.adam_t)
 
-    def step(self, atlas, target, adam=False, lambda_ssim=None):
+    def step(self, atlas, target, adam=False, lambda_ssim=None, reg=None):
         """One fitting step: forward, loss (L1, or the L1/SSIM blend when
-        lambda_ssim is given), adjoint (and Adam)."""
+        lambda_ssim is given), adjoint, the regularisers when reg (a dict of
+        regularisers() arguments) is given, and Adam."""
         self.forward(atlas)
         if lambda_ssim is None:
             self.loss_l1(target)
         else:
             self.loss_photo(target, lambda_ssim)
         self.backward()
+        if reg is not None:
+            self.regularisers(**reg)
         if adam:
             self.adam_step(atlas)
         return self.loss

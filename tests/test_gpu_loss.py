@@ -93,3 +93,30 @@ def test_step_with_ssim_texel_gradient():
     say(f"[gpu] step with SSIM dL/datlas: {st}")
     assert st["n_bad"] == 0 and st["worst_l2"] <= 1e-3, st
     r.close()
+
+
+def test_regularisers_match_oracle():
+    """Scale / opacity regularisers on every Gaussian and on a dynamic subset:
+    means to 1e-6, texel gradient to the gradient rule (FP64 on both sides)."""
+    sc = synth.random_scene(side=14, sh_degree=1, views=2, width=64, height=48, seed=33, frames=2,
+                            lscale=(-1.2, 0.8))
+    r = renderer(sc)
+    r.fetch(atlas_tensor(sc))
+    ids, params = oracle.fetch(sc.atlas, sc.occupancy)
+    F, C, N = params.shape
+    s_max, ws, wo = float(np.exp(-1.0)), 0.7, 1.3
+    rng = np.random.default_rng(12)
+    dyn = (rng.random((F, N)) < 0.4).astype(np.uint8)
+    for d in (None, dyn):
+        r.dL_datlas.zero_()
+        dt = None if d is None else torch.from_numpy(d.reshape(-1)).to("cuda:0")
+        loss = r.regularisers(s_max, ws, wo, dt).cpu().numpy()
+        Ls, Lo, g, n = oracle.regularisers(params, s_max, ws, wo, dyn=d)
+        say(f"[gpu] regularisers ({n} Gaussians): {loss.tolist()} vs {[Ls, Lo]}")
+        assert Ls > 0 and abs(loss[0] - Ls) <= 1e-6 * Ls and abs(loss[1] - Lo) <= 1e-6 * Lo
+        got = r.dL_datlas.cpu().numpy().reshape(F, C, -1)[:, :, ids]
+        st = grad_compare(got[:, [3, 4, 5, 10]], g[:, [3, 4, 5, 10]])
+        assert st["n_bad"] == 0 and st["worst_l2"] <= 1e-3, st
+        others = [c for c in range(C) if c not in (3, 4, 5, 10)]
+        assert not got[:, others].any()
+    r.close()
