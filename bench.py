@@ -237,6 +237,8 @@ def main():
     cpu = None if args.no_cpu_baseline else cpu_baseline(sc, rb, target, args.cpu_seconds)
     lpo = None if args.no_lpo else lpo_leg(sc, atlas, target, tiling, args.steps, args.warmup, not args.no_graph)
     fmask = None if args.no_lpo else flow_mask_leg(sc, rb, atlas)
+    objective = None if args.no_lpo else objective_leg(sc, rb, atlas, target, tiling, args.steps, args.warmup,
+                                                       not args.no_graph)
 
     out = {
         "metric": "fwd+bwd Mpixels/s & Gaussians/s, batched vs plain, at oracle-matched tolerance",
@@ -266,6 +268,7 @@ def main():
         "cpu_baseline": cpu,
         "lpo": lpo,
         "flow_mask": fmask,
+        "full_objective": objective,
         "autotune": tune_info,
     }
     rb.close()
@@ -275,6 +278,69 @@ def main():
         out["other_configs"] = [other_config(int(c), tiling, max(2, args.steps // 4), 2)
                                 for c in args.also_configs.split(",") if c.strip()]
     print(json.dumps(out), flush=True)
+
+
+# Algorithmic FP32 operations per pixel and channel of the photometric loss:
+# five separable window sums (2 passes x 11 taps x 2 flop each), the SSIM
+# value and its three partials (~40), and the separable adjoint blur of the
+# three partial maps (3 x 2 x 11 x 2).  The kernel recomputes the halo of
+# each 32 x 32 block (about 1.6 times this), which is not counted.
+FLOP_PHOTO = 5 * 2 * 11 * 2 + 40 + 3 * 2 * 11 * 2
+LAMBDA_SSIM = 0.2      # 3DGS's weight (the paper does not give one)
+S_MAX = 0.05           # scale cap for the scale regulariser (not given either)
+
+
+def objective_leg(sc, r, atlas, target, tiling, steps, warmup, graph):
+    """The full objective of the fitting step: the L1/SSIM blend (its kernel
+    timed alone with events) and the step with it and both regularisers
+    (weights 1e-4, the paper's)."""
+    import torch
+    stream = torch.cuda.current_stream()
+    r.forward(atlas)
+    r.loss_photo(target, LAMBDA_SSIM)
+    torch.cuda.synchronize()
+    reps = 10
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        r.loss_photo(target, LAMBDA_SSIM)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    lms = e0.elapsed_time(e1) / reps
+    reg = {"s_max": S_MAX, "w_scale": 1e-4, "w_opacity": 1e-4}
+    if graph:
+        side = torch.cuda.Stream()
+        side.wait_stream(stream)
+        with torch.cuda.stream(side):
+            r.step(atlas, target, lambda_ssim=LAMBDA_SSIM, reg=reg)
+        stream.wait_stream(side)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            r.step(atlas, target, lambda_ssim=LAMBDA_SSIM, reg=reg)
+        torch.cuda.synchronize()
+        run = g.replay
+    else:
+        def run():
+            r.step(atlas, target, lambda_ssim=LAMBDA_SSIM, reg=reg)
+    for _ in range(warmup):
+        run()
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(steps):
+        run()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    P = r.n_pixels
+    fl = FLOP_PHOTO * 3 * P
+    ach = fl / (lms / 1e3) / 1e12
+    return {"lambda_ssim": LAMBDA_SSIM, "s_max": S_MAX, "w_scale": 1e-4, "w_opacity": 1e-4,
+            "ms_per_step": round(ms, 4), "mpixels_per_s": round(P / ms / 1e3, 2), "loss": float(r.loss.item()),
+            "photo_loss_ms": round(lms, 4),
+            "photo_loss_roofline": {"bound": "alu", "achieved": round(ach, 3), "peak": PEAK_FP32_TFLOPS,
+                                    "unit": "TFLOP/s", "frac": round(ach / PEAK_FP32_TFLOPS, 4),
+                                    "flop_per_pixel_channel": FLOP_PHOTO}}
 
 
 # FP64 operations of the flow-masking kernel: the projection chain per

@@ -14,8 +14,8 @@
 // partials P_a = dS/da, P_c = dS/dE[x^2], P_e = dS/dE[xy]:
 //   dS/dx_q = (w * P_a)_q + 2 x_q (w * P_c)_q + y_q (w * P_e)_q.
 //
-// One work-group of 1024 threads per 32 x 32 pixel block of a view and one
-// channel at a time.  Everything stays in LDS: the inputs with a 10-pixel
+// One work-group of 512 threads per 32 x 32 pixel block of a view and one
+// channel at a time (the next channel's inputs load while one is computed).  Everything stays in LDS: the inputs with a 10-pixel
 // halo, their separable window sums over the 42 x 42 region the adjoint
 // needs, the three partial maps there (zero outside the view, where no S is
 // taken), and their separable blur back to the block.  The inputs are
@@ -35,7 +35,7 @@ constexpr int kK = 2 * kR + 1;
 constexpr int kB = 32;                      // output block side
 constexpr int kIW = kB + 4 * kR;            // input patch side (42 + 10 = 52 with 2 halos)
 constexpr int kMW = kB + 2 * kR;            // partial-map region side (42)
-constexpr int kThreads = kB * kB;
+constexpr int kThreads = 512;              // two output pixels per thread in the last pass
 constexpr float kC1 = 0.01f * 0.01f, kC2 = 0.03f * 0.03f;
 
 struct Win {
@@ -62,11 +62,18 @@ __global__ __launch_bounds__(kThreads) void k_photo(const ViewDev* __restrict__ 
                                                     const float* __restrict__ image, const float* __restrict__ target,
                                                     Win win, float lambda, double inv_n, float* __restrict__ dimg,
                                                     double* __restrict__ partial) {
-    __shared__ float sx[kIW * kIW], sy[kIW * kIW];
-    __shared__ float h5[5][kIW * kMW];
-    __shared__ float sm[3][kMW * kMW];
-    __shared__ float h3[3][kMW * kB];
+    // LDS by lifetime: the input patch, then (over it) the partial maps; the
+    // window sums, then (over them) the adjoint's horizontal blur.  65 KB, so
+    // two work-groups share a CU.
+    __shared__ float s_in[2 * kIW * kIW];
+    __shared__ float s_h5[5 * kIW * kMW];
     __shared__ double s_w[kThreads / 64];
+    static_assert(3 * kMW * kMW <= 2 * kIW * kIW && 3 * kMW * kB <= 5 * kIW * kMW, "LDS aliasing");
+    float* sx = s_in;
+    float* sy = s_in + kIW * kIW;
+    float (*h5)[kIW * kMW] = reinterpret_cast<float (*)[kIW * kMW]>(s_h5);
+    float (*sm)[kMW * kMW] = reinterpret_cast<float (*)[kMW * kMW]>(s_in);
+    float (*h3)[kMW * kB] = reinterpret_cast<float (*)[kMW * kB]>(s_h5);
     // view of this block (binary search over the per-view block bases)
     const int64_t blk = blockIdx.x;
     int lo = 0, hi = nv - 1;
@@ -80,87 +87,150 @@ __global__ __launch_bounds__(kThreads) void k_photo(const ViewDev* __restrict__ 
     const int32_t x0 = (int32_t)(local % BX) * kB, y0 = (int32_t)(local / BX) * kB;
     const int64_t HW = (int64_t)V.W * V.H;
     const int t = threadIdx.x;
-    const int tx = t % kB, ty = t / kB;
     double s_sum = 0.0, l1_sum = 0.0;
+    // each thread's share of a channel's input patch, loaded one channel ahead
+    constexpr int kPer = (kIW * kIW + kThreads - 1) / kThreads;
+    float px[kPer], py[kPer];
+    auto fetch = [&](int ch) __attribute__((always_inline)) {
+        const float* X = image + 3 * V.pix_base + ch * HW;
+        const float* Y = target + 3 * V.pix_base + ch * HW;
+#pragma unroll
+        for (int u = 0; u < kPer; u++) {
+            const int k = t + u * kThreads;
+            const int gx = x0 - 2 * kR + k % kIW, gy = y0 - 2 * kR + k / kIW;
+            const bool in = k < kIW * kIW && gx >= 0 && gx < V.W && gy >= 0 && gy < V.H;
+            const int64_t p = (int64_t)gy * V.W + gx;
+            px[u] = in ? X[p] : 0.0f;
+            py[u] = in ? Y[p] : 0.0f;
+        }
+    };
+    fetch(0);
     for (int ch = 0; ch < 3; ch++) {
         const float* X = image + 3 * V.pix_base + ch * HW;
         const float* Y = target + 3 * V.pix_base + ch * HW;
         const float kx = X[(int64_t)y0 * V.W + x0], ky = Y[(int64_t)y0 * V.W + x0];
         __syncthreads();   // the previous channel is done with the LDS
-        for (int k = t; k < kIW * kIW; k += kThreads) {
-            const int gx = x0 - 2 * kR + k % kIW, gy = y0 - 2 * kR + k / kIW;
-            const bool in = gx >= 0 && gx < V.W && gy >= 0 && gy < V.H;
-            const int64_t p = (int64_t)gy * V.W + gx;
-            sx[k] = (in ? X[p] : 0.0f) - kx;
-            sy[k] = (in ? Y[p] : 0.0f) - ky;
+#pragma unroll
+        for (int u = 0; u < kPer; u++) {
+            const int k = t + u * kThreads;
+            if (k < kIW * kIW) {
+                sx[k] = px[u] - kx;
+                sy[k] = py[u] - ky;
+            }
         }
         __syncthreads();
-        // horizontal window sums: input rows x partial-map columns
-        for (int k = t; k < kIW * kMW; k += kThreads) {
-            const int r = k / kMW, c = k % kMW;
-            float a = 0.f, b = 0.f, cc = 0.f, d = 0.f, e = 0.f;
+        if (ch < 2) fetch(ch + 1);   // in flight while this channel is computed
+        // horizontal window sums: input rows x partial-map columns, two adjacent
+        // columns per item (12 loads per input plane for 22 taps)
+        for (int k = t; k < kIW * (kMW / 2); k += kThreads) {
+            const int r = k / (kMW / 2), c = 2 * (k % (kMW / 2));
+            float a0 = 0.f, b0 = 0.f, c0 = 0.f, d0 = 0.f, e0 = 0.f;
+            float a1 = 0.f, b1 = 0.f, c1 = 0.f, d1 = 0.f, e1 = 0.f;
+            float xp = sx[r * kIW + c], yp = sy[r * kIW + c];
 #pragma unroll
             for (int j = 0; j < kK; j++) {
-                const float xv = sx[r * kIW + c + j], yv = sy[r * kIW + c + j], w = win.w[j];
-                a = fmaf(w, xv, a);
-                b = fmaf(w, yv, b);
-                cc = fmaf(w, xv * xv, cc);
-                d = fmaf(w, yv * yv, d);
-                e = fmaf(w, xv * yv, e);
+                const float xn = sx[r * kIW + c + j + 1], yn = sy[r * kIW + c + j + 1], w = win.w[j];
+                a0 = fmaf(w, xp, a0);
+                b0 = fmaf(w, yp, b0);
+                c0 = fmaf(w, xp * xp, c0);
+                d0 = fmaf(w, yp * yp, d0);
+                e0 = fmaf(w, xp * yp, e0);
+                a1 = fmaf(w, xn, a1);
+                b1 = fmaf(w, yn, b1);
+                c1 = fmaf(w, xn * xn, c1);
+                d1 = fmaf(w, yn * yn, d1);
+                e1 = fmaf(w, xn * yn, e1);
+                xp = xn;
+                yp = yn;
             }
-            h5[0][k] = a;
-            h5[1][k] = b;
-            h5[2][k] = cc;
-            h5[3][k] = d;
-            h5[4][k] = e;
+            const int o = r * kMW + c;
+            h5[0][o] = a0;
+            h5[1][o] = b0;
+            h5[2][o] = c0;
+            h5[3][o] = d0;
+            h5[4][o] = e0;
+            h5[0][o + 1] = a1;
+            h5[1][o + 1] = b1;
+            h5[2][o + 1] = c1;
+            h5[3][o + 1] = d1;
+            h5[4][o + 1] = e1;
         }
         __syncthreads();
-        // vertical window sums on the partial-map region -> S and its partials
-        for (int k = t; k < kMW * kMW; k += kThreads) {
-            const int r = k / kMW, c = k % kMW;
-            float m[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
+        // vertical window sums on the partial-map region -> S and its partials,
+        // two adjacent rows per item
+        for (int k = t; k < (kMW / 2) * kMW; k += kThreads) {
+            const int r0 = 2 * (k / kMW), c = k % kMW;
+            float m0[5] = {0.f, 0.f, 0.f, 0.f, 0.f}, m1[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
+            float prev[5];
 #pragma unroll
-            for (int j = 0; j < kK; j++) {
-                const float w = win.w[j];
-#pragma unroll
-                for (int q = 0; q < 5; q++) m[q] = fmaf(w, h5[q][(r + j) * kMW + c], m[q]);
-            }
-            const int gx = x0 - kR + c, gy = y0 - kR + r;
-            float pa = 0.f, pc = 0.f, pe = 0.f;
-            if (gx >= 0 && gx < V.W && gy >= 0 && gy < V.H) {
-                const float a = m[0] + kx, b = m[1] + ky;
-                const float vx = m[2] - m[0] * m[0], vy = m[3] - m[1] * m[1], cxy = m[4] - m[0] * m[1];
-                const float N1 = 2.0f * a * b + kC1, N2 = 2.0f * cxy + kC2;
-                const float D1 = a * a + b * b + kC1, D2 = vx + vy + kC2;
-                const float iD = 1.0f / (D1 * D2);
-                const float S = N1 * N2 * iD;
-                pa = 2.0f * b * (N2 - N1) * iD - S * (2.0f * a / D1 - 2.0f * a / D2);
-                pc = -S / D2;
-                pe = 2.0f * N1 * iD;
-                if (r >= kR && r < kR + kB && c >= kR && c < kR + kB) s_sum += (double)S;
-            }
-            sm[0][k] = pa;
-            sm[1][k] = pc;
-            sm[2][k] = pe;
-        }
-        __syncthreads();
-        // adjoint: blur the partial maps back to the block (horizontal, then vertical)
-        for (int k = t; k < kMW * kB; k += kThreads) {
-            const int r = k / kB, c = k % kB;
-            float a = 0.f, cc = 0.f, e = 0.f;
+            for (int q = 0; q < 5; q++) prev[q] = h5[q][r0 * kMW + c];
 #pragma unroll
             for (int j = 0; j < kK; j++) {
                 const float w = win.w[j];
-                a = fmaf(w, sm[0][r * kMW + c + j], a);
-                cc = fmaf(w, sm[1][r * kMW + c + j], cc);
-                e = fmaf(w, sm[2][r * kMW + c + j], e);
+#pragma unroll
+                for (int q = 0; q < 5; q++) {
+                    const float nx = h5[q][(r0 + j + 1) * kMW + c];
+                    m0[q] = fmaf(w, prev[q], m0[q]);
+                    m1[q] = fmaf(w, nx, m1[q]);
+                    prev[q] = nx;
+                }
             }
-            h3[0][k] = a;
-            h3[1][k] = cc;
-            h3[2][k] = e;
+#pragma unroll
+            for (int half = 0; half < 2; half++) {
+                const float* m = half ? m1 : m0;
+                const int r = r0 + half;
+                const int gx = x0 - kR + c, gy = y0 - kR + r;
+                float pa = 0.f, pc = 0.f, pe = 0.f;
+                if (gx >= 0 && gx < V.W && gy >= 0 && gy < V.H) {
+                    const float a = m[0] + kx, b = m[1] + ky;
+                    const float vx = m[2] - m[0] * m[0], vy = m[3] - m[1] * m[1], cxy = m[4] - m[0] * m[1];
+                    const float N1 = 2.0f * a * b + kC1, N2 = 2.0f * cxy + kC2;
+                    const float D1 = a * a + b * b + kC1, D2 = vx + vy + kC2;
+                    const float iD = 1.0f / (D1 * D2);
+                    const float S = N1 * N2 * iD;
+                    pa = 2.0f * b * (N2 - N1) * iD - S * (2.0f * a / D1 - 2.0f * a / D2);
+                    pc = -S / D2;
+                    pe = 2.0f * N1 * iD;
+                    if (r >= kR && r < kR + kB && c >= kR && c < kR + kB) s_sum += (double)S;
+                }
+                sm[0][r * kMW + c] = pa;
+                sm[1][r * kMW + c] = pc;
+                sm[2][r * kMW + c] = pe;
+            }
         }
         __syncthreads();
-        {
+        // adjoint: blur the partial maps back to the block (horizontal, then
+        // vertical), two adjacent columns per item
+        for (int k = t; k < kMW * (kB / 2); k += kThreads) {
+            const int r = k / (kB / 2), c = 2 * (k % (kB / 2));
+            float a0 = 0.f, c0 = 0.f, e0 = 0.f, a1 = 0.f, c1 = 0.f, e1 = 0.f;
+            float pa = sm[0][r * kMW + c], pc = sm[1][r * kMW + c], pe = sm[2][r * kMW + c];
+#pragma unroll
+            for (int j = 0; j < kK; j++) {
+                const float w = win.w[j];
+                const int o = r * kMW + c + j + 1;
+                const float na = sm[0][o], nc = sm[1][o], ne = sm[2][o];
+                a0 = fmaf(w, pa, a0);
+                c0 = fmaf(w, pc, c0);
+                e0 = fmaf(w, pe, e0);
+                a1 = fmaf(w, na, a1);
+                c1 = fmaf(w, nc, c1);
+                e1 = fmaf(w, ne, e1);
+                pa = na;
+                pc = nc;
+                pe = ne;
+            }
+            const int o = r * kB + c;
+            h3[0][o] = a0;
+            h3[1][o] = c0;
+            h3[2][o] = e0;
+            h3[0][o + 1] = a1;
+            h3[1][o + 1] = c1;
+            h3[2][o + 1] = e1;
+        }
+        __syncthreads();
+        for (int o = t; o < kB * kB; o += kThreads) {
+            const int tx = o % kB, ty = o / kB;
             float ga = 0.f, gc = 0.f, ge = 0.f;
 #pragma unroll
             for (int j = 0; j < kK; j++) {
