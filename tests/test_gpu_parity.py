@@ -1,5 +1,6 @@
 """GPU parity: the HIP path through the C ABI against the FP64 oracle on the
-same seeded scenes (tiny ragged scenes, a multi-frame window, and the two
+same seeded scenes (tiny ragged scenes, a multi-frame window, large
+Gaussians whose rectangles exceed 64 tiles, and the two
 workloads small enough for the oracle to finish in seconds: the 64x64-atlas
 single view and the 256x256-atlas ring of eight 512x512 views)."""
 import numpy as np
@@ -19,6 +20,9 @@ SCENES = {
                                          occupancy=0.7, lscale=(-3.0, 0.6)),
     "multiframe": lambda: synth.random_scene(side=10, sh_degree=2, views=2, width=64, height=50, seed=2, frames=3,
                                              lscale=(-2.7, 0.5), dynamic_frac=0.5),
+    # large Gaussians: rectangles of up to 110 tiles (more than 64 keep every tile)
+    "large": lambda: synth.random_scene(side=8, sh_degree=1, views=2, width=200, height=150, seed=5,
+                                        lscale=(-1.3, 0.4)),
     "config1": lambda: synth.make_scene(1),
     "config2": lambda: synth.make_scene(2),
 }
