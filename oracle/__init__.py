@@ -18,6 +18,8 @@ Parity status of each function (what pins it; see ``tests/test_oracle_*.py``):
   backward          -- two-Gaussian closed-form derivatives; central finite
                        differences of the forward with frozen decisions.
   loss_l1, adam     -- textbook closed forms.
+  uv_prune          -- axis directions and the theta = pi / phi = pi edges of the UV equation;
+                       numpy brute force (arctan2, arccos, lexsort) for the pixels and ranks.
   ssim              -- SSIM(x, x) = 1 with zero gradient; constant planes against the closed
                        form (2ab + C1)/(a^2 + b^2 + C1) in the interior; window statistics
                        against scipy.ndimage.correlate; symmetry; FD of the gradient.
@@ -80,6 +82,7 @@ def lib():
             "or_fake_quant": (None, [p, p, i32, i32, i32, i32, p, p, p, p]),
             "or_flow_mask": (None, [p, i64, i32, p, p, p]),
             "or_ssim": (f64, [p, p, i32, i32, p, p]),
+            "or_uv_prune": (None, [p, i64, i32, i32, i32, p, p, p, p]),
             "or_regularisers": (i64, [p, i32, i32, i64, p, f64, f64, f64, p, p]),
             "or_num_threads": (i32, []),
         }
@@ -131,6 +134,19 @@ def fetch(atlas: np.ndarray, occ: np.ndarray):
     got = lib().or_fetch(_p(atlas), _p(occ), F, Cc, H, W, _p(ids), _p(params))
     assert got == n
     return ids[:n], np.ascontiguousarray(params[:, :, :n])
+
+
+def uv_prune(params_f: np.ndarray, M: int, Nv: int, K: int, expected=None):
+    """(uv, rank, keep) of one frame's Gaussians (C, N) on an M x Nv UV map."""
+    P = np.ascontiguousarray(params_f, np.float64)
+    Cc, N = P.shape
+    uv = np.zeros(max(N, 1), np.int32)
+    rank = np.zeros(max(N, 1), np.int32)
+    keep = np.zeros(max(N, 1), np.uint8)
+    e = None if expected is None else np.ascontiguousarray(expected, np.int32)
+    lib().or_uv_prune(_p(P), N, int(M), int(Nv), int(K), _p(e) if e is not None else None, _p(uv), _p(rank),
+                      _p(keep))
+    return uv[:N], rank[:N], keep[:N]
 
 
 def ssim(x: np.ndarray, y: np.ndarray, grad: bool = False, smap: bool = False):

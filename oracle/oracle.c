@@ -24,6 +24,8 @@
  *   - Photometric objective (1 - lambda_ssim) L1 + lambda_ssim (1 - SSIM),
  *     scale and opacity regularisers: Sec. 4.2 "Objective".
  *   - Sparse Adam on FP32 master weights: Sec. 4.3 LPO paragraph.
+ *   - UV-based pruning (valid UV projection, top-K by opacity per UV pixel):
+ *     Sec. 4.2 pruning paragraph and the UV projection equation of Sec. 3.
  *   - Covariance-aware flow masking (dynamic label per Gaussian, OR across
  *     cameras): Sec. 4.2 masking paragraph and Algorithm 1.
  *   - LPO fake quantiser (uniform K-bit proxy, straight-through gradient,
@@ -926,6 +928,69 @@ void or_adam(double* p, const double* g, double* m, double* v, const uint8_t* vi
         const double mh = m[e] / c1, vh = v[e] / c2;
         p[e] = p[e] - lr * mh / (sqrt(vh) + eps);
     }
+}
+
+/* ------------------------------------------------------------------ UV pruning
+ * UV-based pruning (Sec. 4.2 "UV-Based Pruning", with the UV projection
+ * equation of Sec. 3): a Gaussian's position in spherical coordinates
+ * (rho, theta = atan2(y, x), phi = acos(z / rho)) gives the UV pixel
+ * u = floor((pi + theta) / (2 pi) M), v = floor(phi / pi N) of an M x N map.
+ * theta = pi (the direction of -pi) wraps to u = 0; phi = pi stays in the
+ * last row; rho = 0 has no direction and is invalid.  Valid UV projection:
+ * when expected (the pixel v M + u of the texel that stores the Gaussian) is
+ * given, a Gaussian that maps elsewhere is invalid.  Max-K: among the valid
+ * Gaussians of a pixel, the K of highest opacity are kept (ranked by the
+ * logit, which orders like the opacity; ties by ascending id).
+ *   uv    int32 [N] out: v M + u, -1 if invalid
+ *   rank  int32 [N] out: rank inside the pixel, -1 if invalid
+ *   keep  uint8 [N] out */
+typedef struct {
+    int32_t key, id;
+    double logit;
+} or_uvrec;
+
+static int uvrec_cmp(const void* pa, const void* pb) {
+    const or_uvrec* a = (const or_uvrec*)pa;
+    const or_uvrec* b = (const or_uvrec*)pb;
+    if (a->key != b->key) return a->key < b->key ? -1 : 1;
+    if (a->logit != b->logit) return a->logit > b->logit ? -1 : 1;
+    return a->id < b->id ? -1 : (a->id > b->id);
+}
+
+void or_uv_prune(const double* P, int64_t N, int32_t M, int32_t Nv, int32_t K, const int32_t* expected,
+                 int32_t* uv, int32_t* rank, uint8_t* keep) {
+    or_uvrec* r = (or_uvrec*)malloc(sizeof(or_uvrec) * (size_t)(N > 0 ? N : 1));
+    int64_t n = 0;
+    for (int64_t i = 0; i < N; i++) {
+        const double x = P[0 * N + i], y = P[1 * N + i], z = P[2 * N + i];
+        const double rho = sqrt((x * x + y * y) + z * z);
+        uv[i] = -1;
+        rank[i] = -1;
+        keep[i] = 0;
+        if (!(rho > 0.0)) continue;
+        const double theta = atan2(y, x);
+        double c = z / rho;
+        c = c > 1.0 ? 1.0 : (c < -1.0 ? -1.0 : c);
+        const double phi = acos(c);
+        int64_t u = (int64_t)floor((3.141592653589793 + theta) / (2.0 * 3.141592653589793) * (double)M);
+        int64_t v = (int64_t)floor(phi / 3.141592653589793 * (double)Nv);
+        if (u >= M) u -= M;
+        if (v >= Nv) v = Nv - 1;
+        const int32_t key = (int32_t)(v * M + u);
+        if (expected && expected[i] != key) continue;
+        uv[i] = key;
+        r[n].key = key;
+        r[n].id = (int32_t)i;
+        r[n].logit = P[10 * N + i];
+        n++;
+    }
+    qsort(r, (size_t)n, sizeof(or_uvrec), uvrec_cmp);
+    for (int64_t j = 0, start = 0; j < n; j++) {
+        if (j > 0 && r[j].key != r[j - 1].key) start = j;
+        rank[r[j].id] = (int32_t)(j - start);
+        keep[r[j].id] = (j - start) < K;
+    }
+    free(r);
 }
 
 /* ------------------------------------------------------------------ SSIM
