@@ -212,6 +212,27 @@ pg_status pg_atlas_fake_quant(float* params, const int64_t* n_gauss_dev, int64_t
 pg_status pg_project(const pg_views* views, const float* params, pg_splat* splats, pg_bin* bins,
                      pg_tile_set* tiles, uint8_t* visible, void* stream);
 
+/* UV-based pruning (Sec. 4.2 "UV-Based Pruning", with the UV projection
+ * equation of Sec. 3).  Each fetched Gaussian's position gives its UV pixel
+ * on an M x Nv map: u = floor((pi + atan2(y, x)) / (2 pi) M),
+ * v = floor(acos(z / rho) / pi Nv) (FP64; theta = pi wraps to u = 0,
+ * phi = pi stays in the last row; rho = 0 is invalid).  Valid UV
+ * projection: with expected_uv given, a Gaussian that does not map to its
+ * entry there is invalid.  Max-K: per frame and pixel, the K valid
+ * Gaussians of highest opacity are kept (by the logit; ties by ascending
+ * id).  Outputs for the first min(N, n_cap) Gaussians of each frame:
+ *   uv           device int32 [F][n_cap] out: v M + u, -1 if invalid
+ *   rank         device int32 [F][n_cap] out: rank in the pixel by opacity,
+ *                -1 if invalid
+ *   keep         device uint8 [F][n_cap] out: 1 for the kept Gaussians
+ *   expected_uv  device int32 [F][n_cap] or NULL
+ *   ws           device workspace of pg_uv_prune_workspace_size bytes
+ * F M Nv and F n_cap must stay below 2^31. */
+pg_status pg_uv_prune_workspace_size(int64_t n_cap, int32_t frames, int32_t M, int32_t Nv, size_t* bytes);
+pg_status pg_uv_prune(const float* params, const int64_t* n_gauss_dev, int64_t n_cap, int32_t frames,
+                      int32_t channels, int32_t M, int32_t Nv, int32_t K, const int32_t* expected_uv, int32_t* uv,
+                      int32_t* rank, uint8_t* keep, void* ws, size_t ws_bytes, void* stream);
+
 /* Covariance-aware flow masking (Sec. 4.2 "Covariance-Aware Gaussian
  * Masking"; Algorithm 1): the dynamic labels D that gradient freezing uses.
  * For every view and every Gaussian of its frame: the projection of

@@ -70,6 +70,8 @@ SIGNATURES = {
     "pg_project_bwd": (_i32, [_p, _p, _p, _p, _p, _i64, _p, _p, _p, _i32, _i32, _p, _p, _i32, _p]),
     "pg_loss_l1": (_i32, [_p, _p, _i64, _p, _p, _p, _p]),
     "pg_photo_workspace_size": (_i32, [_p, C.POINTER(_sz)]),
+    "pg_uv_prune_workspace_size": (_i32, [_i64, _i32, _i32, _i32, C.POINTER(_sz)]),
+    "pg_uv_prune": (_i32, [_p, _p, _i64, _i32, _i32, _i32, _i32, _i32, _p, _p, _p, _p, _p, _sz, _p]),
     "pg_loss_regularisers": (_i32, [_p, _p, _i64, _i32, _i32, _p, _i32, _i32, _p, _f32, _f32, _f32, _p, _p, _p, _p]),
     "pg_loss_photo": (_i32, [_p, _p, _p, _f32, _p, _p, _p, _sz, _p]),
     "pg_adam_step": (_i32, [_p, _p, _p, _p, _p, _p, _i64, _i32, _i32, _i32, _i32, _f32, _f32, _f32, _f32, _i32, _p,
@@ -274,6 +276,20 @@ def pg_loss_regularisers(params, n_gauss_dev, n_cap, frames, channels, gauss_tex
                                       _ptr(gauss_texel), int(H), int(W), _ptr(dyn_gauss), float(s_max),
                                       float(w_scale), float(w_opacity), _ptr(dL_datlas), _ptr(reg_loss),
                                       _ptr(partial), _stream(stream)), "pg_loss_regularisers")
+
+
+def pg_uv_prune_workspace_size(n_cap, frames, M, Nv) -> int:
+    n = C.c_size_t()
+    _check(lib().pg_uv_prune_workspace_size(int(n_cap), int(frames), int(M), int(Nv), C.byref(n)),
+           "pg_uv_prune_workspace_size")
+    return n.value
+
+
+def pg_uv_prune(params, n_gauss_dev, n_cap, frames, channels, M, Nv, K, expected_uv, uv, rank, keep, ws, ws_bytes,
+                stream=None):
+    _check(lib().pg_uv_prune(_ptr(params), _ptr(n_gauss_dev), int(n_cap), int(frames), int(channels), int(M), int(Nv),
+                             int(K), _ptr(expected_uv), _ptr(uv), _ptr(rank), _ptr(keep), _ptr(ws), int(ws_bytes),
+                             _stream(stream)), "pg_uv_prune")
 
 
 def pg_adam_step(atlas, grad, m, v, visible, texel_gauss, n_gauss, frames, channels, H, W, lr, beta1, beta2, eps,

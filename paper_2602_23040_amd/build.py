@@ -30,7 +30,7 @@ FLAGS = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17", "-ffp-contract=o
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wall", "-Wno-unused-function", "-Wno-unused-variable",
          "-I" + os.path.join(ROOT, "include"), "-I" + CSRC]
-SOURCES = ["api.hip", "scan.hip", "fetch.hip", "quant.hip", "loss.hip", "project.hip", "binsort.hip", "render.hip", "optim.hip"]
+SOURCES = ["api.hip", "scan.hip", "fetch.hip", "quant.hip", "loss.hip", "uvprune.hip", "project.hip", "binsort.hip", "render.hip", "optim.hip"]
 
 
 def _compile(src: str, verbose: bool) -> str:

@@ -374,6 +374,41 @@ pg_status pg_loss_regularisers(const float* params, const int64_t* n_gauss_dev, 
     return PG_OK;
 }
 
+static pg_status uv_prune_check(int64_t n_cap, int32_t frames, int32_t M, int32_t Nv) {
+    if (n_cap < 0 || frames < 1 || M < 1 || Nv < 1) return invalid("need n_cap >= 0, frames, M, Nv >= 1");
+    if ((int64_t)frames * M * Nv + 1 >= INT32_MAX) return invalid("frames * M * Nv must stay below 2^31");
+    if ((int64_t)frames * n_cap >= INT32_MAX) return invalid("frames * n_cap must stay below 2^31");
+    return PG_OK;
+}
+
+pg_status pg_uv_prune_workspace_size(int64_t n_cap, int32_t frames, int32_t M, int32_t Nv, size_t* bytes) {
+    g_error.clear();
+    if (!bytes) return invalid("null argument");
+    const pg_status st = uv_prune_check(n_cap, frames, M, Nv);
+    if (st != PG_OK) return st;
+    *bytes = uv_prune_ws_bytes(n_cap, frames, M, Nv);
+    return PG_OK;
+}
+
+pg_status pg_uv_prune(const float* params, const int64_t* n_gauss_dev, int64_t n_cap, int32_t frames,
+                      int32_t channels, int32_t M, int32_t Nv, int32_t K, const int32_t* expected_uv, int32_t* uv,
+                      int32_t* rank, uint8_t* keep, void* ws, size_t ws_bytes, void* stream) {
+    g_error.clear();
+    const pg_status st = uv_prune_check(n_cap, frames, M, Nv);
+    if (st != PG_OK) return st;
+    if (channels < 11 || K < 0) return invalid("need channels >= 11 and K >= 0");
+    if (!n_gauss_dev || !ws) return invalid("null pointer argument");
+    if (n_cap > 0 && (!params || !uv || !rank || !keep)) return invalid("null pointer argument");
+    if (ws_bytes < uv_prune_ws_bytes(n_cap, frames, M, Nv)) {
+        set_error("UV pruning workspace too small");
+        return PG_ERR_WORKSPACE;
+    }
+    PG_CHECK_HIP(launch_uv_prune(params, n_gauss_dev, n_cap, frames, channels, M, Nv, K, expected_uv, uv, rank, keep,
+                                 ws, (hipStream_t)stream),
+                 "pg_uv_prune");
+    return PG_OK;
+}
+
 pg_status pg_flow_mask(const pg_views* v, const float* params, const uint8_t* flow_masks, uint8_t* tile_motion,
                        uint8_t* dyn_gauss, const int32_t* texel_gauss, int32_t H, int32_t W, uint8_t* dyn_texel,
                        uint64_t* counters, void* stream) {

@@ -530,6 +530,65 @@ __global__ __launch_bounds__(256) void k_ranges(const uint32_t* __restrict__ key
 
 }  // namespace
 
+// ---------------------------------------------------------------- generic stable pair sort
+// The same LSD passes for other parts of the library: n (read on the device,
+// at most cap) uint32 keys whose low `bits` bits matter, with int32 values,
+// ping-ponged between the two buffer pairs; *out_keys / *out_vals name the
+// pair that holds the result.
+namespace {
+SortWs carve_pairs(int64_t cap, int bits, void* ws, size_t* total) {
+    const int passes = imax((bits + kMaxDigitBits - 1) / kMaxDigitBits, 1);
+    const int digit = (bits + passes - 1) / passes;
+    const int64_t ntile = imax(ceil_div(imax(cap, 1), kSortTile), 1);
+    const int64_t nch = ceil_div(ntile, kChunkTiles);
+    SortWs w{};
+    char* p = (char*)ws;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        char* q = p + off;
+        off += align256(bytes);
+        return q;
+    };
+    w.scan_tmp = (int64_t*)take(kScanTmpWords * 8);
+    w.counts = (int32_t*)take(((int64_t)1 << digit) * ntile * 4);
+    w.count_offs = (int32_t*)take(((int64_t)1 << digit) * ntile * 4);
+    w.chunk_dm = (int32_t*)take(((int64_t)1 << digit) * nch * 4);
+    w.chunk_off = (int32_t*)take(((int64_t)1 << digit) * nch * 4);
+    if (total) *total = off;
+    return w;
+}
+}  // namespace
+
+size_t sort_pairs_ws_bytes(int64_t cap, int bits) {
+    size_t total = 0;
+    carve_pairs(cap, bits, nullptr, &total);
+    return total;
+}
+
+hipError_t sort_pairs(uint32_t* keys, int32_t* vals, uint32_t* keys_alt, int32_t* vals_alt, const int64_t* n_dev,
+                      int64_t cap, int bits, void* ws, uint32_t** out_keys, int32_t** out_vals, hipStream_t s) {
+    const int passes = imax((bits + kMaxDigitBits - 1) / kMaxDigitBits, 1);
+    const int digit = (bits + passes - 1) / passes;
+    SortWs w = carve_pairs(cap, bits, ws, nullptr);
+    const unsigned grid = (unsigned)imax(1, imin(kSortGrid, ceil_div(cap, kSortTile)));
+    const int64_t nch = ceil_div(imax(ceil_div(imax(cap, 1), kSortTile), 1), kChunkTiles);
+    uint32_t *ka = keys, *kb = keys_alt;
+    int32_t *va = vals, *vb = vals_alt;
+    for (int p = 0; p < passes; p++) {
+        const hipError_t e = radix_pass<uint32_t>(digit, ka, va, kb, vb, n_dev, nch, p * digit, w, grid, s);
+        if (e != hipSuccess) return e;
+        uint32_t* tk = ka;
+        ka = kb;
+        kb = tk;
+        int32_t* tv = va;
+        va = vb;
+        vb = tv;
+    }
+    *out_keys = ka;
+    *out_vals = va;
+    return hipGetLastError();
+}
+
 size_t sort_ws_bytes(const pg_views* v, int64_t cap) {
     size_t total = 0;
     carve(v, cap, nullptr, &total);

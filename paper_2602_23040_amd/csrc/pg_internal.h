@@ -85,6 +85,12 @@ hipError_t launch_regularisers(const float* params, const int64_t* n_dev, int64_
                                double w_scale, double w_opacity, float* gatlas, float* loss, double* partial,
                                hipStream_t s);
 
+// uvprune.hip
+size_t uv_prune_ws_bytes(int64_t n_cap, int32_t F, int32_t M, int32_t Nv);
+hipError_t launch_uv_prune(const float* params, const int64_t* n_dev, int64_t n_cap, int32_t F, int32_t C, int32_t M,
+                           int32_t Nv, int32_t K, const int32_t* expected, int32_t* uv, int32_t* rank, uint8_t* keep,
+                           void* ws, hipStream_t s);
+
 // quant.hip
 constexpr int kMaxQuantChannels = 64;       // channels a fake-quantiser call may hold
 constexpr int kQuantBlocks = PG_QUANT_BLOCKS;
@@ -111,6 +117,11 @@ hipError_t launch_bin_sort(const pg_views* v, const pg_bin* bins, const pg_tile_
                            uint32_t* keys, int32_t* values,
                            int32_t* ranges, int32_t* inst_first, int64_t* n_inst_dev, int32_t* overflow_dev,
                            float* inst_grad, void* ws, hipStream_t s);
+
+// stable sort of (uint32 key, int32 value) pairs (binsort.hip)
+size_t sort_pairs_ws_bytes(int64_t cap, int bits);
+hipError_t sort_pairs(uint32_t* keys, int32_t* vals, uint32_t* keys_alt, int32_t* vals_alt, const int64_t* n_dev,
+                      int64_t cap, int bits, void* ws, uint32_t** out_keys, int32_t** out_vals, hipStream_t s);
 
 // render.hip
 hipError_t launch_render_fwd(const pg_views* v, const pg_splat* splats, const int32_t* values,

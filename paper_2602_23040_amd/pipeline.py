@@ -249,6 +249,20 @@ class Renderer:
                                  self.reg_partial)
         return self.reg_loss
 
+    def uv_prune(self, atlas: torch.Tensor, M: int, Nv: int, K: int, expected_uv=None):
+        """UV-based pruning of the fetched Gaussians on an M x Nv UV map:
+        returns (uv, rank, keep) as device tensors of shape [F N]."""
+        self.fetch(atlas)
+        n = self.frames * self.N
+        uv = torch.empty(max(n, 1), dtype=torch.int32, device=self.device)
+        rank = torch.empty_like(uv)
+        keep = torch.empty(max(n, 1), dtype=torch.uint8, device=self.device)
+        nb = abi.pg_uv_prune_workspace_size(self.N, self.frames, M, Nv)
+        ws = torch.empty(nb, dtype=torch.uint8, device=self.device)
+        abi.pg_uv_prune(self.params, self.n_gauss_dev, self.N, self.frames, self.C, M, Nv, K, expected_uv, uv, rank,
+                        keep, ws, nb)
+        return uv[:n], rank[:n], keep[:n]
+
     def loss_l1(self, target: torch.Tensor) -> torch.Tensor:
         n = 3 * self.n_pixels
         abi.pg_loss_l1(self.image, target, n, self.dL_dimage, self.loss_partial, self.loss)
