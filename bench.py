@@ -237,6 +237,7 @@ def main():
     cpu = None if args.no_cpu_baseline else cpu_baseline(sc, rb, target, args.cpu_seconds)
     lpo = None if args.no_lpo else lpo_leg(sc, atlas, target, tiling, args.steps, args.warmup, not args.no_graph)
     fmask = None if args.no_lpo else flow_mask_leg(sc, rb, atlas)
+    uvp = None if args.no_lpo else uv_prune_leg(sc, rb, atlas)
     objective = None if args.no_lpo else objective_leg(sc, rb, atlas, target, tiling, args.steps, args.warmup,
                                                        not args.no_graph)
 
@@ -269,6 +270,7 @@ def main():
         "lpo": lpo,
         "flow_mask": fmask,
         "full_objective": objective,
+        "uv_prune": uvp,
         "autotune": tune_info,
     }
     rb.close()
@@ -288,6 +290,35 @@ def main():
 FLOP_PHOTO = 5 * 2 * 11 * 2 + 40 + 3 * 2 * 11 * 2
 LAMBDA_SSIM = 0.2      # 3DGS's weight (the paper does not give one)
 S_MAX = 0.05           # scale cap for the scale regulariser (not given either)
+
+
+def uv_prune_leg(sc, r, atlas, M=512, Nv=256, K=2, reps=5):
+    """UV-based pruning of the workload's Gaussians on an M x Nv map (top K by
+    opacity per pixel), timed with events; HBM-bound: two stable radix sorts
+    of (key, index) pairs over the Gaussians plus a gather of their position
+    and opacity."""
+    import torch
+    from paper_2602_23040_amd import _abi as abi
+    stream = torch.cuda.current_stream()
+    uv, rank, keep = r.uv_prune(atlas, M, Nv, K)
+    torch.cuda.synchronize()
+    kept = int(keep.sum().item())
+    n = r.frames * r.N
+    nb = abi.pg_uv_prune_workspace_size(r.N, r.frames, M, Nv)
+    ws = torch.empty(nb, dtype=torch.uint8, device="cuda:0")
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        abi.pg_uv_prune(r.params, r.n_gauss_dev, r.N, r.frames, r.C, M, Nv, K, None, uv, rank, keep, ws, nb, stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    passes = 4 + (max(1, (r.frames * M * Nv).bit_length()) + 7) // 8
+    nbytes = n * (16 + 4 * 3 + 1) + passes * 20 * n      # read 4 channels, write uv/rank/keep; 20 B per item per pass
+    gbs = nbytes / (ms / 1e3) / 1e9
+    return {"M": M, "N": Nv, "K": K, "ms": round(ms, 4), "gaussians": n, "kept": kept,
+            "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                         "frac": round(gbs / PEAK_HBM_GBS, 4), "bytes": nbytes}}
 
 
 def objective_leg(sc, r, atlas, target, tiling, steps, warmup, graph):
