@@ -196,6 +196,8 @@ def main():
     wall = time.perf_counter() - t0
     ms = e0.elapsed_time(e1) / args.steps
     assert not rb.overflowed(), "instance capacity overflowed inside the timed region"
+    # spread of single steps (after the timed region): each step between its own events
+    dist = step_spread(run_step, max(10, args.steps))
     loss = float(rb.loss.item())
 
     # --- per-kernel live timing of the step's stages (same stream, eager calls)
@@ -211,6 +213,29 @@ def main():
     torch.cuda.synchronize()
     ms_plain = (time.perf_counter() - t0p) * 1e3 / args.plain_steps
     same_img = bool(torch.equal(rp.image, rb.image))
+    # plain + graph: the same per-view chain captured once its capacities are known
+    ms_plain_graph = None
+    if not args.no_graph:
+        rp.plain_sync = False
+        side = torch.cuda.Stream()
+        side.wait_stream(stream)
+        with torch.cuda.stream(side):
+            rp.step(atlas, target)
+        stream.wait_stream(side)
+        torch.cuda.synchronize()
+        pg = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(pg):
+            rp.step(atlas, target)
+        pg.replay()
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(args.plain_steps):
+            pg.replay()
+        e1.record()
+        torch.cuda.synchronize()
+        assert not rp.overflowed(), "plain capacities overflowed under graph replay"
+        ms_plain_graph = e0.elapsed_time(e1) / args.plain_steps
+        del pg
     rp.close()
 
     # --- roofline for the stage with the largest time share
@@ -259,7 +284,9 @@ def main():
                    "tiling": "x".join(str(t) for t in tiling), "graph": not args.no_graph},
         "gaussians_per_s": round(N * V / ms * 1e3, 1),
         "plain": {"ms_per_step": round(ms_plain, 3), "mpixels_per_s": round(P / ms_plain / 1e3, 2),
-                  "gaussians_per_s": round(N * V / ms_plain * 1e3, 1), "image_bitwise_equal": same_img},
+                  "gaussians_per_s": round(N * V / ms_plain * 1e3, 1), "image_bitwise_equal": same_img,
+                  "graph_ms_per_step": None if ms_plain_graph is None else round(ms_plain_graph, 3)},
+        "step_ms_spread": dist,
         "speedup_vs_plain": round(ms_plain / ms, 3),
         "wall_s_timed": round(wall, 4),
         "work": {"instances": n_inst, "pairs_evaluated": n_eval, "pairs_composited": n_comp, "pixels": P,
@@ -290,6 +317,32 @@ def main():
 FLOP_PHOTO = 5 * 2 * 11 * 2 + 40 + 3 * 2 * 11 * 2
 LAMBDA_SSIM = 0.2      # 3DGS's weight (the paper does not give one)
 S_MAX = 0.05           # scale cap for the scale regulariser (not given either)
+
+
+def step_spread(run_step, reps):
+    """Median, p10 and p90 of `reps` single steps, each between its own events."""
+    import numpy as np
+    import torch
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(reps + 1)]
+    ev[0].record()
+    for i in range(reps):
+        run_step()
+        ev[i + 1].record()
+    torch.cuda.synchronize()
+    t = np.array([ev[i].elapsed_time(ev[i + 1]) for i in range(reps)])
+    return {"reps": reps, "median": round(float(np.median(t)), 4), "p10": round(float(np.percentile(t, 10)), 4),
+            "p90": round(float(np.percentile(t, 90)), 4)}
+
+
+def host_cpu():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
 
 
 def uv_prune_leg(sc, r, atlas, M=512, Nv=256, K=2, reps=5):
@@ -633,9 +686,24 @@ def cpu_baseline(sc, rb, target, budget_s):
         unexplained += len(unexp)
         if t_total >= budget_s:
             break
-    return {"value": round(pix / t_total / 1e6, 4), "unit": "Mpixels/s", "cores": oracle.num_threads(),
+    # the same work on one thread (the first view once more)
+    cores = oracle.num_threads()
+    c = sc.cams[0]
+    oracle.set_num_threads(1)
+    try:
+        t0 = time.perf_counter()
+        fw = oracle.Forward(sc, views=[0])
+        _, G = fw.loss({0: rng.uniform(0.0, 1.0, (3, c.height, c.width))})
+        fw.backward(G)
+        t1 = time.perf_counter() - t0
+    finally:
+        oracle.set_num_threads(cores)
+    return {"value": round(pix / t_total / 1e6, 4), "unit": "Mpixels/s", "cores": cores,
             "kind": "oracle",
             "sample": f"views {sample} of the same workload (fwd + L1 + adjoint, FP64), {t_total:.1f} s",
+            "single_thread": {"value": round(c.width * c.height / t1 / 1e6, 4), "unit": "Mpixels/s",
+                              "sample": f"view 0, {t1:.1f} s"},
+            "host": {"cpu": host_cpu(), "nproc": os.cpu_count()},
             "parity_sample": {"pixels": pix, "beyond_1e-4": beyond, "unexplained": unexplained}}
 
 

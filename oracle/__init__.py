@@ -85,6 +85,7 @@ def lib():
             "or_uv_prune": (None, [p, i64, i32, i32, i32, p, p, p, p]),
             "or_regularisers": (i64, [p, i32, i32, i64, p, f64, f64, f64, p, p]),
             "or_num_threads": (i32, []),
+            "or_set_num_threads": (None, [i32]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -100,6 +101,10 @@ def _p(a):
 
 def num_threads() -> int:
     return int(lib().or_num_threads())
+
+
+def set_num_threads(n: int) -> None:
+    lib().or_set_num_threads(int(n))
 
 
 def cam_record(cam) -> np.ndarray:

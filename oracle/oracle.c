@@ -1213,6 +1213,14 @@ void or_fake_quant(const float* atlas, const uint8_t* occ, int32_t F, int32_t C,
     }
 }
 
+void or_set_num_threads(int32_t n) {
+#ifdef _OPENMP
+    omp_set_num_threads(n > 0 ? n : 1);
+#else
+    (void)n;
+#endif
+}
+
 int32_t or_num_threads(void) {
 #ifdef _OPENMP
     return omp_get_max_threads();

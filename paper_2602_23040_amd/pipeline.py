@@ -94,6 +94,9 @@ class Renderer:
         self.V = len(self.cams)
         self.bg = tuple(float(b) for b in bg)
         self.batched = bool(batched)
+        # plain path: check each view's instance count on the host (False once
+        # the capacities are known, e.g. to capture the per-view chain in a graph)
+        self.plain_sync = True
         self.tiling = abi.make_tiling(*tiling)
         dev = self.device
         self.occ = _u8(occ, dev)
@@ -191,7 +194,7 @@ class Renderer:
         abi.pg_project(s.handle, self.params, s.splats, s.bins, s.tiles, self.visible)
         abi.pg_bin_sort(s.handle, s.bins, s.tiles, s.cap, s.keys, s.values, s.ranges, s.inst_first, s.n_inst, s.overflow,
                         s.inst_grad, s.ws, s.ws_bytes)
-        if not self.batched:
+        if not self.batched and self.plain_sync:
             # plain path: one instance-count synchronisation per view
             if int(s.overflow.item()):
                 s.set_capacity(int(math.ceil(int(s.n_inst.item()) * 1.25)))
