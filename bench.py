@@ -59,7 +59,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--config", type=int, default=3)
-    ap.add_argument("--plain-steps", type=int, default=3)
+    ap.add_argument("--plain-steps", type=int, default=3, help="0 skips the plain (per-view) leg")
     ap.add_argument("--tiling", type=str, default="auto", help="auto (autotuner) or WxHxB, e.g. 16x16x256")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
@@ -203,40 +203,42 @@ def main():
     # --- per-kernel live timing of the step's stages (same stream, eager calls)
     stages = stage_times(rb, atlas, target, reps=5)
 
-    # --- plain path: same kernels one view at a time
-    rp = make(False)
-    rp.step(atlas, target)
-    torch.cuda.synchronize()
-    t0p = time.perf_counter()
-    for _ in range(args.plain_steps):
+    # --- plain path: same kernels one view at a time (--plain-steps 0 skips it)
+    ms_plain = ms_plain_graph = None
+    same_img = None
+    if args.plain_steps > 0:
+        rp = make(False)
         rp.step(atlas, target)
-    torch.cuda.synchronize()
-    ms_plain = (time.perf_counter() - t0p) * 1e3 / args.plain_steps
-    same_img = bool(torch.equal(rp.image, rb.image))
-    # plain + graph: the same per-view chain captured once its capacities are known
-    ms_plain_graph = None
-    if not args.no_graph:
-        rp.plain_sync = False
-        side = torch.cuda.Stream()
-        side.wait_stream(stream)
-        with torch.cuda.stream(side):
-            rp.step(atlas, target)
-        stream.wait_stream(side)
         torch.cuda.synchronize()
-        pg = torch.cuda.CUDAGraph()
-        with torch.cuda.graph(pg):
-            rp.step(atlas, target)
-        pg.replay()
-        torch.cuda.synchronize()
-        e0.record()
+        t0p = time.perf_counter()
         for _ in range(args.plain_steps):
-            pg.replay()
-        e1.record()
+            rp.step(atlas, target)
         torch.cuda.synchronize()
-        assert not rp.overflowed(), "plain capacities overflowed under graph replay"
-        ms_plain_graph = e0.elapsed_time(e1) / args.plain_steps
-        del pg
-    rp.close()
+        ms_plain = (time.perf_counter() - t0p) * 1e3 / args.plain_steps
+        same_img = bool(torch.equal(rp.image, rb.image))
+        # plain + graph: the same per-view chain captured once its capacities are known
+        if not args.no_graph:
+            rp.plain_sync = False
+            side = torch.cuda.Stream()
+            side.wait_stream(stream)
+            with torch.cuda.stream(side):
+                rp.step(atlas, target)
+            stream.wait_stream(side)
+            torch.cuda.synchronize()
+            pg = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(pg):
+                rp.step(atlas, target)
+            pg.replay()
+            torch.cuda.synchronize()
+            e0.record()
+            for _ in range(args.plain_steps):
+                pg.replay()
+            e1.record()
+            torch.cuda.synchronize()
+            assert not rp.overflowed(), "plain capacities overflowed under graph replay"
+            ms_plain_graph = e0.elapsed_time(e1) / args.plain_steps
+            del pg
+        rp.close()
 
     # --- roofline for the stage with the largest time share
     sort_passes = rb.sets[0].info.sort_passes
@@ -283,11 +285,12 @@ def main():
                    "resolution": f"{sc.cams[0].width}x{sc.cams[0].height}", "sh_degree": sc.sh_degree,
                    "tiling": "x".join(str(t) for t in tiling), "graph": not args.no_graph},
         "gaussians_per_s": round(N * V / ms * 1e3, 1),
-        "plain": {"ms_per_step": round(ms_plain, 3), "mpixels_per_s": round(P / ms_plain / 1e3, 2),
-                  "gaussians_per_s": round(N * V / ms_plain * 1e3, 1), "image_bitwise_equal": same_img,
-                  "graph_ms_per_step": None if ms_plain_graph is None else round(ms_plain_graph, 3)},
+        "plain": None if ms_plain is None else {
+            "ms_per_step": round(ms_plain, 3), "mpixels_per_s": round(P / ms_plain / 1e3, 2),
+            "gaussians_per_s": round(N * V / ms_plain * 1e3, 1), "image_bitwise_equal": same_img,
+            "graph_ms_per_step": None if ms_plain_graph is None else round(ms_plain_graph, 3)},
         "step_ms_spread": dist,
-        "speedup_vs_plain": round(ms_plain / ms, 3),
+        "speedup_vs_plain": None if ms_plain is None else round(ms_plain / ms, 3),
         "wall_s_timed": round(wall, 4),
         "work": {"instances": n_inst, "pairs_evaluated": n_eval, "pairs_composited": n_comp, "pixels": P,
                  "loss": loss},
@@ -302,7 +305,7 @@ def main():
     }
     rb.close()
     if args.also_configs:
-        del rp, rb
+        rp = rb = None
         torch.cuda.empty_cache()
         out["other_configs"] = [other_config(int(c), tiling, max(2, args.steps // 4), 2)
                                 for c in args.also_configs.split(",") if c.strip()]
@@ -626,12 +629,12 @@ def stage_times(r, atlas, target, reps=5):
     calls = {
         "fetch": lambda: r.fetch(atlas),
         "project": lambda: abi.pg_project(s.handle, r.params, s.splats, s.bins, s.tiles, r.visible, stream),
-        "bin_sort": lambda: abi.pg_bin_sort(s.handle, s.bins, s.tiles, s.cap, s.keys, s.values, s.ranges, s.inst_first,
+        "bin_sort": lambda: abi.pg_bin_sort(s.handle, s.bins, s.tiles, s.cap, s.keys, s.values, s.ranges, s.order, s.inst_first,
                                             s.n_inst, s.overflow, s.inst_grad, s.ws, s.ws_bytes, stream),
-        "render_fwd": lambda: abi.pg_render_fwd(s.handle, s.splats, s.values, s.ranges, r.bg, r.image, r.final_T,
+        "render_fwd": lambda: abi.pg_render_fwd(s.handle, s.splats, s.values, s.ranges, s.order, r.bg, r.image, r.final_T,
                                                 r.n_contrib, s.tile_entries, s.entries, None, stream),
         "loss_l1": lambda: r.loss_l1(target),
-        "render_bwd": lambda: abi.pg_render_bwd(s.handle, s.splats, s.tiles, s.values, s.ranges, s.inst_first,
+        "render_bwd": lambda: abi.pg_render_bwd(s.handle, s.splats, s.tiles, s.values, s.ranges, s.order, s.inst_first,
                                                 s.n_inst, s.cap, s.tile_entries, s.entries, r.n_contrib, r.bg,
                                                 r.final_T, r.dL_dimage, s.inst_grad, stream),
         "project_bwd": lambda: abi.pg_project_bwd(s.handle, r.params, s.bins, s.inst_first, s.n_inst,

@@ -269,6 +269,11 @@ pg_status pg_flow_mask(const pg_views* views, const float* params, const uint8_t
  *                  sorted instance (ascending)
  *   values         device int32 [inst_capacity] out: gv of each sorted instance
  *   tile_ranges    device int32 [n_tiles][2] out: [start, end) per tile
+ *   tile_order     device int32 [n_tiles] out, or NULL: a dispatch order for
+ *                  the compositing calls, every tile once, longest lists
+ *                  first (64 classes of list length, four per octave; the
+ *                  order inside a class is not deterministic).  It only
+ *                  schedules work: results do not depend on it
  *   inst_first     device int32 [n_gv] out: the number of instances of all
  *                  records before gv in (view, id) order.  The adjoint keeps
  *                  one gradient slot per instance, record by record in that
@@ -280,14 +285,19 @@ pg_status pg_flow_mask(const pg_views* views, const float* params, const uint8_t
  *   ws             device workspace of pg_sort_workspace_size bytes */
 pg_status pg_bin_sort(const pg_views* views, const pg_bin* bins, const pg_tile_set* tiles, int64_t inst_capacity,
                       uint32_t* keys,
-                      int32_t* values, int32_t* tile_ranges, int32_t* inst_first, int64_t* n_inst_dev,
-                      int32_t* overflow_dev, float* inst_grad, void* ws, size_t ws_bytes, void* stream);
+                      int32_t* values, int32_t* tile_ranges, int32_t* tile_order, int32_t* inst_first,
+                      int64_t* n_inst_dev, int32_t* overflow_dev, float* inst_grad, void* ws, size_t ws_bytes,
+                      void* stream);
 
 /* a4 -- Front-to-back compositing (supplementary viewer section:
  * C = sum_i T_i alpha_i c_i, T_i = prod_{j<i} (1 - alpha_j); footprint
  * d^2 <= 9 of Sec. 4.2).  Per pixel: skip q > 9; alpha = min(0.99, o e^{-q/2});
  * skip alpha < 1/255; stop before T (1 - alpha) < 1e-4.  Writes C + T bg.
  * Also records, for the adjoint, which pixels composited which Gaussian.
+ *   tile_ranges  from pg_bin_sort
+ *   tile_order   device int32 [n_tiles] from pg_bin_sort, or NULL: the order
+ *                in which tiles are dispatched (NULL: neighbouring tiles
+ *                together); a tile index outside [0, n_tiles) is skipped
  *   bg           host float[3]
  *   image        device float [3 n_pixels] out (per view planar [3][H][W])
  *   final_T      device float [n_pixels] out
@@ -303,7 +313,8 @@ pg_status pg_bin_sort(const pg_views* views, const pg_bin* bins, const pg_tile_s
  *                position fits.
  *   counters     device uint64 [2] or NULL: += {pairs evaluated, pairs composited} */
 pg_status pg_render_fwd(const pg_views* views, const pg_splat* splats, const int32_t* values,
-                        const int32_t* tile_ranges, const float* bg, float* image, float* final_T,
+                        const int32_t* tile_ranges, const int32_t* tile_order, const float* bg, float* image,
+                        float* final_T,
                         int32_t* n_contrib, int32_t* tile_entries, uint32_t* entries, uint64_t* counters,
                         void* stream);
 
@@ -317,6 +328,7 @@ pg_status pg_render_fwd(const pg_views* views, const pg_splat* splats, const int
  * and dL/d(r, g, b).  The mean and conic gradients are linear in the first
  * five; pg_project_bwd forms them per record.  Slots of instances that composited nothing are not written:
  * they keep the zero pg_bin_sort gave them.
+ *   tile_ranges, tile_order   as for pg_render_fwd
  *   tiles, inst_first, n_inst_dev   from pg_project / pg_bin_sort; after an
  *                overflowed sort (n_inst > inst_capacity) no slot is written
  *   tile_entries, entries, n_contrib, final_T   from pg_render_fwd
@@ -325,8 +337,8 @@ pg_status pg_render_fwd(const pg_views* views, const pg_splat* splats, const int
  *   inst_grad    device float [inst_capacity][9] in/out (zeroed by pg_bin_sort), slot inst_first[gv] + k
  *                for the k-th kept tile (row-major) of record gv's rectangle */
 pg_status pg_render_bwd(const pg_views* views, const pg_splat* splats, const pg_tile_set* tiles,
-                        const int32_t* values, const int32_t* tile_ranges, const int32_t* inst_first,
-                        const int64_t* n_inst_dev,
+                        const int32_t* values, const int32_t* tile_ranges, const int32_t* tile_order,
+                        const int32_t* inst_first, const int64_t* n_inst_dev,
                         int64_t inst_capacity, const int32_t* tile_entries, const uint32_t* entries,
                         const int32_t* n_contrib, const float* bg, const float* final_T, const float* dL_dimage,
                         float* inst_grad, void* stream);

@@ -64,9 +64,9 @@ SIGNATURES = {
     "pg_atlas_fake_quant": (_i32, [_p, _p, _i64, _i32, _i32, _p, _p, _p, _p, _p]),
     "pg_project": (_i32, [_p, _p, _p, _p, _p, _p, _p]),
     "pg_flow_mask": (_i32, [_p, _p, _p, _p, _p, _p, _i32, _i32, _p, _p, _p]),
-    "pg_bin_sort": (_i32, [_p, _p, _p, _i64, _p, _p, _p, _p, _p, _p, _p, _p, _sz, _p]),
-    "pg_render_fwd": (_i32, [_p, _p, _p, _p, _p, _p, _p, _p, _p, _p, _p, _p]),
-    "pg_render_bwd": (_i32, [_p, _p, _p, _p, _p, _p, _p, _i64, _p, _p, _p, _p, _p, _p, _p, _p]),
+    "pg_bin_sort": (_i32, [_p, _p, _p, _i64, _p, _p, _p, _p, _p, _p, _p, _p, _p, _sz, _p]),
+    "pg_render_fwd": (_i32, [_p, _p, _p, _p, _p, _p, _p, _p, _p, _p, _p, _p, _p]),
+    "pg_render_bwd": (_i32, [_p, _p, _p, _p, _p, _p, _p, _p, _i64, _p, _p, _p, _p, _p, _p, _p, _p]),
     "pg_project_bwd": (_i32, [_p, _p, _p, _p, _p, _i64, _p, _p, _p, _i32, _i32, _p, _p, _i32, _p]),
     "pg_loss_l1": (_i32, [_p, _p, _i64, _p, _p, _p, _p]),
     "pg_photo_workspace_size": (_i32, [_p, C.POINTER(_sz)]),
@@ -221,26 +221,28 @@ def pg_project(views, params, splats, bins, tiles, visible, stream=None):
                             _stream(stream)), "pg_project")
 
 
-def pg_bin_sort(views, bins, tiles, inst_capacity, keys, values, tile_ranges, inst_first, n_inst_dev,
+def pg_bin_sort(views, bins, tiles, inst_capacity, keys, values, tile_ranges, tile_order, inst_first, n_inst_dev,
                 overflow_dev, inst_grad, ws, ws_bytes, stream=None):
     _check(lib().pg_bin_sort(views, _ptr(bins), _ptr(tiles), int(inst_capacity), _ptr(keys), _ptr(values), _ptr(tile_ranges),
-                             _ptr(inst_first), _ptr(n_inst_dev), _ptr(overflow_dev), _ptr(inst_grad), _ptr(ws),
+                             _ptr(tile_order), _ptr(inst_first), _ptr(n_inst_dev), _ptr(overflow_dev), _ptr(inst_grad), _ptr(ws),
                              int(ws_bytes),
                              _stream(stream)), "pg_bin_sort")
 
 
-def pg_render_fwd(views, splats, values, tile_ranges, bg, image, final_T, n_contrib, tile_entries, entries,
+def pg_render_fwd(views, splats, values, tile_ranges, tile_order, bg, image, final_T, n_contrib, tile_entries, entries,
                   counters=None, stream=None):
     bgv = (C.c_float * 3)(*[float(b) for b in bg])
-    _check(lib().pg_render_fwd(views, _ptr(splats), _ptr(values), _ptr(tile_ranges), C.addressof(bgv), _ptr(image),
+    _check(lib().pg_render_fwd(views, _ptr(splats), _ptr(values), _ptr(tile_ranges), _ptr(tile_order),
+                               C.addressof(bgv), _ptr(image),
                                _ptr(final_T), _ptr(n_contrib), _ptr(tile_entries), _ptr(entries), _ptr(counters),
                                _stream(stream)), "pg_render_fwd")
 
 
-def pg_render_bwd(views, splats, tiles, values, tile_ranges, inst_first, n_inst_dev, inst_capacity,
+def pg_render_bwd(views, splats, tiles, values, tile_ranges, tile_order, inst_first, n_inst_dev, inst_capacity,
                   tile_entries, entries, n_contrib, bg, final_T, dL_dimage, inst_grad, stream=None):
     bgv = (C.c_float * 3)(*[float(b) for b in bg])
-    _check(lib().pg_render_bwd(views, _ptr(splats), _ptr(tiles), _ptr(values), _ptr(tile_ranges), _ptr(inst_first),
+    _check(lib().pg_render_bwd(views, _ptr(splats), _ptr(tiles), _ptr(values), _ptr(tile_ranges), _ptr(tile_order),
+                               _ptr(inst_first),
                                _ptr(n_inst_dev), int(inst_capacity), _ptr(tile_entries), _ptr(entries),
                                _ptr(n_contrib), C.addressof(bgv), _ptr(final_T), _ptr(dL_dimage), _ptr(inst_grad),
                                _stream(stream)), "pg_render_bwd")

@@ -257,7 +257,7 @@ pg_status pg_project(const pg_views* v, const float* params, pg_splat* splats, p
 
 pg_status pg_bin_sort(const pg_views* v, const pg_bin* bins, const pg_tile_set* tiles, int64_t cap, uint32_t* keys,
                       int32_t* values,
-                      int32_t* tile_ranges, int32_t* inst_first, int64_t* n_inst_dev, int32_t* overflow_dev,
+                      int32_t* tile_ranges, int32_t* tile_order, int32_t* inst_first, int64_t* n_inst_dev, int32_t* overflow_dev,
                       float* inst_grad, void* ws, size_t ws_bytes, void* stream) {
     g_error.clear();
     if (!v) return invalid("views is null");
@@ -269,27 +269,28 @@ pg_status pg_bin_sort(const pg_views* v, const pg_bin* bins, const pg_tile_set* 
         set_error("sort workspace too small");
         return PG_ERR_WORKSPACE;
     }
-    PG_CHECK_HIP(launch_bin_sort(v, bins, tiles, cap, keys, values, tile_ranges, inst_first, n_inst_dev, overflow_dev,
+    PG_CHECK_HIP(launch_bin_sort(v, bins, tiles, cap, keys, values, tile_ranges, tile_order, inst_first, n_inst_dev, overflow_dev,
                                  inst_grad, ws, (hipStream_t)stream),
                  "pg_bin_sort");
     return PG_OK;
 }
 
 pg_status pg_render_fwd(const pg_views* v, const pg_splat* splats, const int32_t* values, const int32_t* tile_ranges,
-                        const float* bg, float* image, float* final_T, int32_t* n_contrib, int32_t* tile_entries,
+                        const int32_t* tile_order, const float* bg, float* image, float* final_T, int32_t* n_contrib, int32_t* tile_entries,
                         uint32_t* entries, uint64_t* counters, void* stream) {
     g_error.clear();
     if (!v || !bg) return invalid("null argument");
     if (!image || !final_T || !n_contrib || !tile_ranges || !tile_entries) return invalid("null pointer argument");
     if (v->n_gv > 0 && (!splats || !values || !entries)) return invalid("null pointer argument");
-    PG_CHECK_HIP(launch_render_fwd(v, splats, values, tile_ranges, bg, image, final_T, n_contrib, tile_entries,
+    PG_CHECK_HIP(launch_render_fwd(v, splats, values, tile_ranges, tile_order, bg, image, final_T, n_contrib, tile_entries,
                                    entries, counters, (hipStream_t)stream),
                  "pg_render_fwd");
     return PG_OK;
 }
 
 pg_status pg_render_bwd(const pg_views* v, const pg_splat* splats, const pg_tile_set* tiles,
-                        const int32_t* values, const int32_t* tile_ranges, const int32_t* inst_first, const int64_t* n_inst_dev,
+                        const int32_t* values, const int32_t* tile_ranges, const int32_t* tile_order,
+                        const int32_t* inst_first, const int64_t* n_inst_dev,
                         int64_t inst_capacity, const int32_t* tile_entries, const uint32_t* entries,
                         const int32_t* n_contrib, const float* bg, const float* final_T, const float* dL_dimage,
                         float* inst_grad, void* stream) {
@@ -300,7 +301,7 @@ pg_status pg_render_bwd(const pg_views* v, const pg_splat* splats, const pg_tile
     if (v->n_gv > 0 && (!splats || !tiles || !values || !inst_first || !entries || !inst_grad))
         return invalid("null pointer argument");
     if (inst_capacity < 0 || inst_capacity > INT32_MAX) return invalid("inst_capacity must be in [0, 2^31 - 1]");
-    PG_CHECK_HIP(launch_render_bwd(v, splats, tiles, values, tile_ranges, inst_first, tile_entries, entries,
+    PG_CHECK_HIP(launch_render_bwd(v, splats, tiles, values, tile_ranges, tile_order, inst_first, tile_entries, entries,
                                    n_contrib, bg, final_T, dL_dimage, n_inst_dev, inst_capacity, inst_grad,
                                    (hipStream_t)stream),
                  "pg_render_bwd");

@@ -80,11 +80,14 @@ struct SortWs {
     int32_t* count_offs;     // per radix tile, the output offset of each digit (same layout)
     int32_t* chunk_dm;       // digit-major [digit][chunk] sums of kChunkTiles tiles, and their exclusive scan
     int32_t* chunk_off;
+    int32_t* order_cnt;      // tile dispatch order: per length class, tile count [kOrderClasses] and next free slot
 };
 
 int64_t n_blocks(const pg_views* v) { return imax(ceil_div(v->n_gv, kBlk), 1); }
 
 constexpr int kChunkTiles = 64;   // radix tiles per chunk of the two-level offset scan
+constexpr int kOrderClasses = 64; // length classes of the tile dispatch order (four per octave)
+constexpr int kOrderBlk = 256;
 
 // Radix tiles (and chunks of them) either sort can have at most.
 int64_t tiles_max(const pg_views* v, int64_t cap) {
@@ -126,6 +129,7 @@ SortWs carve(const pg_views* v, int64_t cap, void* ws, size_t* total) {
     w.count_offs = (int32_t*)take(cnt * 4);
     w.chunk_dm = (int32_t*)take(ch * 4);
     w.chunk_off = (int32_t*)take(ch * 4);
+    w.order_cnt = (int32_t*)take(2 * kOrderClasses * 4);
     if (total) *total = off;
     return w;
 }
@@ -528,6 +532,79 @@ __global__ __launch_bounds__(256) void k_ranges(const uint32_t* __restrict__ key
     }
 }
 
+// ---------------------------------------------------------------- tile dispatch order
+// The compositing kernels run one work-group per tile, and tiles differ in
+// cost by their list lengths.  Dispatching the longest lists first (a
+// longest-processing-time-first schedule) shortens the tail of those
+// launches, where a few long tiles would otherwise run on an emptying chip.
+// The order is coarse: 64 classes of list length, four per octave, longest
+// class first; inside a class the order is whatever the atomics give.  Each
+// tile is processed independently, so results do not depend on it.
+__device__ __forceinline__ int order_class(int32_t len) {
+    const uint32_t b = __float_as_uint((float)(len > 0 ? len : 0) + 1.0f);
+    const int c = 4 * ((int)((b >> 23) & 0xffu) - 127) + (int)((b >> 21) & 3u);   // 4 log2(len + 1), floored
+    return kOrderClasses - 1 - (c < 0 ? 0 : (c < kOrderClasses - 1 ? c : kOrderClasses - 1));
+}
+
+__global__ __launch_bounds__(kOrderBlk) void k_order_count(const int2* __restrict__ ranges, int64_t n_tiles,
+                                                           int32_t* __restrict__ cnt) {
+    __shared__ int32_t s_cnt[kOrderClasses];
+    if (threadIdx.x < kOrderClasses) s_cnt[threadIdx.x] = 0;
+    __syncthreads();
+    const int64_t t = (int64_t)blockIdx.x * kOrderBlk + threadIdx.x;
+    if (t < n_tiles) {
+        const int2 r = ranges[t];
+        atomicAdd(&s_cnt[order_class(r.y - r.x)], 1);
+    }
+    __syncthreads();
+    if (threadIdx.x < kOrderClasses && s_cnt[threadIdx.x] > 0) atomicAdd(&cnt[threadIdx.x], s_cnt[threadIdx.x]);
+}
+
+// Exclusive scan of the class counts into each class's first slot (one wave).
+__global__ __launch_bounds__(64) void k_order_scan(int32_t* __restrict__ cnt) {
+    const int c = threadIdx.x;
+    const int32_t n = c < kOrderClasses ? cnt[c] : 0;
+    int32_t incl = n;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int32_t u = __shfl_up(incl, o, 64);
+        if (c >= o) incl += u;
+    }
+    if (c < kOrderClasses) cnt[kOrderClasses + c] = incl - n;
+}
+
+__global__ __launch_bounds__(kOrderBlk) void k_order_place(const int2* __restrict__ ranges, int64_t n_tiles,
+                                                           int32_t* __restrict__ next, int32_t* __restrict__ order) {
+    __shared__ int32_t s_cnt[kOrderClasses];
+    __shared__ int32_t s_base[kOrderClasses];
+    if (threadIdx.x < kOrderClasses) s_cnt[threadIdx.x] = 0;
+    __syncthreads();
+    const int64_t t = (int64_t)blockIdx.x * kOrderBlk + threadIdx.x;
+    int cls = 0, rank = 0;
+    if (t < n_tiles) {
+        const int2 r = ranges[t];
+        cls = order_class(r.y - r.x);
+        rank = atomicAdd(&s_cnt[cls], 1);
+    }
+    __syncthreads();
+    if (threadIdx.x < kOrderClasses && s_cnt[threadIdx.x] > 0)
+        s_base[threadIdx.x] = atomicAdd(&next[threadIdx.x], s_cnt[threadIdx.x]);
+    __syncthreads();
+    if (t < n_tiles) order[s_base[cls] + rank] = (int32_t)t;
+}
+
+hipError_t launch_tile_order(const int32_t* ranges, int64_t n_tiles, int32_t* cnt, int32_t* order, hipStream_t s) {
+    if (!order || n_tiles == 0) return hipSuccess;
+    hipError_t e = fill_u32(cnt, 0u, kOrderClasses, s);
+    if (e != hipSuccess) return e;
+    const unsigned grid = (unsigned)ceil_div(n_tiles, kOrderBlk);
+    k_order_count<<<grid, kOrderBlk, 0, s>>>(reinterpret_cast<const int2*>(ranges), n_tiles, cnt);
+    k_order_scan<<<1, 64, 0, s>>>(cnt);
+    k_order_place<<<grid, kOrderBlk, 0, s>>>(reinterpret_cast<const int2*>(ranges), n_tiles, cnt + kOrderClasses,
+                                             order);
+    return hipGetLastError();
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------- generic stable pair sort
@@ -597,8 +674,8 @@ size_t sort_ws_bytes(const pg_views* v, int64_t cap) {
 
 hipError_t launch_bin_sort(const pg_views* v, const pg_bin* bins, const pg_tile_set* tiles, int64_t cap,
                            uint32_t* keys, int32_t* values,
-                           int32_t* ranges, int32_t* inst_first, int64_t* n_inst_dev, int32_t* overflow_dev,
-                           float* inst_grad, void* ws, hipStream_t s) {
+                           int32_t* ranges, int32_t* tile_order, int32_t* inst_first, int64_t* n_inst_dev,
+                           int32_t* overflow_dev, float* inst_grad, void* ws, hipStream_t s) {
     const SortPlan pl = plan_for(v);
     SortWs w = carve(v, cap, ws, nullptr);
     const int64_t nb = n_blocks(v);
@@ -610,7 +687,9 @@ hipError_t launch_bin_sort(const pg_views* v, const pg_bin* bins, const pg_tile_
         e = fill_u32(n_inst_dev, 0u, 2, s);
         if (e != hipSuccess) return e;
         k_post_count<<<1, 1, 0, s>>>(n_inst_dev, cap, overflow_dev, w.misc);
-        return hipGetLastError();
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        return launch_tile_order(ranges, v->n_tiles, w.order_cnt, tile_order, s);
     }
     // 1. compact surviving records in (view, id) order, keyed by depth; slot offsets in the same order
     int32_t *rva = w.rv0, *rvb = w.rv1;
@@ -651,6 +730,8 @@ hipError_t launch_bin_sort(const pg_views* v, const pg_bin* bins, const pg_tile_
         int32_t* tv = tva; tva = tvb; tvb = tv;
     }
     k_ranges<<<(unsigned)imax(1, imin(kRangeGrid, ceil_div(cap, 256))), 256, 0, s>>>(keys, w.misc, ranges);
+    e = launch_tile_order(ranges, v->n_tiles, w.order_cnt, tile_order, s);
+    if (e != hipSuccess) return e;
     // 6. zero the adjoint's per-instance gradient slots (instances nobody composites keep 0)
     if (inst_grad) return fill_u32_dev(inst_grad, 0u, n_inst_dev, cap, 9, s);
     return hipGetLastError();

@@ -115,8 +115,8 @@ hipError_t launch_project_bwd(const pg_views* v, const float* params, float* gra
 size_t sort_ws_bytes(const pg_views* v, int64_t cap);
 hipError_t launch_bin_sort(const pg_views* v, const pg_bin* bins, const pg_tile_set* tiles, int64_t cap,
                            uint32_t* keys, int32_t* values,
-                           int32_t* ranges, int32_t* inst_first, int64_t* n_inst_dev, int32_t* overflow_dev,
-                           float* inst_grad, void* ws, hipStream_t s);
+                           int32_t* ranges, int32_t* tile_order, int32_t* inst_first, int64_t* n_inst_dev,
+                           int32_t* overflow_dev, float* inst_grad, void* ws, hipStream_t s);
 
 // stable sort of (uint32 key, int32 value) pairs (binsort.hip)
 size_t sort_pairs_ws_bytes(int64_t cap, int bits);
@@ -125,14 +125,14 @@ hipError_t sort_pairs(uint32_t* keys, int32_t* vals, uint32_t* keys_alt, int32_t
 
 // render.hip
 hipError_t launch_render_fwd(const pg_views* v, const pg_splat* splats, const int32_t* values,
-                             const int32_t* ranges, const float bg[3], float* image, float* final_T,
-                             int32_t* n_contrib, int32_t* tile_entries, uint32_t* entries, uint64_t* counters,
-                             hipStream_t s);
-hipError_t launch_render_bwd(const pg_views* v, const pg_splat* splats, const pg_tile_set* tiles, const int32_t* values, const int32_t* ranges,
-                             const int32_t* inst_first, const int32_t* tile_entries,
-                             const uint32_t* entries, const int32_t* n_contrib, const float bg[3],
-                             const float* final_T, const float* dL_dimage, const int64_t* n_inst_dev, int64_t cap,
-                             float* inst_grad, hipStream_t s);
+                             const int32_t* ranges, const int32_t* order, const float bg[3], float* image,
+                             float* final_T, int32_t* n_contrib, int32_t* tile_entries, uint32_t* entries,
+                             uint64_t* counters, hipStream_t s);
+hipError_t launch_render_bwd(const pg_views* v, const pg_splat* splats, const pg_tile_set* tiles, const int32_t* values,
+                             const int32_t* ranges, const int32_t* order, const int32_t* inst_first,
+                             const int32_t* tile_entries, const uint32_t* entries, const int32_t* n_contrib,
+                             const float bg[3], const float* final_T, const float* dL_dimage,
+                             const int64_t* n_inst_dev, int64_t cap, float* inst_grad, hipStream_t s);
 hipError_t fill_u32_dev(void* p, uint32_t value, const int64_t* n_dev, int64_t n_max, int64_t mul, hipStream_t s);
 
 // optim.hip

@@ -48,6 +48,7 @@ class _ViewSet:
         self.grad2d = torch.empty(max(9 * n_gv, 1), dtype=torch.float32, device=device)
         self.ranges = torch.empty(2 * max(self.info.n_tiles, 1), dtype=torch.int32, device=device)
         self.tile_entries = torch.empty(max(self.info.n_tiles, 1), dtype=torch.int32, device=device)
+        self.order = torch.empty(max(self.info.n_tiles, 1), dtype=torch.int32, device=device)   # dispatch order
         self.inst_first = torch.empty(max(n_gv, 1), dtype=torch.int32, device=device)
         self.n_inst = torch.zeros(1, dtype=torch.int64, device=device)
         self.overflow = torch.zeros(1, dtype=torch.int32, device=device)
@@ -192,15 +193,15 @@ class Renderer:
 
     def _project_sort_render(self, s: _ViewSet, pix_off: int, counters):
         abi.pg_project(s.handle, self.params, s.splats, s.bins, s.tiles, self.visible)
-        abi.pg_bin_sort(s.handle, s.bins, s.tiles, s.cap, s.keys, s.values, s.ranges, s.inst_first, s.n_inst, s.overflow,
+        abi.pg_bin_sort(s.handle, s.bins, s.tiles, s.cap, s.keys, s.values, s.ranges, s.order, s.inst_first, s.n_inst, s.overflow,
                         s.inst_grad, s.ws, s.ws_bytes)
         if not self.batched and self.plain_sync:
             # plain path: one instance-count synchronisation per view
             if int(s.overflow.item()):
                 s.set_capacity(int(math.ceil(int(s.n_inst.item()) * 1.25)))
-                abi.pg_bin_sort(s.handle, s.bins, s.tiles, s.cap, s.keys, s.values, s.ranges, s.inst_first, s.n_inst,
+                abi.pg_bin_sort(s.handle, s.bins, s.tiles, s.cap, s.keys, s.values, s.ranges, s.order, s.inst_first, s.n_inst,
                                 s.overflow, s.inst_grad, s.ws, s.ws_bytes)
-        abi.pg_render_fwd(s.handle, s.splats, s.values, s.ranges, self.bg, self._off(self.image, 3 * pix_off),
+        abi.pg_render_fwd(s.handle, s.splats, s.values, s.ranges, s.order, self.bg, self._off(self.image, 3 * pix_off),
                           self._off(self.final_T, pix_off), self._off(self.n_contrib, pix_off), s.tile_entries,
                           s.entries, counters)
 
@@ -277,7 +278,7 @@ class Renderer:
         assert g.is_contiguous() and g.numel() == 3 * self.n_pixels
         if self.batched:
             s = self.sets[0]
-            abi.pg_render_bwd(s.handle, s.splats, s.tiles, s.values, s.ranges, s.inst_first, s.n_inst, s.cap,
+            abi.pg_render_bwd(s.handle, s.splats, s.tiles, s.values, s.ranges, s.order, s.inst_first, s.n_inst, s.cap,
                               s.tile_entries, s.entries, self.n_contrib, self.bg, self.final_T, g, s.inst_grad)
             abi.pg_project_bwd(s.handle, self.params, s.bins, s.inst_first, s.n_inst, s.cap,
                                s.inst_grad, self.gauss_texel, self.dynamic, self.H, self.W, s.grad2d, self.dL_datlas, 0)
@@ -285,7 +286,7 @@ class Renderer:
             self.dL_datlas.zero_()
             for k, s in enumerate(self.sets):
                 po = self.pix_base[k]
-                abi.pg_render_bwd(s.handle, s.splats, s.tiles, s.values, s.ranges, s.inst_first, s.n_inst, s.cap,
+                abi.pg_render_bwd(s.handle, s.splats, s.tiles, s.values, s.ranges, s.order, s.inst_first, s.n_inst, s.cap,
                                   s.tile_entries, s.entries, self._off(self.n_contrib, po), self.bg,
                                   self._off(self.final_T, po), self._off(g, 3 * po), s.inst_grad)
                 abi.pg_project_bwd(s.handle, self.params, s.bins, s.inst_first, s.n_inst, s.cap,
