@@ -80,7 +80,9 @@ struct SortWs {
     int32_t* count_offs;     // per radix tile, the output offset of each digit (same layout)
     int32_t* chunk_dm;       // digit-major [digit][chunk] sums of kChunkTiles tiles, and their exclusive scan
     int32_t* chunk_off;
-    int32_t* order_cnt;      // tile dispatch order: per length class, tile count [kOrderClasses] and next free slot
+    int32_t* order_cnt;      // tile dispatch order: per (tile group, length class) counts
+    int32_t* order_base;     // ... and their class-major exclusive scan
+    int32_t* order_cls;      // ... first slot and size of each class
 };
 
 int64_t n_blocks(const pg_views* v) { return imax(ceil_div(v->n_gv, kBlk), 1); }
@@ -129,7 +131,10 @@ SortWs carve(const pg_views* v, int64_t cap, void* ws, size_t* total) {
     w.count_offs = (int32_t*)take(cnt * 4);
     w.chunk_dm = (int32_t*)take(ch * 4);
     w.chunk_off = (int32_t*)take(ch * 4);
-    w.order_cnt = (int32_t*)take(2 * kOrderClasses * 4);
+    const int64_t order_words = ceil_div(imax(v->n_tiles, 1), kOrderBlk) * kOrderClasses;
+    w.order_cnt = (int32_t*)take(order_words * 4);
+    w.order_base = (int32_t*)take(order_words * 4);
+    w.order_cls = (int32_t*)take(2 * kOrderClasses * 4);
     if (total) *total = off;
     return w;
 }
@@ -538,14 +543,18 @@ __global__ __launch_bounds__(256) void k_ranges(const uint32_t* __restrict__ key
 // longest-processing-time-first schedule) shortens the tail of those
 // launches, where a few long tiles would otherwise run on an emptying chip.
 // The order is coarse: 64 classes of list length, four per octave, longest
-// class first; inside a class the order is whatever the atomics give.  Each
-// tile is processed independently, so results do not depend on it.
+// class first.  Inside a class, tiles keep their index order and are dealt to
+// the XCDs in contiguous runs: the dispatcher hands work-group b to XCD b mod
+// 8, so the slots of a class that land on XCD x receive one run of
+// neighbouring tiles, which share Gaussians and so their records in that
+// XCD's L2.  The order is deterministic and results do not depend on it.
 __device__ __forceinline__ int order_class(int32_t len) {
     const uint32_t b = __float_as_uint((float)(len > 0 ? len : 0) + 1.0f);
     const int c = 4 * ((int)((b >> 23) & 0xffu) - 127) + (int)((b >> 21) & 3u);   // 4 log2(len + 1), floored
     return kOrderClasses - 1 - (c < 0 ? 0 : (c < kOrderClasses - 1 ? c : kOrderClasses - 1));
 }
 
+// Per work-group of kOrderBlk consecutive tiles: the tile count of each class.
 __global__ __launch_bounds__(kOrderBlk) void k_order_count(const int2* __restrict__ ranges, int64_t n_tiles,
                                                            int32_t* __restrict__ cnt) {
     __shared__ int32_t s_cnt[kOrderClasses];
@@ -554,54 +563,100 @@ __global__ __launch_bounds__(kOrderBlk) void k_order_count(const int2* __restric
     const int64_t t = (int64_t)blockIdx.x * kOrderBlk + threadIdx.x;
     if (t < n_tiles) {
         const int2 r = ranges[t];
-        atomicAdd(&s_cnt[order_class(r.y - r.x)], 1);
+        atomicAdd(&s_cnt[order_class(r.y - r.x)], 1);     // counts only: order-free
     }
     __syncthreads();
-    if (threadIdx.x < kOrderClasses && s_cnt[threadIdx.x] > 0) atomicAdd(&cnt[threadIdx.x], s_cnt[threadIdx.x]);
+    if (threadIdx.x < kOrderClasses) cnt[(int64_t)blockIdx.x * kOrderClasses + threadIdx.x] = s_cnt[threadIdx.x];
 }
 
-// Exclusive scan of the class counts into each class's first slot (one wave).
-__global__ __launch_bounds__(64) void k_order_scan(int32_t* __restrict__ cnt) {
-    const int c = threadIdx.x;
-    const int32_t n = c < kOrderClasses ? cnt[c] : 0;
-    int32_t incl = n;
+// Class-major exclusive scan of the counts (one work-group of 1024 threads):
+// base[w][c] = tiles of the classes before c + tiles of class c in groups
+// before w; cls[c] = first slot of class c, cls[kOrderClasses + c] = its size.
+constexpr int kOrderSeg = 1024 / kOrderClasses;     // threads per class in the scan
+__global__ __launch_bounds__(1024) void k_order_scan(const int32_t* __restrict__ cnt, int64_t n_groups,
+                                                     int32_t* __restrict__ base, int32_t* __restrict__ cls) {
+    __shared__ int32_t s_part[kOrderClasses][kOrderSeg];
+    __shared__ int32_t s_first[kOrderClasses];
+    const int c = threadIdx.x / kOrderSeg, k = threadIdx.x % kOrderSeg;
+    const int64_t per = ceil_div(n_groups, kOrderSeg);
+    const int64_t w0 = imin(n_groups, k * per), w1 = imin(n_groups, w0 + per);
+    int32_t sum = 0;
+    for (int64_t w = w0; w < w1; w++) sum += cnt[w * kOrderClasses + c];
+    s_part[c][k] = sum;
+    __syncthreads();
+    if (threadIdx.x < 64) {     // one wave: class totals and their exclusive scan
+        int32_t tot = 0;
+        for (int j = 0; j < kOrderSeg; j++) tot += s_part[threadIdx.x][j];
+        int32_t incl = tot;
 #pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        const int32_t u = __shfl_up(incl, o, 64);
-        if (c >= o) incl += u;
+        for (int o = 1; o < 64; o <<= 1) {
+            const int32_t u = __shfl_up(incl, o, 64);
+            if ((int)threadIdx.x >= o) incl += u;
+        }
+        s_first[threadIdx.x] = incl - tot;
+        cls[threadIdx.x] = incl - tot;
+        cls[kOrderClasses + threadIdx.x] = tot;
     }
-    if (c < kOrderClasses) cnt[kOrderClasses + c] = incl - n;
+    __syncthreads();
+    int32_t run = s_first[c];
+    for (int j = 0; j < k; j++) run += s_part[c][j];
+    for (int64_t w = w0; w < w1; w++) {
+        base[w * kOrderClasses + c] = run;
+        run += cnt[w * kOrderClasses + c];
+    }
+}
+
+// Dispatch slot of the rank-r tile (in index order) of a class holding slots
+// [o, o + n): XCD x receives the ranks [R_x, R_x + m_x), where m_x counts the
+// class's slots s with s mod 8 = x and R_x those of the XCDs before x.
+__device__ __forceinline__ int64_t order_slot(int64_t o, int64_t n, int64_t r) {
+    int64_t R = 0;
+    for (int x = 0; x < 8; x++) {
+        const int64_t f = o + ((x - (o & 7)) & 7);        // first slot of the class on XCD x
+        const int64_t m = f < o + n ? (o + n - f + 7) / 8 : 0;
+        if (r < R + m) return f + 8 * (r - R);
+        R += m;
+    }
+    return -1;     // r >= n: not reached for ranks of the class
 }
 
 __global__ __launch_bounds__(kOrderBlk) void k_order_place(const int2* __restrict__ ranges, int64_t n_tiles,
-                                                           int32_t* __restrict__ next, int32_t* __restrict__ order) {
-    __shared__ int32_t s_cnt[kOrderClasses];
-    __shared__ int32_t s_base[kOrderClasses];
-    if (threadIdx.x < kOrderClasses) s_cnt[threadIdx.x] = 0;
+                                                           const int32_t* __restrict__ base,
+                                                           const int32_t* __restrict__ cls,
+                                                           int32_t* __restrict__ order) {
+    __shared__ uint32_t s_hist[kOrderBlk / 64][kOrderClasses];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    for (int c = lane; c < kOrderClasses; c += 64) s_hist[wid][c] = 0;
     __syncthreads();
     const int64_t t = (int64_t)blockIdx.x * kOrderBlk + threadIdx.x;
-    int cls = 0, rank = 0;
-    if (t < n_tiles) {
+    const bool active = t < n_tiles;
+    int c = 0;
+    if (active) {
         const int2 r = ranges[t];
-        cls = order_class(r.y - r.x);
-        rank = atomicAdd(&s_cnt[cls], 1);
+        c = order_class(r.y - r.x);
     }
+    // rank among the lanes of this wave with the same class, then among earlier waves
+    const uint64_t peers = match_digit<6>((uint32_t)c, active);
+    const uint32_t below = (uint32_t)__popcll(peers & ((1ull << lane) - 1ull));
+    if (active && below == 0) s_hist[wid][c] = (uint32_t)__popcll(peers);
     __syncthreads();
-    if (threadIdx.x < kOrderClasses && s_cnt[threadIdx.x] > 0)
-        s_base[threadIdx.x] = atomicAdd(&next[threadIdx.x], s_cnt[threadIdx.x]);
-    __syncthreads();
-    if (t < n_tiles) order[s_base[cls] + rank] = (int32_t)t;
+    if (!active) return;
+    uint32_t rank = below;
+    for (int w = 0; w < wid; w++) rank += s_hist[w][c];
+    const int64_t o = cls[c], n = cls[kOrderClasses + c];
+    const int64_t r = (int64_t)base[(int64_t)blockIdx.x * kOrderClasses + c] - o + rank;
+    const int64_t slot = order_slot(o, n, r);
+    if (slot >= 0 && slot < n_tiles) order[slot] = (int32_t)t;
 }
 
-hipError_t launch_tile_order(const int32_t* ranges, int64_t n_tiles, int32_t* cnt, int32_t* order, hipStream_t s) {
+hipError_t launch_tile_order(const int32_t* ranges, int64_t n_tiles, int32_t* cnt, int32_t* base, int32_t* cls,
+                             int32_t* order, hipStream_t s) {
     if (!order || n_tiles == 0) return hipSuccess;
-    hipError_t e = fill_u32(cnt, 0u, kOrderClasses, s);
-    if (e != hipSuccess) return e;
-    const unsigned grid = (unsigned)ceil_div(n_tiles, kOrderBlk);
-    k_order_count<<<grid, kOrderBlk, 0, s>>>(reinterpret_cast<const int2*>(ranges), n_tiles, cnt);
-    k_order_scan<<<1, 64, 0, s>>>(cnt);
-    k_order_place<<<grid, kOrderBlk, 0, s>>>(reinterpret_cast<const int2*>(ranges), n_tiles, cnt + kOrderClasses,
-                                             order);
+    const int64_t groups = ceil_div(n_tiles, kOrderBlk);
+    const int2* rg = reinterpret_cast<const int2*>(ranges);
+    k_order_count<<<(unsigned)groups, kOrderBlk, 0, s>>>(rg, n_tiles, cnt);
+    k_order_scan<<<1, 1024, 0, s>>>(cnt, groups, base, cls);
+    k_order_place<<<(unsigned)groups, kOrderBlk, 0, s>>>(rg, n_tiles, base, cls, order);
     return hipGetLastError();
 }
 
@@ -689,7 +744,7 @@ hipError_t launch_bin_sort(const pg_views* v, const pg_bin* bins, const pg_tile_
         k_post_count<<<1, 1, 0, s>>>(n_inst_dev, cap, overflow_dev, w.misc);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
-        return launch_tile_order(ranges, v->n_tiles, w.order_cnt, tile_order, s);
+        return launch_tile_order(ranges, v->n_tiles, w.order_cnt, w.order_base, w.order_cls, tile_order, s);
     }
     // 1. compact surviving records in (view, id) order, keyed by depth; slot offsets in the same order
     int32_t *rva = w.rv0, *rvb = w.rv1;
@@ -730,7 +785,7 @@ hipError_t launch_bin_sort(const pg_views* v, const pg_bin* bins, const pg_tile_
         int32_t* tv = tva; tva = tvb; tvb = tv;
     }
     k_ranges<<<(unsigned)imax(1, imin(kRangeGrid, ceil_div(cap, 256))), 256, 0, s>>>(keys, w.misc, ranges);
-    e = launch_tile_order(ranges, v->n_tiles, w.order_cnt, tile_order, s);
+    e = launch_tile_order(ranges, v->n_tiles, w.order_cnt, w.order_base, w.order_cls, tile_order, s);
     if (e != hipSuccess) return e;
     // 6. zero the adjoint's per-instance gradient slots (instances nobody composites keep 0)
     if (inst_grad) return fill_u32_dev(inst_grad, 0u, n_inst_dev, cap, 9, s);

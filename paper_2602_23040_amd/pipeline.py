@@ -98,6 +98,9 @@ class Renderer:
         # plain path: check each view's instance count on the host (False once
         # the capacities are known, e.g. to capture the per-view chain in a graph)
         self.plain_sync = True
+        # dispatch the compositing kernels' tiles longest-first (pg_bin_sort's
+        # tile order); False keeps the default order (neighbouring tiles together)
+        self.tile_order = True
         self.tiling = abi.make_tiling(*tiling)
         dev = self.device
         self.occ = _u8(occ, dev)
@@ -191,17 +194,20 @@ class Renderer:
             abi.pg_atlas_fake_quant(self.params, self.n_gauss_dev, self.N, self.frames, self.C, self.quant_bits,
                                     self.quant_range, None, self.quant_partial)
 
+    def _order(self, s):
+        return s.order if self.tile_order else None
+
     def _project_sort_render(self, s: _ViewSet, pix_off: int, counters):
         abi.pg_project(s.handle, self.params, s.splats, s.bins, s.tiles, self.visible)
-        abi.pg_bin_sort(s.handle, s.bins, s.tiles, s.cap, s.keys, s.values, s.ranges, s.order, s.inst_first, s.n_inst, s.overflow,
+        abi.pg_bin_sort(s.handle, s.bins, s.tiles, s.cap, s.keys, s.values, s.ranges, self._order(s), s.inst_first, s.n_inst, s.overflow,
                         s.inst_grad, s.ws, s.ws_bytes)
         if not self.batched and self.plain_sync:
             # plain path: one instance-count synchronisation per view
             if int(s.overflow.item()):
                 s.set_capacity(int(math.ceil(int(s.n_inst.item()) * 1.25)))
-                abi.pg_bin_sort(s.handle, s.bins, s.tiles, s.cap, s.keys, s.values, s.ranges, s.order, s.inst_first, s.n_inst,
+                abi.pg_bin_sort(s.handle, s.bins, s.tiles, s.cap, s.keys, s.values, s.ranges, self._order(s), s.inst_first, s.n_inst,
                                 s.overflow, s.inst_grad, s.ws, s.ws_bytes)
-        abi.pg_render_fwd(s.handle, s.splats, s.values, s.ranges, s.order, self.bg, self._off(self.image, 3 * pix_off),
+        abi.pg_render_fwd(s.handle, s.splats, s.values, s.ranges, self._order(s), self.bg, self._off(self.image, 3 * pix_off),
                           self._off(self.final_T, pix_off), self._off(self.n_contrib, pix_off), s.tile_entries,
                           s.entries, counters)
 
@@ -278,7 +284,7 @@ class Renderer:
         assert g.is_contiguous() and g.numel() == 3 * self.n_pixels
         if self.batched:
             s = self.sets[0]
-            abi.pg_render_bwd(s.handle, s.splats, s.tiles, s.values, s.ranges, s.order, s.inst_first, s.n_inst, s.cap,
+            abi.pg_render_bwd(s.handle, s.splats, s.tiles, s.values, s.ranges, self._order(s), s.inst_first, s.n_inst, s.cap,
                               s.tile_entries, s.entries, self.n_contrib, self.bg, self.final_T, g, s.inst_grad)
             abi.pg_project_bwd(s.handle, self.params, s.bins, s.inst_first, s.n_inst, s.cap,
                                s.inst_grad, self.gauss_texel, self.dynamic, self.H, self.W, s.grad2d, self.dL_datlas, 0)
@@ -286,7 +292,7 @@ class Renderer:
             self.dL_datlas.zero_()
             for k, s in enumerate(self.sets):
                 po = self.pix_base[k]
-                abi.pg_render_bwd(s.handle, s.splats, s.tiles, s.values, s.ranges, s.order, s.inst_first, s.n_inst, s.cap,
+                abi.pg_render_bwd(s.handle, s.splats, s.tiles, s.values, s.ranges, self._order(s), s.inst_first, s.n_inst, s.cap,
                                   s.tile_entries, s.entries, self._off(self.n_contrib, po), self.bg,
                                   self._off(self.final_T, po), self._off(g, 3 * po), s.inst_grad)
                 abi.pg_project_bwd(s.handle, self.params, s.bins, s.inst_first, s.n_inst, s.cap,

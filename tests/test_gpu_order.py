@@ -1,7 +1,9 @@
 """The tile dispatch order that pg_bin_sort writes for the compositing calls:
-every tile exactly once, longest list classes first, and the forward and the
-adjoint give bitwise the same images, entries and gradient slots with it as
-with the default order (it schedules work, nothing else)."""
+every tile exactly once, longest list classes first, each class's tiles in
+index order dealt to the XCDs in contiguous runs (checked slot by slot), and
+the forward and the adjoint give bitwise the same images, entries and
+gradient slots with it as with the default order (it schedules work,
+nothing else)."""
 import numpy as np
 import pytest
 import torch
@@ -35,6 +37,25 @@ def length_class(n):
     return 63 - np.minimum(4 * e + q, 63)
 
 
+def expected_order(lengths):
+    """Classes longest first; inside a class, the tiles in index order dealt
+    to the XCDs (slot mod 8) in contiguous runs."""
+    cls = length_class(lengths)
+    tiles = np.lexsort((np.arange(len(lengths)), cls))
+    out = np.empty(len(lengths), np.int64)
+    o = 0
+    for c in range(64):
+        run = tiles[o:o + int((cls == c).sum())]
+        slots = np.arange(o, o + len(run))
+        r = 0
+        for x in range(8):
+            sx = slots[slots % 8 == x]
+            out[sx] = run[r:r + len(sx)]
+            r += len(sx)
+        o += len(run)
+    return out
+
+
 @pytest.mark.parametrize("name", list(SCENES))
 def test_order_is_a_longest_first_permutation_and_changes_nothing(name):
     sc = SCENES[name]()
@@ -51,6 +72,7 @@ def test_order_is_a_longest_first_permutation_and_changes_nothing(name):
     rg = s.ranges[:2 * nt].cpu().numpy().reshape(nt, 2)
     cls = length_class(rg[order, 1] - rg[order, 0])
     assert np.all(np.diff(cls) >= 0), "list length classes are not in descending order"
+    assert np.array_equal(order, expected_order(rg[:, 1] - rg[:, 0])), "order differs from the rule"
     say(f"[gpu] tile order {name}: {nt} tiles, longest list {int((rg[:, 1] - rg[:, 0]).max())} first")
     image, T, nc = r.image.clone(), r.final_T.clone(), r.n_contrib.clone()
     te, ent, slots = s.tile_entries.clone(), s.entries.clone(), s.inst_grad.clone()
