@@ -159,8 +159,8 @@ pg_status pg_views_create(const pg_camera* cams, int32_t n_views, int32_t frames
     p->h_pix_base = new int64_t[n_views + 1];
     std::memcpy(p->h_tile_base, tb.data(), sizeof(int64_t) * (n_views + 1));
     std::memcpy(p->h_pix_base, pb.data(), sizeof(int64_t) * (n_views + 1));
-    hipGetDevice(&p->device);
-    hipError_t e = hipMalloc(&p->d_views, sizeof(ViewDev) * n_views);
+    hipError_t e = hipGetDevice(&p->device);
+    if (e == hipSuccess) e = hipMalloc(&p->d_views, sizeof(ViewDev) * n_views);
     if (e == hipSuccess) e = hipMalloc(&p->d_frame_views, sizeof(int32_t) * (frames + 1));
     if (e == hipSuccess) e = hipMalloc(&p->d_view_order, sizeof(int32_t) * n_views);
     if (e == hipSuccess) e = hipMalloc(&p->d_ssim_base, sizeof(int64_t) * n_views);
@@ -178,14 +178,16 @@ pg_status pg_views_create(const pg_camera* cams, int32_t n_views, int32_t frames
 
 pg_status pg_views_destroy(pg_views* v) {
     if (!v) return PG_OK;
-    if (v->d_views) hipFree(v->d_views);
-    if (v->d_frame_views) hipFree(v->d_frame_views);
-    if (v->d_view_order) hipFree(v->d_view_order);
-    if (v->d_ssim_base) hipFree(v->d_ssim_base);
+    hipError_t e = hipSuccess;
+    for (void* d : {(void*)v->d_views, (void*)v->d_frame_views, (void*)v->d_view_order, (void*)v->d_ssim_base}) {
+        if (!d) continue;
+        const hipError_t r = hipFree(d);
+        if (e == hipSuccess) e = r;      // free everything, report the first failure
+    }
     delete[] v->h_tile_base;
     delete[] v->h_pix_base;
     delete v;
-    return PG_OK;
+    return e == hipSuccess ? PG_OK : hip_fail(e, "pg_views_destroy");
 }
 
 pg_status pg_views_get_info(const pg_views* v, pg_views_info* info) {
