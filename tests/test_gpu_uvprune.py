@@ -72,3 +72,20 @@ def test_uv_prune_temporal_window_sampled_frame():
     for a, b in zip(got, ref):
         assert np.array_equal(a[f].astype(np.int64), np.asarray(b, np.int64))
     say(f"[gpu] uv prune window frame {f}: kept {int(ref[2].sum())} of {len(ref[2])}")
+
+
+def test_uv_prune_degenerate_cases():
+    """No Gaussians at all; a map of one pixel (every valid Gaussian shares it,
+    so K keeps exactly the K largest opacities); K beyond every pixel count."""
+    sc = synth.random_scene(side=4, sh_degree=0, views=1, width=40, height=24, seed=0)
+    sc.occupancy[:] = 0
+    sc.atlas[:] = 0
+    uv, rank, keep = run(sc, 8, 4, 2)
+    assert uv.size == 0 and rank.size == 0 and keep.size == 0
+    sc = SCENES["tiny"]()
+    for M, Nv, K in ((1, 1, 5), (16, 8, 10 ** 6)):
+        got = run(sc, M, Nv, K)
+        ref = reference(sc, M, Nv, K)
+        for a, b in zip(got, ref):
+            assert np.array_equal(a.astype(np.int64), b.astype(np.int64)), (M, Nv, K)
+    say(f"[gpu] uv prune one-pixel map: kept {int(ref[2].sum())}; empty atlas: nothing")
