@@ -23,11 +23,12 @@
 //                               inst_first[gv] = instances of all records before
 //                               gv in (view, id) order: the record's gradient
 //                               slots, one per kept tile in rectangle order
-//   radix passes (32-bit keys)  LSD, digit width <= 10 bits
+//   radix passes (32-bit keys)  LSD, digit width <= 8 bits
 //   k_sorted_count / k_emit     tiles per sorted record -> instance offsets ->
 //                               work-group-cooperative emission (coalesced writes)
 //   radix passes (32-bit keys)  tile ids
 //   k_ranges                    [start, end) of every tile
+//   k_order_count/_scan/_place  the compositing kernels' tile dispatch order
 // Radix passes: per-tile digit histograms (upsweep, LDS atomics), a scan of
 // the histograms into per-tile digit offsets, then a downsweep that ranks keys
 // with a wave-level multisplit (one ballot per digit bit) and scatters through
