@@ -513,27 +513,34 @@ hipError_t radix_pass(int bits, const K* ki, const int32_t* vi, K* ko, int32_t* 
 
 // [start, end) of every tile from the sorted keys: a tile starts where the key
 // differs from its predecessor, which is also where the previous tile ends.
-// One thread per key, over a fixed grid that strides through the device-side
-// count (a grid sized for the capacity was mostly empty groups); the
-// predecessor comes from the neighbouring lane (only the first lane of a wave
-// loads it), so every key is read once.
+// Four consecutive keys per thread, over a fixed grid that strides through
+// the device-side count (a grid sized for the capacity was mostly empty
+// groups); the predecessor of a thread's first key is the neighbouring lane's
+// last (only the first lane of a wave loads it), so every key is read once.
 constexpr int kRangeGrid = 4096;
 __global__ __launch_bounds__(256) void k_ranges(const uint32_t* __restrict__ keys, const int64_t* __restrict__ misc,
                                                 int32_t* __restrict__ ranges) {
     const int64_t I = misc[1];
-    for (int64_t base = (int64_t)blockIdx.x * 256; base < I; base += (int64_t)gridDim.x * 256) {
-        const int64_t i = base + threadIdx.x;
-        const uint32_t k = i < I ? keys[i] : 0u;
-        uint32_t prev = __shfl_up(k, 1, 64);
-        if ((threadIdx.x & 63) == 0 && i > 0 && i < I) prev = keys[i - 1];
-        if (i < I) {
+    const int64_t nq = (I + 3) / 4;
+    for (int64_t base = (int64_t)blockIdx.x * 256; base < nq; base += (int64_t)gridDim.x * 256) {
+        const int64_t i0 = 4 * (base + threadIdx.x);
+        uint32_t k[4];
+#pragma unroll
+        for (int j = 0; j < 4; j++) k[j] = i0 + j < I ? keys[i0 + j] : 0u;
+        uint32_t prev = __shfl_up(k[3], 1, 64);
+        if ((threadIdx.x & 63) == 0 && i0 > 0 && i0 < I) prev = keys[i0 - 1];
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
+            const int64_t i = i0 + j;
+            if (i >= I) break;
+            const uint32_t p = j == 0 ? prev : k[j - 1];
             if (i == 0) {
-                ranges[2 * (int64_t)k] = 0;
-            } else if (prev != k) {
-                ranges[2 * (int64_t)k] = (int32_t)i;
-                ranges[2 * (int64_t)prev + 1] = (int32_t)i;
+                ranges[2 * (int64_t)k[j]] = 0;
+            } else if (p != k[j]) {
+                ranges[2 * (int64_t)k[j]] = (int32_t)i;
+                ranges[2 * (int64_t)p + 1] = (int32_t)i;
             }
-            if (i == I - 1) ranges[2 * (int64_t)k + 1] = (int32_t)I;
+            if (i == I - 1) ranges[2 * (int64_t)k[j] + 1] = (int32_t)I;
         }
     }
 }
