@@ -219,7 +219,7 @@ __global__ __launch_bounds__(kLanes) void k_render_fwd(const ViewDev* __restrict
                 const float4 g = s_geo[k];
                 const float4 cc = s_col[k];
                 const float cb = s_blu[k];
-                const uint32_t mask = s_mask[k];
+                const uint32_t mask = (uint32_t)__builtin_amdgcn_readfirstlane((int)s_mask[k]);   // wave-uniform: bit tests on the scalar unit
                 const int32_t pos1 = b0 - rg.x + k + 1;
                 const uint64_t kbit = 1ull << (k - k0);
 #pragma unroll
