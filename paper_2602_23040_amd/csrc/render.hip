@@ -143,18 +143,27 @@ __device__ __forceinline__ bool tile_geo(const ViewDev* views, int nv, int64_t n
 // ill-conditioned conics, so a skipped block never holds a pixel with q <= 9
 // and results are unchanged.  (Testing the minimum of q over each block
 // rectangle instead cost more at staging than it saved.)
+// One staged Gaussian in LDS: one record per list entry, so a wave reads all
+// of it from a single address register with immediate offsets.  aux holds the
+// block mask (forward) or the gradient slot and the entry word (adjoint).
+struct alignas(16) Staged {
+    float4 geo;          // local mean x, y; conic a, 2 b
+    float4 col;          // conic c, opacity, red, green
+    float blu;           // blue
+    uint32_t aux[3];
+};
+
 template <int TW, int TH, bool MASK>
 __device__ __forceinline__ void stage(const pg_splat* __restrict__ splats, int32_t gv, double ox, double oy,
-                                      float col0, float row0, float4* s_geo, float4* s_col, float* s_blu,
-                                      uint32_t* s_mask, int k) {
+                                      float col0, float row0, Staged* s_st, int k) {
     const float4* sp = reinterpret_cast<const float4*>(splats + gv);
     const float4 a = sp[0], b = sp[1], c = sp[2];
     double2 m;
     *reinterpret_cast<float4*>(&m) = a;
     const float mx = (float)(m.x - ox), my = (float)(m.y - oy);
-    s_geo[k] = make_float4(mx, my, b.x, 2.0f * b.y);
-    s_col[k] = make_float4(b.z, b.w, c.x, c.y);   // conic c, opacity, red, green
-    s_blu[k] = c.z;
+    s_st[k].geo = make_float4(mx, my, b.x, 2.0f * b.y);
+    s_st[k].col = make_float4(b.z, b.w, c.x, c.y);   // conic c, opacity, red, green
+    s_st[k].blu = c.z;
     if (!MASK) return;
     constexpr int BPR = TW / 8;
     const float ac = b.x * b.z;
@@ -170,7 +179,7 @@ __device__ __forceinline__ void stage(const pg_splat* __restrict__ splats, int32
             if (mx + ex >= x0 && mx - ex <= x0 + 7.0f && my + ey >= y0 && my - ey <= y0 + 7.0f) mask |= 1u << j;
         }
     }
-    s_mask[k] = mask;
+    s_st[k].aux[0] = mask;
 }
 
 template <int TW, int TH, int BATCH, bool STATS>
@@ -184,10 +193,7 @@ __global__ __launch_bounds__(kLanes) void k_render_fwd(const ViewDev* __restrict
                                                        int32_t* __restrict__ tile_entries,
                                                        uint32_t* __restrict__ entries,
                                                        unsigned long long* __restrict__ counters) {
-    __shared__ float4 s_geo[BATCH];
-    __shared__ float4 s_col[BATCH];
-    __shared__ float s_blu[BATCH];
-    __shared__ uint32_t s_mask[BATCH];
+    __shared__ Staged s_st[BATCH];     // aux[0]: the mask of 8x8 blocks the ellipse can reach
     TileGeo t;
     if (!tile_geo<TW, TH>(views, nv, n_tiles, order, t)) return;
     const int2 rg = ranges[t.tile];
@@ -208,7 +214,7 @@ __global__ __launch_bounds__(kLanes) void k_render_fwd(const ViewDev* __restrict
         if ((live[0] | live[1] | live[2] | live[3]) == 0) break;
         __syncthreads();
         for (int32_t i = threadIdx.x; i < BATCH && b0 + i < rg.y; i += kLanes)
-            stage<TW, TH, true>(splats, values[b0 + i], t.ox, t.oy, t.col0, t.row0, s_geo, s_col, s_blu, s_mask, i);
+            stage<TW, TH, true>(splats, values[b0 + i], t.ox, t.oy, t.col0, t.row0, s_st, i);
         __syncthreads();
         const int32_t cnt = min(BATCH, rg.y - b0);
         // sub-batches of 64 Gaussians: bit (k - k0) of took[j] records that a pixel of block j took Gaussian k
@@ -216,10 +222,10 @@ __global__ __launch_bounds__(kLanes) void k_render_fwd(const ViewDev* __restrict
             const int32_t k1 = min(cnt, k0 + kLanes);
             uint64_t took[kPPT] = {0, 0, 0, 0};
             for (int32_t k = k0; k < k1; k++) {
-                const float4 g = s_geo[k];
-                const float4 cc = s_col[k];
-                const float cb = s_blu[k];
-                const uint32_t mask = (uint32_t)__builtin_amdgcn_readfirstlane((int)s_mask[k]);   // wave-uniform: bit tests on the scalar unit
+                const float4 g = s_st[k].geo;
+                const float4 cc = s_st[k].col;
+                const float cb = s_st[k].blu;
+                const uint32_t mask = (uint32_t)__builtin_amdgcn_readfirstlane((int)s_st[k].aux[0]);   // wave-uniform: bit tests on the scalar unit
                 const int32_t pos1 = b0 - rg.x + k + 1;
                 const uint64_t kbit = 1ull << (k - k0);
 #pragma unroll
@@ -340,11 +346,9 @@ __global__ __launch_bounds__(kLanes) void k_render_bwd(const ViewDev* __restrict
                                                        const float* __restrict__ dL_dimage,
                                                        const int64_t* __restrict__ n_inst_dev, int64_t cap,
                                                        float* __restrict__ inst_grad) {
-    __shared__ float4 s_geo[BATCH];
-    __shared__ float4 s_col[BATCH];
-    __shared__ float s_blu[BATCH];
-    __shared__ int32_t s_slot[BATCH];      // gradient slot of the (Gaussian, this tile) instance (-1: none)
-    __shared__ uint32_t s_word[BATCH];     // entry word: list position << 4 | blocks that composited it
+    // aux[0]: gradient slot of the (Gaussian, this tile) instance (-1: none);
+    // aux[1]: entry word, list position << 4 | blocks that composited it
+    __shared__ Staged s_st[BATCH];
     TileGeo t;
     if (!tile_geo<TW, TH>(views, nv, n_tiles, order, t)) return;
     const int2 rg = ranges[t.tile];
@@ -384,22 +388,23 @@ __global__ __launch_bounds__(kLanes) void k_render_bwd(const ViewDev* __restrict
         __syncthreads();
         for (int32_t i = lane; i < cnt; i += kLanes) {
             const uint32_t word = entries[rg.x + bstart + i];
-            s_word[i] = word;
+            s_st[i].aux[1] = word;
             const int32_t gv = values[rg.x + (int32_t)(word >> 4)];
             const uint4 ts = reinterpret_cast<const uint4*>(tiles)[gv];     // the record's kept tiles
             const int32_t xlo = (int32_t)(ts.z & 0xffff), ylo = (int32_t)(ts.z >> 16);
             const int32_t w = (int32_t)(ts.w & 0xffff);
             const uint64_t mask = (uint64_t)ts.x | ((uint64_t)ts.y << 32);
             const int32_t slot = inst_first[gv] + kept_rank(mask, (t.ty - ylo) * w + (t.tx - xlo));
-            s_slot[i] = (slot >= 0 && slot < n_inst) ? slot : -1;
-            stage<TW, TH, false>(splats, gv, t.ox, t.oy, t.col0, t.row0, s_geo, s_col, s_blu, nullptr, i);
+            s_st[i].aux[0] = (uint32_t)((slot >= 0 && slot < n_inst) ? slot : -1);
+            stage<TW, TH, false>(splats, gv, t.ox, t.oy, t.col0, t.row0, s_st, i);
         }
         __syncthreads();
         for (int32_t k = cnt - 1; k >= 0; k--) {
-            const float4 g = s_geo[k];
-            const float4 cc = s_col[k];
-            const float cb = s_blu[k];
-            const uint32_t word = (uint32_t)__builtin_amdgcn_readfirstlane((int)s_word[k]);
+            const float4 g = s_st[k].geo;
+            const float4 cc = s_st[k].col;
+            const float cb = s_st[k].blu;
+            const uint32_t word = (uint32_t)__builtin_amdgcn_readfirstlane((int)s_st[k].aux[1]);
+            const int32_t slot = __builtin_amdgcn_readfirstlane((int)s_st[k].aux[0]);
             const int32_t pos = (int32_t)(word >> 4);
             // Per-lane sums over the lane's pixels, later reduced over the wave:
             //   m[0..1] = sum dq' (dx, dy), m[2..4] = sum dq' (dx^2, dx dy, dy^2)
@@ -464,7 +469,6 @@ __global__ __launch_bounds__(kLanes) void k_render_bwd(const ViewDev* __restrict
             const float tot = wave_totals9(m, o1, lane == 63);
             // the (Gaussian, tile) sums go to the instance's own slot: no atomics, and the
             // projection adjoint adds a record's slots in a fixed order
-            const int32_t slot = __builtin_amdgcn_readfirstlane(s_slot[k]);
             if (slot >= 0) {
                 // 36-byte raw buffer over the slot: the address stays scalar, and lanes
                 // holding no total (offset 36) fall outside it and store nothing
