@@ -296,6 +296,7 @@ __global__ __launch_bounds__(kProjBlk) void k_project(const ViewDev* __restrict_
     for (int k = 0; k < 3 * NB; k++) sh[k] = has ? P[(int64_t)(11 + k) * N] : 0.0f;
     World w;
     world_chain(rec, w);
+    const double itw = 1.0 / (double)tw, ith = 1.0 / (double)th;   // exact: tw, th are 8, 16 or 32
     bool any = false;
     for (int32_t k = 0; k < nv; k++) {
         const bool act = v0 + k < v1;
@@ -314,10 +315,12 @@ __global__ __launch_bounds__(kProjBlk) void k_project(const ViewDev* __restrict_
             const double rr = ceil(3.0 * sqrt(lam));
             mx = (V.fx * c.xc) / c.zc + V.cx;
             my = (V.fy * c.yc) / c.zc + V.cy;
-            const double xlo = fmax(0.0, floor((mx - rr) / (double)tw));
-            const double xhi = fmin((double)(V.TX - 1), floor((mx + rr) / (double)tw));
-            const double ylo = fmax(0.0, floor((my - rr) / (double)th));
-            const double yhi = fmin((double)(V.TY - 1), floor((my + rr) / (double)th));
+            // the view table only admits tile sides of 8, 16 or 32: dividing by a power of
+            // two is exactly multiplying by its reciprocal, so these equal the divisions
+            const double xlo = fmax(0.0, floor((mx - rr) * itw));
+            const double xhi = fmin((double)(V.TX - 1), floor((mx + rr) * itw));
+            const double ylo = fmax(0.0, floor((my - rr) * ith));
+            const double yhi = fmin((double)(V.TY - 1), floor((my + rr) * ith));
             const float zf = (float)c.zc;
             double d[3], dn;
             view_dir<L>(V, w, d, &dn);
