@@ -602,6 +602,12 @@ __global__ __launch_bounds__(128) void k_project_bwd_geo(const ViewDev* __restri
     double acc[11];
 #pragma unroll
     for (int k = 0; k < 11; k++) acc[k] = 0.0;
+    // dL/dSigma (world) and dL/do summed over the views: the scale, rotation and
+    // activation chains after them are linear and view-independent, so they run
+    // once per Gaussian on the sums instead of once per record
+    double GSw_sum[9], go_sum = 0.0;
+#pragma unroll
+    for (int k = 0; k < 9; k++) GSw_sum[k] = 0.0;
     World w;
     bool have_world = false;
     for (int32_t vi = v0; vi < v1; vi++) {
@@ -625,8 +631,9 @@ __global__ __launch_bounds__(128) void k_project_bwd_geo(const ViewDev* __restri
         const ViewDev& V = views[v];
         Cam c;
         if (!camera_chain(V, w, c)) continue;   // never for a record with a gradient: the forward kept it
-        const double det = c.det;
-        const double Q00 = c.cp / det, Q01 = -c.bp / det, Q11 = c.ap / det;
+        // (gradients only from here on: reciprocals instead of divisions)
+        const double idet = 1.0 / c.det;
+        const double Q00 = c.cp * idet, Q01 = -c.bp * idet, Q11 = c.ap * idet;
         // 2D gradients from the moments (dL/dq = -dq'/2): dL/dm = Q (m0, m1),
         // dL/d(a, b, c) = -(m2 / 2, m3, m4 / 2); written back as the record's grad2d
         {
@@ -677,13 +684,30 @@ __global__ __launch_bounds__(128) void k_project_bwd_geo(const ViewDev* __restri
         for (int r = 0; r < 3; r++)
 #pragma unroll
             for (int k = 0; k < 3; k++) GSw[3 * r + k] = R[r] * tmp[k] + R[3 + r] * tmp[3 + k] + R[6 + r] * tmp[6 + k];
-        // dL/dM = 2 GSw M ; dL/ds ; dL/dRq
+#pragma unroll
+        for (int k = 0; k < 9; k++) GSw_sum[k] += GSw[k];
+        // mean: dm/dmu_c = J, plus the dependence of J on mu_c
+        const double iz = 1.0 / c.zc, iz2 = iz * iz, iz3 = iz2 * iz;
+        double gmc0 = c.J[0] * g6[0] + c.J[3] * g6[1];
+        double gmc1 = c.J[1] * g6[0] + c.J[4] * g6[1];
+        double gmc2 = c.J[2] * g6[0] + c.J[5] * g6[1];
+        gmc0 += GJm[2] * (-V.fx * iz2);
+        gmc1 += GJm[5] * (-V.fy * iz2);
+        gmc2 += GJm[0] * (-V.fx * iz2) + GJm[2] * (2.0 * V.fx * c.xc * iz3) + GJm[4] * (-V.fy * iz2)
+                + GJm[5] * (2.0 * V.fy * c.yc * iz3);
+#pragma unroll
+        for (int k = 0; k < 3; k++) acc[k] += R[k] * gmc0 + R[3 + k] * gmc1 + R[6 + k] * gmc2;
+        go_sum += g6[5];
+    }
+    if (have_world) {
+        // dL/dM = 2 GSw M ; dL/ds (log-scale) ; dL/dRq -> the normalised quaternion -> the stored one
         double gs[3] = {0.0, 0.0, 0.0}, GR[9];
 #pragma unroll
         for (int r = 0; r < 3; r++)
 #pragma unroll
             for (int k = 0; k < 3; k++) {
-                const double gm = 2.0 * (GSw[3 * r] * w.M[k] + GSw[3 * r + 1] * w.M[3 + k] + GSw[3 * r + 2] * w.M[6 + k]);
+                const double gm = 2.0 * (GSw_sum[3 * r] * w.M[k] + GSw_sum[3 * r + 1] * w.M[3 + k] +
+                                         GSw_sum[3 * r + 2] * w.M[6 + k]);
                 gs[k] += gm * w.Rq[3 * r + k];
                 GR[3 * r + k] = gm * w.s[k];
             }
@@ -697,23 +721,11 @@ __global__ __launch_bounds__(128) void k_project_bwd_geo(const ViewDev* __restri
         gq[3] = 2.0 * (-2.0 * qz * GR[0] - qa * GR[1] + qx * GR[2] + qa * GR[3] - 2.0 * qz * GR[4] + qy * GR[5]
                        + qx * GR[6] + qy * GR[7]);
         const double qd = gq[0] * qa + gq[1] * qx + gq[2] * qy + gq[3] * qz;
-        // mean: dm/dmu_c = J, plus the dependence of J on mu_c
-        const double z2 = c.zc * c.zc, z3 = z2 * c.zc;
-        double gmc0 = c.J[0] * g6[0] + c.J[3] * g6[1];
-        double gmc1 = c.J[1] * g6[0] + c.J[4] * g6[1];
-        double gmc2 = c.J[2] * g6[0] + c.J[5] * g6[1];
-        gmc0 += GJm[2] * (-V.fx / z2);
-        gmc1 += GJm[5] * (-V.fy / z2);
-        gmc2 += GJm[0] * (-V.fx / z2) + GJm[2] * (2.0 * V.fx * c.xc / z3) + GJm[4] * (-V.fy / z2)
-                + GJm[5] * (2.0 * V.fy * c.yc / z3);
 #pragma unroll
-        for (int k = 0; k < 3; k++) {
-            acc[k] += R[k] * gmc0 + R[3 + k] * gmc1 + R[6 + k] * gmc2;
-            acc[3 + k] += w.s[k] * gs[k];
-        }
+        for (int k = 0; k < 3; k++) acc[3 + k] += w.s[k] * gs[k];
 #pragma unroll
         for (int k = 0; k < 4; k++) acc[6 + k] += (gq[k] - w.qh[k] * qd) / w.qn;
-        acc[10] += g6[5] * w.o * (1.0 - w.o);
+        acc[10] += go_sum * w.o * (1.0 - w.o);
     }
     const int64_t texel = gauss_texel[i];
     const float m = dyn ? (dyn[texel] ? 1.f : 0.f) : 1.f;
