@@ -17,12 +17,37 @@ namespace {
 
 constexpr int kLossBlocks = 1024;
 
+// VEC: the three arrays are 16-byte aligned and each thread moves four
+// elements per load and store (the streaming rate of 4-byte accesses was
+// ~4.3 TB/s); the last n mod 4 elements take the scalar loop.
+template <bool VEC>
 __global__ __launch_bounds__(256) void k_l1(const float* __restrict__ img, const float* __restrict__ tgt, int64_t n,
                                             float* __restrict__ g, double* __restrict__ partial) {
     __shared__ double s[4];
     const float inv = (float)(1.0 / (double)n);
     double acc = 0.0;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t done = 0;
+    if (VEC) {
+        const int64_t n4 = n / 4;
+        const float4* a4 = reinterpret_cast<const float4*>(img);
+        const float4* b4 = reinterpret_cast<const float4*>(tgt);
+        float4* g4 = reinterpret_cast<float4*>(g);
+        for (int64_t q = t0; q < n4; q += stride) {
+            const float4 a = a4[q], b = b4[q];
+            const float d[4] = {a.x - b.x, a.y - b.y, a.z - b.z, a.w - b.w};
+            float o[4];
+#pragma unroll
+            for (int j = 0; j < 4; j++) {
+                acc += (double)fabsf(d[j]);
+                o[j] = d[j] > 0.0f ? inv : (d[j] < 0.0f ? -inv : 0.0f);
+            }
+            g4[q] = make_float4(o[0], o[1], o[2], o[3]);
+        }
+        done = 4 * n4;
+    }
+    for (int64_t i = done + t0; i < n; i += stride) {
         const float d = img[i] - tgt[i];
         acc += (double)fabsf(d);
         g[i] = d > 0.0f ? inv : (d < 0.0f ? -inv : 0.0f);
@@ -78,7 +103,10 @@ __global__ void k_step_inc(int32_t* step) { *step += 1; }
 
 hipError_t launch_loss_l1(const float* img, const float* tgt, int64_t n, float* g, double* partial, float* loss,
                           hipStream_t s) {
-    k_l1<<<kLossBlocks, 256, 0, s>>>(img, tgt, n, g, partial);
+    const bool vec = ((reinterpret_cast<uintptr_t>(img) | reinterpret_cast<uintptr_t>(tgt) |
+                       reinterpret_cast<uintptr_t>(g)) & 15) == 0;
+    if (vec) k_l1<true><<<kLossBlocks, 256, 0, s>>>(img, tgt, n, g, partial);
+    else k_l1<false><<<kLossBlocks, 256, 0, s>>>(img, tgt, n, g, partial);
     k_l1_final<<<1, kLossBlocks, 0, s>>>(partial, n, loss);
     return hipGetLastError();
 }
