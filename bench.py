@@ -111,7 +111,7 @@ def main():
         calibrate_copy(args.calibrate_copy)
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; multi-GPU sharding is designed but not built",
+        print(json.dumps({"error": "the step runs on one GPU; sharding the views over several GPUs is not implemented",
                           "n_gpus": args.gpus}))
         sys.exit(2)
     import numpy as np
