@@ -148,6 +148,42 @@ pg_status pg_fetch_workspace_size(int32_t H, int32_t W, size_t* bytes);
 /* Workspace bytes for pg_bin_sort with room for inst_capacity instances. */
 pg_status pg_sort_workspace_size(const pg_views* views, int64_t inst_capacity, size_t* bytes);
 
+/* Byte sizes of every device buffer one fitting step (pg_atlas_fetch ->
+ * pg_project -> pg_bin_sort -> pg_render_fwd -> loss -> pg_backward) needs
+ * for a view table, an H x W atlas and an instance capacity, besides the
+ * atlas itself: the problem statement's "optimise U, render the views,
+ * return the gradient" (Sec. 4.2 "Fitting UV Maps Directly") planned ahead.
+ * Each field is the size of the buffer of the same name in the calls below;
+ * total is their sum with each rounded up to 256 bytes (one allocation that
+ * holds them all). */
+typedef struct pg_plan {
+    size_t params, gauss_texel, texel_gauss, n_gauss, fetch_ws;        /* pg_atlas_fetch */
+    size_t visible, splats, bins, tile_sets;                           /* pg_project */
+    size_t keys, values, tile_ranges, tile_order, inst_first, n_inst, overflow, sort_ws, inst_grad;  /* pg_bin_sort */
+    size_t image, final_T, n_contrib, tile_entries, entries;           /* pg_render_fwd */
+    size_t dL_dimage;                                                  /* loss cotangent */
+    size_t grad2d, dL_datlas;                                          /* pg_backward */
+    size_t total;
+} pg_plan;
+/* Host only: no device work, no synchronisation.  PG_ERR_INVALID_ARG when
+ * H W cannot hold n_gauss texels, H W > 2^31 - 1 or inst_capacity is outside
+ * [0, 2^31 - 1]. */
+pg_status pg_workspace_query(const pg_views* views, int32_t H, int32_t W, int64_t inst_capacity, pg_plan* plan);
+
+/* Host-side status of a step whose instance count the device decides (the
+ * capacity-overflow convention above).  Synchronises `stream`, then reads
+ * *overflow_dev and *n_inst_dev (from pg_bin_sort).  Returns PG_OK, or
+ * PG_ERR_CAPACITY when the last sort overflowed; needed_capacity (host, may
+ * be NULL) receives the instance count that suffices either way.  After
+ * PG_ERR_CAPACITY the step's outputs are undefined: the caller grows the
+ * instance buffers (keys, values, entries, inst_grad, the sort workspace)
+ * to at least that count and runs the step again -- in a captured graph,
+ * re-captures it, since the graph holds the old buffers.  Returns
+ * PG_ERR_INVALID_ARG while `stream` is being captured (it must not
+ * synchronise there): call it after the replay. */
+pg_status pg_status_check(const int32_t* overflow_dev, const int64_t* n_inst_dev, int64_t* needed_capacity,
+                          void* stream);
+
 /* a1 -- Atlas fetch (Sec. 4.2 "Fitting UV Maps Directly"; atlas layout
  * Sec. 4.1).  Compacts occupied texels (row-major rank = Gaussian id) and
  * gathers their raw channels.
@@ -199,16 +235,21 @@ pg_status pg_atlas_fake_quant(float* params, const int64_t* n_gauss_dev, int64_t
  * kept when the least q over the rectangle of its pixel centres is at most
  * 9.001 (q = 0 when the mean is inside; else the least of the four edge
  * minima, each taken at the edge parabola's clamped vertex); larger
- * rectangles keep every tile.  A record with no kept tile is culled.  The
- * kept tiles hold every pixel with q <= 9, so the image does not change.
+ * rectangles keep every tile.  A record with no kept tile is not listed.  The
+ * method lists every tile of the rectangle; the dropped tiles have q > 9 at
+ * every pixel centre, so the image and the gradients do not change.
  * Decision quantities are evaluated in FP64 in a fixed order without
  * contraction, from the FP32 texel values.
  *   params     device float [F][C][n_gauss] (row stride n_gauss)
  *   splats     device pg_splat [n_gv] out
  *   bins       device pg_bin [n_gv] out
  *   tiles      device pg_tile_set [n_gv] out: each record's kept tiles
- *   visible    device uint8 [F n_gauss]: set to 1 for Gaussians with n_tiles > 0
- *              in at least one view of this call; never cleared (OR semantics). */
+ *   visible    device uint8 [F n_gauss]: set to 1 for Gaussians that survive the z
+ *              and det culls in at least one view of this call with a pixel of that
+ *              view within r of the mean on both axes (m_x + r >= 0, m_x - r < W,
+ *              m_y + r >= 0, m_y - r < H: the rectangle with one-pixel tiles is not
+ *              empty).  It does not depend on the tile shape or the tile culling;
+ *              never cleared (OR semantics).  The set sparse Adam updates. */
 pg_status pg_project(const pg_views* views, const float* params, pg_splat* splats, pg_bin* bins,
                      pg_tile_set* tiles, uint8_t* visible, void* stream);
 
@@ -363,6 +404,21 @@ pg_status pg_render_bwd(const pg_views* views, const pg_splat* splats, const pg_
 pg_status pg_project_bwd(const pg_views* views, const float* params, const pg_bin* bins, const int32_t* inst_first,
                          const int64_t* n_inst_dev, int64_t inst_capacity, const float* inst_grad, const int32_t* gauss_texel, const uint8_t* dynamic_mask, int32_t H,
                          int32_t W, float* grad2d, float* dL_datlas, int32_t accumulate, void* stream);
+
+/* a5 -- The whole adjoint: dL/dimage in, dL/datlas out, with gradient
+ * freezing (Sec. 4.2 "Gradient Freezing"; the problem statement's "return
+ * the gradient to U").  Enqueues pg_render_bwd and then pg_project_bwd with
+ * the arguments of the same names, so its results are theirs bit for bit;
+ * the two halves stay separate entry points for callers that keep the
+ * per-instance or per-record gradients.  Argument checks are those of both
+ * calls, made before anything is enqueued. */
+pg_status pg_backward(const pg_views* views, const float* params, const pg_splat* splats, const pg_bin* bins,
+                      const pg_tile_set* tiles, const int32_t* values, const int32_t* tile_ranges,
+                      const int32_t* tile_order, const int32_t* inst_first, const int64_t* n_inst_dev,
+                      int64_t inst_capacity, const int32_t* tile_entries, const uint32_t* entries,
+                      const int32_t* n_contrib, const float* bg, const float* final_T, const float* dL_dimage,
+                      float* inst_grad, const int32_t* gauss_texel, const uint8_t* dynamic_mask, int32_t H, int32_t W,
+                      float* grad2d, float* dL_datlas, int32_t accumulate, void* stream);
 
 /* a4' -- L1 photometric term of Sec. 4.2 "Objective" (lambda_ssim = 0):
  * L = mean |image - target|, dL/dimage = sign(image - target) / n (sign 0 = 0).

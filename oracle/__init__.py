@@ -12,11 +12,19 @@ Parity status of each function (what pins it; see ``tests/test_oracle_*.py``):
                        J J^T, eig(Sigma) = s^2, look-at target -> principal point,
                        rotation about the optical axis; SH basis against scipy's
                        complex SH and quadrature orthonormality.
-  bin_sort          -- brute-force rectangle membership + textbook sort.
+  bin_sort          -- brute-force rectangle membership + textbook sort; every tile of
+                       the rectangle is listed (no culling inside the rectangle).
   render            -- single Gaussian, stacked-Gaussian transmittance product,
-                       two-Gaussian closed form; tiled == brute force bitwise.
+                       two-Gaussian closed form; tiled == brute force bitwise (brute
+                       force walks every Gaussian past the z / det culls, no rectangles).
+  pixel (near / flips) -- one-pixel scenes with q, alpha and T' just inside and just
+                       outside each guard band: the near list, and the value a flip gives,
+                       against hand-evaluated compositing.
   backward          -- two-Gaussian closed-form derivatives; central finite
-                       differences of the forward with frozen decisions.
+                       differences of the forward with frozen decisions; under
+                       flips, against hand-evaluated derivatives and against the
+                       unflipped adjoint of the scene moved across the threshold.
+  visible           -- hand cases at the image border; independence of the tile shape.
   loss_l1, adam     -- textbook closed forms.
   uv_prune          -- axis directions and the theta = pi / phi = pi edges of the UV equation;
                        numpy brute force (arctan2, arccos, lexsort) for the pixels and ranks.
@@ -44,7 +52,7 @@ PROJ_DTYPE = np.dtype([
     ("valid", "<i4"), ("radius", "<i4"), ("rect", "<i4", (4,)), ("key", "<u4"), ("pad", "<u4"),
     ("z", "<f8"), ("mean", "<f8", (2,)), ("cov2d", "<f8", (3,)), ("det", "<f8"),
     ("conic", "<f8", (3,)), ("opacity", "<f8"), ("color", "<f8", (3,)), ("color_raw", "<f8", (3,)),
-    ("tile_mask", "<u8"), ("n_tiles", "<i8"),
+    ("visible", "<i4"), ("pad2", "<i4"), ("n_tiles", "<i8"),
 ])
 INST_DTYPE = np.dtype([("tile", "<i8"), ("key", "<u4"), ("id", "<i4")])
 CAM_DTYPE = np.dtype([
@@ -385,11 +393,13 @@ class Forward:
         return self.params.shape[2]
 
     def visible(self) -> np.ndarray:
-        """(F, N) uint8: Gaussian drawn (valid) in at least one view."""
+        """(F, N) uint8: the set sparse Adam updates -- Gaussians that survive the
+        z and det culls in at least one view with a pixel of that view within r
+        of the mean on both axes (independent of the tile shape)."""
         F = self.params.shape[0]
         vis = np.zeros((F, self.n_gauss), np.uint8)
         for v in self.views:
-            vis[self.scene.cams[v].frame] |= self.proj[v]["valid"].astype(np.uint8)
+            vis[self.scene.cams[v].frame] |= self.proj[v]["visible"].astype(np.uint8)
         return vis
 
     def loss(self, targets: dict):

@@ -59,7 +59,7 @@ typedef struct {
 } or_camera;
 
 typedef struct {
-    int32_t valid;        /* survived z / det culls and touches >= 1 tile */
+    int32_t valid;        /* survived the z / det culls and its tile rectangle is not empty */
     int32_t radius;       /* ceil(3 sqrt(lambda_max)) */
     int32_t rect[4];      /* x_lo, y_lo, x_hi, y_hi inclusive tile indices */
     uint32_t key;         /* bit pattern of fp32(z_c) */
@@ -72,8 +72,10 @@ typedef struct {
     double opacity;
     double color[3];      /* max(0, raw) */
     double color_raw[3];  /* 0.5 + sum_j Y_j k_j */
-    uint64_t tile_mask;   /* rectangles of <= 64 tiles: bit (ty - y_lo) w + (tx - x_lo) set for the kept tiles */
-    int64_t n_tiles;      /* tiles the Gaussian is listed in */
+    int32_t visible;      /* survived the z / det culls and the square of half-side r around the mean
+                             reaches a pixel of the image (the rectangle with one-pixel tiles) */
+    int32_t pad2;
+    int64_t n_tiles;      /* tiles of the rectangle: the Gaussian is listed in every one */
 } or_proj;
 
 typedef struct {
@@ -275,51 +277,6 @@ static void camera_centre(const or_camera* cam, double cw[3]) {
     for (int k = 0; k < 3; k++) cw[k] = -((R[k] * cam->t[0] + R[3 + k] * cam->t[1]) + R[6 + k] * cam->t[2]);
 }
 
-/* Tile culling by the ellipse itself.  A tile of the rectangle is kept when
- * the smallest q over the rectangle spanned by its pixel centres is at most
- * 9 + 1e-3 (the margin covers the compositor's FP32 evaluation of q): zero
- * when the mean lies inside, else the least of the four edge minima, each the
- * parabola on that edge at its clamped vertex.  Rectangles of more than 64
- * tiles keep every tile.  The tile lists are a superset of the tiles holding
- * a pixel with q <= 9, so the image is unchanged (tiled == brute force). */
-#define OR_MASK_TILES 64
-#define OR_QCULL 9.001
-
-static double q_at(double A, double B, double C, double X, double Y) {
-    return (A * X * X + 2.0 * B * X * Y) + C * Y * Y;
-}
-
-static void tile_cull(or_proj* o, int32_t tw, int32_t th) {
-    const int32_t w = o->rect[2] - o->rect[0] + 1, h = o->rect[3] - o->rect[1] + 1;
-    o->tile_mask = 0;
-    if ((int64_t)w * h > OR_MASK_TILES) {
-        o->n_tiles = (int64_t)w * h;
-        return;
-    }
-    const double A = o->conic[0], B = o->conic[1], C = o->conic[2];
-    /* on the edge x = X the parabola q(X, y) has its vertex at y = (-B / C) X;
-     * on y = Y, at x = (-B / A) Y */
-    const double ky = -B / C, kx = -B / A;
-    int64_t n = 0;
-    for (int32_t ty = o->rect[1]; ty <= o->rect[3]; ty++)
-        for (int32_t tx = o->rect[0]; tx <= o->rect[2]; tx++) {
-            const double X0 = ((double)tx * tw + 0.5) - o->mean[0], X1 = X0 + (double)(tw - 1);
-            const double Y0 = ((double)ty * th + 0.5) - o->mean[1], Y1 = Y0 + (double)(th - 1);
-            double qmin = 0.0;
-            if (!(X0 <= 0.0 && X1 >= 0.0 && Y0 <= 0.0 && Y1 >= 0.0)) {
-                const double ya = fmin(fmax(ky * X0, Y0), Y1), yb = fmin(fmax(ky * X1, Y0), Y1);
-                const double xa = fmin(fmax(kx * Y0, X0), X1), xb = fmin(fmax(kx * Y1, X0), X1);
-                qmin = fmin(fmin(q_at(A, B, C, X0, ya), q_at(A, B, C, X1, yb)),
-                            fmin(q_at(A, B, C, xa, Y0), q_at(A, B, C, xb, Y1)));
-            }
-            if (qmin <= OR_QCULL) {
-                o->tile_mask |= (uint64_t)1 << ((ty - o->rect[1]) * w + (tx - o->rect[0]));
-                n++;
-            }
-        }
-    o->n_tiles = n;
-}
-
 static void project_one(const double* P, int64_t N, int64_t i, int32_t L, const or_camera* cam,
                         int32_t tw, int32_t th, or_proj* o) {
     memset(o, 0, sizeof *o);
@@ -361,11 +318,17 @@ static void project_one(const double* P, int64_t N, int64_t i, int32_t L, const 
         o->color_raw[ch] = 0.5 + acc;
         o->color[ch] = o->color_raw[ch] > 0.0 ? o->color_raw[ch] : 0.0;
     }
+    /* Visibility, the set sparse Adam updates: the rectangle the same formula
+     * gives with one-pixel tiles is not empty, i.e. some pixel of the image lies
+     * within r of the mean on both axes.  It does not depend on the tile shape. */
+    const double pxlo = fmax(0.0, floor(o->mean[0] - rr)), pxhi = fmin((double)(cam->width - 1), floor(o->mean[0] + rr));
+    const double pylo = fmax(0.0, floor(o->mean[1] - rr)), pyhi = fmin((double)(cam->height - 1), floor(o->mean[1] + rr));
+    o->visible = pxlo <= pxhi && pylo <= pyhi;
     if (xlo > xhi || ylo > yhi) return;
     o->rect[0] = (int32_t)xlo; o->rect[1] = (int32_t)ylo;
     o->rect[2] = (int32_t)xhi; o->rect[3] = (int32_t)yhi;
-    tile_cull(o, tw, th);
-    o->valid = o->n_tiles > 0;
+    o->n_tiles = (int64_t)(o->rect[2] - o->rect[0] + 1) * (o->rect[3] - o->rect[1] + 1);
+    o->valid = 1;
 }
 
 void or_project(const double* P, int64_t N, int32_t C, int32_t L, const or_camera* cam,
@@ -378,14 +341,6 @@ void or_project(const double* P, int64_t N, int32_t C, int32_t L, const or_camer
 
 static int64_t n_tiles_of(const or_proj* p) { return p->valid ? p->n_tiles : 0; }
 
-/* Is tile (tx, ty) kept for Gaussian p (see tile_cull)? */
-static int tile_kept(const or_proj* p, int32_t tx, int32_t ty) {
-    const int32_t w = p->rect[2] - p->rect[0] + 1, h = p->rect[3] - p->rect[1] + 1;
-    if ((int64_t)w * h > OR_MASK_TILES) return 1;
-    const int32_t bit = (ty - p->rect[1]) * w + (tx - p->rect[0]);
-    return (int)((p->tile_mask >> bit) & 1u);
-}
-
 int64_t or_count_instances(const or_proj* pr, int64_t N) {
     int64_t s = 0;
     for (int64_t i = 0; i < N; i++) s += n_tiles_of(&pr[i]);
@@ -393,7 +348,7 @@ int64_t or_count_instances(const or_proj* pr, int64_t N) {
 }
 
 /* ------------------------------------------------------------------ bin + sort
- * Each surviving Gaussian is listed in every kept tile of its rectangle; lists are
+ * Each surviving Gaussian is listed in every tile of its rectangle; lists are
  * ordered by (tile, depth key, id) -- front to back by camera-space depth,
  * equal depths by ascending id. */
 
@@ -414,7 +369,6 @@ void or_bin_sort(const or_proj* pr, int64_t N, const or_camera* cam, int32_t tw,
         if (!pr[i].valid) continue;
         for (int32_t ty = pr[i].rect[1]; ty <= pr[i].rect[3]; ty++)
             for (int32_t tx = pr[i].rect[0]; tx <= pr[i].rect[2]; tx++) {
-                if (!tile_kept(&pr[i], tx, ty)) continue;
                 inst[k].tile = (int64_t)ty * TX + tx;
                 inst[k].key = pr[i].key;
                 inst[k].id = (int32_t)i;
@@ -564,8 +518,8 @@ void or_render(const or_proj* P, const or_camera* cam, int32_t tw, int32_t th, c
     if (counts) { counts[0] = ev; counts[1] = co; }
 }
 
-/* Brute force: every surviving Gaussian of the view, ordered by (depth key, id),
- * visits every pixel; no tiles. */
+/* Brute force: every Gaussian that survived the z and det culls, ordered by
+ * (depth key, id), visits every pixel; no tiles and no rectangles. */
 typedef struct { uint32_t key; int32_t id; } or_kid;
 static int kid_cmp(const void* a, const void* b) {
     const or_kid* x = (const or_kid*)a;
@@ -579,7 +533,7 @@ void or_render_brute(const or_proj* P, int64_t N, const or_camera* cam, const do
     or_kid* kid = (or_kid*)malloc(sizeof(or_kid) * (size_t)(N ? N : 1));
     int64_t m = 0;
     for (int64_t i = 0; i < N; i++)
-        if (P[i].valid) { kid[m].key = P[i].key; kid[m].id = (int32_t)i; m++; }
+        if (P[i].radius > 0) { kid[m].key = P[i].key; kid[m].id = (int32_t)i; m++; }
     qsort(kid, (size_t)m, sizeof(or_kid), kid_cmp);
     int32_t* list = (int32_t*)malloc(sizeof(int32_t) * (size_t)(m ? m : 1));
     for (int64_t j = 0; j < m; j++) list[j] = kid[j].id;
@@ -1134,6 +1088,10 @@ int64_t or_regularisers(const double* P, int32_t F, int32_t C, int64_t N, const 
  * D is OR-ed in place, so calling this for each camera of a frame gives the
  * paper's OR across cameras.
  *   mask  uint8 [H][W] of this camera;  D  uint8 [N] in/out */
+static double q_at(double A, double B, double C, double X, double Y) {
+    return (A * X * X + 2.0 * B * X * Y) + C * Y * Y;
+}
+
 void or_flow_mask(const double* P, int64_t N, int32_t L, const or_camera* cam, const uint8_t* mask,
                   uint8_t* D) {
     const int32_t W = cam->width, H = cam->height;

@@ -45,7 +45,17 @@ class pg_views_info(C.Structure):
                 ("lds_batch", C.c_int32), ("reserved", C.c_int32)]
 
 
-assert C.sizeof(pg_camera) == 144 and C.sizeof(pg_views_info) == 72
+PLAN_FIELDS = ["params", "gauss_texel", "texel_gauss", "n_gauss", "fetch_ws", "visible", "splats", "bins",
+               "tile_sets", "keys", "values", "tile_ranges", "tile_order", "inst_first", "n_inst", "overflow",
+               "sort_ws", "inst_grad", "image", "final_T", "n_contrib", "tile_entries", "entries", "dL_dimage",
+               "grad2d", "dL_datlas", "total"]
+
+
+class pg_plan(C.Structure):
+    _fields_ = [(f, C.c_size_t) for f in PLAN_FIELDS]
+
+
+assert C.sizeof(pg_camera) == 144 and C.sizeof(pg_views_info) == 72 and C.sizeof(pg_plan) == 8 * 27
 
 _lib = None
 
@@ -68,6 +78,10 @@ SIGNATURES = {
     "pg_render_fwd": (_i32, [_p, _p, _p, _p, _p, _p, _p, _p, _p, _p, _p, _p, _p]),
     "pg_render_bwd": (_i32, [_p, _p, _p, _p, _p, _p, _p, _p, _i64, _p, _p, _p, _p, _p, _p, _p, _p]),
     "pg_project_bwd": (_i32, [_p, _p, _p, _p, _p, _i64, _p, _p, _p, _i32, _i32, _p, _p, _i32, _p]),
+    "pg_backward": (_i32, [_p, _p, _p, _p, _p, _p, _p, _p, _p, _p, _i64, _p, _p, _p, _p, _p, _p, _p, _p, _p, _i32,
+                           _i32, _p, _p, _i32, _p]),
+    "pg_status_check": (_i32, [_p, _p, _p, _p]),
+    "pg_workspace_query": (_i32, [_p, _i32, _i32, _i64, C.POINTER(pg_plan)]),
     "pg_loss_l1": (_i32, [_p, _p, _i64, _p, _p, _p, _p]),
     "pg_photo_workspace_size": (_i32, [_p, C.POINTER(_sz)]),
     "pg_uv_prune_workspace_size": (_i32, [_i64, _i32, _i32, _i32, C.POINTER(_sz)]),
@@ -254,6 +268,37 @@ def pg_project_bwd(views, params, bins, inst_first, n_inst_dev, inst_capacity, i
                                 int(inst_capacity), _ptr(inst_grad), _ptr(gauss_texel),
                                 _ptr(dynamic_mask), int(H), int(W), _ptr(grad2d), _ptr(dL_datlas), int(accumulate),
                                 _stream(stream)), "pg_project_bwd")
+
+
+def pg_backward(views, params, splats, bins, tiles, values, tile_ranges, tile_order, inst_first, n_inst_dev,
+                inst_capacity, tile_entries, entries, n_contrib, bg, final_T, dL_dimage, inst_grad, gauss_texel,
+                dynamic_mask, H, W, grad2d, dL_datlas, accumulate, stream=None):
+    bgv = (C.c_float * 3)(*[float(b) for b in bg])
+    _check(lib().pg_backward(views, _ptr(params), _ptr(splats), _ptr(bins), _ptr(tiles), _ptr(values),
+                             _ptr(tile_ranges), _ptr(tile_order), _ptr(inst_first), _ptr(n_inst_dev),
+                             int(inst_capacity), _ptr(tile_entries), _ptr(entries), _ptr(n_contrib), C.addressof(bgv),
+                             _ptr(final_T), _ptr(dL_dimage), _ptr(inst_grad), _ptr(gauss_texel), _ptr(dynamic_mask),
+                             int(H), int(W), _ptr(grad2d), _ptr(dL_datlas), int(accumulate), _stream(stream)),
+           "pg_backward")
+
+
+PG_ERR_CAPACITY = -3
+
+
+def pg_status_check(overflow_dev, n_inst_dev, stream=None):
+    """(overflowed, needed capacity); synchronises the stream.  Errors other
+    than PG_ERR_CAPACITY raise."""
+    need = C.c_int64()
+    st = lib().pg_status_check(_ptr(overflow_dev), _ptr(n_inst_dev), C.byref(need), _stream(stream))
+    if st not in (PG_OK, PG_ERR_CAPACITY):
+        _check(st, "pg_status_check")
+    return st == PG_ERR_CAPACITY, int(need.value)
+
+
+def pg_workspace_query(views, H, W, inst_capacity) -> dict:
+    plan = pg_plan()
+    _check(lib().pg_workspace_query(views, int(H), int(W), int(inst_capacity), C.byref(plan)), "pg_workspace_query")
+    return {f: int(getattr(plan, f)) for f in PLAN_FIELDS}
 
 
 def pg_loss_l1(image, target, n, dL_dimage, partial, loss_dev, stream=None):

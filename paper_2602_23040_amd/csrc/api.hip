@@ -329,6 +329,103 @@ pg_status pg_project_bwd(const pg_views* v, const float* params, const pg_bin* b
     return PG_OK;
 }
 
+pg_status pg_backward(const pg_views* v, const float* params, const pg_splat* splats, const pg_bin* bins,
+                      const pg_tile_set* tiles, const int32_t* values, const int32_t* tile_ranges,
+                      const int32_t* tile_order, const int32_t* inst_first, const int64_t* n_inst_dev,
+                      int64_t inst_capacity, const int32_t* tile_entries, const uint32_t* entries,
+                      const int32_t* n_contrib, const float* bg, const float* final_T, const float* dL_dimage,
+                      float* inst_grad, const int32_t* gauss_texel, const uint8_t* dynamic_mask, int32_t H, int32_t W,
+                      float* grad2d, float* dL_datlas, int32_t accumulate, void* stream) {
+    g_error.clear();
+    if (!v || !bg) return invalid("null argument");
+    if (!tile_ranges || !tile_entries || !n_contrib || !final_T || !dL_dimage || !n_inst_dev || !dL_datlas)
+        return invalid("null pointer argument");
+    if (v->n_gv > 0 && (!params || !splats || !bins || !tiles || !values || !inst_first || !entries || !inst_grad ||
+                        !gauss_texel || !grad2d))
+        return invalid("null pointer argument");
+    if (inst_capacity < 0 || inst_capacity > INT32_MAX) return invalid("inst_capacity must be in [0, 2^31 - 1]");
+    if (H < 1 || W < 1 || (int64_t)H * W < v->n_gauss) return invalid("H * W must hold n_gauss texels");
+    if (accumulate != 0 && accumulate != 1) return invalid("accumulate must be 0 or 1");
+    hipStream_t s = (hipStream_t)stream;
+    PG_CHECK_HIP(launch_render_bwd(v, splats, tiles, values, tile_ranges, tile_order, inst_first, tile_entries, entries,
+                                   n_contrib, bg, final_T, dL_dimage, n_inst_dev, inst_capacity, inst_grad, s),
+                 "pg_backward (compositing adjoint)");
+    PG_CHECK_HIP(launch_slot_sum(v, bins, inst_first, n_inst_dev, inst_capacity, inst_grad, grad2d, s),
+                 "pg_backward (slot sums)");
+    PG_CHECK_HIP(launch_project_bwd(v, params, grad2d, gauss_texel, dynamic_mask, H, W, dL_datlas, accumulate, s),
+                 "pg_backward (projection adjoint)");
+    return PG_OK;
+}
+
+pg_status pg_status_check(const int32_t* overflow_dev, const int64_t* n_inst_dev, int64_t* needed_capacity,
+                          void* stream) {
+    g_error.clear();
+    if (!overflow_dev || !n_inst_dev) return invalid("null pointer argument");
+    hipStream_t s = (hipStream_t)stream;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    PG_CHECK_HIP(hipStreamIsCapturing(s, &cs), "pg_status_check (hipStreamIsCapturing)");
+    if (cs != hipStreamCaptureStatusNone)
+        return invalid("pg_status_check synchronises the stream: call it after a graph replay, not during capture");
+    int32_t ovf = 0;
+    int64_t need = 0;
+    PG_CHECK_HIP(hipMemcpyAsync(&ovf, overflow_dev, sizeof ovf, hipMemcpyDeviceToHost, s), "pg_status_check (copy)");
+    PG_CHECK_HIP(hipMemcpyAsync(&need, n_inst_dev, sizeof need, hipMemcpyDeviceToHost, s), "pg_status_check (copy)");
+    PG_CHECK_HIP(hipStreamSynchronize(s), "pg_status_check (synchronise)");
+    if (needed_capacity) *needed_capacity = need;
+    if (ovf) {
+        set_error("instance capacity overflow: " + std::to_string(need) + " instances needed");
+        return PG_ERR_CAPACITY;
+    }
+    return PG_OK;
+}
+
+pg_status pg_workspace_query(const pg_views* v, int32_t H, int32_t W, int64_t inst_capacity, pg_plan* plan) {
+    g_error.clear();
+    if (!v || !plan) return invalid("null argument");
+    if (H < 1 || W < 1 || (int64_t)H * W < v->n_gauss) return invalid("H * W must hold n_gauss texels");
+    if ((int64_t)H * W > INT32_MAX) return invalid("H * W exceeds 2^31 - 1");
+    if (inst_capacity < 0 || inst_capacity > INT32_MAX) return invalid("inst_capacity must be in [0, 2^31 - 1]");
+    std::memset(plan, 0, sizeof *plan);
+    const size_t F = (size_t)v->frames, C = (size_t)v->channels, N = (size_t)v->n_gauss;
+    const size_t HW = (size_t)H * W, gv = (size_t)v->n_gv, T = (size_t)v->n_tiles, P = (size_t)v->n_pixels;
+    const size_t cap = (size_t)inst_capacity;
+    plan->params = F * C * N * sizeof(float);
+    plan->gauss_texel = N * sizeof(int32_t);
+    plan->texel_gauss = HW * sizeof(int32_t);
+    plan->n_gauss = sizeof(int64_t);
+    plan->fetch_ws = fetch_ws_bytes(H, W);
+    plan->visible = F * N;
+    plan->splats = gv * sizeof(pg_splat);
+    plan->bins = gv * sizeof(pg_bin);
+    plan->tile_sets = gv * sizeof(pg_tile_set);
+    plan->keys = cap * sizeof(uint32_t);
+    plan->values = cap * sizeof(int32_t);
+    plan->tile_ranges = 2 * T * sizeof(int32_t);
+    plan->tile_order = T * sizeof(int32_t);
+    plan->inst_first = gv * sizeof(int32_t);
+    plan->n_inst = sizeof(int64_t);
+    plan->overflow = sizeof(int32_t);
+    plan->sort_ws = sort_ws_bytes(v, inst_capacity);
+    plan->inst_grad = 9 * cap * sizeof(float);
+    plan->image = 3 * P * sizeof(float);
+    plan->final_T = P * sizeof(float);
+    plan->n_contrib = P * sizeof(int32_t);
+    plan->tile_entries = T * sizeof(int32_t);
+    plan->entries = cap * sizeof(uint32_t);
+    plan->dL_dimage = 3 * P * sizeof(float);
+    plan->grad2d = 9 * gv * sizeof(float);
+    plan->dL_datlas = F * C * HW * sizeof(float);
+    const size_t parts[] = {plan->params, plan->gauss_texel, plan->texel_gauss, plan->n_gauss, plan->fetch_ws,
+                            plan->visible, plan->splats, plan->bins, plan->tile_sets, plan->keys, plan->values,
+                            plan->tile_ranges, plan->tile_order, plan->inst_first, plan->n_inst, plan->overflow,
+                            plan->sort_ws, plan->inst_grad, plan->image, plan->final_T, plan->n_contrib,
+                            plan->tile_entries, plan->entries, plan->dL_dimage, plan->grad2d, plan->dL_datlas};
+    size_t total = 0;
+    for (size_t b : parts) total += align256(b);
+    plan->total = total;
+    return PG_OK;
+}
+
 pg_status pg_loss_l1(const float* image, const float* target, int64_t n, float* dL_dimage, double* partial,
                      float* loss_dev, void* stream) {
     g_error.clear();

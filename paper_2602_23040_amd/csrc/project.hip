@@ -223,8 +223,10 @@ __device__ __forceinline__ void sh_grad_dot_f(float x, float y, float z, const f
 // the mean lies inside, else the least of the four edge minima, each the
 // parabola on that edge at its clamped vertex (on x = X the vertex is at
 // y = (-B / C) X, on y = Y at x = (-B / A) Y).  Rectangles of more than
-// kMaskTiles tiles keep every tile.  Same FP64 operations in the same order
-// as the independent reference, so the kept sets agree bit for bit.
+// kMaskTiles tiles keep every tile.  This is an optimisation of the method's
+// tile lists (every tile of the rectangle): a dropped tile has q > 9 at every
+// pixel centre, so no pixel of it would composite the Gaussian, and the image
+// and gradients do not change.
 constexpr int kMaskTiles = 64;
 constexpr double kQCull = 9.001;
 constexpr int kProjBlk = 128;
@@ -315,6 +317,10 @@ __global__ __launch_bounds__(kProjBlk) void k_project(const ViewDev* __restrict_
             const double rr = ceil(3.0 * sqrt(lam));
             mx = (V.fx * c.xc) / c.zc + V.cx;
             my = (V.fy * c.yc) / c.zc + V.cy;
+            // visibility (the set sparse Adam updates): some pixel of the image lies
+            // within r of the mean on both axes; independent of the tile shape and of
+            // the tile culling below
+            if (mx + rr >= 0.0 && mx - rr < (double)V.W && my + rr >= 0.0 && my - rr < (double)V.H) any = true;
             // the view table only admits tile sides of 8, 16 or 32: dividing by a power of
             // two is exactly multiplying by its reciprocal, so these equal the divisions
             const double xlo = fmax(0.0, floor((mx - rr) * itw));
@@ -400,7 +406,6 @@ __global__ __launch_bounds__(kProjBlk) void k_project(const ViewDev* __restrict_
             bo.w = (uint32_t)nt;
             ts = make_uint4((uint32_t)tmask, (uint32_t)(tmask >> 32), bo.x,
                             (uint32_t)(ixh - ixl + 1) | ((uint32_t)(iyh - iyl + 1) << 16));
-            any = true;
         } else {
             bo = make_uint4(0u, 0u, 0u, 0u);
         }

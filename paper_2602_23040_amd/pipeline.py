@@ -18,6 +18,20 @@ in one of two modes over the same kernels:
   count (one synchronisation per view) before compositing it.
 
 ``PackUVRender`` wraps the forward and adjoint as a ``torch.autograd.Function``.
+
+Instance capacity.  How many (Gaussian, tile) instances a step needs is
+decided on the device.  A sort that would exceed the capacity sets the
+overflow flag and leaves the step's outputs undefined (background images,
+zero gradient).  The protocol is the C ABI's: ``pg_status_check`` after the
+step reports the count that suffices, the caller grows the instance buffers
+and runs the step again.
+
+* Eager steps do this by themselves.  ``forward`` checks after the sort
+  (one synchronisation) and, after an overflow, grows and renders again, so
+  an eager image is never the undefined one.
+* A captured step cannot synchronise.  The caller calls ``check()`` (or
+  ``ensure_capacity()``) after each replay and re-captures after a growth,
+  because the graph holds the old buffers.
 """
 from __future__ import annotations
 
@@ -121,8 +135,9 @@ class Renderer:
         self.loss_partial = torch.empty(1024, dtype=torch.float64, device=dev)
         self.loss = torch.zeros(1, dtype=torch.float32, device=dev)
         if inst_capacity is None:
-            # first guess; an overflow reports the count that suffices (grow_capacity)
-            inst_capacity = 8 * max(self.N, 1) * (self.V if batched else 1)
+            # first guess (about the tile count of a Gaussian at the 50-view workload);
+            # the first eager forward reports the count that suffices and grows to it
+            inst_capacity = max(4096, 2 * max(self.N, 1) * (self.V if batched else 1))
         if batched:
             self.sets = [_ViewSet(self.cams, self.frames, self.N, self.sh_degree, self.tiling, dev, inst_capacity)]
             self.pix_base = self.sets[0].pix_base
@@ -144,6 +159,11 @@ class Renderer:
         self.adam_t = None           # device step counter of the Adam update
         self._photo = None           # (view table, workspace, bytes, own table) of the photometric loss
         self.reg_loss = None         # (L_scale, L_opacity) of the last regulariser call
+        # eager forward: read the overflow flag after the chain and, after an overflow,
+        # grow the instance buffers and render again (one synchronisation per forward).
+        # Never done under graph capture, where check() after each replay does it.
+        self.check_overflow = True
+        self.generation = 0          # forwards run so far (PackUVRender ties a backward to its forward)
 
     # ------------------------------------------------------------------ helpers
     def close(self):
@@ -172,15 +192,43 @@ class Renderer:
     def _off(self, t, elems):
         return t.data_ptr() + elems * t.element_size()
 
-    def grow_capacity(self, factor=1.25):
-        """Re-size instance buffers from the last counts (after an overflow)."""
-        for s in self.sets:
-            need = int(s.n_inst.item())
-            if need > s.cap:
-                s.set_capacity(int(math.ceil(need * factor)))
+    def status(self):
+        """[(overflowed, instances needed)] of each view set's last sort, from
+        pg_status_check (synchronises the current stream)."""
+        return [abi.pg_status_check(s.overflow, s.n_inst) for s in self.sets]
+
+    def check(self) -> bool:
+        """True when no view set's last sort overflowed; call it after each
+        replay of a captured step (an overflowed replay's outputs are undefined)."""
+        return not any(ovf for ovf, _ in self.status())
+
+    def grow_capacity(self, factor=1.25, headroom=False) -> bool:
+        """Re-size the instance buffers from the last sort's counts: to
+        ceil(need * factor) where it overflowed, or, with headroom=True,
+        wherever need * factor exceeds the capacity (room for counts that grow,
+        e.g. while Adam moves the Gaussians between replays).  Returns True
+        when a buffer was re-allocated (a captured step must then be captured
+        again)."""
+        grew = False
+        for s, (ovf, need) in zip(self.sets, self.status()):
+            want = int(math.ceil(need * factor))
+            if ovf or (headroom and want > s.cap):
+                s.set_capacity(max(want, need, 1))
+                grew = True
+        return grew
+
+    def ensure_capacity(self, headroom=1.25) -> bool:
+        """After an overflow, grow to ceil(need * headroom); see grow_capacity."""
+        return self.grow_capacity(headroom)
 
     def overflowed(self) -> bool:
-        return any(int(s.overflow.item()) for s in self.sets)
+        return not self.check()
+
+    def plan(self, inst_capacity=None) -> dict:
+        """pg_workspace_query for the batched view table: bytes of every buffer
+        of one step (host only)."""
+        s = self.sets[0]
+        return abi.pg_workspace_query(s.handle, self.H, self.W, s.cap if inst_capacity is None else inst_capacity)
 
     # ------------------------------------------------------------------ stages
     def fetch(self, atlas: torch.Tensor):
@@ -211,8 +259,7 @@ class Renderer:
                           self._off(self.final_T, pix_off), self._off(self.n_contrib, pix_off), s.tile_entries,
                           s.entries, counters)
 
-    def forward(self, atlas: torch.Tensor, counters: bool = False) -> torch.Tensor:
-        """Render every view; returns the flat image buffer (valid until the next call)."""
+    def _forward_chain(self, atlas, counters):
         self.fetch(atlas)
         self.visible.zero_()
         cnt = self.counters if counters else None
@@ -220,6 +267,24 @@ class Renderer:
             self.counters.zero_()
         for k, s in enumerate(self.sets):
             self._project_sort_render(s, self.pix_base[k] if not self.batched else 0, cnt)
+
+    def forward(self, atlas: torch.Tensor, counters: bool = False, check=None) -> torch.Tensor:
+        """Render every view; returns the flat image buffer (valid until the next call).
+
+        check (default: self.check_overflow) reads the overflow flag after the
+        chain and, after an overflow, grows the instance buffers and renders
+        again.  Under graph capture nothing is read: call check() after the
+        replay."""
+        self.generation += 1
+        self._forward_chain(atlas, counters)
+        # the plain path with per-view synchronisation has already grown every view's buffers
+        checked = not self.batched and self.plain_sync
+        if (self.check_overflow if check is None else check) and not checked \
+                and not torch.cuda.is_current_stream_capturing():
+            if self.ensure_capacity():
+                self._forward_chain(atlas, counters)
+                if not self.check():
+                    raise RuntimeError("instance capacity overflowed again after growing to the reported count")
         return self.image
 
     def flow_mask(self, atlas: torch.Tensor, masks: torch.Tensor, counters=None):
@@ -284,10 +349,10 @@ class Renderer:
         assert g.is_contiguous() and g.numel() == 3 * self.n_pixels
         if self.batched:
             s = self.sets[0]
-            abi.pg_render_bwd(s.handle, s.splats, s.tiles, s.values, s.ranges, self._order(s), s.inst_first, s.n_inst, s.cap,
-                              s.tile_entries, s.entries, self.n_contrib, self.bg, self.final_T, g, s.inst_grad)
-            abi.pg_project_bwd(s.handle, self.params, s.bins, s.inst_first, s.n_inst, s.cap,
-                               s.inst_grad, self.gauss_texel, self.dynamic, self.H, self.W, s.grad2d, self.dL_datlas, 0)
+            abi.pg_backward(s.handle, self.params, s.splats, s.bins, s.tiles, s.values, s.ranges, self._order(s),
+                            s.inst_first, s.n_inst, s.cap, s.tile_entries, s.entries, self.n_contrib, self.bg,
+                            self.final_T, g, s.inst_grad, self.gauss_texel, self.dynamic, self.H, self.W, s.grad2d,
+                            self.dL_datlas, 0)
         else:
             self.dL_datlas.zero_()
             for k, s in enumerate(self.sets):
@@ -352,17 +417,36 @@ class Renderer:
 
 
 class PackUVRender(torch.autograd.Function):
-    """images = PackUVRender.apply(atlas, renderer): flat image buffer of every view.
+    """images = PackUVRender.apply(atlas, renderer): the flat image buffer of
+    every view (view v's [3][H_v][W_v] image at offset 3 renderer.pix_base[v]).
 
-    The backward returns dL/datlas (with the renderer's gradient-freeze mask
-    applied) and nothing for the renderer."""
+    The backward runs the hand-written adjoint (pg_backward: transmittance
+    recomputed from the stored final T, gradient freezing with the renderer's
+    mask) and returns dL/datlas in the atlas's shape, and nothing for the
+    renderer.
+
+    The forward always checks the instance capacity (growing and rendering
+    again after an overflow), so it never returns the undefined output of an
+    overflowed sort; for that reason it cannot run under graph capture
+    (capture Renderer.step instead and call Renderer.check() after each
+    replay).  A renderer holds one step's buffers: the backward raises if the
+    renderer has run another forward since this one."""
 
     @staticmethod
     def forward(ctx, atlas, renderer):
+        if torch.cuda.is_current_stream_capturing():
+            raise RuntimeError("PackUVRender cannot be captured: the instance capacity is only known after the "
+                               "step has run; capture Renderer.step and call Renderer.check() after each replay")
+        img = renderer.forward(atlas.detach().contiguous().reshape(-1), check=True)
         ctx.renderer = renderer
-        return renderer.forward(atlas.contiguous()).clone()
+        ctx.generation = renderer.generation
+        ctx.atlas_shape = atlas.shape
+        return img.clone()
 
     @staticmethod
     def backward(ctx, grad):
-        return ctx.renderer.backward(grad.contiguous()).view(ctx.renderer.frames, ctx.renderer.C, ctx.renderer.H,
-                                                             ctx.renderer.W).clone(), None
+        r = ctx.renderer
+        if r.generation != ctx.generation:
+            raise RuntimeError("PackUVRender: the renderer ran another forward after this one; its buffers hold "
+                               "the later step, so this backward cannot be computed")
+        return r.backward(grad.contiguous()).clone().view(ctx.atlas_shape), None

@@ -2,8 +2,15 @@
 the same seeded scene and compare them.
 
 Comparison rules:
-  * discrete outputs (Gaussian ids, culls, tile rectangles, depth keys, sorted
-    instance lists, tile ranges) must be bit-identical;
+  * discrete outputs (Gaussian ids, culls, tile rectangles, depth keys, tile
+    ranges) must be bit-identical;
+  * tile lists: the oracle lists every tile of a rectangle; the GPU drops the
+    tiles whose pixel centres all lie outside the ellipse.  Each GPU list must
+    be the oracle's list with entries left out and the order kept, and every
+    left-out (Gaussian, tile) must have q > 9 at every pixel centre of the
+    tile inside the image (FP64 brute force from the oracle's mean and conic);
+  * n_contrib is compared after mapping the oracle's list positions onto the
+    GPU's lists, exactly on every pixel not explained by a flip;
   * projected floats within 1e-6 relative of the FP64 oracle;
   * images and final transmittance within 1e-4 absolute per pixel, except
     pixels "explained" by taking at most two of the oracle's near-threshold
@@ -45,13 +52,11 @@ def atlas_tensor(scene):
 
 
 def run_forward(r, atlas, counters=False):
+    """Eager forward; an overflow grows the buffers and renders again inside
+    Renderer.forward, so the step must end without one."""
     r.forward(atlas, counters=counters)
     torch.cuda.synchronize()
-    if r.overflowed():
-        r.grow_capacity()
-        r.forward(atlas, counters=counters)
-        torch.cuda.synchronize()
-    assert not r.overflowed()
+    assert r.check()
 
 
 def gpu_images(r):
@@ -71,14 +76,16 @@ def explain(fw, v, gpu_img, gpu_T=None, tol=IMG_TOL, band=BAND, max_pixels=20000
     A pixel is off when its colour (or, if gpu_T is given, its final
     transmittance) differs from the oracle's by more than tol; it is
     explained when taking at most two of the oracle's near-threshold
-    decisions the other way brings every compared value within tol."""
+    decisions the other way brings every compared value within tol.  More
+    than max_pixels off pixels in one view is a failure, not a sample."""
     cam = fw.scene.cams[v]
     err = np.abs(gpu_img - fw.image[v]).max(0)
     if gpu_T is not None:
         err = np.maximum(err, np.abs(gpu_T - fw.T[v]))
     ys, xs = np.nonzero(err > tol)
+    assert len(xs) <= max_pixels, f"view {v}: {len(xs)} pixels beyond {tol} (more than {max_pixels} to examine)"
     flips, unexplained = {}, []
-    for x, y in list(zip(xs, ys))[:max_pixels]:
+    for x, y in zip(xs, ys):
         _, _, _, near = oracle.pixel(fw.proj[v], cam, fw.tw, fw.th, fw.inst[v], fw.ranges[v], x, y, band=band,
                                      bg=fw.bg)
         found = None
@@ -126,3 +133,96 @@ def grad_compare(g, ref, mask=None, rel=1e-3, floor_frac=0.01):
     if bad_channels:
         out["bad_channels"] = bad_channels   # channel: (count, worst ratio, got, ref, channel max)
     return out
+
+
+def _q_outside_footprint(pr, cam, tw, th, tiles, ids, chunk=4096):
+    """Least FP64 q over the in-image pixel centres of tile tiles[k] for
+    Gaussian ids[k], minimised over k (inf for no pairs)."""
+    TX = (cam.width + tw - 1) // tw
+    lx, ly = np.arange(tw) + 0.5, np.arange(th) + 0.5
+    qmin = np.inf
+    for s0 in range(0, len(tiles), chunk):
+        t = np.asarray(tiles[s0:s0 + chunk], np.int64)
+        i = np.asarray(ids[s0:s0 + chunk], np.int64)
+        X = ((t % TX) * tw)[:, None] + lx[None, :]
+        Y = ((t // TX) * th)[:, None] + ly[None, :]
+        dx = (X - pr["mean"][i, 0][:, None])[:, None, :]
+        dy = (Y - pr["mean"][i, 1][:, None])[:, :, None]
+        a, b, c = (pr["conic"][i, k][:, None, None] for k in range(3))
+        q = a * dx * dx + 2.0 * b * dx * dy + c * dy * dy
+        inside = (X < cam.width)[:, None, :] & (Y < cam.height)[:, :, None]
+        q = np.where(inside, q, np.inf)
+        qmin = min(qmin, float(q.min()))
+    return qmin
+
+
+def check_tile_lists(fw, v, keys, vals, tile_base, N):
+    """View v's sorted GPU instances (keys: global tile ids ascending, vals:
+    v N + Gaussian id) against the oracle's tile lists, which hold every tile
+    of each rectangle.  Asserts that each GPU list is the oracle's with some
+    entries left out and the order kept, and that every left-out
+    (Gaussian, tile) has q > 9 at every pixel centre of the tile inside the
+    image.  Returns the oracle instances' kept flags."""
+    cam, inst = fw.scene.cams[v], fw.inst[v]
+    lo = int(np.searchsorted(keys, np.uint32(tile_base[v]), "left"))
+    hi = int(np.searchsorted(keys, np.uint32(tile_base[v + 1]), "left"))
+    gt = keys[lo:hi].astype(np.int64) - int(tile_base[v])
+    gi = vals[lo:hi].astype(np.int64) - v * N
+    assert gi.size == 0 or (gi.min() >= 0 and gi.max() < N), f"view {v}: GPU values outside the view's records"
+    ocode = (inst["tile"].astype(np.int64) << 28) | inst["id"].astype(np.int64)
+    gcode = (gt << 28) | gi
+    kept = np.isin(ocode, gcode)
+    assert np.array_equal(ocode[kept], gcode), f"view {v}: GPU tile lists are not order-kept sublists of the oracle's"
+    dropped = np.flatnonzero(~kept)
+    qmin = _q_outside_footprint(fw.proj[v], cam, fw.tw, fw.th, inst["tile"][dropped], inst["id"][dropped])
+    assert qmin > 9.0, f"view {v}: a dropped tile has a pixel centre with q = {qmin} <= 9"
+    say(f"[lists] view {v}: {len(inst)} oracle instances, {int(kept.sum())} kept by the GPU, "
+        f"{len(dropped)} dropped (least q over dropped tiles {qmin:.4f})")
+    return kept
+
+
+def gpu_n_contrib(fw, v, kept):
+    """The oracle's n_contrib of view v (1-based position of the last
+    composited Gaussian in the oracle's tile list) moved to positions in the
+    GPU's lists, which are the oracle's with the kept flags applied (the last
+    composited Gaussian has q <= 9, so it is always kept)."""
+    cam = fw.scene.cams[v]
+    TX = (cam.width + fw.tw - 1) // fw.tw
+    ck = np.concatenate([[0], np.cumsum(kept, dtype=np.int64)])
+    ys, xs = np.mgrid[0:cam.height, 0:cam.width]
+    start = fw.ranges[v][(ys // fw.th) * TX + xs // fw.tw, 0]
+    n = fw.n[v].astype(np.int64)
+    return np.where(n > 0, ck[start + n] - ck[start], 0)
+
+
+def check_records(fw, v, bins, tsets, splats, N):
+    """View v's projection records against the oracle: every record the GPU
+    lists is one the oracle lists, with the same rectangle and depth key; its
+    kept tiles lie in the rectangle (a mask of the rectangle's bits, or every
+    tile for rectangles of more than 64 tiles); culled records are zero; FP64
+    means are equal wherever the oracle projects the Gaussian."""
+    pr = fw.proj[v]
+    sl = slice(v * N, (v + 1) * N)
+    b, ts, s = bins[sl], tsets[sl], splats[sl]
+    valid = pr["valid"] == 1
+    listed = b["n_tiles"] > 0
+    assert np.all(valid[listed]), f"view {v}: the GPU lists a record the oracle culls"
+    assert np.array_equal(b["rect"][listed], pr["rect"][listed].astype(np.int16))
+    assert np.array_equal(b["key"][listed], pr["key"][listed])
+    w = pr["rect"][:, 2] - pr["rect"][:, 0] + 1
+    h = pr["rect"][:, 3] - pr["rect"][:, 1] + 1
+    area = (w * h).astype(np.int64)
+    assert np.array_equal(area[valid], pr["n_tiles"][valid])
+    assert np.all(b["n_tiles"][listed] <= area[listed])
+    small = listed & (area <= 64)
+    mask = ts["mask"]
+    assert np.array_equal(np.bitwise_count(mask[small]).astype(np.int64), b["n_tiles"][small].astype(np.int64))
+    assert np.all((mask[small] >> area[small].astype(np.uint64)) == 0), f"view {v}: kept tiles outside the rectangle"
+    big = listed & (area > 64)
+    assert np.all(mask[big] == 0) and np.array_equal(b["n_tiles"][big], area[big])
+    assert np.array_equal(ts["x_lo"][listed], pr["rect"][listed, 0]) and np.array_equal(ts["y_lo"][listed], pr["rect"][listed, 1])
+    assert np.array_equal(ts["width"][listed], w[listed]) and np.array_equal(ts["height"][listed], h[listed])
+    assert not ts.view(np.uint8).reshape(-1, 16)[~listed].any(), f"view {v}: culled tile sets not zero"
+    assert not b.view(np.uint8).reshape(-1, 16)[~listed].any(), f"view {v}: culled bins not zero"
+    assert np.array_equal(s["mean"][valid], pr["mean"][valid]), f"view {v}: FP64 means differ"
+    return valid, listed

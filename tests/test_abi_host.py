@@ -90,3 +90,18 @@ def test_fake_quant_rejects_bad_arguments_on_the_host():
     many = (C.c_int32 * 65)(*([8] * 65))
     assert lib.pg_atlas_fake_quant(dummy, dummy, 4, 1, 65, C.cast(many, C.c_void_p), dummy, None, dummy, None) == -1
     assert abi.lpo_bits(59) == [16, 16, 16] + [8] * 56
+
+
+def test_new_boundary_calls_reject_bad_arguments_on_the_host():
+    """pg_status_check, pg_workspace_query and pg_backward refuse null
+    arguments before any device work (the dummy pointers are never read)."""
+    lib = abi.lib()
+    need = C.c_int64(-7)
+    assert lib.pg_status_check(None, None, C.byref(need), None) == -1
+    assert "null" in abi.pg_last_error() and need.value == -7
+    plan = abi.pg_plan()
+    assert lib.pg_workspace_query(None, 64, 64, 1000, C.byref(plan)) == -1
+    args = [None] * 26
+    args[10], args[20], args[21], args[24] = 0, 1, 1, 0
+    assert lib.pg_backward(*args) == -1
+    assert "null" in abi.pg_last_error()

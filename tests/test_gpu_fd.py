@@ -1,8 +1,10 @@
 """GPU texel gradients against finite differences of the FP64 oracle on the
 ring-of-8 workload (256^2 atlas, 8 views of 512^2, SH 3): 64 visible
 Gaussians (seeded draw) on all 59 channels, plus 4 invisible ones that must
-read exactly zero.  Both sides take the same fixed image cotangent G, so the
-reference is d<G, I(theta)>/dtheta; the oracle's difference keeps its own
+read exactly zero.  The GPU gradient is atlas.grad of <G, images> through
+PackUVRender (the torch.autograd.Function around the forward and the
+hand-written adjoint).  Both sides take the same fixed image cotangent G, so
+the reference is d<G, I(theta)>/dtheta; the oracle's difference keeps its own
 footprint decisions fixed and is Richardson-extrapolated,
 (4 D(h/2) - D(h)) / 3 with h = 1e-3.  Acceptance: per element
 |g - d| <= 1e-3 max(|d|, 0.01 max over the channel |d|), and per channel
@@ -16,7 +18,8 @@ import torch
 
 import oracle
 import synth
-from parity import atlas_tensor, renderer, run_forward, say
+from paper_2602_23040_amd.pipeline import PackUVRender
+from parity import atlas_tensor, renderer, say
 
 pytestmark = pytest.mark.gpu
 
@@ -34,12 +37,14 @@ def test_texel_gradient_matches_oracle_finite_differences():
     rng = np.random.default_rng(402)
     G = {v: rng.standard_normal(fw.image[v].shape) for v in fw.views}
     r = renderer(sc, dynamic=None)
-    run_forward(r, atlas_tensor(sc))
+    # through the autograd function: atlas.grad of <G, images>
+    atlas = atlas_tensor(sc).reshape(sc.frames, sc.C, sc.H, sc.W).clone().requires_grad_()
+    img = PackUVRender.apply(atlas, r)
     g = torch.from_numpy(np.concatenate([G[v].reshape(-1) for v in fw.views]).astype(np.float32)).to("cuda:0")
-    r.backward(g)
+    (g * img).sum().backward()
     torch.cuda.synchronize()
     C = sc.C
-    got = r.dL_datlas.cpu().numpy().reshape(sc.frames, C, -1)[0][:, fw.ids].astype(np.float64)
+    got = atlas.grad.cpu().numpy().reshape(sc.frames, C, -1)[0][:, fw.ids].astype(np.float64)
     vis = fw.visible()[0].astype(bool)
     pick = rng.choice(np.flatnonzero(vis), 64, replace=False)
     hidden = np.flatnonzero(~vis)[:4]

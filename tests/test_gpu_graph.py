@@ -63,7 +63,7 @@ def test_graph_replays_with_adam_count_steps():
     re = renderer(sc)
     a_eager = atlas_tensor(sc)
     run_forward(re, a_eager)
-    re.grow_capacity(2.0)
+    re.grow_capacity(2.0, headroom=True)
     for _ in range(3):
         re.step(a_eager, tgt, adam=True)
     torch.cuda.synchronize()
@@ -72,7 +72,7 @@ def test_graph_replays_with_adam_count_steps():
     rg = renderer(sc)
     a_graph = atlas_tensor(sc)
     run_forward(rg, a_graph)
-    rg.grow_capacity(2.0)
+    rg.grow_capacity(2.0, headroom=True)
     side = torch.cuda.Stream()
     side.wait_stream(torch.cuda.current_stream())
     with torch.cuda.stream(side):
@@ -92,3 +92,61 @@ def test_graph_replays_with_adam_count_steps():
     assert torch.equal(a_graph, a_eager)
     re.close()
     rg.close()
+
+
+def test_captured_overflow_is_reported_then_recaptured():
+    """A captured step with an instance capacity forced too small from the
+    host: the replay overflows, check() (pg_status_check) reports it with the
+    count that suffices, and after growing and capturing again every replay
+    equals the eager step bitwise (images, loss, gradients)."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    sc = synth.random_scene(side=16, sh_degree=3, views=4, width=96, height=70, seed=8, lscale=(-2.9, 0.5))
+    atlas = atlas_tensor(sc)
+    tgt = torch.rand(3 * sc.n_pixels, device="cuda:0", generator=torch.Generator("cuda:0").manual_seed(3))
+    re = renderer(sc)
+    run_forward(re, atlas)
+    re.step(atlas, tgt)
+    torch.cuda.synchronize()
+    ref = (re.image.clone(), re.dL_datlas.clone(), float(re.loss.item()))
+    need_eager = int(re.sets[0].n_inst.item())
+    re.close()
+
+    r = renderer(sc, cap=64)
+    r.check_overflow = False          # keep the tiny buffers for the capture
+    stream = torch.cuda.current_stream()
+
+    def capture():
+        side = torch.cuda.Stream()
+        side.wait_stream(stream)
+        with torch.cuda.stream(side):
+            r.step(atlas, tgt)
+        stream.wait_stream(side)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            r.step(atlas, tgt)
+        torch.cuda.synchronize()
+        return g
+
+    g = capture()
+    say("[gpu] replay with capacity 64")
+    g.replay()
+    torch.cuda.synchronize()
+    [(ovf, need)] = r.status()
+    assert ovf and need == need_eager > 64
+    assert not r.check()
+    assert r.ensure_capacity() and r.sets[0].cap >= need
+    del g
+    g = capture()
+    for rep in range(3):
+        say(f"[gpu] replay {rep} after re-capture")
+        r.image.fill_(-1.0)
+        r.dL_datlas.fill_(7.0)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert r.check()
+        assert torch.equal(r.image, ref[0]) and torch.equal(r.dL_datlas, ref[1])
+        assert float(r.loss.item()) == ref[2]
+    r.close()

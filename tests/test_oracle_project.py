@@ -235,52 +235,64 @@ def test_rect_covers_every_pixel_inside_the_ellipse():
                 assert np.all((ty >= g["rect"][1]) & (ty <= g["rect"][3]))
 
 
-def kept(g, tx, ty):
-    """Membership of tile (tx, ty) in Gaussian g's lists, read from its mask."""
+def in_rect(g, tx, ty):
     r = g["rect"]
-    w, h = r[2] - r[0] + 1, r[3] - r[1] + 1
-    if not (r[0] <= tx <= r[2] and r[1] <= ty <= r[3]):
-        return False
-    if w * h > 64:
-        return True
-    return bool((int(g["tile_mask"]) >> int((ty - r[1]) * w + (tx - r[0]))) & 1)
+    return bool(r[0] <= tx <= r[2] and r[1] <= ty <= r[3])
 
 
-def test_tile_culling_against_dense_sampling():
-    """A culled tile of the rectangle has q > 9.001 everywhere on the rectangle
-    of its pixel centres (checked on a 1/8-pixel grid, whose minimum can only
-    be larger than the true one); a kept tile comes within 0.05 of 9.001 on
-    that grid (the grid's spacing bounds the gap).  n_tiles is the popcount,
-    and a Gaussian with no kept tile is culled."""
-    sc = synth.random_scene(side=10, sh_degree=0, views=3, width=96, height=80, seed=15, lscale=(-2.4, 0.8))
+def test_visibility_at_the_image_border():
+    """visible: past the z / det culls and some pixel of the image within r of
+    the mean on both axes.  An isotropic Gaussian on a shifted principal point
+    is moved across each border: it is visible exactly while m + r >= 0 on the
+    left (top) and m - r < W (H) on the right (bottom), hand-evaluated from
+    the radius of the on-axis closed form."""
+    z, ls = 3.0, -3.5
+    s = math.exp(float(np.float32(ls)))
+    for W, H in ((40, 24), (37, 29)):
+        cam = ident_cam(W, H)
+        r = math.ceil(3 * math.sqrt(cam.fx ** 2 * s * s / (z * z) + 0.3))
+        for cx, cy, expect in ((-r + 0.25, H / 2, True), (-r - 0.25, H / 2, False),
+                               (W + r - 0.25, H / 2, True), (W + r + 0.25, H / 2, False),
+                               (W / 2, -r + 0.25, True), (W / 2, -r - 0.25, False),
+                               (W / 2, H + r - 0.25, True), (W / 2, H + r + 0.25, False)):
+            cam.cx, cam.cy = cx, cy
+            for tw, th in ((16, 16), (8, 32), (32, 8)):
+                g = oracle.project(one_gaussian((0, 0, z), (ls,) * 3), 0, cam, tw, th)[0]
+                assert g["radius"] == r
+                assert bool(g["visible"]) == expect, (W, H, cx, cy, tw, th)
+                if expect:
+                    assert g["valid"] == 1   # a visible Gaussian is always listed
+    # behind the near plane: neither listed nor visible
+    g = oracle.project(one_gaussian((0, 0, 0.1), (ls,) * 3), 0, ident_cam(), 16, 16)[0]
+    assert g["valid"] == 0 and g["visible"] == 0
+
+
+def test_visibility_independent_of_tile_shape():
+    """Ragged views (width and height not multiples of any tile side): the
+    visible flags are the same for every tile shape, every visible Gaussian
+    is listed, and Gaussians listed only because a ragged tile reaches past
+    the image edge are not visible and have no pixel with q <= 9."""
+    sc = synth.random_scene(side=14, sh_degree=0, views=3, width=85, height=43, seed=21, lscale=(-2.6, 0.6))
     ids, params = oracle.fetch(sc.atlas, sc.occupancy)
-    n_culled_tiles = 0
-    for tw, th in ((16, 16), (8, 32), (32, 8)):
-        for cam in sc.cams:
+    n_edge = 0
+    for cam in sc.cams:
+        cam.cx, cam.cy = cam.width, cam.height    # scene centred on the bottom-right corner
+        ys, xs = np.mgrid[0:cam.height, 0:cam.width]
+        ref = None
+        for tw, th in ((16, 16), (8, 32), (32, 8)):
             pr = oracle.project(params[0], 0, cam, tw, th)
-            u = (np.arange(8 * (tw - 1) + 1) / 8.0)
-            v = (np.arange(8 * (th - 1) + 1) / 8.0)
-            for g in pr[pr["valid"] == 1][:60]:
-                r = g["rect"]
-                w, h = r[2] - r[0] + 1, r[3] - r[1] + 1
+            vis = pr["visible"].copy()
+            if ref is None:
+                ref = vis
+            assert np.array_equal(vis, ref)
+            assert np.all(pr["valid"][vis == 1] == 1)
+            for g in pr[(pr["valid"] == 1) & (pr["visible"] == 0)]:
+                n_edge += 1
+                dx, dy = xs + 0.5 - g["mean"][0], ys + 0.5 - g["mean"][1]
                 a, b, c = g["conic"]
-                n = 0
-                for ty in range(r[1], r[3] + 1):
-                    for tx in range(r[0], r[2] + 1):
-                        X = tx * tw + 0.5 + u[None, :] - g["mean"][0]
-                        Y = ty * th + 0.5 + v[:, None] - g["mean"][1]
-                        qmin = float((a * X * X + 2 * b * X * Y + c * Y * Y).min())
-                        if kept(g, tx, ty):
-                            n += 1
-                            if w * h <= 64:
-                                assert qmin <= 9.001 + 0.05, (tx, ty, qmin)
-                        else:
-                            n_culled_tiles += 1
-                            assert qmin > 9.001, (tx, ty, qmin)
-                assert n == g["n_tiles"]
-                assert g["n_tiles"] == (w * h if w * h > 64 else bin(int(g["tile_mask"])).count("1"))
-            assert np.all(pr[pr["valid"] == 0]["n_tiles"] == 0)
-    assert n_culled_tiles > 0, "the scene must exercise culling"
+                assert not np.any(a * dx * dx + 2 * b * dx * dy + c * dy * dy <= 9.0)
+        assert 0 < ref.sum() < len(ref)
+    assert n_edge > 0, "the scene must list Gaussians that are not visible"
 
 
 def test_bin_sort_matches_brute_force_enumeration():
@@ -295,12 +307,16 @@ def test_bin_sort_matches_brute_force_enumeration():
             for t in range(TX * TY):
                 tx, ty = t % TX, t // TX
                 for i in range(pr.shape[0]):
-                    if pr[i]["valid"] and kept(pr[i], tx, ty):
+                    if pr[i]["valid"] and in_rect(pr[i], tx, ty):
                         brute.append((t, int(pr[i]["key"]), i))
             brute.sort()
             got = [(int(a), int(b), int(c)) for a, b, c in zip(inst["tile"], inst["key"], inst["id"])]
             assert got == brute
-            assert len(inst) == int(pr[pr["valid"] == 1]["n_tiles"].sum())
+            v = pr[pr["valid"] == 1]
+            area = (v["rect"][:, 2] - v["rect"][:, 0] + 1) * (v["rect"][:, 3] - v["rect"][:, 1] + 1)
+            assert np.array_equal(v["n_tiles"], area)
+            assert len(inst) == int(area.sum())
+            assert np.all(pr[pr["valid"] == 0]["n_tiles"] == 0)
             # ranges partition [0, I)
             nonempty = ranges[ranges[:, 1] > ranges[:, 0]]
             assert nonempty[0, 0] == 0 and nonempty[-1, 1] == len(inst)
