@@ -10,7 +10,10 @@ Comparison rules:
     left-out (Gaussian, tile) must have q > 9 at every pixel centre of the
     tile inside the image (FP64 brute force from the oracle's mean and conic);
   * n_contrib is compared after mapping the oracle's list positions onto the
-    GPU's lists, exactly on every pixel not explained by a flip;
+    GPU's lists, exactly on every pixel not explained by a flip; a pixel
+    whose count differs (a termination decision at T = 1e-4 can move the
+    count while the colour moves by less than 1e-4) must be explained by the
+    same flip search, which then has to reproduce the count too;
   * projected floats within 1e-6 relative of the FP64 oracle;
   * images and final transmittance within 1e-4 absolute per pixel, except
     pixels "explained" by taking at most two of the oracle's near-threshold
@@ -71,19 +74,45 @@ def gpu_images(r):
     return out
 
 
-def explain(fw, v, gpu_img, gpu_T=None, tol=IMG_TOL, band=BAND, max_pixels=20000):
+def _n_map(fw, v, kept):
+    """Maps the oracle's n_contrib at pixel (x, y) (1-based position in the
+    oracle's tile list) to a position in the GPU's list, which is the
+    oracle's with the kept flags applied (identity for kept = None)."""
+    if kept is None:
+        return lambda x, y, n: n
+    cam = fw.scene.cams[v]
+    TX = (cam.width + fw.tw - 1) // fw.tw
+    ck = np.concatenate([[0], np.cumsum(kept, dtype=np.int64)])
+
+    def f(x, y, n):
+        if n <= 0:
+            return 0
+        s = int(fw.ranges[v][(y // fw.th) * TX + x // fw.tw, 0])
+        return int(ck[s + n] - ck[s])
+    return f
+
+
+def explain(fw, v, gpu_img, gpu_T=None, gpu_n=None, kept=None, tol=IMG_TOL, band=BAND, max_pixels=20000):
     """Returns (flips {pixel: positions}, unexplained [(x, y, err)], n_bad).
     A pixel is off when its colour (or, if gpu_T is given, its final
-    transmittance) differs from the oracle's by more than tol; it is
-    explained when taking at most two of the oracle's near-threshold
-    decisions the other way brings every compared value within tol.  More
-    than max_pixels off pixels in one view is a failure, not a sample."""
+    transmittance) differs from the oracle's by more than tol, or, if gpu_n
+    is given, when its n_contrib differs from the oracle's moved onto the
+    GPU's lists (kept flags from check_tile_lists).  It is explained when
+    taking at most two of the oracle's near-threshold decisions the other
+    way brings every compared value within tol and, with gpu_n, makes the
+    count equal.  More than max_pixels off pixels in one view is a failure,
+    not a sample."""
     cam = fw.scene.cams[v]
     err = np.abs(gpu_img - fw.image[v]).max(0)
     if gpu_T is not None:
         err = np.maximum(err, np.abs(gpu_T - fw.T[v]))
-    ys, xs = np.nonzero(err > tol)
-    assert len(xs) <= max_pixels, f"view {v}: {len(xs)} pixels beyond {tol} (more than {max_pixels} to examine)"
+    off = err > tol
+    if gpu_n is not None:
+        exp_n = gpu_n_contrib(fw, v, kept) if kept is not None else fw.n[v]
+        off |= gpu_n != exp_n
+    nmap = _n_map(fw, v, kept)
+    ys, xs = np.nonzero(off)
+    assert len(xs) <= max_pixels, f"view {v}: {len(xs)} pixels off (more than {max_pixels} to examine)"
     flips, unexplained = {}, []
     for x, y in zip(xs, ys):
         _, _, _, near = oracle.pixel(fw.proj[v], cam, fw.tw, fw.th, fw.inst[v], fw.ranges[v], x, y, band=band,
@@ -91,11 +120,16 @@ def explain(fw, v, gpu_img, gpu_T=None, tol=IMG_TOL, band=BAND, max_pixels=20000
         found = None
         cands = [[k] for k in near] + [list(p) for p in itertools.combinations(near, 2)]
         for fl in cands:
-            rgb, T, _, _ = oracle.pixel(fw.proj[v], cam, fw.tw, fw.th, fw.inst[v], fw.ranges[v], x, y, flips=fl,
+            rgb, T, n, _ = oracle.pixel(fw.proj[v], cam, fw.tw, fw.th, fw.inst[v], fw.ranges[v], x, y, flips=fl,
                                         band=band, bg=fw.bg)
-            if np.abs(rgb - gpu_img[:, y, x]).max() <= tol and (gpu_T is None or abs(T - gpu_T[y, x]) <= tol):
-                found = fl
-                break
+            if np.abs(rgb - gpu_img[:, y, x]).max() > tol:
+                continue
+            if gpu_T is not None and abs(T - gpu_T[y, x]) > tol:
+                continue
+            if gpu_n is not None and nmap(int(x), int(y), n) != int(gpu_n[y, x]):
+                continue
+            found = fl
+            break
         if found is None:
             unexplained.append((int(x), int(y), float(err[y, x])))
         else:

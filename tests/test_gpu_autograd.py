@@ -100,14 +100,14 @@ def test_autograd_l1_loss_end_to_end():
     n = img.numel()
     cot = (torch.sign(img.detach() - tgt) / n).double().cpu().numpy()
     L_ref, G_ref = fw.loss(targets)
-    assert abs(float(loss) - L_ref) <= 1e-6 * max(1.0, L_ref)
+    assert abs(float(loss.detach()) - L_ref) <= 1e-6 * max(1.0, L_ref)
     G, o = {}, 0
     for v in fw.views:
         k = fw.image[v].size
         G[v] = cot[o:o + k].reshape(fw.image[v].shape)
         o += k
     flips_sign = int(sum(int((np.sign(G[v]) != np.sign(G_ref[v])).sum()) for v in fw.views))
-    say(f"[gpu] autograd L1: loss {float(loss):.9f} (oracle {L_ref:.9f}); cotangent sign flips against the "
+    say(f"[gpu] autograd L1: loss {float(loss.detach()):.9f} (oracle {L_ref:.9f}); cotangent sign flips against the "
         f"oracle's own: {flips_sign}")
     ref, _ = fw.backward(G, flips=flips_of(fw, r))
     compare_atlas_grad(sc, atlas.grad.cpu().numpy().astype(np.float64), ref)

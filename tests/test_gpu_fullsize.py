@@ -90,7 +90,7 @@ def test_full_size_sampled_parity(cfg):
         rg = ranges[tb[v]:tb[v + 1]]
         TX, TY = oracle.tiles_of(sc.cams[v], fw.tw, fw.th)
         assert np.array_equal(rg[:, 1] - rg[:, 0], np.bincount(inst["tile"][kept], minlength=TX * TY))
-        fl, unexp, nbad = explain(fw, v, imgs[v][0], imgs[v][1])
+        fl, unexp, nbad = explain(fw, v, imgs[v][0], imgs[v][1], imgs[v][2], kept)
         total_bad += nbad
         assert not unexp, f"view {v}: {len(unexp)} pixels beyond 1e-4 not explained, e.g. {unexp[:3]}"
         if fl:

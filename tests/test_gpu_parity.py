@@ -106,7 +106,8 @@ def test_render_forward_parity(name):
     total_bad = total_unexp = 0
     for v in range(len(sc.cams)):
         gi, gT, gn = imgs[v]
-        flips, unexp, nbad = explain(fw, v, gi, gT)
+        kept = check_tile_lists(fw, v, keys, vals, r.sets[0].tile_base, r.N)
+        flips, unexp, nbad = explain(fw, v, gi, gT, gn, kept)
         total_bad += nbad
         total_unexp += len(unexp)
         ok = np.ones(gn.shape, bool)
@@ -115,7 +116,6 @@ def test_render_forward_parity(name):
         err = np.abs(gi - fw.image[v]).max(0)
         assert err[ok].max() <= IMG_TOL if ok.any() else True
         assert np.abs(gT - fw.T[v])[ok].max() <= IMG_TOL
-        kept = check_tile_lists(fw, v, keys, vals, r.sets[0].tile_base, r.N)
         exp_n = gpu_n_contrib(fw, v, kept)
         bad_n = int((gn != exp_n)[ok].sum())
         assert bad_n == 0, f"view {v}: n_contrib differs on {bad_n} pixels not explained by a flip"
