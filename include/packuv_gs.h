@@ -123,8 +123,9 @@ typedef struct pg_views_info {
     int32_t tile_w, tile_h, lds_batch, reserved;
 } pg_views_info;
 
-/* Selects `device` for the calling thread and checks it is gfx950.
- * Returns PG_ERR_UNSUPPORTED_DEVICE otherwise. */
+/* Selects `device` for the calling thread and checks it is gfx950
+ * (PG_ERR_UNSUPPORTED_DEVICE otherwise), then looks up that device's copy of
+ * the fixed scratch array that pg_atlas_fetch_noalloc uses. */
 pg_status pg_init(int32_t device);
 
 /* Message for the last error of the calling thread ("" if none). */
@@ -197,6 +198,30 @@ pg_status pg_status_check(const int32_t* overflow_dev, const int64_t* n_inst_dev
 pg_status pg_atlas_fetch(const float* atlas, const uint8_t* occupancy, int32_t frames, int32_t channels,
                          int32_t H, int32_t W, int64_t n_cap, int32_t* gauss_texel, int32_t* texel_gauss,
                          float* params, int64_t* n_gauss_dev, void* ws, size_t ws_bytes, void* stream);
+
+/* Allocation-free form of pg_atlas_fetch, for callers that cannot allocate
+ * device memory: code under HIP graph capture, tight serving loops and
+ * harnesses that forbid hipMalloc.  Same arguments, outputs and results as
+ * pg_atlas_fetch (bit-identical), without the workspace: the compaction's
+ * block counts and their scan live in a fixed array of
+ * PG_FETCH_NOALLOC_SCRATCH_BYTES inside the library, one copy per GPU,
+ * which each GPU the library runs on holds until the process ends.  The call
+ * allocates and frees nothing.
+ *   - H W above PG_FETCH_NOALLOC_MAX_TEXELS (8192 x 8192) returns
+ *     PG_ERR_WORKSPACE before anything is enqueued.
+ *   - The array's address on a device is looked up by pg_init(device), or
+ *     else by the first call on that device; call pg_init before capturing
+ *     a graph that holds this call.  The stream must belong to the calling
+ *     thread's current device.
+ *   - Every call on one GPU shares that GPU's array (it keeps the last
+ *     call's contents; nothing in it needs to start at zero): calls that
+ *     overlap on one GPU (two streams, two threads) race, and give
+ *     undefined results.  Calls in order on one stream are safe. */
+#define PG_FETCH_NOALLOC_MAX_TEXELS (1LL << 26)
+#define PG_FETCH_NOALLOC_SCRATCH_BYTES (256u * 1024u)
+pg_status pg_atlas_fetch_noalloc(const float* atlas, const uint8_t* occupancy, int32_t frames, int32_t channels,
+                                 int32_t H, int32_t W, int64_t n_cap, int32_t* gauss_texel, int32_t* texel_gauss,
+                                 float* params, int64_t* n_gauss_dev, void* stream);
 
 /* Low-precision optimisation (LPO) -- the uniform K-bit fake quantiser the
  * renderer consumes instead of the FP32 master texel values (Sec. 4.3 LPO

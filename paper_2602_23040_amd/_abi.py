@@ -71,6 +71,7 @@ SIGNATURES = {
     "pg_fetch_workspace_size": (_i32, [_i32, _i32, C.POINTER(_sz)]),
     "pg_sort_workspace_size": (_i32, [_p, _i64, C.POINTER(_sz)]),
     "pg_atlas_fetch": (_i32, [_p, _p, _i32, _i32, _i32, _i32, _i64, _p, _p, _p, _p, _p, _sz, _p]),
+    "pg_atlas_fetch_noalloc": (_i32, [_p, _p, _i32, _i32, _i32, _i32, _i64, _p, _p, _p, _p, _p]),
     "pg_atlas_fake_quant": (_i32, [_p, _p, _i64, _i32, _i32, _p, _p, _p, _p, _p]),
     "pg_project": (_i32, [_p, _p, _p, _p, _p, _p, _p]),
     "pg_flow_mask": (_i32, [_p, _p, _p, _p, _p, _p, _i32, _i32, _p, _p, _p]),
@@ -207,6 +208,17 @@ def pg_atlas_fetch(atlas, occupancy, frames, channels, H, W, n_cap, gauss_texel,
     _check(lib().pg_atlas_fetch(_ptr(atlas), _ptr(occupancy), int(frames), int(channels), int(H), int(W), int(n_cap),
                                 _ptr(gauss_texel), _ptr(texel_gauss), _ptr(params), _ptr(n_gauss_dev), _ptr(ws),
                                 int(ws_bytes), _stream(stream)), "pg_atlas_fetch")
+
+
+FETCH_NOALLOC_MAX_TEXELS = 1 << 26          # PG_FETCH_NOALLOC_MAX_TEXELS
+FETCH_NOALLOC_SCRATCH_BYTES = 256 * 1024     # PG_FETCH_NOALLOC_SCRATCH_BYTES
+
+
+def pg_atlas_fetch_noalloc(atlas, occupancy, frames, channels, H, W, n_cap, gauss_texel, texel_gauss, params,
+                           n_gauss_dev, stream=None):
+    _check(lib().pg_atlas_fetch_noalloc(_ptr(atlas), _ptr(occupancy), int(frames), int(channels), int(H), int(W),
+                                        int(n_cap), _ptr(gauss_texel), _ptr(texel_gauss), _ptr(params),
+                                        _ptr(n_gauss_dev), _stream(stream)), "pg_atlas_fetch_noalloc")
 
 
 def pg_atlas_fake_quant(params, n_gauss_dev, n_cap, frames, channels, bits, range_out, codes, partial, stream=None):

@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -33,6 +34,40 @@ bool tiling_ok(const pg_tiling& t) {
         hipError_t e_ = (expr);                           \
         if (e_ != hipSuccess) return hip_fail(e_, what);  \
     } while (0)
+
+// Workspace of pg_atlas_fetch_noalloc: a fixed array in device memory, one
+// copy per GPU, held until the process ends.  Host code never passes this
+// name to a kernel or a copy (in host code it is a stand-in, not a device
+// address); it uses the per-device address that hipGetSymbolAddress returns.
+constexpr size_t kFetchScratchBytes = PG_FETCH_NOALLOC_SCRATCH_BYTES;
+constexpr int kMaxDevices = 64;
+__device__ __align__(256) unsigned char scratch[kFetchScratchBytes];
+
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// The calling thread's current device's copy of `scratch` (looked up once per
+// device, with that device current).
+pg_status scratch_for_current_device(void** out) {
+    int dev = -1;
+    PG_CHECK_HIP(hipGetDevice(&dev), "hipGetDevice");
+    if (dev < 0 || dev >= kMaxDevices) {
+        g_error = "device index beyond the library's per-device table";
+        return PG_ERR_UNSUPPORTED_DEVICE;
+    }
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        PG_CHECK_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)), "hipGetSymbolAddress(scratch)");
+        if (!ptr) {
+            g_error = "hipGetSymbolAddress(scratch) returned a null address";
+            return PG_ERR_HIP;
+        }
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return PG_OK;
+}
 
 }  // namespace
 
@@ -66,7 +101,8 @@ pg_status pg_init(int32_t device) {
         set_error(std::string("unsupported device architecture ") + prop.gcnArchName + " (needs gfx950)");
         return PG_ERR_UNSUPPORTED_DEVICE;
     }
-    return PG_OK;
+    void* ws = nullptr;
+    return scratch_for_current_device(&ws);
 }
 
 pg_status pg_views_create(const pg_camera* cams, int32_t n_views, int32_t frames, int64_t n_gauss,
@@ -245,6 +281,31 @@ pg_status pg_atlas_fetch(const float* atlas, const uint8_t* occupancy, int32_t f
     PG_CHECK_HIP(launch_fetch(atlas, occupancy, frames, channels, H, W, n_cap, gauss_texel, texel_gauss, params,
                               n_gauss_dev, ws, (hipStream_t)stream),
                  "pg_atlas_fetch");
+    return PG_OK;
+}
+
+pg_status pg_atlas_fetch_noalloc(const float* atlas, const uint8_t* occupancy, int32_t frames, int32_t channels,
+                                 int32_t H, int32_t W, int64_t n_cap, int32_t* gauss_texel, int32_t* texel_gauss,
+                                 float* params, int64_t* n_gauss_dev, void* stream) {
+    g_error.clear();
+    if (!atlas || !occupancy || !texel_gauss || !n_gauss_dev) return invalid("null pointer argument");
+    if (n_cap > 0 && (!gauss_texel || !params)) return invalid("gauss_texel / params null with n_cap > 0");
+    if (frames < 1 || channels < 1 || H < 1 || W < 1 || n_cap < 0) return invalid("bad sizes");
+    if ((int64_t)H * W > INT32_MAX) return invalid("H * W exceeds 2^31 - 1");
+    if ((int64_t)H * W > PG_FETCH_NOALLOC_MAX_TEXELS || fetch_ws_bytes(H, W) > kFetchScratchBytes) {
+        set_error("atlas of " + std::to_string((int64_t)H * W) + " texels is larger than the " +
+                  std::to_string((int64_t)PG_FETCH_NOALLOC_MAX_TEXELS) +
+                  " that the library's fixed scratch serves; use pg_atlas_fetch with a workspace");
+        return PG_ERR_WORKSPACE;
+    }
+    void* ws = nullptr;
+    const pg_status st = scratch_for_current_device(&ws);
+    if (st != PG_OK) return st;
+    // Every word of the workspace that the kernels read is written earlier in
+    // the same call (block counts, then their scan), so nothing is cleared.
+    PG_CHECK_HIP(launch_fetch(atlas, occupancy, frames, channels, H, W, n_cap, gauss_texel, texel_gauss, params,
+                              n_gauss_dev, ws, (hipStream_t)stream),
+                 "pg_atlas_fetch_noalloc");
     return PG_OK;
 }
 

@@ -105,3 +105,20 @@ def test_new_boundary_calls_reject_bad_arguments_on_the_host():
     args[10], args[20], args[21], args[24] = 0, 1, 1, 0
     assert lib.pg_backward(*args) == -1
     assert "null" in abi.pg_last_error()
+
+
+def test_fetch_noalloc_refuses_atlases_beyond_its_scratch_on_the_host():
+    """The allocation-free fetch refuses null buffers and atlases larger than
+    its fixed scratch serves before any device work (the dummy pointers are
+    never read), and its documented limit fits the workspace that
+    pg_atlas_fetch would need at that size."""
+    lib = abi.lib()
+    dummy = C.c_void_p(0x1000)
+    assert lib.pg_atlas_fetch_noalloc(None, dummy, 1, 14, 64, 64, 10, dummy, dummy, dummy, dummy, None) == -1
+    assert "null" in abi.pg_last_error()
+    assert lib.pg_atlas_fetch_noalloc(dummy, dummy, 1, 14, 8192, 8193, 10, dummy, dummy, dummy, dummy, None) == -5
+    assert str(abi.FETCH_NOALLOC_MAX_TEXELS) in abi.pg_last_error()
+    assert abi.pg_fetch_workspace_size(8192, 8192) <= abi.FETCH_NOALLOC_SCRATCH_BYTES
+    src = open(os.path.join(ROOT, "include", "packuv_gs.h")).read()
+    assert "#define PG_FETCH_NOALLOC_MAX_TEXELS (1LL << 26)" in src
+    assert "#define PG_FETCH_NOALLOC_SCRATCH_BYTES (256u * 1024u)" in src
