@@ -302,7 +302,7 @@ def main():
     if args.also_configs:
         rp = rb = None
         torch.cuda.empty_cache()
-        out["other_configs"] = [other_config(int(c), tiling, max(2, args.steps // 4), 2)
+        out["other_configs"] = [other_config(int(c), None if args.tiling == "auto" else tiling, max(2, args.steps // 4), 2)
                                 for c in args.also_configs.split(",") if c.strip()]
     print(json.dumps(out), flush=True)
 
@@ -532,11 +532,13 @@ def lpo_leg(sc, atlas, target, tiling, steps, warmup, graph):
 def other_config(cfg, tiling, steps, warmup):
     """Batched (graph) and plain step time of another workload: fetch,
     projection, bin/sort, compositing, L1 against a second seeded Gaussian
-    set, adjoint, and for the 2048^2 workload the sparse Adam update."""
+    set, adjoint, and for the 2048^2 workload the sparse Adam update.
+    tiling None: the autotuner picks it for this workload (cached)."""
     import numpy as np
     import torch
 
     import synth
+    from paper_2602_23040_amd import autotune
     from paper_2602_23040_amd.pipeline import Renderer
 
     dev = torch.device("cuda:0")
@@ -544,6 +546,10 @@ def other_config(cfg, tiling, steps, warmup):
     tgt_sc = synth.make_scene(cfg, target=True)
     adam = cfg == 5
     atlas = torch.from_numpy(np.ascontiguousarray(sc.atlas).reshape(-1)).to(dev)
+    tune_info = None
+    if tiling is None:
+        tiling, tune_info = autotune.choose(sc, atlas, device=dev)
+        torch.cuda.empty_cache()
     tgt_atlas = torch.from_numpy(np.ascontiguousarray(tgt_sc.atlas).reshape(-1)).to(dev)
     del tgt_sc
     V, N = len(sc.cams), sc.n_gauss
@@ -589,6 +595,24 @@ def other_config(cfg, tiling, steps, warmup):
     assert rb.check(), f"config {cfg}: instance capacity overflowed inside the timed region"
     n_inst = int(rb.sets[0].n_inst.item())
     P = rb.n_pixels
+    adam_info = None
+    if adam:
+        # the sparse Adam kernel alone, on the state the last replay left: 28 algorithmic bytes per updated
+        # element (read p, g, m, v; write p, m, v) plus 5 per texel (id and visibility lookups)
+        n_vis = int(rb.visible.sum().item())
+        elems = n_vis * sc.C
+        a0, a1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        reps = 10
+        a0.record()
+        for _ in range(reps):
+            rb.adam_step(work)
+        a1.record()
+        torch.cuda.synchronize()
+        adam_ms = a0.elapsed_time(a1) / reps
+        alg = 28 * elems + 5 * sc.H * sc.W * sc.frames
+        adam_info = {"ms": round(adam_ms, 4), "visible_gaussians": n_vis, "updated_elements": elems,
+                     "roofline": {"bound": "hbm", "achieved": round(alg / adam_ms / 1e6, 1), "peak": 8000.0,
+                                  "unit": "GB/s", "frac": round(alg / adam_ms / 1e6 / 8000.0, 4), "bytes": alg}}
     rb.close()
     del rb, graph
     torch.cuda.empty_cache()
@@ -607,7 +631,8 @@ def other_config(cfg, tiling, steps, warmup):
     return {"config": cfg, "workload": sc.name, "views": V, "frames": sc.frames, "gaussians": N, "pixels": P,
             "instances": n_inst, "adam": adam, "steps": steps, "ms_per_step": round(ms, 3),
             "mpixels_per_s": round(P / ms / 1e3, 2), "gaussians_per_s": round(N * V / ms * 1e3, 1),
-            "plain_ms_per_step": round(ms_plain, 3), "speedup_vs_plain": round(ms_plain / ms, 3)}
+            "plain_ms_per_step": round(ms_plain, 3), "speedup_vs_plain": round(ms_plain / ms, 3),
+            "tiling": "x".join(map(str, tiling)), "autotune": tune_info, "adam_kernel": adam_info}
 
 
 def stage_times(r, atlas, target, reps=5):

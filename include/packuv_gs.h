@@ -345,7 +345,10 @@ pg_status pg_flow_mask(const pg_views* views, const float* params, const uint8_t
  *                  one gradient slot per instance, record by record in that
  *                  order, the record's kept tiles in rectangle row-major order.
  *   n_inst_dev     device int64 [1] out: number of instances
- *   overflow_dev   device int32 [1] out: 1 if n_inst > inst_capacity, else 0
+ *   overflow_dev   device int32 [1] out: bit 0 set if n_inst > inst_capacity;
+ *                  bit 1 set if a radix pass gave up waiting on an earlier
+ *                  tile's counts (never in a working run; pg_status_check
+ *                  then returns PG_ERR_HIP); 0 otherwise
  *   inst_grad      device float [inst_capacity][9] or NULL: the adjoint's
  *                  per-instance gradient slots; the first n_inst are zeroed
  *   ws             device workspace of pg_sort_workspace_size bytes */
@@ -492,7 +495,7 @@ pg_status pg_loss_regularisers(const float* params, const int64_t* n_gauss_dev, 
  * weights, Sparse Adam).  Textbook Adam with bias correction at `step` >= 1,
  * applied to channels of texels whose Gaussian is visible (visible[f N + i]);
  * other texels and their moments are left untouched.
- *   atlas, m, v  device float [F][C][H][W] in/out;  grad same layout
+ *   atlas, m, v  device float [F][C][H][W] in/out;  grad same layout (F <= 65535)
  *   step         the step number (>= 1) for bias correction, or ignored when
  *   step_dev     (device int32 [1], may be NULL) is given: the call then adds
  *                1 to *step_dev on the device and uses the new value, so the

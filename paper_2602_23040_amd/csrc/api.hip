@@ -433,6 +433,10 @@ pg_status pg_status_check(const int32_t* overflow_dev, const int64_t* n_inst_dev
     PG_CHECK_HIP(hipMemcpyAsync(&need, n_inst_dev, sizeof need, hipMemcpyDeviceToHost, s), "pg_status_check (copy)");
     PG_CHECK_HIP(hipStreamSynchronize(s), "pg_status_check (synchronise)");
     if (needed_capacity) *needed_capacity = need;
+    if (ovf & 2) {
+        set_error("a radix pass of the sort gave up waiting for an earlier tile's counts; outputs are undefined");
+        return PG_ERR_HIP;
+    }
     if (ovf) {
         set_error("instance capacity overflow: " + std::to_string(need) + " instances needed");
         return PG_ERR_CAPACITY;
@@ -606,7 +610,7 @@ pg_status pg_adam_step(float* atlas, const float* grad, float* m, float* v, cons
                        void* stream) {
     g_error.clear();
     if (!atlas || !grad || !m || !v || !visible || !texel_gauss) return invalid("null pointer argument");
-    if (frames < 1 || channels < 1 || H < 1 || W < 1 || n_gauss < 0) return invalid("bad sizes");
+    if (frames < 1 || frames > 65535 || channels < 1 || H < 1 || W < 1 || n_gauss < 0) return invalid("bad sizes");
     if (!step_dev && step < 1) return invalid("step must be >= 1");
     if (!(beta1 >= 0.0f && beta1 < 1.0f) || !(beta2 >= 0.0f && beta2 < 1.0f) || !(eps > 0.0f))
         return invalid("need 0 <= beta < 1 and eps > 0");

@@ -23,19 +23,19 @@
 //                               inst_first[gv] = instances of all records before
 //                               gv in (view, id) order: the record's gradient
 //                               slots, one per kept tile in rectangle order
-//   radix passes (32-bit keys)  LSD, digit width <= 8 bits
+//   radix passes (32-bit keys)  LSD, four 8-bit digits of the depth bits
 //   k_sorted_count / k_emit     tiles per sorted record -> instance offsets ->
 //                               work-group-cooperative emission (coalesced writes)
-//   radix passes (32-bit keys)  tile ids
+//   radix passes (32-bit keys)  tile ids, 6-bit digits
 //   k_ranges                    [start, end) of every tile
 //   k_order_count/_scan/_place  the compositing kernels' tile dispatch order
-// Radix passes: per-tile digit histograms (upsweep, LDS atomics), a scan of
-// the histograms into per-tile digit offsets, then a downsweep that ranks keys
-// with a wave-level multisplit (one ballot per digit bit) and scatters through
-// LDS so each digit's run is written contiguously.  Histograms and offsets are
-// stored tile-major ([tile][digit], coalesced for both kernels) and scanned in
-// two levels over chunks of 64 tiles.  Counts that only the device knows are
-// read from device memory, so the chain needs no host synchronisation.
+// Radix passes: one histogram kernel counts every digit of the sort in one
+// read of the keys; then one kernel per digit ranks each 4096-key tile with a
+// wave-level multisplit (one ballot per digit bit), takes each digit's output
+// offset from the counts of the tiles before it (decoupled look-back), and
+// scatters through LDS so each digit's run is written contiguously.  Counts
+// that only the device knows are read from device memory, so the chain needs
+// no host synchronisation.
 #include "pg_internal.h"
 
 namespace pg {
@@ -43,25 +43,33 @@ namespace pg {
 namespace {
 
 constexpr int kBlk = 1024;           // records per compaction / emission work-group
-constexpr int kSortGrid = 2048;      // persistent grid of the radix kernels (grid-stride over tiles)
-constexpr int kMaxDigitBits = 8;     // digit width cap of both sorts: wider digits rank and scatter slower
+
+struct DigitPlan {
+    int passes, digit;      // LSD passes of equal width digit bits
+};
+constexpr int kOsMaxBits = 9;                // digit width the radix pass kernels are built for
+constexpr int kDepthDigitBits = 8;           // digit width caps of the record (depth) and instance (tile) sorts
+constexpr int kTileDigitBits = 6;
+
+DigitPlan digit_plan(int bits, int max_bits) {
+    DigitPlan p;
+    p.passes = (int)imax((bits + max_bits - 1) / max_bits, 1);
+    p.digit = (bits + p.passes - 1) / p.passes;
+    return p;
+}
 
 struct SortPlan {
-    int d_bits, d_passes;            // depth sort: key bits, digit width, passes
-    int d_digit;
-    int t_bits, t_passes, t_digit;   // tile sort
+    DigitPlan depth, tile;  // record sort (32-bit depth keys), instance sort (tile ids)
 };
 
 SortPlan plan_for(const pg_views* v) {
-    SortPlan p{};
-    p.d_bits = 32;
-    p.d_passes = (p.d_bits + kMaxDigitBits - 1) / kMaxDigitBits;
-    p.d_digit = (p.d_bits + p.d_passes - 1) / p.d_passes;
-    p.t_bits = v->key_bits;          // ceil(log2(n_tiles)), >= 1
-    p.t_passes = (p.t_bits + kMaxDigitBits - 1) / kMaxDigitBits;
-    p.t_digit = (p.t_bits + p.t_passes - 1) / p.t_passes;
+    SortPlan p;
+    p.depth = digit_plan(32, kDepthDigitBits);
+    p.tile = digit_plan(v->key_bits, kTileDigitBits);   // ceil(log2(n_tiles)), >= 1
     return p;
 }
+
+size_t os_ws_bytes(int64_t cap, DigitPlan pl);
 
 struct SortWs {
     int64_t* blk_a;          // per-block sums (compaction / emission)
@@ -77,10 +85,7 @@ struct SortWs {
     uint4* stiles;           // the records' tile sets gathered in depth order (read by the emission)
     uint32_t* tk_alt;        // tile sort ping-pong partner of the caller's arrays
     int32_t* tv_alt;
-    int32_t* counts;         // per radix tile, its digit counts (tile-major: [tile][digit])
-    int32_t* count_offs;     // per radix tile, the output offset of each digit (same layout)
-    int32_t* chunk_dm;       // digit-major [digit][chunk] sums of kChunkTiles tiles, and their exclusive scan
-    int32_t* chunk_off;
+    char* os;                // radix pass state (histograms, look-back status), shared by both sorts
     int32_t* order_cnt;      // tile dispatch order: per (tile group, length class) counts
     int32_t* order_base;     // ... and their class-major exclusive scan
     int32_t* order_cls;      // ... first slot and size of each class
@@ -88,26 +93,14 @@ struct SortWs {
 
 int64_t n_blocks(const pg_views* v) { return imax(ceil_div(v->n_gv, kBlk), 1); }
 
-constexpr int kChunkTiles = 64;   // radix tiles per chunk of the two-level offset scan
 constexpr int kOrderClasses = 64; // length classes of the tile dispatch order (four per octave)
 constexpr int kOrderBlk = 256;
-
-// Radix tiles (and chunks of them) either sort can have at most.
-int64_t tiles_max(const pg_views* v, int64_t cap) {
-    return imax(imax(ceil_div(imax(v->n_gv, 1), kSortTile), ceil_div(imax(cap, 1), kSortTile)), 1);
-}
-int64_t chunks_max(const pg_views* v, int64_t cap) { return ceil_div(tiles_max(v, cap), kChunkTiles); }
 
 SortWs carve(const pg_views* v, int64_t cap, void* ws, size_t* total) {
     const SortPlan pl = plan_for(v);
     SortWs w{};
     const int64_t nb = n_blocks(v);
     const int64_t ngv = imax(v->n_gv, 1);
-    const int64_t cnt_d = ((int64_t)1 << pl.d_digit) * imax(ceil_div(ngv, kSortTile), 1);
-    const int64_t cnt_t = ((int64_t)1 << pl.t_digit) * imax(ceil_div(imax(cap, 1), kSortTile), 1);
-    const int64_t cnt = imax(cnt_d, cnt_t);
-    const int64_t nch = chunks_max(v, cap);
-    const int64_t ch = ((int64_t)1 << imax(pl.d_digit, pl.t_digit)) * nch;
     char* p = (char*)ws;
     size_t off = 0;
     auto take = [&](size_t bytes) {
@@ -128,10 +121,7 @@ SortWs carve(const pg_views* v, int64_t cap, void* ws, size_t* total) {
     w.stiles = (uint4*)take(ngv * 16);
     w.tk_alt = (uint32_t*)take(imax(cap, 1) * 4);
     w.tv_alt = (int32_t*)take(imax(cap, 1) * 4);
-    w.counts = (int32_t*)take(cnt * 4);
-    w.count_offs = (int32_t*)take(cnt * 4);
-    w.chunk_dm = (int32_t*)take(ch * 4);
-    w.chunk_off = (int32_t*)take(ch * 4);
+    w.os = take(std::max(os_ws_bytes(ngv, pl.depth), os_ws_bytes(cap, pl.tile)));
     const int64_t order_words = ceil_div(imax(v->n_tiles, 1), kOrderBlk) * kOrderClasses;
     w.order_cnt = (int32_t*)take(order_words * 4);
     w.order_base = (int32_t*)take(order_words * 4);
@@ -238,7 +228,7 @@ __global__ __launch_bounds__(kBlk) void k_sorted_count(const pg_tile_set* __rest
 __global__ void k_post_count(const int64_t* n_inst, int64_t cap, int32_t* overflow, int64_t* misc) {
     const int64_t I = *n_inst;
     const bool of = I > cap;
-    *overflow = of ? 1 : 0;
+    *overflow = (*overflow & 2) | (of ? 1 : 0);
     const int64_t eff = of ? 0 : I;
     misc[1] = eff;
 }
@@ -303,211 +293,371 @@ __global__ __launch_bounds__(kBlk) void k_emit(const uint4* __restrict__ stiles,
 }
 
 // ------------------------------------------------------------------ LSD radix pass
-// Peers of this lane: active lanes holding the same BITS-bit digit.
+// Peers of this lane: active lanes holding the same BITS-bit digit.  Per
+// bit, the ballot of the lanes that have it set, flipped where this lane's
+// bit is clear, marks the lanes that differ from it in that bit; a peer
+// differs in none.  Each half of the 64-lane mask costs an exclusive-or with
+// the lane's sign-extended bit and an or per bit.
 template <int BITS>
 __device__ __forceinline__ uint64_t match_digit(uint32_t d, bool active) {
-    uint64_t peers = __ballot(active);
+    uint32_t diff_lo = 0u, diff_hi = 0u;
 #pragma unroll
     for (int b = 0; b < BITS; b++) {
-        const bool bit = (d >> b) & 1u;
-        const uint64_t m = __ballot(bit);
-        peers &= bit ? m : ~m;
+        const uint32_t s = (uint32_t)__builtin_amdgcn_sbfe((int32_t)d, b, 1);   // all ones where this lane's bit is set
+        const uint64_t m = __ballot(s != 0u);
+        diff_lo |= (uint32_t)m ^ s;
+        diff_hi |= (uint32_t)(m >> 32) ^ s;
     }
-    return peers;
+    const uint64_t eq = ~(((uint64_t)diff_hi << 32) | diff_lo);
+    return eq & __ballot(active);
 }
 
-template <typename K, int BITS>
-__global__ __launch_bounds__(kSortThreads) void k_radix_upsweep(const K* __restrict__ keys,
-                                                                const int64_t* __restrict__ n_ptr, int shift,
-                                                                int32_t* __restrict__ counts) {
+// ------------------------------------------------------------------ onesweep LSD radix passes
+// One kernel per digit.  Work-group b ranks the keys of radix tile b (4096
+// pairs) with the wave multisplit, publishes its digit counts, and finds
+// each digit's output offset by looking back over the tiles before it
+// (decoupled look-back): a tile's status word per digit holds either its own
+// count (AGG) or the count of that digit over every tile up to and including
+// it (PRE).  The digit offsets over the whole input come from one histogram
+// pass over the keys for every digit of the sort.  A pass reads and writes
+// each pair once.
+// Waiting on lower-numbered work-groups cannot deadlock because every XCD
+// starts its share of the grid in index order: the lowest-numbered unfinished
+// work-group has no unfinished predecessor, and if it had not started, its
+// XCD would hold only finished lower-numbered groups and so have room for it.
+// (An atomic ticket per work-group, which does not rely on that order, made
+// the passes 15 % slower.)  The wait is bounded anyway: a look-back that
+// polls kLookbackSpins times gives up, and the sort reports it.
+constexpr uint32_t kStAgg = 1u, kStPre = 2u;
+constexpr int kLookbackSpins = 1 << 22;      // a bound that a working chain never reaches (~1 s of polling)
+constexpr int kMaxSortPasses = 4;
+constexpr int kLookWindow = 8;               // predecessors read at once by the look-back
+
+__device__ __forceinline__ void st_publish(unsigned long long* p, uint32_t flag, uint32_t value) {
+    __hip_atomic_store(p, ((unsigned long long)flag << 32) | value, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ unsigned long long st_read(unsigned long long* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Digit counts of every pass of a sort in one read of the keys:
+// hist[p NB + d] = keys whose bits [p BITS, (p + 1) BITS) equal d.  Each wave
+// counts into its own LDS histogram; with UNIFORM, a wave whose active lanes
+// share a digit adds once (depth keys share their high bits, which would
+// otherwise serialise the LDS atomics).
+template <int BITS, bool UNIFORM>
+__global__ __launch_bounds__(256) void k_os_hist(const uint32_t* __restrict__ keys, const int64_t* __restrict__ n_ptr,
+                                                 int passes, uint32_t* __restrict__ hist) {
     constexpr int NB = 1 << BITS;
-    __shared__ uint32_t s_cnt[NB];
-    const int64_t n = *n_ptr;
-    const int64_t ntile = ceil_div(n, kSortTile);
+    constexpr int KPT = 16;                      // keys per thread per sweep, all loaded before they are counted
+    __shared__ uint32_t s[4][kMaxSortPasses * NB];
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    for (int64_t b = blockIdx.x; b < ntile; b += gridDim.x) {
-        for (int d = threadIdx.x; d < NB; d += kSortThreads) s_cnt[d] = 0;
-        __syncthreads();
-        const int64_t start = b * kSortTile + (int64_t)wid * (kSortTile / 4);
-#pragma unroll 4
-        for (int r = 0; r < kSortItems; r++) {
-            const int64_t idx = start + r * 64 + lane;
-            if (idx < n) atomicAdd(&s_cnt[(uint32_t)((keys[idx] >> shift) & (NB - 1))], 1u);   // counts only: order-free
-        }
-        __syncthreads();
-        for (int d = threadIdx.x; d < NB; d += kSortThreads) counts[b * NB + d] = (int32_t)s_cnt[d];
-        __syncthreads();
+    for (int i = threadIdx.x; i < passes * NB; i += 256) {
+#pragma unroll
+        for (int w = 0; w < 4; w++) s[w][i] = 0;
     }
-}
-
-template <typename K, int BITS>
-__global__ __launch_bounds__(kSortThreads) void k_radix_downsweep(const K* __restrict__ keys_in,
-                                                                  const int32_t* __restrict__ vals_in,
-                                                                  K* __restrict__ keys_out,
-                                                                  int32_t* __restrict__ vals_out,
-                                                                  const int64_t* __restrict__ n_ptr, int shift,
-                                                                  const int32_t* __restrict__ count_offs) {
-    constexpr int NB = 1 << BITS;
-    constexpr int PER = NB >= kSortThreads ? NB / kSortThreads : 1;   // digits per thread in the digit scan
-    constexpr int ACT = NB / PER;                                     // threads taking part in it
-    __shared__ uint32_t s_hist[4][NB];
-    __shared__ uint32_t s_boff[NB];
-    __shared__ int32_t s_glob[NB];
-    __shared__ uint32_t s_part[kSortThreads];
-    __shared__ K s_keys[kSortTile];
-    __shared__ int32_t s_vals[kSortTile];
+    __syncthreads();
     const int64_t n = *n_ptr;
-    const int64_t ntile = ceil_div(n, kSortTile);
-    const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
-    for (int64_t b = blockIdx.x; b < ntile; b += gridDim.x) {
-        for (int d = t; d < NB; d += kSortThreads) {
+    uint32_t* sw = s[wid];
+    for (int64_t base = (int64_t)blockIdx.x * 256 * KPT; base < n; base += (int64_t)gridDim.x * 256 * KPT) {
+        uint32_t k[KPT];
 #pragma unroll
-            for (int w = 0; w < 4; w++) s_hist[w][d] = 0;
+        for (int j = 0; j < KPT; j++) {
+            const int64_t i = base + (int64_t)j * 256 + threadIdx.x;
+            k[j] = i < n ? keys[i] : 0u;
         }
-        __syncthreads();
-        const int64_t start = b * kSortTile + (int64_t)wid * (kSortTile / 4);
-        K key[kSortItems];
-        int32_t val[kSortItems];
-        uint32_t rank[kSortItems];
 #pragma unroll
-        for (int r = 0; r < kSortItems; r++) {
-            const int64_t idx = start + r * 64 + lane;
-            const bool active = idx < n;
-            key[r] = active ? keys_in[idx] : (K)0;
-            val[r] = active ? vals_in[idx] : 0;
-            const uint32_t d = (uint32_t)((key[r] >> shift) & (NB - 1));
-            const uint64_t peers = match_digit<BITS>(d, active);
-            const uint64_t below = peers & ((1ull << lane) - 1ull);
-            const uint32_t base = s_hist[wid][d];
-            rank[r] = base + (uint32_t)__popcll(below);
-            if (active && below == 0) s_hist[wid][d] = base + (uint32_t)__popcll(peers);
-        }
-        __syncthreads();
-        // per digit: exclusive over waves; then exclusive over digits of the block totals
-        uint32_t tot[PER];
-        uint32_t mine = 0;
-        if (t < ACT) {
-#pragma unroll
-            for (int e = 0; e < PER; e++) {
-                const int d = t * PER + e;
-                uint32_t run = 0;
-#pragma unroll
-                for (int w = 0; w < 4; w++) {
-                    const uint32_t c = s_hist[w][d];
-                    s_hist[w][d] = run;
-                    run += c;
+        for (int j = 0; j < KPT; j++) {
+            const bool active = base + (int64_t)j * 256 + threadIdx.x < n;
+            if (!UNIFORM) {
+                if (active)
+                    for (int p = 0; p < passes; p++) atomicAdd(&sw[p * NB + ((k[j] >> (p * BITS)) & (NB - 1))], 1u);
+                continue;
+            }
+            const uint64_t act = __ballot(active);
+            if (act == 0) break;
+            const int lead = __builtin_ctzll(act);
+            for (int p = 0; p < passes; p++) {
+                const uint32_t d = (k[j] >> (p * BITS)) & (NB - 1);
+                const uint32_t d0 = __shfl(d, lead, 64);
+                if (__ballot(active && d == d0) == act) {
+                    if (lane == lead) atomicAdd(&sw[p * NB + d0], (uint32_t)__popcll(act));   // counts only: order-free
+                } else if (active) {
+                    atomicAdd(&sw[p * NB + d], 1u);
                 }
-                tot[e] = run;
-                mine += run;
-                s_glob[d] = count_offs[b * NB + d];
             }
         }
-        // exclusive scan of s_part over the first ACT threads (serial per wave, then waves)
-        uint32_t incl = mine;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < passes * NB; i += 256) {
+        const uint32_t c = s[0][i] + s[1][i] + s[2][i] + s[3][i];
+        if (c) atomicAdd(&hist[i], c);
+    }
+}
+
+// Exclusive scan of each pass's digit counts (one work-group of 512 threads).
+__global__ __launch_bounds__(512) void k_os_scan(uint32_t* __restrict__ hist, int passes, int nb) {
+    __shared__ uint32_t s_w[8];
+    const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
+    for (int p = 0; p < passes; p++) {
+        const uint32_t c = t < nb ? hist[p * nb + t] : 0u;
+        uint32_t incl = c;
 #pragma unroll
         for (int o = 1; o < 64; o <<= 1) {
             const uint32_t u = __shfl_up(incl, o, 64);
             if (lane >= o) incl += u;
         }
+        if (lane == 63) s_w[wid] = incl;
         __syncthreads();
-        if (lane == 63) s_part[wid] = incl;
-        __syncthreads();
-        uint32_t pre = 0;
-        for (int w = 0; w < wid; w++) pre += s_part[w];
-        if (t < ACT) {
-            uint32_t x = pre + incl - mine;
-#pragma unroll
-            for (int e = 0; e < PER; e++) {
-                s_boff[t * PER + e] = x;
-                x += tot[e];
-            }
-        }
-        __syncthreads();
-        const int64_t tile_n = imin(kSortTile, n - b * kSortTile);
-#pragma unroll
-        for (int r = 0; r < kSortItems; r++) {
-            const int64_t idx = start + r * 64 + lane;
-            if (idx < n) {
-                const uint32_t d = (uint32_t)((key[r] >> shift) & (NB - 1));
-                const uint32_t pos = s_boff[d] + s_hist[wid][d] + rank[r];
-                s_keys[pos] = key[r];
-                s_vals[pos] = val[r];
-            }
-        }
-        __syncthreads();
-        for (int64_t i = t; i < tile_n; i += kSortThreads) {
-            const K k = s_keys[i];
-            const uint32_t d = (uint32_t)((k >> shift) & (NB - 1));
-            const int64_t o = (int64_t)s_glob[d] + (i - (int64_t)s_boff[d]);
-            keys_out[o] = k;
-            vals_out[o] = s_vals[i];
-        }
+        uint32_t before = 0;
+        for (int w = 0; w < wid; w++) before += s_w[w];
+        if (t < nb) hist[p * nb + t] = before + incl - c;
         __syncthreads();
     }
 }
 
-// Two-level scan of the tile-major digit counts into output offsets:
-// offset(tile b, digit d) = (keys with a digit below d) + (keys with digit d in
-// tiles before b).  Threads are (chunk, digit) pairs with the digit fastest,
-// so every pass over the counts reads consecutive words.
-__global__ void k_chunk_sums(const int32_t* __restrict__ counts, const int64_t* __restrict__ n_ptr, int nd,
-                             int64_t nch, int32_t* __restrict__ chunk_dm) {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= nch * nd) return;
-    const int64_t c = t / nd;
-    const int d = (int)(t - c * nd);
-    const int64_t ntile = ceil_div(*n_ptr, kSortTile);
-    const int64_t b1 = imin(ntile, (c + 1) * kChunkTiles);
-    int32_t sum = 0;
-    for (int64_t b = c * kChunkTiles; b < b1; b++) sum += counts[b * nd + d];
-    chunk_dm[(int64_t)d * nch + c] = sum;
+// Clears what the passes of one sort count on: the histograms, the look-back
+// error flag and the status words of the tiles the device-side
+// count needs (status is [pass][tile][NB], tile stride NB, pass stride
+// tiles_max NB).
+__global__ void k_os_clear(const int64_t* __restrict__ n_ptr, int passes, int nb, int64_t tiles_max,
+                           unsigned long long* __restrict__ status, uint32_t* __restrict__ hist,
+                           int32_t* __restrict__ err) {
+    const int64_t ntile = imin(ceil_div(*n_ptr, kSortTile), tiles_max);
+    const int64_t words = ntile * nb;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (int p = 0; p < passes; p++)
+        for (int64_t i = i0; i < words; i += stride) status[p * tiles_max * nb + i] = 0ull;
+    for (int64_t i = i0; i < (int64_t)passes * nb; i += stride) hist[i] = 0u;
+    if (i0 == 0) *err = 0;
 }
 
-__global__ void k_tile_offsets(const int32_t* __restrict__ counts, const int32_t* __restrict__ chunk_off,
-                               const int64_t* __restrict__ n_ptr, int nd, int64_t nch, int32_t* __restrict__ offs) {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= nch * nd) return;
-    const int64_t c = t / nd;
-    const int d = (int)(t - c * nd);
-    const int64_t ntile = ceil_div(*n_ptr, kSortTile);
-    const int64_t b1 = imin(ntile, (c + 1) * kChunkTiles);
-    int32_t run = chunk_off[(int64_t)d * nch + c];
-    for (int64_t b = c * kChunkTiles; b < b1; b++) {
-        offs[b * nd + d] = run;
-        run += counts[b * nd + d];
+template <int BITS>
+__global__ __launch_bounds__(kSortThreads) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_onesweep(const uint32_t* __restrict__ keys_in,
+                                                           const int32_t* __restrict__ vals_in,
+                                                           uint32_t* __restrict__ keys_out,
+                                                           int32_t* __restrict__ vals_out,
+                                                           const int64_t* __restrict__ n_ptr, int shift,
+                                                           const uint32_t* __restrict__ digit_base,
+                                                           unsigned long long* __restrict__ status,
+                                                           int32_t* __restrict__ err) {
+    constexpr int NB = 1 << BITS;
+    constexpr int PER = NB >= kSortThreads ? NB / kSortThreads : 1;   // digits per thread
+    constexpr int ACT = NB / PER;                                     // threads owning digits
+    __shared__ uint32_t s_hist[4][NB];      // per-wave digit counts, then each wave's offset inside the digit
+    __shared__ uint32_t s_lstart[NB];       // first position of each digit in the tile
+    __shared__ int32_t s_glob[NB];          // output index of a digit's first pair, less s_lstart
+    __shared__ uint32_t s_part[kSortThreads / 64];
+    __shared__ uint32_t s_keys[kSortTile];
+    __shared__ int32_t s_vals[kSortTile];
+    const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
+    for (int d = t; d < NB; d += kSortThreads) {
+#pragma unroll
+        for (int w = 0; w < 4; w++) s_hist[w][d] = 0;
+    }
+    __syncthreads();
+    const int64_t n = *n_ptr;
+    const int64_t b = blockIdx.x;
+    if (b >= ceil_div(n, kSortTile)) return;
+    uint32_t key[kSortItems];
+    int32_t val[kSortItems];
+    uint32_t rank[kSortItems];
+#pragma unroll
+    for (int r = 0; r < kSortItems; r++) {
+        const int64_t idx = b * kSortTile + (int64_t)wid * (kSortTile / 4) + r * 64 + lane;
+        const bool active = idx < n;
+        key[r] = active ? keys_in[idx] : 0u;
+        val[r] = active ? vals_in[idx] : 0;
+    }
+    const int64_t start = b * kSortTile + (int64_t)wid * (kSortTile / 4);
+#pragma unroll
+    for (int r = 0; r < kSortItems; r++) {
+        const int64_t idx = start + r * 64 + lane;
+        const bool active = idx < n;
+        const uint32_t d = (key[r] >> shift) & (NB - 1);
+        const uint64_t peers = match_digit<BITS>(d, active);
+        const uint64_t below = peers & ((1ull << lane) - 1ull);
+        const uint32_t base = s_hist[wid][d];
+        rank[r] = base + (uint32_t)__popcll(below);
+        if (active && below == 0) s_hist[wid][d] = base + (uint32_t)__popcll(peers);
+    }
+    __syncthreads();
+    // per digit: offsets of the waves inside the digit, the tile's count, and its status word
+    uint32_t tot[PER];
+    uint32_t mine = 0;
+    if (t < ACT) {
+#pragma unroll
+        for (int e = 0; e < PER; e++) {
+            const int d = t * PER + e;
+            uint32_t run = 0;
+#pragma unroll
+            for (int w = 0; w < 4; w++) {
+                const uint32_t c = s_hist[w][d];
+                s_hist[w][d] = run;
+                run += c;
+            }
+            tot[e] = run;
+            mine += run;
+            st_publish(&status[b * NB + d], b == 0 ? kStPre : kStAgg, run);
+        }
+    }
+    // exclusive scan of the tile's digit counts -> s_lstart
+    uint32_t incl = mine;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t u = __shfl_up(incl, o, 64);
+        if (lane >= o) incl += u;
+    }
+    if (lane == 63) s_part[wid] = incl;
+    __syncthreads();
+    uint32_t pre = 0;
+    for (int w = 0; w < wid; w++) pre += s_part[w];
+    if (t < ACT) {
+        uint32_t x = pre + incl - mine;
+#pragma unroll
+        for (int e = 0; e < PER; e++) {
+            s_lstart[t * PER + e] = x;
+            x += tot[e];
+        }
+    }
+    __syncthreads();
+    // the tile's pairs in digit order in LDS (stable: waves, then rounds, then lanes)
+#pragma unroll
+    for (int r = 0; r < kSortItems; r++) {
+        const int64_t idx = start + r * 64 + lane;
+        if (idx < n) {
+            const uint32_t d = (key[r] >> shift) & (NB - 1);
+            const uint32_t pos = s_lstart[d] + s_hist[wid][d] + rank[r];
+            s_keys[pos] = key[r];
+            s_vals[pos] = val[r];
+        }
+    }
+    // look-back: this digit's count over the tiles before b, reading kLookWindow
+    // predecessors at a time (a first wave of work-groups starts together, and
+    // one dependent load per predecessor would make its walks long)
+    if (t < ACT) {
+#pragma unroll
+        for (int e = 0; e < PER; e++) {
+            const int d = t * PER + e;
+            uint32_t excl = 0;
+            if (b > 0) {
+                int64_t k = b - 1;          // newest predecessor not yet added
+                int spins = 0;
+                bool done = false;
+                while (!done) {
+                    unsigned long long w[kLookWindow];
+#pragma unroll
+                    for (int j = 0; j < kLookWindow; j++)
+                        w[j] = k - j >= 0 ? st_read(&status[(k - j) * NB + d]) : 0ull;
+                    // newest first: add counts until a PRE word; stop at a word not published yet
+                    int adv = 0;
+                    bool stop = false;
+#pragma unroll
+                    for (int j = 0; j < kLookWindow; j++) {
+                        const uint32_t flag = (uint32_t)(w[j] >> 32);
+                        if (!stop && !done) {
+                            if (k - j < 0 || flag == 0u) {
+                                stop = true;
+                            } else {
+                                excl += (uint32_t)w[j];
+                                adv = j + 1;
+                                done = flag == kStPre || k - j == 0;
+                            }
+                        }
+                    }
+                    if (done) break;
+                    k -= adv;
+                    if (adv < kLookWindow) {      // waiting on an unpublished word
+                        if (++spins > kLookbackSpins) {     // never in a working chain: report, do not hang
+                            atomicOr(err, 1);
+                            break;
+                        }
+                        __builtin_amdgcn_s_sleep(1);
+                    }
+                }
+                st_publish(&status[b * NB + d], kStPre, excl + tot[e]);
+            }
+            s_glob[d] = (int32_t)(digit_base[d] + excl) - (int32_t)s_lstart[d];
+        }
+    }
+    __syncthreads();
+    const int64_t tile_n = imin(kSortTile, n - b * kSortTile);
+    for (int64_t i = t; i < tile_n; i += kSortThreads) {
+        const uint32_t k = s_keys[i];
+        const int64_t o = (int64_t)s_glob[(k >> shift) & (NB - 1)] + i;
+        keys_out[o] = k;
+        vals_out[o] = s_vals[i];
     }
 }
 
-template <typename K>
-hipError_t radix_pass(int bits, const K* ki, const int32_t* vi, K* ko, int32_t* vo, const int64_t* n_ptr,
-                      int64_t nch, int shift, SortWs& w, unsigned grid, hipStream_t s) {
-    switch (bits) {
-#define PG_PASS(B)                                                                                       \
-    case B:                                                                                              \
-        k_radix_upsweep<K, B><<<grid, kSortThreads, 0, s>>>(ki, n_ptr, shift, w.counts);                 \
+// Bit 1 of the caller's overflow word: some look-back gave up (results undefined).
+__global__ void k_os_report(const int32_t* __restrict__ err, int32_t* __restrict__ overflow) {
+    if (*err) *overflow |= 2;
+}
+
+// Workspace of the onesweep passes of one sort of at most `cap` pairs.
+struct OsWs {
+    unsigned long long* status;
+    uint32_t* hist;
+    int32_t* err;
+    int64_t tiles_max;
+};
+size_t os_ws_bytes(int64_t cap, DigitPlan pl) {
+    const int64_t tiles = imax(ceil_div(imax(cap, 1), kSortTile), 1);
+    return align256((size_t)pl.passes * tiles * ((size_t)1 << pl.digit) * 8) +
+           align256((size_t)kMaxSortPasses * ((size_t)1 << kOsMaxBits) * 4) + align256(4);
+}
+OsWs os_carve(int64_t cap, DigitPlan pl, char* p) {
+    OsWs w{};
+    w.tiles_max = imax(ceil_div(imax(cap, 1), kSortTile), 1);
+    size_t off = 0;
+    w.status = (unsigned long long*)(p + off);
+    off += align256((size_t)pl.passes * w.tiles_max * ((size_t)1 << pl.digit) * 8);
+    w.hist = (uint32_t*)(p + off);
+    off += align256((size_t)kMaxSortPasses * ((size_t)1 << kOsMaxBits) * 4);
+    w.err = (int32_t*)(p + off);
+    return w;
+}
+
+// Stable LSD sort of the *n_ptr (<= cap) pairs in (ka, va) by their low
+// pl.passes * pl.digit key bits, ping-ponging with (kb, vb); the result
+// lands in (ka, va) for an even number of passes, else in (kb, vb).
+// uniform_high: keys whose high digits mostly agree (depth bits), counted with
+// the wave-uniform shortcut.
+hipError_t onesweep_sort(DigitPlan pl, uint32_t* ka, int32_t* va, uint32_t* kb, int32_t* vb, const int64_t* n_ptr,
+                         int64_t cap, OsWs w, int32_t* overflow, bool uniform_high, hipStream_t s) {
+    const int nb = 1 << pl.digit;
+    k_os_clear<<<1024, 256, 0, s>>>(n_ptr, pl.passes, nb, w.tiles_max, w.status, w.hist, w.err);
+    const unsigned hgrid = (unsigned)imax(1, imin(2048, ceil_div(imax(cap, 1), 256 * 16)));
+    switch (pl.digit) {
+#define PG_HIST(B)                                                                                     \
+    case B:                                                                                            \
+        if (uniform_high) k_os_hist<B, true><<<hgrid, 256, 0, s>>>(ka, n_ptr, pl.passes, w.hist);      \
+        else k_os_hist<B, false><<<hgrid, 256, 0, s>>>(ka, n_ptr, pl.passes, w.hist);                  \
         break;
-        PG_PASS(1) PG_PASS(2) PG_PASS(3) PG_PASS(4) PG_PASS(5) PG_PASS(6) PG_PASS(7) PG_PASS(8) PG_PASS(9)
-        PG_PASS(10)
-#undef PG_PASS
+        PG_HIST(1) PG_HIST(2) PG_HIST(3) PG_HIST(4) PG_HIST(5) PG_HIST(6) PG_HIST(7) PG_HIST(8) PG_HIST(9)
+#undef PG_HIST
         default: return hipErrorInvalidValue;
     }
-    const int nd = 1 << bits;
-    const int64_t nth = nch * nd;
-    const unsigned g2 = (unsigned)ceil_div(nth, 256);
-    k_chunk_sums<<<g2, 256, 0, s>>>(w.counts, n_ptr, nd, nch, w.chunk_dm);
-    hipError_t e = scan_i32(w.chunk_dm, w.chunk_off, nullptr, 0, nth, nullptr, w.scan_tmp, s);
-    if (e != hipSuccess) return e;
-    k_tile_offsets<<<g2, 256, 0, s>>>(w.counts, w.chunk_off, n_ptr, nd, nch, w.count_offs);
-    switch (bits) {
-#define PG_PASS(B)                                                                                              \
-    case B:                                                                                                     \
-        k_radix_downsweep<K, B><<<grid, kSortThreads, 0, s>>>(ki, vi, ko, vo, n_ptr, shift, w.count_offs);       \
+    k_os_scan<<<1, 512, 0, s>>>(w.hist, pl.passes, nb);
+    const unsigned grid = (unsigned)w.tiles_max;
+    for (int p = 0; p < pl.passes; p++) {
+        unsigned long long* st = w.status + (int64_t)p * w.tiles_max * nb;
+        switch (pl.digit) {
+#define PG_PASS(B)                                                                                          \
+    case B:                                                                                                 \
+        k_onesweep<B><<<grid, kSortThreads, 0, s>>>(ka, va, kb, vb, n_ptr, p * pl.digit, w.hist + p * nb, st, \
+                                                   w.err);                                                  \
         break;
-        PG_PASS(1) PG_PASS(2) PG_PASS(3) PG_PASS(4) PG_PASS(5) PG_PASS(6) PG_PASS(7) PG_PASS(8) PG_PASS(9)
-        PG_PASS(10)
+            PG_PASS(1) PG_PASS(2) PG_PASS(3) PG_PASS(4) PG_PASS(5) PG_PASS(6) PG_PASS(7) PG_PASS(8) PG_PASS(9)
 #undef PG_PASS
-        default: return hipErrorInvalidValue;
+            default: return hipErrorInvalidValue;
+        }
+        uint32_t* tk = ka; ka = kb; kb = tk;
+        int32_t* tv = va; va = vb; vb = tv;
     }
+    if (overflow) k_os_report<<<1, 1, 0, s>>>(w.err, overflow);
     return hipGetLastError();
 }
 
@@ -676,57 +826,21 @@ hipError_t launch_tile_order(const int32_t* ranges, int64_t n_tiles, int32_t* cn
 // ping-ponged between the two buffer pairs; *out_keys / *out_vals name the
 // pair that holds the result.
 namespace {
-SortWs carve_pairs(int64_t cap, int bits, void* ws, size_t* total) {
-    const int passes = imax((bits + kMaxDigitBits - 1) / kMaxDigitBits, 1);
-    const int digit = (bits + passes - 1) / passes;
-    const int64_t ntile = imax(ceil_div(imax(cap, 1), kSortTile), 1);
-    const int64_t nch = ceil_div(ntile, kChunkTiles);
-    SortWs w{};
-    char* p = (char*)ws;
-    size_t off = 0;
-    auto take = [&](size_t bytes) {
-        char* q = p + off;
-        off += align256(bytes);
-        return q;
-    };
-    w.scan_tmp = (int64_t*)take(kScanTmpWords * 8);
-    w.counts = (int32_t*)take(((int64_t)1 << digit) * ntile * 4);
-    w.count_offs = (int32_t*)take(((int64_t)1 << digit) * ntile * 4);
-    w.chunk_dm = (int32_t*)take(((int64_t)1 << digit) * nch * 4);
-    w.chunk_off = (int32_t*)take(((int64_t)1 << digit) * nch * 4);
-    if (total) *total = off;
-    return w;
-}
 }  // namespace
 
 size_t sort_pairs_ws_bytes(int64_t cap, int bits) {
-    size_t total = 0;
-    carve_pairs(cap, bits, nullptr, &total);
-    return total;
+    return os_ws_bytes(cap, digit_plan(bits, kDepthDigitBits));
 }
 
 hipError_t sort_pairs(uint32_t* keys, int32_t* vals, uint32_t* keys_alt, int32_t* vals_alt, const int64_t* n_dev,
                       int64_t cap, int bits, void* ws, uint32_t** out_keys, int32_t** out_vals, hipStream_t s) {
-    const int passes = imax((bits + kMaxDigitBits - 1) / kMaxDigitBits, 1);
-    const int digit = (bits + passes - 1) / passes;
-    SortWs w = carve_pairs(cap, bits, ws, nullptr);
-    const unsigned grid = (unsigned)imax(1, imin(kSortGrid, ceil_div(cap, kSortTile)));
-    const int64_t nch = ceil_div(imax(ceil_div(imax(cap, 1), kSortTile), 1), kChunkTiles);
-    uint32_t *ka = keys, *kb = keys_alt;
-    int32_t *va = vals, *vb = vals_alt;
-    for (int p = 0; p < passes; p++) {
-        const hipError_t e = radix_pass<uint32_t>(digit, ka, va, kb, vb, n_dev, nch, p * digit, w, grid, s);
-        if (e != hipSuccess) return e;
-        uint32_t* tk = ka;
-        ka = kb;
-        kb = tk;
-        int32_t* tv = va;
-        va = vb;
-        vb = tv;
-    }
-    *out_keys = ka;
-    *out_vals = va;
-    return hipGetLastError();
+    const DigitPlan pl = digit_plan(bits, kDepthDigitBits);
+    const hipError_t e = onesweep_sort(pl, keys, vals, keys_alt, vals_alt, n_dev, cap, os_carve(cap, pl, (char*)ws),
+                                       nullptr, true, s);
+    const bool even = pl.passes % 2 == 0;
+    *out_keys = even ? keys : keys_alt;
+    *out_vals = even ? vals : vals_alt;
+    return e;
 }
 
 size_t sort_ws_bytes(const pg_views* v, int64_t cap) {
@@ -744,6 +858,8 @@ hipError_t launch_bin_sort(const pg_views* v, const pg_bin* bins, const pg_tile_
     const int64_t nb = n_blocks(v);
     hipError_t e = fill_u32(ranges, 0u, 2 * v->n_tiles, s);
     if (e != hipSuccess) return e;
+    e = fill_u32(overflow_dev, 0u, 1, s);      // bit 0: capacity overflow; bit 1: a radix pass gave up waiting
+    if (e != hipSuccess) return e;
     if (v->n_gv == 0) {
         e = fill_u32(w.misc, 0u, 16, s);
         if (e != hipSuccess) return e;
@@ -755,43 +871,32 @@ hipError_t launch_bin_sort(const pg_views* v, const pg_bin* bins, const pg_tile_
         return launch_tile_order(ranges, v->n_tiles, w.order_cnt, w.order_base, w.order_cls, tile_order, s);
     }
     // 1. compact surviving records in (view, id) order, keyed by depth; slot offsets in the same order
-    int32_t *rva = w.rv0, *rvb = w.rv1;
     k_valid_count<<<(unsigned)nb, kBlk, 0, s>>>(bins, v->n_gv, w.blk_a, w.blk_b);
     e = scan_i64(w.blk_a, w.blk_a_off, nullptr, 0, nb, w.misc + 0, w.scan_tmp, s);
     if (e != hipSuccess) return e;
     e = scan_i64(w.blk_b, w.blk_b_off, nullptr, 0, nb, w.misc + 4, w.scan_tmp, s);
     if (e != hipSuccess) return e;
-    k_compact<<<(unsigned)nb, kBlk, 0, s>>>(bins, v->n_gv, w.blk_a_off, w.blk_b_off, w.rk0, rva, inst_first);
+    k_compact<<<(unsigned)nb, kBlk, 0, s>>>(bins, v->n_gv, w.blk_a_off, w.blk_b_off, w.rk0, w.rv0, inst_first);
     // 2. stable LSD sort of the records by depth
-    const unsigned grid_r = (unsigned)imax(1, imin(kSortGrid, ceil_div(v->n_gv, kSortTile)));
-    const int64_t nch_r = ceil_div(imax(ceil_div(v->n_gv, kSortTile), 1), kChunkTiles);
-    uint32_t *rka = w.rk0, *rkb = w.rk1;
-    for (int p = 0; p < pl.d_passes; p++) {
-        e = radix_pass<uint32_t>(pl.d_digit, rka, rva, rkb, rvb, w.misc + 0, nch_r, p * pl.d_digit, w, grid_r, s);
-        if (e != hipSuccess) return e;
-        uint32_t* tk = rka; rka = rkb; rkb = tk;
-        int32_t* tv = rva; rva = rvb; rvb = tv;
-    }
+    e = onesweep_sort(pl.depth, w.rk0, w.rv0, w.rk1, w.rv1, w.misc + 0, v->n_gv, os_carve(v->n_gv, pl.depth, w.os),
+                      overflow_dev, true, s);
+    if (e != hipSuccess) return e;
+    const int32_t* rva = pl.depth.passes % 2 == 0 ? w.rv0 : w.rv1;
     // 3. instance offsets in sorted-record order; overflow check
     k_sorted_count<<<(unsigned)nb, kBlk, 0, s>>>(tiles, rva, w.misc, w.blk_a, w.stiles);
     e = scan_i64(w.blk_a, w.blk_a_off, nullptr, 0, nb, n_inst_dev, w.scan_tmp, s);
     if (e != hipSuccess) return e;
     k_post_count<<<1, 1, 0, s>>>(n_inst_dev, cap, overflow_dev, w.misc);
     // 4. emit (tile, gv) in record order into the buffer that makes the last tile pass land in the caller's arrays
-    uint32_t* ta = (pl.t_passes % 2 == 0) ? keys : w.tk_alt;
-    int32_t* tva = (pl.t_passes % 2 == 0) ? values : w.tv_alt;
-    uint32_t* tb = (pl.t_passes % 2 == 0) ? w.tk_alt : keys;
-    int32_t* tvb = (pl.t_passes % 2 == 0) ? w.tv_alt : values;
+    const bool even = pl.tile.passes % 2 == 0;
+    uint32_t* ta = even ? keys : w.tk_alt;
+    int32_t* tva = even ? values : w.tv_alt;
+    uint32_t* tb = even ? w.tk_alt : keys;
+    int32_t* tvb = even ? w.tv_alt : values;
     k_emit<<<(unsigned)nb, kBlk, 0, s>>>(w.stiles, rva, v->n_gauss, v->d_views, w.blk_a_off, w.misc, ta, tva);
     // 5. stable LSD sort of the instances by tile id
-    const unsigned grid_i = (unsigned)imax(1, imin(kSortGrid, ceil_div(cap, kSortTile)));
-    const int64_t nch_i = ceil_div(imax(ceil_div(cap, kSortTile), 1), kChunkTiles);
-    for (int p = 0; p < pl.t_passes; p++) {
-        e = radix_pass<uint32_t>(pl.t_digit, ta, tva, tb, tvb, w.misc + 1, nch_i, p * pl.t_digit, w, grid_i, s);
-        if (e != hipSuccess) return e;
-        uint32_t* tk = ta; ta = tb; tb = tk;
-        int32_t* tv = tva; tva = tvb; tvb = tv;
-    }
+    e = onesweep_sort(pl.tile, ta, tva, tb, tvb, w.misc + 1, cap, os_carve(cap, pl.tile, w.os), overflow_dev, false, s);
+    if (e != hipSuccess) return e;
     k_ranges<<<(unsigned)imax(1, imin(kRangeGrid, ceil_div(cap, 256))), 256, 0, s>>>(keys, w.misc, ranges);
     e = launch_tile_order(ranges, v->n_tiles, w.order_cnt, w.order_base, w.order_cls, tile_order, s);
     if (e != hipSuccess) return e;

@@ -71,29 +71,95 @@ __global__ __launch_bounds__(kLossBlocks) void k_l1_final(const double* __restri
     if (threadIdx.x == 0) *loss = (float)(s[0] / (double)n);
 }
 
-__global__ __launch_bounds__(256) void k_adam(float* __restrict__ p, const float* __restrict__ g,
-                                              float* __restrict__ m, float* __restrict__ v,
-                                              const uint8_t* __restrict__ visible,
-                                              const int32_t* __restrict__ texel_gauss, int64_t N, int32_t C,
-                                              int64_t HW, int64_t total, float lr, float b1, float b2, float eps,
-                                              float inv_c1, float inv_c2, const int32_t* __restrict__ step_dev) {
+// One Adam update of element (p, g, m, v); the same expression for every
+// element and both launch shapes below.
+__device__ __forceinline__ void adam_elem(float& p, float g, float& m, float& v, float lr, float b1, float b2,
+                                          float eps, float inv_c1, float inv_c2) {
+    const float mm = b1 * m + (1.0f - b1) * g;
+    const float vv = b2 * v + (1.0f - b2) * g * g;
+    m = mm;
+    v = vv;
+    p = p - lr * (mm * inv_c1) / (sqrtf(vv * inv_c2) + eps);
+}
+
+__device__ __forceinline__ void bias_corrections(const int32_t* step_dev, float b1, float b2, float& inv_c1,
+                                                 float& inv_c2) {
     if (step_dev) {   // bias correction of the device-counted step
         const double t = (double)*step_dev;
         inv_c1 = (float)(1.0 / (1.0 - pow((double)b1, t)));
         inv_c2 = (float)(1.0 / (1.0 - pow((double)b2, t)));
     }
-    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
-         e += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t texel = e % HW;
-        const int64_t f = e / (HW * C);
-        const int32_t id = texel_gauss[texel];
-        if (id < 0 || !visible[f * N + id]) continue;
-        const float gr = g[e];
-        const float mm = b1 * m[e] + (1.0f - b1) * gr;
-        const float vv = b2 * v[e] + (1.0f - b2) * gr * gr;
-        m[e] = mm;
-        v[e] = vv;
-        p[e] = p[e] - lr * (mm * inv_c1) / (sqrtf(vv * inv_c2) + eps);
+}
+
+// Texel-major sparse Adam: a thread owns TPT consecutive texels of one frame
+// (blockIdx.y), looks their Gaussians and visibility up once, and walks the
+// C channel planes; texels whose Gaussian is not visible read and write
+// nothing.  VEC (TPT = 4): the four texels' channel values move as one
+// 16-byte access (planes 16-byte aligned: H W % 4 == 0 and aligned buffers);
+// then only planes where all four are invisible are skipped, and invisible
+// lanes of a visible quad are written back unchanged.
+template <bool VEC>
+__global__ __launch_bounds__(256) void k_adam(float* __restrict__ p, const float* __restrict__ g,
+                                              float* __restrict__ m, float* __restrict__ v,
+                                              const uint8_t* __restrict__ visible,
+                                              const int32_t* __restrict__ texel_gauss, int64_t N, int32_t C,
+                                              int64_t HW, float lr, float b1, float b2, float eps, float inv_c1,
+                                              float inv_c2, const int32_t* __restrict__ step_dev) {
+    constexpr int TPT = VEC ? 4 : 1;
+    bias_corrections(step_dev, b1, b2, inv_c1, inv_c2);
+    const int64_t f = blockIdx.y;
+    const int64_t t0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * TPT;
+    if (t0 >= HW) return;
+    bool on[TPT];
+    bool any = false;
+#pragma unroll
+    for (int k = 0; k < TPT; k++) {
+        const int32_t id = (t0 + k < HW) ? texel_gauss[t0 + k] : -1;
+        on[k] = id >= 0 && visible[f * N + id] != 0;
+        any |= on[k];
+    }
+    if (!any) return;
+    const int64_t plane0 = f * (int64_t)C * HW + t0;
+    if (VEC) {
+        // channels in groups of CG: every load of a group is issued before its
+        // arithmetic, so each wave keeps 4 CG 16-byte loads in flight
+        constexpr int CG = 4;
+        auto group = [&](const int32_t c0, const int ng) __attribute__((always_inline)) {
+            float4 gr[CG], pp[CG], mm[CG], vv[CG];
+#pragma unroll
+            for (int k = 0; k < CG; k++) {
+                if (k >= ng) break;
+                const int64_t e = plane0 + (int64_t)(c0 + k) * HW;
+                gr[k] = *reinterpret_cast<const float4*>(g + e);
+                pp[k] = *reinterpret_cast<const float4*>(p + e);
+                mm[k] = *reinterpret_cast<const float4*>(m + e);
+                vv[k] = *reinterpret_cast<const float4*>(v + e);
+            }
+#pragma unroll
+            for (int k = 0; k < CG; k++) {
+                if (k >= ng) break;
+                if (on[0]) adam_elem(pp[k].x, gr[k].x, mm[k].x, vv[k].x, lr, b1, b2, eps, inv_c1, inv_c2);
+                if (on[1]) adam_elem(pp[k].y, gr[k].y, mm[k].y, vv[k].y, lr, b1, b2, eps, inv_c1, inv_c2);
+                if (on[2]) adam_elem(pp[k].z, gr[k].z, mm[k].z, vv[k].z, lr, b1, b2, eps, inv_c1, inv_c2);
+                if (on[3]) adam_elem(pp[k].w, gr[k].w, mm[k].w, vv[k].w, lr, b1, b2, eps, inv_c1, inv_c2);
+                const int64_t e = plane0 + (int64_t)(c0 + k) * HW;
+                *reinterpret_cast<float4*>(p + e) = pp[k];
+                *reinterpret_cast<float4*>(m + e) = mm[k];
+                *reinterpret_cast<float4*>(v + e) = vv[k];
+            }
+        };
+        int32_t c = 0;
+        for (; c + CG <= C; c += CG) group(c, CG);
+        if (c < C) group(c, C - c);
+    } else {
+        for (int32_t c = 0; c < C; c++) {
+            const int64_t e = plane0 + (int64_t)c * HW;
+            float pp = p[e], mm = m[e], vv = v[e];
+            adam_elem(pp, g[e], mm, vv, lr, b1, b2, eps, inv_c1, inv_c2);
+            p[e] = pp;
+            m[e] = mm;
+            v[e] = vv;
+        }
     }
 }
 
@@ -115,14 +181,20 @@ hipError_t launch_adam(float* atlas, const float* grad, float* m, float* v, cons
                        const int32_t* texel_gauss, int64_t n_gauss, int32_t F, int32_t C, int32_t H, int32_t W,
                        float lr, float b1, float b2, float eps, int32_t step, int32_t* step_dev, hipStream_t s) {
     const int64_t HW = (int64_t)H * W;
-    const int64_t total = (int64_t)F * C * HW;
     if (step_dev) k_step_inc<<<1, 1, 0, s>>>(step_dev);
-    if (total == 0) return hipGetLastError();
+    if (HW == 0) return hipGetLastError();
     const double c1 = step_dev ? 1.0 : 1.0 - pow((double)b1, (double)step);
     const double c2 = step_dev ? 1.0 : 1.0 - pow((double)b2, (double)step);
-    const unsigned grid = (unsigned)imin(ceil_div(total, 256), 8192);
-    k_adam<<<grid, 256, 0, s>>>(atlas, grad, m, v, visible, texel_gauss, n_gauss, C, HW, total, lr, b1, b2, eps,
-                                (float)(1.0 / c1), (float)(1.0 / c2), step_dev);
+    const bool vec = HW % 4 == 0 && ((reinterpret_cast<uintptr_t>(atlas) | reinterpret_cast<uintptr_t>(grad) |
+                                      reinterpret_cast<uintptr_t>(m) | reinterpret_cast<uintptr_t>(v)) & 15) == 0;
+    const int64_t threads = vec ? HW / 4 : HW;
+    const dim3 grid((unsigned)ceil_div(threads, 256), (unsigned)F);
+    if (vec)
+        k_adam<true><<<grid, 256, 0, s>>>(atlas, grad, m, v, visible, texel_gauss, n_gauss, C, HW, lr, b1, b2, eps,
+                                          (float)(1.0 / c1), (float)(1.0 / c2), step_dev);
+    else
+        k_adam<false><<<grid, 256, 0, s>>>(atlas, grad, m, v, visible, texel_gauss, n_gauss, C, HW, lr, b1, b2, eps,
+                                           (float)(1.0 / c1), (float)(1.0 / c2), step_dev);
     return hipGetLastError();
 }
 

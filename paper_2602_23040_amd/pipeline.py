@@ -251,8 +251,9 @@ class Renderer:
                         s.inst_grad, s.ws, s.ws_bytes)
         if not self.batched and self.plain_sync:
             # plain path: one instance-count synchronisation per view
-            if int(s.overflow.item()):
-                s.set_capacity(int(math.ceil(int(s.n_inst.item()) * 1.25)))
+            ovf, need = abi.pg_status_check(s.overflow, s.n_inst)      # raises if a sort pass failed
+            if ovf:
+                s.set_capacity(int(math.ceil(need * 1.25)))
                 abi.pg_bin_sort(s.handle, s.bins, s.tiles, s.cap, s.keys, s.values, s.ranges, self._order(s), s.inst_first, s.n_inst,
                                 s.overflow, s.inst_grad, s.ws, s.ws_bytes)
         abi.pg_render_fwd(s.handle, s.splats, s.values, s.ranges, self._order(s), self.bg, self._off(self.image, 3 * pix_off),

@@ -176,8 +176,16 @@ def test_loss_l1_parity():
     r.close()
 
 
-def test_adam_parity():
-    sc, fw = case("multiframe")
+@pytest.mark.parametrize("name", ["multiframe", "odd_atlas"])
+def test_adam_parity(name):
+    """Sparse Adam against the oracle over three steps: a 10 x 10 atlas
+    (16-byte texel quads) and a 9 x 9 one (one texel per thread)."""
+    if name == "odd_atlas":
+        sc = synth.random_scene(side=9, sh_degree=1, views=2, width=64, height=50, seed=9, frames=2,
+                                occupancy=0.8, lscale=(-2.7, 0.5))
+        fw = oracle.Forward(sc)
+    else:
+        sc, fw = case(name)
     r = renderer(sc)
     atlas = atlas_tensor(sc)
     run_forward(r, atlas)
