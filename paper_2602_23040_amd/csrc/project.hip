@@ -615,19 +615,27 @@ __global__ __launch_bounds__(128) void k_project_bwd_geo(const ViewDev* __restri
     for (int k = 0; k < 9; k++) GSw_sum[k] = 0.0;
     World w;
     bool have_world = false;
+    // the record's slot sums (0 for culled records): the compositing moments
+    // sum dq' (dx, dy, dx^2, dx dy, dy^2) with dq' = alpha dL/dalpha, and dL/do;
+    // the next view's are loaded while this view's are used
+    float nxt[6];
+    auto load6 = [&](int32_t vi) __attribute__((always_inline)) {
+        const int64_t gv = (int64_t)view_order[vi] * N + i;
+#pragma unroll
+        for (int k = 0; k < 6; k++) nxt[k] = grad2d[(int64_t)k * n_gv + gv];
+    };
+    if (v0 < v1) load6(v0);
     for (int32_t vi = v0; vi < v1; vi++) {
         const int32_t v = view_order[vi];
         const int64_t gv = (int64_t)v * N + i;
-        // the record's slot sums (0 for culled records): the compositing moments
-        // sum dq' (dx, dy, dx^2, dx dy, dy^2) with dq' = alpha dL/dalpha, and dL/do
         double g6[6];
         bool nz = false;
 #pragma unroll
         for (int k = 0; k < 6; k++) {
-            const float x = grad2d[(int64_t)k * n_gv + gv];
-            g6[k] = (double)x;
-            nz |= (x != 0.0f);
+            g6[k] = (double)nxt[k];
+            nz |= (nxt[k] != 0.0f);
         }
+        if (vi + 1 < v1) load6(vi + 1);
         if (!nz) continue;
         if (!have_world) {
             world_chain(rec, w);
@@ -773,12 +781,17 @@ __global__ __launch_bounds__(128) void k_project_bwd_sh(const ViewDev* __restric
     float acc[3 * NB], gmu[3] = {0.0f, 0.0f, 0.0f};
 #pragma unroll
     for (int k = 0; k < 3 * NB; k++) acc[k] = 0.0f;
+    float nxt[3];     // the next view's colour gradients, loaded while this view's are used
+    auto load3 = [&](int32_t vi) __attribute__((always_inline)) {
+        const int64_t gv = (int64_t)view_order[vi] * N + i;
+#pragma unroll
+        for (int ch = 0; ch < 3; ch++) nxt[ch] = grad2d[(int64_t)(6 + ch) * n_gv + gv];
+    };
+    if (v0 < v1) load3(v0);
     for (int32_t vi = v0; vi < v1; vi++) {
         const int32_t v = view_order[vi];
-        const int64_t gv = (int64_t)v * N + i;
-        float gcol[3];
-#pragma unroll
-        for (int ch = 0; ch < 3; ch++) gcol[ch] = grad2d[(int64_t)(6 + ch) * n_gv + gv];
+        const float gcol[3] = {nxt[0], nxt[1], nxt[2]};
+        if (vi + 1 < v1) load3(vi + 1);
         if (gcol[0] == 0.0f && gcol[1] == 0.0f && gcol[2] == 0.0f) continue;
         const ViewDev& V = views[v];
         double dd64[3], dn64;
