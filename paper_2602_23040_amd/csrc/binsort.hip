@@ -234,65 +234,77 @@ __global__ void k_post_count(const int64_t* n_inst, int64_t cap, int32_t* overfl
 }
 
 
-// Emission in sorted-record order: the group's output range is written
-// contiguously; each lane finds its (record, kept tile) by binary search over
-// the group's prefix sums, then the tile's rectangle bit from the kept-tile
-// mask.  Per record the group keeps, in LDS, the global tile id of the
-// rectangle's first tile, the rectangle width, the row stride of the view's
-// tile grid and the mask, so an instance costs one small division.
+// Emission in sorted-record order.  The group's 1024 records own consecutive
+// output ranges (their kept-tile counts scanned over the group); each thread
+// walks its own record's kept-tile bits in increasing order (row-major over
+// the rectangle) and writes (tile, gv) at its range, so an instance costs a
+// bit scan and one small division.  The lanes of a wave write into one
+// window of the output a few hundred instances long.  Records keeping every
+// tile of a rectangle larger than 64 tiles are rare and long: their waves
+// emit them one after another, all 64 lanes on one record.
+__device__ __forceinline__ void rect_tile(int32_t k, int32_t w, float rw, int32_t& row, int32_t& col) {
+    // row = k / w from a float estimate (k < 2^24), corrected to the exact quotient
+    row = (int32_t)((float)k * rw);
+    col = k - row * w;
+    if (col < 0) { row--; col += w; }
+    else if (col >= w) { row++; col -= w; }
+}
+
 __global__ __launch_bounds__(kBlk) void k_emit(const uint4* __restrict__ stiles, const int32_t* __restrict__ rv,
                                                int64_t N, const ViewDev* __restrict__ views,
                                                const int64_t* __restrict__ blk_off, const int64_t* __restrict__ misc,
                                                uint32_t* __restrict__ tkeys, int32_t* __restrict__ tvals) {
-    __shared__ int32_t s_incl[kBlk];
-    __shared__ uint32_t s_tile0[kBlk];     // global tile id of the rectangle's first (top-left) tile
-    __shared__ int32_t s_w[kBlk];          // rectangle width in tiles
-    __shared__ int32_t s_tx[kBlk];         // tiles per row of the view
-    __shared__ float s_rw[kBlk];           // 1 / width
-    __shared__ int32_t s_gv[kBlk];
-    __shared__ uint64_t s_mask[kBlk];
     __shared__ int32_t s_warp[kBlk / 64];
     if (misc[1] == 0) return;   // overflow (or nothing to emit): uniform exit
-    const int t = threadIdx.x;
+    const int t = threadIdx.x, lane = t & 63;
     const int64_t p = (int64_t)blockIdx.x * kBlk + t;
-    int32_t nt = 0;
+    int32_t nt = 0, gv = 0, w = 1, tx = 0;
+    uint32_t tile0 = 0u;
+    uint64_t mask = 0;
     if (p < misc[0]) {
-        const int32_t gv = rv[p];
+        gv = rv[p];
         const uint4 ts = stiles[p];
         nt = kept_count(ts);
         const int32_t xlo = (int32_t)(ts.z & 0xffff), ylo = (int32_t)(ts.z >> 16);
         const ViewDev& V = views[gv / N];
-        const int32_t w = (int32_t)(ts.w & 0xffff);
-        s_tile0[t] = (uint32_t)(V.tile_base + (int64_t)ylo * V.TX + xlo);
-        s_w[t] = w;
-        s_tx[t] = V.TX;
-        s_rw[t] = 1.0f / (float)w;
-        s_gv[t] = gv;
-        s_mask[t] = (uint64_t)ts.x | ((uint64_t)ts.y << 32);
+        w = (int32_t)(ts.w & 0xffff);
+        tx = V.TX;
+        tile0 = (uint32_t)(V.tile_base + (int64_t)ylo * V.TX + xlo);
+        mask = (uint64_t)ts.x | ((uint64_t)ts.y << 32);
     }
-    s_incl[t] = block_incl_1024(nt, s_warp);
-    __syncthreads();
-    const int32_t total = s_incl[kBlk - 1];
-    const int64_t base = blk_off[blockIdx.x];
-    for (int32_t q = t; q < total; q += kBlk) {
-        int lo = 0, hi = kBlk - 1;     // first j with s_incl[j] > q
-        while (lo < hi) {
-            const int mid = (lo + hi) >> 1;
-            if (s_incl[mid] > q) hi = mid; else lo = mid + 1;
+    const int32_t incl = block_incl_1024(nt, s_warp);
+    const int64_t e0 = blk_off[blockIdx.x] + incl - nt;     // this record's first output
+    const float rw = 1.0f / (float)w;
+    if (mask != 0) {
+        uint64_t m = mask;
+        for (int64_t e = e0; m != 0; e++) {
+            const int32_t bit = (int32_t)__builtin_ctzll(m);
+            m &= m - 1;
+            int32_t row, col;
+            rect_tile(bit, w, rw, row, col);
+            tkeys[e] = tile0 + (uint32_t)(row * tx + col);
+            tvals[e] = gv;
         }
-        const int32_t k = kept_select(s_mask[lo], q - (lo ? s_incl[lo - 1] : 0));
-        const int32_t w = s_w[lo];
-        // row = k / w from a float estimate (k < 2^24), corrected to the exact quotient
-        int32_t row = (int32_t)((float)k * s_rw[lo]);
-        int32_t col = k - row * w;
-        if (col < 0) { row--; col += w; }
-        else if (col >= w) { row++; col -= w; }
-        tkeys[base + q] = s_tile0[lo] + (uint32_t)(row * s_tx[lo] + col);
-        tvals[base + q] = s_gv[lo];
+    }
+    // records that keep every tile of their rectangle, one at a time per wave
+    uint64_t big = __ballot(mask == 0 && nt > 0);
+    while (big) {
+        const int src = __builtin_ctzll(big);
+        big &= big - 1;
+        const int32_t bn = __shfl(nt, src, 64), bw = __shfl(w, src, 64), btx = __shfl(tx, src, 64);
+        const int32_t bgv = __shfl(gv, src, 64);
+        const uint32_t bt0 = (uint32_t)__shfl((int)tile0, src, 64);
+        const int64_t be0 = __shfl(e0, src, 64);
+        const float brw = 1.0f / (float)bw;
+        for (int32_t k = lane; k < bn; k += 64) {
+            int32_t row, col;
+            rect_tile(k, bw, brw, row, col);
+            tkeys[be0 + k] = bt0 + (uint32_t)(row * btx + col);
+            tvals[be0 + k] = bgv;
+        }
     }
 }
 
-// ------------------------------------------------------------------ LSD radix pass
 // Peers of this lane: active lanes holding the same BITS-bit digit.  Per
 // bit, the ballot of the lanes that have it set, flipped where this lane's
 // bit is clear, marks the lanes that differ from it in that bit; a peer

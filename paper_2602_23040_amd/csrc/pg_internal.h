@@ -165,24 +165,6 @@ __device__ __forceinline__ int32_t kept_rank(uint64_t mask, int32_t bit) {
     return mask ? (int32_t)__popcll(mask & (((uint64_t)1 << bit) - 1)) : bit;
 }
 
-// Rectangle bit of the k-th kept tile (k < number kept): halving search on
-// bit counts.
-__device__ __forceinline__ int32_t kept_select(uint64_t mask, int32_t k) {
-    if (!mask) return k;
-    int32_t pos = 0;
-#pragma unroll
-    for (int wdt = 32; wdt >= 1; wdt >>= 1) {
-        const uint64_t low = mask & ((((uint64_t)1) << wdt) - 1);
-        const int32_t c = (int32_t)__popcll(low);
-        if (k >= c) {
-            k -= c;
-            mask >>= wdt;
-            pos += wdt;
-        }
-    }
-    return pos;
-}
-
 // Cross-lane data-parallel-primitive move of a float: lanes of rows disabled
 // by ROW_MASK read 0 (control codes: quad_perm 0x00-0xFF, row_ror:n 0x120+n,
 // row_mirror 0x140, row_half_mirror 0x141, row_bcast:15 0x142, row_bcast:31 0x143).
