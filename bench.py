@@ -156,7 +156,7 @@ def main():
     rb.forward(atlas, counters=True)
     torch.cuda.synchronize()
     n_eval, n_comp = (int(x) for x in rb.counters.cpu().tolist())
-    n_inst = int(rb.sets[0].n_inst.item())
+    n_inst = int(rb.sets[0].n_inst[0].item())
     P = rb.n_pixels
 
     stream = torch.cuda.current_stream()
@@ -593,7 +593,7 @@ def other_config(cfg, tiling, steps, warmup):
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / steps
     assert rb.check(), f"config {cfg}: instance capacity overflowed inside the timed region"
-    n_inst = int(rb.sets[0].n_inst.item())
+    n_inst = int(rb.sets[0].n_inst[0].item())
     P = rb.n_pixels
     adam_info = None
     if adam:
@@ -647,7 +647,7 @@ def stage_times(r, atlas, target, reps=5):
         "fetch": lambda: r.fetch(atlas),
         "project": lambda: abi.pg_project(s.handle, r.params, s.splats, s.bins, s.tiles, r.visible, stream),
         "bin_sort": lambda: abi.pg_bin_sort(s.handle, s.bins, s.tiles, s.cap, s.keys, s.values, s.ranges, s.order, s.inst_first,
-                                            s.n_inst, s.overflow, s.inst_grad, s.ws, s.ws_bytes, stream),
+                                            s.n_inst, s.overflow, s.ws, s.ws_bytes, stream),
         "render_fwd": lambda: abi.pg_render_fwd(s.handle, s.splats, s.values, s.ranges, s.order, r.bg, r.image, r.final_T,
                                                 r.n_contrib, s.tile_entries, s.entries, None, stream),
         "loss_l1": lambda: r.loss_l1(target),

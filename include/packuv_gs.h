@@ -160,7 +160,8 @@ pg_status pg_sort_workspace_size(const pg_views* views, int64_t inst_capacity, s
 typedef struct pg_plan {
     size_t params, gauss_texel, texel_gauss, n_gauss, fetch_ws;        /* pg_atlas_fetch */
     size_t visible, splats, bins, tile_sets;                           /* pg_project */
-    size_t keys, values, tile_ranges, tile_order, inst_first, n_inst, overflow, sort_ws, inst_grad;  /* pg_bin_sort */
+    size_t keys, values, tile_ranges, tile_order, inst_first, n_inst, overflow, sort_ws;  /* pg_bin_sort */
+    size_t inst_grad;                                                  /* the adjoint's gradient slots */
     size_t image, final_T, n_contrib, tile_entries, entries;           /* pg_render_fwd */
     size_t dL_dimage;                                                  /* loss cotangent */
     size_t grad2d, dL_datlas;                                          /* pg_backward */
@@ -344,18 +345,21 @@ pg_status pg_flow_mask(const pg_views* views, const float* params, const uint8_t
  *                  records before gv in (view, id) order.  The adjoint keeps
  *                  one gradient slot per instance, record by record in that
  *                  order, the record's kept tiles in rectangle row-major order.
- *   n_inst_dev     device int64 [1] out: number of instances
+ *   n_inst_dev     device int64 [2] in/out: [0] out: number of instances;
+ *                  [1] the sort generation, advanced by one (skipping 0) on
+ *                  every call.  The adjoint tags the gradient slots it writes
+ *                  with it, and slots with another tag read as zero, so the
+ *                  slots are never cleared: allocate n_inst_dev and the
+ *                  slots (pg_render_bwd's inst_grad) zero-filled once.
  *   overflow_dev   device int32 [1] out: bit 0 set if n_inst > inst_capacity;
  *                  bit 1 set if a radix pass gave up waiting on an earlier
  *                  tile's counts (never in a working run; pg_status_check
  *                  then returns PG_ERR_HIP); 0 otherwise
- *   inst_grad      device float [inst_capacity][9] or NULL: the adjoint's
- *                  per-instance gradient slots; the first n_inst are zeroed
  *   ws             device workspace of pg_sort_workspace_size bytes */
 pg_status pg_bin_sort(const pg_views* views, const pg_bin* bins, const pg_tile_set* tiles, int64_t inst_capacity,
                       uint32_t* keys,
                       int32_t* values, int32_t* tile_ranges, int32_t* tile_order, int32_t* inst_first,
-                      int64_t* n_inst_dev, int32_t* overflow_dev, float* inst_grad, void* ws, size_t ws_bytes,
+                      int64_t* n_inst_dev, int32_t* overflow_dev, void* ws, size_t ws_bytes,
                       void* stream);
 
 /* a4 -- Front-to-back compositing (supplementary viewer section:
@@ -395,15 +399,19 @@ pg_status pg_render_fwd(const pg_views* views, const pg_splat* splats, const int
  * dL/dq = -dq'/2) and (dx, dy) = pixel - mean, the nine floats are
  * sum dq' dx, sum dq' dy, sum dq' dx^2, sum dq' dx dy, sum dq' dy^2, dL/dopacity
  * and dL/d(r, g, b).  The mean and conic gradients are linear in the first
- * five; pg_project_bwd forms them per record.  Slots of instances that composited nothing are not written:
- * they keep the zero pg_bin_sort gave them.
+ * five; pg_project_bwd forms them per record.  A slot is 10 words: the
+ * nine sums, then the sort generation (n_inst_dev[1], as uint32 bits) that
+ * marks it as written by this step.  Slots of instances that composited
+ * nothing are not written: they keep an older tag (or the zero of a
+ * zero-filled buffer) and pg_project_bwd counts them as zero.
  *   tile_ranges, tile_order   as for pg_render_fwd
  *   tiles, inst_first, n_inst_dev   from pg_project / pg_bin_sort; after an
  *                overflowed sort (n_inst > inst_capacity) no slot is written
  *   tile_entries, entries, n_contrib, final_T   from pg_render_fwd
  *   dL_dimage    device float [3 n_pixels]
  *   inst_capacity the capacity given to pg_bin_sort
- *   inst_grad    device float [inst_capacity][9] in/out (zeroed by pg_bin_sort), slot inst_first[gv] + k
+ *   inst_grad    device float [inst_capacity][10] in/out, zero-filled when
+ *                allocated (never cleared afterwards), slot inst_first[gv] + k
  *                for the k-th kept tile (row-major) of record gv's rectangle */
 pg_status pg_render_bwd(const pg_views* views, const pg_splat* splats, const pg_tile_set* tiles,
                         const int32_t* values, const int32_t* tile_ranges, const int32_t* tile_order,
@@ -420,7 +428,8 @@ pg_status pg_render_bwd(const pg_views* views, const pg_splat* splats, const pg_
  * the SH colour of every view of the Gaussian's frame.
  *   bins, inst_first, n_inst_dev   from pg_project / pg_bin_sort;
  *                after an overflowed sort the texel gradient is zero
- *   inst_grad    device float [inst_capacity][9] from pg_render_bwd
+ *   inst_grad    device float [inst_capacity][10] from pg_render_bwd; a slot
+ *                counts only when its tag is the current sort generation
  *   gauss_texel  device int32 [n_gauss] (from pg_atlas_fetch)
  *   dynamic_mask device uint8 [H][W] or NULL (NULL: every Gaussian dynamic)
  *   grad2d       device float [9][n_gv] out: per (view, Gaussian) dL/d(m_x,

@@ -17,6 +17,7 @@ STATUS_NAMES = {0: "PG_OK", -1: "PG_ERR_INVALID_ARG", -2: "PG_ERR_UNSUPPORTED_DE
                 -4: "PG_ERR_HIP", -5: "PG_ERR_WORKSPACE"}
 
 SPLAT_BYTES = 48
+SLOT_WORDS = 10             # words of one per-instance gradient slot (nine sums and the generation tag)
 BIN_BYTES = 16
 QUANT_BLOCKS = 256          # PG_QUANT_BLOCKS: the fake quantiser's workspace is 2 * QUANT_BLOCKS * C floats
 REG_BLOCKS = 256            # PG_REG_BLOCKS: the regularisers' workspace is 3 * REG_BLOCKS + 1 doubles
@@ -75,7 +76,7 @@ SIGNATURES = {
     "pg_atlas_fake_quant": (_i32, [_p, _p, _i64, _i32, _i32, _p, _p, _p, _p, _p]),
     "pg_project": (_i32, [_p, _p, _p, _p, _p, _p, _p]),
     "pg_flow_mask": (_i32, [_p, _p, _p, _p, _p, _p, _i32, _i32, _p, _p, _p]),
-    "pg_bin_sort": (_i32, [_p, _p, _p, _i64, _p, _p, _p, _p, _p, _p, _p, _p, _p, _sz, _p]),
+    "pg_bin_sort": (_i32, [_p, _p, _p, _i64, _p, _p, _p, _p, _p, _p, _p, _p, _sz, _p]),
     "pg_render_fwd": (_i32, [_p, _p, _p, _p, _p, _p, _p, _p, _p, _p, _p, _p, _p]),
     "pg_render_bwd": (_i32, [_p, _p, _p, _p, _p, _p, _p, _p, _i64, _p, _p, _p, _p, _p, _p, _p, _p]),
     "pg_project_bwd": (_i32, [_p, _p, _p, _p, _p, _i64, _p, _p, _p, _i32, _i32, _p, _p, _i32, _p]),
@@ -248,9 +249,9 @@ def pg_project(views, params, splats, bins, tiles, visible, stream=None):
 
 
 def pg_bin_sort(views, bins, tiles, inst_capacity, keys, values, tile_ranges, tile_order, inst_first, n_inst_dev,
-                overflow_dev, inst_grad, ws, ws_bytes, stream=None):
+                overflow_dev, ws, ws_bytes, stream=None):
     _check(lib().pg_bin_sort(views, _ptr(bins), _ptr(tiles), int(inst_capacity), _ptr(keys), _ptr(values), _ptr(tile_ranges),
-                             _ptr(tile_order), _ptr(inst_first), _ptr(n_inst_dev), _ptr(overflow_dev), _ptr(inst_grad), _ptr(ws),
+                             _ptr(tile_order), _ptr(inst_first), _ptr(n_inst_dev), _ptr(overflow_dev), _ptr(ws),
                              int(ws_bytes),
                              _stream(stream)), "pg_bin_sort")
 

@@ -321,7 +321,7 @@ pg_status pg_project(const pg_views* v, const float* params, pg_splat* splats, p
 pg_status pg_bin_sort(const pg_views* v, const pg_bin* bins, const pg_tile_set* tiles, int64_t cap, uint32_t* keys,
                       int32_t* values,
                       int32_t* tile_ranges, int32_t* tile_order, int32_t* inst_first, int64_t* n_inst_dev, int32_t* overflow_dev,
-                      float* inst_grad, void* ws, size_t ws_bytes, void* stream) {
+                      void* ws, size_t ws_bytes, void* stream) {
     g_error.clear();
     if (!v) return invalid("views is null");
     if (!tile_ranges || !n_inst_dev || !overflow_dev || !ws) return invalid("null pointer argument");
@@ -333,7 +333,7 @@ pg_status pg_bin_sort(const pg_views* v, const pg_bin* bins, const pg_tile_set* 
         return PG_ERR_WORKSPACE;
     }
     PG_CHECK_HIP(launch_bin_sort(v, bins, tiles, cap, keys, values, tile_ranges, tile_order, inst_first, n_inst_dev, overflow_dev,
-                                 inst_grad, ws, (hipStream_t)stream),
+                                 ws, (hipStream_t)stream),
                  "pg_bin_sort");
     return PG_OK;
 }
@@ -468,10 +468,10 @@ pg_status pg_workspace_query(const pg_views* v, int32_t H, int32_t W, int64_t in
     plan->tile_ranges = 2 * T * sizeof(int32_t);
     plan->tile_order = T * sizeof(int32_t);
     plan->inst_first = gv * sizeof(int32_t);
-    plan->n_inst = sizeof(int64_t);
+    plan->n_inst = 2 * sizeof(int64_t);
     plan->overflow = sizeof(int32_t);
     plan->sort_ws = sort_ws_bytes(v, inst_capacity);
-    plan->inst_grad = 9 * cap * sizeof(float);
+    plan->inst_grad = (size_t)kSlotWords * cap * sizeof(float);
     plan->image = 3 * P * sizeof(float);
     plan->final_T = P * sizeof(float);
     plan->n_contrib = P * sizeof(int32_t);

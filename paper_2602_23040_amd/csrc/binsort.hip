@@ -225,7 +225,12 @@ __global__ __launch_bounds__(kBlk) void k_sorted_count(const pg_tile_set* __rest
     if (threadIdx.x == 0) blk[blockIdx.x] = t;
 }
 
-__global__ void k_post_count(const int64_t* n_inst, int64_t cap, int32_t* overflow, int64_t* misc) {
+// Overflow check and the next sort generation (n_inst[1], never 0: slots the
+// adjoint has not written this generation, zero-filled ones included, read
+// as zero).
+__global__ void k_post_count(int64_t* n_inst, int64_t cap, int32_t* overflow, int64_t* misc) {
+    uint32_t gen = (uint32_t)n_inst[1] + 1u;
+    n_inst[1] = (int64_t)(gen == 0u ? 1u : gen);
     const int64_t I = *n_inst;
     const bool of = I > cap;
     *overflow = (*overflow & 2) | (of ? 1 : 0);
@@ -864,7 +869,7 @@ size_t sort_ws_bytes(const pg_views* v, int64_t cap) {
 hipError_t launch_bin_sort(const pg_views* v, const pg_bin* bins, const pg_tile_set* tiles, int64_t cap,
                            uint32_t* keys, int32_t* values,
                            int32_t* ranges, int32_t* tile_order, int32_t* inst_first, int64_t* n_inst_dev,
-                           int32_t* overflow_dev, float* inst_grad, void* ws, hipStream_t s) {
+                           int32_t* overflow_dev, void* ws, hipStream_t s) {
     const SortPlan pl = plan_for(v);
     SortWs w = carve(v, cap, ws, nullptr);
     const int64_t nb = n_blocks(v);
@@ -910,11 +915,7 @@ hipError_t launch_bin_sort(const pg_views* v, const pg_bin* bins, const pg_tile_
     e = onesweep_sort(pl.tile, ta, tva, tb, tvb, w.misc + 1, cap, os_carve(cap, pl.tile, w.os), overflow_dev, false, s);
     if (e != hipSuccess) return e;
     k_ranges<<<(unsigned)imax(1, imin(kRangeGrid, ceil_div(cap, 256))), 256, 0, s>>>(keys, w.misc, ranges);
-    e = launch_tile_order(ranges, v->n_tiles, w.order_cnt, w.order_base, w.order_cls, tile_order, s);
-    if (e != hipSuccess) return e;
-    // 6. zero the adjoint's per-instance gradient slots (instances nobody composites keep 0)
-    if (inst_grad) return fill_u32_dev(inst_grad, 0u, n_inst_dev, cap, 9, s);
-    return hipGetLastError();
+    return launch_tile_order(ranges, v->n_tiles, w.order_cnt, w.order_base, w.order_cls, tile_order, s);
 }
 
 }  // namespace pg

@@ -15,6 +15,9 @@ constexpr int kScanBlocks = 1024;    // fixed grid of the device-length scans
 constexpr int kSortThreads = 256;    // radix sort work-group
 constexpr int kSortItems = 16;       // keys per thread
 constexpr int kSortTile = kSortThreads * kSortItems;
+// Words of one per-instance gradient slot: nine sums and the generation tag
+// (the sort generation the adjoint wrote it in; other slots read as zero).
+constexpr int kSlotWords = 10;
 
 // Per-view table resident on the device.
 struct ViewDev {
@@ -116,7 +119,7 @@ size_t sort_ws_bytes(const pg_views* v, int64_t cap);
 hipError_t launch_bin_sort(const pg_views* v, const pg_bin* bins, const pg_tile_set* tiles, int64_t cap,
                            uint32_t* keys, int32_t* values,
                            int32_t* ranges, int32_t* tile_order, int32_t* inst_first, int64_t* n_inst_dev,
-                           int32_t* overflow_dev, float* inst_grad, void* ws, hipStream_t s);
+                           int32_t* overflow_dev, void* ws, hipStream_t s);
 
 // stable sort of (uint32 key, int32 value) pairs (binsort.hip)
 size_t sort_pairs_ws_bytes(int64_t cap, int bits);

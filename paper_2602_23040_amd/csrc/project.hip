@@ -848,24 +848,26 @@ __global__ __launch_bounds__(128) void k_project_bwd_sh(const ViewDev* __restric
 // Per-record sums of the instance slots.  Slots are laid out record by
 // record in (view, id) order, so one work-group takes 256 consecutive
 // records, whose slots form one contiguous range; the group streams it
-// through LDS in coalesced chunks (nine independent loads per thread in
+// through LDS in coalesced chunks (ten independent loads per thread in
 // flight) while each thread adds its own record's slots in rectangle
-// row-major order, and grad2d is written coalesced.  After an overflowed
-// sort there are no slots and every sum is 0.
+// row-major order, and grad2d is written coalesced.  A slot counts only when
+// its tag is this sort's generation (the adjoint wrote it in this step);
+// after an overflowed sort there are no slots and every sum is 0.
 constexpr int kSumRecs = 256;
-constexpr int kSumChunk = 256;    // instances per LDS chunk (9 KiB)
+constexpr int kSumChunk = 256;    // instances per LDS chunk (10 KiB)
 
 __global__ __launch_bounds__(kSumRecs) void k_slot_sum(const pg_bin* __restrict__ bins,
                                                        const int32_t* __restrict__ inst_first,
                                                        const int64_t* __restrict__ n_inst_dev, int64_t cap,
                                                        const float* __restrict__ inst_grad, int64_t n_gv,
                                                        float* __restrict__ grad2d) {
-    __shared__ float s_g[kSumChunk * 9];
+    __shared__ float s_g[kSumChunk * kSlotWords];
     __shared__ int64_t s_range[2];
     const int64_t g0 = (int64_t)blockIdx.x * kSumRecs;
     const int64_t gv = g0 + threadIdx.x;
     const int64_t glast = imin(g0 + kSumRecs, n_gv) - 1;
     const bool sorted_ok = *n_inst_dev <= cap;
+    const uint32_t gen = (uint32_t)n_inst_dev[1];
     int32_t nt = 0;
     int64_t first = 0;
     if (gv <= glast && sorted_ok) {
@@ -881,22 +883,23 @@ __global__ __launch_bounds__(kSumRecs) void k_slot_sum(const pg_bin* __restrict_
     for (int k = 0; k < 9; k++) s9[k] = 0.0f;
     for (int64_t c0 = e0; c0 < e1; c0 += kSumChunk) {
         const int64_t c1 = imin(e1, c0 + kSumChunk);
-        const int32_t nw = (int32_t)((c1 - c0) * 9);
+        const int32_t nw = (int32_t)((c1 - c0) * kSlotWords);
         __syncthreads();
-        const float* src = inst_grad + c0 * 9;
-        float x[9];
+        const float* src = inst_grad + c0 * kSlotWords;
+        float x[kSlotWords];
 #pragma unroll
-        for (int r = 0; r < 9; r++) {
+        for (int r = 0; r < kSlotWords; r++) {
             const int32_t w = r * kSumRecs + threadIdx.x;
             x[r] = w < nw ? src[w] : 0.0f;
         }
 #pragma unroll
-        for (int r = 0; r < 9; r++) s_g[r * kSumRecs + threadIdx.x] = x[r];
+        for (int r = 0; r < kSlotWords; r++) s_g[r * kSumRecs + threadIdx.x] = x[r];
         __syncthreads();
         const int32_t a = (int32_t)(imax(first, c0) - c0), b = (int32_t)(imin(first + nt, c1) - c0);
         for (int32_t u = a; u < b; u++) {
+            if (__float_as_uint(s_g[u * kSlotWords + kSlotWords - 1]) != gen) continue;   // not written this step
 #pragma unroll
-            for (int k = 0; k < 9; k++) s9[k] += s_g[u * 9 + k];
+            for (int k = 0; k < 9; k++) s9[k] += s_g[u * kSlotWords + k];
         }
     }
     if (gv <= glast) {

@@ -40,9 +40,12 @@
 // Gaussian k is recovered as T_k = T_{k+1} / (1 - alpha_k) from the stored
 // final T (no per-step storage).  Per-Gaussian sums over the tile's pixels
 // are reduced across the wave with DPP / permlane moves and written, without
-// atomics, to the (Gaussian, tile) instance's own slot; the projection
-// adjoint then adds the slots of each (view, Gaussian) in a fixed order, so
-// gradients are bitwise deterministic.
+// atomics, to the (Gaussian, tile) instance's own slot, tagged with the
+// sort's generation; the projection adjoint then adds the slots of each
+// (view, Gaussian) in a fixed order, counting only slots of the current
+// generation (instances that composited nothing keep an older tag and read as
+// zero, so the slots are never cleared), and gradients are bitwise
+// deterministic.
 #include "pg_internal.h"
 
 namespace pg {
@@ -355,6 +358,7 @@ __global__ __launch_bounds__(kLanes) void k_render_bwd(const ViewDev* __restrict
     const int32_t count = tile_entries[t.tile];
     const int64_t n_inst = *n_inst_dev;
     if (count == 0 || n_inst > cap) return;       // nothing composited here, or the sort overflowed
+    const uint32_t gen = (uint32_t)n_inst_dev[1];  // this sort's generation: tags the slots written here
     const int64_t HW = (int64_t)t.W * t.H;
     // Per pixel: T, the colour cotangent G, and S = G . B, where B is the colour
     // composited behind the current Gaussian (background first); with
@@ -380,7 +384,9 @@ __global__ __launch_bounds__(kLanes) void k_render_bwd(const ViewDev* __restrict
     const int lane = threadIdx.x;
     const bool o1 = lane & 1;
     const int tidx = total_index(lane);
-    const int toff = tidx >= 0 ? 4 * tidx : 36;     // byte offset of this lane's total in a slot
+    // byte offset of this lane's word in a slot: its total, the generation tag
+    // (lane 62 holds no total), or past the slot (stores nothing)
+    const int toff = tidx >= 0 ? 4 * tidx : (lane == 62 ? 4 * (kSlotWords - 1) : 4 * kSlotWords);
     // entries (composited Gaussians of this tile) back to front
     for (int32_t bend = count; bend > 0; bend -= BATCH) {
         const int32_t bstart = max(0, bend - BATCH);
@@ -467,14 +473,15 @@ __global__ __launch_bounds__(kLanes) void k_render_bwd(const ViewDev* __restrict
             // linear in them (dm = Q (m0, m1), d(a, b, c) = -(m2 / 2, m3, m4 / 2)), so the
             // projection adjoint forms them once per record from its summed slots
             const float tot = wave_totals9(m, o1, lane == 63);
+            const uint32_t sword = lane == 62 ? gen : __float_as_uint(tot);
             // the (Gaussian, tile) sums go to the instance's own slot: no atomics, and the
             // projection adjoint adds a record's slots in a fixed order
             if (slot >= 0) {
-                // 36-byte raw buffer over the slot: the address stays scalar, and lanes
-                // holding no total (offset 36) fall outside it and store nothing
+                // raw buffer over the slot's 40 bytes: the address stays scalar, and lanes
+                // holding neither a total nor the tag (offset 40) fall outside it and store nothing
                 const __amdgpu_buffer_rsrc_t dst = __builtin_amdgcn_make_buffer_rsrc(
-                    inst_grad + (int64_t)slot * 9, (short)0, 36, kBufWord3);
-                __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(tot), dst, toff, 0, 0);
+                    inst_grad + (int64_t)slot * kSlotWords, (short)0, 4 * kSlotWords, kBufWord3);
+                __builtin_amdgcn_raw_buffer_store_b32(sword, dst, toff, 0, 0);
             }
         }
     }

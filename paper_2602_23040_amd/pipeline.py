@@ -64,7 +64,7 @@ class _ViewSet:
         self.tile_entries = torch.empty(max(self.info.n_tiles, 1), dtype=torch.int32, device=device)
         self.order = torch.empty(max(self.info.n_tiles, 1), dtype=torch.int32, device=device)   # dispatch order
         self.inst_first = torch.empty(max(n_gv, 1), dtype=torch.int32, device=device)
-        self.n_inst = torch.zeros(1, dtype=torch.int64, device=device)
+        self.n_inst = torch.zeros(2, dtype=torch.int64, device=device)   # instances, sort generation
         self.overflow = torch.zeros(1, dtype=torch.int32, device=device)
         self.device = device
         self.set_capacity(inst_capacity)
@@ -75,7 +75,8 @@ class _ViewSet:
         self.keys = torch.empty(cap, dtype=torch.int32, device=self.device)
         self.values = torch.empty(cap, dtype=torch.int32, device=self.device)
         self.entries = torch.empty(cap, dtype=torch.int32, device=self.device)
-        self.inst_grad = torch.empty(9 * cap, dtype=torch.float32, device=self.device)
+        # gradient slots, zero-filled once: a zero tag never matches a sort generation
+        self.inst_grad = torch.zeros(abi.SLOT_WORDS * cap, dtype=torch.float32, device=self.device)
         self.ws_bytes = abi.pg_sort_workspace_size(self.handle, cap)
         self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.device)
 
@@ -248,14 +249,14 @@ class Renderer:
     def _project_sort_render(self, s: _ViewSet, pix_off: int, counters):
         abi.pg_project(s.handle, self.params, s.splats, s.bins, s.tiles, self.visible)
         abi.pg_bin_sort(s.handle, s.bins, s.tiles, s.cap, s.keys, s.values, s.ranges, self._order(s), s.inst_first, s.n_inst, s.overflow,
-                        s.inst_grad, s.ws, s.ws_bytes)
+                        s.ws, s.ws_bytes)
         if not self.batched and self.plain_sync:
             # plain path: one instance-count synchronisation per view
             ovf, need = abi.pg_status_check(s.overflow, s.n_inst)      # raises if a sort pass failed
             if ovf:
                 s.set_capacity(int(math.ceil(need * 1.25)))
                 abi.pg_bin_sort(s.handle, s.bins, s.tiles, s.cap, s.keys, s.values, s.ranges, self._order(s), s.inst_first, s.n_inst,
-                                s.overflow, s.inst_grad, s.ws, s.ws_bytes)
+                                s.overflow, s.ws, s.ws_bytes)
         abi.pg_render_fwd(s.handle, s.splats, s.values, s.ranges, self._order(s), self.bg, self._off(self.image, 3 * pix_off),
                           self._off(self.final_T, pix_off), self._off(self.n_contrib, pix_off), s.tile_entries,
                           s.entries, counters)
@@ -413,7 +414,7 @@ class Renderer:
 
     def sorted_instances(self, k=0):
         s = self.sets[k]
-        n = int(s.n_inst.item())
+        n = int(s.n_inst[0].item())
         return s.keys[:n].cpu().numpy().view(np.uint32), s.values[:n].cpu().numpy()
 
 

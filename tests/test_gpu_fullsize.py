@@ -69,7 +69,7 @@ def test_full_size_sampled_parity(cfg):
     atlas = atlas_tensor(sc)
     run_forward(r, atlas)
     N = r.N
-    say(f"[gpu] config {cfg}: {int(r.sets[0].n_inst.item())} instances; oracle on views {views}")
+    say(f"[gpu] config {cfg}: {int(r.sets[0].n_inst[0].item())} instances; oracle on views {views}")
     fw = oracle.Forward(sc, views=views)
     assert fw.n_gauss == N
     spl, bins = r.splat_records(), r.bin_records()

@@ -109,7 +109,7 @@ def test_captured_overflow_is_reported_then_recaptured():
     re.step(atlas, tgt)
     torch.cuda.synchronize()
     ref = (re.image.clone(), re.dL_datlas.clone(), float(re.loss.item()))
-    need_eager = int(re.sets[0].n_inst.item())
+    need_eager = int(re.sets[0].n_inst[0].item())
     re.close()
 
     r = renderer(sc, cap=64)

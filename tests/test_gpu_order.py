@@ -76,7 +76,7 @@ def test_order_is_a_longest_first_permutation_and_changes_nothing(name):
     say(f"[gpu] tile order {name}: {nt} tiles, longest list {int((rg[:, 1] - rg[:, 0]).max())} first")
     image, T, nc = r.image.clone(), r.final_T.clone(), r.n_contrib.clone()
     te, ent, slots = s.tile_entries.clone(), s.entries.clone(), s.inst_grad.clone()
-    n_inst = int(s.n_inst.item())
+    n_inst = int(s.n_inst[0].item())
     # the same calls in the default (neighbouring tiles together) order
     r.image.zero_()
     s.inst_grad.zero_()
@@ -88,5 +88,5 @@ def test_order_is_a_longest_first_permutation_and_changes_nothing(name):
     assert torch.equal(image, r.image) and torch.equal(T, r.final_T) and torch.equal(nc, r.n_contrib)
     assert torch.equal(te, s.tile_entries)
     assert torch.equal(ent[:n_inst], s.entries[:n_inst])
-    assert torch.equal(slots[:9 * n_inst], s.inst_grad[:9 * n_inst])
+    assert torch.equal(slots[:abi.SLOT_WORDS * n_inst], s.inst_grad[:abi.SLOT_WORDS * n_inst])
     r.close()
