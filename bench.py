@@ -157,6 +157,8 @@ def main():
     torch.cuda.synchronize()
     n_eval, n_comp = (int(x) for x in rb.counters.cpu().tolist())
     n_inst = int(rb.sets[0].n_inst[0].item())
+    s0 = rb.sets[0]
+    n_rec = int((s0.bins[:4 * s0.info.n_gv].view(-1, 4)[:, 3] > 0).sum().item())   # records keeping a tile
     P = rb.n_pixels
 
     stream = torch.cuda.current_stream()
@@ -287,7 +289,7 @@ def main():
         "step_ms_spread": dist,
         "speedup_vs_plain": None if ms_plain is None else round(ms_plain / ms, 3),
         "wall_s_timed": round(wall, 4),
-        "work": {"instances": n_inst, "pairs_evaluated": n_eval, "pairs_composited": n_comp, "pixels": P,
+        "work": {"instances": n_inst, "records": n_rec, "pairs_evaluated": n_eval, "pairs_composited": n_comp, "pixels": P,
                  "loss": loss},
         "stages_ms": {k: round(v, 4) for k, v in stages.items()},
         "roofline": roof,

@@ -396,7 +396,7 @@ __global__ __launch_bounds__(256) void k_os_hist(const uint32_t* __restrict__ ke
             const int lead = __builtin_ctzll(act);
             for (int p = 0; p < passes; p++) {
                 const uint32_t d = (k[j] >> (p * BITS)) & (NB - 1);
-                const uint32_t d0 = __shfl(d, lead, 64);
+                const uint32_t d0 = (uint32_t)__builtin_amdgcn_readlane((int)d, lead);
                 if (__ballot(active && d == d0) == act) {
                     if (lane == lead) atomicAdd(&sw[p * NB + d0], (uint32_t)__popcll(act));   // counts only: order-free
                 } else if (active) {
@@ -752,10 +752,13 @@ __global__ __launch_bounds__(1024) void k_order_scan(const int32_t* __restrict__
                                                      int32_t* __restrict__ base, int32_t* __restrict__ cls) {
     __shared__ int32_t s_part[kOrderClasses][kOrderSeg];
     __shared__ int32_t s_first[kOrderClasses];
-    const int c = threadIdx.x / kOrderSeg, k = threadIdx.x % kOrderSeg;
+    // thread (c, k): class c of the k-th run of groups; a wave reads whole rows
+    // of 64 class counts, and the loads of a run are independent
+    const int c = threadIdx.x % kOrderClasses, k = threadIdx.x / kOrderClasses;
     const int64_t per = ceil_div(n_groups, kOrderSeg);
     const int64_t w0 = imin(n_groups, k * per), w1 = imin(n_groups, w0 + per);
     int32_t sum = 0;
+#pragma unroll 8
     for (int64_t w = w0; w < w1; w++) sum += cnt[w * kOrderClasses + c];
     s_part[c][k] = sum;
     __syncthreads();
@@ -775,6 +778,7 @@ __global__ __launch_bounds__(1024) void k_order_scan(const int32_t* __restrict__
     __syncthreads();
     int32_t run = s_first[c];
     for (int j = 0; j < k; j++) run += s_part[c][j];
+#pragma unroll 8
     for (int64_t w = w0; w < w1; w++) {
         base[w * kOrderClasses + c] = run;
         run += cnt[w * kOrderClasses + c];

@@ -39,7 +39,8 @@
 // adjoint's decisions are the forward's.  The transmittance in front of
 // Gaussian k is recovered as T_k = T_{k+1} / (1 - alpha_k) from the stored
 // final T (no per-step storage).  Per-Gaussian sums over the tile's pixels
-// are reduced across the wave with DPP / permlane moves and written, without
+// are reduced across the wave with DPP / permlane moves, two consecutive
+// entries at a time (they share the exchange steps), and written, without
 // atomics, to the (Gaussian, tile) instance's own slot, tagged with the
 // sort's generation; the projection adjoint then adds the slots of each
 // (view, Gaussian) in a fixed order, counting only slots of the current
@@ -291,17 +292,21 @@ __device__ __forceinline__ float dpp(float v) {
     return dpp_f32<CTRL, ROW_MASK>(v);
 }
 
-// Totals of nine per-lane values over the 64 lanes of the wave.  The first
-// eight go across the four 16-lane rows first, with the gfx950 register
-// swaps: a row swap of two registers a, b followed by an add leaves rows
-// (a0+a1, b0+b1, a2+a3, b2+b3), and a half-wave swap of two such registers
-// then leaves one register whose row r holds value r summed over the rows --
-// four values per register, no selects.  Inside each row, a transposed
-// exchange with the lane at xor 1 merges the two registers (even lanes values
-// 0-3, odd lanes 4-7), and three more exchanges finish the row sums.  The
-// ninth is summed inside each row and then across rows by two row
-// broadcasts.  Result: lane 16 r holds the total of v[r], lane 16 r + 1 that
-// of v[4 + r], lane 63 that of v[8] (see total_index).  No LDS traffic.
+// Cross-wave totals of the nine per-lane sums of two consecutive entries
+// (A, B), with the gfx950 register swaps and DPP moves; no LDS traffic.
+//  1. Row swaps: a row swap of two registers a, b followed by an add leaves
+//     rows (a0+a1, b0+b1, a2+a3, b2+b3), and a half-wave swap of two such
+//     registers then leaves one register whose row r holds value r summed over
+//     the four rows.  Each entry's first eight sums become two such registers
+//     (values 0-3 and 4-7, one per row) as soon as the entry is done; the two
+//     ninth sums share one register (rows 0 and 1).
+//  2. Inside the rows, four exchange steps (lane xor 1, xor 2, rotate by 4 and
+//     by 8) finish the sums.  At the first three, two registers are merged:
+//     each lane keeps one operand and adds the partner lane's other operand,
+//     so a register's values occupy half as many lanes after each step and
+//     the five registers end as one.
+// Result: lane 16 r + 0 / + 1 hold A's totals r / 4 + r, lanes 16 r + 2 / + 3
+// B's, lane 4 A's ninth and lane 20 B's ninth (see pair_offsets).
 __device__ __forceinline__ float swap16_sum(float a, float b) {
     auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(a), __float_as_uint(b), false, false);
     return __uint_as_float(r[0]) + __uint_as_float(r[1]);
@@ -311,27 +316,41 @@ __device__ __forceinline__ float swap32_sum(float a, float b) {
     return __uint_as_float(r[0]) + __uint_as_float(r[1]);
 }
 
-__device__ __forceinline__ float wave_totals9(const float* v, bool o1, bool last) {
-    const float t0 = swap32_sum(swap16_sum(v[0], v[1]), swap16_sum(v[2], v[3]));
-    const float t1 = swap32_sum(swap16_sum(v[4], v[5]), swap16_sum(v[6], v[7]));
-    float u = (o1 ? t1 : t0) + dpp<0xB1>(o1 ? t0 : t1);     // quad_perm [1,0,3,2]
-    u += dpp<0x4E>(u);                                      // quad_perm [2,3,0,1]
-    u += dpp<0x124>(u);                                     // row_ror:4
-    u += dpp<0x128>(u);                                     // row_ror:8
-    float x = v[8];
-    x += dpp<0xB1>(x);
-    x += dpp<0x4E>(x);
-    x += dpp<0x124>(x);
-    x += dpp<0x128>(x);
-    x += dpp_f32<0x142, 0xa>(x);                            // row_bcast:15 into rows 1, 3
-    x += dpp_f32<0x143, 0xc>(x);                            // row_bcast:31 into rows 2, 3
-    return last ? x : u;
+// lane keeps p where sel is false and q where it is true, summed with the partner lane's copy
+template <int CTRL>
+__device__ __forceinline__ float merge(float p, float q, bool sel) {
+    return (sel ? q : p) + dpp<CTRL>(sel ? p : q);
 }
 
-// Which total wave_totals9 leaves in `lane` (-1: none).
-__device__ __forceinline__ int total_index(int lane) {
+struct RowSums {
+    float lo, hi;        // values 0-3 and 4-7 of one entry, one per row
+};
+__device__ __forceinline__ RowSums row_sums(const float* v) {
+    return {swap32_sum(swap16_sum(v[0], v[1]), swap16_sum(v[2], v[3])),
+            swap32_sum(swap16_sum(v[4], v[5]), swap16_sum(v[6], v[7]))};
+}
+
+__device__ __forceinline__ float pair_totals(RowSums a, float a8, RowSums b, float b8, int lane) {
+    const float n = swap32_sum(swap16_sum(a8, b8), 0.0f);          // rows: A's ninth, B's ninth, 0, 0
+    const float ma = merge<0xB1>(a.lo, a.hi, lane & 1);             // quad_perm [1,0,3,2]
+    const float mb = merge<0xB1>(b.lo, b.hi, lane & 1);
+    const float n1 = n + dpp<0xB1>(n);
+    const float m = merge<0x4E>(ma, mb, lane & 2);                  // quad_perm [2,3,0,1]
+    const float n2 = n1 + dpp<0x4E>(n1);
+    const float t = merge<0x124>(m, n2, lane & 4);                  // row_ror:4
+    // row_ror:8 (every lane has a source, so bound_ctrl changes nothing; it lets
+    // the move fold into the add)
+    return t + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(t), 0x128, 0xf, 0xf, true));
+}
+
+// Byte offsets, in A's and B's 40-byte slots, of the word this lane stores
+// after pair_totals: a total, the generation tag (lanes 8 and 24 hold no total
+// of their entry), or 40 (outside the slot: nothing is stored).
+__device__ __forceinline__ void pair_offsets(int lane, int& offA, int& offB) {
     const int p = lane & 15, r = lane >> 4;
-    return p == 0 ? r : (p == 1 ? 4 + r : (lane == 63 ? 8 : -1));
+    const int tag = 4 * (kSlotWords - 1), none = 4 * kSlotWords;
+    offA = p == 0 ? 4 * r : (p == 1 ? 4 * (4 + r) : (lane == 4 ? 32 : (lane == 8 ? tag : none)));
+    offB = p == 2 ? 4 * r : (p == 3 ? 4 * (4 + r) : (lane == 20 ? 32 : (lane == 24 ? tag : none)));
 }
 
 template <int TW, int TH, int BATCH>
@@ -382,11 +401,24 @@ __global__ __launch_bounds__(kLanes) void k_render_bwd(const ViewDev* __restrict
         S[j] = fmaf(G2[j], bg2, fmaf(G1[j], bg1, G0[j] * bg0));
     }
     const int lane = threadIdx.x;
-    const bool o1 = lane & 1;
-    const int tidx = total_index(lane);
-    // byte offset of this lane's word in a slot: its total, the generation tag
-    // (lane 62 holds no total), or past the slot (stores nothing)
-    const int toff = tidx >= 0 ? 4 * tidx : (lane == 62 ? 4 * (kSlotWords - 1) : 4 * kSlotWords);
+    int offA, offB;
+    pair_offsets(lane, offA, offB);
+    const uint32_t tag_bits = (lane == 8 || lane == 24) ? ~0u : 0u;   // lanes that store the generation tag
+    // The (Gaussian, tile) sums go to the instance's own slot: no atomics, and the
+    // projection adjoint adds a record's slots in a fixed order.  Raw buffer
+    // stores over the slot's 40 bytes: the address stays scalar, and lanes whose
+    // offset is 40 fall outside it and store nothing.
+    auto store_pair = [&](float t, int32_t sa, int32_t sb) __attribute__((always_inline)) {
+        const uint32_t w = (gen & tag_bits) | (__float_as_uint(t) & ~tag_bits);
+        if (sa >= 0)
+            __builtin_amdgcn_raw_buffer_store_b32(
+                w, __builtin_amdgcn_make_buffer_rsrc(inst_grad + (int64_t)sa * kSlotWords, (short)0, 4 * kSlotWords, kBufWord3),
+                offA, 0, 0);
+        if (sb >= 0)
+            __builtin_amdgcn_raw_buffer_store_b32(
+                w, __builtin_amdgcn_make_buffer_rsrc(inst_grad + (int64_t)sb * kSlotWords, (short)0, 4 * kSlotWords, kBufWord3),
+                offB, 0, 0);
+    };
     // entries (composited Gaussians of this tile) back to front
     for (int32_t bend = count; bend > 0; bend -= BATCH) {
         const int32_t bstart = max(0, bend - BATCH);
@@ -405,7 +437,8 @@ __global__ __launch_bounds__(kLanes) void k_render_bwd(const ViewDev* __restrict
             stage<TW, TH, false>(splats, gv, t.ox, t.oy, t.col0, t.row0, s_st, i);
         }
         __syncthreads();
-        for (int32_t k = cnt - 1; k >= 0; k--) {
+        // one entry: its nine per-lane sums, as row sums and the ninth, and its slot
+        auto entry = [&](const int32_t k, RowSums& rs, float& m8, int32_t& slot_out) __attribute__((always_inline)) {
             const float4 g = s_st[k].geo;
             const float4 cc = s_st[k].col;
             const float cb = s_st[k].blu;
@@ -472,17 +505,26 @@ __global__ __launch_bounds__(kLanes) void k_render_bwd(const ViewDev* __restrict
             // the moments go to the slot as they are: the mean and conic gradients are
             // linear in them (dm = Q (m0, m1), d(a, b, c) = -(m2 / 2, m3, m4 / 2)), so the
             // projection adjoint forms them once per record from its summed slots
-            const float tot = wave_totals9(m, o1, lane == 63);
-            const uint32_t sword = lane == 62 ? gen : __float_as_uint(tot);
-            // the (Gaussian, tile) sums go to the instance's own slot: no atomics, and the
-            // projection adjoint adds a record's slots in a fixed order
-            if (slot >= 0) {
-                // raw buffer over the slot's 40 bytes: the address stays scalar, and lanes
-                // holding neither a total nor the tag (offset 40) fall outside it and store nothing
-                const __amdgpu_buffer_rsrc_t dst = __builtin_amdgcn_make_buffer_rsrc(
-                    inst_grad + (int64_t)slot * kSlotWords, (short)0, 4 * kSlotWords, kBufWord3);
-                __builtin_amdgcn_raw_buffer_store_b32(sword, dst, toff, 0, 0);
-            }
+            rs = row_sums(m);
+            m8 = m[8];
+            slot_out = slot;
+        };
+        // entries in pairs, back to front (a staged batch is even except the tile's first)
+        int32_t k = cnt - 1;
+        for (; k >= 1; k -= 2) {
+            RowSums ra, rb;
+            float a8, b8;
+            int32_t sa, sb;
+            entry(k, ra, a8, sa);
+            entry(k - 1, rb, b8, sb);
+            store_pair(pair_totals(ra, a8, rb, b8, lane), sa, sb);
+        }
+        if (k == 0) {
+            RowSums ra;
+            float a8;
+            int32_t sa;
+            entry(0, ra, a8, sa);
+            store_pair(pair_totals(ra, a8, RowSums{0.0f, 0.0f}, 0.0f, lane), sa, -1);
         }
     }
 }
