@@ -374,8 +374,10 @@ pg_status pg_bin_sort(const pg_views* views, const pg_bin* bins, const pg_tile_s
  *   bg           host float[3]
  *   image        device float [3 n_pixels] out (per view planar [3][H][W])
  *   final_T      device float [n_pixels] out
- *   n_contrib    device int32 [n_pixels] out: 1-based list position of the
- *                last composited Gaussian, 0 if none
+ *   n_contrib    device int32 [n_pixels] out: list positions the pixel
+ *                reached: the 0-based position of the Gaussian at which it
+ *                stopped (T would have dropped below 1e-4), else the length
+ *                of its tile's list
  *   tile_entries device int32 [n_tiles] out: number of entries of each tile
  *   entries      device uint32 [inst_capacity] out: for tile t, words
  *                [start_t, start_t + tile_entries[t]) describe, in ascending

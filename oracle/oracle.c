@@ -391,8 +391,10 @@ void or_bin_sort(const or_proj* pr, int64_t N, const or_camera* cam, int32_t tw,
  *   alpha = min(0.99, o exp(-q/2)); skip if alpha < 1/255;
  *   stop before a Gaussian whose T (1 - alpha) < 1e-4;
  *   C += T alpha c; T *= 1 - alpha.
- * Output C + T bg.  n_contrib = 1-based list position of the last composited
- * Gaussian (0 if none).
+ * Output C + T bg.  n_contrib = the list positions the pixel reached: the
+ * 0-based position of the Gaussian it stopped before, or the list length if
+ * it never stopped (every earlier Gaussian that passes both tests was
+ * composited, so this and the tests tell which ones were).
  *
  * For the parity protocol, decisions whose FP64 margin is within a relative
  * band are reported ("near"), and a list of positions can be given at which
@@ -432,7 +434,7 @@ static int32_t composite(const or_proj* P, const int32_t* list, int64_t len, dou
                          const double bg[3], or_decide* D, double rgb[3], double* Tout, int32_t* nout,
                          or_contrib* rec, int64_t* n_eval) {
     double T = 1.0, C0 = 0.0, C1 = 0.0, C2 = 0.0;
-    int32_t n = 0, nc = 0;
+    int32_t n = (int32_t)len, nc = 0;
     const double band = D ? D->band : 0.0;
     for (int64_t k = 0; k < len; k++) {
         const or_proj* g = &P[list[k]];
@@ -462,7 +464,10 @@ static int32_t composite(const or_proj* P, const int32_t* list, int64_t len, dou
             note_near(D, (int32_t)k);
             if (flip) { stop = !stop; flip = 0; }
         }
-        if (stop) break;
+        if (stop) {
+            n = (int32_t)k;
+            break;
+        }
         if (rec) {
             rec[nc].pos = (int32_t)k; rec[nc].id = list[k]; rec[nc].clamped = clamped;
             rec[nc].alpha = alpha; rec[nc].ex = ex; rec[nc].T = T; rec[nc].dx = dx; rec[nc].dy = dy;
@@ -472,7 +477,6 @@ static int32_t composite(const or_proj* P, const int32_t* list, int64_t len, dou
         C1 += T * alpha * g->color[1];
         C2 += T * alpha * g->color[2];
         T = Tn;
-        n = (int32_t)(k + 1);
     }
     rgb[0] = C0 + T * bg[0];
     rgb[1] = C1 + T * bg[1];

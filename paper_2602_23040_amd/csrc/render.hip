@@ -32,10 +32,12 @@
 // 64 Gaussians are composited, one scalar bit mask per block collects which
 // of them were taken; lane i then forms the word of Gaussian i and the words
 // are stored compacted and coalesced.  The adjoint walks only those entries,
-// back to front.  A pixel took
-// entry k exactly when its list position is below the pixel's n_contrib and
-// q <= 9 and alpha >= 1/255 (a pixel stops only after its last contribution),
-// and q and alpha are recomputed by the same code as the forward, so the
+// back to front.  n_contrib is the list position at which the pixel stopped
+// (the Gaussian that would have brought T below 1e-4), or the list length if
+// it never did; until then a pixel takes every Gaussian with q <= 9 and
+// alpha >= 1/255.  So a pixel took entry k exactly when k is below its
+// n_contrib and both tests pass, and q and alpha are recomputed by the same
+// code as the forward, so the
 // adjoint's decisions are the forward's.  The transmittance in front of
 // Gaussian k is recovered as T_k = T_{k+1} / (1 - alpha_k) from the stored
 // final T (no per-step storage).  Per-Gaussian sums over the tile's pixels
@@ -57,13 +59,16 @@ constexpr float kQMax = 9.0f;
 constexpr float kAlphaMax = 0.99f;
 constexpr float kAlphaMin = 1.0f / 255.0f;
 constexpr float kTMin = 1e-4f;
-constexpr float kNegHalfLog2e = -0.72134752044448170f;   // -log2(e) / 2
+// The staged conic is scaled by -log2(e) / 2, so the quadratic form gives
+// s = -q log2(e) / 2 directly: e^{-q/2} = 2^s, and q <= 9 reads s >= 9 (-log2(e) / 2).
+constexpr float kQScale = -0.72134752044448170f;
+constexpr float kSMin = kQMax * kQScale;
 
-// The one definition of q and alpha used by both the forward and the adjoint,
+// The one definition of s and alpha used by both the forward and the adjoint,
 // with explicit fused multiply-adds so both kernels take bit-identical
 // decisions (the library is compiled with -ffp-contract=off).
 struct Eval {
-    float q, e, raw, alpha;
+    float e, raw, alpha;
 };
 
 __device__ __forceinline__ float quad(float dx, float dy, float a, float b2, float c) {
@@ -71,10 +76,9 @@ __device__ __forceinline__ float quad(float dx, float dy, float a, float b2, flo
     return fmaf(u, dx, (c * dy) * dy);         // dx (a dx + 2 b dy) + c dy^2
 }
 
-__device__ __forceinline__ Eval evaluate(float q, float o) {
+__device__ __forceinline__ Eval evaluate(float s, float o) {
     Eval r;
-    r.q = q;
-    r.e = __builtin_amdgcn_exp2f(q * kNegHalfLog2e);   // e^{-q/2} as 2^{-q log2(e) / 2}
+    r.e = __builtin_amdgcn_exp2f(s);           // e^{-q/2}
     r.raw = o * r.e;
     r.alpha = r.raw < kAlphaMax ? r.raw : kAlphaMax;
     return r;
@@ -151,8 +155,8 @@ __device__ __forceinline__ bool tile_geo(const ViewDev* views, int nv, int64_t n
 // of it from a single address register with immediate offsets.  aux holds the
 // block mask (forward) or the gradient slot and the entry word (adjoint).
 struct alignas(16) Staged {
-    float4 geo;          // local mean x, y; conic a, 2 b
-    float4 col;          // conic c, opacity, red, green
+    float4 geo;          // local mean x, y; conic a, 2 b (scaled by kQScale)
+    float4 col;          // conic c (scaled by kQScale), opacity, red, green
     float blu;           // blue
     uint32_t aux[3];
 };
@@ -165,8 +169,8 @@ __device__ __forceinline__ void stage(const pg_splat* __restrict__ splats, int32
     double2 m;
     *reinterpret_cast<float4*>(&m) = a;
     const float mx = (float)(m.x - ox), my = (float)(m.y - oy);
-    s_st[k].geo = make_float4(mx, my, b.x, 2.0f * b.y);
-    s_st[k].col = make_float4(b.z, b.w, c.x, c.y);   // conic c, opacity, red, green
+    s_st[k].geo = make_float4(mx, my, b.x * kQScale, 2.0f * b.y * kQScale);
+    s_st[k].col = make_float4(b.z * kQScale, b.w, c.x, c.y);   // scaled conic c, opacity, red, green
     s_st[k].blu = c.z;
     if (!MASK) return;
     constexpr int BPR = TW / 8;
@@ -202,13 +206,13 @@ __global__ __launch_bounds__(kLanes) void k_render_fwd(const ViewDev* __restrict
     if (!tile_geo<TW, TH>(views, nv, n_tiles, order, t)) return;
     const int2 rg = ranges[t.tile];
     float T[kPPT], C0[kPPT], C1[kPPT], C2[kPPT];
-    int32_t n[kPPT];
+    int32_t n[kPPT];         // list positions the pixel reached: where it stopped, else the list length
     uint64_t live[kPPT];     // lanes of slot j still compositing (wave-uniform lane mask)
 #pragma unroll
     for (int j = 0; j < kPPT; j++) {
         T[j] = 1.0f;
         C0[j] = C1[j] = C2[j] = 0.0f;
-        n[j] = 0;
+        n[j] = rg.y - rg.x;
         live[j] = __ballot(t.inside[j]);
     }
     uint64_t n_eval = 0, n_comp = 0;        // wave totals (STATS only)
@@ -230,22 +234,25 @@ __global__ __launch_bounds__(kLanes) void k_render_fwd(const ViewDev* __restrict
                 const float4 cc = s_st[k].col;
                 const float cb = s_st[k].blu;
                 const uint32_t mask = (uint32_t)__builtin_amdgcn_readfirstlane((int)s_st[k].aux[0]);   // wave-uniform: bit tests on the scalar unit
-                const int32_t pos1 = b0 - rg.x + k + 1;
+                const int32_t pos = b0 - rg.x + k;
                 const uint64_t kbit = 1ull << (k - k0);
 #pragma unroll
                 for (int j = 0; j < kPPT; j++) {
                     if (STATS) n_eval += __popcll(live[j]);
                     if (!((mask >> j) & 1u) || live[j] == 0) continue;   // ellipse misses the block / block done
                     const float dx = t.fx[j] - g.x, dy = t.fy[j] - g.y;
-                    const float q = quad(dx, dy, g.z, g.w, cc.x);
-                    const uint64_t inm = __ballot(q <= kQMax) & live[j];
+                    const float qs = quad(dx, dy, g.z, g.w, cc.x);     // -q log2(e) / 2
+                    const uint64_t inm = __ballot(qs >= kSMin) & live[j];
                     if (inm == 0) continue;
-                    const Eval ev = evaluate(q, cc.y);
+                    const Eval ev = evaluate(qs, cc.y);
                     const uint64_t passm = __ballot(ev.alpha >= kAlphaMin) & inm;
                     const float Tn = T[j] * (1.0f - ev.alpha);
                     const uint64_t stopm = __ballot(Tn < kTMin) & passm;
                     const uint64_t takem = passm & ~stopm;
-                    live[j] &= ~stopm;
+                    if (stopm) {     // once per pixel
+                        live[j] &= ~stopm;
+                        n[j] = __builtin_amdgcn_inverse_ballot_w64(stopm) ? pos : n[j];
+                    }
                     took[j] |= takem ? kbit : 0ull;
                     if (STATS) n_comp += __popcll(takem);
                     const bool take = __builtin_amdgcn_inverse_ballot_w64(takem);
@@ -254,7 +261,6 @@ __global__ __launch_bounds__(kLanes) void k_render_fwd(const ViewDev* __restrict
                     C1[j] = fmaf(w, cc.w, C1[j]);
                     C2[j] = fmaf(w, cb, C2[j]);
                     T[j] = take ? Tn : T[j];
-                    n[j] = take ? pos1 : n[j];
                 }
                 if ((live[0] | live[1] | live[2] | live[3]) == 0) break;   // every pixel has terminated
             }
@@ -455,11 +461,11 @@ __global__ __launch_bounds__(kLanes) void k_render_bwd(const ViewDev* __restrict
             // one block of the lane's four pixels (j is a constant after inlining)
             auto block = [&](const int j) __attribute__((always_inline)) {
                 const float dx = t.fx[j] - g.x, dy = t.fy[j] - g.y;
-                const float q = quad(dx, dy, g.z, g.w, cc.x);
-                const Eval ev = evaluate(q, cc.y);    // bit-identical to the forward's alpha
+                const float qs = quad(dx, dy, g.z, g.w, cc.x);     // -q log2(e) / 2
+                const Eval ev = evaluate(qs, cc.y);   // bit-identical to the forward's alpha
                 // the forward's decision: a pixel still compositing at this position took every
                 // Gaussian inside the footprint with alpha >= 1/255 (it stops only after its last one)
-                const bool in = pos < nc[j] && q <= kQMax && ev.alpha >= kAlphaMin;
+                const bool in = pos < nc[j] && qs >= kSMin && ev.alpha >= kAlphaMin;
                 const float al = ev.alpha;
                 const float ae = in ? al : 0.0f;      // 0 for pixels that did not take it: T, S unchanged
                 const float Tk = T[j] * __builtin_amdgcn_rcpf(1.0f - ae);   // transmittance in front of k

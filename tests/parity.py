@@ -83,7 +83,7 @@ def gpu_images(r):
 
 
 def _n_map(fw, v, kept):
-    """Maps the oracle's n_contrib at pixel (x, y) (1-based position in the
+    """Maps the oracle's n_contrib at pixel (x, y) (a position in the
     oracle's tile list) to a position in the GPU's list, which is the
     oracle's with the kept flags applied (identity for kept = None)."""
     if kept is None:
@@ -230,17 +230,18 @@ def check_tile_lists(fw, v, keys, vals, tile_base, N):
 
 
 def gpu_n_contrib(fw, v, kept):
-    """The oracle's n_contrib of view v (1-based position of the last
-    composited Gaussian in the oracle's tile list) moved to positions in the
-    GPU's lists, which are the oracle's with the kept flags applied (the last
-    composited Gaussian has q <= 9, so it is always kept)."""
+    """The oracle's n_contrib of view v (list positions reached: where the
+    pixel stopped, else its tile list's length) moved to positions in the
+    GPU's lists, which are the oracle's with the kept flags applied: the
+    number of kept entries before that position (the Gaussian a pixel stops
+    at has q <= 9 there, so its tile is kept for it)."""
     cam = fw.scene.cams[v]
     TX = (cam.width + fw.tw - 1) // fw.tw
     ck = np.concatenate([[0], np.cumsum(kept, dtype=np.int64)])
     ys, xs = np.mgrid[0:cam.height, 0:cam.width]
     start = fw.ranges[v][(ys // fw.th) * TX + xs // fw.tw, 0]
     n = fw.n[v].astype(np.int64)
-    return np.where(n > 0, ck[start + n] - ck[start], 0)
+    return ck[start + n] - ck[start]
 
 
 def check_records(fw, v, bins, tsets, splats, N):

@@ -96,12 +96,13 @@ def test_q_band(eps):
     on = q <= 9.0
     rgb, T, n, near = pixel(fw, PX, PY)
     assert near == ([0] if abs(eps) == INSIDE else [])
-    expect = (alpha * c, 1.0 - alpha, 1) if on else (np.zeros(3), 1.0, 0)
+    # n_contrib: the pixel never stops, so it reaches the end of its one-Gaussian list
+    expect = (alpha * c, 1.0 - alpha, 1) if on else (np.zeros(3), 1.0, 1)
     np.testing.assert_allclose(rgb, expect[0], rtol=1e-10, atol=1e-15)
     assert math.isclose(T, expect[1], rel_tol=1e-12) and n == expect[2]
     rgb_f, T_f, n_f, _ = pixel(fw, PX, PY, flips=[0])
     if abs(eps) == INSIDE:       # the flip takes the footprint decision the other way
-        flipped = (np.zeros(3), 1.0, 0) if on else (alpha * c, 1.0 - alpha, 1)
+        flipped = (np.zeros(3), 1.0, 1) if on else (alpha * c, 1.0 - alpha, 1)
         np.testing.assert_allclose(rgb_f, flipped[0], rtol=1e-10, atol=1e-15)
         assert math.isclose(T_f, flipped[1], rel_tol=1e-12) and n_f == flipped[2]
     else:                        # outside the band a flip changes nothing
@@ -128,12 +129,12 @@ def test_alpha_band(eps):
     on = o >= 1.0 / 255.0
     rgb, T, n, near = pixel(fw, 8, 8)
     assert near == ([0] if abs(eps) == INSIDE else [])
-    expect = (o * c, 1.0 - o, 1) if on else (np.zeros(3), 1.0, 0)
+    expect = (o * c, 1.0 - o, 1) if on else (np.zeros(3), 1.0, 1)
     np.testing.assert_allclose(rgb, expect[0], rtol=1e-12, atol=1e-15)
     assert math.isclose(T, expect[1], rel_tol=1e-12) and n == expect[2]
     rgb_f, T_f, n_f, _ = pixel(fw, 8, 8, flips=[0])
     if abs(eps) == INSIDE:
-        flipped = (np.zeros(3), 1.0, 0) if on else (o * c, 1.0 - o, 1)
+        flipped = (np.zeros(3), 1.0, 1) if on else (o * c, 1.0 - o, 1)
         np.testing.assert_allclose(rgb_f, flipped[0], rtol=1e-12, atol=1e-15)
         assert math.isclose(T_f, flipped[1], rel_tol=1e-12) and n_f == flipped[2]
     else:
@@ -212,8 +213,9 @@ def test_two_near_decisions_flip_together():
     d = np.array([PX + 0.5, PY + 0.5]) - fw.proj[0]["mean"][1]
     assert np.abs(d).max() < 1e-5
     a2 = opacity(sc, 1)
+    # nothing stops the pixel, so n_contrib is its list length (2) under every flip set
     rgb, T, n, near = pixel(fw, PX, PY)
-    assert near == [0, 1] and n == 0 and np.all(rgb == 0.0) and T == 1.0
+    assert near == [0, 1] and n == 2 and np.all(rgb == 0.0) and T == 1.0
     rgb, T, n, _ = pixel(fw, PX, PY, flips=[0, 1])
     np.testing.assert_allclose(rgb, a1 * c1 + (1 - a1) * a2 * c2, rtol=1e-6)
     assert n == 2
@@ -222,7 +224,7 @@ def test_two_near_decisions_flip_together():
     assert n == 2
     rgb, T, n, _ = pixel(fw, PX, PY, flips=[0])
     np.testing.assert_allclose(rgb, a1 * c1, rtol=1e-10)
-    assert n == 1
+    assert n == 2
 
 
 # ------------------------------------------------------------------ adjoint under flips

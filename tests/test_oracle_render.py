@@ -36,6 +36,15 @@ def logit(o):
     return math.log(o / (1 - o))
 
 
+def tile_list_lengths(fw, v):
+    """Length of the tile list of every pixel of view v."""
+    cam = fw.scene.cams[v]
+    TX = (cam.width + fw.tw - 1) // fw.tw
+    ys, xs = np.mgrid[0:cam.height, 0:cam.width]
+    t = (ys // fw.th) * TX + xs // fw.tw
+    return (fw.ranges[v][t, 1] - fw.ranges[v][t, 0]).astype(np.int32)
+
+
 def test_single_gaussian_closed_form():
     cam = synth.pinhole(np.eye(3), np.zeros(3), 64, 48)
     z, sigma, o = 3.0, 0.03, 0.8
@@ -53,13 +62,18 @@ def test_single_gaussian_closed_form():
     expect = np.where(on[None], alpha[None] * col[:, None, None], 0.0)
     np.testing.assert_allclose(fw.image[0], expect, rtol=1e-9, atol=1e-12)
     np.testing.assert_allclose(fw.T[0], np.where(on, 1 - alpha, 1.0), rtol=1e-12)
-    assert np.array_equal(fw.n[0], on.astype(np.int32))
+    # T never drops below 1e-4 (alpha <= 0.99), so every pixel reaches the end of its
+    # tile's list: one Gaussian where the tile lists it, which includes every lit pixel
+    tl = tile_list_lengths(fw, 0)
+    assert np.array_equal(fw.n[0], tl) and np.all(tl[on] == 1)
 
 
 @pytest.mark.parametrize("o,k", [(0.5, 5), (0.5, 20), (0.9, 8), (0.3, 40)])
 def test_stacked_transmittance_product(o, k):
     """k identical Gaussians centred on a pixel centre: C = c (1 - (1-o)^n),
-    n = min(k, n*), n* = largest n with (1 - o)^n >= 1e-4."""
+    n = min(k, n*), n* = largest n with (1 - o)^n >= 1e-4; n is also the
+    pixel's n_contrib (it stops before Gaussian n* when k > n*, else reaches
+    the end of its list of k)."""
     cam = synth.pinhole(np.eye(3), np.zeros(3), 16, 16)
     cam.cx = cam.cy = 8.5  # principal point on the centre of pixel (8, 8)
     lo = np.float32(logit(o))
@@ -120,7 +134,15 @@ def test_tiled_equals_brute_force_bitwise(seed):
         img, T, n, _ = oracle.render(pr, cam, 16, 16, inst, ranges)
         bimg, bT, bn = oracle.render_brute(pr, cam)
         assert np.array_equal(img, bimg) and np.array_equal(T, bT)
-        assert np.array_equal(n > 0, bn > 0)
+        # a pixel stops before the end of its tile list exactly when it stops
+        # before the end of the full list (the Gaussians it composites are the same)
+        TX = (cam.width + 15) // 16
+        ys, xs = np.mgrid[0:cam.height, 0:cam.width]
+        t = (ys // 16) * TX + xs // 16
+        tl = ranges[t, 1] - ranges[t, 0]
+        m = int((pr["radius"] > 0).sum())
+        assert np.all(n <= tl) and np.all(bn <= m)
+        assert np.array_equal(n < tl, bn < m)
         assert img.max() > 0.05
 
 
