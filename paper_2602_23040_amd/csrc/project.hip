@@ -344,8 +344,9 @@ __global__ __launch_bounds__(kProjBlk) void k_project(const ViewDev* __restrict_
             A = c.cp / c.det;
             B = -c.bp / c.det;
             Cq = c.ap / c.det;
-            const double2 m2 = make_double2(mx, my);
-            o0 = *reinterpret_cast<const float4*>(&m2);
+            const uint64_t bx = (uint64_t)__double_as_longlong(mx), by = (uint64_t)__double_as_longlong(my);
+            o0 = make_float4(__uint_as_float((uint32_t)bx), __uint_as_float((uint32_t)(bx >> 32)),
+                             __uint_as_float((uint32_t)by), __uint_as_float((uint32_t)(by >> 32)));   // the FP64 mean's bits
             o1 = make_float4((float)A, (float)B, (float)Cq, (float)w.o);
             o2 = make_float4(col[0], col[1], col[2], zf);
             if (xlo <= xhi && ylo <= yhi) {
