@@ -412,12 +412,18 @@ __global__ __launch_bounds__(256) void k_os_hist(const uint32_t* __restrict__ ke
     }
 }
 
-// Exclusive scan of each pass's digit counts (one work-group of 512 threads).
-__global__ __launch_bounds__(512) void k_os_scan(uint32_t* __restrict__ hist, int passes, int nb) {
+// Exclusive scan of each pass's digit counts (one work-group of 512 threads);
+// uni[p] = 1 when one digit of pass p holds every key (the pass is then the
+// identity permutation).
+__global__ __launch_bounds__(512) void k_os_scan(uint32_t* __restrict__ hist, int passes, int nb,
+                                                 const int64_t* __restrict__ n_ptr, uint32_t* __restrict__ uni) {
     __shared__ uint32_t s_w[8];
     const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
+    const int64_t n = *n_ptr;
     for (int p = 0; p < passes; p++) {
         const uint32_t c = t < nb ? hist[p * nb + t] : 0u;
+        const int all_one = __syncthreads_or(n > 0 && (int64_t)c == n);
+        if (t == 0) uni[p] = (uint32_t)all_one;
         uint32_t incl = c;
 #pragma unroll
         for (int o = 1; o < 64; o <<= 1) {
@@ -457,6 +463,7 @@ __global__ __launch_bounds__(kSortThreads) __attribute__((amdgpu_waves_per_eu(4,
                                                            int32_t* __restrict__ vals_out,
                                                            const int64_t* __restrict__ n_ptr, int shift,
                                                            const uint32_t* __restrict__ digit_base,
+                                                           const uint32_t* __restrict__ uniform,
                                                            unsigned long long* __restrict__ status,
                                                            int32_t* __restrict__ err) {
     constexpr int NB = 1 << BITS;
@@ -477,6 +484,14 @@ __global__ __launch_bounds__(kSortThreads) __attribute__((amdgpu_waves_per_eu(4,
     const int64_t n = *n_ptr;
     const int64_t b = blockIdx.x;
     if (b >= ceil_div(n, kSortTile)) return;
+    if (*uniform) {     // every key has the same digit: the stable order is the input order
+        const int64_t e = imin(n, (b + 1) * kSortTile);
+        for (int64_t i = b * kSortTile + t; i < e; i += kSortThreads) {
+            keys_out[i] = keys_in[i];
+            vals_out[i] = vals_in[i];
+        }
+        return;
+    }
     uint32_t key[kSortItems];
     int32_t val[kSortItems];
     uint32_t rank[kSortItems];
@@ -617,13 +632,15 @@ __global__ void k_os_report(const int32_t* __restrict__ err, int32_t* __restrict
 struct OsWs {
     unsigned long long* status;
     uint32_t* hist;
+    uint32_t* uni;       // per pass: one digit holds every key
     int32_t* err;
     int64_t tiles_max;
 };
 size_t os_ws_bytes(int64_t cap, DigitPlan pl) {
     const int64_t tiles = imax(ceil_div(imax(cap, 1), kSortTile), 1);
     return align256((size_t)pl.passes * tiles * ((size_t)1 << pl.digit) * 8) +
-           align256((size_t)kMaxSortPasses * ((size_t)1 << kOsMaxBits) * 4) + align256(4);
+           align256((size_t)kMaxSortPasses * ((size_t)1 << kOsMaxBits) * 4) + align256(kMaxSortPasses * 4) +
+           align256(4);
 }
 OsWs os_carve(int64_t cap, DigitPlan pl, char* p) {
     OsWs w{};
@@ -633,6 +650,8 @@ OsWs os_carve(int64_t cap, DigitPlan pl, char* p) {
     off += align256((size_t)pl.passes * w.tiles_max * ((size_t)1 << pl.digit) * 8);
     w.hist = (uint32_t*)(p + off);
     off += align256((size_t)kMaxSortPasses * ((size_t)1 << kOsMaxBits) * 4);
+    w.uni = (uint32_t*)(p + off);
+    off += align256(kMaxSortPasses * 4);
     w.err = (int32_t*)(p + off);
     return w;
 }
@@ -657,15 +676,15 @@ hipError_t onesweep_sort(DigitPlan pl, uint32_t* ka, int32_t* va, uint32_t* kb, 
 #undef PG_HIST
         default: return hipErrorInvalidValue;
     }
-    k_os_scan<<<1, 512, 0, s>>>(w.hist, pl.passes, nb);
+    k_os_scan<<<1, 512, 0, s>>>(w.hist, pl.passes, nb, n_ptr, w.uni);
     const unsigned grid = (unsigned)w.tiles_max;
     for (int p = 0; p < pl.passes; p++) {
         unsigned long long* st = w.status + (int64_t)p * w.tiles_max * nb;
         switch (pl.digit) {
 #define PG_PASS(B)                                                                                          \
     case B:                                                                                                 \
-        k_onesweep<B><<<grid, kSortThreads, 0, s>>>(ka, va, kb, vb, n_ptr, p * pl.digit, w.hist + p * nb, st, \
-                                                   w.err);                                                  \
+        k_onesweep<B><<<grid, kSortThreads, 0, s>>>(ka, va, kb, vb, n_ptr, p * pl.digit, w.hist + p * nb,    \
+                                                   w.uni + p, st, w.err);                                   \
         break;
             PG_PASS(1) PG_PASS(2) PG_PASS(3) PG_PASS(4) PG_PASS(5) PG_PASS(6) PG_PASS(7) PG_PASS(8) PG_PASS(9)
 #undef PG_PASS
