@@ -190,8 +190,11 @@ __device__ __forceinline__ void stage(const pg_splat* __restrict__ splats, int32
     s_st[k].aux[0] = mask;
 }
 
+// Eight waves per SIMD (64 registers): the forward waits on its per-Gaussian
+// LDS reads between short VALU runs, and the eighth wave hides more of that
+// (2.13 -> 2.08 ms on 50 views); the adjoint stays at seven, where eight would spill.
 template <int TW, int TH, int BATCH, bool STATS>
-__global__ __launch_bounds__(kLanes) void k_render_fwd(const ViewDev* __restrict__ views, int nv, int64_t n_tiles,
+__global__ __launch_bounds__(kLanes) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_render_fwd(const ViewDev* __restrict__ views, int nv, int64_t n_tiles,
                                                        const pg_splat* __restrict__ splats,
                                                        const int32_t* __restrict__ values,
                                                        const int2* __restrict__ ranges,
