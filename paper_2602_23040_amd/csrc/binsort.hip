@@ -357,6 +357,51 @@ __device__ __forceinline__ unsigned long long st_read(unsigned long long* p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Decoupled look-back: the sum of the values of work-groups 0 .. b-1 (b > 0)
+// from their status words (work-group k's at p[k * stride]), read
+// kLookWindow at a time from b - 1 backwards (a first wave of work-groups
+// starts together, and one dependent load per predecessor would make its
+// walks long) and added until a word flagged kStPre (an inclusive prefix).  A
+// word not yet published is read again; after kLookbackSpins waits the walk
+// gives up and sets *err (never in a working chain: report, do not hang).
+__device__ __forceinline__ uint32_t lookback_excl(unsigned long long* p, int64_t stride, int64_t b, int32_t* err) {
+    uint32_t excl = 0;
+    int64_t k = b - 1;          // newest predecessor not yet added
+    int spins = 0;
+    bool done = false;
+    while (!done) {
+        unsigned long long w[kLookWindow];
+#pragma unroll
+        for (int j = 0; j < kLookWindow; j++) w[j] = k - j >= 0 ? st_read(&p[(k - j) * stride]) : 0ull;
+        // newest first: add counts until a PRE word; stop at a word not published yet
+        int adv = 0;
+        bool stop = false;
+#pragma unroll
+        for (int j = 0; j < kLookWindow; j++) {
+            const uint32_t flag = (uint32_t)(w[j] >> 32);
+            if (!stop && !done) {
+                if (k - j < 0 || flag == 0u) {
+                    stop = true;
+                } else {
+                    excl += (uint32_t)w[j];
+                    adv = j + 1;
+                    done = flag == kStPre || k - j == 0;
+                }
+            }
+        }
+        if (done) break;
+        k -= adv;
+        if (adv < kLookWindow) {      // waiting on an unpublished word
+            if (++spins > kLookbackSpins) {
+                atomicOr(err, 1);
+                break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+        }
+    }
+    return excl;
+}
+
 // Digit counts of every pass of a sort in one read of the keys:
 // hist[p NB + d] = keys whose bits [p BITS, (p + 1) BITS) equal d.  Each wave
 // counts into its own LDS histogram; with UNIFORM, a wave whose active lanes
@@ -565,49 +610,14 @@ __global__ __launch_bounds__(kSortThreads) __attribute__((amdgpu_waves_per_eu(4,
             s_vals[pos] = val[r];
         }
     }
-    // look-back: this digit's count over the tiles before b, reading kLookWindow
-    // predecessors at a time (a first wave of work-groups starts together, and
-    // one dependent load per predecessor would make its walks long)
+    // look-back: this digit's count over the tiles before b
     if (t < ACT) {
 #pragma unroll
         for (int e = 0; e < PER; e++) {
             const int d = t * PER + e;
             uint32_t excl = 0;
             if (b > 0) {
-                int64_t k = b - 1;          // newest predecessor not yet added
-                int spins = 0;
-                bool done = false;
-                while (!done) {
-                    unsigned long long w[kLookWindow];
-#pragma unroll
-                    for (int j = 0; j < kLookWindow; j++)
-                        w[j] = k - j >= 0 ? st_read(&status[(k - j) * NB + d]) : 0ull;
-                    // newest first: add counts until a PRE word; stop at a word not published yet
-                    int adv = 0;
-                    bool stop = false;
-#pragma unroll
-                    for (int j = 0; j < kLookWindow; j++) {
-                        const uint32_t flag = (uint32_t)(w[j] >> 32);
-                        if (!stop && !done) {
-                            if (k - j < 0 || flag == 0u) {
-                                stop = true;
-                            } else {
-                                excl += (uint32_t)w[j];
-                                adv = j + 1;
-                                done = flag == kStPre || k - j == 0;
-                            }
-                        }
-                    }
-                    if (done) break;
-                    k -= adv;
-                    if (adv < kLookWindow) {      // waiting on an unpublished word
-                        if (++spins > kLookbackSpins) {     // never in a working chain: report, do not hang
-                            atomicOr(err, 1);
-                            break;
-                        }
-                        __builtin_amdgcn_s_sleep(1);
-                    }
-                }
+                excl = lookback_excl(status + d, NB, b, err);
                 st_publish(&status[b * NB + d], kStPre, excl + tot[e]);
             }
             s_glob[d] = (int32_t)(digit_base[d] + excl) - (int32_t)s_lstart[d];
