@@ -1,6 +1,6 @@
 """GPU parity: the HIP path through the C ABI against the FP64 oracle on the
 same seeded scenes (tiny ragged scenes, a multi-frame window, large
-Gaussians whose rectangles exceed 64 tiles, and the two
+Gaussians whose rectangles exceed 64 tiles, Gaussians all at one depth, and the two
 workloads small enough for the oracle to finish in seconds: the 64x64-atlas
 single view and the 256x256-atlas ring of eight 512x512 views)."""
 import numpy as np
@@ -24,6 +24,10 @@ SCENES = {
     # large Gaussians: rectangles of up to 110 tiles (more than 64 keep every tile)
     "large": lambda: synth.random_scene(side=8, sh_degree=1, views=2, width=200, height=150, seed=5,
                                         lscale=(-1.3, 0.4)),
+    # every Gaussian at one depth in front of one camera: each pass of the depth sort sees a
+    # single digit (the copy path) and the tile lists keep equal depths in id order
+    "flat": lambda: synth.random_scene(side=12, sh_degree=1, views=0, width=64, height=48, seed=7,
+                                       pos=((-1, -1, 3), (1, 1, 3)), lscale=(-3.4, 0.4)),
     "config1": lambda: synth.make_scene(1),
     "config2": lambda: synth.make_scene(2),
 }
