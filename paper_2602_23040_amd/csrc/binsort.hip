@@ -209,11 +209,16 @@ __global__ __launch_bounds__(kBlk) void k_compact(const pg_bin* __restrict__ bin
 
 // Tile sets gathered into depth order (one 16-byte read per record) and the
 // group sums of the kept-tile counts.
+// The sorted records are in rv_moved, or in rv_stayed when the depth sort's
+// last pass had one digit for every key and moved nothing (*stayed).
 __global__ __launch_bounds__(kBlk) void k_sorted_count(const pg_tile_set* __restrict__ tiles,
-                                                       const int32_t* __restrict__ rv,
+                                                       const int32_t* __restrict__ rv_moved,
+                                                       const int32_t* __restrict__ rv_stayed,
+                                                       const uint32_t* __restrict__ stayed,
                                                        const int64_t* __restrict__ misc, int64_t* __restrict__ blk,
                                                        uint4* __restrict__ stiles) {
     __shared__ int64_t s[kBlk / 64];
+    const int32_t* __restrict__ rv = *stayed ? rv_stayed : rv_moved;
     const int64_t p = (int64_t)blockIdx.x * kBlk + threadIdx.x;
     int64_t c = 0;
     if (p < misc[0]) {
@@ -255,10 +260,13 @@ __device__ __forceinline__ void rect_tile(int32_t k, int32_t w, float rw, int32_
     else if (col >= w) { row++; col -= w; }
 }
 
-__global__ __launch_bounds__(kBlk) void k_emit(const uint4* __restrict__ stiles, const int32_t* __restrict__ rv,
-                                               int64_t N, const ViewDev* __restrict__ views,
+__global__ __launch_bounds__(kBlk) void k_emit(const uint4* __restrict__ stiles, const int32_t* __restrict__ rv_moved,
+                                               const int32_t* __restrict__ rv_stayed,
+                                               const uint32_t* __restrict__ stayed, int64_t N,
+                                               const ViewDev* __restrict__ views,
                                                const int64_t* __restrict__ blk_off, const int64_t* __restrict__ misc,
                                                uint32_t* __restrict__ tkeys, int32_t* __restrict__ tvals) {
+    const int32_t* __restrict__ rv = *stayed ? rv_stayed : rv_moved;   // as in k_sorted_count
     __shared__ int32_t s_warp[kBlk / 64];
     if (misc[1] == 0) return;   // overflow (or nothing to emit): uniform exit
     const int t = threadIdx.x, lane = t & 63;
@@ -508,7 +516,7 @@ __global__ __launch_bounds__(kSortThreads) __attribute__((amdgpu_waves_per_eu(4,
                                                            int32_t* __restrict__ vals_out,
                                                            const int64_t* __restrict__ n_ptr, int shift,
                                                            const uint32_t* __restrict__ digit_base,
-                                                           const uint32_t* __restrict__ uniform,
+                                                           const uint32_t* __restrict__ uniform, int stay,
                                                            unsigned long long* __restrict__ status,
                                                            int32_t* __restrict__ err) {
     constexpr int NB = 1 << BITS;
@@ -530,6 +538,7 @@ __global__ __launch_bounds__(kSortThreads) __attribute__((amdgpu_waves_per_eu(4,
     const int64_t b = blockIdx.x;
     if (b >= ceil_div(n, kSortTile)) return;
     if (*uniform) {     // every key has the same digit: the stable order is the input order
+        if (stay) return;   // the caller reads the input buffers when this pass is uniform
         const int64_t e = imin(n, (b + 1) * kSortTile);
         for (int64_t i = b * kSortTile + t; i < e; i += kSortThreads) {
             keys_out[i] = keys_in[i];
@@ -670,9 +679,12 @@ OsWs os_carve(int64_t cap, DigitPlan pl, char* p) {
 // pl.passes * pl.digit key bits, ping-ponging with (kb, vb); the result
 // lands in (ka, va) for an even number of passes, else in (kb, vb).
 // uniform_high: keys whose high digits mostly agree (depth bits), counted with
-// the wave-uniform shortcut.
+// the wave-uniform shortcut.  last_may_stay: when the last pass's digit is one
+// value for every key, that pass moves nothing and the result stays where the
+// pass before left it; w.uni[passes - 1] tells the caller which.
 hipError_t onesweep_sort(DigitPlan pl, uint32_t* ka, int32_t* va, uint32_t* kb, int32_t* vb, const int64_t* n_ptr,
-                         int64_t cap, OsWs w, int32_t* overflow, bool uniform_high, hipStream_t s) {
+                         int64_t cap, OsWs w, int32_t* overflow, bool uniform_high, bool last_may_stay,
+                         hipStream_t s) {
     const int nb = 1 << pl.digit;
     k_os_clear<<<1024, 256, 0, s>>>(n_ptr, pl.passes, nb, w.tiles_max, w.status, w.hist, w.err);
     const unsigned hgrid = (unsigned)imax(1, imin(2048, ceil_div(imax(cap, 1), 256 * 16)));
@@ -690,11 +702,12 @@ hipError_t onesweep_sort(DigitPlan pl, uint32_t* ka, int32_t* va, uint32_t* kb, 
     const unsigned grid = (unsigned)w.tiles_max;
     for (int p = 0; p < pl.passes; p++) {
         unsigned long long* st = w.status + (int64_t)p * w.tiles_max * nb;
+        const int stay = last_may_stay && p == pl.passes - 1 ? 1 : 0;
         switch (pl.digit) {
 #define PG_PASS(B)                                                                                          \
     case B:                                                                                                 \
         k_onesweep<B><<<grid, kSortThreads, 0, s>>>(ka, va, kb, vb, n_ptr, p * pl.digit, w.hist + p * nb,    \
-                                                   w.uni + p, st, w.err);                                   \
+                                                   w.uni + p, stay, st, w.err);                             \
         break;
             PG_PASS(1) PG_PASS(2) PG_PASS(3) PG_PASS(4) PG_PASS(5) PG_PASS(6) PG_PASS(7) PG_PASS(8) PG_PASS(9)
 #undef PG_PASS
@@ -886,7 +899,7 @@ hipError_t sort_pairs(uint32_t* keys, int32_t* vals, uint32_t* keys_alt, int32_t
                       int64_t cap, int bits, void* ws, uint32_t** out_keys, int32_t** out_vals, hipStream_t s) {
     const DigitPlan pl = digit_plan(bits, kDepthDigitBits);
     const hipError_t e = onesweep_sort(pl, keys, vals, keys_alt, vals_alt, n_dev, cap, os_carve(cap, pl, (char*)ws),
-                                       nullptr, true, s);
+                                       nullptr, true, false, s);
     const bool even = pl.passes % 2 == 0;
     *out_keys = even ? keys : keys_alt;
     *out_vals = even ? vals : vals_alt;
@@ -928,12 +941,16 @@ hipError_t launch_bin_sort(const pg_views* v, const pg_bin* bins, const pg_tile_
     if (e != hipSuccess) return e;
     k_compact<<<(unsigned)nb, kBlk, 0, s>>>(bins, v->n_gv, w.blk_a_off, w.blk_b_off, w.rk0, w.rv0, inst_first);
     // 2. stable LSD sort of the records by depth
-    e = onesweep_sort(pl.depth, w.rk0, w.rv0, w.rk1, w.rv1, w.misc + 0, v->n_gv, os_carve(v->n_gv, pl.depth, w.os),
-                      overflow_dev, true, s);
+    // (when the last digit is one value for every key, that pass moves nothing: the
+    // records stay in the buffer the pass before wrote, and its flag says so)
+    const OsWs dws = os_carve(v->n_gv, pl.depth, w.os);
+    e = onesweep_sort(pl.depth, w.rk0, w.rv0, w.rk1, w.rv1, w.misc + 0, v->n_gv, dws, overflow_dev, true, true, s);
     if (e != hipSuccess) return e;
     const int32_t* rva = pl.depth.passes % 2 == 0 ? w.rv0 : w.rv1;
+    const int32_t* rvb = pl.depth.passes % 2 == 0 ? w.rv1 : w.rv0;
+    const uint32_t* stayed = dws.uni + pl.depth.passes - 1;
     // 3. instance offsets in sorted-record order; overflow check
-    k_sorted_count<<<(unsigned)nb, kBlk, 0, s>>>(tiles, rva, w.misc, w.blk_a, w.stiles);
+    k_sorted_count<<<(unsigned)nb, kBlk, 0, s>>>(tiles, rva, rvb, stayed, w.misc, w.blk_a, w.stiles);
     e = scan_i64(w.blk_a, w.blk_a_off, nullptr, 0, nb, n_inst_dev, w.scan_tmp, s);
     if (e != hipSuccess) return e;
     k_post_count<<<1, 1, 0, s>>>(n_inst_dev, cap, overflow_dev, w.misc);
@@ -943,9 +960,12 @@ hipError_t launch_bin_sort(const pg_views* v, const pg_bin* bins, const pg_tile_
     int32_t* tva = even ? values : w.tv_alt;
     uint32_t* tb = even ? w.tk_alt : keys;
     int32_t* tvb = even ? w.tv_alt : values;
-    k_emit<<<(unsigned)nb, kBlk, 0, s>>>(w.stiles, rva, v->n_gauss, v->d_views, w.blk_a_off, w.misc, ta, tva);
-    // 5. stable LSD sort of the instances by tile id
-    e = onesweep_sort(pl.tile, ta, tva, tb, tvb, w.misc + 1, cap, os_carve(cap, pl.tile, w.os), overflow_dev, false, s);
+    k_emit<<<(unsigned)nb, kBlk, 0, s>>>(w.stiles, rva, rvb, stayed, v->n_gauss, v->d_views, w.blk_a_off, w.misc, ta,
+                                         tva);
+    // 5. stable LSD sort of the instances by tile id (its workspace overlaps the depth sort's, whose flag
+    // the emission has read by then)
+    e = onesweep_sort(pl.tile, ta, tva, tb, tvb, w.misc + 1, cap, os_carve(cap, pl.tile, w.os), overflow_dev, false,
+                      false, s);
     if (e != hipSuccess) return e;
     k_ranges<<<(unsigned)imax(1, imin(kRangeGrid, ceil_div(cap, 256))), 256, 0, s>>>(keys, w.misc, ranges);
     return launch_tile_order(ranges, v->n_tiles, w.order_cnt, w.order_base, w.order_cls, tile_order, s);
