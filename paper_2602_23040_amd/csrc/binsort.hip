@@ -49,7 +49,7 @@ struct DigitPlan {
 };
 constexpr int kOsMaxBits = 9;                // digit width the radix pass kernels are built for
 constexpr int kDepthDigitBits = 8;           // digit width caps of the record (depth) and instance (tile) sorts
-constexpr int kTileDigitBits = 6;
+constexpr int kTileDigitBits = 7;            // 18-bit tile ids: 3 x 6 bits; 19-21 bits: 3 x 7 instead of 4 x 5
 
 DigitPlan digit_plan(int bits, int max_bits) {
     DigitPlan p;
