@@ -42,12 +42,12 @@ FLOP_EVAL = 9
 FLOP_COMP = 12
 # FP32 operations per composited pair in the compositing adjoint: dx, dy (2),
 # q (7), alpha (-q/2, exp, o e, clamp: 4), 1 - alpha, its reciprocal, T_k (3),
-# T alpha (1), colour moments (3 FMA: 6), G . c (5), G . c - S (1), S update
-# (FMA: 2), dL/dalpha = T (G . c - S) (1), opacity moment (FMA: 2),
-# alpha dL/dalpha (1), dq' (dx, dy) (2), first moments (2), second moments
-# (3 FMA: 6) = 45.  (S = G . B is the colour behind the Gaussian projected on
-# the pixel's colour cotangent G.)
-FLOP_BWD = 45
+# T alpha (1), colour moments (3 FMA: 6), G . c - S (3 FMA: 6), S update
+# (FMA: 2), dq' = alpha dL/dalpha = T alpha (G . c - S) (1), opacity moment
+# sum dq' (1), dq' (dx, dy) (2), first moments (2), second moments (3 FMA: 6)
+# = 43.  (S = G . B is the colour behind the Gaussian projected on the pixel's
+# colour cotangent G; dL/do = sum dq' / o is formed per record.)
+FLOP_BWD = 43
 # Bytes per radix pass and instance: upsweep reads the key (8), downsweep reads
 # key + value (12) and writes them (12).
 SORT_BYTES_PER_PASS = 32

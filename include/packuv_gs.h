@@ -399,9 +399,10 @@ pg_status pg_render_fwd(const pg_views* views, const pg_splat* splats, const int
  * and writes each (Gaussian, tile) instance's sums over the tile's pixels to
  * that instance's own slot (no atomics): with dq' = alpha dL/dalpha (so
  * dL/dq = -dq'/2) and (dx, dy) = pixel - mean, the nine floats are
- * sum dq' dx, sum dq' dy, sum dq' dx^2, sum dq' dx dy, sum dq' dy^2, dL/dopacity
+ * sum dq' dx, sum dq' dy, sum dq' dx^2, sum dq' dx dy, sum dq' dy^2, sum dq'
  * and dL/d(r, g, b).  The mean and conic gradients are linear in the first
- * five; pg_project_bwd forms them per record.  A slot is 10 words: the
+ * five and dL/dopacity is sum dq' / opacity; pg_project_bwd forms them per
+ * record.  A slot is 10 words: the
  * nine sums, then the sort generation (n_inst_dev[1], as uint32 bits) that
  * marks it as written by this step.  Slots of instances that composited
  * nothing are not written: they keep an older tag (or the zero of a

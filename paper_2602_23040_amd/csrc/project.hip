@@ -617,7 +617,7 @@ __global__ __launch_bounds__(128) void k_project_bwd_geo(const ViewDev* __restri
     World w;
     bool have_world = false;
     // the record's slot sums (0 for culled records): the compositing moments
-    // sum dq' (dx, dy, dx^2, dx dy, dy^2) with dq' = alpha dL/dalpha, and dL/do;
+    // sum dq' (dx, dy, dx^2, dx dy, dy^2) and sum dq', with dq' = alpha dL/dalpha;
     // the next view's are loaded while this view's are used
     float nxt[6];
     auto load6 = [&](int32_t vi) __attribute__((always_inline)) {
@@ -649,7 +649,9 @@ __global__ __launch_bounds__(128) void k_project_bwd_geo(const ViewDev* __restri
         const double idet = 1.0 / c.det;
         const double Q00 = c.cp * idet, Q01 = -c.bp * idet, Q11 = c.ap * idet;
         // 2D gradients from the moments (dL/dq = -dq'/2): dL/dm = Q (m0, m1),
-        // dL/d(a, b, c) = -(m2 / 2, m3, m4 / 2); written back as the record's grad2d
+        // dL/d(a, b, c) = -(m2 / 2, m3, m4 / 2), and dL/do = sum e dL/dalpha =
+        // sum dq' / o (alpha = o e^{-q/2} wherever dq' is not zero); written back
+        // as the record's grad2d
         {
             const double m0 = g6[0], m1 = g6[1];
             g6[0] = Q00 * m0 + Q01 * m1;
@@ -657,8 +659,9 @@ __global__ __launch_bounds__(128) void k_project_bwd_geo(const ViewDev* __restri
             g6[2] = -0.5 * g6[2];
             g6[3] = -g6[3];
             g6[4] = -0.5 * g6[4];
+            g6[5] = g6[5] / w.o;
 #pragma unroll
-            for (int k = 0; k < 5; k++) grad2d[(int64_t)k * n_gv + gv] = (float)g6[k];
+            for (int k = 0; k < 6; k++) grad2d[(int64_t)k * n_gv + gv] = (float)g6[k];
         }
         const double G00 = g6[2], G01 = 0.5 * g6[3], G11 = g6[4];
         // QG = Q Gh ; GS = -(QG Q)

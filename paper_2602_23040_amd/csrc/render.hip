@@ -64,24 +64,40 @@ constexpr float kTMin = 1e-4f;
 constexpr float kQScale = -0.72134752044448170f;
 constexpr float kSMin = kQMax * kQScale;
 
-// The one definition of s and alpha used by both the forward and the adjoint,
-// with explicit fused multiply-adds so both kernels take bit-identical
-// decisions (the library is compiled with -ffp-contract=off).
-struct Eval {
-    float e, raw, alpha;
-};
-
+// The one definition of s, alpha and the take decision used by both the
+// forward and the adjoint, with explicit fused multiply-adds so both kernels
+// take bit-identical decisions (the library is compiled with -ffp-contract=off).
 __device__ __forceinline__ float quad(float dx, float dy, float a, float b2, float c) {
     const float u = fmaf(b2, dy, a * dx);      // a dx + 2 b dy
     return fmaf(u, dx, (c * dy) * dy);         // dx (a dx + 2 b dy) + c dy^2
 }
 
-__device__ __forceinline__ Eval evaluate(float s, float o) {
-    Eval r;
-    r.e = __builtin_amdgcn_exp2f(s);           // e^{-q/2}
-    r.raw = o * r.e;
-    r.alpha = r.raw < kAlphaMax ? r.raw : kAlphaMax;
-    return r;
+// Smallest s a pixel needs: q <= 9 (s >= kSMin) and alpha >= 1/255, i.e.
+// o 2^s >= 1/255, s >= log2(1 / (255 o)); one compare per pixel instead of two.
+// Exact up to the rounding of the logarithm (a relative 1e-7 of alpha at the
+// threshold) where the product test would round exp2 instead.
+__device__ __forceinline__ float take_threshold(float o) {
+    return o > 0.0f ? fmaxf(kSMin, __builtin_amdgcn_logf(kAlphaMin / o)) : __builtin_inff();
+}
+
+// The 0.99 clamp can only bind when o >= 0.99, since e^{-q/2} <= 1: the flag
+// is decided per Gaussian (as integer bits, the same in both kernels).  The
+// forward clamps at alpha_cap (0.99, or +inf below that opacity: one min
+// either way); the adjoint has a copy of its loop without the clamp for the
+// Gaussians that cannot reach it, and takes alpha = o e^{-q/2} there, which
+// is the forward's value for every non-NaN product.
+__device__ __forceinline__ bool may_clamp(float o) {
+    return __float_as_int(o) >= __float_as_int(kAlphaMax);
+}
+
+__device__ __forceinline__ float raw_alpha(float s, float o) {
+    return o * __builtin_amdgcn_exp2f(s);                 // o e^{-q/2}
+}
+
+// min(raw, cap) for the raw >= 0 of every pixel that can take the Gaussian
+// (its opacity is positive): one median, with no NaN canonicalisation of cap
+__device__ __forceinline__ float clamp_alpha(float raw, float cap) {
+    return __builtin_amdgcn_fmed3f(raw, 0.0f, cap);
 }
 
 __device__ __forceinline__ int64_t xcd_remap(int64_t i, int64_t n) {
@@ -158,8 +174,11 @@ struct alignas(16) Staged {
     float4 geo;          // local mean x, y; conic a, 2 b (scaled by kQScale)
     float4 col;          // conic c (scaled by kQScale), opacity, red, green
     float blu;           // blue
-    uint32_t aux[3];
+    float thr;           // take_threshold(opacity)
+    uint32_t aux[2];
 };
+
+constexpr uint32_t kClampBit = 1u << kPPT;   // forward's aux[0]: may_clamp(opacity)
 
 template <int TW, int TH, bool MASK>
 __device__ __forceinline__ void stage(const pg_splat* __restrict__ splats, int32_t gv, double ox, double oy,
@@ -172,6 +191,7 @@ __device__ __forceinline__ void stage(const pg_splat* __restrict__ splats, int32
     s_st[k].geo = make_float4(mx, my, b.x * kQScale, 2.0f * b.y * kQScale);
     s_st[k].col = make_float4(b.z * kQScale, b.w, c.x, c.y);   // scaled conic c, opacity, red, green
     s_st[k].blu = c.z;
+    s_st[k].thr = take_threshold(b.w);
     if (!MASK) return;
     constexpr int BPR = TW / 8;
     const float ac = b.x * b.z;
@@ -187,7 +207,7 @@ __device__ __forceinline__ void stage(const pg_splat* __restrict__ splats, int32
             if (mx + ex >= x0 && mx - ex <= x0 + 7.0f && my + ey >= y0 && my - ey <= y0 + 7.0f) mask |= 1u << j;
         }
     }
-    s_st[k].aux[0] = mask;
+    s_st[k].aux[0] = mask | (may_clamp(b.w) ? kClampBit : 0u);
 }
 
 // Eight waves per SIMD (64 registers): the forward waits on its per-Gaussian
@@ -204,7 +224,7 @@ __global__ __launch_bounds__(kLanes) __attribute__((amdgpu_waves_per_eu(8, 8))) 
                                                        int32_t* __restrict__ tile_entries,
                                                        uint32_t* __restrict__ entries,
                                                        unsigned long long* __restrict__ counters) {
-    __shared__ Staged s_st[BATCH];     // aux[0]: the mask of 8x8 blocks the ellipse can reach
+    __shared__ Staged s_st[BATCH];     // aux[0]: the mask of 8x8 blocks the ellipse can reach, kClampBit
     TileGeo t;
     if (!tile_geo<TW, TH>(views, nv, n_tiles, order, t)) return;
     const int2 rg = ranges[t.tile];
@@ -236,22 +256,24 @@ __global__ __launch_bounds__(kLanes) __attribute__((amdgpu_waves_per_eu(8, 8))) 
                 const float4 g = s_st[k].geo;
                 const float4 cc = s_st[k].col;
                 const float cb = s_st[k].blu;
-                const uint32_t mask = (uint32_t)__builtin_amdgcn_readfirstlane((int)s_st[k].aux[0]);   // wave-uniform: bit tests on the scalar unit
+                const float thr = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(s_st[k].thr)));
+                // wave-uniform: block bits and the clamp flag, tested on the scalar unit
+                const uint32_t mask = (uint32_t)__builtin_amdgcn_readfirstlane((int)s_st[k].aux[0]);
                 const int32_t pos = b0 - rg.x + k;
                 const uint64_t kbit = 1ull << (k - k0);
+                const float cap = (mask & kClampBit) ? kAlphaMax : __builtin_inff();
 #pragma unroll
                 for (int j = 0; j < kPPT; j++) {
                     if (STATS) n_eval += __popcll(live[j]);
                     if (!((mask >> j) & 1u) || live[j] == 0) continue;   // ellipse misses the block / block done
                     const float dx = t.fx[j] - g.x, dy = t.fy[j] - g.y;
                     const float qs = quad(dx, dy, g.z, g.w, cc.x);     // -q log2(e) / 2
-                    const uint64_t inm = __ballot(qs >= kSMin) & live[j];
+                    const uint64_t inm = __ballot(qs >= thr) & live[j];   // q <= 9 and alpha >= 1/255
                     if (inm == 0) continue;
-                    const Eval ev = evaluate(qs, cc.y);
-                    const uint64_t passm = __ballot(ev.alpha >= kAlphaMin) & inm;
-                    const float Tn = T[j] * (1.0f - ev.alpha);
-                    const uint64_t stopm = __ballot(Tn < kTMin) & passm;
-                    const uint64_t takem = passm & ~stopm;
+                    const float alpha = clamp_alpha(raw_alpha(qs, cc.y), cap);
+                    const float Tn = T[j] * (1.0f - alpha);
+                    const uint64_t stopm = __ballot(Tn < kTMin) & inm;
+                    const uint64_t takem = inm & ~stopm;
                     if (stopm) {     // once per pixel
                         live[j] &= ~stopm;
                         n[j] = __builtin_amdgcn_inverse_ballot_w64(stopm) ? pos : n[j];
@@ -259,7 +281,7 @@ __global__ __launch_bounds__(kLanes) __attribute__((amdgpu_waves_per_eu(8, 8))) 
                     took[j] |= takem ? kbit : 0ull;
                     if (STATS) n_comp += __popcll(takem);
                     const bool take = __builtin_amdgcn_inverse_ballot_w64(takem);
-                    const float w = take ? T[j] * ev.alpha : 0.0f;
+                    const float w = take ? T[j] * alpha : 0.0f;
                     C0[j] = fmaf(w, cc.z, C0[j]);
                     C1[j] = fmaf(w, cc.w, C1[j]);
                     C2[j] = fmaf(w, cb, C2[j]);
@@ -451,25 +473,29 @@ __global__ __launch_bounds__(kLanes) void k_render_bwd(const ViewDev* __restrict
             const float4 g = s_st[k].geo;
             const float4 cc = s_st[k].col;
             const float cb = s_st[k].blu;
+            const float thr = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(s_st[k].thr)));
             const uint32_t word = (uint32_t)__builtin_amdgcn_readfirstlane((int)s_st[k].aux[1]);
             const int32_t slot = __builtin_amdgcn_readfirstlane((int)s_st[k].aux[0]);
+            const float o = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(cc.y)));
             const int32_t pos = (int32_t)(word >> 4);
             // Per-lane sums over the lane's pixels, later reduced over the wave:
             //   m[0..1] = sum dq' (dx, dy), m[2..4] = sum dq' (dx^2, dx dy, dy^2)
-            //   with dq' = alpha dL/dalpha (so dL/dq = -dq'/2), m[5] = sum e dL/dalpha,
+            //   with dq' = alpha dL/dalpha (so dL/dq = -dq'/2), m[5] = sum dq'
+            //   (dL/do = m[5] / o, since alpha = o e^{-q/2} wherever dq' is not zero),
             //   m[6..8] = sum T alpha G (colour).
+            // They start at -0, the additive identity, so the first block's adds fold away.
             float m[9];
 #pragma unroll
-            for (int i = 0; i < 9; i++) m[i] = 0.0f;
-            // one block of the lane's four pixels (j is a constant after inlining)
-            auto block = [&](const int j) __attribute__((always_inline)) {
+            for (int i = 0; i < 9; i++) m[i] = -0.0f;
+            // one block of the lane's four pixels (j and clamp are constants after inlining)
+            auto block = [&](const int j, const bool clamp) __attribute__((always_inline)) {
                 const float dx = t.fx[j] - g.x, dy = t.fy[j] - g.y;
                 const float qs = quad(dx, dy, g.z, g.w, cc.x);     // -q log2(e) / 2
-                const Eval ev = evaluate(qs, cc.y);   // bit-identical to the forward's alpha
+                const float raw = raw_alpha(qs, o);
+                const float al = clamp ? clamp_alpha(raw, kAlphaMax) : raw;   // the forward's alpha
                 // the forward's decision: a pixel still compositing at this position took every
                 // Gaussian inside the footprint with alpha >= 1/255 (it stops only after its last one)
-                const bool in = pos < nc[j] && qs >= kSMin && ev.alpha >= kAlphaMin;
-                const float al = ev.alpha;
+                const bool in = pos < nc[j] && qs >= thr;
                 const float ae = in ? al : 0.0f;      // 0 for pixels that did not take it: T, S unchanged
                 const float Tk = T[j] * __builtin_amdgcn_rcpf(1.0f - ae);   // transmittance in front of k
                 T[j] = Tk;
@@ -477,13 +503,14 @@ __global__ __launch_bounds__(kLanes) void k_render_bwd(const ViewDev* __restrict
                 m[6] = fmaf(w, G0[j], m[6]);
                 m[7] = fmaf(w, G1[j], m[7]);
                 m[8] = fmaf(w, G2[j], m[8]);
-                const float gc = fmaf(G2[j], cb, fmaf(G1[j], cc.w, G0[j] * cc.z));
-                const float diff = gc - S[j];         // G . (c - B)
+                // G . (c - B) = G . c - S
+                const float diff = fmaf(G2[j], cb, fmaf(G1[j], cc.w, fmaf(G0[j], cc.z, -S[j])));
                 S[j] = fmaf(ae, diff, S[j]);
-                // dL/dalpha, kept only where the pixel took the Gaussian and alpha was not clamped
-                const float dau = (in && ev.raw < kAlphaMax) ? Tk * diff : 0.0f;
-                m[5] = fmaf(dau, ev.e, m[5]);
-                const float dqp = al * dau;
+                // dq' = alpha dL/dalpha = T_k alpha G . (c - B): zero where the pixel did not take
+                // the Gaussian (w = 0) and where the clamp holds alpha at 0.99
+                float dqp = w * diff;
+                if (clamp) dqp = al < kAlphaMax ? dqp : 0.0f;
+                m[5] += dqp;
                 const float px = dqp * dx, py = dqp * dy;
                 m[0] += px;
                 m[1] += py;
@@ -492,25 +519,29 @@ __global__ __launch_bounds__(kLanes) void k_render_bwd(const ViewDev* __restrict
                 m[4] = fmaf(py, dy, m[4]);
             };
             // blocks whose bit is set, entered at the first one so that its code starts the
-            // sums from zero (a tile's entry always has at least one block)
+            // sums (a tile's entry always has at least one block)
             static_assert(kPPT == 4, "four blocks per tile");
             const uint32_t bits = word & ((1u << kPPT) - 1u);
             const int j0 = __builtin_ctz(bits);
-            if (j0 == 0) {
-                block(0);
-                if (bits & 2u) block(1);
-                if (bits & 4u) block(2);
-                if (bits & 8u) block(3);
-            } else if (j0 == 1) {
-                block(1);
-                if (bits & 4u) block(2);
-                if (bits & 8u) block(3);
-            } else if (j0 == 2) {
-                block(2);
-                if (bits & 8u) block(3);
-            } else {
-                block(3);
-            }
+            auto blocks = [&](const bool clamp) __attribute__((always_inline)) {
+                if (j0 == 0) {
+                    block(0, clamp);
+                    if (bits & 2u) block(1, clamp);
+                    if (bits & 4u) block(2, clamp);
+                    if (bits & 8u) block(3, clamp);
+                } else if (j0 == 1) {
+                    block(1, clamp);
+                    if (bits & 4u) block(2, clamp);
+                    if (bits & 8u) block(3, clamp);
+                } else if (j0 == 2) {
+                    block(2, clamp);
+                    if (bits & 8u) block(3, clamp);
+                } else {
+                    block(3, clamp);
+                }
+            };
+            if (may_clamp(o)) blocks(true);
+            else blocks(false);
             // the moments go to the slot as they are: the mean and conic gradients are
             // linear in them (dm = Q (m0, m1), d(a, b, c) = -(m2 / 2, m3, m4 / 2)), so the
             // projection adjoint forms them once per record from its summed slots
