@@ -231,25 +231,27 @@ __global__ __launch_bounds__(kLanes) __attribute__((amdgpu_waves_per_eu(8, 8))) 
     float T[kPPT], C0[kPPT], C1[kPPT], C2[kPPT];
     int32_t n[kPPT];         // list positions the pixel reached: where it stopped, else the list length
     uint64_t live[kPPT];     // lanes of slot j still compositing (wave-uniform lane mask)
+    uint32_t alive = 0;      // bit j: live[j] != 0 (one scalar test per block instead of a 64-bit one)
 #pragma unroll
     for (int j = 0; j < kPPT; j++) {
         T[j] = 1.0f;
         C0[j] = C1[j] = C2[j] = 0.0f;
         n[j] = rg.y - rg.x;
         live[j] = __ballot(t.inside[j]);
+        alive |= live[j] != 0 ? 1u << j : 0u;
     }
     uint64_t n_eval = 0, n_comp = 0;        // wave totals (STATS only)
     int32_t n_entries = 0;                  // Gaussians of the tile list that composited somewhere
     const int lane = threadIdx.x;
     for (int32_t b0 = rg.x; b0 < rg.y; b0 += BATCH) {
-        if ((live[0] | live[1] | live[2] | live[3]) == 0) break;
+        if (alive == 0) break;
         __syncthreads();
         for (int32_t i = threadIdx.x; i < BATCH && b0 + i < rg.y; i += kLanes)
             stage<TW, TH, true>(splats, values[b0 + i], t.ox, t.oy, t.col0, t.row0, s_st, i);
         __syncthreads();
         const int32_t cnt = min(BATCH, rg.y - b0);
         // sub-batches of 64 Gaussians: bit (k - k0) of took[j] records that a pixel of block j took Gaussian k
-        for (int32_t k0 = 0; k0 < cnt && (live[0] | live[1] | live[2] | live[3]) != 0; k0 += kLanes) {
+        for (int32_t k0 = 0; k0 < cnt && alive != 0; k0 += kLanes) {
             const int32_t k1 = min(cnt, k0 + kLanes);
             uint64_t took[kPPT] = {0, 0, 0, 0};
             for (int32_t k = k0; k < k1; k++) {
@@ -261,11 +263,13 @@ __global__ __launch_bounds__(kLanes) __attribute__((amdgpu_waves_per_eu(8, 8))) 
                 const uint32_t mask = (uint32_t)__builtin_amdgcn_readfirstlane((int)s_st[k].aux[0]);
                 const int32_t pos = b0 - rg.x + k;
                 const uint64_t kbit = 1ull << (k - k0);
-                const float cap = (mask & kClampBit) ? kAlphaMax : __builtin_inff();
+                // selected as integer bits, so the select stays on the scalar unit
+                const float cap = __int_as_float((mask & kClampBit) ? __float_as_int(kAlphaMax) : 0x7f800000);
+                const uint32_t act = mask & alive;    // blocks the ellipse can reach that still composite
 #pragma unroll
                 for (int j = 0; j < kPPT; j++) {
                     if (STATS) n_eval += __popcll(live[j]);
-                    if (!((mask >> j) & 1u) || live[j] == 0) continue;   // ellipse misses the block / block done
+                    if (!((act >> j) & 1u)) continue;   // ellipse misses the block / block done
                     const float dx = t.fx[j] - g.x, dy = t.fy[j] - g.y;
                     const float qs = quad(dx, dy, g.z, g.w, cc.x);     // -q log2(e) / 2
                     const uint64_t inm = __ballot(qs >= thr) & live[j];   // q <= 9 and alpha >= 1/255
@@ -277,6 +281,7 @@ __global__ __launch_bounds__(kLanes) __attribute__((amdgpu_waves_per_eu(8, 8))) 
                     if (stopm) {     // once per pixel
                         live[j] &= ~stopm;
                         n[j] = __builtin_amdgcn_inverse_ballot_w64(stopm) ? pos : n[j];
+                        if (live[j] == 0) alive &= ~(1u << j);
                     }
                     took[j] |= takem ? kbit : 0ull;
                     if (STATS) n_comp += __popcll(takem);
@@ -287,7 +292,7 @@ __global__ __launch_bounds__(kLanes) __attribute__((amdgpu_waves_per_eu(8, 8))) 
                     C2[j] = fmaf(w, cb, C2[j]);
                     T[j] = take ? Tn : T[j];
                 }
-                if ((live[0] | live[1] | live[2] | live[3]) == 0) break;   // every pixel has terminated
+                if (alive == 0) break;   // every pixel has terminated
             }
             // entries of the sub-batch for the adjoint (lane i: Gaussian k0 + i), stored in list order
             uint32_t bits = 0;
