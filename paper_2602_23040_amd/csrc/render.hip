@@ -61,37 +61,42 @@ constexpr float kAlphaMin = 1.0f / 255.0f;
 constexpr float kTMin = 1e-4f;
 // The staged conic is scaled by -log2(e) / 2, so the quadratic form gives
 // s = -q log2(e) / 2 directly: e^{-q/2} = 2^s, and q <= 9 reads s >= 9 (-log2(e) / 2).
+// The opacity is staged as lo = log2 o and added in the quadratic's last
+// fused multiply-add: s' = s + lo, and o e^{-q/2} = 2^{s'} without a multiply.
 constexpr float kQScale = -0.72134752044448170f;
 constexpr float kSMin = kQMax * kQScale;
+constexpr float kLog2AlphaMin = -7.99435343685885793f;     // log2(1 / 255)
+constexpr float kLog2AlphaMax = -0.01449956969511509f;     // log2(0.99)
 
-// The one definition of s, alpha and the take decision used by both the
+// The one definition of s', alpha and the take decision used by both the
 // forward and the adjoint, with explicit fused multiply-adds so both kernels
 // take bit-identical decisions (the library is compiled with -ffp-contract=off).
-__device__ __forceinline__ float quad(float dx, float dy, float a, float b2, float c) {
+__device__ __forceinline__ float quad(float dx, float dy, float a, float b2, float c, float lo) {
     const float u = fmaf(b2, dy, a * dx);      // a dx + 2 b dy
-    return fmaf(u, dx, (c * dy) * dy);         // dx (a dx + 2 b dy) + c dy^2
+    return fmaf(u, dx, fmaf(c * dy, dy, lo));  // dx (a dx + 2 b dy) + c dy^2 + lo
 }
 
-// Smallest s a pixel needs: q <= 9 (s >= kSMin) and alpha >= 1/255, i.e.
-// o 2^s >= 1/255, s >= log2(1 / (255 o)); one compare per pixel instead of two.
-// Exact up to the rounding of the logarithm (a relative 1e-7 of alpha at the
-// threshold) where the product test would round exp2 instead.
-__device__ __forceinline__ float take_threshold(float o) {
-    return o > 0.0f ? fmaxf(kSMin, __builtin_amdgcn_logf(kAlphaMin / o)) : __builtin_inff();
+// Smallest s' a pixel needs: q <= 9 (s' >= kSMin + lo) and alpha >= 1/255
+// (s' >= log2(1/255)); one compare per pixel.  log2 o = -inf (o = 0) or NaN
+// (o < 0) makes s' -inf or NaN, which no pixel passes.
+__device__ __forceinline__ float take_threshold(float lo) {
+    return fmaxf(kSMin + lo, kLog2AlphaMin);
 }
 
-// The 0.99 clamp can only bind when o >= 0.99, since e^{-q/2} <= 1: the flag
-// is decided per Gaussian (as integer bits, the same in both kernels).  The
-// forward clamps at alpha_cap (0.99, or +inf below that opacity: one min
-// either way); the adjoint has a copy of its loop without the clamp for the
-// Gaussians that cannot reach it, and takes alpha = o e^{-q/2} there, which
-// is the forward's value for every non-NaN product.
-__device__ __forceinline__ bool may_clamp(float o) {
-    return __float_as_int(o) >= __float_as_int(kAlphaMax);
+// The 0.99 clamp can only bind when lo >= log2(0.99), since 2^{s'} <= 2^{lo}
+// for q >= 0: the flag is decided per Gaussian (as integer bits, the same in
+// both kernels; lo <= 0, and lo = 0 for o = 1).  The forward clamps at a cap
+// (0.99, or +inf when the flag is clear: one median either way); the adjoint
+// has a copy of its loop without the clamp for the Gaussians that cannot
+// reach it, and takes alpha = 2^{s'} there, the forward's value for every
+// non-NaN s'.
+__device__ __forceinline__ bool may_clamp(float lo) {
+    const int b = __float_as_int(lo);
+    return b >= 0 || b <= __float_as_int(kLog2AlphaMax);
 }
 
-__device__ __forceinline__ float raw_alpha(float s, float o) {
-    return o * __builtin_amdgcn_exp2f(s);                 // o e^{-q/2}
+__device__ __forceinline__ float raw_alpha(float s1) {
+    return __builtin_amdgcn_exp2f(s1);                    // o e^{-q/2}
 }
 
 // min(raw, cap) for the raw >= 0 of every pixel that can take the Gaussian
@@ -172,13 +177,13 @@ __device__ __forceinline__ bool tile_geo(const ViewDev* views, int nv, int64_t n
 // block mask (forward) or the gradient slot and the entry word (adjoint).
 struct alignas(16) Staged {
     float4 geo;          // local mean x, y; conic a, 2 b (scaled by kQScale)
-    float4 col;          // conic c (scaled by kQScale), opacity, red, green
+    float4 col;          // conic c (scaled by kQScale), log2 opacity, red, green
     float blu;           // blue
-    float thr;           // take_threshold(opacity)
+    float thr;           // take_threshold(log2 opacity)
     uint32_t aux[2];
 };
 
-constexpr uint32_t kClampBit = 1u << kPPT;   // forward's aux[0]: may_clamp(opacity)
+constexpr uint32_t kClampBit = 1u << kPPT;   // forward's aux[0]: may_clamp(log2 opacity)
 
 template <int TW, int TH, bool MASK>
 __device__ __forceinline__ void stage(const pg_splat* __restrict__ splats, int32_t gv, double ox, double oy,
@@ -189,9 +194,10 @@ __device__ __forceinline__ void stage(const pg_splat* __restrict__ splats, int32
     *reinterpret_cast<float4*>(&m) = a;
     const float mx = (float)(m.x - ox), my = (float)(m.y - oy);
     s_st[k].geo = make_float4(mx, my, b.x * kQScale, 2.0f * b.y * kQScale);
-    s_st[k].col = make_float4(b.z * kQScale, b.w, c.x, c.y);   // scaled conic c, opacity, red, green
+    const float lo = __builtin_amdgcn_logf(b.w);                // log2 opacity
+    s_st[k].col = make_float4(b.z * kQScale, lo, c.x, c.y);     // scaled conic c, log2 opacity, red, green
     s_st[k].blu = c.z;
-    s_st[k].thr = take_threshold(b.w);
+    s_st[k].thr = take_threshold(lo);
     if (!MASK) return;
     constexpr int BPR = TW / 8;
     const float ac = b.x * b.z;
@@ -207,7 +213,7 @@ __device__ __forceinline__ void stage(const pg_splat* __restrict__ splats, int32
             if (mx + ex >= x0 && mx - ex <= x0 + 7.0f && my + ey >= y0 && my - ey <= y0 + 7.0f) mask |= 1u << j;
         }
     }
-    s_st[k].aux[0] = mask | (may_clamp(b.w) ? kClampBit : 0u);
+    s_st[k].aux[0] = mask | (may_clamp(lo) ? kClampBit : 0u);
 }
 
 // Eight waves per SIMD (64 registers): the forward waits on its per-Gaussian
@@ -271,10 +277,10 @@ __global__ __launch_bounds__(kLanes) __attribute__((amdgpu_waves_per_eu(8, 8))) 
                     if (STATS) n_eval += __popcll(live[j]);
                     if (!((act >> j) & 1u)) continue;   // ellipse misses the block / block done
                     const float dx = t.fx[j] - g.x, dy = t.fy[j] - g.y;
-                    const float qs = quad(dx, dy, g.z, g.w, cc.x);     // -q log2(e) / 2
+                    const float qs = quad(dx, dy, g.z, g.w, cc.x, cc.y);   // -q log2(e) / 2 + log2 o
                     const uint64_t inm = __ballot(qs >= thr) & live[j];   // q <= 9 and alpha >= 1/255
                     if (inm == 0) continue;
-                    const float alpha = clamp_alpha(raw_alpha(qs, cc.y), cap);
+                    const float alpha = clamp_alpha(raw_alpha(qs), cap);
                     const float Tn = T[j] * (1.0f - alpha);
                     const uint64_t stopm = __ballot(Tn < kTMin) & inm;
                     const uint64_t takem = inm & ~stopm;
@@ -481,7 +487,7 @@ __global__ __launch_bounds__(kLanes) void k_render_bwd(const ViewDev* __restrict
             const float thr = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(s_st[k].thr)));
             const uint32_t word = (uint32_t)__builtin_amdgcn_readfirstlane((int)s_st[k].aux[1]);
             const int32_t slot = __builtin_amdgcn_readfirstlane((int)s_st[k].aux[0]);
-            const float o = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(cc.y)));
+            const float lo = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(cc.y)));
             const int32_t pos = (int32_t)(word >> 4);
             // Per-lane sums over the lane's pixels, later reduced over the wave:
             //   m[0..1] = sum dq' (dx, dy), m[2..4] = sum dq' (dx^2, dx dy, dy^2)
@@ -495,8 +501,8 @@ __global__ __launch_bounds__(kLanes) void k_render_bwd(const ViewDev* __restrict
             // one block of the lane's four pixels (j and clamp are constants after inlining)
             auto block = [&](const int j, const bool clamp) __attribute__((always_inline)) {
                 const float dx = t.fx[j] - g.x, dy = t.fy[j] - g.y;
-                const float qs = quad(dx, dy, g.z, g.w, cc.x);     // -q log2(e) / 2
-                const float raw = raw_alpha(qs, o);
+                const float qs = quad(dx, dy, g.z, g.w, cc.x, lo);   // -q log2(e) / 2 + log2 o
+                const float raw = raw_alpha(qs);
                 const float al = clamp ? clamp_alpha(raw, kAlphaMax) : raw;   // the forward's alpha
                 // the forward's decision: a pixel still compositing at this position took every
                 // Gaussian inside the footprint with alpha >= 1/255 (it stops only after its last one)
@@ -545,7 +551,7 @@ __global__ __launch_bounds__(kLanes) void k_render_bwd(const ViewDev* __restrict
                     block(3, clamp);
                 }
             };
-            if (may_clamp(o)) blocks(true);
+            if (may_clamp(lo)) blocks(true);
             else blocks(false);
             // the moments go to the slot as they are: the mean and conic gradients are
             // linear in them (dm = Q (m0, m1), d(a, b, c) = -(m2 / 2, m3, m4 / 2)), so the
