@@ -159,7 +159,8 @@ __device__ __forceinline__ void view_dir(const ViewDev& V, const World& w, doubl
     d[1] = w.mu[1] - V.cw[1];
     d[2] = w.mu[2] - V.cw[2];
     *dn = sqrt((d[0] * d[0] + d[1] * d[1]) + d[2] * d[2]);
-    d[0] /= *dn; d[1] /= *dn; d[2] /= *dn;
+    const double inv = 1.0 / *dn;      // the direction only feeds the colour (no integer decision)
+    d[0] *= inv; d[1] *= inv; d[2] *= inv;
 }
 
 // ---- FP32 SH basis and its contracted gradient for the colour adjoint
@@ -341,9 +342,12 @@ __global__ __launch_bounds__(kProjBlk) void k_project(const ViewDev* __restrict_
                 const double raw = 0.5 + acc;
                 col[ch] = (float)(raw > 0.0 ? raw : 0.0);
             }
-            A = c.cp / c.det;
-            B = -c.bp / c.det;
-            Cq = c.ap / c.det;
+            // the conic decides no integer by itself (the tile test below keeps a
+            // margin), so one reciprocal serves its three entries
+            const double idet = 1.0 / c.det;
+            A = c.cp * idet;
+            B = -c.bp * idet;
+            Cq = c.ap * idet;
             const uint64_t bx = (uint64_t)__double_as_longlong(mx), by = (uint64_t)__double_as_longlong(my);
             o0 = make_float4(__uint_as_float((uint32_t)bx), __uint_as_float((uint32_t)(bx >> 32)),
                              __uint_as_float((uint32_t)by), __uint_as_float((uint32_t)(by >> 32)));   // the FP64 mean's bits
@@ -368,8 +372,9 @@ __global__ __launch_bounds__(kProjBlk) void k_project(const ViewDev* __restrict_
         s_geo[2][tid] = A;
         s_geo[3][tid] = B;
         s_geo[4][tid] = Cq;
-        s_geo[5][tid] = -B / Cq;
-        s_geo[6][tid] = -B / A;
+        const double iac = 1.0 / (A * Cq);         // edge-vertex slopes -B / C and -B / A
+        s_geo[5][tid] = -B * A * iac;
+        s_geo[6][tid] = -B * Cq * iac;
         s_rect[0][tid] = ixl;
         s_rect[1][tid] = iyl;
         s_rect[2][tid] = wdt;
