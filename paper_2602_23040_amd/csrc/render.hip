@@ -281,7 +281,8 @@ __global__ __launch_bounds__(kLanes) __attribute__((amdgpu_waves_per_eu(8, 8))) 
                     const uint64_t inm = __ballot(qs >= thr) & live[j];   // q <= 9 and alpha >= 1/255
                     if (inm == 0) continue;
                     const float alpha = clamp_alpha(raw_alpha(qs), cap);
-                    const float Tn = T[j] * (1.0f - alpha);
+                    const float wa = T[j] * alpha;
+                    const float Tn = T[j] - wa;          // T (1 - alpha)
                     const uint64_t stopm = __ballot(Tn < kTMin) & inm;
                     const uint64_t takem = inm & ~stopm;
                     if (stopm) {     // once per pixel
@@ -292,7 +293,7 @@ __global__ __launch_bounds__(kLanes) __attribute__((amdgpu_waves_per_eu(8, 8))) 
                     took[j] |= takem ? kbit : 0ull;
                     if (STATS) n_comp += __popcll(takem);
                     const bool take = __builtin_amdgcn_inverse_ballot_w64(takem);
-                    const float w = take ? T[j] * alpha : 0.0f;
+                    const float w = take ? wa : 0.0f;
                     C0[j] = fmaf(w, cc.z, C0[j]);
                     C1[j] = fmaf(w, cc.w, C1[j]);
                     C2[j] = fmaf(w, cb, C2[j]);
