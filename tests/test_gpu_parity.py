@@ -28,6 +28,11 @@ SCENES = {
     # single digit (the copy path) and the tile lists keep equal depths in id order
     "flat": lambda: synth.random_scene(side=12, sh_degree=1, views=0, width=64, height=48, seed=7,
                                        pos=((-1, -1, 3), (1, 1, 3)), lscale=(-3.4, 0.4)),
+    # mostly opaque Gaussians (logit-opacity N(6, 1.5): about 80 % at o >= 0.99, with a few
+    # dozen clamped pixels per view): the compositing kernels' clamped-alpha paths, and
+    # pixels that stop early
+    "opaque": lambda: synth.random_scene(side=14, sh_degree=1, views=2, width=80, height=60, seed=11,
+                                         lscale=(-2.2, 0.4), lopac=(6.0, 1.5)),
     "config1": lambda: synth.make_scene(1),
     "config2": lambda: synth.make_scene(2),
 }
