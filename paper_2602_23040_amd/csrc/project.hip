@@ -592,7 +592,7 @@ __global__ __launch_bounds__(256) void k_dyn_texel(const uint8_t* __restrict__ d
 // elongated Gaussian's long axis (and the quaternion's tangent component in
 // general) is a small difference of large terms: in FP32 a few texels of the
 // 2048^2 workload missed 1e-3.  No SH coefficients are held here.
-__global__ __launch_bounds__(128) void k_project_bwd_geo(const ViewDev* __restrict__ views,
+__global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(3))) void k_project_bwd_geo(const ViewDev* __restrict__ views,
                                                          const int32_t* __restrict__ frame_views,
                                                          const int32_t* __restrict__ view_order, int32_t F,
                                                          int32_t C, int64_t N, int64_t n_gv,
@@ -616,10 +616,11 @@ __global__ __launch_bounds__(128) void k_project_bwd_geo(const ViewDev* __restri
     // dL/dSigma (world) and dL/do summed over the views: the scale, rotation and
     // activation chains after them are linear and view-independent, so they run
     // once per Gaussian on the sums instead of once per record
-    double GSw_sum[9], go_sum = 0.0;
+    // (dL/dSigma is symmetric: its upper triangle 00, 01, 02, 11, 12, 22 is summed)
+    double GSw_sum[6], go_sum = 0.0;
 #pragma unroll
-    for (int k = 0; k < 9; k++) GSw_sum[k] = 0.0;
-    World w;
+    for (int k = 0; k < 6; k++) GSw_sum[k] = 0.0;
+    World w;     // in the view loop only its mean, Sigma and opacity are used
     bool have_world = false;
     // the record's slot sums (0 for culled records): the compositing moments
     // sum dq' (dx, dy, dx^2, dx dy, dy^2) and sum dq', with dq' = alpha dL/dalpha;
@@ -705,9 +706,13 @@ __global__ __launch_bounds__(128) void k_project_bwd_geo(const ViewDev* __restri
 #pragma unroll
         for (int r = 0; r < 3; r++)
 #pragma unroll
-            for (int k = 0; k < 3; k++) GSw[3 * r + k] = R[r] * tmp[k] + R[3 + r] * tmp[3 + k] + R[6 + r] * tmp[6 + k];
-#pragma unroll
-        for (int k = 0; k < 9; k++) GSw_sum[k] += GSw[k];
+            for (int k = r; k < 3; k++) GSw[3 * r + k] = R[r] * tmp[k] + R[3 + r] * tmp[3 + k] + R[6 + r] * tmp[6 + k];
+        GSw_sum[0] += GSw[0];
+        GSw_sum[1] += GSw[1];
+        GSw_sum[2] += GSw[2];
+        GSw_sum[3] += GSw[4];
+        GSw_sum[4] += GSw[5];
+        GSw_sum[5] += GSw[8];
         // mean: dm/dmu_c = J, plus the dependence of J on mu_c
         const double iz = 1.0 / c.zc, iz2 = iz * iz, iz3 = iz2 * iz;
         double gmc0 = c.J[0] * g6[0] + c.J[3] * g6[1];
@@ -722,14 +727,21 @@ __global__ __launch_bounds__(128) void k_project_bwd_geo(const ViewDev* __restri
         go_sum += g6[5];
     }
     if (have_world) {
+        // The world chain again, so that its rotation, scale and M need no registers
+        // during the view loop (the opaque step keeps the compiler from reusing w).
+#pragma unroll
+        for (int k = 0; k < 11; k++) asm volatile("" : "+v"(rec[k]));
+        world_chain(rec, w);
+        const double Gs[9] = {GSw_sum[0], GSw_sum[1], GSw_sum[2], GSw_sum[1], GSw_sum[3], GSw_sum[4],
+                              GSw_sum[2], GSw_sum[4], GSw_sum[5]};
         // dL/dM = 2 GSw M ; dL/ds (log-scale) ; dL/dRq -> the normalised quaternion -> the stored one
         double gs[3] = {0.0, 0.0, 0.0}, GR[9];
 #pragma unroll
         for (int r = 0; r < 3; r++)
 #pragma unroll
             for (int k = 0; k < 3; k++) {
-                const double gm = 2.0 * (GSw_sum[3 * r] * w.M[k] + GSw_sum[3 * r + 1] * w.M[3 + k] +
-                                         GSw_sum[3 * r + 2] * w.M[6 + k]);
+                const double gm = 2.0 * (Gs[3 * r] * w.M[k] + Gs[3 * r + 1] * w.M[3 + k] +
+                                         Gs[3 * r + 2] * w.M[6 + k]);
                 gs[k] += gm * w.Rq[3 * r + k];
                 GR[3 * r + k] = gm * w.s[k];
             }
