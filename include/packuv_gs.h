@@ -134,8 +134,9 @@ const char* pg_last_error(void);
 /* Builds the device-resident view table for V cameras over `frames` atlases
  * of `n_gauss` Gaussians each (SH degree 0..3).  cams: host [V].  Fails with
  * PG_ERR_INVALID_ARG on bad cameras (fx, fy <= 0, size < 1, frame out of
- * range), unsupported tiling, when n_gauss exceeds 2^28, or when V * n_gauss
- * or the tile count exceed 2^31 - 1.  Allocates device memory (the only
+ * range), unsupported tiling, when frames exceeds 65535 (the projection
+ * kernels launch one grid row per frame), when n_gauss exceeds 2^28, or when
+ * V * n_gauss or the tile count exceed 2^31 - 1.  Allocates device memory (the only
  * allocating call). */
 pg_status pg_views_create(const pg_camera* cams, int32_t n_views, int32_t frames, int64_t n_gauss,
                           int32_t sh_degree, pg_tiling tiling, pg_views** out);

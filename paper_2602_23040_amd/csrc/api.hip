@@ -112,7 +112,7 @@ pg_status pg_views_create(const pg_camera* cams, int32_t n_views, int32_t frames
     *out = nullptr;
     if (!cams) return invalid("cams is null");
     if (n_views < 1 || n_views > kMaxViews) return invalid("n_views must be in [1, 65536]");
-    if (frames < 1) return invalid("frames must be >= 1");
+    if (frames < 1 || frames > 65535) return invalid("frames must be in [1, 65535]");
     if (n_gauss < 0) return invalid("n_gauss must be >= 0");
     if (sh_degree < 0 || sh_degree > 3) return invalid("sh_degree must be in [0, 3]");
     if (!tiling_ok(tiling))

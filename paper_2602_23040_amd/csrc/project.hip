@@ -272,25 +272,19 @@ __global__ __launch_bounds__(kProjBlk) void k_project(const ViewDev* __restrict_
     __shared__ uint16_t s_item[kProjBlk * kMaskTiles];   // test q: owner thread << 6 | rectangle bit
     __shared__ unsigned long long s_mask[kProjBlk];
     __shared__ int32_t s_wsum[kProjBlk / 64];
-    __shared__ int32_t s_nv;
     const int tid = threadIdx.x;
-    const int64_t g = (int64_t)blockIdx.x * kProjBlk + tid;
-    int32_t f = 0, v0 = 0, v1 = 0;
-    int64_t i = 0;
-    if (g < (int64_t)F * N) {
-        f = (int32_t)(g / N);
-        i = g - (int64_t)f * N;
-        v0 = frame_views[f];
-        v1 = frame_views[f + 1];
-    }
-    if (tid == 0) s_nv = 0;
-    __syncthreads();
-    if (v1 > v0) atomicMax(&s_nv, v1 - v0);
-    __syncthreads();
-    const int32_t nv = s_nv;
-    if (nv == 0) return;     // uniform over the work-group
+    // grid (Gaussian chunks, frames): the frame, its views and so every view's camera
+    // are uniform over the work-group, and the camera is read with scalar loads
+    const int32_t f = (int32_t)blockIdx.y;
+    const int64_t i0 = (int64_t)blockIdx.x * kProjBlk + tid;
+    const bool in_range = i0 < N;
+    const int64_t i = in_range ? i0 : 0;
+    const int64_t g = (int64_t)f * N + i;
+    const int32_t v0 = frame_views[f], v1 = frame_views[f + 1];
+    const int32_t nv = v1 - v0;
+    if (nv <= 0) return;     // uniform over the work-group
     const float* P = params + (int64_t)f * C * N + i;
-    const bool has = v1 > v0;
+    const bool has = in_range;
     float rec[11];
 #pragma unroll
     for (int k = 0; k < 11; k++) rec[k] = has ? P[(int64_t)k * N] : 0.0f;
@@ -302,8 +296,8 @@ __global__ __launch_bounds__(kProjBlk) void k_project(const ViewDev* __restrict_
     const double itw = 1.0 / (double)tw, ith = 1.0 / (double)th;   // exact: tw, th are 8, 16 or 32
     bool any = false;
     for (int32_t k = 0; k < nv; k++) {
-        const bool act = v0 + k < v1;
-        const int32_t v = act ? view_order[v0 + k] : 0;
+        const bool act = has;
+        const int32_t v = view_order[v0 + k];
         const ViewDev& V = views[v];
         Cam c;
         float4 o0 = make_float4(0.f, 0.f, 0.f, 0.f), o1 = o0, o2 = o0;
@@ -425,7 +419,7 @@ __global__ __launch_bounds__(kProjBlk) void k_project(const ViewDev* __restrict_
             reinterpret_cast<uint4*>(tiles)[gv] = ts;
         }
     }
-    if (any) visible[g] = 1;
+    if (any && has) visible[g] = 1;
 }
 
 // ---------------------------------------------------------------- flow masking
@@ -601,10 +595,11 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(3))) void k
                                                          const int32_t* __restrict__ gauss_texel,
                                                          const uint8_t* __restrict__ dyn, int64_t HW,
                                                          float* __restrict__ gatlas, int32_t accumulate) {
-    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= (int64_t)F * N) return;
-    const int32_t f = (int32_t)(g / N);
-    const int64_t i = g - (int64_t)f * N;
+    // grid (Gaussian chunks, frames): the frame and its cameras are uniform over the
+    // work-group, so the cameras are read with scalar loads
+    const int32_t f = (int32_t)blockIdx.y;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
     const int32_t v0 = frame_views[f], v1 = frame_views[f + 1];
     const float* P = params + (int64_t)f * C * N + i;
     float rec[11];
@@ -786,10 +781,11 @@ __global__ __launch_bounds__(128) void k_project_bwd_sh(const ViewDev* __restric
                                                         const uint8_t* __restrict__ dyn, int64_t HW,
                                                         float* __restrict__ gatlas, int32_t accumulate) {
     constexpr int NB = (L + 1) * (L + 1);
-    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= (int64_t)F * N) return;
-    const int32_t f = (int32_t)(g / N);
-    const int64_t i = g - (int64_t)f * N;
+    // grid (Gaussian chunks, frames): the frame and its cameras are uniform over the
+    // work-group, so the cameras are read with scalar loads
+    const int32_t f = (int32_t)blockIdx.y;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
     const int32_t v0 = frame_views[f], v1 = frame_views[f + 1];
     const float* P = params + (int64_t)f * C * N + i;
     World wpos;                      // only mu is used (view direction)
@@ -953,7 +949,7 @@ hipError_t launch_project(const pg_views* v, const float* params, pg_splat* spla
                           pg_tile_set* tiles, uint8_t* visible, hipStream_t s) {
     const int64_t n = (int64_t)v->frames * v->n_gauss;
     if (n == 0) return hipSuccess;
-    const unsigned grid = (unsigned)ceil_div(n, 128);
+    const dim3 grid((unsigned)ceil_div(v->n_gauss, 128), (unsigned)v->frames);
     auto args = [&](auto kern) {
         kern<<<grid, 128, 0, s>>>(v->d_views, v->d_frame_views, v->d_view_order, v->frames, v->channels, v->n_gauss,
                                   v->tiling.tile_w, v->tiling.tile_h, params, splats, bins, tiles, visible);
@@ -986,7 +982,7 @@ hipError_t launch_project_bwd(const pg_views* v, const float* params, float* gra
     }
     const int64_t n = (int64_t)v->frames * v->n_gauss;
     if (n == 0) return hipGetLastError();
-    const unsigned grid = (unsigned)ceil_div(n, 128);
+    const dim3 grid((unsigned)ceil_div(v->n_gauss, 128), (unsigned)v->frames);
     k_project_bwd_geo<<<grid, 128, 0, s>>>(v->d_views, v->d_frame_views, v->d_view_order, v->frames, v->channels,
                                            v->n_gauss, v->n_gv, params, grad2d, gauss_texel, dyn, HW, dL_datlas,
                                            accumulate);

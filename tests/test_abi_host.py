@@ -64,6 +64,9 @@ def test_views_create_rejects_bad_sh_degree_and_overflow():
     with pytest.raises(abi.PGError) as e:
         abi.pg_views_create([_cam()] * 3, 1, 2 ** 30, 0, abi.make_tiling())
     assert "2^31" in str(e.value)
+    with pytest.raises(abi.PGError) as e:     # one projection grid row per frame
+        abi.pg_views_create([_cam()], 65536, 10, 0, abi.make_tiling())
+    assert "frames must be" in str(e.value)
 
 
 def test_entry_points_reject_null_pointers():
