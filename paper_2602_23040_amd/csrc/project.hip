@@ -468,17 +468,19 @@ __global__ __launch_bounds__(128) void k_flow_mask(const ViewDev* __restrict__ v
                                                    const uint8_t* __restrict__ masks,
                                                    const uint8_t* __restrict__ tmot, uint8_t* __restrict__ dyn_gauss,
                                                    unsigned long long* __restrict__ counters) {
-    const int64_t gv = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    // work-group b takes records [c * 128, c * 128 + 128) of view b / chunks (c = b mod
+    // chunks): the view, so its camera, is uniform over the work-group (scalar loads)
+    const int64_t chunks = (N + 127) / 128;
+    const int32_t v = (int32_t)((int64_t)blockIdx.x / chunks);
+    const int64_t i = ((int64_t)blockIdx.x - (int64_t)v * chunks) * 128 + threadIdx.x;
     const int lane = (int)(threadIdx.x & 63);
     uint64_t tests = 0;
     // this thread's record: projection, clipped square and the motion-tile test
     bool any = false;
-    int32_t v = 0, ix0 = 0, ix1 = -1, iy0 = 0, iy1 = -1;
+    int32_t ix0 = 0, ix1 = -1, iy0 = 0, iy1 = -1;
     int64_t out = 0;
     double mx = 0.0, my = 0.0, A = 1.0, B = 0.0, Cq = 1.0;
-    if (gv < n_gv) {
-        v = (int32_t)(gv / N);
-        const int64_t i = gv - (int64_t)v * N;
+    if (i < N) {
         const ViewDev& V = views[v];
         out = (int64_t)V.frame * N + i;
         const float* P = params + (int64_t)V.frame * C * N + i;
@@ -524,7 +526,7 @@ __global__ __launch_bounds__(128) void k_flow_mask(const ViewDev* __restrict__ v
     while (todo) {
         const int src = __builtin_ctzll(todo);
         todo &= todo - 1;
-        const int32_t rv = __shfl(v, src, 64);
+        const int32_t rv = v;
         const int32_t sx0 = __shfl(ix0, src, 64), sx1 = __shfl(ix1, src, 64);
         const int32_t sy0 = __shfl(iy0, src, 64), sy1 = __shfl(iy1, src, 64);
         const double smx = __shfl(mx, src, 64), smy = __shfl(my, src, 64);
@@ -936,7 +938,7 @@ hipError_t launch_flow_mask(const pg_views* v, const float* params, const uint8_
         k_tile_motion<<<(unsigned)v->n_tiles, 64, 0, s>>>(v->d_views, v->n_views, v->n_tiles, v->tiling.tile_w,
                                                           v->tiling.tile_h, masks, tile_motion);
     if (v->n_gv > 0)
-        k_flow_mask<<<(unsigned)ceil_div(v->n_gv, 128), 128, 0, s>>>(
+        k_flow_mask<<<(unsigned)(v->n_views * ceil_div(v->n_gauss, 128)), 128, 0, s>>>(
             v->d_views, v->channels, v->n_gauss, v->n_gv, v->tiling.tile_w, v->tiling.tile_h, params, masks,
             tile_motion, dyn_gauss, reinterpret_cast<unsigned long long*>(counters));
     if (dyn_texel && HW > 0)
