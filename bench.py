@@ -652,10 +652,13 @@ def stage_times(r, atlas, target, reps=5):
                                             s.n_inst, s.overflow, s.ws, s.ws_bytes, stream),
         "render_fwd": lambda: abi.pg_render_fwd(s.handle, s.splats, s.values, s.ranges, s.order, r.bg, r.image, r.final_T,
                                                 r.n_contrib, s.tile_entries, s.entries, None, stream),
-        "loss_l1": lambda: r.loss_l1(target),
-        "render_bwd": lambda: abi.pg_render_bwd(s.handle, s.splats, s.tiles, s.values, s.ranges, s.order, s.inst_first,
-                                                s.n_inst, s.cap, s.tile_entries, s.entries, r.n_contrib, r.bg,
-                                                r.final_T, r.dL_dimage, s.inst_grad, stream),
+        # the step's L1 path: the cotangent and the tiles' |image - target| sums inside the
+        # compositing adjoint, then the loss value from those sums
+        "render_bwd": lambda: abi.pg_render_bwd_l1(s.handle, s.splats, s.tiles, s.values, s.ranges, s.order,
+                                                   s.inst_first, s.n_inst, s.cap, s.tile_entries, s.entries,
+                                                   r.n_contrib, r.bg, r.final_T, r.image, target, 3 * r.n_pixels,
+                                                   r.tile_loss, s.inst_grad, stream),
+        "loss_l1": lambda: abi.pg_loss_l1_tiles(r.tile_loss, s.info.n_tiles, 3 * r.n_pixels, r.loss, stream),
         "project_bwd": lambda: abi.pg_project_bwd(s.handle, r.params, s.bins, s.inst_first, s.n_inst,
                                                   s.cap, s.inst_grad, r.gauss_texel, r.dynamic, r.H, r.W, s.grad2d,
                                                   r.dL_datlas, 0, stream),

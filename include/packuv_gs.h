@@ -424,6 +424,31 @@ pg_status pg_render_bwd(const pg_views* views, const pg_splat* splats, const pg_
                         const int32_t* n_contrib, const float* bg, const float* final_T, const float* dL_dimage,
                         float* inst_grad, void* stream);
 
+/* a4' and a5 first half together, for the L1 objective of Sec. 4.2
+ * "Objective" (lambda_ssim = 0): pg_render_bwd with its cotangent formed per
+ * pixel from image and target as sign(image - target) / n, the expression of
+ * pg_loss_l1 (so the slots equal those of pg_loss_l1 + pg_render_bwd bit for
+ * bit), and each tile's sum of |image - target| (FP64, fixed order) written
+ * to tile_loss[tile]; pg_loss_l1_tiles then forms the loss value.  This
+ * spares the cotangent's write and read and the L1 pass over the images.
+ *   image, target  device float [3 n_pixels] (per view planar [3][H][W])
+ *   n              the number of image floats in the whole objective (3
+ *                  n_pixels of the table, or more when several tables share
+ *                  one loss); the cotangent is 1 / n per float
+ *   tile_loss      device double [n_tiles] out (every tile written)
+ * The other arguments are those of pg_render_bwd. */
+pg_status pg_render_bwd_l1(const pg_views* views, const pg_splat* splats, const pg_tile_set* tiles,
+                           const int32_t* values, const int32_t* tile_ranges, const int32_t* tile_order,
+                           const int32_t* inst_first, const int64_t* n_inst_dev, int64_t inst_capacity,
+                           const int32_t* tile_entries, const uint32_t* entries, const int32_t* n_contrib,
+                           const float* bg, const float* final_T, const float* image, const float* target, int64_t n,
+                           double* tile_loss, float* inst_grad, void* stream);
+
+/* L = sum(tile_loss[0 .. n_tiles)) / n (FP64, fixed order) into loss_dev
+ * (device float [1]): the L1 loss value after pg_render_bwd_l1 (one call
+ * for tables whose tile sums lie side by side in tile_loss). */
+pg_status pg_loss_l1_tiles(const double* tile_loss, int64_t n_tiles, int64_t n, float* loss_dev, void* stream);
+
 /* a5, second half -- Adjoint of the projection (a2) and the fetch (a1)
  * back to the texels, with gradient freezing grad <- D_i grad (Sec. 4.2
  * "Gradient Freezing").  Adds each record's instance slots in rectangle

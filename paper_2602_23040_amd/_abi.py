@@ -79,6 +79,9 @@ SIGNATURES = {
     "pg_bin_sort": (_i32, [_p, _p, _p, _i64, _p, _p, _p, _p, _p, _p, _p, _p, _sz, _p]),
     "pg_render_fwd": (_i32, [_p, _p, _p, _p, _p, _p, _p, _p, _p, _p, _p, _p, _p]),
     "pg_render_bwd": (_i32, [_p, _p, _p, _p, _p, _p, _p, _p, _i64, _p, _p, _p, _p, _p, _p, _p, _p]),
+    "pg_render_bwd_l1": (_i32, [_p, _p, _p, _p, _p, _p, _p, _p, _i64, _p, _p, _p, _p, _p, _p, _p, _i64, _p, _p,
+                                _p]),
+    "pg_loss_l1_tiles": (_i32, [_p, _i64, _i64, _p, _p]),
     "pg_project_bwd": (_i32, [_p, _p, _p, _p, _p, _i64, _p, _p, _p, _i32, _i32, _p, _p, _i32, _p]),
     "pg_backward": (_i32, [_p, _p, _p, _p, _p, _p, _p, _p, _p, _p, _i64, _p, _p, _p, _p, _p, _p, _p, _p, _p, _i32,
                            _i32, _p, _p, _i32, _p]),
@@ -273,6 +276,22 @@ def pg_render_bwd(views, splats, tiles, values, tile_ranges, tile_order, inst_fi
                                _ptr(n_inst_dev), int(inst_capacity), _ptr(tile_entries), _ptr(entries),
                                _ptr(n_contrib), C.addressof(bgv), _ptr(final_T), _ptr(dL_dimage), _ptr(inst_grad),
                                _stream(stream)), "pg_render_bwd")
+
+
+def pg_render_bwd_l1(views, splats, tiles, values, tile_ranges, tile_order, inst_first, n_inst_dev, inst_capacity,
+                     tile_entries, entries, n_contrib, bg, final_T, image, target, n, tile_loss, inst_grad,
+                     stream=None):
+    bgv = (C.c_float * 3)(*[float(b) for b in bg])
+    _check(lib().pg_render_bwd_l1(views, _ptr(splats), _ptr(tiles), _ptr(values), _ptr(tile_ranges),
+                                  _ptr(tile_order), _ptr(inst_first), _ptr(n_inst_dev), int(inst_capacity),
+                                  _ptr(tile_entries), _ptr(entries), _ptr(n_contrib), C.addressof(bgv),
+                                  _ptr(final_T), _ptr(image), _ptr(target), int(n), _ptr(tile_loss),
+                                  _ptr(inst_grad), _stream(stream)), "pg_render_bwd_l1")
+
+
+def pg_loss_l1_tiles(tile_loss, n_tiles, n, loss_dev, stream=None):
+    _check(lib().pg_loss_l1_tiles(_ptr(tile_loss), int(n_tiles), int(n), _ptr(loss_dev), _stream(stream)),
+           "pg_loss_l1_tiles")
 
 
 def pg_project_bwd(views, params, bins, inst_first, n_inst_dev, inst_capacity, inst_grad, gauss_texel, dynamic_mask,

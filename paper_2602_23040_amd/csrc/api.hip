@@ -365,9 +365,39 @@ pg_status pg_render_bwd(const pg_views* v, const pg_splat* splats, const pg_tile
         return invalid("null pointer argument");
     if (inst_capacity < 0 || inst_capacity > INT32_MAX) return invalid("inst_capacity must be in [0, 2^31 - 1]");
     PG_CHECK_HIP(launch_render_bwd(v, splats, tiles, values, tile_ranges, tile_order, inst_first, tile_entries, entries,
-                                   n_contrib, bg, final_T, dL_dimage, n_inst_dev, inst_capacity, inst_grad,
+                                   n_contrib, bg, final_T, dL_dimage, n_inst_dev, inst_capacity, inst_grad, nullptr,
                                    (hipStream_t)stream),
                  "pg_render_bwd");
+    return PG_OK;
+}
+
+pg_status pg_render_bwd_l1(const pg_views* v, const pg_splat* splats, const pg_tile_set* tiles,
+                           const int32_t* values, const int32_t* tile_ranges, const int32_t* tile_order,
+                           const int32_t* inst_first, const int64_t* n_inst_dev, int64_t inst_capacity,
+                           const int32_t* tile_entries, const uint32_t* entries, const int32_t* n_contrib,
+                           const float* bg, const float* final_T, const float* image, const float* target, int64_t n,
+                           double* tile_loss, float* inst_grad, void* stream) {
+    g_error.clear();
+    if (!v || !bg) return invalid("null argument");
+    if (!tile_ranges || !tile_entries || !n_contrib || !final_T || !image || !target || !tile_loss || !n_inst_dev)
+        return invalid("null pointer argument");
+    if (v->n_gv > 0 && (!splats || !tiles || !values || !inst_first || !entries || !inst_grad))
+        return invalid("null pointer argument");
+    if (inst_capacity < 0 || inst_capacity > INT32_MAX) return invalid("inst_capacity must be in [0, 2^31 - 1]");
+    if (n < 3 * v->n_pixels) return invalid("n must count at least this table's 3 n_pixels floats");
+    const BwdL1 l1{image, target, n, tile_loss};
+    PG_CHECK_HIP(launch_render_bwd(v, splats, tiles, values, tile_ranges, tile_order, inst_first, tile_entries, entries,
+                                   n_contrib, bg, final_T, nullptr, n_inst_dev, inst_capacity, inst_grad, &l1,
+                                   (hipStream_t)stream),
+                 "pg_render_bwd_l1");
+    return PG_OK;
+}
+
+pg_status pg_loss_l1_tiles(const double* tile_loss, int64_t n_tiles, int64_t n, float* loss_dev, void* stream) {
+    g_error.clear();
+    if (!tile_loss || !loss_dev) return invalid("null pointer argument");
+    if (n_tiles < 0 || n < 1) return invalid("need n_tiles >= 0 and n >= 1");
+    PG_CHECK_HIP(launch_loss_l1_tiles(tile_loss, n_tiles, n, loss_dev, (hipStream_t)stream), "pg_loss_l1_tiles");
     return PG_OK;
 }
 
@@ -409,7 +439,7 @@ pg_status pg_backward(const pg_views* v, const float* params, const pg_splat* sp
     if (accumulate != 0 && accumulate != 1) return invalid("accumulate must be 0 or 1");
     hipStream_t s = (hipStream_t)stream;
     PG_CHECK_HIP(launch_render_bwd(v, splats, tiles, values, tile_ranges, tile_order, inst_first, tile_entries, entries,
-                                   n_contrib, bg, final_T, dL_dimage, n_inst_dev, inst_capacity, inst_grad, s),
+                                   n_contrib, bg, final_T, dL_dimage, n_inst_dev, inst_capacity, inst_grad, nullptr, s),
                  "pg_backward (compositing adjoint)");
     PG_CHECK_HIP(launch_slot_sum(v, bins, inst_first, n_inst_dev, inst_capacity, inst_grad, grad2d, s),
                  "pg_backward (slot sums)");

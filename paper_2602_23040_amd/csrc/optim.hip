@@ -71,6 +71,23 @@ __global__ __launch_bounds__(kLossBlocks) void k_l1_final(const double* __restri
     if (threadIdx.x == 0) *loss = (float)(s[0] / (double)n);
 }
 
+// The loss value from the compositing adjoint's per-tile sums of |image -
+// target| (the L1 term formed inside the adjoint): thread t adds tiles t,
+// t + 1024, ... in order, then a fixed tree, so the value is deterministic.
+__global__ __launch_bounds__(kLossBlocks) void k_l1_tiles(const double* __restrict__ tile_loss, int64_t n_tiles,
+                                                          int64_t n, float* __restrict__ loss) {
+    __shared__ double s[kLossBlocks];
+    double a = 0.0;
+    for (int64_t t = threadIdx.x; t < n_tiles; t += kLossBlocks) a += tile_loss[t];
+    s[threadIdx.x] = a;
+    __syncthreads();
+    for (int o = kLossBlocks / 2; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) s[threadIdx.x] += s[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *loss = (float)(s[0] / (double)n);
+}
+
 // One Adam update of element (p, g, m, v); the same expression for every
 // element and both launch shapes below.
 __device__ __forceinline__ void adam_elem(float& p, float g, float& m, float& v, float lr, float b1, float b2,
@@ -174,6 +191,11 @@ hipError_t launch_loss_l1(const float* img, const float* tgt, int64_t n, float* 
     if (vec) k_l1<true><<<kLossBlocks, 256, 0, s>>>(img, tgt, n, g, partial);
     else k_l1<false><<<kLossBlocks, 256, 0, s>>>(img, tgt, n, g, partial);
     k_l1_final<<<1, kLossBlocks, 0, s>>>(partial, n, loss);
+    return hipGetLastError();
+}
+
+hipError_t launch_loss_l1_tiles(const double* tile_loss, int64_t n_tiles, int64_t n, float* loss, hipStream_t s) {
+    k_l1_tiles<<<1, kLossBlocks, 0, s>>>(tile_loss, n_tiles, n, loss);
     return hipGetLastError();
 }
 

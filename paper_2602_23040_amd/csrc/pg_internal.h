@@ -131,16 +131,28 @@ hipError_t launch_render_fwd(const pg_views* v, const pg_splat* splats, const in
                              const int32_t* ranges, const int32_t* order, const float bg[3], float* image,
                              float* final_T, int32_t* n_contrib, int32_t* tile_entries, uint32_t* entries,
                              uint64_t* counters, hipStream_t s);
+// The L1 term formed inside the compositing adjoint: its cotangent from image
+// and target (n floats in the whole objective), and the tiles' sums of
+// |image - target| in tile_loss.
+struct BwdL1 {
+    const float* image;
+    const float* target;
+    int64_t n;
+    double* tile_loss;
+};
+// dL_dimage is read when l1 is null; otherwise the cotangent is the L1 term's.
 hipError_t launch_render_bwd(const pg_views* v, const pg_splat* splats, const pg_tile_set* tiles, const int32_t* values,
                              const int32_t* ranges, const int32_t* order, const int32_t* inst_first,
                              const int32_t* tile_entries, const uint32_t* entries, const int32_t* n_contrib,
                              const float bg[3], const float* final_T, const float* dL_dimage,
-                             const int64_t* n_inst_dev, int64_t cap, float* inst_grad, hipStream_t s);
+                             const int64_t* n_inst_dev, int64_t cap, float* inst_grad, const BwdL1* l1,
+                             hipStream_t s);
 hipError_t fill_u32_dev(void* p, uint32_t value, const int64_t* n_dev, int64_t n_max, int64_t mul, hipStream_t s);
 
 // optim.hip
 hipError_t launch_loss_l1(const float* img, const float* tgt, int64_t n, float* g, double* partial, float* loss,
                           hipStream_t s);
+hipError_t launch_loss_l1_tiles(const double* tile_loss, int64_t n_tiles, int64_t n, float* loss, hipStream_t s);
 hipError_t launch_adam(float* atlas, const float* grad, float* m, float* v, const uint8_t* visible,
                        const int32_t* texel_gauss, int64_t n_gauss, int32_t F, int32_t C, int32_t H, int32_t W,
                        float lr, float b1, float b2, float eps, int32_t step, int32_t* step_dev, hipStream_t s);

@@ -396,7 +396,12 @@ __device__ __forceinline__ void pair_offsets(int lane, int& offA, int& offB) {
     offB = p == 2 ? 4 * r : (p == 3 ? 4 * (4 + r) : (lane == 20 ? 32 : (lane == 24 ? tag : none)));
 }
 
-template <int TW, int TH, int BATCH>
+// L1: the cotangent is the L1 term's, sign(image - target) / n per channel
+// (the expression of the L1 loss kernel, so bitwise its values), formed from
+// image and target as the tile starts; the tile's sum of |image - target|
+// (FP32 inside each row of 16 lanes, the four rows in FP64; a fixed order)
+// goes to tile_loss[tile] for the loss value.
+template <int TW, int TH, int BATCH, bool L1>
 __global__ __launch_bounds__(kLanes) void k_render_bwd(const ViewDev* __restrict__ views, int nv, int64_t n_tiles,
                                                        const pg_splat* __restrict__ splats,
                                                        const pg_tile_set* __restrict__ tiles,
@@ -410,23 +415,21 @@ __global__ __launch_bounds__(kLanes) void k_render_bwd(const ViewDev* __restrict
                                                        float bg1, float bg2, const float* __restrict__ final_T,
                                                        const float* __restrict__ dL_dimage,
                                                        const int64_t* __restrict__ n_inst_dev, int64_t cap,
-                                                       float* __restrict__ inst_grad) {
+                                                       float* __restrict__ inst_grad, const float* __restrict__ image,
+                                                       const float* __restrict__ target, float inv_n,
+                                                       double* __restrict__ tile_loss) {
     // aux[0]: gradient slot of the (Gaussian, this tile) instance (-1: none);
     // aux[1]: entry word, list position << 4 | blocks that composited it
     __shared__ Staged s_st[BATCH];
     TileGeo t;
     if (!tile_geo<TW, TH>(views, nv, n_tiles, order, t)) return;
-    const int2 rg = ranges[t.tile];
-    const int32_t count = tile_entries[t.tile];
-    const int64_t n_inst = *n_inst_dev;
-    if (count == 0 || n_inst > cap) return;       // nothing composited here, or the sort overflowed
-    const uint32_t gen = (uint32_t)n_inst_dev[1];  // this sort's generation: tags the slots written here
     const int64_t HW = (int64_t)t.W * t.H;
     // Per pixel: T, the colour cotangent G, and S = G . B, where B is the colour
     // composited behind the current Gaussian (background first); with
     // B <- alpha c + (1 - alpha) B, S follows S <- S + alpha (G . c - S).
     float T[kPPT], G0[kPPT], G1[kPPT], G2[kPPT], S[kPPT];
     int32_t nc[kPPT];      // list positions below nc[j] were reached by pixel j (0 outside the image)
+    float lsum = 0.0f;     // L1: this lane's sum of |image - target|
 #pragma unroll
     for (int j = 0; j < kPPT; j++) {
         T[j] = 1.0f;
@@ -434,15 +437,48 @@ __global__ __launch_bounds__(kLanes) void k_render_bwd(const ViewDev* __restrict
         G0[j] = G1[j] = G2[j] = 0.0f;
         if (t.inside[j]) {
             const int64_t p = (int64_t)t.py[j] * t.W + t.px[j];
-            const float* gi = dL_dimage + 3 * t.vbase + p;
-            G0[j] = gi[0];
-            G1[j] = gi[HW];
-            G2[j] = gi[2 * HW];
+            const int64_t o = 3 * t.vbase + p;
+            if (L1) {
+                float gc[3];
+#pragma unroll
+                for (int ch = 0; ch < 3; ch++) {
+                    const float d = image[o + ch * HW] - target[o + ch * HW];
+                    lsum += fabsf(d);
+                    gc[ch] = d > 0.0f ? inv_n : (d < 0.0f ? -inv_n : 0.0f);
+                }
+                G0[j] = gc[0];
+                G1[j] = gc[1];
+                G2[j] = gc[2];
+            } else {
+                G0[j] = dL_dimage[o];
+                G1[j] = dL_dimage[o + HW];
+                G2[j] = dL_dimage[o + 2 * HW];
+            }
             T[j] = final_T[t.vbase + p];
             nc[j] = n_contrib[t.vbase + p];
         }
-        S[j] = fmaf(G2[j], bg2, fmaf(G1[j], bg1, G0[j] * bg0));
     }
+    if (L1) {
+        // the tile's sum: DPP sums inside each row of 16 lanes, then the four row
+        // totals added in FP64 in a fixed order
+        float x = lsum;
+        x += dpp<0xB1>(x);     // quad_perm [1,0,3,2]
+        x += dpp<0x4E>(x);     // quad_perm [2,3,0,1]
+        x += dpp<0x124>(x);    // row_ror:4
+        x += dpp<0x128>(x);    // row_ror:8
+        auto row = [&](int l) {
+            return (double)__int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), l));
+        };
+        const double tot = (row(0) + row(16)) + (row(32) + row(48));
+        if (threadIdx.x == 0) tile_loss[t.tile] = tot;
+    }
+    const int2 rg = ranges[t.tile];
+    const int32_t count = tile_entries[t.tile];
+    const int64_t n_inst = *n_inst_dev;
+    if (count == 0 || n_inst > cap) return;       // nothing composited here, or the sort overflowed
+    const uint32_t gen = (uint32_t)n_inst_dev[1];  // this sort's generation: tags the slots written here
+#pragma unroll
+    for (int j = 0; j < kPPT; j++) S[j] = fmaf(G2[j], bg2, fmaf(G1[j], bg1, G0[j] * bg0));
     const int lane = threadIdx.x;
     int offA, offB;
     pair_offsets(lane, offA, offB);
@@ -602,10 +638,18 @@ void bwd_launch(const pg_views* v, const pg_splat* splats, const pg_tile_set* ti
                 const int32_t* values,
                 const int32_t* ranges, const int32_t* order, const int32_t* inst_first, const int32_t* tile_entries,
                 const uint32_t* entries, const int32_t* n_contrib, const float bg[3], const float* final_T,
-                const float* dL_dimage, const int64_t* n_inst_dev, int64_t cap, float* inst_grad, hipStream_t s) {
-    k_render_bwd<TW, TH, BATCH><<<(unsigned)v->n_tiles, kLanes, 0, s>>>(
-        v->d_views, v->n_views, v->n_tiles, splats, tiles, values, reinterpret_cast<const int2*>(ranges), order,
-        inst_first, tile_entries, entries, n_contrib, bg[0], bg[1], bg[2], final_T, dL_dimage, n_inst_dev, cap, inst_grad);
+                const float* dL_dimage, const int64_t* n_inst_dev, int64_t cap, float* inst_grad, const BwdL1* l1,
+                hipStream_t s) {
+    if (l1)
+        k_render_bwd<TW, TH, BATCH, true><<<(unsigned)v->n_tiles, kLanes, 0, s>>>(
+            v->d_views, v->n_views, v->n_tiles, splats, tiles, values, reinterpret_cast<const int2*>(ranges), order,
+            inst_first, tile_entries, entries, n_contrib, bg[0], bg[1], bg[2], final_T, nullptr, n_inst_dev, cap,
+            inst_grad, l1->image, l1->target, (float)(1.0 / (double)l1->n), l1->tile_loss);
+    else
+        k_render_bwd<TW, TH, BATCH, false><<<(unsigned)v->n_tiles, kLanes, 0, s>>>(
+            v->d_views, v->n_views, v->n_tiles, splats, tiles, values, reinterpret_cast<const int2*>(ranges), order,
+            inst_first, tile_entries, entries, n_contrib, bg[0], bg[1], bg[2], final_T, dL_dimage, n_inst_dev, cap,
+            inst_grad, nullptr, nullptr, 0.0f, nullptr);
 }
 
 template <template <int, int, int> class F, typename... A>
@@ -647,10 +691,11 @@ hipError_t launch_render_bwd(const pg_views* v, const pg_splat* splats, const pg
                              const int32_t* ranges, const int32_t* order, const int32_t* inst_first,
                              const int32_t* tile_entries, const uint32_t* entries, const int32_t* n_contrib,
                              const float bg[3], const float* final_T, const float* dL_dimage,
-                             const int64_t* n_inst_dev, int64_t cap, float* inst_grad, hipStream_t s) {
+                             const int64_t* n_inst_dev, int64_t cap, float* inst_grad, const BwdL1* l1,
+                             hipStream_t s) {
     if (v->n_tiles == 0) return hipSuccess;
     dispatch<BwdRun>(v->tiling, v, splats, tiles, values, ranges, order, inst_first, tile_entries, entries, n_contrib, bg,
-                     final_T, dL_dimage, n_inst_dev, cap, inst_grad, s);
+                     final_T, dL_dimage, n_inst_dev, cap, inst_grad, l1, s);
     return hipGetLastError();
 }
 

@@ -150,6 +150,12 @@ class Renderer:
                 pb.append(pb[-1] + c.width * c.height)
             self.pix_base = pb
         self.n_pixels = self.pix_base[-1]
+        # per-tile sums of |image - target| of the fused L1 adjoint, the view sets' tiles side by side
+        self.tile_off = [0]
+        for s in self.sets:
+            self.tile_off.append(self.tile_off[-1] + s.info.n_tiles)
+        self.tile_loss = torch.empty(max(self.tile_off[-1], 1), dtype=torch.float64, device=dev)
+        self.fuse_l1 = True          # step(): the L1 term inside the compositing adjoint
         self.image = torch.empty(3 * self.n_pixels, dtype=torch.float32, device=dev)
         self.final_T = torch.empty(self.n_pixels, dtype=torch.float32, device=dev)
         self.n_contrib = torch.empty(self.n_pixels, dtype=torch.int32, device=dev)
@@ -367,6 +373,36 @@ class Renderer:
                                    self.dL_datlas, 1)
         return self.dL_datlas
 
+    def backward_l1(self, target: torch.Tensor) -> torch.Tensor:
+        """The L1 loss and its texel gradients in one pass: the compositing adjoint
+        forms the L1 cotangent from the image and target itself (pg_render_bwd_l1)
+        and the loss value comes from its per-tile sums.  dL/datlas equals that of
+        loss_l1() + backward() bit for bit; self.dL_dimage is not written."""
+        assert target.is_contiguous() and target.numel() == 3 * self.n_pixels
+        n = 3 * self.n_pixels
+        if self.batched:
+            s = self.sets[0]
+            abi.pg_render_bwd_l1(s.handle, s.splats, s.tiles, s.values, s.ranges, self._order(s), s.inst_first,
+                                 s.n_inst, s.cap, s.tile_entries, s.entries, self.n_contrib, self.bg, self.final_T,
+                                 self.image, target, n, self.tile_loss, s.inst_grad)
+            abi.pg_loss_l1_tiles(self.tile_loss, s.info.n_tiles, n, self.loss)
+            abi.pg_project_bwd(s.handle, self.params, s.bins, s.inst_first, s.n_inst, s.cap, s.inst_grad,
+                               self.gauss_texel, self.dynamic, self.H, self.W, s.grad2d, self.dL_datlas, 0)
+        else:
+            self.dL_datlas.zero_()
+            for k, s in enumerate(self.sets):
+                po = self.pix_base[k]
+                abi.pg_render_bwd_l1(s.handle, s.splats, s.tiles, s.values, s.ranges, self._order(s), s.inst_first,
+                                     s.n_inst, s.cap, s.tile_entries, s.entries, self._off(self.n_contrib, po),
+                                     self.bg, self._off(self.final_T, po), self._off(self.image, 3 * po),
+                                     self._off(target, 3 * po), n, self._off(self.tile_loss, self.tile_off[k]),
+                                     s.inst_grad)
+                abi.pg_project_bwd(s.handle, self.params, s.bins, s.inst_first, s.n_inst, s.cap,
+                                   s.inst_grad, self.gauss_texel, self.dynamic, self.H, self.W, s.grad2d,
+                                   self.dL_datlas, 1)
+            abi.pg_loss_l1_tiles(self.tile_loss, self.tile_off[-1], n, self.loss)
+        return self.loss
+
     def adam_step(self, atlas: torch.Tensor, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
         """Sparse Adam on `atlas` in place; the step count lives on the device, so
         replays of a captured step keep counting."""
@@ -382,11 +418,14 @@ class Renderer:
         lambda_ssim is given), adjoint, the regularisers when reg (a dict of
         regularisers() arguments) is given, and Adam."""
         self.forward(atlas)
-        if lambda_ssim is None:
-            self.loss_l1(target)
+        if lambda_ssim is None and self.fuse_l1:
+            self.backward_l1(target)
         else:
-            self.loss_photo(target, lambda_ssim)
-        self.backward()
+            if lambda_ssim is None:
+                self.loss_l1(target)
+            else:
+                self.loss_photo(target, lambda_ssim)
+            self.backward()
         if reg is not None:
             self.regularisers(**reg)
         if adam:
