@@ -260,7 +260,9 @@ __global__ __launch_bounds__(kLanes) __attribute__((amdgpu_waves_per_eu(8, 8))) 
         for (int32_t k0 = 0; k0 < cnt && alive != 0; k0 += kLanes) {
             const int32_t k1 = min(cnt, k0 + kLanes);
             uint64_t took[kPPT] = {0, 0, 0, 0};
-            for (int32_t k = k0; k < k1; k++) {
+            // one Gaussian of the sub-batch (two per loop iteration: the loop and
+            // liveness bookkeeping is shared)
+            auto gauss = [&](const int32_t k) __attribute__((always_inline)) {
                 const float4 g = s_st[k].geo;
                 const float4 cc = s_st[k].col;
                 const float cb = s_st[k].blu;
@@ -299,7 +301,14 @@ __global__ __launch_bounds__(kLanes) __attribute__((amdgpu_waves_per_eu(8, 8))) 
                     C2[j] = fmaf(w, cb, C2[j]);
                     T[j] = take ? Tn : T[j];
                 }
+            };
+            for (int32_t k = k0; k < k1; k += 2) {
+                gauss(k);
                 if (alive == 0) break;   // every pixel has terminated
+                if (k + 1 < k1) {
+                    gauss(k + 1);
+                    if (alive == 0) break;
+                }
             }
             // entries of the sub-batch for the adjoint (lane i: Gaussian k0 + i), stored in list order
             uint32_t bits = 0;
