@@ -439,33 +439,32 @@ __global__ __launch_bounds__(kLanes) void k_render_bwd(const ViewDev* __restrict
     float T[kPPT], G0[kPPT], G1[kPPT], G2[kPPT], S[kPPT];
     int32_t nc[kPPT];      // list positions below nc[j] were reached by pixel j (0 outside the image)
     float lsum = 0.0f;     // L1: this lane's sum of |image - target|
+    // Every pixel's loads are issued unconditionally (pixels outside the image read
+    // the nearest pixel inside, and their values are then replaced), so the four
+    // pixels' loads are in flight together instead of one pixel after another.
 #pragma unroll
     for (int j = 0; j < kPPT; j++) {
-        T[j] = 1.0f;
-        nc[j] = 0;
-        G0[j] = G1[j] = G2[j] = 0.0f;
-        if (t.inside[j]) {
-            const int64_t p = (int64_t)t.py[j] * t.W + t.px[j];
-            const int64_t o = 3 * t.vbase + p;
-            if (L1) {
-                float gc[3];
+        const int64_t p = (int64_t)min(t.py[j], t.H - 1) * t.W + min(t.px[j], t.W - 1);
+        const int64_t o = 3 * t.vbase + p;
+        const bool in = t.inside[j];
+        float gc[3];
 #pragma unroll
-                for (int ch = 0; ch < 3; ch++) {
-                    const float d = image[o + ch * HW] - target[o + ch * HW];
-                    lsum += fabsf(d);
-                    gc[ch] = d > 0.0f ? inv_n : (d < 0.0f ? -inv_n : 0.0f);
-                }
-                G0[j] = gc[0];
-                G1[j] = gc[1];
-                G2[j] = gc[2];
+        for (int ch = 0; ch < 3; ch++) {
+            if (L1) {
+                const float d = image[o + ch * HW] - target[o + ch * HW];
+                lsum += in ? fabsf(d) : 0.0f;
+                gc[ch] = d > 0.0f ? inv_n : (d < 0.0f ? -inv_n : 0.0f);
             } else {
-                G0[j] = dL_dimage[o];
-                G1[j] = dL_dimage[o + HW];
-                G2[j] = dL_dimage[o + 2 * HW];
+                gc[ch] = dL_dimage[o + ch * HW];
             }
-            T[j] = final_T[t.vbase + p];
-            nc[j] = n_contrib[t.vbase + p];
         }
+        const float Tp = final_T[t.vbase + p];
+        const int32_t np = n_contrib[t.vbase + p];
+        G0[j] = in ? gc[0] : 0.0f;
+        G1[j] = in ? gc[1] : 0.0f;
+        G2[j] = in ? gc[2] : 0.0f;
+        T[j] = in ? Tp : 1.0f;
+        nc[j] = in ? np : 0;
     }
     if (L1) {
         // the tile's sum: DPP sums inside each row of 16 lanes, then the four row
