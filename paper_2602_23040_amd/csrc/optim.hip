@@ -78,6 +78,8 @@ __global__ __launch_bounds__(kLossBlocks) void k_l1_tiles(const double* __restri
                                                           int64_t n, float* __restrict__ loss) {
     __shared__ double s[kLossBlocks];
     double a = 0.0;
+    // unrolled so that eight loads are in flight; the additions keep their order
+#pragma unroll 8
     for (int64_t t = threadIdx.x; t < n_tiles; t += kLossBlocks) a += tile_loss[t];
     s[threadIdx.x] = a;
     __syncthreads();

@@ -890,8 +890,11 @@ __global__ __launch_bounds__(kSumRecs) void k_slot_sum(const pg_bin* __restrict_
     int32_t nt = 0;
     int64_t first = 0;
     if (gv <= glast && sorted_ok) {
-        nt = bins[gv].n_tiles;
+        // the record's kept tiles from the slot offsets (an exclusive scan of them over
+        // every record), so the 16-byte bins need not be read
         first = inst_first[gv];
+        const int64_t next = gv + 1 < n_gv ? (int64_t)inst_first[gv + 1] : *n_inst_dev;
+        nt = (int32_t)(next - first);
     }
     if (gv == g0) s_range[0] = first;
     if (gv == glast) s_range[1] = first + nt;
