@@ -1,5 +1,6 @@
 // a4 -- front-to-back compositing per screen tile, and (a5, first half) its
-// adjoint per pixel.
+// adjoint per pixel; the adjoint takes the image cotangent as given, or forms
+// the L1 term's (Sec. 4.2 "Objective") from image and target itself.
 //
 // Compositing follows C = sum_i T_i alpha_i c_i with T_i = prod_{j<i}
 // (1 - alpha_j) (supplementary, viewer section), restricted to the 3-sigma
