@@ -659,7 +659,7 @@ def stage_times(r, atlas, target, reps=5):
                                                    r.n_contrib, r.bg, r.final_T, r.image, target, 3 * r.n_pixels,
                                                    r.tile_loss, s.inst_grad, stream),
         "loss_l1": lambda: abi.pg_loss_l1_tiles(r.tile_loss, s.info.n_tiles, 3 * r.n_pixels, r.loss, stream),
-        "project_bwd": lambda: abi.pg_project_bwd(s.handle, r.params, s.bins, s.inst_first, s.n_inst,
+        "project_bwd": lambda: abi.pg_project_bwd(s.handle, r.params, s.splats, s.bins, s.inst_first, s.n_inst,
                                                   s.cap, s.inst_grad, r.gauss_texel, r.dynamic, r.H, r.W, s.grad2d,
                                                   r.dL_datlas, 0, stream),
     }

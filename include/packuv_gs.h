@@ -455,6 +455,9 @@ pg_status pg_loss_l1_tiles(const double* tile_loss, int64_t n_tiles, int64_t n, 
  * order (a fixed order, so the result is bitwise deterministic), then
  * applies the chain rule through the EWA projection, the activations and
  * the SH colour of every view of the Gaussian's frame.
+ *   splats       from pg_project: the SH adjoint takes a colour channel's clamp
+ *                decision (colour = max(0, 0.5 + sum Y k)) from the forward's
+ *                stored colour where its own FP32 sum lies within 1e-3 of 0
  *   bins, inst_first, n_inst_dev   from pg_project / pg_bin_sort;
  *                after an overflowed sort the texel gradient is zero
  *   inst_grad    device float [inst_capacity][10] from pg_render_bwd; a slot
@@ -467,7 +470,8 @@ pg_status pg_loss_l1_tiles(const double* tile_loss, int64_t n_tiles, int64_t n, 
  *   dL_datlas    device float [F][C][H][W] out; written (accumulate = 0: every
  *                texel, unoccupied = 0) or added to (accumulate = 1: occupied
  *                texels only). */
-pg_status pg_project_bwd(const pg_views* views, const float* params, const pg_bin* bins, const int32_t* inst_first,
+pg_status pg_project_bwd(const pg_views* views, const float* params, const pg_splat* splats, const pg_bin* bins,
+                         const int32_t* inst_first,
                          const int64_t* n_inst_dev, int64_t inst_capacity, const float* inst_grad, const int32_t* gauss_texel, const uint8_t* dynamic_mask, int32_t H,
                          int32_t W, float* grad2d, float* dL_datlas, int32_t accumulate, void* stream);
 

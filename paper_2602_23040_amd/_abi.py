@@ -82,7 +82,7 @@ SIGNATURES = {
     "pg_render_bwd_l1": (_i32, [_p, _p, _p, _p, _p, _p, _p, _p, _i64, _p, _p, _p, _p, _p, _p, _p, _i64, _p, _p,
                                 _p]),
     "pg_loss_l1_tiles": (_i32, [_p, _i64, _i64, _p, _p]),
-    "pg_project_bwd": (_i32, [_p, _p, _p, _p, _p, _i64, _p, _p, _p, _i32, _i32, _p, _p, _i32, _p]),
+    "pg_project_bwd": (_i32, [_p, _p, _p, _p, _p, _p, _i64, _p, _p, _p, _i32, _i32, _p, _p, _i32, _p]),
     "pg_backward": (_i32, [_p, _p, _p, _p, _p, _p, _p, _p, _p, _p, _i64, _p, _p, _p, _p, _p, _p, _p, _p, _p, _i32,
                            _i32, _p, _p, _i32, _p]),
     "pg_status_check": (_i32, [_p, _p, _p, _p]),
@@ -294,9 +294,9 @@ def pg_loss_l1_tiles(tile_loss, n_tiles, n, loss_dev, stream=None):
            "pg_loss_l1_tiles")
 
 
-def pg_project_bwd(views, params, bins, inst_first, n_inst_dev, inst_capacity, inst_grad, gauss_texel, dynamic_mask,
-                   H, W, grad2d, dL_datlas, accumulate, stream=None):
-    _check(lib().pg_project_bwd(views, _ptr(params), _ptr(bins), _ptr(inst_first), _ptr(n_inst_dev),
+def pg_project_bwd(views, params, splats, bins, inst_first, n_inst_dev, inst_capacity, inst_grad, gauss_texel,
+                   dynamic_mask, H, W, grad2d, dL_datlas, accumulate, stream=None):
+    _check(lib().pg_project_bwd(views, _ptr(params), _ptr(splats), _ptr(bins), _ptr(inst_first), _ptr(n_inst_dev),
                                 int(inst_capacity), _ptr(inst_grad), _ptr(gauss_texel),
                                 _ptr(dynamic_mask), int(H), int(W), _ptr(grad2d), _ptr(dL_datlas), int(accumulate),
                                 _stream(stream)), "pg_project_bwd")

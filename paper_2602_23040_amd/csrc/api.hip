@@ -401,13 +401,14 @@ pg_status pg_loss_l1_tiles(const double* tile_loss, int64_t n_tiles, int64_t n, 
     return PG_OK;
 }
 
-pg_status pg_project_bwd(const pg_views* v, const float* params, const pg_bin* bins, const int32_t* inst_first,
+pg_status pg_project_bwd(const pg_views* v, const float* params, const pg_splat* splats, const pg_bin* bins,
+                         const int32_t* inst_first,
                          const int64_t* n_inst_dev, int64_t inst_capacity, const float* inst_grad, const int32_t* gauss_texel, const uint8_t* dynamic_mask, int32_t H,
                          int32_t W, float* grad2d, float* dL_datlas, int32_t accumulate, void* stream) {
     g_error.clear();
     if (!v) return invalid("null argument");
     if (!dL_datlas || !n_inst_dev) return invalid("null pointer argument");
-    if (v->n_gv > 0 && (!params || !bins || !inst_first || !inst_grad || !gauss_texel || !grad2d))
+    if (v->n_gv > 0 && (!params || !splats || !bins || !inst_first || !inst_grad || !gauss_texel || !grad2d))
         return invalid("null pointer argument");
     if (H < 1 || W < 1 || (int64_t)H * W < v->n_gauss) return invalid("H * W must hold n_gauss texels");
     if (accumulate != 0 && accumulate != 1) return invalid("accumulate must be 0 or 1");
@@ -415,7 +416,8 @@ pg_status pg_project_bwd(const pg_views* v, const float* params, const pg_bin* b
     hipStream_t s = (hipStream_t)stream;
     PG_CHECK_HIP(launch_slot_sum(v, bins, inst_first, n_inst_dev, inst_capacity, inst_grad, grad2d, s),
                  "pg_project_bwd (slot sums)");
-    PG_CHECK_HIP(launch_project_bwd(v, params, grad2d, gauss_texel, dynamic_mask, H, W, dL_datlas, accumulate, s),
+    PG_CHECK_HIP(launch_project_bwd(v, params, splats, grad2d, gauss_texel, dynamic_mask, H, W, dL_datlas, accumulate,
+                                    s),
                  "pg_project_bwd");
     return PG_OK;
 }
@@ -443,7 +445,8 @@ pg_status pg_backward(const pg_views* v, const float* params, const pg_splat* sp
                  "pg_backward (compositing adjoint)");
     PG_CHECK_HIP(launch_slot_sum(v, bins, inst_first, n_inst_dev, inst_capacity, inst_grad, grad2d, s),
                  "pg_backward (slot sums)");
-    PG_CHECK_HIP(launch_project_bwd(v, params, grad2d, gauss_texel, dynamic_mask, H, W, dL_datlas, accumulate, s),
+    PG_CHECK_HIP(launch_project_bwd(v, params, splats, grad2d, gauss_texel, dynamic_mask, H, W, dL_datlas, accumulate,
+                                    s),
                  "pg_backward (projection adjoint)");
     return PG_OK;
 }

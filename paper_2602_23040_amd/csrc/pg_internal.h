@@ -110,7 +110,7 @@ hipError_t launch_flow_mask(const pg_views* v, const float* params, const uint8_
 hipError_t launch_slot_sum(const pg_views* v, const pg_bin* bins, const int32_t* inst_first,
                            const int64_t* n_inst_dev, int64_t cap, const float* inst_grad, float* grad2d,
                            hipStream_t s);
-hipError_t launch_project_bwd(const pg_views* v, const float* params, float* grad2d,
+hipError_t launch_project_bwd(const pg_views* v, const float* params, const pg_splat* splats, float* grad2d,
                               const int32_t* gauss_texel, const uint8_t* dyn, int32_t H, int32_t W,
                               float* dL_datlas, int32_t accumulate, hipStream_t s);
 

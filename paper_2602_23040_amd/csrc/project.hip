@@ -778,6 +778,7 @@ __global__ __launch_bounds__(128) void k_project_bwd_sh(const ViewDev* __restric
                                                         const int32_t* __restrict__ view_order, int32_t F,
                                                         int32_t C, int64_t N, int64_t n_gv,
                                                         const float* __restrict__ params,
+                                                        const pg_splat* __restrict__ splats,
                                                         const float* __restrict__ grad2d,
                                                         const int32_t* __restrict__ gauss_texel,
                                                         const uint8_t* __restrict__ dyn, int64_t HW,
@@ -820,7 +821,9 @@ __global__ __launch_bounds__(128) void k_project_bwd_sh(const ViewDev* __restric
         float Y[NB];
         sh_basis_f<L>(d[0], d[1], d[2], Y);
         // clamp decision: the FP32 colour sum settles it unless it lies within 1e-3 of the clamp;
-        // then the forward's own FP64 sum decides
+        // there the forward's own decision is read back from its colour (max(0, its FP64 sum),
+        // stored as float: 0 exactly when it clamped), instead of forming the FP64 sum again
+        // (whose sixteen doubles doubled this kernel's registers)
         float gc[3];
 #pragma unroll
         for (int ch = 0; ch < 3; ch++) {
@@ -828,14 +831,7 @@ __global__ __launch_bounds__(128) void k_project_bwd_sh(const ViewDev* __restric
 #pragma unroll
             for (int j = 0; j < NB; j++) raw = fmaf(Y[j], sh[3 * j + ch], raw);
             bool clamped = raw < 0.0f;
-            if (fabsf(raw) < 1e-3f) {
-                double Y64[NB];
-                sh_basis<L>(dd64[0], dd64[1], dd64[2], Y64);
-                double r64 = 0.0;
-#pragma unroll
-                for (int j = 0; j < NB; j++) r64 += Y64[j] * (double)sh[3 * j + ch];
-                clamped = r64 + 0.5 < 0.0;
-            }
+            if (fabsf(raw) < 1e-3f) clamped = !(splats[(int64_t)v * N + i].color[ch] > 0.0f);
             gc[ch] = clamped ? 0.0f : gcol[ch];   // clamped channel: no gradient
         }
         // SH coefficients: dL/dk[j][ch] = Y_j gc_ch; direction: sum_j (sum_ch k[j][ch] gc_ch) grad Y_j
@@ -977,7 +973,7 @@ hipError_t launch_slot_sum(const pg_views* v, const pg_bin* bins, const int32_t*
     return hipGetLastError();
 }
 
-hipError_t launch_project_bwd(const pg_views* v, const float* params, float* grad2d,
+hipError_t launch_project_bwd(const pg_views* v, const float* params, const pg_splat* splats, float* grad2d,
                               const int32_t* gauss_texel, const uint8_t* dyn, int32_t H, int32_t W,
                               float* dL_datlas, int32_t accumulate, hipStream_t s) {
     const int64_t HW = (int64_t)H * W;
@@ -993,7 +989,7 @@ hipError_t launch_project_bwd(const pg_views* v, const float* params, float* gra
                                            accumulate);
     auto args = [&](auto kern) {
         kern<<<grid, 128, 0, s>>>(v->d_views, v->d_frame_views, v->d_view_order, v->frames, v->channels, v->n_gauss,
-                                  v->n_gv, params, grad2d, gauss_texel, dyn, HW, dL_datlas, accumulate);
+                                  v->n_gv, params, splats, grad2d, gauss_texel, dyn, HW, dL_datlas, accumulate);
     };
     switch (v->sh_degree) {
         case 0: args(k_project_bwd_sh<0>); break;

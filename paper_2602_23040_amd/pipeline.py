@@ -368,7 +368,7 @@ class Renderer:
                 abi.pg_render_bwd(s.handle, s.splats, s.tiles, s.values, s.ranges, self._order(s), s.inst_first, s.n_inst, s.cap,
                                   s.tile_entries, s.entries, self._off(self.n_contrib, po), self.bg,
                                   self._off(self.final_T, po), self._off(g, 3 * po), s.inst_grad)
-                abi.pg_project_bwd(s.handle, self.params, s.bins, s.inst_first, s.n_inst, s.cap,
+                abi.pg_project_bwd(s.handle, self.params, s.splats, s.bins, s.inst_first, s.n_inst, s.cap,
                                    s.inst_grad, self.gauss_texel, self.dynamic, self.H, self.W, s.grad2d,
                                    self.dL_datlas, 1)
         return self.dL_datlas
@@ -386,7 +386,7 @@ class Renderer:
                                  s.n_inst, s.cap, s.tile_entries, s.entries, self.n_contrib, self.bg, self.final_T,
                                  self.image, target, n, self.tile_loss, s.inst_grad)
             abi.pg_loss_l1_tiles(self.tile_loss, s.info.n_tiles, n, self.loss)
-            abi.pg_project_bwd(s.handle, self.params, s.bins, s.inst_first, s.n_inst, s.cap, s.inst_grad,
+            abi.pg_project_bwd(s.handle, self.params, s.splats, s.bins, s.inst_first, s.n_inst, s.cap, s.inst_grad,
                                self.gauss_texel, self.dynamic, self.H, self.W, s.grad2d, self.dL_datlas, 0)
         else:
             self.dL_datlas.zero_()
@@ -397,7 +397,7 @@ class Renderer:
                                      self.bg, self._off(self.final_T, po), self._off(self.image, 3 * po),
                                      self._off(target, 3 * po), n, self._off(self.tile_loss, self.tile_off[k]),
                                      s.inst_grad)
-                abi.pg_project_bwd(s.handle, self.params, s.bins, s.inst_first, s.n_inst, s.cap,
+                abi.pg_project_bwd(s.handle, self.params, s.splats, s.bins, s.inst_first, s.n_inst, s.cap,
                                    s.inst_grad, self.gauss_texel, self.dynamic, self.H, self.W, s.grad2d,
                                    self.dL_datlas, 1)
             abi.pg_loss_l1_tiles(self.tile_loss, self.tile_off[-1], n, self.loss)
