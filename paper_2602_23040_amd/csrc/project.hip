@@ -770,8 +770,9 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(3))) void k
 
 // Colour part of the adjoint, FP32: SH coefficient gradients Y_j gc and the
 // view-direction term of the position gradient, added to what the geometric
-// kernel wrote.  The clamp decision (colour = max(0, 0.5 + sum Y k)) is taken
-// on the forward's own FP64 sum, so it is the forward's decision.
+// kernel wrote.  The clamp decision (colour = max(0, 0.5 + sum Y k)) is the
+// forward's: the FP32 sum settles it away from 0, and near 0 the forward's
+// stored colour (0 exactly where its FP64 sum clamped) is read back.
 template <int L>
 __global__ __launch_bounds__(128) void k_project_bwd_sh(const ViewDev* __restrict__ views,
                                                         const int32_t* __restrict__ frame_views,
