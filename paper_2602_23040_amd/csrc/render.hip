@@ -74,7 +74,7 @@ constexpr float kLog2AlphaMax = -0.01449956969511509f;     // log2(0.99)
 // take bit-identical decisions (the library is compiled with -ffp-contract=off).
 __device__ __forceinline__ float quad(float dx, float dy, float a, float b2, float c, float lo) {
     const float u = fmaf(b2, dy, a * dx);      // a dx + 2 b dy
-    return fmaf(u, dx, fmaf(c * dy, dy, lo));  // dx (a dx + 2 b dy) + c dy^2 + lo
+    return fmaf(u, dx, fmaf(c, dy * dy, lo));  // dx (a dx + 2 b dy) + c dy^2 + lo
 }
 
 // Smallest s' a pixel needs: q <= 9 (s' >= kSMin + lo) and alpha >= 1/255
@@ -411,8 +411,9 @@ __device__ __forceinline__ void pair_offsets(int lane, int& offA, int& offB) {
 // image and target as the tile starts; the tile's sum of |image - target|
 // (FP32 inside each row of 16 lanes, the four rows in FP64; a fixed order)
 // goes to tile_loss[tile] for the loss value.
+// Seven waves per SIMD: the hint holds the register allocation at 72.
 template <int TW, int TH, int BATCH, bool L1>
-__global__ __launch_bounds__(kLanes) void k_render_bwd(const ViewDev* __restrict__ views, int nv, int64_t n_tiles,
+__global__ __launch_bounds__(kLanes) __attribute__((amdgpu_waves_per_eu(7))) void k_render_bwd(const ViewDev* __restrict__ views, int nv, int64_t n_tiles,
                                                        const pg_splat* __restrict__ splats,
                                                        const pg_tile_set* __restrict__ tiles,
                                                        const int32_t* __restrict__ values,
@@ -568,12 +569,12 @@ __global__ __launch_bounds__(kLanes) void k_render_bwd(const ViewDev* __restrict
                 float dqp = w * diff;
                 if (clamp) dqp = al < kAlphaMax ? dqp : 0.0f;
                 m[5] += dqp;
-                const float px = dqp * dx, py = dqp * dy;
+                const float px = dqp * dx;
                 m[0] += px;
-                m[1] += py;
+                m[1] = fmaf(dqp, dy, m[1]);
                 m[2] = fmaf(px, dx, m[2]);
                 m[3] = fmaf(px, dy, m[3]);
-                m[4] = fmaf(py, dy, m[4]);
+                m[4] = fmaf(dqp, dy * dy, m[4]);   // dy^2 is the quadratic's, shared by a row of blocks
             };
             // blocks whose bit is set, entered at the first one so that its code starts the
             // sums (a tile's entry always has at least one block)
