@@ -31,11 +31,16 @@ FLAGS = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17", "-ffp-contract=o
          "-Wall", "-Wno-unused-function", "-Wno-unused-variable",
          "-I" + os.path.join(ROOT, "include"), "-I" + CSRC]
 SOURCES = ["api.hip", "scan.hip", "fetch.hip", "quant.hip", "loss.hip", "uvprune.hip", "project.hip", "binsort.hip", "render.hip", "optim.hip"]
+# Per-file flags.  render.hip: branches on wave-uniform values (the adjoint's
+# per-entry block and clamp dispatch) are left unstructured.  Structurized, they
+# became flow blocks that kept each pixel's transmittance and colour-behind
+# state in two register sets, with two copies per skipped block and entry.
+EXTRA_FLAGS = {"render.hip": ["-mllvm", "-structurizecfg-skip-uniform-regions=1"]}
 
 
 def _compile(src: str, verbose: bool) -> str:
     obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
-    cmd = [HIPCC, *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+    cmd = [HIPCC, *FLAGS, *EXTRA_FLAGS.get(src, []), "-c", os.path.join(CSRC, src), "-o", obj]
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)
