@@ -81,17 +81,22 @@ def recorded_traffic(kernel, workload, tiling):
     """HBM bytes per launch of `kernel` from the committed counter record
     (profiles/traffic.json: FETCH_SIZE and WRITE_SIZE of the same launch,
     scaled by what the counters read for a copy of known size), or None when
-    there is no record for this workload and tiling or the kernel's source
-    has changed since the counters were taken."""
+    there is no record for this workload and tiling or the kernel's source or
+    its build flags (the build script) have changed since the counters were
+    taken."""
     import hashlib
+
+    def digest(path):
+        with open(os.path.join(ROOT, path), "rb") as f:
+            return hashlib.sha256(f.read()).hexdigest()
+
     try:
         with open(os.path.join(ROOT, "profiles", "traffic.json")) as f:
             rec = json.load(f)[f"{kernel}|{workload}|{tiling}"]
-        with open(os.path.join(ROOT, rec["source"]), "rb") as f:
-            digest = hashlib.sha256(f.read()).hexdigest()
+        same = digest(rec["source"]) == rec["source_sha256"] and digest(rec["build"]) == rec["build_sha256"]
     except (OSError, KeyError, ValueError):
         return None
-    return rec["bytes_per_launch"] if digest == rec["source_sha256"] else None
+    return rec["bytes_per_launch"] if same else None
 
 
 def calibrate_copy(mib):
