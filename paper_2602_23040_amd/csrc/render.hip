@@ -185,9 +185,12 @@ struct alignas(16) Staged {
 };
 
 constexpr uint32_t kClampBit = 1u << kPPT;   // forward's aux[0]: may_clamp(log2 opacity)
+// adjoint's aux[0]: the gradient slot (kNoSlot: none) and, in bit 31, may_clamp(log2 opacity)
+constexpr uint32_t kNoSlot = 0x7fffffffu;
+constexpr uint32_t kSlotClamp = 0x80000000u;
 
 template <int TW, int TH, bool MASK>
-__device__ __forceinline__ void stage(const pg_splat* __restrict__ splats, int32_t gv, double ox, double oy,
+__device__ __forceinline__ float stage(const pg_splat* __restrict__ splats, int32_t gv, double ox, double oy,
                                       float col0, float row0, Staged* s_st, int k) {
     const float4* sp = reinterpret_cast<const float4*>(splats + gv);
     const float4 a = sp[0], b = sp[1], c = sp[2];
@@ -199,7 +202,7 @@ __device__ __forceinline__ void stage(const pg_splat* __restrict__ splats, int32
     s_st[k].col = make_float4(b.z * kQScale, lo, c.x, c.y);     // scaled conic c, log2 opacity, red, green
     s_st[k].blu = c.z;
     s_st[k].thr = take_threshold(lo);
-    if (!MASK) return;
+    if (!MASK) return lo;
     constexpr int BPR = TW / 8;
     const float ac = b.x * b.z;
     const float det = ac - b.y * b.y;
@@ -215,6 +218,7 @@ __device__ __forceinline__ void stage(const pg_splat* __restrict__ splats, int32
         }
     }
     s_st[k].aux[0] = mask | (may_clamp(lo) ? kClampBit : 0u);
+    return lo;
 }
 
 // Eight waves per SIMD (64 registers): the forward waits on its per-Gaussian
@@ -429,7 +433,7 @@ __global__ __launch_bounds__(kLanes) __attribute__((amdgpu_waves_per_eu(7))) voi
                                                        float* __restrict__ inst_grad, const float* __restrict__ image,
                                                        const float* __restrict__ target, float inv_n,
                                                        double* __restrict__ tile_loss) {
-    // aux[0]: gradient slot of the (Gaussian, this tile) instance (-1: none);
+    // aux[0]: gradient slot of the (Gaussian, this tile) instance (kNoSlot: none) | kSlotClamp;
     // aux[1]: entry word, list position << 4 | blocks that composited it
     __shared__ Staged s_st[BATCH];
     TileGeo t;
@@ -522,8 +526,8 @@ __global__ __launch_bounds__(kLanes) __attribute__((amdgpu_waves_per_eu(7))) voi
             const int32_t w = (int32_t)(ts.w & 0xffff);
             const uint64_t mask = (uint64_t)ts.x | ((uint64_t)ts.y << 32);
             const int32_t slot = inst_first[gv] + kept_rank(mask, (t.ty - ylo) * w + (t.tx - xlo));
-            s_st[i].aux[0] = (uint32_t)((slot >= 0 && slot < n_inst) ? slot : -1);
-            stage<TW, TH, false>(splats, gv, t.ox, t.oy, t.col0, t.row0, s_st, i);
+            const float lo = stage<TW, TH, false>(splats, gv, t.ox, t.oy, t.col0, t.row0, s_st, i);
+            s_st[i].aux[0] = ((slot >= 0 && slot < n_inst) ? (uint32_t)slot : kNoSlot) | (may_clamp(lo) ? kSlotClamp : 0u);
         }
         __syncthreads();
         // one entry: its nine per-lane sums, as row sums and the ninth, and its slot
@@ -533,8 +537,9 @@ __global__ __launch_bounds__(kLanes) __attribute__((amdgpu_waves_per_eu(7))) voi
             const float cb = s_st[k].blu;
             const float thr = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(s_st[k].thr)));
             const uint32_t word = (uint32_t)__builtin_amdgcn_readfirstlane((int)s_st[k].aux[1]);
-            const int32_t slot = __builtin_amdgcn_readfirstlane((int)s_st[k].aux[0]);
-            const float lo = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(cc.y)));
+            const uint32_t sw = (uint32_t)__builtin_amdgcn_readfirstlane((int)s_st[k].aux[0]);
+            const int32_t slot = (sw & kNoSlot) == kNoSlot ? -1 : (int32_t)(sw & kNoSlot);
+            const float lo = cc.y;    // a vector operand: the clamp flag comes with the slot
             const int32_t pos = (int32_t)(word >> 4);
             // Per-lane sums over the lane's pixels, later reduced over the wave:
             //   m[0..1] = sum dq' (dx, dy), m[2..4] = sum dq' (dx^2, dx dy, dy^2)
@@ -598,7 +603,7 @@ __global__ __launch_bounds__(kLanes) __attribute__((amdgpu_waves_per_eu(7))) voi
                     block(3, clamp);
                 }
             };
-            if (may_clamp(lo)) blocks(true);
+            if (sw & kSlotClamp) blocks(true);
             else blocks(false);
             // the moments go to the slot as they are: the mean and conic gradients are
             // linear in them (dm = Q (m0, m1), d(a, b, c) = -(m2 / 2, m3, m4 / 2)), so the
