@@ -11,6 +11,8 @@ and linked into one shared library exporting the C ABI of
 * ``-munsafe-fp-atomics``: hardware float atomics for gradient sums.
 * ``-Xclang -target-feature -Xclang -packed-fp32-ops``: packed FP32 vector
   instructions are kept out of the generated code.
+* ``-mllvm -structurizecfg-skip-uniform-regions=1`` (render.hip only):
+  branches on wave-uniform values stay unstructured (see EXTRA_FLAGS).
 """
 from __future__ import annotations
 
